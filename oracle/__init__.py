@@ -1,0 +1,206 @@
+"""CPU oracle for motif-based community detection (arXiv 2412.12382).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The GPU library never imports, links
+or runs anything here, and nothing here imports the GPU library.
+
+The arithmetic lives in ``oracle.c`` (plain C, gcc -O2 -fopenmp); this module
+marshals numpy arrays.  See the C file's header for the passages followed.
+Edges are reported in canonical order: sorted (lo, hi), lo < hi.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+_lib = None
+
+TECTONIC, TW = 0, 1
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.or_canon.argtypes = [I64, I64, P, P, P, P, P]
+        L.or_degrees.argtypes = [I64, I64, P, P, P]
+        L.or_adjacency.argtypes = [I64, I64, P, P, P, P, P]
+        L.or_triangles.argtypes = [I64, P, P, P, P]
+        L.or_tectonic.argtypes = [I64, P, P, P, P, P]
+        L.or_wedges.argtypes = [I64, P, P, P, P, P]
+        L.or_tw.argtypes = [I64, P, P, P, P, P]
+        L.or_prune.argtypes = [I64, ctypes.c_int, P, P, P, P, I64, I64, P, P]
+        L.or_components.argtypes = [I64, I64, P, P, P, P]
+        L.or_components.restype = I64
+        L.or_percentile.argtypes = [I64, ctypes.c_int, P, P, P, P, I64, I64, P, P]
+        L.or_histogram.argtypes = [I64, P, P, P, P, P]
+        L.or_ari.argtypes = [I64, P, P, P]
+        L.or_ari.restype = ctypes.c_double
+        L.or_query_edges.argtypes = [I64, I64, P, P, I64, P, P, P, P, P, P]
+        L.or_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def canon(n: int, src, dst):
+    """Sorted unique (lo, hi) edges of the simple graph on the raw pairs."""
+    src, dst = _c(src, np.int32), _c(dst, np.int32)
+    P = len(src)
+    lo = np.empty(max(P, 1), np.int32)
+    hi = np.empty(max(P, 1), np.int32)
+    m = ctypes.c_int64(0)
+    rc = lib().or_canon(n, P, _p(src), _p(dst), ctypes.byref(m), _p(lo), _p(hi))
+    if rc == -2:
+        raise OracleError("vertex id out of range")
+    if rc != 0:
+        raise OracleError(f"or_canon failed ({rc})")
+    return lo[:m.value].copy(), hi[:m.value].copy()
+
+
+def degrees(n: int, lo, hi):
+    deg = np.empty(max(n, 1), np.int32)
+    lib().or_degrees(n, len(lo), _p(lo), _p(hi), _p(deg))
+    return deg[:n]
+
+
+def adjacency(n: int, lo, hi):
+    m = len(lo)
+    off = np.empty(n + 1, np.int64)
+    adj = np.empty(max(2 * m, 1), np.int32)
+    eid = np.empty(max(2 * m, 1), np.int32)
+    lib().or_adjacency(n, m, _p(lo), _p(hi), _p(off), _p(adj), _p(eid))
+    return off, adj[:2 * m], eid[:2 * m]
+
+
+def triangles(n: int, lo, hi):
+    """t(e) = |N(lo) n N(hi)| per canonical edge."""
+    off, adj, eid = adjacency(n, lo, hi)
+    t = np.zeros(max(len(lo), 1), np.int32)
+    lib().or_triangles(n, _p(off), _p(adj), _p(eid), _p(t))
+    return t[:len(lo)]
+
+
+def tectonic(lo, hi, t, deg):
+    w = np.empty(max(len(lo), 1), np.float64)
+    lib().or_tectonic(len(lo), _p(lo), _p(hi), _p(t), _p(deg), _p(w))
+    return w[:len(lo)]
+
+
+def wedges(lo, hi, t, deg):
+    w = np.empty(max(len(lo), 1), np.int64)
+    lib().or_wedges(len(lo), _p(lo), _p(hi), _p(t), _p(deg), _p(w))
+    return w[:len(lo)]
+
+
+def tw(lo, hi, t, deg):
+    w = np.empty(max(len(lo), 1), np.int64)
+    lib().or_tw(len(lo), _p(lo), _p(hi), _p(t), _p(deg), _p(w))
+    return w[:len(lo)]
+
+
+def prune(measure: int, lo, hi, t, deg, num: int, den: int):
+    """keep[e] = NOT (sim(e) < num/den)  (Algorithm 1), as uint8."""
+    keep = np.empty(max(len(lo), 1), np.uint8)
+    k = ctypes.c_int64(0)
+    rc = lib().or_prune(len(lo), measure, _p(lo), _p(hi), _p(t), _p(deg), num, den, _p(keep),
+                        ctypes.byref(k))
+    if rc != 0:
+        raise OracleError(f"or_prune failed ({rc})")
+    return keep[:len(lo)]
+
+
+def components(n: int, lo, hi, keep=None):
+    """Min-vertex labels of the components of (V, kept edges) and their count."""
+    label = np.empty(max(n, 1), np.int32)
+    kp = None if keep is None else _c(keep, np.uint8)
+    ncc = lib().or_components(n, len(lo), _p(lo), _p(hi), _p(kp), _p(label))
+    return label[:n], int(ncc)
+
+
+def percentile(measure: int, lo, hi, t, deg, pn: int, pd: int):
+    num, den = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = lib().or_percentile(len(lo), measure, _p(lo), _p(hi), _p(t), _p(deg), pn, pd,
+                             ctypes.byref(num), ctypes.byref(den))
+    if rc != 0:
+        raise OracleError(f"or_percentile failed ({rc})")
+    return num.value, den.value
+
+
+def histogram(lo, hi, t, deg):
+    h = np.zeros(64, np.int64)
+    lib().or_histogram(len(lo), _p(lo), _p(hi), _p(t), _p(deg), _p(h))
+    return h
+
+
+def ari(x, y):
+    """(ARI, [S, A, B, N]) of two labelings."""
+    x, y = _c(x, np.int32), _c(y, np.int32)
+    sums = np.zeros(4, np.int64)
+    v = lib().or_ari(len(x), _p(x), _p(y), _p(sums))
+    return v, sums
+
+
+def query_edges(n: int, src, dst, qu, qv):
+    """From raw pairs: (is_edge, deg_u, deg_v, t) for each query pair."""
+    src, dst = _c(src, np.int32), _c(dst, np.int32)
+    qu, qv = _c(qu, np.int32), _c(qv, np.int32)
+    K = len(qu)
+    out = [np.zeros(max(K, 1), np.int32) for _ in range(4)]
+    rc = lib().or_query_edges(n, len(src), _p(src), _p(dst), K, _p(qu), _p(qv),
+                              *[_p(a) for a in out])
+    if rc != 0:
+        raise OracleError(f"or_query_edges failed ({rc})")
+    return tuple(a[:K] for a in out)
+
+
+def run(n: int, src, dst, measure: int, num: int, den: int, timings: dict | None = None):
+    """Algorithm 1 end to end on raw pairs; returns a dict of every product."""
+    tm = {} if timings is None else timings
+    t0 = time.perf_counter()
+    lo, hi = canon(n, src, dst)
+    deg = degrees(n, lo, hi)
+    t1 = time.perf_counter()
+    t = triangles(n, lo, hi)
+    t2 = time.perf_counter()
+    keep = prune(measure, lo, hi, t, deg, num, den)
+    w = tectonic(lo, hi, t, deg) if measure == TECTONIC else tw(lo, hi, t, deg)
+    t3 = time.perf_counter()
+    labels, ncc = components(n, lo, hi, keep)
+    t4 = time.perf_counter()
+    tm.update(canon=t1 - t0, triangles=t2 - t1, weight_prune=t3 - t2, components=t4 - t3)
+    return dict(lo=lo, hi=hi, deg=deg, t=t, w=w, keep=keep, labels=labels, ncc=ncc)
