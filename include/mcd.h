@@ -1,0 +1,184 @@
+/*
+ * mcd.h - C ABI of the MI355X (gfx950) motif-based community detection library.
+ *
+ * The library computes Algorithm 1 of Chen & Tsourakakis, "Parallel
+ * Motif-Based Community Detection" (arXiv 2412.12382): weight every edge of an
+ * undirected simple graph by a triangle-based similarity, remove the edges
+ * whose similarity is below a threshold, and return the connected components
+ * of what remains.  Definitions follow the paper's notation paragraph (Sec. 1)
+ * and Table "tab:simfunctions":
+ *     t(u,v)      = |N(u) n N(v)|                    (triangles on the edge)
+ *     wedge(u,v)  = |N(u) u N(v)| - |N(u) n N(v)| - 2
+ *     Tectonic    = t(u,v) / (deg u + deg v)
+ *     TW          = t(u,v) - wedge(u,v) = 3 t - deg u - deg v + 2   (Eq. eq:tw)
+ *
+ * Conventions
+ *   - Every call returns mcd_status: MCD_OK (0) or a negative error.  Nothing
+ *     aborts or throws across the ABI.  mcd_last_error() gives a message for
+ *     the calling thread's most recent failure.
+ *   - Array arguments are DEVICE pointers owned by the caller unless the name
+ *     says host_.  The library never allocates device memory except a small
+ *     control block in mcd_ctx_create.  Calls that need scratch memory take a
+ *     workspace (ws, ws_bytes) sized by the matching *_workspace_size query;
+ *     a smaller workspace gives MCD_ERR_WORKSPACE.
+ *   - Work is enqueued on the context's stream.  Calls documented as
+ *     "synchronous" wait for that stream before returning (they return host
+ *     scalars); all others are asynchronous and their outputs are valid once
+ *     the stream reaches them.
+ *   - Handles (mcd_ctx, mcd_graph) are host objects created and freed by the
+ *     library.  A graph handle BORROWS the caller's storage buffer, which must
+ *     outlive it.  One context per host thread.
+ *   - Vertex ids are int32 in [0, n); n < 2^31; edge counts fit in int64.
+ *   - Per-edge arrays are in LIBRARY EDGE ORDER: the order of mcd_graph_edges,
+ *     fixed for a graph handle.  Vertex arrays are indexed by original id.
+ */
+#ifndef MCD_H
+#define MCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mcd_status;
+#define MCD_OK 0
+#define MCD_ERR_INVALID_ARG (-1)    /* NULL pointer, negative size, den <= 0 ...    */
+#define MCD_ERR_INVALID_VERTEX (-2) /* an input id outside [0, n)                    */
+#define MCD_ERR_RANGE (-3)          /* a size beyond the supported range             */
+#define MCD_ERR_WORKSPACE (-4)      /* workspace or storage smaller than required    */
+#define MCD_ERR_NO_DEVICE (-5)      /* no HIP device, or the device id is invalid    */
+#define MCD_ERR_DEVICE (-6)         /* a HIP runtime call failed                     */
+#define MCD_ERR_NOT_CONVERGED (-7)  /* an iterative step hit its iteration cap       */
+#define MCD_ERR_EMPTY (-8)          /* the requested statistic has no data           */
+
+typedef struct mcd_ctx mcd_ctx;
+typedef struct mcd_graph mcd_graph;
+
+/* A threshold delta = num / den, den > 0, |num| and den below 2^31. */
+typedef struct {
+    int64_t num;
+    int64_t den;
+} mcd_rational;
+
+/* Similarity measures of Table tab:simfunctions that the library evaluates. */
+typedef enum {
+    MCD_SIM_TECTONIC = 0, /* t / (deg u + deg v)                      */
+    MCD_SIM_TW = 1        /* t - wedge = 3t - deg u - deg v + 2       */
+} mcd_measure;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device` whose work goes to `stream` (a
+ * hipStream_t, NULL = the default stream).  Allocates a small device control
+ * block and pinned host memory for scalar read-backs.
+ * Errors: MCD_ERR_NO_DEVICE, MCD_ERR_DEVICE, MCD_ERR_INVALID_ARG (out NULL). */
+mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out);
+/* Replaces the stream of a context. */
+mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream);
+mcd_status mcd_ctx_destroy(mcd_ctx* ctx);
+
+/* Name of a status code (static string). */
+const char* mcd_status_string(mcd_status s);
+/* Message of the calling thread's last failure ("" if none). */
+const char* mcd_last_error(void);
+
+/* ------------------------------------------------------------ graph build */
+
+/* Sizes for mcd_graph_build on n_pairs raw pairs over n_vertices vertices:
+ *   storage_bytes: the persistent graph storage the handle borrows;
+ *   ws_bytes:      scratch needed only during the build.
+ * Errors: MCD_ERR_INVALID_ARG, MCD_ERR_RANGE (n_vertices >= 2^31). */
+mcd_status mcd_graph_build_sizes(int64_t n_pairs, int64_t n_vertices, size_t* storage_bytes,
+                                 size_t* ws_bytes);
+
+/* Builds the simple undirected graph G of the paper's notation paragraph
+ * (Sec. 1) from raw pairs (src[i], dst[i]), i < n_pairs: every pair with
+ * src != dst is the undirected edge {src, dst}; self-loops are dropped and
+ * duplicates (in either direction) collapse to one edge.
+ * Internally vertices are ranked by (degree, id) and each edge is oriented
+ * from its lower- to its higher-ranked endpoint (the degree ordering that
+ * Sec. 2 cites for triangle counting); the result is a CSR of out-neighbours
+ * sorted by rank, plus the row of every edge.
+ *   src, dst:  device int32[n_pairs], read only.
+ *   storage:   device buffer of at least storage_bytes (mcd_graph_build_sizes),
+ *              borrowed by the handle until mcd_graph_destroy.
+ *   ws:        device scratch of at least ws_bytes, free again on return.
+ * Synchronous (returns the handle with m known on the host).
+ * Errors: MCD_ERR_INVALID_VERTEX (an id outside [0, n_vertices); no handle is
+ * returned), MCD_ERR_WORKSPACE, MCD_ERR_INVALID_ARG, MCD_ERR_RANGE, MCD_ERR_DEVICE. */
+mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst, int64_t n_pairs,
+                           int64_t n_vertices, void* storage, size_t storage_bytes, void* ws,
+                           size_t ws_bytes, mcd_graph** out);
+
+/* Host-side facts of a built graph: n, m (undirected edges), max degree and
+ * max out-degree of the orientation.  Any output pointer may be NULL. */
+mcd_status mcd_graph_info(const mcd_graph* g, int64_t* n, int64_t* m, int32_t* max_deg,
+                          int32_t* max_outdeg);
+
+/* Endpoints (original ids) of every edge in library edge order: u[e] is the
+ * lower-ranked endpoint, v[e] the higher-ranked one.  u, v: device int32[m]. */
+mcd_status mcd_graph_edges(const mcd_graph* g, int32_t* u, int32_t* v);
+
+/* deg(x) = |N(x)| for every original id x.  deg: device int32[n]. */
+mcd_status mcd_graph_degrees(const mcd_graph* g, int32_t* deg);
+
+mcd_status mcd_graph_destroy(mcd_graph* g);
+
+/* ----------------------------------------------------------------- steps */
+
+/* t(e) = |N(u) n N(v)| for every edge e = {u,v} (Sec. 1 notation; Sec. 3.3
+ * names this the dominant cost).  Each triangle is found once, from its
+ * lowest-ranked edge, and credited to its three edges.  t: device int32[m]. */
+mcd_status mcd_triangles(const mcd_graph* g, int32_t* t);
+
+/* Edge similarity of Table tab:simfunctions from t (as produced by
+ * mcd_triangles).  w_f32 (device float[m], may be NULL): the measure in IEEE
+ * fp32, Tectonic as the correctly rounded quotient t / (deg u + deg v).
+ * w_i32 (device int32[m], may be NULL; TW only): the exact integer TW. */
+mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t, float* w_f32,
+                       int32_t* w_i32);
+
+/* Algorithm 1, first step: edge e is removed iff sim(e) < delta, so it is
+ * kept iff NOT (sim(e) < delta); ties are kept.  The decision is exact
+ * integer arithmetic: Tectonic keeps iff t den >= num (deg u + deg v), TW
+ * keeps iff TW den >= num.
+ *   keep_bits: device uint32[ceil(m/32)], bit (e % 32) of word e / 32.
+ *   n_kept:    device int64[1] (may be NULL), the number of kept edges. */
+mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
+                     uint32_t* keep_bits, int64_t* n_kept);
+
+/* Scratch for mcd_components / mcd_run on this graph. */
+mcd_status mcd_components_workspace_size(const mcd_graph* g, size_t* bytes);
+mcd_status mcd_run_workspace_size(const mcd_graph* g, size_t* bytes);
+
+/* Algorithm 1, second step: connected components of (V, kept edges).
+ * labels[x] (device int32[n], by original id) is the smallest original id in
+ * x's component, so isolated vertices label themselves.  keep_bits may be
+ * NULL (every edge kept).  n_components: device int64[1] (may be NULL).
+ * Union-find with hooking toward the smaller original id and pointer jumping. */
+mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
+                          int64_t* n_components, void* ws, size_t ws_bytes);
+
+/* Algorithm 1 in one call: triangles, weights, prune at delta, components.
+ * labels / n_components as in mcd_components.  Asynchronous. */
+mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, int32_t* labels,
+                   int64_t* n_components, void* ws, size_t ws_bytes);
+
+/* Scratch for mcd_percentile_threshold. */
+mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes);
+
+/* Nearest-rank percentile pct_num/pct_den of the NONZERO similarities: with
+ * the K nonzero values in exact ascending order, the value at 0-based index
+ * ceil(pct_num K / pct_den) - 1 (at least 0), returned exactly as a rational
+ * (Tectonic: t / (deg u + deg v) unreduced; TW: den = 1) in *host_out.
+ * Synchronous.  Errors: MCD_ERR_EMPTY if every similarity is zero. */
+mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                                    int64_t pct_num, int64_t pct_den, void* ws, size_t ws_bytes,
+                                    mcd_rational* host_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCD_H */

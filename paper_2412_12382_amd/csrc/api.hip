@@ -1,0 +1,439 @@
+// C ABI of the library: argument checks, workspace carving, orchestration of
+// the kernels on the context stream, and scalar read-backs.
+#include <limits.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <string>
+
+#include "common.hpp"
+
+// The library is built with hidden visibility; the C ABI below is exported.
+#pragma GCC visibility push(default)
+#include "mcd.h"
+#pragma GCC visibility pop
+
+static thread_local std::string g_last_error;
+
+mcd_status mcd_fail(mcd_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define REQUIRE(cond, code, msg)                \
+    do {                                        \
+        if (!(cond)) return mcd_fail(code, msg); \
+    } while (0)
+
+namespace {
+
+int id_bits(int64_t n) {
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+mcd_status use_device(const mcd_ctx* ctx) {
+    MCD_HIP(hipSetDevice(ctx->device));
+    return MCD_OK;
+}
+
+mcd_status check_delta(mcd_rational d) {
+    REQUIRE(d.den > 0, MCD_ERR_INVALID_ARG, "threshold denominator must be positive");
+    REQUIRE(d.den < ((int64_t)1 << 31) && d.num < ((int64_t)1 << 31) && d.num > -((int64_t)1 << 31),
+            MCD_ERR_RANGE, "threshold numerator and denominator must lie below 2^31 in magnitude");
+    return MCD_OK;
+}
+
+// Layout of the graph storage buffer.
+struct StorageLayout {
+    int64_t* off;
+    int32_t* src;
+    int32_t* adj;
+    int32_t* deg;
+    int32_t* perm;
+    size_t bytes;
+};
+
+StorageLayout storage_layout(void* base, int64_t P, int64_t n) {
+    Carve c{(char*)base, 0, 0};
+    StorageLayout L;
+    L.off = c.take<int64_t>((size_t)n + 1);
+    L.src = c.take<int32_t>((size_t)P);
+    L.adj = c.take<int32_t>((size_t)P);
+    L.deg = c.take<int32_t>((size_t)n);
+    L.perm = c.take<int32_t>((size_t)n);
+    L.bytes = c.used;
+    return L;
+}
+
+struct BuildLayout {
+    uint64_t* k1;
+    uint64_t* k2;
+    uint64_t* uniq;
+    int32_t* inv;
+    int32_t* deg_orig;
+    int32_t* outdeg;
+    void* radix;
+    void* compact;
+    void* scan;
+    size_t bytes;
+};
+
+BuildLayout build_layout(void* base, int64_t P, int64_t n) {
+    Carve c{(char*)base, 0, 0};
+    BuildLayout L;
+    const int64_t K = P > n ? P : n;
+    L.k1 = c.take<uint64_t>((size_t)K);
+    L.k2 = c.take<uint64_t>((size_t)K);
+    L.uniq = c.take<uint64_t>((size_t)P);
+    L.inv = c.take<int32_t>((size_t)n);
+    L.deg_orig = c.take<int32_t>((size_t)n);
+    L.outdeg = c.take<int32_t>((size_t)n);
+    L.radix = c.take<char>(mcd::radix_scratch_bytes(K));
+    L.compact = c.take<char>(mcd::compact_scratch_bytes(K));
+    L.scan = c.take<char>(mcd::scan_scratch_bytes(n));
+    L.bytes = c.used;
+    return L;
+}
+
+struct RunLayout {
+    int32_t* t;
+    uint32_t* keep;
+    int32_t* parent;
+    size_t bytes;
+};
+
+RunLayout run_layout(void* base, const mcd_graph* g) {
+    Carve c{(char*)base, 0, 0};
+    RunLayout L;
+    L.t = c.take<int32_t>((size_t)g->m);
+    L.keep = c.take<uint32_t>((size_t)(g->m + 31) / 32);
+    L.parent = c.take<int32_t>((size_t)g->n);
+    L.bytes = c.used;
+    return L;
+}
+
+mcd_status sync_read(mcd_ctx* ctx, const int64_t* d, int64_t* h, int count) {
+    MCD_HIP(hipMemcpyAsync(h, d, sizeof(int64_t) * count, hipMemcpyDeviceToHost, ctx->stream));
+    MCD_HIP(hipStreamSynchronize(ctx->stream));
+    return MCD_OK;
+}
+
+}  // namespace
+
+#pragma GCC visibility push(default)
+extern "C" {
+
+const char* mcd_status_string(mcd_status s) {
+    switch (s) {
+        case MCD_OK: return "MCD_OK";
+        case MCD_ERR_INVALID_ARG: return "MCD_ERR_INVALID_ARG";
+        case MCD_ERR_INVALID_VERTEX: return "MCD_ERR_INVALID_VERTEX";
+        case MCD_ERR_RANGE: return "MCD_ERR_RANGE";
+        case MCD_ERR_WORKSPACE: return "MCD_ERR_WORKSPACE";
+        case MCD_ERR_NO_DEVICE: return "MCD_ERR_NO_DEVICE";
+        case MCD_ERR_DEVICE: return "MCD_ERR_DEVICE";
+        case MCD_ERR_NOT_CONVERGED: return "MCD_ERR_NOT_CONVERGED";
+        case MCD_ERR_EMPTY: return "MCD_ERR_EMPTY";
+        default: return "MCD_ERR_UNKNOWN";
+    }
+}
+
+const char* mcd_last_error(void) { return g_last_error.c_str(); }
+
+mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
+    REQUIRE(out, MCD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return mcd_fail(MCD_ERR_NO_DEVICE, "no HIP device available");
+    REQUIRE(device >= 0 && device < count, MCD_ERR_NO_DEVICE, "device id out of range");
+    MCD_HIP(hipSetDevice(device));
+    mcd_ctx* c = new mcd_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (hipMalloc((void**)&c->d_ctrl, sizeof(int64_t) * MCD_CTRL_WORDS) != hipSuccess) {
+        delete c;
+        return mcd_fail(MCD_ERR_DEVICE, "hipMalloc of the control block failed");
+    }
+    if (hipHostMalloc((void**)&c->h_ctrl, sizeof(int64_t) * MCD_CTRL_WORDS, hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipFree(c->d_ctrl);
+        delete c;
+        return mcd_fail(MCD_ERR_DEVICE, "hipHostMalloc of the read-back block failed");
+    }
+    *out = c;
+    return MCD_OK;
+}
+
+mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream) {
+    REQUIRE(ctx, MCD_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+    return MCD_OK;
+}
+
+mcd_status mcd_ctx_destroy(mcd_ctx* ctx) {
+    if (!ctx) return MCD_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->d_ctrl);
+    (void)hipHostFree(ctx->h_ctrl);
+    delete ctx;
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_build_sizes(int64_t n_pairs, int64_t n_vertices, size_t* storage_bytes,
+                                 size_t* ws_bytes) {
+    REQUIRE(n_pairs >= 0 && n_vertices >= 0, MCD_ERR_INVALID_ARG, "negative size");
+    REQUIRE(n_vertices < ((int64_t)1 << 31) - 1, MCD_ERR_RANGE, "n_vertices must be below 2^31 - 1");
+    REQUIRE(n_pairs < ((int64_t)1 << 31), MCD_ERR_RANGE, "n_pairs must be below 2^31");
+    if (storage_bytes) *storage_bytes = storage_layout(nullptr, n_pairs, n_vertices).bytes;
+    if (ws_bytes) *ws_bytes = build_layout(nullptr, n_pairs, n_vertices).bytes;
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst, int64_t n_pairs,
+                           int64_t n_vertices, void* storage, size_t storage_bytes, void* ws,
+                           size_t ws_bytes, mcd_graph** out) {
+    REQUIRE(ctx && out, MCD_ERR_INVALID_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    size_t need_st = 0, need_ws = 0;
+    mcd_status st = mcd_graph_build_sizes(n_pairs, n_vertices, &need_st, &need_ws);
+    if (st != MCD_OK) return st;
+    REQUIRE(n_pairs == 0 || (src && dst), MCD_ERR_INVALID_ARG, "src or dst is NULL");
+    REQUIRE(storage && ws, MCD_ERR_INVALID_ARG, "storage or workspace is NULL");
+    REQUIRE(storage_bytes >= need_st, MCD_ERR_WORKSPACE, "graph storage too small");
+    REQUIRE(ws_bytes >= need_ws, MCD_ERR_WORKSPACE, "build workspace too small");
+    if ((st = use_device(ctx)) != MCD_OK) return st;
+
+    hipStream_t s = ctx->stream;
+    const int64_t P = n_pairs, n = n_vertices;
+    const int bits = id_bits(n);
+    StorageLayout G = storage_layout(storage, P, n);
+    BuildLayout B = build_layout(ws, P, n);
+    int64_t* ctrl = ctx->d_ctrl;  // [0] bad id flag, [1] m, [2] max out-degree
+    mcd::fill_i64(ctrl, 4, 0, s);
+
+    // Canonical simple graph: sort + dedup of packed (min, max) pairs.
+    mcd::launch_canon(src, dst, P, n, bits, B.k1, ctrl + 0, s);
+    uint64_t* sorted = mcd::radix_sort_u64(B.k1, B.k2, P, 2 * bits, B.radix, s);
+    mcd::unique_sorted_u64(sorted, P, B.uniq, ctrl + 1, B.compact, s);
+    if ((st = sync_read(ctx, ctrl, ctx->h_ctrl, 2)) != MCD_OK) return st;
+    if (ctx->h_ctrl[0]) return mcd_fail(MCD_ERR_INVALID_VERTEX, "a pair has an id outside [0, n)");
+    const int64_t m = ctx->h_ctrl[1];
+
+    // Degrees, rank by (degree, id), orientation low -> high rank, CSR.
+    mcd::fill_i32(B.deg_orig, n, 0, s);
+    mcd::launch_degree(B.uniq, m, bits, B.deg_orig, s);
+    mcd::launch_rank_keys(B.deg_orig, n, bits, B.k1, s);
+    uint64_t* ranked = mcd::radix_sort_u64(B.k1, B.k2, n, 2 * bits, B.radix, s);
+    mcd::launch_rank_apply(ranked, n, bits, B.deg_orig, G.perm, B.inv, G.deg, s);
+    mcd::launch_orient_keys(B.uniq, m, bits, B.inv, B.k1, s);
+    uint64_t* oriented = mcd::radix_sort_u64(B.k1, B.k2, m, 2 * bits, B.radix, s);
+    mcd::fill_i32(B.outdeg, n, 0, s);
+    mcd::launch_csr_fill(oriented, m, bits, G.src, G.adj, B.outdeg, s);
+    mcd::exclusive_scan_i32_i64(B.outdeg, n, G.off, B.scan, s);
+    mcd::launch_max_i32(B.outdeg, n, ctrl + 2, s);
+    mcd::launch_max_i32(G.deg, n, ctrl + 3, s);
+    if ((st = sync_read(ctx, ctrl, ctx->h_ctrl, 4)) != MCD_OK) return st;
+
+    mcd_graph* g = new mcd_graph();
+    g->ctx = ctx;
+    g->n = n;
+    g->m = m;
+    g->cap = P;
+    g->bits = bits;
+    g->max_outdeg = (int32_t)ctx->h_ctrl[2];
+    g->max_deg = (int32_t)ctx->h_ctrl[3];
+    g->off = G.off;
+    g->src = G.src;
+    g->adj = G.adj;
+    g->deg = G.deg;
+    g->perm = G.perm;
+    *out = g;
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_info(const mcd_graph* g, int64_t* n, int64_t* m, int32_t* max_deg,
+                          int32_t* max_outdeg) {
+    REQUIRE(g, MCD_ERR_INVALID_ARG, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_deg) *max_deg = g->max_deg;
+    if (max_outdeg) *max_outdeg = g->max_outdeg;
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_edges(const mcd_graph* g, int32_t* u, int32_t* v) {
+    REQUIRE(g && u && v, MCD_ERR_INVALID_ARG, "NULL argument");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_edges_orig(g->src, g->adj, g->perm, g->m, u, v, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_degrees(const mcd_graph* g, int32_t* deg) {
+    REQUIRE(g && deg, MCD_ERR_INVALID_ARG, "NULL argument");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_scatter_by_perm(g->deg, g->perm, g->n, deg, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_destroy(mcd_graph* g) {
+    delete g;
+    return MCD_OK;
+}
+
+mcd_status mcd_triangles(const mcd_graph* g, int32_t* t) {
+    REQUIRE(g && t, MCD_ERR_INVALID_ARG, "NULL argument");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_triangles(g, t, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t, float* w_f32,
+                       int32_t* w_i32) {
+    REQUIRE(g && t, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(!(measure == MCD_SIM_TECTONIC && w_i32), MCD_ERR_INVALID_ARG,
+            "integer weights exist for TW only");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_weights(g, measure, t, w_f32, w_i32, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
+                     uint32_t* keep_bits, int64_t* n_kept) {
+    REQUIRE(g && t && keep_bits, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    mcd_status st = check_delta(delta);
+    if (st != MCD_OK) return st;
+    if ((st = use_device(g->ctx)) != MCD_OK) return st;
+    mcd::launch_prune(g, measure, t, delta.num, delta.den, keep_bits, n_kept, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_components_workspace_size(const mcd_graph* g, size_t* bytes) {
+    REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
+    *bytes = mcd_align(sizeof(int32_t) * (size_t)g->n + 1);
+    return MCD_OK;
+}
+
+mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
+                          int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE(g && labels && ws, MCD_ERR_INVALID_ARG, "NULL argument");
+    size_t need = 0;
+    mcd_components_workspace_size(g, &need);
+    REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "components workspace too small");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_components(g, keep_bits, labels, n_components, (int32_t*)ws, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_run_workspace_size(const mcd_graph* g, size_t* bytes) {
+    REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
+    *bytes = run_layout(nullptr, g).bytes;
+    return MCD_OK;
+}
+
+mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, int32_t* labels,
+                   int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE(g && labels && ws, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    mcd_status st = check_delta(delta);
+    if (st != MCD_OK) return st;
+    size_t need = 0;
+    mcd_run_workspace_size(g, &need);
+    REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "run workspace too small");
+    if ((st = use_device(g->ctx)) != MCD_OK) return st;
+    RunLayout L = run_layout(ws, g);
+    hipStream_t s = g->ctx->stream;
+    mcd::launch_triangles(g, L.t, s);
+    mcd::launch_prune(g, measure, L.t, delta.num, delta.den, L.keep, nullptr, s);
+    mcd::launch_components(g, L.keep, labels, n_components, L.parent, s);
+    return MCD_OK;
+}
+
+mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes) {
+    REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
+    *bytes = mcd::select_scratch_bytes(g);
+    return MCD_OK;
+}
+
+mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                                    int64_t pct_num, int64_t pct_den, void* ws, size_t ws_bytes,
+                                    mcd_rational* host_out) {
+    REQUIRE(g && t && ws && host_out, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(pct_den > 0 && pct_num >= 0 && pct_num <= pct_den && pct_den < ((int64_t)1 << 31),
+            MCD_ERR_INVALID_ARG, "percentile must be a fraction in [0, 1] with den below 2^31");
+    size_t need = 0;
+    mcd_percentile_workspace_size(g, &need);
+    REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "percentile workspace too small");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    hipStream_t s = g->ctx->stream;
+    mcd_ctx* ctx = g->ctx;
+    int64_t* hist = (int64_t*)ws;
+    int64_t* res = hist + 256;
+    int64_t* part = hist + 264;
+    int64_t hh[256];
+    uint32_t prefix = 0, pmask = 0;
+    int64_t k = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        mcd::sel_hist(g, measure, t, prefix, pmask, shift, hist, s);
+        MCD_HIP(hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s));
+        MCD_HIP(hipStreamSynchronize(s));
+        if (shift == 24) {
+            int64_t K = 0;
+            for (int d = 0; d < 256; ++d) K += hh[d];
+            if (K == 0) return mcd_fail(MCD_ERR_EMPTY, "every similarity is zero");
+            k = (pct_num * K + pct_den - 1) / pct_den - 1;
+            if (k < 0) k = 0;
+        }
+        int d = 0;
+        while (d < 255 && k >= hh[d]) {
+            k -= hh[d];
+            ++d;
+        }
+        prefix |= (uint32_t)d << shift;
+        pmask |= 255u << shift;
+    }
+    if (measure == MCD_SIM_TW) {
+        host_out->num = (int64_t)(int32_t)(prefix ^ 0x80000000u);
+        host_out->den = 1;
+        return MCD_OK;
+    }
+    // Distinct rationals sharing one fp32 key: walk them in exact order.
+    int64_t lb_num = 0, lb_den = 1;
+    int lb_valid = 0;
+    for (int guard = 0; guard < 1 << 20; ++guard) {
+        mcd::sel_min_above(g, measure, t, prefix, lb_num, lb_den, lb_valid, part, res, s);
+        MCD_HIP(hipMemcpyAsync(ctx->h_ctrl, res, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, s));
+        MCD_HIP(hipStreamSynchronize(s));
+        const int64_t num = ctx->h_ctrl[0], den = ctx->h_ctrl[1];
+        if (den == 0) return mcd_fail(MCD_ERR_DEVICE, "percentile selection lost its bucket");
+        mcd::sel_count_eq(g, measure, t, prefix, num, den, res + 2, s);
+        MCD_HIP(hipMemcpyAsync(ctx->h_ctrl + 2, res + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        MCD_HIP(hipStreamSynchronize(s));
+        const int64_t c = ctx->h_ctrl[2];
+        if (k < c) {
+            host_out->num = num;
+            host_out->den = den;
+            return MCD_OK;
+        }
+        k -= c;
+        lb_num = num;
+        lb_den = den;
+        lb_valid = 1;
+    }
+    return mcd_fail(MCD_ERR_NOT_CONVERGED, "percentile tie resolution did not finish");
+}
+
+}  // extern "C"
+#pragma GCC visibility pop

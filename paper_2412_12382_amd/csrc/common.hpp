@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "mcd.h"
+
+// Sort key that marks a dropped pair (self-loop or invalid id): all ones, so it
+// sorts after every valid packed key.
+#define MCD_SENTINEL 0xffffffffffffffffull
+
+struct mcd_ctx {
+    int device;
+    hipStream_t stream;
+    int64_t* d_ctrl;   // device control block: flags and counters (MCD_CTRL_WORDS int64)
+    int64_t* h_ctrl;   // pinned host mirror for scalar read-backs
+};
+#define MCD_CTRL_WORDS 64
+
+struct mcd_graph {
+    mcd_ctx* ctx;
+    int64_t n;         // vertices
+    int64_t m;         // undirected edges
+    int64_t cap;       // capacity of the per-edge arrays (= n_pairs of the build)
+    int bits;          // bits of a vertex id in packed keys (>= 1)
+    int32_t max_deg;
+    int32_t max_outdeg;
+    // Borrowed from the caller's storage buffer.  Vertices are renumbered by
+    // rank (degree, original id); "new id" below means that rank.
+    int64_t* off;      // [n+1] CSR row offsets of the oriented graph (rows = new ids)
+    int32_t* src;      // [cap] row (new id) of every edge
+    int32_t* adj;      // [cap] head (new id) of every edge; rows sorted ascending
+    int32_t* deg;      // [n]   degree by new id (non-decreasing)
+    int32_t* perm;     // [n]   original id of every new id
+};
+
+// Thread-local error reporting used by the ABI layer.
+mcd_status mcd_fail(mcd_status s, const std::string& msg);
+
+#define MCD_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return mcd_fail(MCD_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static inline size_t mcd_align(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocator over a caller-provided buffer.
+struct Carve {
+    char* base;
+    size_t used;
+    size_t cap;
+    template <class T>
+    T* take(size_t count) {
+        size_t bytes = mcd_align(count * sizeof(T) + 1);
+        T* p = (T*)(base ? base + used : nullptr);
+        used += bytes;
+        return p;
+    }
+    bool ok() const { return used <= cap; }
+};
+
+namespace mcd {
+
+// ---- device-wide primitives (prim.hip) ----
+// Radix sort of N keys on bits [0, nbits): ping-pongs between a and b and
+// returns the buffer holding the result.  scratch: radix_scratch_bytes(N).
+size_t radix_scratch_bytes(int64_t N);
+uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch,
+                         hipStream_t s);
+// Distinct keys of a sorted array, MCD_SENTINEL excluded, into out; the count
+// goes to *d_count (device).  scratch: compact_scratch_bytes(N).
+size_t compact_scratch_bytes(int64_t N);
+void unique_sorted_u64(const uint64_t* in, int64_t N, uint64_t* out, int64_t* d_count,
+                       void* scratch, hipStream_t s);
+// out[0..N] = exclusive prefix sums of in[0..N) (out[N] = total).
+size_t scan_scratch_bytes(int64_t N);
+void exclusive_scan_i32_i64(const int32_t* in, int64_t N, int64_t* out, void* scratch,
+                            hipStream_t s);
+void fill_i32(int32_t* p, int64_t N, int32_t v, hipStream_t s);
+void fill_i64(int64_t* p, int64_t N, int64_t v, hipStream_t s);
+void fill_u32(uint32_t* p, int64_t N, uint32_t v, hipStream_t s);
+
+// ---- graph construction (build.hip) ----
+void launch_canon(const int32_t* src, const int32_t* dst, int64_t P, int64_t n, int bits,
+                  uint64_t* keys, int64_t* d_err, hipStream_t s);
+void launch_degree(const uint64_t* uniq, int64_t m, int bits, int32_t* deg_orig, hipStream_t s);
+void launch_rank_keys(const int32_t* deg_orig, int64_t n, int bits, uint64_t* keys, hipStream_t s);
+void launch_rank_apply(const uint64_t* sorted, int64_t n, int bits, const int32_t* deg_orig,
+                       int32_t* perm, int32_t* inv, int32_t* deg_new, hipStream_t s);
+void launch_orient_keys(const uint64_t* uniq, int64_t m, int bits, const int32_t* inv,
+                        uint64_t* keys, hipStream_t s);
+void launch_csr_fill(const uint64_t* sorted, int64_t m, int bits, int32_t* src, int32_t* adj,
+                     int32_t* outdeg, hipStream_t s);
+void launch_max_i32(const int32_t* a, int64_t N, int64_t* d_out, hipStream_t s);
+void launch_edges_orig(const int32_t* src, const int32_t* adj, const int32_t* perm, int64_t m,
+                       int32_t* u, int32_t* v, hipStream_t s);
+void launch_scatter_by_perm(const int32_t* val_new, const int32_t* perm, int64_t n,
+                            int32_t* out_orig, hipStream_t s);
+
+// ---- triangles (tc.hip) ----
+void launch_triangles(const mcd_graph* g, int32_t* t, hipStream_t s);
+
+// ---- weights / prune (weight.hip) ----
+void launch_weights(const mcd_graph* g, int measure, const int32_t* t, float* wf, int32_t* wi,
+                    hipStream_t s);
+void launch_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den,
+                  uint32_t* keep_bits, int64_t* n_kept, hipStream_t s);
+
+// ---- components (cc.hip) ----
+void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
+                       int64_t* n_components, int32_t* parent, hipStream_t s);
+
+// ---- percentile (select.hip) ----
+size_t select_scratch_bytes(const mcd_graph* g);
+// Histogram (256 int64) of the digit at `shift` of the keys of nonzero
+// similarities whose key matches prefix under pmask.
+void sel_hist(const mcd_graph* g, int measure, const int32_t* t, uint32_t prefix, uint32_t pmask,
+              int shift, int64_t* hist256, hipStream_t s);
+// Minimum rational (out2[0] / out2[1], den 0 = none) strictly above lb among
+// nonzero similarities with the given key; part holds 2 int64 per block.
+void sel_min_above(const mcd_graph* g, int measure, const int32_t* t, uint32_t key, int64_t lb_num,
+                   int64_t lb_den, int lb_valid, int64_t* part, int64_t* out2, hipStream_t s);
+// Number of nonzero similarities with the given key equal to num/den.
+void sel_count_eq(const mcd_graph* g, int measure, const int32_t* t, uint32_t key, int64_t num,
+                  int64_t den, int64_t* cnt, hipStream_t s);
+
+}  // namespace mcd

@@ -1,0 +1,317 @@
+// Device-wide primitives for gfx950: LSD radix sort of 64-bit keys, unique
+// compaction of a sorted key array, exclusive scan, fills.
+//
+// All kernels use 256-thread workgroups (four 64-lane wavefronts).  Block-level
+// work is split into contiguous ranges so that every pass is stable and
+// deterministic, and per-block partial results go through a single-block scan.
+#include "common.hpp"
+
+namespace mcd {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kIters = 16;                   // 64-key rounds per wave and tile
+constexpr int kTile = kThreads * kIters;     // 4096 keys per block iteration
+constexpr int kMaxBlocks = 2048;
+constexpr int kScanThreads = 1024;
+
+__host__ __device__ inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int grid_blocks(int64_t tiles) {
+    if (tiles < 1) return 1;
+    return (int)(tiles < kMaxBlocks ? tiles : kMaxBlocks);
+}
+
+__device__ __forceinline__ uint64_t lane_lt_mask() { return __lanemask_lt(); }
+
+// Digit histogram of block b's key range, stored digit-major: counts[d*NB + b].
+__global__ __launch_bounds__(kThreads) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t N,
+                                                      int shift, int64_t tpb, int NB,
+                                                      int64_t* __restrict__ counts) {
+    __shared__ uint32_t h[kWaves][256];
+    const int tid = threadIdx.x, w = tid >> 6;
+    for (int i = tid; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * tpb * kTile;
+    const int64_t end = min(N, beg + tpb * (int64_t)kTile);
+    for (int64_t i = beg + tid; i < end; i += kThreads) {
+        uint32_t d = (uint32_t)(keys[i] >> shift) & 255u;
+        atomicAdd(&h[w][d], 1u);
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) s += h[ww][tid];
+    counts[(int64_t)tid * NB + blockIdx.x] = s;
+}
+
+// In-place exclusive scan of a[0..len) by one workgroup; *total (if non-null)
+// receives the sum.
+__global__ __launch_bounds__(kScanThreads) void k_scan_single(int64_t* __restrict__ a, int64_t len,
+                                                              int64_t* __restrict__ total) {
+    __shared__ int64_t part[kScanThreads];
+    const int tid = threadIdx.x;
+    const int64_t per = (len + kScanThreads - 1) / kScanThreads;
+    const int64_t b = tid * per, e = min(len, b + per);
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += a[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - s;
+    for (int64_t i = b; i < e; ++i) {
+        int64_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (total && tid == kScanThreads - 1) *total = part[tid];
+}
+
+// Stable scatter of block b's key range by the digit at `shift`.  Each wave
+// ranks its own contiguous 1024-key slice of the tile with 64-lane ballots
+// (lanes holding the same digit form a peer mask); slices are ordered wave by
+// wave, so the rank order equals the input order.
+__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restrict__ in,
+                                                         uint64_t* __restrict__ out, int64_t N,
+                                                         int shift, int64_t tpb, int NB,
+                                                         const int64_t* __restrict__ offs) {
+    __shared__ int64_t run[256];
+    __shared__ int64_t wbase[kWaves][256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    run[tid] = offs[(int64_t)tid * NB + blockIdx.x];
+    const int64_t ntiles = div_up(N, kTile);
+    const int64_t t0 = (int64_t)blockIdx.x * tpb;
+    const int64_t t1 = min(ntiles, t0 + tpb);
+    const uint64_t lt = lane_lt_mask();
+    __syncthreads();
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        for (int j = lane; j < 256; j += 64) wcnt[w][j] = 0;
+        uint64_t key[kIters];
+        uint32_t rnk[kIters];
+        const int64_t base = tile * kTile + (int64_t)w * (kTile / kWaves);
+#pragma unroll
+        for (int it = 0; it < kIters; ++it) {
+            const int64_t i = base + it * 64 + lane;
+            const bool valid = i < N;
+            const uint64_t k = valid ? in[i] : 0;
+            const uint32_t d = (uint32_t)(k >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const uint64_t bb = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? bb : ~bb;
+            }
+            const uint32_t before = valid ? wcnt[w][d] : 0u;
+            rnk[it] = before + (uint32_t)__popcll(peers & lt);
+            if (valid && (peers & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+            key[it] = k;
+        }
+        __syncthreads();
+        {
+            int64_t acc = run[tid];
+#pragma unroll
+            for (int ww = 0; ww < kWaves; ++ww) {
+                wbase[ww][tid] = acc;
+                acc += wcnt[ww][tid];
+            }
+            run[tid] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kIters; ++it) {
+            const int64_t i = base + it * 64 + lane;
+            if (i < N) {
+                const uint32_t d = (uint32_t)(key[it] >> shift) & 255u;
+                out[wbase[w][d] + rnk[it]] = key[it];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ bool uniq_flag(const uint64_t* __restrict__ in, int64_t i) {
+    const uint64_t k = in[i];
+    return k != MCD_SENTINEL && (i == 0 || in[i - 1] != k);
+}
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* sh) {
+    // sh: kWaves entries
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    int64_t s = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) s += sh[ww];
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_uniq_count(const uint64_t* __restrict__ in, int64_t N,
+                                                         int64_t tpb, int64_t* __restrict__ counts) {
+    __shared__ int64_t sh[kWaves];
+    const int64_t beg = (int64_t)blockIdx.x * tpb * kTile;
+    const int64_t end = min(N, beg + tpb * (int64_t)kTile);
+    int64_t c = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) c += uniq_flag(in, i) ? 1 : 0;
+    const int64_t s = block_sum_i64(c, sh);
+    if (threadIdx.x == 0) counts[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_uniq_scatter(const uint64_t* __restrict__ in, int64_t N,
+                                                           int64_t tpb, const int64_t* __restrict__ offs,
+                                                           uint64_t* __restrict__ out) {
+    __shared__ uint32_t wc[kWaves];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const int64_t beg = (int64_t)blockIdx.x * tpb * kTile;
+    const int64_t end = min(N, beg + tpb * (int64_t)kTile);
+    const uint64_t lt = lane_lt_mask();
+    int64_t run = offs[blockIdx.x];
+    for (int64_t c0 = beg; c0 < end; c0 += kThreads) {
+        const int64_t i = c0 + tid;
+        const bool f = (i < end) && uniq_flag(in, i);
+        const uint64_t bal = __ballot(f);
+        if ((tid & 63) == 0) wc[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t woff = 0, tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) {
+            woff += (ww < w) ? wc[ww] : 0u;
+            tot += wc[ww];
+        }
+        if (f) out[run + woff + __popcll(bal & lt)] = in[i];
+        run += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_count_i32(const int32_t* __restrict__ in, int64_t N,
+                                                             int64_t tpb, int64_t* __restrict__ counts) {
+    __shared__ int64_t sh[kWaves];
+    const int64_t beg = (int64_t)blockIdx.x * tpb * kTile;
+    const int64_t end = min(N, beg + tpb * (int64_t)kTile);
+    int64_t c = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) c += in[i];
+    const int64_t s = block_sum_i64(c, sh);
+    if (threadIdx.x == 0) counts[blockIdx.x] = s;
+}
+
+// Block-local exclusive scan of 256 values per round, carried across rounds.
+__global__ __launch_bounds__(kThreads) void k_scan_apply_i32(const int32_t* __restrict__ in, int64_t N,
+                                                             int64_t tpb, const int64_t* __restrict__ offs,
+                                                             int64_t* __restrict__ out) {
+    __shared__ int64_t ws[kWaves];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int64_t beg = (int64_t)blockIdx.x * tpb * kTile;
+    const int64_t end = min(N, beg + tpb * (int64_t)kTile);
+    int64_t run = offs[blockIdx.x];
+    for (int64_t c0 = beg; c0 < end; c0 += kThreads) {
+        const int64_t i = c0 + tid;
+        const int64_t v = (i < end) ? (int64_t)in[i] : 0;
+        int64_t x = v;  // inclusive wave scan
+        for (int off = 1; off < 64; off <<= 1) {
+            int64_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) ws[w] = x;
+        __syncthreads();
+        int64_t woff = 0, tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) {
+            woff += (ww < w) ? ws[ww] : 0;
+            tot += ws[ww];
+        }
+        if (i < end) out[i] = run + woff + x - v;
+        run += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void k_copy_total(const int64_t* __restrict__ a, int64_t* __restrict__ dst) { *dst = *a; }
+
+template <class T>
+__global__ void k_fill(T* __restrict__ p, int64_t N, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+void fill_any(T* p, int64_t N, T v, hipStream_t s) {
+    if (N <= 0) return;
+    int64_t blocks = div_up(N, kThreads);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, N, v);
+}
+
+}  // namespace
+
+size_t radix_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * 256 * kMaxBlocks); }
+
+uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch,
+                         hipStream_t s) {
+    if (N <= 1 || nbits <= 0) return a;
+    const int64_t ntiles = div_up(N, kTile);
+    const int NB = grid_blocks(ntiles);
+    const int64_t tpb = div_up(ntiles, NB);
+    int64_t* counts = (int64_t*)scratch;
+    const int passes = (nbits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(NB), dim3(kThreads), 0, s, a, N, shift, tpb, NB, counts);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, counts,
+                           (int64_t)256 * NB, (int64_t*)nullptr);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(NB), dim3(kThreads), 0, s, a, b, N, shift, tpb, NB,
+                           counts);
+        uint64_t* t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+size_t compact_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * (kMaxBlocks + 1)); }
+
+void unique_sorted_u64(const uint64_t* in, int64_t N, uint64_t* out, int64_t* d_count,
+                       void* scratch, hipStream_t s) {
+    if (N <= 0) {
+        fill_any<int64_t>(d_count, 1, 0, s);
+        return;
+    }
+    const int64_t ntiles = div_up(N, kTile);
+    const int NB = grid_blocks(ntiles);
+    const int64_t tpb = div_up(ntiles, NB);
+    int64_t* counts = (int64_t*)scratch;
+    hipLaunchKernelGGL(k_uniq_count, dim3(NB), dim3(kThreads), 0, s, in, N, tpb, counts);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, counts, (int64_t)NB, d_count);
+    hipLaunchKernelGGL(k_uniq_scatter, dim3(NB), dim3(kThreads), 0, s, in, N, tpb, counts, out);
+}
+
+size_t scan_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * (kMaxBlocks + 1)); }
+
+void exclusive_scan_i32_i64(const int32_t* in, int64_t N, int64_t* out, void* scratch,
+                            hipStream_t s) {
+    if (N <= 0) {
+        fill_any<int64_t>(out, 1, 0, s);
+        return;
+    }
+    const int64_t ntiles = div_up(N, kTile);
+    const int NB = grid_blocks(ntiles);
+    const int64_t tpb = div_up(ntiles, NB);
+    int64_t* counts = (int64_t*)scratch;
+    hipLaunchKernelGGL(k_scan_count_i32, dim3(NB), dim3(kThreads), 0, s, in, N, tpb, counts);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, counts, (int64_t)NB, out + N);
+    hipLaunchKernelGGL(k_scan_apply_i32, dim3(NB), dim3(kThreads), 0, s, in, N, tpb, counts, out);
+}
+
+void fill_i32(int32_t* p, int64_t N, int32_t v, hipStream_t s) { fill_any<int32_t>(p, N, v, s); }
+void fill_i64(int64_t* p, int64_t N, int64_t v, hipStream_t s) { fill_any<int64_t>(p, N, v, s); }
+void fill_u32(uint32_t* p, int64_t N, uint32_t v, hipStream_t s) { fill_any<uint32_t>(p, N, v, s); }
+
+}  // namespace mcd

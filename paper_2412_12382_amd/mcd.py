@@ -1,0 +1,288 @@
+"""Thin ctypes binding of libmcd.so (include/mcd.h).
+
+Functions carry the C names and only marshal arguments: torch tensors supply
+device memory (``data_ptr``) and the stream; every step runs in the HIP
+library.  Outputs that the caller does not pass are allocated as torch
+tensors on the context's device.  There is no CPU fallback: if the library is
+not built, importing raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcd.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mcd.h")
+
+MCD_SIM_TECTONIC = 0
+MCD_SIM_TW = 1
+
+STATUS = {0: "MCD_OK", -1: "MCD_ERR_INVALID_ARG", -2: "MCD_ERR_INVALID_VERTEX", -3: "MCD_ERR_RANGE",
+          -4: "MCD_ERR_WORKSPACE", -5: "MCD_ERR_NO_DEVICE", -6: "MCD_ERR_DEVICE",
+          -7: "MCD_ERR_NOT_CONVERGED", -8: "MCD_ERR_EMPTY"}
+
+
+class MCDError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class mcd_rational(ctypes.Structure):
+    _fields_ = [("num", ctypes.c_int64), ("den", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "mcd_ctx_create": [ctypes.c_int, P, PP],
+            "mcd_ctx_set_stream": [P, P],
+            "mcd_ctx_destroy": [P],
+            "mcd_graph_build_sizes": [I64, I64, ctypes.POINTER(SZ), ctypes.POINTER(SZ)],
+            "mcd_graph_build": [P, P, P, I64, I64, P, SZ, P, SZ, PP],
+            "mcd_graph_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32),
+                               ctypes.POINTER(I32)],
+            "mcd_graph_edges": [P, P, P],
+            "mcd_graph_degrees": [P, P],
+            "mcd_graph_destroy": [P],
+            "mcd_triangles": [P, P],
+            "mcd_weights": [P, ctypes.c_int, P, P, P],
+            "mcd_prune": [P, ctypes.c_int, P, mcd_rational, P, P],
+            "mcd_components_workspace_size": [P, ctypes.POINTER(SZ)],
+            "mcd_run_workspace_size": [P, ctypes.POINTER(SZ)],
+            "mcd_components": [P, P, P, P, P, SZ],
+            "mcd_run": [P, ctypes.c_int, mcd_rational, P, P, P, SZ],
+            "mcd_percentile_workspace_size": [P, ctypes.POINTER(SZ)],
+            "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        L.mcd_status_string.argtypes = [ctypes.c_int32]
+        L.mcd_status_string.restype = ctypes.c_char_p
+        L.mcd_last_error.argtypes = []
+        L.mcd_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/mcd.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcd_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != 0:
+        raise MCDError(status, lib().mcd_last_error().decode())
+
+
+def _p(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device: torch.device, stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    def __init__(self, handle, device: torch.device):
+        self.handle = handle
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcd_ctx_destroy(self.handle)
+            self.handle = None
+
+
+@dataclass
+class Graph:
+    handle: ctypes.c_void_p
+    ctx: Context
+    storage: torch.Tensor
+    n: int
+    m: int
+    max_deg: int
+    max_outdeg: int
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcd_graph_destroy(self.handle)
+            self.handle = None
+
+
+def _rat(delta) -> mcd_rational:
+    num, den = delta
+    return mcd_rational(int(num), int(den))
+
+
+def _empty(shape, dtype, device):
+    return torch.empty(shape, dtype=dtype, device=device)
+
+
+def _bytes(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------ context
+
+def mcd_ctx_create(device: int = 0, stream=None) -> Context:
+    dev = torch.device("cuda", device)
+    h = ctypes.c_void_p()
+    _check(lib().mcd_ctx_create(device, _stream_handle(dev, stream), ctypes.byref(h)))
+    return Context(h, dev)
+
+
+def mcd_ctx_set_stream(ctx: Context, stream) -> None:
+    _check(lib().mcd_ctx_set_stream(ctx.handle, _stream_handle(ctx.device, stream)))
+
+
+# -------------------------------------------------------------------- graph
+
+def mcd_graph_build_sizes(n_pairs: int, n_vertices: int) -> tuple[int, int]:
+    st, ws = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mcd_graph_build_sizes(n_pairs, n_vertices, ctypes.byref(st), ctypes.byref(ws)))
+    return st.value, ws.value
+
+
+def mcd_graph_build(ctx: Context, src: torch.Tensor, dst: torch.Tensor, n_vertices: int,
+                    storage: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> Graph:
+    assert src.dtype == torch.int32 and dst.dtype == torch.int32 and src.is_contiguous() and dst.is_contiguous()
+    assert src.numel() == dst.numel() and src.device == ctx.device and dst.device == ctx.device
+    P = src.numel()
+    st_b, ws_b = mcd_graph_build_sizes(P, n_vertices)
+    if storage is None:
+        storage = _bytes(st_b, ctx.device)
+    own_ws = ws is None
+    if own_ws:
+        ws = _bytes(ws_b, ctx.device)
+    h = ctypes.c_void_p()
+    _check(lib().mcd_graph_build(ctx.handle, _p(src), _p(dst), P, n_vertices, _p(storage),
+                                 storage.numel() * storage.element_size(), _p(ws),
+                                 ws.numel() * ws.element_size(), ctypes.byref(h)))
+    if own_ws:
+        del ws
+    n, m = ctypes.c_int64(), ctypes.c_int64()
+    md, mo = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mcd_graph_info(h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(md), ctypes.byref(mo)))
+    return Graph(h, ctx, storage, n.value, m.value, md.value, mo.value)
+
+
+def mcd_graph_info(g: Graph) -> dict:
+    return dict(n=g.n, m=g.m, max_deg=g.max_deg, max_outdeg=g.max_outdeg)
+
+
+def mcd_graph_edges(g: Graph, u=None, v=None):
+    u = _empty(g.m, torch.int32, g.ctx.device) if u is None else u
+    v = _empty(g.m, torch.int32, g.ctx.device) if v is None else v
+    _check(lib().mcd_graph_edges(g.handle, _p(u), _p(v)))
+    return u, v
+
+
+def mcd_graph_degrees(g: Graph, deg=None):
+    deg = _empty(g.n, torch.int32, g.ctx.device) if deg is None else deg
+    _check(lib().mcd_graph_degrees(g.handle, _p(deg)))
+    return deg
+
+
+# -------------------------------------------------------------------- steps
+
+def mcd_triangles(g: Graph, t=None):
+    t = _empty(max(g.m, 1), torch.int32, g.ctx.device) if t is None else t
+    _check(lib().mcd_triangles(g.handle, _p(t)))
+    return t[:g.m]
+
+
+def mcd_weights(g: Graph, measure: int, t, w_f32=None, w_i32=None, want_f32=True, want_i32=False):
+    if w_f32 is None and want_f32:
+        w_f32 = _empty(max(g.m, 1), torch.float32, g.ctx.device)
+    if w_i32 is None and want_i32:
+        w_i32 = _empty(max(g.m, 1), torch.int32, g.ctx.device)
+    _check(lib().mcd_weights(g.handle, measure, _p(t), _p(w_f32), _p(w_i32)))
+    return (None if w_f32 is None else w_f32[:g.m]), (None if w_i32 is None else w_i32[:g.m])
+
+
+def mcd_prune(g: Graph, measure: int, t, delta, keep_bits=None, n_kept=None):
+    words = max((g.m + 31) // 32, 1)
+    keep_bits = _empty(words, torch.int32, g.ctx.device) if keep_bits is None else keep_bits
+    n_kept = _empty(1, torch.int64, g.ctx.device) if n_kept is None else n_kept
+    _check(lib().mcd_prune(g.handle, measure, _p(t), _rat(delta), _p(keep_bits), _p(n_kept)))
+    return keep_bits, n_kept
+
+
+def mcd_components_workspace_size(g: Graph) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_components_workspace_size(g.handle, ctypes.byref(b)))
+    return b.value
+
+
+def mcd_run_workspace_size(g: Graph) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_run_workspace_size(g.handle, ctypes.byref(b)))
+    return b.value
+
+
+def mcd_components(g: Graph, keep_bits=None, labels=None, n_components=None, ws=None):
+    labels = _empty(max(g.n, 1), torch.int32, g.ctx.device) if labels is None else labels
+    n_components = _empty(1, torch.int64, g.ctx.device) if n_components is None else n_components
+    if ws is None:
+        ws = _bytes(mcd_components_workspace_size(g), g.ctx.device)
+    _check(lib().mcd_components(g.handle, _p(keep_bits), _p(labels), _p(n_components), _p(ws),
+                                ws.numel() * ws.element_size()))
+    return labels[:g.n], n_components
+
+
+def mcd_run(g: Graph, measure: int, delta, labels=None, n_components=None, ws=None):
+    labels = _empty(max(g.n, 1), torch.int32, g.ctx.device) if labels is None else labels
+    n_components = _empty(1, torch.int64, g.ctx.device) if n_components is None else n_components
+    if ws is None:
+        ws = _bytes(mcd_run_workspace_size(g), g.ctx.device)
+    _check(lib().mcd_run(g.handle, measure, _rat(delta), _p(labels), _p(n_components), _p(ws),
+                         ws.numel() * ws.element_size()))
+    return labels[:g.n], n_components
+
+
+def mcd_percentile_workspace_size(g: Graph) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_percentile_workspace_size(g.handle, ctypes.byref(b)))
+    return b.value
+
+
+def mcd_percentile_threshold(g: Graph, measure: int, t, pct_num: int, pct_den: int, ws=None):
+    if ws is None:
+        ws = _bytes(mcd_percentile_workspace_size(g), g.ctx.device)
+    out = mcd_rational()
+    _check(lib().mcd_percentile_threshold(g.handle, measure, _p(t), pct_num, pct_den, _p(ws),
+                                          ws.numel() * ws.element_size(), ctypes.byref(out)))
+    return out.num, out.den
+
+
+def mcd_status_string(status: int) -> str:
+    return lib().mcd_status_string(status).decode()
+
+
+def mcd_last_error() -> str:
+    return lib().mcd_last_error().decode()
+

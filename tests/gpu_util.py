@@ -1,0 +1,61 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI and
+bring its outputs into the oracle's canonical edge order (sorted (lo, hi))."""
+import numpy as np
+import torch
+
+import paper_2412_12382_amd.mcd as M
+
+_CTX = None
+
+
+def ctx():
+    global _CTX
+    if _CTX is None:
+        _CTX = M.mcd_ctx_create(0)
+    return _CTX
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to("cuda:0")
+
+
+def unpack_bits(keep_bits, m):
+    w = keep_bits.detach().cpu().numpy().view(np.uint32)
+    bits = np.unpackbits(w.view(np.uint8), bitorder="little")
+    return bits[:m].astype(np.uint8)
+
+
+def build(src, dst, n):
+    return M.mcd_graph_build(ctx(), to_dev(src), to_dev(dst), n)
+
+
+def canonical_order(g):
+    """(lo, hi, order): canonical endpoints and the permutation that sorts
+    library edge order into (lo, hi) order."""
+    u, v = M.mcd_graph_edges(g)
+    u = u.cpu().numpy().astype(np.int64)
+    v = v.cpu().numpy().astype(np.int64)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    order = np.argsort(lo * (g.n + 1) + hi, kind="stable")
+    return lo[order].astype(np.int32), hi[order].astype(np.int32), order
+
+
+def gpu_all(src, dst, n, measure, delta):
+    """Every product of the pipeline on the GPU, canonical edge order."""
+    g = build(src, dst, n)
+    lo, hi, order = canonical_order(g)
+    deg = M.mcd_graph_degrees(g).cpu().numpy()
+    t = M.mcd_triangles(g)
+    wf, wi = M.mcd_weights(g, measure, t, want_f32=True, want_i32=(measure == M.MCD_SIM_TW))
+    keep, nk = M.mcd_prune(g, measure, t, delta)
+    labels, ncc = M.mcd_components(g, keep)
+    labels_run, ncc_run = M.mcd_run(g, measure, delta)
+    torch.cuda.synchronize()
+    out = dict(g=g, lo=lo, hi=hi, deg=deg[:n], t=t.cpu().numpy()[order],
+               w=wf.cpu().numpy()[order] if g.m else np.zeros(0, np.float32),
+               keep=unpack_bits(keep, g.m)[order], n_kept=int(nk.item()),
+               labels=labels.cpu().numpy(), ncc=int(ncc.item()),
+               labels_run=labels_run.cpu().numpy(), ncc_run=int(ncc_run.item()))
+    if wi is not None:
+        out["tw"] = wi.cpu().numpy()[order]
+    return out

@@ -1,0 +1,135 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer products (edges, degrees, triangle counts, TW, keep masks, labels,
+component counts, percentile thresholds) must be bit-exact; fp32 Tectonic
+weights must match the oracle's fp64 value within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+M = pytest.importorskip("paper_2412_12382_amd.mcd")
+
+
+def check_all(src, dst, n, measure, delta):
+    from gpu_util import gpu_all
+    r = gpu_all(src, dst, n, measure, delta)
+    lo, hi = oracle.canon(n, src, dst)
+    assert r["g"].m == len(lo)
+    assert np.array_equal(r["lo"], lo) and np.array_equal(r["hi"], hi)
+    deg = oracle.degrees(n, lo, hi)
+    assert np.array_equal(r["deg"], deg)
+    if len(lo):
+        assert r["g"].max_deg == deg.max()
+    t = oracle.triangles(n, lo, hi)
+    assert np.array_equal(r["t"], t)
+    if measure == oracle.TECTONIC:
+        w = oracle.tectonic(lo, hi, t, deg)
+        assert np.all(np.abs(r["w"].astype(np.float64) - w) <= 1e-6 * np.abs(w))
+        assert np.all((r["w"] == 0) == (w == 0))
+    else:
+        tw = oracle.tw(lo, hi, t, deg)
+        assert np.array_equal(r["tw"].astype(np.int64), tw)
+        assert np.array_equal(r["w"].astype(np.float64), tw.astype(np.float64))
+    keep = oracle.prune(measure, lo, hi, t, deg, *delta)
+    assert np.array_equal(r["keep"], keep)
+    assert r["n_kept"] == int(keep.sum())
+    labels, ncc = oracle.components(n, lo, hi, keep)
+    assert np.array_equal(r["labels"], labels) and r["ncc"] == ncc
+    assert np.array_equal(r["labels_run"], labels) and r["ncc_run"] == ncc
+    return r
+
+
+def test_c1_sbm_tectonic():
+    c1 = gg.sbm_c1()
+    check_all(c1["src"], c1["dst"], c1["n"], oracle.TECTONIC, (3, 50))
+
+
+def test_c1_sbm_tw():
+    c1 = gg.sbm_c1()
+    check_all(c1["src"], c1["dst"], c1["n"], oracle.TW, (-20, 1))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_small_random_graphs(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 300))
+    P = int(rng.integers(0, 6 * n))
+    src = rng.integers(0, n, P).astype(np.int32)
+    dst = rng.integers(0, n, P).astype(np.int32)
+    check_all(src, dst, n, seed % 2, (1, 7) if seed % 2 == 0 else (-3, 2))
+
+
+def test_degenerate_inputs():
+    # no pairs; only self-loops; a single edge; duplicates in both directions
+    check_all(np.zeros(0, np.int32), np.zeros(0, np.int32), 5, oracle.TECTONIC, (0, 1))
+    check_all(np.arange(4, dtype=np.int32), np.arange(4, dtype=np.int32), 4, oracle.TECTONIC, (1, 3))
+    check_all(np.array([1], np.int32), np.array([0], np.int32), 2, oracle.TW, (0, 1))
+    s = np.array([0, 1, 1, 2, 0, 2, 2], np.int32)
+    d = np.array([1, 0, 2, 1, 2, 0, 0], np.int32)
+    check_all(s, d, 3, oracle.TECTONIC, (1, 4))
+    check_all(s, d, 1 << 12, oracle.TECTONIC, (1, 4))  # mostly isolated vertices
+
+
+def test_invalid_vertex_rejected():
+    from gpu_util import build
+    with pytest.raises(M.MCDError) as ei:
+        build(np.array([0, 5], np.int32), np.array([1, 2], np.int32), 5)
+    assert ei.value.status == -2
+    with pytest.raises(M.MCDError) as ei:
+        build(np.array([0, -1], np.int32), np.array([1, 2], np.int32), 5)
+    assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("scale", [12, 16])
+def test_rmat_both_measures(scale):
+    s, d, n = gg.rmat(scale, seed=scale)
+    check_all(s, d, n, oracle.TECTONIC, (1, 20))
+    check_all(s, d, n, oracle.TW, (-10, 1))
+
+
+def test_rmat_percentile_thresholds():
+    from gpu_util import build
+    s, d, n = gg.rmat(14, seed=1)
+    lo, hi = oracle.canon(n, s, d)
+    deg = oracle.degrees(n, lo, hi)
+    t = oracle.triangles(n, lo, hi)
+    g = build(s, d, n)
+    tg = M.mcd_triangles(g)
+    for measure in (oracle.TECTONIC, oracle.TW):
+        for pn, pd in ((3, 10), (1, 2), (1, 1), (1, 1000), (0, 1)):
+            want = oracle.percentile(measure, lo, hi, t, deg, pn, pd)
+            got = M.mcd_percentile_threshold(g, measure, tg, pn, pd)
+            assert got == want, (measure, pn, pd, got, want)
+
+
+def test_percentile_empty():
+    from gpu_util import build
+    s = np.array([0, 2, 4], np.int32)
+    d = np.array([1, 3, 5], np.int32)  # a matching: every t = 0
+    g = build(s, d, 6)
+    t = M.mcd_triangles(g)
+    with pytest.raises(M.MCDError) as ei:
+        M.mcd_percentile_threshold(g, oracle.TECTONIC, t, 3, 10)
+    assert ei.value.status == -8
+
+
+def test_repeat_runs_bit_identical():
+    from gpu_util import build, unpack_bits
+    s, d, n = gg.rmat(15, seed=4)
+    g = build(s, d, n)
+    outs = []
+    for _ in range(3):
+        t = M.mcd_triangles(g)
+        keep, _ = M.mcd_prune(g, oracle.TECTONIC, t, (1, 25))
+        lab, ncc = M.mcd_components(g, keep)
+        torch.cuda.synchronize()
+        outs.append((t.cpu().numpy().copy(), unpack_bits(keep, g.m), lab.cpu().numpy().copy()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
