@@ -171,8 +171,8 @@ mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes);
 
 /* Nearest-rank percentile pct_num/pct_den of the NONZERO similarities: with
  * the K nonzero values in exact ascending order, the value at 0-based index
- * ceil(pct_num K / pct_den) - 1 (at least 0), returned exactly as a rational
- * (Tectonic: t / (deg u + deg v) unreduced; TW: den = 1) in *host_out.
+ * ceil(pct_num K / pct_den) - 1 (at least 0), returned exactly as a reduced
+ * fraction (TW: den = 1) in *host_out.
  * Synchronous.  Errors: MCD_ERR_EMPTY if every similarity is zero. */
 mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                                     int64_t pct_num, int64_t pct_den, void* ws, size_t ws_bytes,

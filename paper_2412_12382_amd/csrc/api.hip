@@ -266,7 +266,7 @@ mcd_status mcd_graph_info(const mcd_graph* g, int64_t* n, int64_t* m, int32_t* m
 }
 
 mcd_status mcd_graph_edges(const mcd_graph* g, int32_t* u, int32_t* v) {
-    REQUIRE(g && u && v, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g && (g->m == 0 || (u && v)), MCD_ERR_INVALID_ARG, "NULL argument");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_edges_orig(g->src, g->adj, g->perm, g->m, u, v, g->ctx->stream);
@@ -274,7 +274,7 @@ mcd_status mcd_graph_edges(const mcd_graph* g, int32_t* u, int32_t* v) {
 }
 
 mcd_status mcd_graph_degrees(const mcd_graph* g, int32_t* deg) {
-    REQUIRE(g && deg, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g && (g->n == 0 || deg), MCD_ERR_INVALID_ARG, "NULL argument");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_scatter_by_perm(g->deg, g->perm, g->n, deg, g->ctx->stream);
@@ -287,7 +287,7 @@ mcd_status mcd_graph_destroy(mcd_graph* g) {
 }
 
 mcd_status mcd_triangles(const mcd_graph* g, int32_t* t) {
-    REQUIRE(g && t, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g && (g->m == 0 || t), MCD_ERR_INVALID_ARG, "NULL argument");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_triangles(g, t, g->ctx->stream);
@@ -296,7 +296,7 @@ mcd_status mcd_triangles(const mcd_graph* g, int32_t* t) {
 
 mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t, float* w_f32,
                        int32_t* w_i32) {
-    REQUIRE(g && t, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g && (g->m == 0 || t), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
     REQUIRE(!(measure == MCD_SIM_TECTONIC && w_i32), MCD_ERR_INVALID_ARG,
             "integer weights exist for TW only");
@@ -308,7 +308,7 @@ mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t
 
 mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
                      uint32_t* keep_bits, int64_t* n_kept) {
-    REQUIRE(g && t && keep_bits, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g && (g->m == 0 || (t && keep_bits)), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
     mcd_status st = check_delta(delta);
     if (st != MCD_OK) return st;
@@ -325,7 +325,7 @@ mcd_status mcd_components_workspace_size(const mcd_graph* g, size_t* bytes) {
 
 mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
                           int64_t* n_components, void* ws, size_t ws_bytes) {
-    REQUIRE(g && labels && ws, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     size_t need = 0;
     mcd_components_workspace_size(g, &need);
     REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "components workspace too small");
@@ -343,7 +343,7 @@ mcd_status mcd_run_workspace_size(const mcd_graph* g, size_t* bytes) {
 
 mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, int32_t* labels,
                    int64_t* n_components, void* ws, size_t ws_bytes) {
-    REQUIRE(g && labels && ws, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
     mcd_status st = check_delta(delta);
     if (st != MCD_OK) return st;
@@ -423,8 +423,14 @@ mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, con
         MCD_HIP(hipStreamSynchronize(s));
         const int64_t c = ctx->h_ctrl[2];
         if (k < c) {
-            host_out->num = num;
-            host_out->den = den;
+            int64_t x = num < 0 ? -num : num, y = den;
+            while (y) {
+                const int64_t r = x % y;
+                x = y;
+                y = r;
+            }
+            host_out->num = num / x;
+            host_out->den = den / x;
             return MCD_OK;
         }
         k -= c;

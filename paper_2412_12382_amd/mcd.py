@@ -195,16 +195,16 @@ def mcd_graph_info(g: Graph) -> dict:
 
 
 def mcd_graph_edges(g: Graph, u=None, v=None):
-    u = _empty(g.m, torch.int32, g.ctx.device) if u is None else u
-    v = _empty(g.m, torch.int32, g.ctx.device) if v is None else v
+    u = _empty(max(g.m, 1), torch.int32, g.ctx.device) if u is None else u
+    v = _empty(max(g.m, 1), torch.int32, g.ctx.device) if v is None else v
     _check(lib().mcd_graph_edges(g.handle, _p(u), _p(v)))
-    return u, v
+    return u[:g.m], v[:g.m]
 
 
 def mcd_graph_degrees(g: Graph, deg=None):
-    deg = _empty(g.n, torch.int32, g.ctx.device) if deg is None else deg
+    deg = _empty(max(g.n, 1), torch.int32, g.ctx.device) if deg is None else deg
     _check(lib().mcd_graph_degrees(g.handle, _p(deg)))
-    return deg
+    return deg[:g.n]
 
 
 # -------------------------------------------------------------------- steps

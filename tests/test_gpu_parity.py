@@ -4,6 +4,9 @@ Integer products (edges, degrees, triangle counts, TW, keep masks, labels,
 component counts, percentile thresholds) must be bit-exact; fp32 Tectonic
 weights must match the oracle's fp64 value within 1e-6 relative.
 """
+import math
+from fractions import Fraction
+
 import numpy as np
 import pytest
 import torch
@@ -103,9 +106,10 @@ def test_rmat_percentile_thresholds():
     tg = M.mcd_triangles(g)
     for measure in (oracle.TECTONIC, oracle.TW):
         for pn, pd in ((3, 10), (1, 2), (1, 1), (1, 1000), (0, 1)):
-            want = oracle.percentile(measure, lo, hi, t, deg, pn, pd)
-            got = M.mcd_percentile_threshold(g, measure, tg, pn, pd)
-            assert got == want, (measure, pn, pd, got, want)
+            want = Fraction(*oracle.percentile(measure, lo, hi, t, deg, pn, pd))
+            num, den = M.mcd_percentile_threshold(g, measure, tg, pn, pd)
+            assert Fraction(num, den) == want, (measure, pn, pd, num, den, want)
+            assert math.gcd(num, den) == 1 and den > 0
 
 
 def test_percentile_empty():
