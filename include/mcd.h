@@ -77,6 +77,14 @@ typedef enum {
 mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out);
 /* Replaces the stream of a context. */
 mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream);
+/* Launch parameters of later calls on this context (results never depend on
+ * them; the autotuner sets them):
+ *   "tc_chunk"   in-edges per triangle-count work item, [1, 2^24], default 512;
+ *   "tc_lds_max" longest out-neighbour row hashed in LDS, [0, 4096], default
+ *                4096; longer rows use the binary-search path.
+ * Errors: MCD_ERR_INVALID_ARG (unknown name), MCD_ERR_RANGE (bad value). */
+mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value);
+mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* value);
 mcd_status mcd_ctx_destroy(mcd_ctx* ctx);
 
 /* Name of a status code (static string). */
@@ -128,10 +136,14 @@ mcd_status mcd_graph_destroy(mcd_graph* g);
 
 /* ----------------------------------------------------------------- steps */
 
+/* Scratch for mcd_triangles with the context's current parameters. */
+mcd_status mcd_triangles_workspace_size(const mcd_graph* g, size_t* bytes);
+
 /* t(e) = |N(u) n N(v)| for every edge e = {u,v} (Sec. 1 notation; Sec. 3.3
  * names this the dominant cost).  Each triangle is found once, from its
- * lowest-ranked edge, and credited to its three edges.  t: device int32[m]. */
-mcd_status mcd_triangles(const mcd_graph* g, int32_t* t);
+ * lowest-ranked edge, and credited to its three edges.  t: device int32[m];
+ * ws: device scratch of mcd_triangles_workspace_size bytes. */
+mcd_status mcd_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes);
 
 /* Edge similarity of Table tab:simfunctions from t (as produced by
  * mcd_triangles).  w_f32 (device float[m], may be NULL): the measure in IEEE

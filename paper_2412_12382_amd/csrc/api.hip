@@ -52,6 +52,8 @@ struct StorageLayout {
     int32_t* adj;
     int32_t* deg;
     int32_t* perm;
+    int64_t* in_off;
+    int32_t* in_e;
     size_t bytes;
 };
 
@@ -63,6 +65,8 @@ StorageLayout storage_layout(void* base, int64_t P, int64_t n) {
     L.adj = c.take<int32_t>((size_t)P);
     L.deg = c.take<int32_t>((size_t)n);
     L.perm = c.take<int32_t>((size_t)n);
+    L.in_off = c.take<int64_t>((size_t)n + 1);
+    L.in_e = c.take<int32_t>((size_t)P);
     L.bytes = c.used;
     return L;
 }
@@ -101,6 +105,7 @@ struct RunLayout {
     int32_t* t;
     uint32_t* keep;
     int32_t* parent;
+    void* tc;
     size_t bytes;
 };
 
@@ -110,6 +115,7 @@ RunLayout run_layout(void* base, const mcd_graph* g) {
     L.t = c.take<int32_t>((size_t)g->m);
     L.keep = c.take<uint32_t>((size_t)(g->m + 31) / 32);
     L.parent = c.take<int32_t>((size_t)g->n);
+    L.tc = c.take<char>(mcd::tc_scratch_bytes(g, g->ctx->tc_chunk));
     L.bytes = c.used;
     return L;
 }
@@ -153,6 +159,8 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
     mcd_ctx* c = new mcd_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
+    c->tc_chunk = 512;
+    c->tc_lds_max = MCD_TC_LDS_LIMIT;
     if (hipMalloc((void**)&c->d_ctrl, sizeof(int64_t) * MCD_CTRL_WORDS) != hipSuccess) {
         delete c;
         return mcd_fail(MCD_ERR_DEVICE, "hipMalloc of the control block failed");
@@ -170,6 +178,30 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
 mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream) {
     REQUIRE(ctx, MCD_ERR_INVALID_ARG, "ctx is NULL");
     ctx->stream = (hipStream_t)stream;
+    return MCD_OK;
+}
+
+mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value) {
+    REQUIRE(ctx && name, MCD_ERR_INVALID_ARG, "NULL argument");
+    const std::string k(name);
+    if (k == "tc_chunk") {
+        REQUIRE(value >= 1 && value <= (1 << 24), MCD_ERR_RANGE, "tc_chunk must lie in [1, 2^24]");
+        ctx->tc_chunk = value;
+    } else if (k == "tc_lds_max") {
+        REQUIRE(value >= 0 && value <= MCD_TC_LDS_LIMIT, MCD_ERR_RANGE, "tc_lds_max must lie in [0, 4096]");
+        ctx->tc_lds_max = value;
+    } else {
+        return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
+    }
+    return MCD_OK;
+}
+
+mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* value) {
+    REQUIRE(ctx && name && value, MCD_ERR_INVALID_ARG, "NULL argument");
+    const std::string k(name);
+    if (k == "tc_chunk") *value = ctx->tc_chunk;
+    else if (k == "tc_lds_max") *value = ctx->tc_lds_max;
+    else return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     return MCD_OK;
 }
 
@@ -236,6 +268,11 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     mcd::exclusive_scan_i32_i64(B.outdeg, n, G.off, B.scan, s);
     mcd::launch_max_i32(B.outdeg, n, ctrl + 2, s);
     mcd::launch_max_i32(G.deg, n, ctrl + 3, s);
+    // in-edge lists (edges grouped by head), in-degree = degree - out-degree
+    mcd::launch_in_count(G.deg, B.outdeg, n, B.inv, s);
+    mcd::exclusive_scan_i32_i64(B.inv, n, G.in_off, B.scan, s);
+    mcd::fill_i32(B.deg_orig, n, 0, s);
+    mcd::launch_in_scatter(G.adj, m, G.in_off, B.deg_orig, G.in_e, s);
     if ((st = sync_read(ctx, ctrl, ctx->h_ctrl, 4)) != MCD_OK) return st;
 
     mcd_graph* g = new mcd_graph();
@@ -251,6 +288,8 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     g->adj = G.adj;
     g->deg = G.deg;
     g->perm = G.perm;
+    g->in_off = G.in_off;
+    g->in_e = G.in_e;
     *out = g;
     return MCD_OK;
 }
@@ -286,11 +325,20 @@ mcd_status mcd_graph_destroy(mcd_graph* g) {
     return MCD_OK;
 }
 
-mcd_status mcd_triangles(const mcd_graph* g, int32_t* t) {
-    REQUIRE(g && (g->m == 0 || t), MCD_ERR_INVALID_ARG, "NULL argument");
+mcd_status mcd_triangles_workspace_size(const mcd_graph* g, size_t* bytes) {
+    REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
+    *bytes = mcd::tc_scratch_bytes(g, g->ctx->tc_chunk);
+    return MCD_OK;
+}
+
+mcd_status mcd_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes) {
+    REQUIRE(g && (g->m == 0 || (t && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
+    size_t need = 0;
+    mcd_triangles_workspace_size(g, &need);
+    REQUIRE(g->m == 0 || ws_bytes >= need, MCD_ERR_WORKSPACE, "triangle workspace too small");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
-    mcd::launch_triangles(g, t, g->ctx->stream);
+    mcd::launch_triangles(g, t, ws, g->ctx->tc_chunk, g->ctx->tc_lds_max, g->ctx->stream);
     return MCD_OK;
 }
 
@@ -353,7 +401,7 @@ mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, 
     if ((st = use_device(g->ctx)) != MCD_OK) return st;
     RunLayout L = run_layout(ws, g);
     hipStream_t s = g->ctx->stream;
-    mcd::launch_triangles(g, L.t, s);
+    mcd::launch_triangles(g, L.t, L.tc, g->ctx->tc_chunk, g->ctx->tc_lds_max, s);
     mcd::launch_prune(g, measure, L.t, delta.num, delta.den, L.keep, nullptr, s);
     mcd::launch_components(g, L.keep, labels, n_components, L.parent, s);
     return MCD_OK;

@@ -138,7 +138,36 @@ __global__ __launch_bounds__(kThreads) void k_scatter_by_perm(const int32_t* __r
     GRID_STRIDE(v, n) out[perm[v]] = val[v];
 }
 
+__global__ __launch_bounds__(kThreads) void k_in_count(const int32_t* __restrict__ deg,
+                                                       const int32_t* __restrict__ outdeg, int64_t n,
+                                                       int32_t* __restrict__ in_cnt) {
+    GRID_STRIDE(v, n) in_cnt[v] = deg[v] - outdeg[v];
+}
+
+__global__ __launch_bounds__(kThreads) void k_in_scatter(const int32_t* __restrict__ adj, int64_t m,
+                                                         const int64_t* __restrict__ in_off,
+                                                         int32_t* __restrict__ fill,
+                                                         int32_t* __restrict__ in_e) {
+    GRID_STRIDE(e, m) {
+        const int32_t v = adj[e];
+        const int32_t k = atomicAdd(&fill[v], 1);
+        in_e[in_off[v] + k] = (int32_t)e;
+    }
+}
+
 }  // namespace
+
+void launch_in_count(const int32_t* deg, const int32_t* outdeg, int64_t n, int32_t* in_cnt,
+                     hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_in_count, dim3(grid_for(n)), dim3(kThreads), 0, s, deg, outdeg, n, in_cnt);
+}
+
+void launch_in_scatter(const int32_t* adj, int64_t m, const int64_t* in_off, int32_t* fill,
+                       int32_t* in_e, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_in_scatter, dim3(grid_for(m)), dim3(kThreads), 0, s, adj, m, in_off, fill, in_e);
+}
 
 void launch_canon(const int32_t* src, const int32_t* dst, int64_t P, int64_t n, int bits,
                   uint64_t* keys, int64_t* d_err, hipStream_t s) {

@@ -17,7 +17,11 @@ struct mcd_ctx {
     hipStream_t stream;
     int64_t* d_ctrl;   // device control block: flags and counters (MCD_CTRL_WORDS int64)
     int64_t* h_ctrl;   // pinned host mirror for scalar read-backs
+    // tunable launch parameters (mcd_ctx_set_param)
+    int64_t tc_chunk;    // in-edges per triangle work item
+    int64_t tc_lds_max;  // longest row hashed in LDS; longer rows use binary search
 };
+#define MCD_TC_LDS_LIMIT 4096
 #define MCD_CTRL_WORDS 64
 
 struct mcd_graph {
@@ -35,6 +39,8 @@ struct mcd_graph {
     int32_t* adj;      // [cap] head (new id) of every edge; rows sorted ascending
     int32_t* deg;      // [n]   degree by new id (non-decreasing)
     int32_t* perm;     // [n]   original id of every new id
+    int64_t* in_off;   // [n+1] offsets of the in-edge lists
+    int32_t* in_e;     // [cap] ids of the edges x->v, grouped by head v
 };
 
 // Thread-local error reporting used by the ABI layer.
@@ -101,9 +107,17 @@ void launch_edges_orig(const int32_t* src, const int32_t* adj, const int32_t* pe
                        int32_t* u, int32_t* v, hipStream_t s);
 void launch_scatter_by_perm(const int32_t* val_new, const int32_t* perm, int64_t n,
                             int32_t* out_orig, hipStream_t s);
+// in_cnt[v] = deg[v] - outdeg[v]
+void launch_in_count(const int32_t* deg, const int32_t* outdeg, int64_t n, int32_t* in_cnt,
+                     hipStream_t s);
+// in_e[in_off[v] + k] = edges with head v (fill: zeroed int32[n] counters)
+void launch_in_scatter(const int32_t* adj, int64_t m, const int64_t* in_off, int32_t* fill,
+                       int32_t* in_e, hipStream_t s);
 
 // ---- triangles (tc.hip) ----
-void launch_triangles(const mcd_graph* g, int32_t* t, hipStream_t s);
+size_t tc_scratch_bytes(const mcd_graph* g, int64_t chunk);
+void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, int64_t lds_max,
+                      hipStream_t s);
 
 // ---- weights / prune (weight.hip) ----
 void launch_weights(const mcd_graph* g, int measure, const int32_t* t, float* wf, int32_t* wi,

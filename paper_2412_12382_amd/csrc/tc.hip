@@ -2,12 +2,23 @@
 // orientation.
 //
 // Vertices are numbered by rank, every edge points from the lower to the
-// higher id, and row u of the CSR lists N+(u) (out-neighbours) in increasing
-// id.  A triangle {u < v < w} is found exactly once, at edge u->v, as the
-// common element w of N+(u) and N+(v).  Only the part of N+(u) after v can
-// meet N+(v) (whose ids all exceed v).  Each find credits the three edges
-// u->v, u->w and v->w; integer atomics are commutative, so the counts do not
-// depend on scheduling.
+// higher id, and row x of the CSR lists N+(x) in increasing id.  A triangle
+// {u < v < w} is found exactly once: at the edge u->v, as an element w of the
+// part of N+(u) after v that also lies in N+(v).  The work is organised around
+// the middle vertex v: a work item is v together with a slice of its in-edges
+// u->v.  The workgroup hashes N+(v) into LDS (key w -> position in N+(v)) and
+// every wave streams, for one in-edge at a time, the suffix of row u after v
+// in 64-element coalesced chunks, probing each element.  A hit w credits
+//     t(u,v) : one atomic per in-edge (wave ballot count),
+//     t(u,w) : a global atomic at the suffix position (same cache lines just read),
+//     t(v,w) : an LDS counter of v's row, flushed once per work item.
+// The probe count is the sum over edges of |suffix of N+(u) after v|, the
+// smallest list the intersection needs to scan.  All increments are integer
+// atomics, so the counts do not depend on scheduling.
+//
+// Items are grouped by |N+(v)| into LDS size classes (a wave, two waves or
+// four waves per item); rows longer than the largest class (or than the
+// configured cap) take a binary-search path.
 #include "common.hpp"
 
 namespace mcd {
@@ -15,7 +26,121 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// First index in [lo, hi) whose value is >= x.
+struct Item {
+    int32_t v;
+    int32_t pad;
+    int64_t s;  // first in-edge slot (index into in_e)
+};
+
+__device__ __forceinline__ void add_relaxed(int32_t* p, int32_t x) {
+    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int LOG2S>
+__device__ __forceinline__ uint32_t slot_of(int32_t w) {
+    const uint32_t x = (uint32_t)w;
+    return (x ^ (x >> LOG2S)) & ((1u << LOG2S) - 1u);
+}
+
+// One item per WPI waves; 4/WPI items per workgroup.  LOG2S: log2 of hash
+// slots; rows up to 2^(LOG2S-1) out-neighbours.
+template <int LOG2S, int WPI>
+__global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ all_items,
+                                                       const int64_t* __restrict__ heads, int cls,
+                                                       int64_t chunk,
+                                                       const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ src,
+                                                       const int32_t* __restrict__ adj,
+                                                       const int64_t* __restrict__ in_off,
+                                                       const int32_t* __restrict__ in_e,
+                                                       int32_t* __restrict__ t) {
+    constexpr int S = 1 << LOG2S;
+    constexpr int NI = 4 / WPI;
+    constexpr int MAXB = S / 2;
+    __shared__ int32_t keys[NI][S];
+    __shared__ uint16_t pos[NI][S];
+    __shared__ int32_t cnt[NI][MAXB];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = wave / WPI;         // which item of the workgroup
+    const int wsub = wave % WPI;         // wave index inside the item
+    const int tsub = threadIdx.x % (64 * WPI);
+    const Item* __restrict__ items = all_items + heads[2 * cls];
+    const int64_t n_items = heads[2 * cls + 1];
+
+    for (int64_t base = (int64_t)blockIdx.x * NI; base < n_items; base += (int64_t)gridDim.x * NI) {
+        const int64_t it = base + slot;
+        const bool have = it < n_items;
+        int32_t v = 0;
+        int64_t s = 0, s_end = 0, b0 = 0;
+        int32_t B = 0;
+        if (have) {
+            const Item I = items[it];
+            v = I.v;
+            s = I.s;
+            s_end = min(I.s + chunk, in_off[v + 1]);
+            b0 = off[v];
+            B = (int32_t)(off[v + 1] - b0);
+        }
+        for (int i = tsub; i < S; i += 64 * WPI) keys[slot][i] = -1;
+        for (int i = tsub; i < MAXB; i += 64 * WPI) cnt[slot][i] = 0;
+        __syncthreads();
+        int32_t maxv = -1;
+        if (have) {
+            for (int j = tsub; j < B; j += 64 * WPI) {
+                const int32_t w = adj[b0 + j];
+                uint32_t h = slot_of<LOG2S>(w);
+                while (atomicCAS(&keys[slot][h], -1, w) != -1) h = (h + 1) & (S - 1);
+                pos[slot][h] = (uint16_t)j;
+            }
+            maxv = adj[b0 + B - 1];
+        }
+        __syncthreads();
+        if (have) {
+            for (int64_t k = s + wsub; k < s_end; k += WPI) {
+                const int64_t e = in_e[k];
+                const int32_t u = src[e];
+                const int64_t a1 = off[u + 1];
+                uint32_t c = 0;
+                for (int64_t cb = e + 1; cb < a1; cb += 64) {
+                    const int64_t i = cb + lane;
+                    const bool valid = i < a1;
+                    const int32_t w = valid ? adj[i] : INT32_MAX;
+                    const bool cand = valid && w <= maxv;
+                    if (__ballot(cand) == 0) break;  // suffix sorted: nothing further can match
+                    bool hit = false;
+                    if (cand) {
+                        uint32_t h = slot_of<LOG2S>(w);
+                        for (;;) {
+                            const int32_t kk = keys[slot][h];
+                            if (kk == w) {
+                                hit = true;
+                                break;
+                            }
+                            if (kk == -1) break;
+                            h = (h + 1) & (S - 1);
+                        }
+                        if (hit) {
+                            atomicAdd(&cnt[slot][pos[slot][h]], 1);
+                            add_relaxed(&t[i], 1);
+                        }
+                    }
+                    c += (uint32_t)__popcll(__ballot(hit));
+                }
+                if (lane == 0 && c) add_relaxed(&t[e], (int32_t)c);
+            }
+        }
+        __syncthreads();
+        if (have) {
+            for (int j = tsub; j < B; j += 64 * WPI) {
+                const int32_t x = cnt[slot][j];
+                if (x) add_relaxed(&t[b0 + j], x);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ int64_t lower_bound(const int32_t* __restrict__ a, int64_t lo, int64_t hi,
                                                int32_t x) {
     while (lo < hi) {
@@ -26,54 +151,170 @@ __device__ __forceinline__ int64_t lower_bound(const int32_t* __restrict__ a, in
     return lo;
 }
 
-__global__ __launch_bounds__(kThreads) void k_tc_edge(const int64_t* __restrict__ off,
-                                                      const int32_t* __restrict__ src,
-                                                      const int32_t* __restrict__ adj, int64_t m,
-                                                      int32_t* __restrict__ t) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t u = src[e], v = adj[e];
-        int64_t a0 = e + 1, a1 = off[u + 1];
-        int64_t b0 = off[v], b1 = off[v + 1];
-        if (a0 >= a1 || b0 >= b1) continue;
-        int32_t c = 0;
-        if (a1 - a0 <= b1 - b0) {
-            // walk N+(u) after v, search each w in N+(v); searches move right
-            for (int64_t i = a0; i < a1 && b0 < b1; ++i) {
+// Rows too long for LDS: one thread per in-edge u->v, each suffix element of
+// N+(u) searched in N+(v) (searches move right).
+__global__ __launch_bounds__(kThreads) void k_tc_search(const Item* __restrict__ all_items,
+                                                        const int64_t* __restrict__ heads, int cls,
+                                                        int64_t chunk,
+                                                        const int64_t* __restrict__ off,
+                                                        const int32_t* __restrict__ src,
+                                                        const int32_t* __restrict__ adj,
+                                                        const int64_t* __restrict__ in_off,
+                                                        const int32_t* __restrict__ in_e,
+                                                        int32_t* __restrict__ t) {
+    const Item* __restrict__ items = all_items + heads[2 * cls];
+    const int64_t n_items = heads[2 * cls + 1];
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const Item I = items[it];
+        const int32_t v = I.v;
+        const int64_t s_end = min(I.s + chunk, in_off[v + 1]);
+        const int64_t bb = off[v], be = off[v + 1];
+        for (int64_t k = I.s + threadIdx.x; k < s_end; k += blockDim.x) {
+            const int64_t e = in_e[k];
+            const int64_t a1 = off[src[e] + 1];
+            int64_t b = bb;
+            int32_t c = 0;
+            for (int64_t i = e + 1; i < a1 && b < be; ++i) {
                 const int32_t w = adj[i];
-                b0 = lower_bound(adj, b0, b1, w);
-                if (b0 < b1 && adj[b0] == w) {
-                    atomicAdd(&t[i], 1);
-                    atomicAdd(&t[b0], 1);
+                b = lower_bound(adj, b, be, w);
+                if (b < be && adj[b] == w) {
+                    add_relaxed(&t[i], 1);
+                    add_relaxed(&t[b], 1);
                     ++c;
-                    ++b0;
+                    ++b;
                 }
             }
-        } else {
-            for (int64_t j = b0; j < b1 && a0 < a1; ++j) {
-                const int32_t w = adj[j];
-                a0 = lower_bound(adj, a0, a1, w);
-                if (a0 < a1 && adj[a0] == w) {
-                    atomicAdd(&t[a0], 1);
-                    atomicAdd(&t[j], 1);
-                    ++c;
-                    ++a0;
-                }
+            if (c) add_relaxed(&t[e], c);
+        }
+    }
+}
+
+constexpr int kClasses = 5;  // LDS classes 0..3, search class 4
+constexpr int kMaxB[4] = {128, 512, 2048, 4096};
+
+// Number of work items of vertex v in each class (one class is non-zero).
+__global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restrict__ off,
+                                                         const int64_t* __restrict__ in_off, int64_t n,
+                                                         int64_t chunk, int64_t lds_max,
+                                                         int32_t* __restrict__ cnt) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t B = off[v + 1] - off[v];
+        const int64_t I = in_off[v + 1] - in_off[v];
+        int cls = -1;
+        if (B > 0 && I > 0) {
+            cls = 4;
+            if (B <= lds_max) {
+                for (int c = 3; c >= 0; --c)
+                    if (B <= kMaxB[c]) cls = c;
             }
         }
-        if (c) atomicAdd(&t[e], c);
+        const int32_t k = cls >= 0 ? (int32_t)((I + chunk - 1) / chunk) : 0;
+        for (int c = 0; c < kClasses; ++c) cnt[(int64_t)c * n + v] = (c == cls) ? k : 0;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_item_fill(const int64_t* __restrict__ in_off, int64_t n,
+                                                        int64_t chunk, const int32_t* __restrict__ cnt,
+                                                        const int64_t* __restrict__ base,
+                                                        Item* __restrict__ items) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < kClasses; ++c) {
+            const int32_t k = cnt[(int64_t)c * n + v];
+            if (!k) continue;
+            // class lists are laid out one after another: base of class c is
+            // the total of the earlier classes
+            int64_t b = base[(int64_t)c * (n + 1) + v];
+            for (int cc = 0; cc < c; ++cc) b += base[(int64_t)cc * (n + 1) + n];
+            for (int32_t j = 0; j < k; ++j) {
+                Item I;
+                I.v = (int32_t)v;
+                I.pad = 0;
+                I.s = in_off[v] + (int64_t)j * chunk;
+                items[b + j] = I;
+            }
+        }
+    }
+}
+
+// Offsets of the class lists and their lengths, on the device.
+__global__ void k_item_heads(const int64_t* __restrict__ base, int64_t n, int64_t* __restrict__ heads) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        const int64_t len = base[(int64_t)c * (n + 1) + n];
+        heads[2 * c] = acc;
+        heads[2 * c + 1] = len;
+        acc += len;
+    }
+}
+
+inline unsigned grid_for(int64_t N, int64_t cap) {
+    int64_t b = (N + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+struct TcLayout {
+    int32_t* cnt;    // [kClasses][n]
+    int64_t* base;   // [kClasses][n+1]
+    Item* items;     // [max items]
+    int64_t* heads;  // [2*kClasses]: start, length per class
+    void* scan;
+    size_t bytes;
+};
+
+TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
+    Carve c{(char*)p, 0, 0};
+    TcLayout L;
+    const int64_t n = g->n;
+    const int64_t max_items = n + g->m / (chunk > 0 ? chunk : 1) + 1;
+    L.cnt = c.take<int32_t>((size_t)kClasses * n);
+    L.base = c.take<int64_t>((size_t)kClasses * (n + 1));
+    L.items = c.take<Item>((size_t)max_items);
+    L.heads = c.take<int64_t>(2 * kClasses);
+    L.scan = c.take<char>(scan_scratch_bytes(n));
+    L.bytes = c.used;
+    return L;
+}
+
+template <int LOG2S, int WPI>
+void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
+    constexpr int NI = 4 / WPI;
+    // grid-stride over the class list; its length is read on the device
+    const int64_t cap_items = g->n + g->m / chunk + 1;
+    int64_t blocks = (cap_items + NI - 1) / NI;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL((k_tc_items<LOG2S, WPI>), dim3((unsigned)blocks), dim3(kThreads), 0, s, L.items,
+                       L.heads, c, chunk, g->off, g->src, g->adj, g->in_off, g->in_e, t);
 }
 
 }  // namespace
 
-void launch_triangles(const mcd_graph* g, int32_t* t, hipStream_t s) {
+size_t tc_scratch_bytes(const mcd_graph* g, int64_t chunk) { return tc_layout(nullptr, g, chunk).bytes; }
+
+void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, int64_t lds_max,
+                      hipStream_t s) {
     fill_i32(t, g->m, 0, s);
-    if (g->m <= 0) return;
-    int64_t blocks = (g->m + kThreads - 1) / kThreads;
-    if (blocks > 1 << 20) blocks = 1 << 20;
-    hipLaunchKernelGGL(k_tc_edge, dim3((unsigned)blocks), dim3(kThreads), 0, s, g->off, g->src, g->adj,
-                       g->m, t);
+    if (g->m <= 0 || g->n <= 0) return;
+    if (chunk < 1) chunk = 1;
+    TcLayout L = tc_layout(ws, g, chunk);
+    const int64_t n = g->n;
+    hipLaunchKernelGGL(k_item_count, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
+                       chunk, lds_max, L.cnt);
+    for (int c = 0; c < kClasses; ++c)
+        exclusive_scan_i32_i64(L.cnt + (int64_t)c * n, n, L.base + (int64_t)c * (n + 1), L.scan, s);
+    hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->in_off, n, chunk,
+                       L.cnt, L.base, L.items);
+    hipLaunchKernelGGL(k_item_heads, dim3(1), dim3(64), 0, s, L.base, n, L.heads);
+    launch_class<8, 1>(g, L, 0, chunk, t, s);
+    launch_class<10, 2>(g, L, 1, chunk, t, s);
+    launch_class<12, 4>(g, L, 2, chunk, t, s);
+    launch_class<13, 4>(g, L, 3, chunk, t, s);
+    hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, 4, chunk, g->off,
+                       g->src, g->adj, g->in_off, g->in_e, t);
 }
 
 }  // namespace mcd

@@ -52,6 +52,9 @@ def lib():
         sig = {
             "mcd_ctx_create": [ctypes.c_int, P, PP],
             "mcd_ctx_set_stream": [P, P],
+            "mcd_ctx_set_param": [P, ctypes.c_char_p, I64],
+            "mcd_ctx_get_param": [P, ctypes.c_char_p, ctypes.POINTER(I64)],
+            "mcd_triangles_workspace_size": [P, ctypes.POINTER(SZ)],
             "mcd_ctx_destroy": [P],
             "mcd_graph_build_sizes": [I64, I64, ctypes.POINTER(SZ), ctypes.POINTER(SZ)],
             "mcd_graph_build": [P, P, P, I64, I64, P, SZ, P, SZ, PP],
@@ -60,7 +63,7 @@ def lib():
             "mcd_graph_edges": [P, P, P],
             "mcd_graph_degrees": [P, P],
             "mcd_graph_destroy": [P],
-            "mcd_triangles": [P, P],
+            "mcd_triangles": [P, P, P, SZ],
             "mcd_weights": [P, ctypes.c_int, P, P, P],
             "mcd_prune": [P, ctypes.c_int, P, mcd_rational, P, P],
             "mcd_components_workspace_size": [P, ctypes.POINTER(SZ)],
@@ -159,6 +162,16 @@ def mcd_ctx_set_stream(ctx: Context, stream) -> None:
     _check(lib().mcd_ctx_set_stream(ctx.handle, _stream_handle(ctx.device, stream)))
 
 
+def mcd_ctx_set_param(ctx: Context, name: str, value: int) -> None:
+    _check(lib().mcd_ctx_set_param(ctx.handle, name.encode(), int(value)))
+
+
+def mcd_ctx_get_param(ctx: Context, name: str) -> int:
+    v = ctypes.c_int64()
+    _check(lib().mcd_ctx_get_param(ctx.handle, name.encode(), ctypes.byref(v)))
+    return v.value
+
+
 # -------------------------------------------------------------------- graph
 
 def mcd_graph_build_sizes(n_pairs: int, n_vertices: int) -> tuple[int, int]:
@@ -209,9 +222,17 @@ def mcd_graph_degrees(g: Graph, deg=None):
 
 # -------------------------------------------------------------------- steps
 
-def mcd_triangles(g: Graph, t=None):
+def mcd_triangles_workspace_size(g: Graph) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_triangles_workspace_size(g.handle, ctypes.byref(b)))
+    return b.value
+
+
+def mcd_triangles(g: Graph, t=None, ws=None):
     t = _empty(max(g.m, 1), torch.int32, g.ctx.device) if t is None else t
-    _check(lib().mcd_triangles(g.handle, _p(t)))
+    if ws is None:
+        ws = _bytes(mcd_triangles_workspace_size(g), g.ctx.device)
+    _check(lib().mcd_triangles(g.handle, _p(t), _p(ws), ws.numel() * ws.element_size()))
     return t[:g.m]
 
 

@@ -137,3 +137,49 @@ def test_repeat_runs_bit_identical():
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("chunk,lds_max", [(512, 4096), (1, 4096), (7, 100), (64, 0), (3, 600), (100000, 2048)])
+def test_triangle_paths_and_chunks(chunk, lds_max):
+    # every launch configuration (work-item size, LDS classes vs binary search)
+    # must give the oracle's counts
+    from gpu_util import ctx, build
+    s, d, n = gg.rmat(15, seed=21)
+    lo, hi = oracle.canon(n, s, d)
+    t_o = oracle.triangles(n, lo, hi)
+    c = ctx()
+    old = (M.mcd_ctx_get_param(c, "tc_chunk"), M.mcd_ctx_get_param(c, "tc_lds_max"))
+    try:
+        M.mcd_ctx_set_param(c, "tc_chunk", chunk)
+        M.mcd_ctx_set_param(c, "tc_lds_max", lds_max)
+        from gpu_util import canonical_order
+        g = build(s, d, n)
+        _, _, order = canonical_order(g)
+        t = M.mcd_triangles(g).cpu().numpy()[order]
+        assert np.array_equal(t, t_o)
+    finally:
+        M.mcd_ctx_set_param(c, "tc_chunk", old[0])
+        M.mcd_ctx_set_param(c, "tc_lds_max", old[1])
+
+
+def test_param_validation():
+    from gpu_util import ctx
+    c = ctx()
+    for name, bad in (("tc_chunk", 0), ("tc_lds_max", 5000), ("tc_lds_max", -1)):
+        with pytest.raises(M.MCDError) as ei:
+            M.mcd_ctx_set_param(c, name, bad)
+        assert ei.value.status == -3
+    with pytest.raises(M.MCDError) as ei:
+        M.mcd_ctx_set_param(c, "no_such_param", 1)
+    assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("k", [5, 130, 700])
+def test_complete_graph_closed_form(k):
+    # K_k: every edge lies in k-2 triangles (rows longer than the small LDS classes)
+    from gpu_util import build
+    i, j = np.triu_indices(k, 1)
+    g = build(i.astype(np.int32), j.astype(np.int32), k)
+    t = M.mcd_triangles(g).cpu().numpy()
+    assert g.m == k * (k - 1) // 2 and np.all(t == k - 2)
+    assert g.max_outdeg == k - 1
