@@ -35,7 +35,7 @@ def test_null_arguments_rejected_without_device():
     L = M.lib()
     assert L.mcd_ctx_create(0, None, None) == -1
     assert L.mcd_graph_info(None, None, None, None, None) == -1
-    assert L.mcd_triangles(None, None) == -1
+    assert L.mcd_triangles(None, None, None, 0) == -1
     assert L.mcd_run(None, 0, M.mcd_rational(1, 2), None, None, None, 0) == -1
 
 
