@@ -53,7 +53,7 @@ struct StorageLayout {
     int32_t* deg;
     int32_t* perm;
     int64_t* in_off;
-    int32_t* in_e;
+    int2* in_ea;
     size_t bytes;
 };
 
@@ -66,7 +66,7 @@ StorageLayout storage_layout(void* base, int64_t P, int64_t n) {
     L.deg = c.take<int32_t>((size_t)n);
     L.perm = c.take<int32_t>((size_t)n);
     L.in_off = c.take<int64_t>((size_t)n + 1);
-    L.in_e = c.take<int32_t>((size_t)P);
+    L.in_ea = c.take<int2>((size_t)P);
     L.bytes = c.used;
     return L;
 }
@@ -272,7 +272,7 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     mcd::launch_in_count(G.deg, B.outdeg, n, B.inv, s);
     mcd::exclusive_scan_i32_i64(B.inv, n, G.in_off, B.scan, s);
     mcd::fill_i32(B.deg_orig, n, 0, s);
-    mcd::launch_in_scatter(G.adj, m, G.in_off, B.deg_orig, G.in_e, s);
+    mcd::launch_in_scatter(G.src, G.adj, G.off, m, G.in_off, B.deg_orig, G.in_ea, s);
     if ((st = sync_read(ctx, ctrl, ctx->h_ctrl, 4)) != MCD_OK) return st;
 
     mcd_graph* g = new mcd_graph();
@@ -289,7 +289,7 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     g->deg = G.deg;
     g->perm = G.perm;
     g->in_off = G.in_off;
-    g->in_e = G.in_e;
+    g->in_ea = G.in_ea;
     *out = g;
     return MCD_OK;
 }

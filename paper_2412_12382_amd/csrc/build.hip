@@ -144,14 +144,16 @@ __global__ __launch_bounds__(kThreads) void k_in_count(const int32_t* __restrict
     GRID_STRIDE(v, n) in_cnt[v] = deg[v] - outdeg[v];
 }
 
-__global__ __launch_bounds__(kThreads) void k_in_scatter(const int32_t* __restrict__ adj, int64_t m,
+__global__ __launch_bounds__(kThreads) void k_in_scatter(const int32_t* __restrict__ src,
+                                                         const int32_t* __restrict__ adj,
+                                                         const int64_t* __restrict__ off, int64_t m,
                                                          const int64_t* __restrict__ in_off,
                                                          int32_t* __restrict__ fill,
-                                                         int32_t* __restrict__ in_e) {
+                                                         int2* __restrict__ in_ea) {
     GRID_STRIDE(e, m) {
         const int32_t v = adj[e];
         const int32_t k = atomicAdd(&fill[v], 1);
-        in_e[in_off[v] + k] = (int32_t)e;
+        in_ea[in_off[v] + k] = make_int2((int32_t)e, (int32_t)(off[src[e] + 1] - e - 1));
     }
 }
 
@@ -163,10 +165,11 @@ void launch_in_count(const int32_t* deg, const int32_t* outdeg, int64_t n, int32
     hipLaunchKernelGGL(k_in_count, dim3(grid_for(n)), dim3(kThreads), 0, s, deg, outdeg, n, in_cnt);
 }
 
-void launch_in_scatter(const int32_t* adj, int64_t m, const int64_t* in_off, int32_t* fill,
-                       int32_t* in_e, hipStream_t s) {
+void launch_in_scatter(const int32_t* src, const int32_t* adj, const int64_t* off, int64_t m,
+                       const int64_t* in_off, int32_t* fill, int2* in_ea, hipStream_t s) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_in_scatter, dim3(grid_for(m)), dim3(kThreads), 0, s, adj, m, in_off, fill, in_e);
+    hipLaunchKernelGGL(k_in_scatter, dim3(grid_for(m)), dim3(kThreads), 0, s, src, adj, off, m, in_off, fill,
+                       in_ea);
 }
 
 void launch_canon(const int32_t* src, const int32_t* dst, int64_t P, int64_t n, int bits,

@@ -40,7 +40,7 @@ struct mcd_graph {
     int32_t* deg;      // [n]   degree by new id (non-decreasing)
     int32_t* perm;     // [n]   original id of every new id
     int64_t* in_off;   // [n+1] offsets of the in-edge lists
-    int32_t* in_e;     // [cap] ids of the edges x->v, grouped by head v
+    int2* in_ea;       // [cap] (edge id e of x->v, length of row x after v), grouped by head v
 };
 
 // Thread-local error reporting used by the ABI layer.
@@ -110,9 +110,10 @@ void launch_scatter_by_perm(const int32_t* val_new, const int32_t* perm, int64_t
 // in_cnt[v] = deg[v] - outdeg[v]
 void launch_in_count(const int32_t* deg, const int32_t* outdeg, int64_t n, int32_t* in_cnt,
                      hipStream_t s);
-// in_e[in_off[v] + k] = edges with head v (fill: zeroed int32[n] counters)
-void launch_in_scatter(const int32_t* adj, int64_t m, const int64_t* in_off, int32_t* fill,
-                       int32_t* in_e, hipStream_t s);
+// in_ea[in_off[v] + k] = (e, off[src[e]+1] - e - 1) for the edges e with head v
+// (fill: zeroed int32[n] counters)
+void launch_in_scatter(const int32_t* src, const int32_t* adj, const int64_t* off, int64_t m,
+                       const int64_t* in_off, int32_t* fill, int2* in_ea, hipStream_t s);
 
 // ---- triangles (tc.hip) ----
 size_t tc_scratch_bytes(const mcd_graph* g, int64_t chunk);

@@ -28,8 +28,8 @@ constexpr int kThreads = 256;
 
 struct Item {
     int32_t v;
-    int32_t pad;
-    int64_t s;  // first in-edge slot (index into in_e)
+    int32_t len;  // in-edges of this item
+    int64_t s;    // first in-edge slot (index into in_ea)
 };
 
 __device__ __forceinline__ void add_relaxed(int32_t* p, int32_t x) {
@@ -43,47 +43,51 @@ __device__ __forceinline__ uint32_t slot_of(int32_t w) {
 }
 
 // One item per WPI waves; 4/WPI items per workgroup.  LOG2S: log2 of hash
-// slots; rows up to 2^(LOG2S-1) out-neighbours.
-template <int LOG2S, int WPI>
+// slots (rows up to 2^(LOG2S-1) out-neighbours).  Each wave is split into
+// 64/G groups of G lanes; a group walks its own in-edges (static stride inside
+// the item) and streams each suffix G elements at a time, with the next
+// in-edge descriptor prefetched.  t(v,w) partial counts live in LDS as packed
+// 16-bit halves (an item has at most 65535 in-edges, so a half cannot carry).
+template <int LOG2S, int WPI, int G>
 __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ all_items,
                                                        const int64_t* __restrict__ heads, int cls,
-                                                       int64_t chunk,
                                                        const int64_t* __restrict__ off,
-                                                       const int32_t* __restrict__ src,
                                                        const int32_t* __restrict__ adj,
-                                                       const int64_t* __restrict__ in_off,
-                                                       const int32_t* __restrict__ in_e,
+                                                       const int2* __restrict__ in_ea,
                                                        int32_t* __restrict__ t) {
     constexpr int S = 1 << LOG2S;
     constexpr int NI = 4 / WPI;
     constexpr int MAXB = S / 2;
+    constexpr int GPW = 64 / G;
+    constexpr int NGI = WPI * GPW;  // groups per item
     __shared__ int32_t keys[NI][S];
     __shared__ uint16_t pos[NI][S];
-    __shared__ int32_t cnt[NI][MAXB];
+    __shared__ uint32_t cnt[NI][MAXB / 2];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = wave / WPI;         // which item of the workgroup
-    const int wsub = wave % WPI;         // wave index inside the item
+    const int slot = wave / WPI;
+    const int wsub = wave % WPI;
     const int tsub = threadIdx.x % (64 * WPI);
+    const int gl = lane % G, gi = lane / G;
+    const int gid = wsub * GPW + gi;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (gi * G));
     const Item* __restrict__ items = all_items + heads[2 * cls];
     const int64_t n_items = heads[2 * cls + 1];
 
     for (int64_t base = (int64_t)blockIdx.x * NI; base < n_items; base += (int64_t)gridDim.x * NI) {
         const int64_t it = base + slot;
         const bool have = it < n_items;
-        int32_t v = 0;
-        int64_t s = 0, s_end = 0, b0 = 0;
-        int32_t B = 0;
+        int64_t s = 0, b0 = 0;
+        int32_t B = 0, len = 0;
         if (have) {
             const Item I = items[it];
-            v = I.v;
             s = I.s;
-            s_end = min(I.s + chunk, in_off[v + 1]);
-            b0 = off[v];
-            B = (int32_t)(off[v + 1] - b0);
+            len = I.len;
+            b0 = off[I.v];
+            B = (int32_t)(off[I.v + 1] - b0);
         }
         for (int i = tsub; i < S; i += 64 * WPI) keys[slot][i] = -1;
-        for (int i = tsub; i < MAXB; i += 64 * WPI) cnt[slot][i] = 0;
+        for (int i = tsub; i < MAXB / 2; i += 64 * WPI) cnt[slot][i] = 0;
         __syncthreads();
         int32_t maxv = -1;
         if (have) {
@@ -97,44 +101,63 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
         }
         __syncthreads();
         if (have) {
-            for (int64_t k = s + wsub; k < s_end; k += WPI) {
-                const int64_t e = in_e[k];
-                const int32_t u = src[e];
-                const int64_t a1 = off[u + 1];
-                uint32_t c = 0;
-                for (int64_t cb = e + 1; cb < a1; cb += 64) {
-                    const int64_t i = cb + lane;
-                    const bool valid = i < a1;
-                    const int32_t w = valid ? adj[i] : INT32_MAX;
-                    const bool cand = valid && w <= maxv;
-                    if (__ballot(cand) == 0) break;  // suffix sorted: nothing further can match
-                    bool hit = false;
-                    if (cand) {
-                        uint32_t h = slot_of<LOG2S>(w);
-                        for (;;) {
-                            const int32_t kk = keys[slot][h];
-                            if (kk == w) {
-                                hit = true;
-                                break;
-                            }
-                            if (kk == -1) break;
-                            h = (h + 1) & (S - 1);
+            const int64_t kend = s + len;
+            int64_t k = s + gid;
+            bool done = k >= kend;
+            int2 cur = done ? make_int2(0, 0) : in_ea[k];
+            int2 nxt = (k + NGI < kend) ? in_ea[k + NGI] : make_int2(0, 0);
+            int64_t cursor = (int64_t)cur.x + 1, end = cursor + cur.y;
+            uint32_t c = 0;
+            for (;;) {
+                if (__ballot(!done) == 0) break;
+                const int64_t i = cursor + gl;
+                const bool valid = !done && i < end;
+                const int32_t w = valid ? adj[i] : INT32_MAX;
+                const bool cand = valid && w <= maxv;
+                const uint64_t cb = __ballot(cand);
+                bool hit = false;
+                if (cand) {
+                    uint32_t h = slot_of<LOG2S>(w);
+                    for (;;) {
+                        const int32_t kk = keys[slot][h];
+                        if (kk == w) {
+                            hit = true;
+                            break;
                         }
-                        if (hit) {
-                            atomicAdd(&cnt[slot][pos[slot][h]], 1);
-                            add_relaxed(&t[i], 1);
-                        }
+                        if (kk == -1) break;
+                        h = (h + 1) & (S - 1);
                     }
-                    c += (uint32_t)__popcll(__ballot(hit));
+                    if (hit) {
+                        const uint32_t p = pos[slot][h];
+                        atomicAdd(&cnt[slot][p >> 1], 1u << ((p & 1u) * 16u));
+                        add_relaxed(&t[i], 1);
+                    }
                 }
-                if (lane == 0 && c) add_relaxed(&t[e], (int32_t)c);
+                c += (uint32_t)__popcll(__ballot(hit) & gmask);
+                cursor += G;
+                // suffix sorted ascending: once no lane of the group holds a
+                // candidate, nothing later in this suffix can match
+                const bool fin = !done && (cursor >= end || (cb & gmask) == 0);
+                if (fin) {
+                    if (gl == 0 && c) add_relaxed(&t[cur.x], (int32_t)c);
+                    c = 0;
+                    k += NGI;
+                    if (k >= kend) {
+                        done = true;
+                    } else {
+                        cur = nxt;
+                        cursor = (int64_t)cur.x + 1;
+                        end = cursor + cur.y;
+                        nxt = (k + NGI < kend) ? in_ea[k + NGI] : make_int2(0, 0);
+                    }
+                }
             }
         }
         __syncthreads();
         if (have) {
             for (int j = tsub; j < B; j += 64 * WPI) {
-                const int32_t x = cnt[slot][j];
-                if (x) add_relaxed(&t[b0 + j], x);
+                const uint32_t x = (cnt[slot][j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+                if (x) add_relaxed(&t[b0 + j], (int32_t)x);
             }
         }
         __syncthreads();
@@ -155,23 +178,19 @@ __device__ __forceinline__ int64_t lower_bound(const int32_t* __restrict__ a, in
 // N+(u) searched in N+(v) (searches move right).
 __global__ __launch_bounds__(kThreads) void k_tc_search(const Item* __restrict__ all_items,
                                                         const int64_t* __restrict__ heads, int cls,
-                                                        int64_t chunk,
                                                         const int64_t* __restrict__ off,
-                                                        const int32_t* __restrict__ src,
                                                         const int32_t* __restrict__ adj,
-                                                        const int64_t* __restrict__ in_off,
-                                                        const int32_t* __restrict__ in_e,
+                                                        const int2* __restrict__ in_ea,
                                                         int32_t* __restrict__ t) {
     const Item* __restrict__ items = all_items + heads[2 * cls];
     const int64_t n_items = heads[2 * cls + 1];
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item I = items[it];
-        const int32_t v = I.v;
-        const int64_t s_end = min(I.s + chunk, in_off[v + 1]);
-        const int64_t bb = off[v], be = off[v + 1];
-        for (int64_t k = I.s + threadIdx.x; k < s_end; k += blockDim.x) {
-            const int64_t e = in_e[k];
-            const int64_t a1 = off[src[e] + 1];
+        const int64_t bb = off[I.v], be = off[I.v + 1];
+        for (int64_t k = I.s + threadIdx.x; k < I.s + I.len; k += blockDim.x) {
+            const int2 ea = in_ea[k];
+            const int64_t e = ea.x;
+            const int64_t a1 = e + 1 + ea.y;
             int64_t b = bb;
             int32_t c = 0;
             for (int64_t i = e + 1; i < a1 && b < be; ++i) {
@@ -190,6 +209,13 @@ __global__ __launch_bounds__(kThreads) void k_tc_search(const Item* __restrict__
 }
 
 constexpr int kClasses = 5;  // LDS classes 0..3, search class 4
+
+// In-edges per work item: at least the row length (the hash build is then at
+// most half the item's cost) and at most 65535 (16-bit LDS counters).
+__host__ __device__ inline int64_t item_size(int64_t chunk, int64_t B) {
+    int64_t cs = chunk > B ? chunk : B;
+    return cs > 65535 ? 65535 : cs;
+}
 constexpr int kMaxB[4] = {128, 512, 2048, 4096};
 
 // Number of work items of vertex v in each class (one class is non-zero).
@@ -209,12 +235,14 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
                     if (B <= kMaxB[c]) cls = c;
             }
         }
-        const int32_t k = cls >= 0 ? (int32_t)((I + chunk - 1) / chunk) : 0;
+        const int64_t cs = item_size(chunk, B);
+        const int32_t k = cls >= 0 ? (int32_t)((I + cs - 1) / cs) : 0;
         for (int c = 0; c < kClasses; ++c) cnt[(int64_t)c * n + v] = (c == cls) ? k : 0;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_item_fill(const int64_t* __restrict__ in_off, int64_t n,
+__global__ __launch_bounds__(kThreads) void k_item_fill(const int64_t* __restrict__ off,
+                                                        const int64_t* __restrict__ in_off, int64_t n,
                                                         int64_t chunk, const int32_t* __restrict__ cnt,
                                                         const int64_t* __restrict__ base,
                                                         Item* __restrict__ items) {
@@ -227,11 +255,13 @@ __global__ __launch_bounds__(kThreads) void k_item_fill(const int64_t* __restric
             // the total of the earlier classes
             int64_t b = base[(int64_t)c * (n + 1) + v];
             for (int cc = 0; cc < c; ++cc) b += base[(int64_t)cc * (n + 1) + n];
+            const int64_t cs = item_size(chunk, off[v + 1] - off[v]);
+            const int64_t i0 = in_off[v], i1 = in_off[v + 1];
             for (int32_t j = 0; j < k; ++j) {
                 Item I;
                 I.v = (int32_t)v;
-                I.pad = 0;
-                I.s = in_off[v] + (int64_t)j * chunk;
+                I.s = i0 + (int64_t)j * cs;
+                I.len = (int32_t)min(cs, i1 - I.s);
                 items[b + j] = I;
             }
         }
@@ -270,7 +300,7 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     Carve c{(char*)p, 0, 0};
     TcLayout L;
     const int64_t n = g->n;
-    const int64_t max_items = n + g->m / (chunk > 0 ? chunk : 1) + 1;
+    const int64_t max_items = n + g->m / item_size(chunk, 0) + 1;  // items hold >= item_size(chunk, 0) in-edges
     L.cnt = c.take<int32_t>((size_t)kClasses * n);
     L.base = c.take<int64_t>((size_t)kClasses * (n + 1));
     L.items = c.take<Item>((size_t)max_items);
@@ -280,15 +310,15 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     return L;
 }
 
-template <int LOG2S, int WPI>
+template <int LOG2S, int WPI, int G>
 void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
     constexpr int NI = 4 / WPI;
     // grid-stride over the class list; its length is read on the device
-    const int64_t cap_items = g->n + g->m / chunk + 1;
+    const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = (cap_items + NI - 1) / NI;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL((k_tc_items<LOG2S, WPI>), dim3((unsigned)blocks), dim3(kThreads), 0, s, L.items,
-                       L.heads, c, chunk, g->off, g->src, g->adj, g->in_off, g->in_e, t);
+    hipLaunchKernelGGL((k_tc_items<LOG2S, WPI, G>), dim3((unsigned)blocks), dim3(kThreads), 0, s, L.items,
+                       L.heads, c, g->off, g->adj, g->in_ea, t);
 }
 
 }  // namespace
@@ -306,15 +336,15 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
                        chunk, lds_max, L.cnt);
     for (int c = 0; c < kClasses; ++c)
         exclusive_scan_i32_i64(L.cnt + (int64_t)c * n, n, L.base + (int64_t)c * (n + 1), L.scan, s);
-    hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->in_off, n, chunk,
-                       L.cnt, L.base, L.items);
+    hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
+                       chunk, L.cnt, L.base, L.items);
     hipLaunchKernelGGL(k_item_heads, dim3(1), dim3(64), 0, s, L.base, n, L.heads);
-    launch_class<8, 1>(g, L, 0, chunk, t, s);
-    launch_class<10, 2>(g, L, 1, chunk, t, s);
-    launch_class<12, 4>(g, L, 2, chunk, t, s);
-    launch_class<13, 4>(g, L, 3, chunk, t, s);
-    hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, 4, chunk, g->off,
-                       g->src, g->adj, g->in_off, g->in_e, t);
+    launch_class<8, 1, 16>(g, L, 0, chunk, t, s);
+    launch_class<10, 2, 16>(g, L, 1, chunk, t, s);
+    launch_class<12, 4, 16>(g, L, 2, chunk, t, s);
+    launch_class<13, 4, 16>(g, L, 3, chunk, t, s);
+    hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, 4, g->off, g->adj,
+                       g->in_ea, t);
 }
 
 }  // namespace mcd
