@@ -81,7 +81,10 @@ mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream);
  * them; the autotuner sets them):
  *   "tc_chunk"   in-edges per triangle-count work item, [1, 2^24], default 512;
  *   "tc_lds_max" longest out-neighbour row hashed in LDS, [0, 4096], default
- *                4096; longer rows use the binary-search path.
+ *                4096; longer rows use the binary-search path;
+ *   "tc_packed_range" widest rank range of a row stored in the one-word LDS
+ *                table, [0, 2^20 - 2], default 2^20 - 2; wider rows use the
+ *                two-array table.
  * Errors: MCD_ERR_INVALID_ARG (unknown name), MCD_ERR_RANGE (bad value). */
 mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value);
 mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* value);

@@ -36,19 +36,75 @@ __device__ __forceinline__ void add_relaxed(int32_t* p, int32_t x) {
     __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Hash table of N+(v) in LDS.  PACKED (every key of the row lies within 2^20
+// ranks above v): one 32-bit word per slot, ((w - v - 1) << 12) | position, so
+// a single LDS read yields key and position; the slot is the key's low bits
+// folded once, which is collision-free when the row's rank range fits the
+// table (the dense rows of the highest-ranked vertices).  WIDE: separate key
+// and 16-bit position arrays for rows that span more ranks.
+template <int LOG2S, bool PACKED>
+struct RowHash;
+
 template <int LOG2S>
-__device__ __forceinline__ uint32_t slot_of(int32_t w) {
-    const uint32_t x = (uint32_t)w;
-    return (x ^ (x >> LOG2S)) & ((1u << LOG2S) - 1u);
-}
+struct RowHash<LOG2S, true> {
+    static constexpr int S = 1 << LOG2S;
+    uint32_t tab[S];
+    __device__ __forceinline__ void clear(int tid, int nt) {
+        for (int i = tid; i < S; i += nt) tab[i] = 0xffffffffu;
+    }
+    __device__ __forceinline__ void insert(int32_t w, int32_t v, int j) {
+        const uint32_t r = (uint32_t)(w - v - 1);
+        uint32_t h = (r ^ (r >> LOG2S)) & (S - 1);
+        const uint32_t ent = (r << 12) | (uint32_t)j;
+        while (atomicCAS(&tab[h], 0xffffffffu, ent) != 0xffffffffu) h = (h + 1) & (S - 1);
+    }
+    // position of w in the row, or -1
+    __device__ __forceinline__ int find(int32_t w, int32_t v) const {
+        const uint32_t r = (uint32_t)(w - v - 1);
+        uint32_t h = (r ^ (r >> LOG2S)) & (S - 1);
+        for (;;) {
+            const uint32_t e = tab[h];
+            if (e == 0xffffffffu) return -1;
+            if ((e >> 12) == r) return (int)(e & 4095u);
+            h = (h + 1) & (S - 1);
+        }
+    }
+};
+
+template <int LOG2S>
+struct RowHash<LOG2S, false> {
+    static constexpr int S = 1 << LOG2S;
+    int32_t keys[S];
+    uint16_t pos[S];
+    __device__ __forceinline__ void clear(int tid, int nt) {
+        for (int i = tid; i < S; i += nt) keys[i] = -1;
+    }
+    __device__ __forceinline__ void insert(int32_t w, int32_t, int j) {
+        const uint32_t x = (uint32_t)w;
+        uint32_t h = (x ^ (x >> LOG2S)) & (S - 1);
+        while (atomicCAS(&keys[h], -1, w) != -1) h = (h + 1) & (S - 1);
+        pos[h] = (uint16_t)j;
+    }
+    __device__ __forceinline__ int find(int32_t w, int32_t) const {
+        const uint32_t x = (uint32_t)w;
+        uint32_t h = (x ^ (x >> LOG2S)) & (S - 1);
+        for (;;) {
+            const int32_t k = keys[h];
+            if (k == w) return pos[h];
+            if (k == -1) return -1;
+            h = (h + 1) & (S - 1);
+        }
+    }
+};
 
 // One item per WPI waves; 4/WPI items per workgroup.  LOG2S: log2 of hash
 // slots (rows up to 2^(LOG2S-1) out-neighbours).  Each wave is split into
 // 64/G groups of G lanes; a group walks its own in-edges (static stride inside
-// the item) and streams each suffix G elements at a time, with the next
-// in-edge descriptor prefetched.  t(v,w) partial counts live in LDS as packed
-// 16-bit halves (an item has at most 65535 in-edges, so a half cannot carry).
-template <int LOG2S, int WPI, int G>
+// the item) and streams each suffix G elements at a time, loading the next
+// chunk and the next in-edge descriptor ahead of use.  t(v,w) partial counts
+// live in LDS as packed 16-bit halves (an item has at most 65535 in-edges, so
+// a half cannot carry).
+template <int LOG2S, int WPI, int G, bool PACKED>
 __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ all_items,
                                                        const int64_t* __restrict__ heads, int cls,
                                                        const int64_t* __restrict__ off,
@@ -60,8 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
     constexpr int MAXB = S / 2;
     constexpr int GPW = 64 / G;
     constexpr int NGI = WPI * GPW;  // groups per item
-    __shared__ int32_t keys[NI][S];
-    __shared__ uint16_t pos[NI][S];
+    __shared__ RowHash<LOG2S, PACKED> hash[NI];
     __shared__ uint32_t cnt[NI][MAXB / 2];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -73,30 +128,27 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (gi * G));
     const Item* __restrict__ items = all_items + heads[2 * cls];
     const int64_t n_items = heads[2 * cls + 1];
+    RowHash<LOG2S, PACKED>& H = hash[slot];
 
     for (int64_t base = (int64_t)blockIdx.x * NI; base < n_items; base += (int64_t)gridDim.x * NI) {
         const int64_t it = base + slot;
         const bool have = it < n_items;
         int64_t s = 0, b0 = 0;
-        int32_t B = 0, len = 0;
+        int32_t B = 0, len = 0, v = 0;
         if (have) {
             const Item I = items[it];
             s = I.s;
             len = I.len;
-            b0 = off[I.v];
-            B = (int32_t)(off[I.v + 1] - b0);
+            v = I.v;
+            b0 = off[v];
+            B = (int32_t)(off[v + 1] - b0);
         }
-        for (int i = tsub; i < S; i += 64 * WPI) keys[slot][i] = -1;
+        H.clear(tsub, 64 * WPI);
         for (int i = tsub; i < MAXB / 2; i += 64 * WPI) cnt[slot][i] = 0;
         __syncthreads();
         int32_t maxv = -1;
         if (have) {
-            for (int j = tsub; j < B; j += 64 * WPI) {
-                const int32_t w = adj[b0 + j];
-                uint32_t h = slot_of<LOG2S>(w);
-                while (atomicCAS(&keys[slot][h], -1, w) != -1) h = (h + 1) & (S - 1);
-                pos[slot][h] = (uint16_t)j;
-            }
+            for (int j = tsub; j < B; j += 64 * WPI) H.insert(adj[b0 + j], v, j);
             maxv = adj[b0 + B - 1];
         }
         __syncthreads();
@@ -107,34 +159,28 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
             int2 cur = done ? make_int2(0, 0) : in_ea[k];
             int2 nxt = (k + NGI < kend) ? in_ea[k + NGI] : make_int2(0, 0);
             int64_t cursor = (int64_t)cur.x + 1, end = cursor + cur.y;
+            int32_t wn = (!done && cursor + gl < end) ? adj[cursor + gl] : INT32_MAX;
             uint32_t c = 0;
             for (;;) {
                 if (__ballot(!done) == 0) break;
                 const int64_t i = cursor + gl;
                 const bool valid = !done && i < end;
-                const int32_t w = valid ? adj[i] : INT32_MAX;
+                const int32_t w = valid ? wn : INT32_MAX;
+                cursor += G;
+                // next chunk of this suffix, in flight while this one is probed
+                wn = (!done && cursor + gl < end) ? adj[cursor + gl] : INT32_MAX;
                 const bool cand = valid && w <= maxv;
                 const uint64_t cb = __ballot(cand);
                 bool hit = false;
                 if (cand) {
-                    uint32_t h = slot_of<LOG2S>(w);
-                    for (;;) {
-                        const int32_t kk = keys[slot][h];
-                        if (kk == w) {
-                            hit = true;
-                            break;
-                        }
-                        if (kk == -1) break;
-                        h = (h + 1) & (S - 1);
-                    }
-                    if (hit) {
-                        const uint32_t p = pos[slot][h];
-                        atomicAdd(&cnt[slot][p >> 1], 1u << ((p & 1u) * 16u));
+                    const int p = H.find(w, v);
+                    if (p >= 0) {
+                        hit = true;
+                        atomicAdd(&cnt[slot][p >> 1], 1u << ((p & 1) * 16));
                         add_relaxed(&t[i], 1);
                     }
                 }
                 c += (uint32_t)__popcll(__ballot(hit) & gmask);
-                cursor += G;
                 // suffix sorted ascending: once no lane of the group holds a
                 // candidate, nothing later in this suffix can match
                 const bool fin = !done && (cursor >= end || (cb & gmask) == 0);
@@ -148,6 +194,7 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
                         cur = nxt;
                         cursor = (int64_t)cur.x + 1;
                         end = cursor + cur.y;
+                        wn = (cursor + gl < end) ? adj[cursor + gl] : INT32_MAX;
                         nxt = (k + NGI < kend) ? in_ea[k + NGI] : make_int2(0, 0);
                     }
                 }
@@ -208,7 +255,10 @@ __global__ __launch_bounds__(kThreads) void k_tc_search(const Item* __restrict__
     }
 }
 
-constexpr int kClasses = 5;  // LDS classes 0..3, search class 4
+// LDS classes 0..3 (packed table, row within 2^20 ranks above v), 4..7 (wide
+// table), 8 (binary search)
+constexpr int kClasses = 9;
+constexpr int kSearch = 8;
 
 // In-edges per work item: at least the row length (the hash build is then at
 // most half the item's cost) and at most 65535 (16-bit LDS counters).
@@ -222,6 +272,7 @@ constexpr int kMaxB[4] = {128, 512, 2048, 4096};
 __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restrict__ off,
                                                          const int64_t* __restrict__ in_off, int64_t n,
                                                          int64_t chunk, int64_t lds_max,
+                                                         int64_t packed_range,
                                                          int32_t* __restrict__ cnt) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -229,10 +280,11 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
         const int64_t I = in_off[v + 1] - in_off[v];
         int cls = -1;
         if (B > 0 && I > 0) {
-            cls = 4;
+            cls = kSearch;
             if (B <= lds_max) {
                 for (int c = 3; c >= 0; --c)
                     if (B <= kMaxB[c]) cls = c;
+                if (n - 1 - v > packed_range) cls += 4;
             }
         }
         const int64_t cs = item_size(chunk, B);
@@ -310,14 +362,14 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     return L;
 }
 
-template <int LOG2S, int WPI, int G>
+template <int LOG2S, int WPI, int G, bool PACKED>
 void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
     constexpr int NI = 4 / WPI;
     // grid-stride over the class list; its length is read on the device
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = (cap_items + NI - 1) / NI;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL((k_tc_items<LOG2S, WPI, G>), dim3((unsigned)blocks), dim3(kThreads), 0, s, L.items,
+    hipLaunchKernelGGL((k_tc_items<LOG2S, WPI, G, PACKED>), dim3((unsigned)blocks), dim3(kThreads), 0, s, L.items,
                        L.heads, c, g->off, g->adj, g->in_ea, t);
 }
 
@@ -326,25 +378,29 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
 size_t tc_scratch_bytes(const mcd_graph* g, int64_t chunk) { return tc_layout(nullptr, g, chunk).bytes; }
 
 void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, int64_t lds_max,
-                      hipStream_t s) {
+                      int64_t packed_range, hipStream_t s) {
     fill_i32(t, g->m, 0, s);
     if (g->m <= 0 || g->n <= 0) return;
     if (chunk < 1) chunk = 1;
     TcLayout L = tc_layout(ws, g, chunk);
     const int64_t n = g->n;
     hipLaunchKernelGGL(k_item_count, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
-                       chunk, lds_max, L.cnt);
+                       chunk, lds_max, packed_range, L.cnt);
     for (int c = 0; c < kClasses; ++c)
         exclusive_scan_i32_i64(L.cnt + (int64_t)c * n, n, L.base + (int64_t)c * (n + 1), L.scan, s);
     hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
                        chunk, L.cnt, L.base, L.items);
     hipLaunchKernelGGL(k_item_heads, dim3(1), dim3(64), 0, s, L.base, n, L.heads);
-    launch_class<8, 1, 16>(g, L, 0, chunk, t, s);
-    launch_class<10, 2, 16>(g, L, 1, chunk, t, s);
-    launch_class<12, 4, 16>(g, L, 2, chunk, t, s);
-    launch_class<13, 4, 16>(g, L, 3, chunk, t, s);
-    hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, 4, g->off, g->adj,
-                       g->in_ea, t);
+    launch_class<8, 1, 16, true>(g, L, 0, chunk, t, s);
+    launch_class<10, 2, 64, true>(g, L, 1, chunk, t, s);
+    launch_class<12, 4, 64, true>(g, L, 2, chunk, t, s);
+    launch_class<13, 4, 64, true>(g, L, 3, chunk, t, s);
+    launch_class<8, 1, 16, false>(g, L, 4, chunk, t, s);
+    launch_class<10, 2, 64, false>(g, L, 5, chunk, t, s);
+    launch_class<12, 4, 64, false>(g, L, 6, chunk, t, s);
+    launch_class<13, 4, 64, false>(g, L, 7, chunk, t, s);
+    hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
+                       g->adj, g->in_ea, t);
 }
 
 }  // namespace mcd

@@ -139,8 +139,10 @@ def test_repeat_runs_bit_identical():
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("chunk,lds_max", [(512, 4096), (1, 4096), (7, 100), (64, 0), (3, 600), (100000, 2048)])
-def test_triangle_paths_and_chunks(chunk, lds_max):
+@pytest.mark.parametrize("chunk,lds_max,packed", [(512, 4096, 1048574), (1, 4096, 1048574), (7, 100, 0),
+                                                  (64, 0, 1048574), (3, 600, 5000), (100000, 2048, 0),
+                                                  (512, 4096, 0)])
+def test_triangle_paths_and_chunks(chunk, lds_max, packed):
     # every launch configuration (work-item size, LDS classes vs binary search)
     # must give the oracle's counts
     from gpu_util import ctx, build
@@ -148,24 +150,26 @@ def test_triangle_paths_and_chunks(chunk, lds_max):
     lo, hi = oracle.canon(n, s, d)
     t_o = oracle.triangles(n, lo, hi)
     c = ctx()
-    old = (M.mcd_ctx_get_param(c, "tc_chunk"), M.mcd_ctx_get_param(c, "tc_lds_max"))
+    names = ("tc_chunk", "tc_lds_max", "tc_packed_range")
+    old = [M.mcd_ctx_get_param(c, k) for k in names]
     try:
-        M.mcd_ctx_set_param(c, "tc_chunk", chunk)
-        M.mcd_ctx_set_param(c, "tc_lds_max", lds_max)
+        for k, val in zip(names, (chunk, lds_max, packed)):
+            M.mcd_ctx_set_param(c, k, val)
         from gpu_util import canonical_order
         g = build(s, d, n)
         _, _, order = canonical_order(g)
         t = M.mcd_triangles(g).cpu().numpy()[order]
         assert np.array_equal(t, t_o)
     finally:
-        M.mcd_ctx_set_param(c, "tc_chunk", old[0])
-        M.mcd_ctx_set_param(c, "tc_lds_max", old[1])
+        for k, val in zip(names, old):
+            M.mcd_ctx_set_param(c, k, val)
 
 
 def test_param_validation():
     from gpu_util import ctx
     c = ctx()
-    for name, bad in (("tc_chunk", 0), ("tc_lds_max", 5000), ("tc_lds_max", -1)):
+    for name, bad in (("tc_chunk", 0), ("tc_lds_max", 5000), ("tc_lds_max", -1),
+                      ("tc_packed_range", 1 << 20)):
         with pytest.raises(M.MCDError) as ei:
             M.mcd_ctx_set_param(c, name, bad)
         assert ei.value.status == -3
