@@ -84,7 +84,9 @@ mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream);
  *                4096; longer rows use the binary-search path;
  *   "tc_packed_range" widest rank range of a row stored in the one-word LDS
  *                table, [0, 2^20 - 2], default 2^20 - 2; wider rows use the
- *                two-array table.
+ *                two-array table;
+ *   "tc_window_max" widest rank range of a row held as an LDS rank bitmap,
+ *                [0, 2^18], default 2^18 (0 disables the bitmap path).
  * Errors: MCD_ERR_INVALID_ARG (unknown name), MCD_ERR_RANGE (bad value). */
 mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value);
 mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* value);

@@ -62,7 +62,7 @@ StorageLayout storage_layout(void* base, int64_t P, int64_t n) {
     StorageLayout L;
     L.off = c.take<int64_t>((size_t)n + 1);
     L.src = c.take<int32_t>((size_t)P);
-    L.adj = c.take<int32_t>((size_t)P);
+    L.adj = c.take<int32_t>((size_t)P + 4);  // +4: 16-byte loads may read past the last edge
     L.deg = c.take<int32_t>((size_t)n);
     L.perm = c.take<int32_t>((size_t)n);
     L.in_off = c.take<int64_t>((size_t)n + 1);
@@ -162,6 +162,7 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
     c->tc_chunk = 512;
     c->tc_lds_max = MCD_TC_LDS_LIMIT;
     c->tc_packed_range = MCD_TC_PACKED_LIMIT;
+    c->tc_window_max = MCD_TC_WINDOW_LIMIT;
     if (hipMalloc((void**)&c->d_ctrl, sizeof(int64_t) * MCD_CTRL_WORDS) != hipSuccess) {
         delete c;
         return mcd_fail(MCD_ERR_DEVICE, "hipMalloc of the control block failed");
@@ -191,6 +192,9 @@ mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value) {
     } else if (k == "tc_lds_max") {
         REQUIRE(value >= 0 && value <= MCD_TC_LDS_LIMIT, MCD_ERR_RANGE, "tc_lds_max must lie in [0, 4096]");
         ctx->tc_lds_max = value;
+    } else if (k == "tc_window_max") {
+        REQUIRE(value >= 0 && value <= MCD_TC_WINDOW_LIMIT, MCD_ERR_RANGE, "tc_window_max must lie in [0, 2^18]");
+        ctx->tc_window_max = value;
     } else if (k == "tc_packed_range") {
         REQUIRE(value >= 0 && value <= MCD_TC_PACKED_LIMIT, MCD_ERR_RANGE,
                 "tc_packed_range must lie in [0, 2^20 - 2]");
@@ -207,6 +211,7 @@ mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* valu
     if (k == "tc_chunk") *value = ctx->tc_chunk;
     else if (k == "tc_lds_max") *value = ctx->tc_lds_max;
     else if (k == "tc_packed_range") *value = ctx->tc_packed_range;
+    else if (k == "tc_window_max") *value = ctx->tc_window_max;
     else return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     return MCD_OK;
 }
@@ -345,7 +350,7 @@ mcd_status mcd_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_byt
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_triangles(g, t, ws, g->ctx->tc_chunk, g->ctx->tc_lds_max, g->ctx->tc_packed_range,
-                          g->ctx->stream);
+                          g->ctx->tc_window_max, g->ctx->stream);
     return MCD_OK;
 }
 
@@ -408,7 +413,8 @@ mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, 
     if ((st = use_device(g->ctx)) != MCD_OK) return st;
     RunLayout L = run_layout(ws, g);
     hipStream_t s = g->ctx->stream;
-    mcd::launch_triangles(g, L.t, L.tc, g->ctx->tc_chunk, g->ctx->tc_lds_max, g->ctx->tc_packed_range, s);
+    mcd::launch_triangles(g, L.t, L.tc, g->ctx->tc_chunk, g->ctx->tc_lds_max, g->ctx->tc_packed_range,
+                          g->ctx->tc_window_max, s);
     mcd::launch_prune(g, measure, L.t, delta.num, delta.den, L.keep, nullptr, s);
     mcd::launch_components(g, L.keep, labels, n_components, L.parent, s);
     return MCD_OK;

@@ -21,7 +21,9 @@ struct mcd_ctx {
     int64_t tc_chunk;    // in-edges per triangle work item
     int64_t tc_lds_max;  // longest row hashed in LDS; longer rows use binary search
     int64_t tc_packed_range;  // widest rank range (w - v - 1) of a packed LDS table
+    int64_t tc_window_max;    // widest rank range of a row held as an LDS rank window
 };
+#define MCD_TC_WINDOW_LIMIT (1 << 18)
 #define MCD_TC_LDS_LIMIT 4096
 #define MCD_TC_PACKED_LIMIT ((1 << 20) - 2)
 #define MCD_CTRL_WORDS 64
@@ -120,7 +122,7 @@ void launch_in_scatter(const int32_t* src, const int32_t* adj, const int64_t* of
 // ---- triangles (tc.hip) ----
 size_t tc_scratch_bytes(const mcd_graph* g, int64_t chunk);
 void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, int64_t lds_max,
-                      int64_t packed_range, hipStream_t s);
+                      int64_t packed_range, int64_t window_max, hipStream_t s);
 
 // ---- weights / prune (weight.hip) ----
 void launch_weights(const mcd_graph* g, int measure, const int32_t* t, float* wf, int32_t* wi,

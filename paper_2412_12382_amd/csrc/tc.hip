@@ -45,23 +45,32 @@ __device__ __forceinline__ void add_relaxed(int32_t* p, int32_t x) {
 template <int LOG2S, bool PACKED>
 struct RowHash;
 
+// Fibonacci hashing: spreads runs of consecutive ranks over the table, so
+// linear-probe clusters stay short.
+template <int LOG2S>
+__device__ __forceinline__ uint32_t fib_slot(uint32_t x) {
+    return (x * 0x9E3779B1u) >> (32 - LOG2S);
+}
+
 template <int LOG2S>
 struct RowHash<LOG2S, true> {
     static constexpr int S = 1 << LOG2S;
     uint32_t tab[S];
+    static __device__ __forceinline__ uint32_t slot_of(uint32_t r) { return fib_slot<LOG2S>(r); }
+    __device__ __forceinline__ void prepare(int, int, int32_t) {}
     __device__ __forceinline__ void clear(int tid, int nt) {
         for (int i = tid; i < S; i += nt) tab[i] = 0xffffffffu;
     }
     __device__ __forceinline__ void insert(int32_t w, int32_t v, int j) {
         const uint32_t r = (uint32_t)(w - v - 1);
-        uint32_t h = (r ^ (r >> LOG2S)) & (S - 1);
+        uint32_t h = slot_of(r);
         const uint32_t ent = (r << 12) | (uint32_t)j;
         while (atomicCAS(&tab[h], 0xffffffffu, ent) != 0xffffffffu) h = (h + 1) & (S - 1);
     }
     // position of w in the row, or -1
     __device__ __forceinline__ int find(int32_t w, int32_t v) const {
         const uint32_t r = (uint32_t)(w - v - 1);
-        uint32_t h = (r ^ (r >> LOG2S)) & (S - 1);
+        uint32_t h = slot_of(r);
         for (;;) {
             const uint32_t e = tab[h];
             if (e == 0xffffffffu) return -1;
@@ -76,24 +85,74 @@ struct RowHash<LOG2S, false> {
     static constexpr int S = 1 << LOG2S;
     int32_t keys[S];
     uint16_t pos[S];
+    static __device__ __forceinline__ uint32_t slot_of(uint32_t r) { return fib_slot<LOG2S>(r); }
+    __device__ __forceinline__ void prepare(int, int, int32_t) {}
     __device__ __forceinline__ void clear(int tid, int nt) {
         for (int i = tid; i < S; i += nt) keys[i] = -1;
     }
     __device__ __forceinline__ void insert(int32_t w, int32_t, int j) {
-        const uint32_t x = (uint32_t)w;
-        uint32_t h = (x ^ (x >> LOG2S)) & (S - 1);
+        uint32_t h = slot_of((uint32_t)w);
         while (atomicCAS(&keys[h], -1, w) != -1) h = (h + 1) & (S - 1);
         pos[h] = (uint16_t)j;
     }
     __device__ __forceinline__ int find(int32_t w, int32_t) const {
-        const uint32_t x = (uint32_t)w;
-        uint32_t h = (x ^ (x >> LOG2S)) & (S - 1);
+        uint32_t h = slot_of((uint32_t)w);
         for (;;) {
             const int32_t k = keys[h];
             if (k == w) return pos[h];
             if (k == -1) return -1;
             h = (h + 1) & (S - 1);
         }
+    }
+};
+
+// Rank window of N+(v) in LDS, for rows whose ranks all lie in (v, v + 2^LOG2R]:
+// bit r of the bitmap marks rank v + 1 + r, and pre[k] counts the set bits
+// before word k, so a lookup is two independent LDS reads (word and prefix)
+// and a popcount, with no probe loop.  The prefix pass needs the whole
+// workgroup (one item per workgroup).
+template <int LOG2R>
+struct RowWindow {
+    static constexpr int NW = (1 << LOG2R) / 32;
+    uint32_t bm[NW];
+    uint16_t pre[NW];
+    uint32_t part[4];
+    __device__ __forceinline__ void clear(int tid, int nt) {
+        for (int i = tid; i < NW; i += nt) bm[i] = 0;
+    }
+    __device__ __forceinline__ void insert(int32_t w, int32_t v, int) {
+        const uint32_t r = (uint32_t)(w - v - 1);
+        atomicOr(&bm[r >> 5], 1u << (r & 31));
+    }
+    // exclusive prefix of popcounts over the words that can hold ranks <= v + R
+    __device__ __forceinline__ void prepare(int tid, int nt, int32_t R) {
+        const int nw = (R + 31) >> 5;
+        const int per = (nw + nt - 1) / nt;
+        const int w0 = tid * per, w1 = min(nw, w0 + per);
+        uint32_t s = 0;
+        for (int i = w0; i < w1; ++i) s += __popc(bm[i]);
+        uint32_t x = s;  // inclusive wave scan
+        const int lane = tid & 63;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) part[tid >> 6] = x;
+        __syncthreads();
+        uint32_t run = x - s;
+        for (int k = 0; k < (tid >> 6); ++k) run += part[k];
+        for (int i = w0; i < w1; ++i) {
+            pre[i] = (uint16_t)run;
+            run += __popc(bm[i]);
+        }
+    }
+    __device__ __forceinline__ int find(int32_t w, int32_t v) const {
+        const uint32_t r = (uint32_t)(w - v - 1);
+        const uint32_t word = bm[r >> 5];
+        const uint32_t p0 = pre[r >> 5];
+        const uint32_t bit = 1u << (r & 31);
+        if (!(word & bit)) return -1;
+        return (int)(p0 + __popc(word & (bit - 1u)));
     }
 };
 
@@ -104,19 +163,17 @@ struct RowHash<LOG2S, false> {
 // chunk and the next in-edge descriptor ahead of use.  t(v,w) partial counts
 // live in LDS as packed 16-bit halves (an item has at most 65535 in-edges, so
 // a half cannot carry).
-template <int LOG2S, int WPI, int G, bool PACKED>
+template <class Table, int MAXB, int WPI, int G>
 __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ all_items,
                                                        const int64_t* __restrict__ heads, int cls,
                                                        const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ adj,
                                                        const int2* __restrict__ in_ea,
                                                        int32_t* __restrict__ t) {
-    constexpr int S = 1 << LOG2S;
     constexpr int NI = 4 / WPI;
-    constexpr int MAXB = S / 2;
     constexpr int GPW = 64 / G;
     constexpr int NGI = WPI * GPW;  // groups per item
-    __shared__ RowHash<LOG2S, PACKED> hash[NI];
+    __shared__ Table hash[NI];
     __shared__ uint32_t cnt[NI][MAXB / 2];
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -128,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (gi * G));
     const Item* __restrict__ items = all_items + heads[2 * cls];
     const int64_t n_items = heads[2 * cls + 1];
-    RowHash<LOG2S, PACKED>& H = hash[slot];
+    Table& H = hash[slot];
 
     for (int64_t base = (int64_t)blockIdx.x * NI; base < n_items; base += (int64_t)gridDim.x * NI) {
         const int64_t it = base + slot;
@@ -151,6 +208,8 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
             for (int j = tsub; j < B; j += 64 * WPI) H.insert(adj[b0 + j], v, j);
             maxv = adj[b0 + B - 1];
         }
+        __syncthreads();
+        H.prepare(tsub, 64 * WPI, maxv - v);  // window: rank range actually used
         __syncthreads();
         if (have) {
             const int64_t kend = s + len;
@@ -255,10 +314,14 @@ __global__ __launch_bounds__(kThreads) void k_tc_search(const Item* __restrict__
     }
 }
 
-// LDS classes 0..3 (packed table, row within 2^20 ranks above v), 4..7 (wide
-// table), 8 (binary search)
-constexpr int kClasses = 9;
-constexpr int kSearch = 8;
+// Work-item classes:
+//   0..3  hash, packed entries (row within 2^20 ranks above v), by row length
+//   4..7  hash, wide entries, by row length
+//   8..10 rank window of 2^14, 2^16, 2^18 ranks (rows longer than 128)
+//   11    binary search (rows longer than the LDS cap)
+constexpr int kClasses = 12;
+constexpr int kSearch = 11;
+constexpr int kWindowLog2[3] = {14, 16, 18};
 
 // In-edges per work item: at least the row length (the hash build is then at
 // most half the item's cost) and at most 65535 (16-bit LDS counters).
@@ -270,9 +333,10 @@ constexpr int kMaxB[4] = {128, 512, 2048, 4096};
 
 // Number of work items of vertex v in each class (one class is non-zero).
 __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restrict__ off,
+                                                         const int32_t* __restrict__ adj,
                                                          const int64_t* __restrict__ in_off, int64_t n,
                                                          int64_t chunk, int64_t lds_max,
-                                                         int64_t packed_range,
+                                                         int64_t packed_range, int64_t window_max,
                                                          int32_t* __restrict__ cnt) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -285,6 +349,12 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
                 for (int c = 3; c >= 0; --c)
                     if (B <= kMaxB[c]) cls = c;
                 if (n - 1 - v > packed_range) cls += 4;
+                // rank range of the row: its last (largest) element minus v
+                const int64_t R = (int64_t)adj[off[v + 1] - 1] - v;
+                if (B > kMaxB[0] && window_max > 0) {
+                    for (int c = 2; c >= 0; --c)
+                        if (R <= ((int64_t)1 << kWindowLog2[c]) && R <= window_max) cls = 8 + c;
+                }
             }
         }
         const int64_t cs = item_size(chunk, B);
@@ -362,15 +432,15 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     return L;
 }
 
-template <int LOG2S, int WPI, int G, bool PACKED>
+template <class Table, int MAXB, int WPI, int G>
 void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
     constexpr int NI = 4 / WPI;
     // grid-stride over the class list; its length is read on the device
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = (cap_items + NI - 1) / NI;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL((k_tc_items<LOG2S, WPI, G, PACKED>), dim3((unsigned)blocks), dim3(kThreads), 0, s, L.items,
-                       L.heads, c, g->off, g->adj, g->in_ea, t);
+    hipLaunchKernelGGL((k_tc_items<Table, MAXB, WPI, G>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                       L.items, L.heads, c, g->off, g->adj, g->in_ea, t);
 }
 
 }  // namespace
@@ -378,27 +448,30 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
 size_t tc_scratch_bytes(const mcd_graph* g, int64_t chunk) { return tc_layout(nullptr, g, chunk).bytes; }
 
 void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, int64_t lds_max,
-                      int64_t packed_range, hipStream_t s) {
+                      int64_t packed_range, int64_t window_max, hipStream_t s) {
     fill_i32(t, g->m, 0, s);
     if (g->m <= 0 || g->n <= 0) return;
     if (chunk < 1) chunk = 1;
     TcLayout L = tc_layout(ws, g, chunk);
     const int64_t n = g->n;
-    hipLaunchKernelGGL(k_item_count, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
-                       chunk, lds_max, packed_range, L.cnt);
+    hipLaunchKernelGGL(k_item_count, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->adj, g->in_off,
+                       n, chunk, lds_max, packed_range, window_max, L.cnt);
     for (int c = 0; c < kClasses; ++c)
         exclusive_scan_i32_i64(L.cnt + (int64_t)c * n, n, L.base + (int64_t)c * (n + 1), L.scan, s);
     hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
                        chunk, L.cnt, L.base, L.items);
     hipLaunchKernelGGL(k_item_heads, dim3(1), dim3(64), 0, s, L.base, n, L.heads);
-    launch_class<8, 1, 16, true>(g, L, 0, chunk, t, s);
-    launch_class<10, 2, 64, true>(g, L, 1, chunk, t, s);
-    launch_class<12, 4, 64, true>(g, L, 2, chunk, t, s);
-    launch_class<13, 4, 64, true>(g, L, 3, chunk, t, s);
-    launch_class<8, 1, 16, false>(g, L, 4, chunk, t, s);
-    launch_class<10, 2, 64, false>(g, L, 5, chunk, t, s);
-    launch_class<12, 4, 64, false>(g, L, 6, chunk, t, s);
-    launch_class<13, 4, 64, false>(g, L, 7, chunk, t, s);
+    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s);
+    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s);
+    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s);
+    launch_class<RowHash<13, true>, 4096, 4, 64>(g, L, 3, chunk, t, s);
+    launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
+    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s);
+    launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
+    launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
+    launch_class<RowWindow<14>, 4096, 4, 64>(g, L, 8, chunk, t, s);
+    launch_class<RowWindow<16>, 4096, 4, 64>(g, L, 9, chunk, t, s);
+    launch_class<RowWindow<18>, 4096, 4, 64>(g, L, 10, chunk, t, s);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
 }
