@@ -183,6 +183,49 @@ mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t
 mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, int32_t* labels,
                    int64_t* n_components, void* ws, size_t ws_bytes);
 
+/* Per graph and threshold results of mcd_sweep. */
+typedef struct {
+    int64_t m_kept;            /* edges kept (NOT sim < delta)                       */
+    int64_t n_components;      /* connected components, singletons included          */
+    int64_t largest_component; /* vertices in the largest component                  */
+    int64_t pairs_cluster;     /* A: vertex pairs that share a component             */
+    int64_t pairs_class;       /* B: vertex pairs that share a planted class (or 0)  */
+    int64_t pairs_both;        /* S: vertex pairs that share both (or 0)             */
+    int64_t pairs_total;       /* N = n_g (n_g - 1) / 2                               */
+} mcd_sweep_stats;
+
+/* Most thresholds one mcd_sweep call evaluates. */
+#define MCD_SWEEP_MAX_THRESHOLDS 64
+
+/* Scratch for mcd_sweep. */
+mcd_status mcd_sweep_workspace_size(const mcd_graph* g, int32_t n_graphs, int32_t n_thresholds,
+                                    int32_t has_truth, size_t* bytes);
+
+/* Algorithm 1 at K thresholds at once, over one graph or a batch of disjoint
+ * graphs packed into g (graph k owns the original ids [vbase[k], vbase[k+1])).
+ * Every edge's level (how many of the thresholds it survives) fixes all K prune
+ * masks; one union-find then absorbs the edges level by level from the
+ * highest threshold down, and after each level per-graph statistics are taken
+ * (the selection statistics of Sec. 4.4: kept edges, number of components,
+ * largest component).  With planted labels `truth`, the adjusted Rand index
+ * ARI = (S - A B / N) / ((A + B) / 2 - A B / N) (1 when the denominator is 0)
+ * is evaluated in fp64 from the exact pair counts.
+ *   host_deltas: K thresholds (any order, duplicates allowed), K <= 64.
+ *   vbase:       device int64[n_graphs + 1], vbase[0] = 0, vbase[n_graphs] = n,
+ *                non-decreasing (n_graphs = 1, vbase = {0, n}: a single graph).
+ *   truth:       device int32[n] class of every original id, ids in [0, n); a
+ *                class may not span two graphs.  NULL: no ARI (pairs_class,
+ *                pairs_both and ari are 0).
+ *   stats:       device mcd_sweep_stats[n_graphs][K] (slot k = caller's k-th threshold).
+ *   ari:         device double[n_graphs][K], may be NULL.
+ *   labels:      device int32[K][n] min-original-id labels per threshold, may be NULL.
+ * Asynchronous; no host synchronisation or memset inside, so the call can be
+ * captured in a HIP graph. */
+mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                     const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
+                     const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
+                     int32_t* labels, void* ws, size_t ws_bytes);
+
 /* Scratch for mcd_percentile_threshold. */
 mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes);
 

@@ -204,3 +204,42 @@ def run(n: int, src, dst, measure: int, num: int, den: int, timings: dict | None
     t4 = time.perf_counter()
     tm.update(canon=t1 - t0, triangles=t2 - t1, weight_prune=t3 - t2, components=t4 - t3)
     return dict(lo=lo, hi=hi, deg=deg, t=t, w=w, keep=keep, labels=labels, ncc=ncc)
+
+
+def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None):
+    """Algorithm 1 at every threshold of `deltas`, one graph or a batch of
+    disjoint graphs (graph k owns ids [vbase[k], vbase[k+1])).
+
+    Returns (stats[G][K][7], ari[G][K] or None, labels[K][n]) with the fields
+    m_kept, n_components, largest_component, pairs_cluster (A), pairs_class
+    (B), pairs_both (S), pairs_total (N); ARI from or_ari on each graph."""
+    if vbase is None:
+        vbase = np.array([0, n], np.int64)
+    vbase = np.asarray(vbase, np.int64)
+    G, K = len(vbase) - 1, len(deltas)
+    stats = np.zeros((G, K, 7), np.int64)
+    ari_out = np.zeros((G, K)) if truth is not None else None
+    labels_all = np.zeros((K, n), np.int32)
+    egraph = np.searchsorted(vbase, lo, side="right") - 1
+    for i, (num, den) in enumerate(deltas):
+        keep = prune(measure, lo, hi, t, deg, num, den)
+        labels, _ = components(n, lo, hi, keep)
+        labels_all[i] = labels
+        for gk in range(G):
+            a, b = vbase[gk], vbase[gk + 1]
+            lab = labels[a:b]
+            nv = b - a
+            roots = np.count_nonzero(lab == np.arange(a, b))
+            sizes = np.bincount(lab - a, minlength=max(nv, 1)) if nv else np.zeros(1, np.int64)
+            row = [int(keep[egraph == gk].sum()), roots, int(sizes.max()) if nv else 0]
+            if truth is not None and nv:
+                v, sums = ari(lab, truth[a:b])
+                row += [int(sums[1]), int(sums[2]), int(sums[0]), int(sums[3])]
+                ari_out[gk, i] = v
+            else:
+                A = int((sizes * (sizes - 1) // 2).sum()) if nv else 0
+                row += [A, 0, 0, nv * (nv - 1) // 2]
+                if truth is not None:
+                    ari_out[gk, i] = 1.0
+            stats[gk, i] = row
+    return stats, ari_out, labels_all

@@ -420,6 +420,56 @@ mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, 
     return MCD_OK;
 }
 
+mcd_status mcd_sweep_workspace_size(const mcd_graph* g, int32_t n_graphs, int32_t n_thresholds,
+                                    int32_t has_truth, size_t* bytes) {
+    REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(n_graphs >= 1 && n_thresholds >= 1 && n_thresholds <= MCD_SWEEP_MAX_THRESHOLDS,
+            MCD_ERR_INVALID_ARG, "need n_graphs >= 1 and 1 <= n_thresholds <= 64");
+    *bytes = mcd::sweep_scratch_bytes(g, n_graphs, n_thresholds, has_truth != 0);
+    return MCD_OK;
+}
+
+mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                     const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
+                     const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
+                     int32_t* labels, void* ws, size_t ws_bytes) {
+    REQUIRE(g && host_deltas && vbase && stats && ws, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
+    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    size_t need = 0;
+    mcd_status st = mcd_sweep_workspace_size(g, n_graphs, n_thresholds, truth != nullptr, &need);
+    if (st != MCD_OK) return st;
+    REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "sweep workspace too small");
+    const int K = n_thresholds;
+    int order[MCD_SWEEP_MAX_THRESHOLDS];
+    for (int i = 0; i < K; ++i) {
+        if ((st = check_delta(host_deltas[i])) != MCD_OK) return st;
+        order[i] = i;
+    }
+    // insertion sort by exact value; equal thresholds keep the caller's order
+    for (int i = 1; i < K; ++i) {
+        const int x = order[i];
+        int j = i - 1;
+        while (j >= 0) {
+            const mcd_rational& a = host_deltas[order[j]];
+            const mcd_rational& b = host_deltas[x];
+            if ((__int128)a.num * b.den <= (__int128)b.num * a.den) break;
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = x;
+    }
+    mcd::SweepDeltas ds;
+    ds.K = K;
+    for (int i = 0; i < K; ++i) {
+        ds.num[i] = host_deltas[order[i]].num;
+        ds.den[i] = host_deltas[order[i]].den;
+    }
+    if ((st = use_device(g->ctx)) != MCD_OK) return st;
+    mcd::launch_sweep(g, measure, t, ds, order, n_graphs, vbase, truth, stats, ari, labels, ws, g->ctx->stream);
+    return MCD_OK;
+}
+
 mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes) {
     REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
     *bytes = mcd::select_scratch_bytes(g);

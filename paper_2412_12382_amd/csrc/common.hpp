@@ -148,4 +148,17 @@ void sel_min_above(const mcd_graph* g, int measure, const int32_t* t, uint32_t k
 void sel_count_eq(const mcd_graph* g, int measure, const int32_t* t, uint32_t key, int64_t num,
                   int64_t den, int64_t* cnt, hipStream_t s);
 
+// ---- threshold sweep (sweep.hip) ----
+#define MCD_SWEEP_MAX 64
+struct SweepDeltas {  // thresholds sorted ascending, passed by value to kernels
+    int K;
+    int64_t num[MCD_SWEEP_MAX];
+    int64_t den[MCD_SWEEP_MAX];
+};
+size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth);
+// out_index[i]: caller's slot of the i-th smallest threshold
+void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
+                  const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
+                  mcd_sweep_stats* stats, double* ari, int32_t* labels, void* ws, hipStream_t s);
+
 }  // namespace mcd

@@ -1,0 +1,427 @@
+// Threshold sweep over one graph or a batch of disjoint graphs, with
+// per-threshold statistics and the adjusted Rand index against planted labels.
+//
+// Algorithm 1 keeps an edge at threshold delta iff NOT (sim < delta), so with
+// thresholds sorted ascending an edge's "level" (the number of thresholds it
+// survives) decides all K prune masks at once: kept at threshold i iff
+// level > i.  Walking i from K-1 down to 0 only ever adds edges, so one
+// union-find absorbs each level's edges in turn; after each level the
+// partition is exactly the components of the edges kept at threshold i (hooks
+// still go toward the smaller original id, so roots are canonical labels).
+//
+// ARI (Hubert & Arabie) per graph and threshold from exact pair counts:
+//   S = sum over (cluster, class) cells of C(n_cc, 2)
+//   A = sum over clusters of C(a, 2), B = sum over classes of C(b, 2), N = C(n, 2)
+// each gathered as sum over vertices of (cell size - 1) / 2.
+#include "common.hpp"
+
+namespace mcd {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t N, int64_t cap) {
+    int64_t b = (N + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+#define GRID_STRIDE(i, N)                                                              \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (N);          \
+         i += (int64_t)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ int rat_cmp(int64_t a, int64_t b, int64_t c, int64_t d) {
+    const __int128 l = (__int128)a * d, r = (__int128)c * b;
+    return (l > r) - (l < r);
+}
+
+// acc[key] += val, summing first over the lanes of the wave whose key equals
+// lane 0's (the common case: one graph, one giant component).  All lanes of
+// the wave that reach the call must be active together (grid-stride loops
+// keep the active lanes a prefix of the wave).
+__device__ __forceinline__ void agg_add(unsigned long long* acc, int64_t key, unsigned long long val) {
+    const int64_t k0 = __shfl(key, 0);
+    const bool same = key == k0;
+    unsigned long long x = same ? val : 0ull;
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if ((threadIdx.x & 63) == 0) {
+        if (x) atomicAdd(&acc[k0], x);
+    }
+    if (!same && val) atomicAdd(&acc[key], val);
+}
+
+// level[e] = number of sorted thresholds delta_i with NOT (sim(e) < delta_i)
+__global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ src,
+                                                    const int32_t* __restrict__ adj,
+                                                    const int32_t* __restrict__ deg,
+                                                    const int32_t* __restrict__ t, int64_t m, int measure,
+                                                    SweepDeltas ds, uint8_t* __restrict__ level) {
+    GRID_STRIDE(e, m) {
+        const int64_t D = (int64_t)deg[src[e]] + deg[adj[e]];
+        const int64_t tt = t[e];
+        const int64_t num = measure == MCD_SIM_TECTONIC ? tt : 3 * tt - D + 2;
+        const int64_t den = measure == MCD_SIM_TECTONIC ? D : 1;
+        int lo = 0, hi = ds.K;  // first threshold that prunes e
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rat_cmp(num, den, ds.num[mid], ds.den[mid]) >= 0) lo = mid + 1;
+            else hi = mid;
+        }
+        level[e] = (uint8_t)lo;
+    }
+}
+
+// graph id and class of every rank-numbered vertex
+__global__ __launch_bounds__(kThreads) void k_vertex_info(const int32_t* __restrict__ perm, int64_t n,
+                                                          const int64_t* __restrict__ vbase, int G,
+                                                          const int32_t* __restrict__ truth,
+                                                          int32_t* __restrict__ gid, int32_t* __restrict__ cls) {
+    GRID_STRIDE(v, n) {
+        const int64_t x = perm[v];
+        int lo = 0, hi = G;  // last g with vbase[g] <= x
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (vbase[mid] <= x) lo = mid;
+            else hi = mid;
+        }
+        gid[v] = lo;
+        if (truth) cls[v] = truth[x];
+    }
+}
+
+// per-graph count of edges at each level; an LDS histogram when it fits
+__global__ __launch_bounds__(kThreads) void k_level_hist(const int32_t* __restrict__ src,
+                                                         const uint8_t* __restrict__ level, int64_t m,
+                                                         const int32_t* __restrict__ gid, int K, int nbins,
+                                                         unsigned long long* __restrict__ hist) {
+    __shared__ uint32_t h[2048];
+    const bool local = nbins <= 2048;
+    if (local)
+        for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    GRID_STRIDE(e, m) {
+        const int64_t key = (int64_t)gid[src[e]] * (K + 1) + level[e];
+        if (local) atomicAdd(&h[key], 1u);
+        else atomicAdd(&hist[key], 1ull);
+    }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+            if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+__device__ __forceinline__ int32_t ld_parent(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_parent(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x) {
+    for (;;) {
+        const int32_t p = ld_parent(&parent[x]);
+        if (p == x) return x;
+        const int32_t gp = ld_parent(&parent[p]);
+        if (gp != p) st_parent(&parent[x], gp);
+        x = gp;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_init_parent(int32_t* __restrict__ parent, int64_t n) {
+    GRID_STRIDE(v, n) parent[v] = (int32_t)v;
+}
+
+// unite the endpoints of every edge at level lv
+__global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restrict__ src,
+                                                          const int32_t* __restrict__ adj,
+                                                          const uint8_t* __restrict__ level, int64_t m,
+                                                          int lv, const int32_t* __restrict__ perm,
+                                                          int32_t* parent) {
+    GRID_STRIDE(e, m) {
+        if (level[e] != lv) continue;
+        int32_t a = src[e], b = adj[e];
+        for (;;) {
+            a = find_root(parent, a);
+            b = find_root(parent, b);
+            if (a == b) break;
+            if (perm[a] < perm[b]) {
+                const int32_t x = a;
+                a = b;
+                b = x;
+            }
+            int32_t expected = a;
+            if (__hip_atomic_compare_exchange_strong(&parent[a], &expected, b, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+    }
+}
+
+// Pass 1 over vertices: compress to the root, count roots per graph, size of
+// every component, optional labels of this threshold.
+__global__ __launch_bounds__(kThreads) void k_pass_size(int32_t* parent, int64_t n,
+                                                        const int32_t* __restrict__ gid,
+                                                        const int32_t* __restrict__ perm,
+                                                        int32_t* __restrict__ size,
+                                                        unsigned long long* __restrict__ ncc,
+                                                        int32_t* __restrict__ labels) {
+    const int lane = threadIdx.x & 63;
+    GRID_STRIDE(v, n) {
+        const int32_t r = find_root(parent, (int32_t)v);
+        st_parent(&parent[v], r);
+        agg_add(ncc, gid[v], r == (int32_t)v ? 1ull : 0ull);
+        if (labels) labels[perm[v]] = perm[r];
+        const int32_t r0 = __shfl(r, 0);
+        const uint64_t same = __ballot(r == r0);
+        if (r == r0) {
+            if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&size[r], (int32_t)__popcll(same));
+        } else {
+            atomicAdd(&size[r], 1);
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t cell_key(int32_t r, int32_t c) {
+    return ((uint64_t)(uint32_t)r << 32) | (uint32_t)c;
+}
+
+__device__ __forceinline__ uint32_t cell_slot(uint64_t k, int log2cap) {
+    return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
+}
+
+// Pass 2: A (same cluster pairs) and the largest component per graph; with
+// labels, count every (cluster, class) cell in a hash table.
+__global__ __launch_bounds__(kThreads) void k_pass_cells(const int32_t* __restrict__ parent, int64_t n,
+                                                         const int32_t* __restrict__ gid,
+                                                         const int32_t* __restrict__ size,
+                                                         const int32_t* __restrict__ cls,
+                                                         unsigned long long* __restrict__ acc_a,
+                                                         unsigned long long* __restrict__ largest,
+                                                         unsigned long long* __restrict__ keys,
+                                                         int32_t* __restrict__ counts, int log2cap) {
+    const int lane = threadIdx.x & 63;
+    GRID_STRIDE(v, n) {
+        const int32_t r = parent[v];  // compressed in pass 1
+        const int32_t g = gid[v];
+        const int32_t sz = size[r];
+        agg_add(acc_a, g, (unsigned long long)(sz - 1));
+        if (r == (int32_t)v) atomicMax(&largest[g], (unsigned long long)sz);
+        if (cls) {
+            const uint64_t k = cell_key(r, cls[v]);
+            const uint32_t mask = (1u << log2cap) - 1u;
+            uint32_t h = cell_slot(k, log2cap);
+            for (;;) {
+                const unsigned long long prev = atomicCAS(&keys[h], ~0ull, (unsigned long long)k);
+                if (prev == ~0ull || prev == k) break;
+                h = (h + 1) & mask;
+            }
+            const uint64_t k0 = __shfl(k, 0);
+            const uint64_t same = __ballot(k == k0);
+            if (k == k0) {
+                if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&counts[h], (int32_t)__popcll(same));
+            } else {
+                atomicAdd(&counts[h], 1);
+            }
+        }
+    }
+}
+
+// Pass 3: S (pairs sharing cluster and class) per graph.
+__global__ __launch_bounds__(kThreads) void k_pass_s(const int32_t* __restrict__ parent, int64_t n,
+                                                     const int32_t* __restrict__ gid,
+                                                     const int32_t* __restrict__ cls,
+                                                     const unsigned long long* __restrict__ keys,
+                                                     const int32_t* __restrict__ counts, int log2cap,
+                                                     unsigned long long* __restrict__ acc_s) {
+    GRID_STRIDE(v, n) {
+        const uint64_t k = cell_key(parent[v], cls[v]);
+        const uint32_t mask = (1u << log2cap) - 1u;
+        uint32_t h = cell_slot(k, log2cap);
+        while (keys[h] != k) h = (h + 1) & mask;
+        agg_add(acc_s, gid[v], (unsigned long long)(counts[h] - 1));
+    }
+}
+
+// class sizes (truth ids lie in [0, n)), then B per graph
+__global__ __launch_bounds__(kThreads) void k_class_size(const int32_t* __restrict__ cls, int64_t n,
+                                                         int32_t* __restrict__ csize) {
+    const int lane = threadIdx.x & 63;
+    GRID_STRIDE(v, n) {
+        const int32_t c = cls[v];
+        const int32_t c0 = __shfl(c, 0);
+        const uint64_t same = __ballot(c == c0);
+        if (c == c0) {
+            if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&csize[c], (int32_t)__popcll(same));
+        } else {
+            atomicAdd(&csize[c], 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_class_b(const int32_t* __restrict__ cls, int64_t n,
+                                                      const int32_t* __restrict__ gid,
+                                                      const int32_t* __restrict__ csize,
+                                                      unsigned long long* __restrict__ acc_b) {
+    GRID_STRIDE(v, n) agg_add(acc_b, gid[v], (unsigned long long)(csize[cls[v]] - 1));
+}
+
+// Writes the statistics of threshold slot `out_i` for every graph.
+__global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_thresh, int out_i,
+                                                          const unsigned long long* __restrict__ hist,
+                                                          const unsigned long long* __restrict__ ncc,
+                                                          const unsigned long long* __restrict__ largest,
+                                                          const unsigned long long* __restrict__ acc_a,
+                                                          const unsigned long long* __restrict__ acc_s,
+                                                          const unsigned long long* __restrict__ acc_b,
+                                                          const int64_t* __restrict__ vbase, int has_truth,
+                                                          mcd_sweep_stats* __restrict__ stats,
+                                                          double* __restrict__ ari) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+        int64_t kept = 0;
+        for (int l = lv_thresh + 1; l <= K; ++l) kept += (int64_t)hist[(int64_t)g * (K + 1) + l];
+        mcd_sweep_stats st;
+        const int64_t nv = vbase[g + 1] - vbase[g];
+        st.m_kept = kept;
+        st.n_components = (int64_t)ncc[g];
+        st.largest_component = (int64_t)largest[g];
+        st.pairs_cluster = (int64_t)(acc_a[g] / 2);
+        st.pairs_class = has_truth ? (int64_t)(acc_b[g] / 2) : 0;
+        st.pairs_both = has_truth ? (int64_t)(acc_s[g] / 2) : 0;
+        st.pairs_total = nv * (nv - 1) / 2;
+        stats[(int64_t)g * K + out_i] = st;
+        if (ari) {
+            double r = 0.0;
+            if (has_truth) {
+                const double A = (double)st.pairs_cluster, B = (double)st.pairs_class;
+                const double S = (double)st.pairs_both, N = (double)st.pairs_total;
+                const double prod = (A * B) / N;
+                const double den = 0.5 * (A + B) - prod;
+                r = (st.pairs_total == 0 || den == 0.0) ? 1.0 : (S - prod) / den;
+            }
+            ari[(int64_t)g * K + out_i] = r;
+        }
+    }
+}
+
+template <class T>
+__global__ void k_fill_t(T* __restrict__ p, int64_t N, T v) {
+    GRID_STRIDE(i, N) p[i] = v;
+}
+
+template <class T>
+void fill_t(T* p, int64_t N, T v, hipStream_t s) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_fill_t<T>, dim3(grid_for(N, 8192)), dim3(kThreads), 0, s, p, N, v);
+}
+
+int cells_log2(int64_t n) {
+    int l = 4;
+    while (((int64_t)1 << l) < 2 * n + 16) ++l;
+    return l;
+}
+
+struct SweepLayout {
+    uint8_t* level;
+    int32_t* parent;
+    int32_t* gid;
+    int32_t* cls;
+    int32_t* size;
+    int32_t* csize;
+    unsigned long long* keys;
+    int32_t* counts;
+    unsigned long long* hist;    // [G][K+1]
+    unsigned long long* ncc;     // [G]
+    unsigned long long* largest; // [G]
+    unsigned long long* acc_a;   // [G]
+    unsigned long long* acc_s;   // [G]
+    unsigned long long* acc_b;   // [G]
+    size_t bytes;
+};
+
+SweepLayout sweep_layout(void* p, const mcd_graph* g, int G, int K, bool truth) {
+    Carve c{(char*)p, 0, 0};
+    SweepLayout L;
+    const int64_t n = g->n, m = g->m;
+    L.level = c.take<uint8_t>((size_t)m);
+    L.parent = c.take<int32_t>((size_t)n);
+    L.gid = c.take<int32_t>((size_t)n);
+    L.size = c.take<int32_t>((size_t)n);
+    L.cls = truth ? c.take<int32_t>((size_t)n) : nullptr;
+    L.csize = truth ? c.take<int32_t>((size_t)n) : nullptr;
+    const int64_t cap = truth ? ((int64_t)1 << cells_log2(n)) : 0;
+    L.keys = truth ? c.take<unsigned long long>((size_t)cap) : nullptr;
+    L.counts = truth ? c.take<int32_t>((size_t)cap) : nullptr;
+    L.hist = c.take<unsigned long long>((size_t)G * (K + 1));
+    L.ncc = c.take<unsigned long long>((size_t)G);
+    L.largest = c.take<unsigned long long>((size_t)G);
+    L.acc_a = c.take<unsigned long long>((size_t)G);
+    L.acc_s = c.take<unsigned long long>((size_t)G);
+    L.acc_b = c.take<unsigned long long>((size_t)G);
+    L.bytes = c.used;
+    return L;
+}
+
+}  // namespace
+
+size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth) {
+    return sweep_layout(nullptr, g, G, K, truth).bytes;
+}
+
+void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
+                  const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
+                  mcd_sweep_stats* stats, double* ari, int32_t* labels, void* ws, hipStream_t s) {
+    const int K = ds.K;
+    const int64_t n = g->n, m = g->m;
+    SweepLayout L = sweep_layout(ws, g, G, K, truth != nullptr);
+    const int l2 = truth ? cells_log2(n) : 0;
+    const int64_t cap = truth ? ((int64_t)1 << l2) : 0;
+    fill_t<unsigned long long>(L.hist, (int64_t)G * (K + 1), 0ull, s);
+    fill_t<unsigned long long>(L.acc_b, G, 0ull, s);
+    if (n > 0)
+        hipLaunchKernelGGL(k_vertex_info, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->perm, n, vbase, G,
+                           truth, L.gid, L.cls);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_level, dim3(grid_for(m, 16384)), dim3(kThreads), 0, s, g->src, g->adj, g->deg, t, m,
+                           measure, ds, L.level);
+        hipLaunchKernelGGL(k_level_hist, dim3(grid_for(m, 4096)), dim3(kThreads), 0, s, g->src, L.level, m,
+                           L.gid, K, G * (K + 1), L.hist);
+    }
+    if (truth && n > 0) {
+        fill_t<int32_t>(L.csize, n, 0, s);
+        hipLaunchKernelGGL(k_class_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.csize);
+        hipLaunchKernelGGL(k_class_b, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.gid, L.csize,
+                           L.acc_b);
+    }
+    if (n > 0) hipLaunchKernelGGL(k_init_parent, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n);
+    for (int i = K - 1; i >= 0; --i) {
+        if (m > 0)
+            hipLaunchKernelGGL(k_union_level, dim3(grid_for(m, 16384)), dim3(kThreads), 0, s, g->src, g->adj,
+                               L.level, m, i + 1, g->perm, L.parent);
+        fill_t<unsigned long long>(L.ncc, G, 0ull, s);
+        fill_t<unsigned long long>(L.largest, G, 0ull, s);
+        fill_t<unsigned long long>(L.acc_a, G, 0ull, s);
+        fill_t<unsigned long long>(L.acc_s, G, 0ull, s);
+        fill_t<int32_t>(L.size, n, 0, s);
+        int32_t* lab = labels ? labels + (int64_t)out_index[i] * n : nullptr;
+        if (n > 0) {
+            hipLaunchKernelGGL(k_pass_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid,
+                               g->perm, L.size, L.ncc, lab);
+            if (truth) {
+                fill_t<unsigned long long>(L.keys, cap, ~0ull, s);
+                fill_t<int32_t>(L.counts, cap, 0, s);
+            }
+            hipLaunchKernelGGL(k_pass_cells, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid,
+                               L.size, L.cls, L.acc_a, L.largest, L.keys, L.counts, l2);
+            if (truth)
+                hipLaunchKernelGGL(k_pass_s, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid,
+                                   L.cls, L.keys, L.counts, l2, L.acc_s);
+        }
+        hipLaunchKernelGGL(k_write_stats, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), 0, s, G, K, i,
+                           out_index[i], L.hist, L.ncc, L.largest, L.acc_a, L.acc_s, L.acc_b, vbase,
+                           truth ? 1 : 0, stats, ari);
+    }
+}
+
+}  // namespace mcd

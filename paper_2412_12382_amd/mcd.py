@@ -37,6 +37,11 @@ class mcd_rational(ctypes.Structure):
     _fields_ = [("num", ctypes.c_int64), ("den", ctypes.c_int64)]
 
 
+SWEEP_FIELDS = ("m_kept", "n_components", "largest_component", "pairs_cluster", "pairs_class",
+                "pairs_both", "pairs_total")
+SWEEP_MAX = 64
+
+
 _lib = None
 
 
@@ -71,6 +76,8 @@ def lib():
             "mcd_components": [P, P, P, P, P, SZ],
             "mcd_run": [P, ctypes.c_int, mcd_rational, P, P, P, SZ],
             "mcd_percentile_workspace_size": [P, ctypes.POINTER(SZ)],
+            "mcd_sweep_workspace_size": [P, I32, I32, I32, ctypes.POINTER(SZ)],
+            "mcd_sweep": [P, ctypes.c_int, P, P, I32, I32, P, P, P, P, P, P, SZ],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
         for name, args in sig.items():
@@ -298,6 +305,34 @@ def mcd_percentile_threshold(g: Graph, measure: int, t, pct_num: int, pct_den: i
     _check(lib().mcd_percentile_threshold(g.handle, measure, _p(t), pct_num, pct_den, _p(ws),
                                           ws.numel() * ws.element_size(), ctypes.byref(out)))
     return out.num, out.den
+
+
+def mcd_sweep_workspace_size(g: Graph, n_graphs: int, K: int, has_truth: bool) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_sweep_workspace_size(g.handle, n_graphs, K, int(has_truth), ctypes.byref(b)))
+    return b.value
+
+
+def mcd_sweep(g: Graph, measure: int, t, deltas, vbase=None, truth=None, stats=None, ari=None,
+              labels=None, want_labels=False, ws=None):
+    """Returns (stats int64[G][K][7], ari float64[G][K] or None, labels int32[K][n] or None)."""
+    K = len(deltas)
+    dev = g.ctx.device
+    if vbase is None:
+        vbase = torch.tensor([0, g.n], dtype=torch.int64, device=dev)
+    G = vbase.numel() - 1
+    arr = (mcd_rational * K)(*[mcd_rational(int(a), int(b)) for a, b in deltas])
+    if stats is None:
+        stats = _empty((G, K, len(SWEEP_FIELDS)), torch.int64, dev)
+    if ari is None and truth is not None:
+        ari = _empty((G, K), torch.float64, dev)
+    if labels is None and want_labels:
+        labels = _empty((K, max(g.n, 1)), torch.int32, dev)
+    if ws is None:
+        ws = _bytes(mcd_sweep_workspace_size(g, G, K, truth is not None), dev)
+    _check(lib().mcd_sweep(g.handle, measure, _p(t), ctypes.cast(arr, ctypes.c_void_p), K, G, _p(vbase),
+                           _p(truth), _p(stats), _p(ari), _p(labels), _p(ws), ws.numel() * ws.element_size()))
+    return stats, ari, labels
 
 
 def mcd_status_string(status: int) -> str:

@@ -1,0 +1,100 @@
+"""GPU parity of the batched threshold sweep (levels + incremental
+union-find + per-graph statistics + ARI) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+M = pytest.importorskip("paper_2412_12382_amd.mcd")
+
+GRID64 = [(9 + 7 * i, 900) for i in range(64)]
+GRID16 = [(k, 50) for k in range(16)]
+
+
+def gpu_sweep(src, dst, n, measure, deltas, truth=None, vbase=None):
+    from gpu_util import build
+    g = build(src, dst, n)
+    t = M.mcd_triangles(g)
+    vb = None if vbase is None else torch.from_numpy(np.asarray(vbase, np.int64)).cuda()
+    tr = None if truth is None else torch.from_numpy(np.asarray(truth, np.int32)).cuda()
+    stats, ari, labels = M.mcd_sweep(g, measure, t, deltas, vbase=vb, truth=tr, want_labels=True)
+    torch.cuda.synchronize()
+    return (stats.cpu().numpy(), None if ari is None else ari.cpu().numpy(), labels.cpu().numpy()[:, :n])
+
+
+def oracle_sweep(src, dst, n, measure, deltas, truth=None, vbase=None):
+    lo, hi = oracle.canon(n, src, dst)
+    deg = oracle.degrees(n, lo, hi)
+    t = oracle.triangles(n, lo, hi)
+    return oracle.sweep(n, lo, hi, t, deg, measure, deltas, truth, vbase)
+
+
+def compare(got, want):
+    gs, ga, gl = got
+    ws, wa, wl = want
+    assert np.array_equal(gl, wl)
+    assert np.array_equal(gs, ws)
+    if wa is not None:
+        assert np.all(np.abs(ga - wa) <= 1e-12)
+
+
+def test_sweep_rmat_grid16():
+    s, d, n = gg.rmat(14, seed=31)
+    compare(gpu_sweep(s, d, n, oracle.TECTONIC, GRID16), oracle_sweep(s, d, n, oracle.TECTONIC, GRID16))
+
+
+def test_sweep_tw_unsorted_duplicates():
+    s, d, n = gg.rmat(12, seed=32)
+    deltas = [(0, 1), (-10, 1), (3, 2), (-10, 1), (-40, 3), (7, 1), (-1, 1)]
+    compare(gpu_sweep(s, d, n, oracle.TW, deltas), oracle_sweep(s, d, n, oracle.TW, deltas))
+
+
+def test_sweep_sbm_planted_ari():
+    c1 = gg.sbm_c1()
+    args = (c1["src"], c1["dst"], c1["n"], oracle.TECTONIC, GRID64, c1["truth"])
+    compare(gpu_sweep(*args), oracle_sweep(*args))
+
+
+def test_sweep_batch_of_sbms():
+    graphs = []
+    for g in range(6):
+        pr = gg.sbm_batch_params(g)
+        n = min(pr["n"], 3000)
+        k = min(pr["k"], n // 4)
+        src, dst, lab = gg.sbm_skip(n, k, min(pr["d_in"] / (n / k - 1), 0.5),
+                                    pr["mu"] * pr["d_in"] / ((1 - pr["mu"]) * n), 1000 + g)
+        graphs.append((n, src, dst, lab))
+    vbase = np.zeros(len(graphs) + 1, np.int64)
+    srcs, dsts, truths = [], [], []
+    cbase = 0
+    for i, (n, src, dst, lab) in enumerate(graphs):
+        vbase[i + 1] = vbase[i] + n
+        srcs.append(src + vbase[i])
+        dsts.append(dst + vbase[i])
+        truths.append(lab + cbase)
+        cbase += int(lab.max()) + 1
+    N = int(vbase[-1])
+    src = np.concatenate(srcs).astype(np.int32)
+    dst = np.concatenate(dsts).astype(np.int32)
+    truth = np.concatenate(truths).astype(np.int32)
+    args = (src, dst, N, oracle.TECTONIC, GRID64, truth, vbase)
+    compare(gpu_sweep(*args), oracle_sweep(*args))
+
+
+def test_sweep_matches_single_threshold_pipeline():
+    # every sweep slot equals prune + components at that threshold alone
+    from gpu_util import build
+    s, d, n = gg.rmat(13, seed=33)
+    g = build(s, d, n)
+    t = M.mcd_triangles(g)
+    stats, _, labels = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, GRID16, want_labels=True)
+    for k, delta in enumerate(GRID16):
+        keep, nk = M.mcd_prune(g, M.MCD_SIM_TECTONIC, t, delta)
+        lab, ncc = M.mcd_components(g, keep)
+        torch.cuda.synchronize()
+        assert torch.equal(lab, labels[k, :n])
+        assert int(ncc.item()) == int(stats[0, k, 1].item())
+        assert int(nk.item()) == int(stats[0, k, 0].item())
