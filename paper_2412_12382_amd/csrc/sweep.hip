@@ -193,7 +193,7 @@ __device__ __forceinline__ uint32_t cell_slot(uint64_t k, int log2cap) {
 
 // Pass 2: A (same cluster pairs) and the largest component per graph; with
 // labels, count every (cluster, class) cell in a hash table.
-__global__ __launch_bounds__(kThreads) void k_pass_cells(const int32_t* __restrict__ parent, int64_t n,
+__global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_t n,
                                                          const int32_t* __restrict__ gid,
                                                          const int32_t* __restrict__ size,
                                                          const int32_t* __restrict__ cls,
@@ -203,7 +203,9 @@ __global__ __launch_bounds__(kThreads) void k_pass_cells(const int32_t* __restri
                                                          int32_t* __restrict__ counts, int log2cap) {
     const int lane = threadIdx.x & 63;
     GRID_STRIDE(v, n) {
-        const int32_t r = parent[v];  // compressed in pass 1
+        // pass 1 compressed the paths, but a concurrent halving may have left
+        // parent[v] at an ancestor below the root: always follow to the root
+        const int32_t r = find_root(parent, (int32_t)v);
         const int32_t g = gid[v];
         const int32_t sz = size[r];
         agg_add(acc_a, g, (unsigned long long)(sz - 1));
@@ -229,14 +231,14 @@ __global__ __launch_bounds__(kThreads) void k_pass_cells(const int32_t* __restri
 }
 
 // Pass 3: S (pairs sharing cluster and class) per graph.
-__global__ __launch_bounds__(kThreads) void k_pass_s(const int32_t* __restrict__ parent, int64_t n,
+__global__ __launch_bounds__(kThreads) void k_pass_s(int32_t* parent, int64_t n,
                                                      const int32_t* __restrict__ gid,
                                                      const int32_t* __restrict__ cls,
                                                      const unsigned long long* __restrict__ keys,
                                                      const int32_t* __restrict__ counts, int log2cap,
                                                      unsigned long long* __restrict__ acc_s) {
     GRID_STRIDE(v, n) {
-        const uint64_t k = cell_key(parent[v], cls[v]);
+        const uint64_t k = cell_key(find_root(parent, (int32_t)v), cls[v]);
         const uint32_t mask = (1u << log2cap) - 1u;
         uint32_t h = cell_slot(k, log2cap);
         while (keys[h] != k) h = (h + 1) & mask;

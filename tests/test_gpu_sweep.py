@@ -36,7 +36,8 @@ def compare(got, want):
     gs, ga, gl = got
     ws, wa, wl = want
     assert np.array_equal(gl, wl)
-    assert np.array_equal(gs, ws)
+    bad = np.argwhere(gs != ws)
+    assert len(bad) == 0, [(tuple(b), int(gs[tuple(b)]), int(ws[tuple(b)])) for b in bad[:10]]
     if wa is not None:
         assert np.all(np.abs(ga - wa) <= 1e-12)
 
@@ -81,7 +82,9 @@ def test_sweep_batch_of_sbms():
     dst = np.concatenate(dsts).astype(np.int32)
     truth = np.concatenate(truths).astype(np.int32)
     args = (src, dst, N, oracle.TECTONIC, GRID64, truth, vbase)
-    compare(gpu_sweep(*args), oracle_sweep(*args))
+    want = oracle_sweep(*args)
+    for _ in range(3):  # repeated runs must agree exactly (surfaces races)
+        compare(gpu_sweep(*args), want)
 
 
 def test_sweep_matches_single_threshold_pipeline():
