@@ -241,3 +241,33 @@ def sbm_batch_graph(g: int):
     pr = sbm_batch_params(g)
     src, dst, labels = sbm_skip(pr["n"], pr["k"], pr["p_in"], pr["p_out"], pr["seed"])
     return dict(name=f"sbm_batch_{g}", n=pr["n"], src=src, dst=dst, truth=labels, params=pr)
+
+
+def sbm_batch(G: int = 256, n_max: int | None = None, first: int = 0):
+    """Graphs first .. first+G-1 of the planted-partition batch as one disjoint
+    union: dict(src, dst, n, vbase[G+1], truth (class ids unique across
+    graphs), params).  n_max caps each graph's vertex count (smaller test
+    batches); the other parameters keep their draws."""
+    srcs, dsts, truths, params = [], [], [], []
+    vbase = [0]
+    cbase = 0
+    for g in range(first, first + G):
+        pr = dict(sbm_batch_params(g))
+        if n_max is not None and pr["n"] > n_max:
+            n = n_max
+            k = max(2, min(pr["k"], n // 4))
+            s = n / k
+            p_in = min(pr["d_in"] / (s - 1.0), 0.5)
+            d_in = p_in * (s - 1.0)
+            p_out = pr["mu"] * d_in / ((1.0 - pr["mu"]) * (n - s))
+            pr.update(n=n, k=k, p_in=p_in, p_out=p_out, d_in=d_in)
+        src, dst, lab = sbm_skip(pr["n"], pr["k"], pr["p_in"], pr["p_out"], pr["seed"])
+        srcs.append(src + vbase[-1])
+        dsts.append(dst + vbase[-1])
+        truths.append(lab + cbase)
+        cbase += pr["k"]
+        vbase.append(vbase[-1] + pr["n"])
+        params.append(pr)
+    return dict(src=np.concatenate(srcs).astype(np.int32), dst=np.concatenate(dsts).astype(np.int32),
+                n=vbase[-1], vbase=np.array(vbase, np.int64),
+                truth=np.concatenate(truths).astype(np.int32), params=params)

@@ -226,6 +226,66 @@ mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                      const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
                      int32_t* labels, void* ws, size_t ws_bytes);
 
+/* -------------------------------------------------- learned threshold picker */
+
+#define MCD_MLP_IN 66      /* 64 histogram bins, log1p mean degree, log1p max degree */
+#define MCD_MLP_HIDDEN 64
+#define MCD_MLP_PARAMS 8513 /* W1[64][66] b1[64] W2[64][64] b2[64] W3[64] b3 */
+
+/* Per-graph input features of the picker (one graph, or a batch as in
+ * mcd_sweep): x[k][0..63] = fraction of graph k's edges whose Tectonic value
+ * t / D falls in bin floor(128 t / D) (the values lie in [0, 1/2)),
+ * x[k][64] = log1p(2 m_k / n_k), x[k][65] = log1p(max degree).
+ * x: device float[n_graphs][66]. */
+mcd_status mcd_features_workspace_size(int32_t n_graphs, size_t* bytes);
+mcd_status mcd_features(const mcd_graph* g, const int32_t* t, int32_t n_graphs, const int64_t* vbase,
+                        float* x, void* ws, size_t ws_bytes);
+
+/* Column mean and population standard deviation (1 where it is 0) of a
+ * feature matrix x (device float[batch][66]) into mean, std (device float[66]). */
+mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float* mean, float* std);
+
+/* FP32 MLP 66 -> 64 -> 64 -> 1 with ReLU on the hidden layers, applied to
+ * (x - mean) / std.  params: device float[MCD_MLP_PARAMS]; y: device float[batch]. */
+mcd_status mcd_mlp_forward(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
+                           const float* x, int32_t batch, float* y);
+
+/* Scratch for mcd_mlp_gradient / mcd_mlp_train_step at this batch size. */
+mcd_status mcd_mlp_workspace_size(int32_t batch, size_t* bytes);
+
+/* Gradient of L = (1/batch) sum (y - target)^2 with respect to params (device
+ * float[MCD_MLP_PARAMS]) and L itself (device float[1], may be NULL), summed
+ * over the batch in a fixed order. */
+mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
+                            const float* x, const float* target, int32_t batch, float* grad, float* loss,
+                            void* ws, size_t ws_bytes);
+
+/* One full-batch Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
+ * step counted from 1) on params with moment buffers adam_m, adam_v (device
+ * float[MCD_MLP_PARAMS], zero before step 1).  loss: the pre-step loss. */
+mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
+                              float lr, const float* mean, const float* std, const float* x,
+                              const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes);
+
+/* Snaps picker outputs to the grid delta_i = (a + b i) / c, i = 0..K-1:
+ * i = clamp(round((K - 1) y), 0, K - 1).  index: device int32[batch] (may be
+ * NULL); delta: device int64[batch][2] = (num, den) (may be NULL).  c > 0. */
+mcd_status mcd_grid_select(mcd_ctx* ctx, const float* y, int32_t batch, int32_t K, int64_t a, int64_t b,
+                           int64_t c, int32_t* index, int64_t* delta);
+
+/* Training targets from a sweep's ARI table (device double[n_graphs][K]): the
+ * first run of thresholds that reach the best ARI, its lower middle index
+ * (index, device int32[n_graphs], may be NULL) and index / (K - 1) (y, device
+ * float[n_graphs], may be NULL). */
+mcd_status mcd_sweep_targets(mcd_ctx* ctx, const double* ari, int32_t n_graphs, int32_t K, int32_t* index,
+                             float* y);
+
+/* mcd_prune with one threshold per graph of a batch, read from device memory:
+ * deltas[2k] / deltas[2k+1] (den > 0) is graph k's threshold. */
+mcd_status mcd_prune_graphs(const mcd_graph* g, mcd_measure measure, const int32_t* t, int32_t n_graphs,
+                            const int64_t* vbase, const int64_t* deltas, uint32_t* keep_bits,
+                            int64_t* n_kept);
+
 /* Scratch for mcd_percentile_threshold. */
 mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes);
 

@@ -1,0 +1,110 @@
+"""Float64 reference of the learned threshold picker (test infrastructure).
+
+A plain numpy statement of the network and its training rule:
+  y = W3 . relu(W2 relu(W1 xs + b1) + b2) + b3,   xs = (x - mean) / std,
+  L = (1/B) sum_r (y_r - target_r)^2,
+  Adam (Kingma & Ba, ICLR 2015): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+  p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
+Parameters are one flat vector: W1[64][66], b1[64], W2[64][64], b2[64], W3[64], b3.
+The GPU library shares no code with this file.
+"""
+import numpy as np
+
+NI, NH = 66, 64
+SIZES = [("W1", (NH, NI)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)), ("W3", (NH,)), ("b3", (1,))]
+NPAR = sum(int(np.prod(s)) for _, s in SIZES)
+
+
+def unpack(p):
+    out, o = {}, 0
+    for name, shp in SIZES:
+        k = int(np.prod(shp))
+        out[name] = np.asarray(p[o:o + k], np.float64).reshape(shp)
+        o += k
+    return out
+
+
+def pack(d):
+    return np.concatenate([np.asarray(d[name], np.float64).reshape(-1) for name, _ in SIZES])
+
+
+def forward(p, mean, std, x):
+    P = unpack(p)
+    xs = (np.asarray(x, np.float64) - mean) / std
+    a1 = xs @ P["W1"].T + P["b1"]
+    h1 = np.maximum(a1, 0.0)
+    a2 = h1 @ P["W2"].T + P["b2"]
+    h2 = np.maximum(a2, 0.0)
+    y = h2 @ P["W3"] + P["b3"][0]
+    return y, (xs, a1, h1, a2, h2)
+
+
+def loss(p, mean, std, x, target):
+    y, _ = forward(p, mean, std, x)
+    return float(np.mean((y - target) ** 2))
+
+
+def gradient(p, mean, std, x, target):
+    """Analytic gradient of the loss (chain rule, ReLU derivative 1 iff > 0)."""
+    P = unpack(p)
+    y, (xs, a1, h1, a2, h2) = forward(p, mean, std, x)
+    B = len(y)
+    dy = 2.0 * (y - target) / B
+    g = {"W3": dy @ h2, "b3": np.array([dy.sum()])}
+    dh2 = np.outer(dy, P["W3"]) * (a2 > 0)
+    g["W2"] = dh2.T @ h1
+    g["b2"] = dh2.sum(0)
+    dh1 = (dh2 @ P["W2"]) * (a1 > 0)
+    g["W1"] = dh1.T @ xs
+    g["b1"] = dh1.sum(0)
+    return pack(g), float(np.mean((y - target) ** 2))
+
+
+def adam_step(p, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    p = p - lr * (m / (1 - b1 ** step)) / (np.sqrt(v / (1 - b2 ** step)) + eps)
+    return p, m, v
+
+
+def feature_stats(x):
+    x = np.asarray(x, np.float64)
+    mu = x.mean(0)
+    sd = x.std(0)
+    return mu, np.where(sd > 1e-12, sd, 1.0)
+
+
+def features(n, lo, hi, t, deg):
+    """Picker inputs of one graph: fraction of edges per Tectonic bin
+    floor(128 t / D) (64 bins on [0, 1/2)), log1p(2m/n), log1p(max degree)."""
+    from . import histogram
+    h = histogram(lo, hi, t, deg).astype(np.float64)
+    m = len(lo)
+    x = np.zeros(NI)
+    x[:64] = h / m if m else 0.0
+    x[64] = np.log1p(2.0 * m / n) if n else 0.0
+    x[65] = np.log1p(deg.max() if len(deg) else 0)
+    return x
+
+
+def targets(ari):
+    """First run of thresholds reaching the best ARI; its lower middle index."""
+    ari = np.asarray(ari)
+    idx = np.zeros(ari.shape[0], np.int64)
+    for g, row in enumerate(ari):
+        best = row.max()
+        s = int(np.argmax(row == best))
+        e = s
+        while e + 1 < len(row) and row[e + 1] == best:
+            e += 1
+        idx[g] = (s + e) // 2
+    return idx
+
+
+def select(y, K, a, b, c):
+    """Grid snap i = clamp(round((K-1) y), 0, K-1) (round half to even), delta =
+    (a+b i)/c.  The product is rounded in fp32, the precision of the network
+    output, so both sides take the integer decision in the same precision."""
+    q = np.float32(K - 1) * np.asarray(y, np.float32)
+    i = np.clip(np.rint(q), 0, K - 1).astype(np.int64)
+    return i, np.stack([a + b * i, np.full_like(i, c)], 1)

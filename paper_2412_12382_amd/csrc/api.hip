@@ -470,6 +470,104 @@ mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
     return MCD_OK;
 }
 
+mcd_status mcd_features_workspace_size(int32_t n_graphs, size_t* bytes) {
+    REQUIRE(bytes && n_graphs >= 1, MCD_ERR_INVALID_ARG, "need n_graphs >= 1");
+    *bytes = mcd::features_scratch_bytes(n_graphs);
+    return MCD_OK;
+}
+
+mcd_status mcd_features(const mcd_graph* g, const int32_t* t, int32_t n_graphs, const int64_t* vbase,
+                        float* x, void* ws, size_t ws_bytes) {
+    REQUIRE(g && vbase && x && ws && (g->m == 0 || t), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "need n_graphs >= 1");
+    REQUIRE(ws_bytes >= mcd::features_scratch_bytes(n_graphs), MCD_ERR_WORKSPACE, "features workspace too small");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_features(g, t, n_graphs, vbase, x, ws, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float* mean, float* std) {
+    REQUIRE(ctx && x && mean && std && batch >= 1, MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_feature_stats(x, batch, mean, std, ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_mlp_forward(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
+                           const float* x, int32_t batch, float* y) {
+    REQUIRE(ctx && params && mean && std && batch >= 0 && (batch == 0 || (x && y)), MCD_ERR_INVALID_ARG,
+            "NULL argument");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_mlp_forward(params, mean, std, x, batch, y, ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_mlp_workspace_size(int32_t batch, size_t* bytes) {
+    REQUIRE(bytes && batch >= 1, MCD_ERR_INVALID_ARG, "need batch >= 1");
+    *bytes = mcd::mlp_scratch_bytes(batch);
+    return MCD_OK;
+}
+
+mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
+                            const float* x, const float* target, int32_t batch, float* grad, float* loss,
+                            void* ws, size_t ws_bytes) {
+    REQUIRE(ctx && params && mean && std && x && target && grad && ws && batch >= 1, MCD_ERR_INVALID_ARG,
+            "NULL argument or empty batch");
+    REQUIRE(ws_bytes >= mcd::mlp_scratch_bytes(batch), MCD_ERR_WORKSPACE, "MLP workspace too small");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_mlp_gradient(params, mean, std, x, target, batch, grad, loss, ws, ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
+                              float lr, const float* mean, const float* std, const float* x,
+                              const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes) {
+    REQUIRE(ctx && params && adam_m && adam_v && mean && std && x && target && ws && batch >= 1,
+            MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
+    REQUIRE(step >= 1, MCD_ERR_INVALID_ARG, "Adam steps count from 1");
+    REQUIRE(ws_bytes >= mcd::mlp_scratch_bytes(batch), MCD_ERR_WORKSPACE, "MLP workspace too small");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_mlp_train_step(params, adam_m, adam_v, step, lr, mean, std, x, target, batch, loss, ws,
+                               ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_grid_select(mcd_ctx* ctx, const float* y, int32_t batch, int32_t K, int64_t a, int64_t b,
+                           int64_t c, int32_t* index, int64_t* delta) {
+    REQUIRE(ctx && batch >= 0 && (batch == 0 || y), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(K >= 1 && c > 0, MCD_ERR_INVALID_ARG, "need K >= 1 and c > 0");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_select(y, batch, K, a, b, c, index, delta, ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_sweep_targets(mcd_ctx* ctx, const double* ari, int32_t n_graphs, int32_t K, int32_t* index,
+                             float* y) {
+    REQUIRE(ctx && ari && n_graphs >= 1 && K >= 1, MCD_ERR_INVALID_ARG, "NULL argument or empty table");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_targets(ari, n_graphs, K, index, y, ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_prune_graphs(const mcd_graph* g, mcd_measure measure, const int32_t* t, int32_t n_graphs,
+                            const int64_t* vbase, const int64_t* deltas, uint32_t* keep_bits,
+                            int64_t* n_kept) {
+    REQUIRE(g && vbase && deltas && (g->m == 0 || (t && keep_bits)), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "need n_graphs >= 1");
+    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_prune_graphs(g, measure, t, n_graphs, vbase, deltas, keep_bits, n_kept, g->ctx->stream);
+    return MCD_OK;
+}
+
 mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes) {
     REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
     *bytes = mcd::select_scratch_bytes(g);

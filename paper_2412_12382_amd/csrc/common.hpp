@@ -129,6 +129,8 @@ void launch_weights(const mcd_graph* g, int measure, const int32_t* t, float* wf
                     hipStream_t s);
 void launch_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den,
                   uint32_t* keep_bits, int64_t* n_kept, hipStream_t s);
+void launch_prune_graphs(const mcd_graph* g, int measure, const int32_t* t, int G, const int64_t* vbase,
+                         const int64_t* deltas, uint32_t* keep_bits, int64_t* n_kept, hipStream_t s);
 
 // ---- components (cc.hip) ----
 void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
@@ -160,5 +162,22 @@ size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth);
 void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
                   const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
                   mcd_sweep_stats* stats, double* ari, int32_t* labels, void* ws, hipStream_t s);
+
+// ---- picker (picker.hip) ----
+size_t features_scratch_bytes(int G);
+void launch_features(const mcd_graph* g, const int32_t* t, int G, const int64_t* vbase, float* x, void* ws,
+                     hipStream_t s);
+size_t mlp_scratch_bytes(int B);
+void launch_mlp_forward(const float* params, const float* mean, const float* stdv, const float* x, int B,
+                        float* y, hipStream_t s);
+void launch_mlp_gradient(const float* params, const float* mean, const float* stdv, const float* x,
+                         const float* target, int B, float* grad, float* loss, void* ws, hipStream_t s);
+void launch_mlp_train_step(float* params, float* m1, float* m2, int step, float lr, const float* mean,
+                           const float* stdv, const float* x, const float* target, int B, float* loss, void* ws,
+                           hipStream_t s);
+void launch_select(const float* y, int B, int K, int64_t a, int64_t b, int64_t c, int32_t* index,
+                   int64_t* delta, hipStream_t s);
+void launch_targets(const double* ari, int G, int K, int32_t* index, float* y, hipStream_t s);
+void launch_feature_stats(const float* x, int B, float* mean, float* stdv, hipStream_t s);
 
 }  // namespace mcd

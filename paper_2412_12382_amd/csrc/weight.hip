@@ -80,7 +80,72 @@ __global__ __launch_bounds__(kThreads) void k_prune(const int32_t* __restrict__ 
     }
 }
 
+__device__ __forceinline__ int graph_of(const int64_t* __restrict__ vbase, int G, int64_t x) {
+    int lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (vbase[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Algorithm 1's removal rule with a per-graph threshold read from device
+// memory (deltas[2g] / deltas[2g+1]); compared exactly in 128-bit integers.
+__global__ __launch_bounds__(kThreads) void k_prune_graphs(const int32_t* __restrict__ src,
+                                                           const int32_t* __restrict__ adj,
+                                                           const int32_t* __restrict__ deg,
+                                                           const int32_t* __restrict__ perm,
+                                                           const int32_t* __restrict__ t, int64_t m,
+                                                           int measure, int G, const int64_t* __restrict__ vbase,
+                                                           const int64_t* __restrict__ deltas,
+                                                           uint32_t* __restrict__ keep,
+                                                           unsigned long long* __restrict__ n_kept) {
+    __shared__ unsigned long long wsum[kThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t nchunks = (m + 63) >> 6;
+    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+    unsigned long long kept = 0;
+    for (int64_t c = (int64_t)blockIdx.x * (kThreads / 64) + w; c < nchunks; c += waves) {
+        const int64_t e = (c << 6) + lane;
+        bool k = false;
+        if (e < m) {
+            const int32_t u = src[e];
+            const int64_t D = (int64_t)deg[u] + deg[adj[e]];
+            const int64_t tt = t[e];
+            const int g = G == 1 ? 0 : graph_of(vbase, G, perm[u]);
+            const int64_t num = deltas[2 * g], den = deltas[2 * g + 1];
+            const int64_t sn = measure == MCD_SIM_TECTONIC ? tt : 3 * tt - D + 2;
+            const int64_t sd = measure == MCD_SIM_TECTONIC ? D : 1;
+            k = (__int128)sn * den >= (__int128)num * sd;
+        }
+        const uint64_t bal = __ballot(k);
+        if (lane == 0) {
+            keep[c * 2] = (uint32_t)bal;
+            kept += (unsigned long long)__popcll(bal);
+        } else if (lane == 1 && (c << 6) + 32 < m) {
+            keep[c * 2 + 1] = (uint32_t)(bal >> 32);
+        }
+    }
+    if (!n_kept) return;
+    if (lane == 0) wsum[w] = kept;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < kThreads / 64; ++i) s += wsum[i];
+        if (s) atomicAdd(n_kept, s);
+    }
+}
+
 }  // namespace
+
+void launch_prune_graphs(const mcd_graph* g, int measure, const int32_t* t, int G, const int64_t* vbase,
+                         const int64_t* deltas, uint32_t* keep_bits, int64_t* n_kept, hipStream_t s) {
+    if (n_kept) fill_i64(n_kept, 1, 0, s);
+    if (g->m <= 0) return;
+    hipLaunchKernelGGL(k_prune_graphs, dim3(grid_for(g->m, 4096)), dim3(kThreads), 0, s, g->src, g->adj, g->deg,
+                       g->perm, t, g->m, measure, G, vbase, deltas, keep_bits, (unsigned long long*)n_kept);
+}
 
 void launch_weights(const mcd_graph* g, int measure, const int32_t* t, float* wf, int32_t* wi,
                     hipStream_t s) {

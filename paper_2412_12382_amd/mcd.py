@@ -78,6 +78,16 @@ def lib():
             "mcd_percentile_workspace_size": [P, ctypes.POINTER(SZ)],
             "mcd_sweep_workspace_size": [P, I32, I32, I32, ctypes.POINTER(SZ)],
             "mcd_sweep": [P, ctypes.c_int, P, P, I32, I32, P, P, P, P, P, P, SZ],
+            "mcd_features_workspace_size": [I32, ctypes.POINTER(SZ)],
+            "mcd_features": [P, P, I32, P, P, P, SZ],
+            "mcd_feature_stats": [P, P, I32, P, P],
+            "mcd_mlp_forward": [P, P, P, P, P, I32, P],
+            "mcd_mlp_workspace_size": [I32, ctypes.POINTER(SZ)],
+            "mcd_mlp_gradient": [P, P, P, P, P, P, I32, P, P, P, SZ],
+            "mcd_mlp_train_step": [P, P, P, P, I32, ctypes.c_float, P, P, P, P, I32, P, P, SZ],
+            "mcd_grid_select": [P, P, I32, I32, I64, I64, I64, P, P],
+            "mcd_sweep_targets": [P, P, I32, I32, P, P],
+            "mcd_prune_graphs": [P, ctypes.c_int, P, I32, P, P, P, P],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
         for name, args in sig.items():
@@ -333,6 +343,93 @@ def mcd_sweep(g: Graph, measure: int, t, deltas, vbase=None, truth=None, stats=N
     _check(lib().mcd_sweep(g.handle, measure, _p(t), ctypes.cast(arr, ctypes.c_void_p), K, G, _p(vbase),
                            _p(truth), _p(stats), _p(ari), _p(labels), _p(ws), ws.numel() * ws.element_size()))
     return stats, ari, labels
+
+
+MLP_IN, MLP_HIDDEN, MLP_PARAMS = 66, 64, 8513
+
+
+def _vbase(g: Graph, vbase):
+    if vbase is None:
+        return torch.tensor([0, g.n], dtype=torch.int64, device=g.ctx.device)
+    return vbase
+
+
+def mcd_features(g: Graph, t, vbase=None, x=None, ws=None):
+    vb = _vbase(g, vbase)
+    G = vb.numel() - 1
+    x = _empty((G, MLP_IN), torch.float32, g.ctx.device) if x is None else x
+    if ws is None:
+        b = ctypes.c_size_t()
+        _check(lib().mcd_features_workspace_size(G, ctypes.byref(b)))
+        ws = _bytes(b.value, g.ctx.device)
+    _check(lib().mcd_features(g.handle, _p(t), G, _p(vb), _p(x), _p(ws), ws.numel() * ws.element_size()))
+    return x
+
+
+def mcd_feature_stats(ctx: Context, x, mean=None, std=None):
+    mean = _empty(MLP_IN, torch.float32, ctx.device) if mean is None else mean
+    std = _empty(MLP_IN, torch.float32, ctx.device) if std is None else std
+    _check(lib().mcd_feature_stats(ctx.handle, _p(x), x.shape[0], _p(mean), _p(std)))
+    return mean, std
+
+
+def mcd_mlp_forward(ctx: Context, params, mean, std, x, y=None):
+    B = x.shape[0]
+    y = _empty(max(B, 1), torch.float32, ctx.device) if y is None else y
+    _check(lib().mcd_mlp_forward(ctx.handle, _p(params), _p(mean), _p(std), _p(x), B, _p(y)))
+    return y[:B]
+
+
+def mcd_mlp_workspace_size(batch: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_mlp_workspace_size(batch, ctypes.byref(b)))
+    return b.value
+
+
+def mcd_mlp_gradient(ctx: Context, params, mean, std, x, target, grad=None, loss=None, ws=None):
+    B = x.shape[0]
+    grad = _empty(MLP_PARAMS, torch.float32, ctx.device) if grad is None else grad
+    loss = _empty(1, torch.float32, ctx.device) if loss is None else loss
+    ws = _bytes(mcd_mlp_workspace_size(B), ctx.device) if ws is None else ws
+    _check(lib().mcd_mlp_gradient(ctx.handle, _p(params), _p(mean), _p(std), _p(x), _p(target), B, _p(grad),
+                                  _p(loss), _p(ws), ws.numel() * ws.element_size()))
+    return grad, loss
+
+
+def mcd_mlp_train_step(ctx: Context, params, adam_m, adam_v, step: int, lr: float, mean, std, x, target,
+                       loss=None, ws=None):
+    B = x.shape[0]
+    loss = _empty(1, torch.float32, ctx.device) if loss is None else loss
+    ws = _bytes(mcd_mlp_workspace_size(B), ctx.device) if ws is None else ws
+    _check(lib().mcd_mlp_train_step(ctx.handle, _p(params), _p(adam_m), _p(adam_v), step, lr, _p(mean), _p(std),
+                                    _p(x), _p(target), B, _p(loss), _p(ws), ws.numel() * ws.element_size()))
+    return loss
+
+
+def mcd_grid_select(ctx: Context, y, K: int, a: int, b: int, c: int, index=None, delta=None):
+    B = y.numel()
+    index = _empty(max(B, 1), torch.int32, ctx.device) if index is None else index
+    delta = _empty((max(B, 1), 2), torch.int64, ctx.device) if delta is None else delta
+    _check(lib().mcd_grid_select(ctx.handle, _p(y), B, K, a, b, c, _p(index), _p(delta)))
+    return index[:B], delta[:B]
+
+
+def mcd_sweep_targets(ctx: Context, ari, index=None, y=None):
+    G, K = ari.shape
+    index = _empty(G, torch.int32, ctx.device) if index is None else index
+    y = _empty(G, torch.float32, ctx.device) if y is None else y
+    _check(lib().mcd_sweep_targets(ctx.handle, _p(ari), G, K, _p(index), _p(y)))
+    return index, y
+
+
+def mcd_prune_graphs(g: Graph, measure: int, t, deltas, vbase=None, keep_bits=None, n_kept=None):
+    vb = _vbase(g, vbase)
+    words = max((g.m + 31) // 32, 1)
+    keep_bits = _empty(words, torch.int32, g.ctx.device) if keep_bits is None else keep_bits
+    n_kept = _empty(1, torch.int64, g.ctx.device) if n_kept is None else n_kept
+    _check(lib().mcd_prune_graphs(g.handle, measure, _p(t), vb.numel() - 1, _p(vb), _p(deltas), _p(keep_bits),
+                                  _p(n_kept)))
+    return keep_bits, n_kept
 
 
 def mcd_status_string(status: int) -> str:

@@ -1,0 +1,66 @@
+"""Learned threshold picker driver (training loop and picking on the GPU).
+
+The arithmetic runs in libmcd.so: features, the FP32 MLP forward/backward/
+Adam kernels, the grid snap, per-graph pruning and components.  This module
+only sequences those calls.  The threshold grid is delta_i = (9 + 7 i) / 900,
+i = 0..63 (64 evenly spaced values in [0.01, 0.5]); a picked index is the
+network output snapped to that grid.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import mcd as M
+
+GRID_A, GRID_B, GRID_C, GRID_K = 9, 7, 900, 64
+GRID = [(GRID_A + GRID_B * i, GRID_C) for i in range(GRID_K)]
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-uniform weights (bound sqrt(6 / fan_in)), zero biases, drawn from the
+    seeded counter-based generator of the input module."""
+    import graphgen
+
+    u = graphgen.uniforms(seed, 0x4D4C5030, M.MLP_PARAMS)  # "MLP0"
+    p = np.zeros(M.MLP_PARAMS, np.float32)
+    o = 0
+    for fan_out, fan_in in ((64, 66), (64, 64), (1, 64)):
+        k = fan_out * fan_in
+        bound = math.sqrt(6.0 / fan_in)
+        p[o:o + k] = ((2.0 * u[o:o + k] - 1.0) * bound).astype(np.float32)
+        o += k + (fan_out if fan_out > 1 else 1)  # skip the bias block
+    return p
+
+
+class Picker:
+    def __init__(self, params, mean, std):
+        self.params, self.mean, self.std = params, mean, std
+
+
+def train(ctx, x, y, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log_every: int = 0):
+    """Full-batch Adam on (x, y) (device tensors); returns (Picker, losses)."""
+    dev = ctx.device
+    params = torch.from_numpy(init_params(seed)).to(dev)
+    m1 = torch.zeros_like(params)
+    m2 = torch.zeros_like(params)
+    mean, std = M.mcd_feature_stats(ctx, x)
+    ws = torch.empty(M.mcd_mlp_workspace_size(x.shape[0]), dtype=torch.uint8, device=dev)
+    loss = torch.empty(max(steps, 1), dtype=torch.float32, device=dev)
+    for s in range(1, steps + 1):
+        M.mcd_mlp_train_step(ctx, params, m1, m2, s, lr, mean, std, x, y, loss=loss[s - 1:s], ws=ws)
+    return Picker(params, mean, std), loss.cpu().numpy()
+
+
+def pick(g, t, picker: Picker, vbase=None, measure: int = M.MCD_SIM_TECTONIC):
+    """Features -> MLP -> grid snap -> per-graph prune -> components.
+    Returns (index int32[G], deltas int64[G][2], labels int32[n], n_components)."""
+    ctx = g.ctx
+    x = M.mcd_features(g, t, vbase)
+    y = M.mcd_mlp_forward(ctx, picker.params, picker.mean, picker.std, x)
+    index, deltas = M.mcd_grid_select(ctx, y, GRID_K, GRID_A, GRID_B, GRID_C)
+    keep, _ = M.mcd_prune_graphs(g, measure, t, deltas, vbase)
+    labels, ncc = M.mcd_components(g, keep)
+    return index, deltas, labels, ncc

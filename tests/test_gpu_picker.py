@@ -1,0 +1,153 @@
+"""GPU parity of the learned threshold picker kernels against the float64
+reference (oracle.mlp) and the oracle's histogram, prune and components."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+M = pytest.importorskip("paper_2412_12382_amd.mcd")
+
+
+def rand_problem(seed, B):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, 0.3, mlp.NPAR).astype(np.float32)
+    x = rng.normal(0, 1, (B, mlp.NI)).astype(np.float32)
+    mean = rng.normal(0, 0.1, mlp.NI).astype(np.float32)
+    std = rng.uniform(0.5, 2.0, mlp.NI).astype(np.float32)
+    target = rng.uniform(0, 1, B).astype(np.float32)
+    return p, mean, std, x, target
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_mlp_forward_and_gradient():
+    from gpu_util import ctx
+    for B in (1, 7, 192):
+        p, mean, std, x, target = rand_problem(B, B)
+        y = M.mcd_mlp_forward(ctx(), cuda(p), cuda(mean), cuda(std), cuda(x)).cpu().numpy()
+        yo, _ = mlp.forward(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x)
+        assert np.all(np.abs(y - yo) <= 1e-5 * np.maximum(np.abs(yo), 1.0))
+        g, loss = M.mcd_mlp_gradient(ctx(), cuda(p), cuda(mean), cuda(std), cuda(x), cuda(target))
+        go, lo = mlp.gradient(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x,
+                              target.astype(np.float64))
+        g = g.cpu().numpy()
+        assert np.all(np.abs(g - go) <= 1e-4 * (np.abs(go) + 1e-3))
+        assert abs(float(loss.item()) - lo) <= 1e-5 * max(lo, 1.0)
+
+
+def test_adam_step_matches_reference():
+    from gpu_util import ctx
+    B, lr = 32, 1e-3
+    p, mean, std, x, target = rand_problem(5, B)
+    P = cuda(p)
+    m1, m2 = torch.zeros_like(P), torch.zeros_like(P)
+    M.mcd_mlp_train_step(ctx(), P, m1, m2, 1, lr, cuda(mean), cuda(std), cuda(x), cuda(target))
+    go, _ = mlp.gradient(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x,
+                         target.astype(np.float64))
+    po, _, _ = mlp.adam_step(p.astype(np.float64), 0 * go, 0 * go, go, 1, lr)
+    dp = P.cpu().numpy().astype(np.float64) - p
+    dpo = po - p
+    sel = np.abs(go) > 1e-4  # where the step's direction is well defined
+    assert np.all(np.abs(dp[sel] - dpo[sel]) <= 1e-3 * lr + 1e-6 * np.abs(p[sel]))
+    # training decreases the loss
+    losses = []
+    for s in range(2, 200):
+        losses.append(float(M.mcd_mlp_train_step(ctx(), P, m1, m2, s, lr, cuda(mean), cuda(std), cuda(x),
+                                                 cuda(target)).item()))
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_features_batch():
+    from gpu_util import build
+    b = gg.sbm_batch(5, n_max=3000)
+    n, vbase = b["n"], b["vbase"]
+    g = build(b["src"], b["dst"], n)
+    t = M.mcd_triangles(g)
+    x = M.mcd_features(g, t, cuda(vbase)).cpu().numpy()
+    lo, hi = oracle.canon(n, b["src"], b["dst"])
+    for k in range(5):
+        a, c = vbase[k], vbase[k + 1]
+        sel = (lo >= a) & (lo < c)
+        l2, h2 = (lo[sel] - a).astype(np.int32), (hi[sel] - a).astype(np.int32)
+        deg = oracle.degrees(c - a, l2, h2)
+        tk = oracle.triangles(c - a, l2, h2)
+        xo = mlp.features(c - a, l2, h2, tk, deg)
+        assert np.all(np.abs(x[k] - xo) <= 1e-6 * np.maximum(np.abs(xo), 1e-30))
+
+
+def test_select_targets_and_per_graph_prune():
+    from gpu_util import ctx, build, unpack_bits, canonical_order
+    y = np.array([-0.3, 0.0, 0.2, 0.49, 0.5, 0.999, 1.5, 31.5 / 63], np.float32)
+    idx, d = M.mcd_grid_select(ctx(), cuda(y), 64, 9, 7, 900)
+    io, do = mlp.select(y, 64, 9, 7, 900)
+    assert np.array_equal(idx.cpu().numpy(), io) and np.array_equal(d.cpu().numpy(), do)
+    ari = np.random.default_rng(3).choice([0.1, 0.4, 0.7], (9, 64))
+    ti, ty = M.mcd_sweep_targets(ctx(), cuda(ari))
+    assert np.array_equal(ti.cpu().numpy(), mlp.targets(ari))
+    assert np.allclose(ty.cpu().numpy(), mlp.targets(ari) / 63.0)
+    # per-graph thresholds
+    b = gg.sbm_batch(4, n_max=2000)
+    n, vbase = b["n"], b["vbase"]
+    deltas = np.array([[9 + 7 * i, 900] for i in (3, 10, 0, 40)], np.int64)
+    g = build(b["src"], b["dst"], n)
+    t = M.mcd_triangles(g)
+    keep, nk = M.mcd_prune_graphs(g, M.MCD_SIM_TECTONIC, t, cuda(deltas), cuda(vbase))
+    lab, ncc = M.mcd_components(g, keep)
+    _, _, order = canonical_order(g)
+    kg = unpack_bits(keep, g.m)[order]
+    lo, hi = oracle.canon(n, b["src"], b["dst"])
+    deg = oracle.degrees(n, lo, hi)
+    to = oracle.triangles(n, lo, hi)
+    want = np.zeros(len(lo), np.uint8)
+    eg = np.searchsorted(vbase, lo, side="right") - 1
+    for k in range(4):
+        want[eg == k] = oracle.prune(oracle.TECTONIC, lo, hi, to, deg, *deltas[k])[eg == k]
+    assert np.array_equal(kg, want) and int(nk.item()) == int(want.sum())
+    lab_o, ncc_o = oracle.components(n, lo, hi, want)
+    assert np.array_equal(lab.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o
+
+
+def test_picker_end_to_end_small_batch():
+    # a reduced planted-partition batch: sweep -> targets -> train -> pick;
+    # the picked labels are the oracle's at the picked thresholds, and the
+    # trained picker's validation ARI is reported against two baselines
+    from gpu_util import ctx, build
+    from paper_2412_12382_amd import picker as PK
+    G = 48
+    b = gg.sbm_batch(G, n_max=6000)
+    n, vbase = b["n"], cuda(b["vbase"])
+    g = build(b["src"], b["dst"], n)
+    t = M.mcd_triangles(g)
+    stats, ari, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vbase, truth=cuda(b["truth"]))
+    idx, y = M.mcd_sweep_targets(ctx(), ari)
+    x = M.mcd_features(g, t, vbase)
+    gi = np.arange(G)
+    tr, va = gi[gi % 4 != 3], gi[gi % 4 == 3]
+    model, losses = PK.train(ctx(), x[torch.from_numpy(tr).cuda()].contiguous(),
+                             y[torch.from_numpy(tr).cuda()].contiguous(), steps=1500, lr=3e-3)
+    assert losses[-1] < losses[0]
+    index, deltas, labels, ncc = PK.pick(g, t, model, vbase)
+    A = ari.cpu().numpy()
+    pi = index.cpu().numpy()
+    picked = A[va, pi[va]].mean()
+    best = A[va].max(1).mean()
+    glob = A[va][:, np.argmax(A[tr].mean(0))].mean()
+    print(f"val ARI: picker {picked:.4f}  per-graph best {best:.4f}  best global {glob:.4f}")
+    assert picked >= glob - 0.05
+    # labels equal the oracle's components at the picked per-graph thresholds
+    lo, hi = oracle.canon(n, b["src"], b["dst"])
+    deg = oracle.degrees(n, lo, hi)
+    to = oracle.triangles(n, lo, hi)
+    eg = np.searchsorted(b["vbase"], lo, side="right") - 1
+    keep = np.zeros(len(lo), np.uint8)
+    dd = deltas.cpu().numpy()
+    for k in range(G):
+        keep[eg == k] = oracle.prune(oracle.TECTONIC, lo, hi, to, deg, *dd[k])[eg == k]
+    lab_o, ncc_o = oracle.components(n, lo, hi, keep)
+    assert np.array_equal(labels.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o
