@@ -241,9 +241,11 @@ mcd_status mcd_features_workspace_size(int32_t n_graphs, size_t* bytes);
 mcd_status mcd_features(const mcd_graph* g, const int32_t* t, int32_t n_graphs, const int64_t* vbase,
                         float* x, void* ws, size_t ws_bytes);
 
-/* Column mean and population standard deviation (1 where it is 0) of a
- * feature matrix x (device float[batch][66]) into mean, std (device float[66]). */
-mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float* mean, float* std);
+/* Column mean and population standard deviation, raised to at least min_std
+ * (> 0) so near-constant columns are not amplified, of a feature matrix x
+ * (device float[batch][66]) into mean, std (device float[66]). */
+mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float min_std, float* mean,
+                             float* std);
 
 /* FP32 MLP 66 -> 64 -> 64 -> 1 with ReLU on the hidden layers, applied to
  * (x - mean) / std.  params: device float[MCD_MLP_PARAMS]; y: device float[batch]. */
@@ -262,9 +264,10 @@ mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean
 
 /* One full-batch Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
  * step counted from 1) on params with moment buffers adam_m, adam_v (device
- * float[MCD_MLP_PARAMS], zero before step 1).  loss: the pre-step loss. */
+ * float[MCD_MLP_PARAMS], zero before step 1), with decoupled weight decay
+ * (p -= lr * weight_decay * p first; 0 = plain Adam).  loss: the pre-step loss. */
 mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
-                              float lr, const float* mean, const float* std, const float* x,
+                              float lr, float weight_decay, const float* mean, const float* std, const float* x,
                               const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes);
 
 /* Snaps picker outputs to the grid delta_i = (a + b i) / c, i = 0..K-1:
@@ -273,12 +276,13 @@ mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float*
 mcd_status mcd_grid_select(mcd_ctx* ctx, const float* y, int32_t batch, int32_t K, int64_t a, int64_t b,
                            int64_t c, int32_t* index, int64_t* delta);
 
-/* Training targets from a sweep's ARI table (device double[n_graphs][K]): the
- * first run of thresholds that reach the best ARI, its lower middle index
- * (index, device int32[n_graphs], may be NULL) and index / (K - 1) (y, device
- * float[n_graphs], may be NULL). */
-mcd_status mcd_sweep_targets(mcd_ctx* ctx, const double* ari, int32_t n_graphs, int32_t K, int32_t* index,
-                             float* y);
+/* Training targets from a sweep's ARI table (device double[n_graphs][K], K >= 2):
+ * the centroid c of the thresholds whose ARI is at least
+ * best - (1 - frac) |best|, 0 < frac <= 1 (1: the exact maxima only), as the
+ * index round-half-down(c) (index, device int32[n_graphs], may be NULL) and as
+ * c / (K - 1) (y, device float[n_graphs], may be NULL). */
+mcd_status mcd_sweep_targets(mcd_ctx* ctx, const double* ari, int32_t n_graphs, int32_t K, double frac,
+                             int32_t* index, float* y);
 
 /* mcd_prune with one threshold per graph of a batch, read from device memory:
  * deltas[2k] / deltas[2k+1] (den > 0) is graph k's threshold. */

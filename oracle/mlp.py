@@ -87,18 +87,20 @@ def features(n, lo, hi, t, deg):
     return x
 
 
-def targets(ari):
-    """First run of thresholds reaching the best ARI; its lower middle index."""
-    ari = np.asarray(ari)
+def targets(ari, frac=0.95):
+    """Centroid c of the thresholds with ARI >= best - (1 - frac)|best|;
+    returns (index = round half down of c, y = c / (K - 1))."""
+    ari = np.asarray(ari, np.float64)
+    K = ari.shape[1]
     idx = np.zeros(ari.shape[0], np.int64)
+    y = np.zeros(ari.shape[0])
     for g, row in enumerate(ari):
         best = row.max()
-        s = int(np.argmax(row == best))
-        e = s
-        while e + 1 < len(row) and row[e + 1] == best:
-            e += 1
-        idx[g] = (s + e) // 2
-    return idx
+        sel = np.nonzero(row >= best - (1 - frac) * abs(best))[0]
+        s, c = int(sel.sum()), len(sel)
+        idx[g] = (2 * s + c - 1) // (2 * c)
+        y[g] = s / c / (K - 1)
+    return idx, y
 
 
 def select(y, K, a, b, c):

@@ -487,11 +487,13 @@ mcd_status mcd_features(const mcd_graph* g, const int32_t* t, int32_t n_graphs, 
     return MCD_OK;
 }
 
-mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float* mean, float* std) {
+mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float min_std, float* mean,
+                             float* std) {
     REQUIRE(ctx && x && mean && std && batch >= 1, MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
+    REQUIRE(min_std > 0.f, MCD_ERR_INVALID_ARG, "min_std must be positive");
     mcd_status st = use_device(ctx);
     if (st != MCD_OK) return st;
-    mcd::launch_feature_stats(x, batch, mean, std, ctx->stream);
+    mcd::launch_feature_stats(x, batch, min_std, mean, std, ctx->stream);
     return MCD_OK;
 }
 
@@ -524,7 +526,7 @@ mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean
 }
 
 mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
-                              float lr, const float* mean, const float* std, const float* x,
+                              float lr, float weight_decay, const float* mean, const float* std, const float* x,
                               const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes) {
     REQUIRE(ctx && params && adam_m && adam_v && mean && std && x && target && ws && batch >= 1,
             MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
@@ -532,8 +534,8 @@ mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float*
     REQUIRE(ws_bytes >= mcd::mlp_scratch_bytes(batch), MCD_ERR_WORKSPACE, "MLP workspace too small");
     mcd_status st = use_device(ctx);
     if (st != MCD_OK) return st;
-    mcd::launch_mlp_train_step(params, adam_m, adam_v, step, lr, mean, std, x, target, batch, loss, ws,
-                               ctx->stream);
+    mcd::launch_mlp_train_step(params, adam_m, adam_v, step, lr, weight_decay, mean, std, x, target, batch,
+                               loss, ws, ctx->stream);
     return MCD_OK;
 }
 
@@ -547,12 +549,13 @@ mcd_status mcd_grid_select(mcd_ctx* ctx, const float* y, int32_t batch, int32_t 
     return MCD_OK;
 }
 
-mcd_status mcd_sweep_targets(mcd_ctx* ctx, const double* ari, int32_t n_graphs, int32_t K, int32_t* index,
-                             float* y) {
-    REQUIRE(ctx && ari && n_graphs >= 1 && K >= 1, MCD_ERR_INVALID_ARG, "NULL argument or empty table");
+mcd_status mcd_sweep_targets(mcd_ctx* ctx, const double* ari, int32_t n_graphs, int32_t K, double frac,
+                             int32_t* index, float* y) {
+    REQUIRE(ctx && ari && n_graphs >= 1 && K >= 2, MCD_ERR_INVALID_ARG, "NULL argument or table under 2 columns");
+    REQUIRE(frac > 0.0 && frac <= 1.0, MCD_ERR_INVALID_ARG, "frac must lie in (0, 1]");
     mcd_status st = use_device(ctx);
     if (st != MCD_OK) return st;
-    mcd::launch_targets(ari, n_graphs, K, index, y, ctx->stream);
+    mcd::launch_targets(ari, n_graphs, K, frac, index, y, ctx->stream);
     return MCD_OK;
 }
 

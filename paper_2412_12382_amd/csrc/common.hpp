@@ -172,12 +172,12 @@ void launch_mlp_forward(const float* params, const float* mean, const float* std
                         float* y, hipStream_t s);
 void launch_mlp_gradient(const float* params, const float* mean, const float* stdv, const float* x,
                          const float* target, int B, float* grad, float* loss, void* ws, hipStream_t s);
-void launch_mlp_train_step(float* params, float* m1, float* m2, int step, float lr, const float* mean,
+void launch_mlp_train_step(float* params, float* m1, float* m2, int step, float lr, float wd, const float* mean,
                            const float* stdv, const float* x, const float* target, int B, float* loss, void* ws,
                            hipStream_t s);
 void launch_select(const float* y, int B, int K, int64_t a, int64_t b, int64_t c, int32_t* index,
                    int64_t* delta, hipStream_t s);
-void launch_targets(const double* ari, int G, int K, int32_t* index, float* y, hipStream_t s);
-void launch_feature_stats(const float* x, int B, float* mean, float* stdv, hipStream_t s);
+void launch_targets(const double* ari, int G, int K, double frac, int32_t* index, float* y, hipStream_t s);
+void launch_feature_stats(const float* x, int B, float min_std, float* mean, float* stdv, hipStream_t s);
 
 }  // namespace mcd

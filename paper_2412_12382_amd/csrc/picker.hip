@@ -187,10 +187,11 @@ __global__ __launch_bounds__(kThreads) void k_mlp_reduce(const float* __restrict
     }
 }
 
-// Adam (Kingma & Ba) with bias correction; step counts from 1.
+// Adam (Kingma & Ba) with bias correction; step counts from 1.  Weight decay
+// is decoupled (Loshchilov & Hutter): p -= lr * wd * p before the Adam update.
 __global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                                    float* __restrict__ m1, float* __restrict__ m2, int step,
-                                                   float lr, float beta1, float beta2, float eps) {
+                                                   float lr, float wd, float beta1, float beta2, float eps) {
     const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
     GRID_STRIDE(q, NPAR) {
         const float gq = g[q];
@@ -198,7 +199,8 @@ __global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ p, const 
         const float b = beta2 * m2[q] + (1.f - beta2) * gq * gq;
         m1[q] = a;
         m2[q] = b;
-        p[q] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+        const float pq = p[q] - lr * wd * p[q];
+        p[q] = pq - lr * (a / c1) / (sqrtf(b / c2) + eps);
     }
 }
 
@@ -218,27 +220,34 @@ __global__ __launch_bounds__(kThreads) void k_select(const float* __restrict__ y
     }
 }
 
-// Training target per graph: the first run of thresholds that all reach the
-// best ARI, and the lower middle index of that run.
-__global__ __launch_bounds__(kThreads) void k_targets(const double* __restrict__ ari, int G, int K,
+// Training target per graph: the centroid of the thresholds whose ARI is
+// within a fraction of the best, i.e. ARI >= best - (1 - frac) |best|
+// (frac = 1: the centroid of the exact maxima); index = round-half-down of the
+// centroid, y = centroid / (K - 1).
+__global__ __launch_bounds__(kThreads) void k_targets(const double* __restrict__ ari, int G, int K, double frac,
                                                       int32_t* __restrict__ index, float* __restrict__ y) {
     GRID_STRIDE(g, G) {
         const double* a = ari + (int64_t)g * K;
         double best = a[0];
         for (int i = 1; i < K; ++i) best = fmax(best, a[i]);
-        int s = 0;
-        while (a[s] != best) ++s;
-        int e = s;
-        while (e + 1 < K && a[e + 1] == best) ++e;
-        const int mid = (s + e) / 2;
+        const double cut = best - (1.0 - frac) * fabs(best);
+        int64_t s = 0, c = 0;
+        for (int i = 0; i < K; ++i)
+            if (a[i] >= cut) {
+                s += i;
+                ++c;
+            }
+        // centroid = s / c; round half down in exact integer arithmetic
+        const int32_t mid = (int32_t)((2 * s + c - 1) / (2 * c));
         if (index) index[g] = mid;
-        if (y) y[g] = (float)mid / (float)(K - 1);
+        if (y) y[g] = (float)((double)s / (double)c / (double)(K - 1));
     }
 }
 
-// column mean and standard deviation (population; 1 where it is 0)
-__global__ __launch_bounds__(64) void k_feat_stats(const float* __restrict__ x, int B, float* __restrict__ mean,
-                                                   float* __restrict__ stdv) {
+// column mean and standard deviation (population), the latter raised to at
+// least min_std so near-constant columns are not blown up
+__global__ __launch_bounds__(64) void k_feat_stats(const float* __restrict__ x, int B, float min_std,
+                                                   float* __restrict__ mean, float* __restrict__ stdv) {
     for (int k = threadIdx.x; k < NI; k += 64) {
         double s = 0, ss = 0;
         for (int r = 0; r < B; ++r) {
@@ -251,7 +260,7 @@ __global__ __launch_bounds__(64) void k_feat_stats(const float* __restrict__ x, 
         if (var < 0) var = 0;
         const double sd = sqrt(var);
         mean[k] = (float)mu;
-        stdv[k] = sd > 1e-12 ? (float)sd : 1.f;
+        stdv[k] = (float)fmax(sd, (double)min_std);
     }
 }
 
@@ -310,13 +319,13 @@ void launch_mlp_gradient(const float* params, const float* mean, const float* st
                        grad ? grad : w.grad, loss);
 }
 
-void launch_mlp_train_step(float* params, float* m1, float* m2, int step, float lr, const float* mean,
+void launch_mlp_train_step(float* params, float* m1, float* m2, int step, float lr, float wd, const float* mean,
                            const float* stdv, const float* x, const float* target, int B, float* loss, void* ws,
                            hipStream_t s) {
     MlpWs w = mlp_ws(ws, B);
     launch_mlp_gradient(params, mean, stdv, x, target, B, w.grad, loss, ws, s);
     hipLaunchKernelGGL(k_adam, dim3(grid_for(NPAR, 64)), dim3(kThreads), 0, s, params, w.grad, m1, m2, step, lr,
-                       0.9f, 0.999f, 1e-8f);
+                       wd, 0.9f, 0.999f, 1e-8f);
 }
 
 void launch_select(const float* y, int B, int K, int64_t a, int64_t b, int64_t c, int32_t* index,
@@ -325,13 +334,13 @@ void launch_select(const float* y, int B, int K, int64_t a, int64_t b, int64_t c
     hipLaunchKernelGGL(k_select, dim3(grid_for(B, 1024)), dim3(kThreads), 0, s, y, B, K, a, b, c, index, delta);
 }
 
-void launch_targets(const double* ari, int G, int K, int32_t* index, float* y, hipStream_t s) {
+void launch_targets(const double* ari, int G, int K, double frac, int32_t* index, float* y, hipStream_t s) {
     if (G <= 0) return;
-    hipLaunchKernelGGL(k_targets, dim3(grid_for(G, 1024)), dim3(kThreads), 0, s, ari, G, K, index, y);
+    hipLaunchKernelGGL(k_targets, dim3(grid_for(G, 1024)), dim3(kThreads), 0, s, ari, G, K, frac, index, y);
 }
 
-void launch_feature_stats(const float* x, int B, float* mean, float* stdv, hipStream_t s) {
-    hipLaunchKernelGGL(k_feat_stats, dim3(1), dim3(64), 0, s, x, B, mean, stdv);
+void launch_feature_stats(const float* x, int B, float min_std, float* mean, float* stdv, hipStream_t s) {
+    hipLaunchKernelGGL(k_feat_stats, dim3(1), dim3(64), 0, s, x, B, min_std, mean, stdv);
 }
 
 }  // namespace mcd

@@ -80,13 +80,13 @@ def lib():
             "mcd_sweep": [P, ctypes.c_int, P, P, I32, I32, P, P, P, P, P, P, SZ],
             "mcd_features_workspace_size": [I32, ctypes.POINTER(SZ)],
             "mcd_features": [P, P, I32, P, P, P, SZ],
-            "mcd_feature_stats": [P, P, I32, P, P],
+            "mcd_feature_stats": [P, P, I32, ctypes.c_float, P, P],
             "mcd_mlp_forward": [P, P, P, P, P, I32, P],
             "mcd_mlp_workspace_size": [I32, ctypes.POINTER(SZ)],
             "mcd_mlp_gradient": [P, P, P, P, P, P, I32, P, P, P, SZ],
-            "mcd_mlp_train_step": [P, P, P, P, I32, ctypes.c_float, P, P, P, P, I32, P, P, SZ],
+            "mcd_mlp_train_step": [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, P, P, P, P, I32, P, P, SZ],
             "mcd_grid_select": [P, P, I32, I32, I64, I64, I64, P, P],
-            "mcd_sweep_targets": [P, P, I32, I32, P, P],
+            "mcd_sweep_targets": [P, P, I32, I32, ctypes.c_double, P, P],
             "mcd_prune_graphs": [P, ctypes.c_int, P, I32, P, P, P, P],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
@@ -366,10 +366,10 @@ def mcd_features(g: Graph, t, vbase=None, x=None, ws=None):
     return x
 
 
-def mcd_feature_stats(ctx: Context, x, mean=None, std=None):
+def mcd_feature_stats(ctx: Context, x, min_std: float = 1e-2, mean=None, std=None):
     mean = _empty(MLP_IN, torch.float32, ctx.device) if mean is None else mean
     std = _empty(MLP_IN, torch.float32, ctx.device) if std is None else std
-    _check(lib().mcd_feature_stats(ctx.handle, _p(x), x.shape[0], _p(mean), _p(std)))
+    _check(lib().mcd_feature_stats(ctx.handle, _p(x), x.shape[0], min_std, _p(mean), _p(std)))
     return mean, std
 
 
@@ -397,11 +397,12 @@ def mcd_mlp_gradient(ctx: Context, params, mean, std, x, target, grad=None, loss
 
 
 def mcd_mlp_train_step(ctx: Context, params, adam_m, adam_v, step: int, lr: float, mean, std, x, target,
-                       loss=None, ws=None):
+                       loss=None, ws=None, weight_decay: float = 0.0):
     B = x.shape[0]
     loss = _empty(1, torch.float32, ctx.device) if loss is None else loss
     ws = _bytes(mcd_mlp_workspace_size(B), ctx.device) if ws is None else ws
-    _check(lib().mcd_mlp_train_step(ctx.handle, _p(params), _p(adam_m), _p(adam_v), step, lr, _p(mean), _p(std),
+    _check(lib().mcd_mlp_train_step(ctx.handle, _p(params), _p(adam_m), _p(adam_v), step, lr, weight_decay,
+                                    _p(mean), _p(std),
                                     _p(x), _p(target), B, _p(loss), _p(ws), ws.numel() * ws.element_size()))
     return loss
 
@@ -414,11 +415,11 @@ def mcd_grid_select(ctx: Context, y, K: int, a: int, b: int, c: int, index=None,
     return index[:B], delta[:B]
 
 
-def mcd_sweep_targets(ctx: Context, ari, index=None, y=None):
+def mcd_sweep_targets(ctx: Context, ari, frac: float = 0.95, index=None, y=None):
     G, K = ari.shape
     index = _empty(G, torch.int32, ctx.device) if index is None else index
     y = _empty(G, torch.float32, ctx.device) if y is None else y
-    _check(lib().mcd_sweep_targets(ctx.handle, _p(ari), G, K, _p(index), _p(y)))
+    _check(lib().mcd_sweep_targets(ctx.handle, _p(ari), G, K, frac, _p(index), _p(y)))
     return index, y
 
 

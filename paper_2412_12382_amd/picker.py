@@ -40,17 +40,20 @@ class Picker:
         self.params, self.mean, self.std = params, mean, std
 
 
-def train(ctx, x, y, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log_every: int = 0):
-    """Full-batch Adam on (x, y) (device tensors); returns (Picker, losses)."""
+def train(ctx, x, y, steps: int = 2000, lr: float = 3e-3, seed: int = 0, weight_decay: float = 1.0,
+          min_std: float = 1.0):
+    """Full-batch Adam (decoupled weight decay) on (x, y) (device tensors);
+    returns (Picker, losses)."""
     dev = ctx.device
     params = torch.from_numpy(init_params(seed)).to(dev)
     m1 = torch.zeros_like(params)
     m2 = torch.zeros_like(params)
-    mean, std = M.mcd_feature_stats(ctx, x)
+    mean, std = M.mcd_feature_stats(ctx, x, min_std)
     ws = torch.empty(M.mcd_mlp_workspace_size(x.shape[0]), dtype=torch.uint8, device=dev)
     loss = torch.empty(max(steps, 1), dtype=torch.float32, device=dev)
     for s in range(1, steps + 1):
-        M.mcd_mlp_train_step(ctx, params, m1, m2, s, lr, mean, std, x, y, loss=loss[s - 1:s], ws=ws)
+        M.mcd_mlp_train_step(ctx, params, m1, m2, s, lr, mean, std, x, y, loss=loss[s - 1:s], ws=ws,
+                             weight_decay=weight_decay)
     return Picker(params, mean, std), loss.cpu().numpy()
 
 

@@ -37,7 +37,15 @@ def test_mlp_forward_and_gradient():
         go, lo = mlp.gradient(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x,
                               target.astype(np.float64))
         g = g.cpu().numpy()
-        assert np.all(np.abs(g - go) <= 1e-4 * (np.abs(go) + 1e-3))
+        # fp32 batch sum: besides 1e-4 relative per entry, allow the recursive
+        # summation bound (B - 1) u sum_r |dL_r/dp| (u = 2^-24) for cancellation
+        sabs = np.zeros(mlp.NPAR)
+        for r in range(B):
+            gr, _ = mlp.gradient(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64),
+                                 x[r:r + 1], target[r:r + 1].astype(np.float64))
+            sabs += np.abs(gr) / B
+        tol = 1e-4 * (np.abs(go) + 1e-3) + 4 * (B + 8) * 2.0 ** -24 * sabs
+        assert np.all(np.abs(g - go) <= tol), np.max(np.abs(g - go) / tol)
         assert abs(float(loss.item()) - lo) <= 1e-5 * max(lo, 1.0)
 
 
@@ -88,9 +96,11 @@ def test_select_targets_and_per_graph_prune():
     io, do = mlp.select(y, 64, 9, 7, 900)
     assert np.array_equal(idx.cpu().numpy(), io) and np.array_equal(d.cpu().numpy(), do)
     ari = np.random.default_rng(3).choice([0.1, 0.4, 0.7], (9, 64))
-    ti, ty = M.mcd_sweep_targets(ctx(), cuda(ari))
-    assert np.array_equal(ti.cpu().numpy(), mlp.targets(ari))
-    assert np.allclose(ty.cpu().numpy(), mlp.targets(ari) / 63.0)
+    for frac in (1.0, 0.95, 0.6):
+        ti, ty = M.mcd_sweep_targets(ctx(), cuda(ari), frac)
+        io_, yo_ = mlp.targets(ari, frac)
+        assert np.array_equal(ti.cpu().numpy(), io_)
+        assert np.allclose(ty.cpu().numpy(), yo_, rtol=1e-6)
     # per-graph thresholds
     b = gg.sbm_batch(4, n_max=2000)
     n, vbase = b["n"], b["vbase"]
@@ -130,7 +140,7 @@ def test_picker_end_to_end_small_batch():
     gi = np.arange(G)
     tr, va = gi[gi % 4 != 3], gi[gi % 4 == 3]
     model, losses = PK.train(ctx(), x[torch.from_numpy(tr).cuda()].contiguous(),
-                             y[torch.from_numpy(tr).cuda()].contiguous(), steps=1500, lr=3e-3)
+                             y[torch.from_numpy(tr).cuda()].contiguous())
     assert losses[-1] < losses[0]
     index, deltas, labels, ncc = PK.pick(g, t, model, vbase)
     A = ari.cpu().numpy()

@@ -49,7 +49,11 @@ def test_targets_and_select():
     ari = np.array([[0.1, 0.5, 0.5, 0.5, 0.2, 0.5],
                     [0.9, 0.1, 0.2, 0.3, 0.4, 0.5],
                     [0.0, 0.0, 0.3, 0.3, 0.0, 0.0]])
-    assert mlp.targets(ari).tolist() == [2, 0, 2]
+    # exact maxima (frac 1): centroids 2.75 -> 3, 0, 2.5 -> 2 (half rounds down)
+    assert mlp.targets(ari, 1.0)[0].tolist() == [3, 0, 2]
+    # within 20% of the best: row 0 keeps 0.5s (0.4 cut), row 1 only 0.9, row 2 the 0.3s
+    assert mlp.targets(ari, 0.8)[0].tolist() == [3, 0, 2]
+    assert np.allclose(mlp.targets(ari, 1.0)[1], np.array([2.75, 0, 2.5]) / 5)
     i, d = mlp.select([-0.2, 0.0, 0.49, 0.5, 1.7], 64, 9, 7, 900)
     assert i.tolist() == [0, 0, 31, 32, 63]
     assert d[1].tolist() == [9, 900] and d[4].tolist() == [9 + 7 * 63, 900]
