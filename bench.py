@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
-"""Benchmark: Tectonic pipeline (Algorithm 1 of arXiv 2412.12382) on R-MAT.
+"""Benchmark of the motif-based community detection path (Algorithm 1 of
+arXiv 2412.12382) on one MI355X.
 
-Workload (default): R-MAT scale 26, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05),
-seeded vertex permutation, raw directed pairs resident in HBM.  One step is one
-full pass of the path on the GPU:
-    graph build (canonicalise + dedup + degree rank + orientation CSR)
-    -> per-edge triangle counts -> Tectonic weights -> prune at delta
-    -> connected components (min-vertex labels).
-value = undirected edges m / step time (edges/s).  Per-kernel HIP-event times
-give the roofline of the dominant kernel (triangle counting) and of the
+Workload: R-MAT scale 26, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05), seeded
+vertex permutation; raw directed pairs resident in HBM (about 67M vertices,
+1.05 billion undirected edges after symmetrising and deduplicating).  One
+timed step is one full pass of the path on the GPU:
+    graph build (canonicalise, dedup, degree rank, oriented CSR, in-edge lists)
+    -> per-edge triangle counts -> Tectonic weights
+    -> learned threshold (features, FP32 MLP, snap to the grid (9 + 7 i)/900)
+    -> prune at that threshold -> connected components (min-vertex labels)
+    -> 16-point check sweep at k/50, k = 0..15 (kept edges, components,
+       largest component per threshold).
+value = undirected edges m / step time.  HIP events around every stage give
+the roofline of the dominant kernel (triangle counting) and of the
 weight+prune+components part.
 
-Prints ONE JSON line (stdout).  Progress goes to stderr.
+Before the timed steps (not timed): the picker is trained on the 256-graph
+planted-partition batch (192 train / 64 validation); its validation ARI is
+compared with the best swept threshold per graph and the best single global
+threshold, and its latency with the 64-threshold sweep on the same GPU.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -39,15 +49,15 @@ def parse():
     ap.add_argument("--scale", type=int, default=26)
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--delta", type=str, default="3/50", help="Tectonic threshold num/den")
-    ap.add_argument("--cpu-scale", type=int, default=20, help="R-MAT scale of the oracle sample")
+    ap.add_argument("--cpu-scale", type=int, default=22, help="R-MAT scale of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-picker", action="store_true", help="skip picker training (use delta 3/50)")
     return ap.parse_args()
 
 
 def cpu_baseline(scale: int, ef: int, seed: int, num: int, den: int):
     """The oracle (plain C, OpenMP) on a bounded sample of the same workload
-    family: R-MAT at a smaller scale, same generator and threshold."""
+    family: R-MAT at a smaller scale, same generator and a fixed threshold."""
     import graphgen as gg
     import oracle
 
@@ -58,10 +68,82 @@ def cpu_baseline(scale: int, ef: int, seed: int, num: int, den: int):
     dt = time.perf_counter() - t0
     m = len(r["lo"])
     return dict(value=m / dt, unit="edges/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"R-MAT scale {scale} edge factor {ef} (n={n}, m={m}), full pipeline "
-                       f"(canonicalise, triangles, Tectonic, prune {num}/{den}, BFS components), "
-                       f"{dt:.2f} s",
+                sample=f"R-MAT scale {scale} edge factor {ef} (n={n}, m={m}): canonicalise, triangles, "
+                       f"Tectonic weights, prune at {num}/{den}, BFS components; {dt:.2f} s",
                 seconds=dt, stages_s={k: round(v, 3) for k, v in tm.items()})
+
+
+def picker_study(M, PK, dev):
+    """Train on the planted batch, score validation graphs, time picker vs sweep."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = M.mcd_ctx_create(0)
+    b = gg.sbm_batch(256)
+    vb = cu(b["vbase"])
+    g = M.mcd_graph_build(ctx, cu(b["src"]), cu(b["dst"]), b["n"])
+    t = M.mcd_triangles(g)
+    _, ari, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vb, truth=cu(b["truth"]))
+    _, y = M.mcd_sweep_targets(ctx, ari)
+    x = M.mcd_features(g, t, vb)
+    gi = np.arange(256)
+    tr, va = gi[gi % 4 != 3], gi[gi % 4 == 3]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model, losses = PK.train(ctx, x[cu(tr)].contiguous(), y[cu(tr)].contiguous())
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    index, _, _, _ = PK.pick(g, t, model, vb)
+    A = ari.cpu().numpy()
+    pi = index.cpu().numpy()
+    res = dict(train_graphs=int(len(tr)), val_graphs=int(len(va)), train_steps=len(losses),
+               train_seconds=round(train_s, 3), final_loss=float(losses[-1]),
+               ari_picker=float(A[va, pi[va]].mean()), ari_best_swept=float(A[va].max(1).mean()),
+               ari_best_global=float(A[va][:, int(np.argmax(A[tr].mean(0)))].mean()))
+    res["gap_to_best"] = res["ari_best_swept"] - res["ari_picker"]
+    res["gain_over_global"] = res["ari_picker"] - res["ari_best_global"]
+    # latency on the validation graphs packed as their own batch
+    srcs, dsts, tru, vbv = [], [], [], [0]
+    for k in va:
+        a, c = b["vbase"][k], b["vbase"][k + 1]
+        sel = (b["src"] >= a) & (b["src"] < c)
+        srcs.append(b["src"][sel] - a + vbv[-1])
+        dsts.append(b["dst"][sel] - a + vbv[-1])
+        tru.append(b["truth"][a:c])
+        vbv.append(vbv[-1] + (c - a))
+    gv = M.mcd_graph_build(ctx, cu(np.concatenate(srcs).astype(np.int32)),
+                           cu(np.concatenate(dsts).astype(np.int32)), int(vbv[-1]))
+    vbv_t = cu(np.array(vbv, np.int64))
+    tv = M.mcd_triangles(gv)
+    truth_v = cu(np.concatenate(tru).astype(np.int32))
+    ws_sweep = torch.empty(M.mcd_sweep_workspace_size(gv, len(va), 64, True), dtype=torch.uint8, device=dev)
+
+    def run_sweep():
+        M.mcd_sweep(gv, M.MCD_SIM_TECTONIC, tv, PK.GRID, vbase=vbv_t, truth=truth_v, ws=ws_sweep)
+
+    def run_pick():
+        PK.pick(gv, tv, model, vbv_t)
+
+    def timeit(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    res["latency_sweep_ms"] = timeit(run_sweep)
+    res["latency_picker_ms"] = timeit(run_pick)
+    res["latency_ratio"] = res["latency_sweep_ms"] / res["latency_picker_ms"]
+    res["latency_workload"] = (f"{len(va)} validation graphs as one batch (n={int(vbv[-1])}, m={gv.m}); sweep: "
+                               f"64 thresholds with ARI; picker: features, MLP, snap, prune, components")
+    return model, res
 
 
 def main():
@@ -75,10 +157,19 @@ def main():
 
     import graphgen as gg
     import paper_2412_12382_amd.mcd as M
+    from paper_2412_12382_amd import picker as PK
 
-    num, den = (int(x) for x in args.delta.split("/"))
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    model, pick_res = None, None
+    if not args.no_picker:
+        log("training the threshold picker on the 256-graph planted-partition batch")
+        model, pick_res = picker_study(M, PK, dev)
+        log(f"picker: val ARI {pick_res['ari_picker']:.4f} (best swept {pick_res['ari_best_swept']:.4f}, "
+            f"best global {pick_res['ari_best_global']:.4f}); latency {pick_res['latency_picker_ms']:.3f} ms vs "
+            f"sweep {pick_res['latency_sweep_ms']:.3f} ms")
+        torch.cuda.empty_cache()
 
     log(f"generating R-MAT scale {args.scale} edge factor {args.edge_factor} on the host")
     t0 = time.perf_counter()
@@ -93,31 +184,47 @@ def main():
     ctx = M.mcd_ctx_create(0)
     st_b, ws_b = M.mcd_graph_build_sizes(P, n)
     storage = torch.empty(st_b, dtype=torch.uint8, device=dev)
-    ws = torch.empty(ws_b, dtype=torch.uint8, device=dev)
+    ws = torch.empty(ws_b, dtype=torch.uint8, device=dev)  # build scratch, reused by later stages
     t = torch.empty(P, dtype=torch.int32, device=dev)
     wf = torch.empty(P, dtype=torch.float32, device=dev)
     keep = torch.empty((P + 31) // 32 + 1, dtype=torch.int32, device=dev)
     n_kept = torch.empty(1, dtype=torch.int64, device=dev)
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ncc = torch.empty(1, dtype=torch.int64, device=dev)
+    vbase = torch.tensor([0, n], dtype=torch.int64, device=dev)
+    x = torch.empty((1, M.MLP_IN), dtype=torch.float32, device=dev)
+    yhat = torch.empty(1, dtype=torch.float32, device=dev)
+    pidx = torch.empty(1, dtype=torch.int32, device=dev)
+    pdelta = torch.empty((1, 2), dtype=torch.int64, device=dev)
+    grid16 = [(k, 50) for k in range(16)]
+    sweep_stats = torch.empty((1, 16, 7), dtype=torch.int64, device=dev)
     log(f"HBM in use after allocation: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    stage_names = ["build", "triangles", "weights", "prune", "components"]
+    stage_names = ["build", "triangles", "weights", "picker", "prune", "components", "sweep16"]
 
     def step():
         e = [ev() for _ in range(len(stage_names) + 1)]
         e[0].record()
         g = M.mcd_graph_build(ctx, src, dst, n, storage=storage, ws=ws)
         e[1].record()
-        M.mcd_triangles(g, t)
+        M.mcd_triangles(g, t, ws=ws)
         e[2].record()
         M.mcd_weights(g, M.MCD_SIM_TECTONIC, t, w_f32=wf)
         e[3].record()
-        M.mcd_prune(g, M.MCD_SIM_TECTONIC, t, (num, den), keep, n_kept)
+        if model is not None:
+            M.mcd_features(g, t, vbase, x=x, ws=ws)
+            M.mcd_mlp_forward(ctx, model.params, model.mean, model.std, x, y=yhat)
+            M.mcd_grid_select(ctx, yhat, PK.GRID_K, PK.GRID_A, PK.GRID_B, PK.GRID_C, index=pidx, delta=pdelta)
+        else:
+            pdelta.copy_(torch.tensor([[3, 50]], dtype=torch.int64))
         e[4].record()
-        M.mcd_components(g, keep, labels, ncc, ws=ws)
+        M.mcd_prune_graphs(g, M.MCD_SIM_TECTONIC, t, pdelta, vbase, keep_bits=keep, n_kept=n_kept)
         e[5].record()
+        M.mcd_components(g, keep, labels, ncc, ws=ws)
+        e[6].record()
+        M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, grid16, vbase=vbase, stats=sweep_stats, ws=ws)
+        e[7].record()
         return g, e
 
     for i in range(args.warmup):
@@ -142,7 +249,7 @@ def main():
 
     # algorithmic bytes of the triangle kernel: the lists a merge-based
     # intersection streams for every oriented edge u->v (suffix of N+(u) after
-    # v, all of N+(v)), plus t written, src/adj of the edge and row offsets.
+    # v, all of N+(v)), plus t written, the edge's own row/head and offsets
     u, v = M.mcd_graph_edges(g)
     outd = torch.bincount(u.long(), minlength=n).double()
     ind = torch.bincount(v.long(), minlength=n).double()
@@ -151,19 +258,23 @@ def main():
     tc_bytes = 4.0 * W + 12.0 * m + 8.0 * (n + 1)
     tc_gbs = tc_bytes / (avg["triangles"] * 1e-3) / 1e9
     kept = int(n_kept.item())
-    # weight+prune+components: t, src, adj read; deg gathered for both ends;
-    # w written; keep bits written and read; kept edges' endpoints re-read by
-    # the union step; parent init/finalise and labels over n.
-    wpc_bytes = (4.0 * m * 5 + 4.0 * m) + (m / 8.0) * 2 + 8.0 * kept + 16.0 * n
+    tri = int(t[:m].sum(dtype=torch.int64).item()) // 3
+    # weight + prune + components: t, src, adj and both degrees per edge read
+    # once per pass (weights, prune), w written, keep bits written then read,
+    # kept edges' endpoints read by the union step, parent/labels over n
+    wpc_bytes = 2 * (4.0 * m * 4) + 4.0 * m + (m / 8.0) * 2 + 8.0 * kept + 16.0 * n
     wpc_ms = avg["weights"] + avg["prune"] + avg["components"]
     wpc_gbs = wpc_bytes / (wpc_ms * 1e-3) / 1e9
     ncomp = int(ncc.item())
-    log(f"m={m} kept={kept} components={ncomp} W={W:.3e} tc {tc_gbs:.0f} GB/s, wpc {wpc_gbs:.0f} GB/s")
+    sw = sweep_stats.cpu().numpy()[0]
+    pick_delta = [int(v_) for v_ in pdelta.cpu().numpy()[0]]
+    log(f"m={m} triangles={tri} picked delta={pick_delta[0]}/{pick_delta[1]} kept={kept} components={ncomp} "
+        f"W={W:.3e} tc {tc_gbs:.0f} GB/s, wpc {wpc_gbs:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on R-MAT scale {args.cpu_scale}")
-        cpu = cpu_baseline(args.cpu_scale, args.edge_factor, args.seed, num, den)
+        cpu = cpu_baseline(args.cpu_scale, args.edge_factor, args.seed, 3, 50)
         log(f"oracle: {cpu['value']:.3e} edges/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
 
     out = {
@@ -180,18 +291,22 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"R-MAT scale {args.scale}, edge factor {args.edge_factor}, "
-                               f"(a,b,c,d)=(0.57,0.19,0.19,0.05), symmetrised, deduplicated; "
-                               f"Tectonic weights, prune at {num}/{den}, components",
-                   "n": n, "m": m, "pairs": P, "delta": f"{num}/{den}",
-                   "step": "build+triangles+weights+prune+components"},
-        "stages_ms": {k: round(v, 3) for k, v in avg.items()},
+                               f"(a,b,c,d)=(0.57,0.19,0.19,0.05), symmetrised, deduplicated; Tectonic weights, "
+                               f"learned threshold, 16-point check sweep k/50, components",
+                   "n": n, "m": m, "pairs": P,
+                   "step": "build+triangles+weights+picker+prune+components+sweep16"},
+        "stages_ms": {k: round(v_, 3) for k, v_ in avg.items()},
         "wpc_edges_per_s": m / (wpc_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": tc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": tc_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "triangles",
                      "algorithmic_bytes": tc_bytes, "W": W},
         "roofline_wpc": {"bound": "hbm", "achieved": wpc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": wpc_gbs / HBM_PEAK_GBS, "algorithmic_bytes": wpc_bytes},
-        "results": {"n_kept": kept, "n_components": ncomp},
+        "results": {"triangles": tri, "picked_delta": pick_delta, "n_kept": kept, "n_components": ncomp,
+                    "sweep16": {"delta": [f"{a}/{b}" for a, b in grid16],
+                                "m_kept": sw[:, 0].tolist(), "n_components": sw[:, 1].tolist(),
+                                "largest_component": sw[:, 2].tolist()}},
+        "picker": pick_res,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

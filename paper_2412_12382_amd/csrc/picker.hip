@@ -76,13 +76,22 @@ __global__ __launch_bounds__(kThreads) void k_feat_hist(const int32_t* __restric
             if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
+// max degree per graph; lanes sharing lane 0's graph reduce before one atomic
 __global__ __launch_bounds__(kThreads) void k_feat_maxdeg(const int32_t* __restrict__ deg,
                                                           const int32_t* __restrict__ perm, int64_t n,
                                                           const int64_t* __restrict__ vbase, int G,
                                                           unsigned long long* __restrict__ mdeg) {
     GRID_STRIDE(v, n) {
         const int g = G == 1 ? 0 : graph_of(vbase, G, perm[v]);
-        atomicMax(&mdeg[g], (unsigned long long)deg[v]);
+        const unsigned long long d = (unsigned long long)deg[v];
+        const int g0 = __shfl(g, 0);
+        unsigned long long x = g == g0 ? d : 0ull;
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long y = __shfl_xor(x, o);
+            x = y > x ? y : x;
+        }
+        if ((threadIdx.x & 63) == 0 && x) atomicMax(&mdeg[g0], x);
+        if (g != g0) atomicMax(&mdeg[g], d);
     }
 }
 

@@ -51,6 +51,21 @@ __device__ __forceinline__ void agg_add(unsigned long long* acc, int64_t key, un
     if (!same && val) atomicAdd(&acc[key], val);
 }
 
+// acc[key] = max(acc[key], val), reduced first over the lanes sharing lane 0's key
+__device__ __forceinline__ void agg_max(unsigned long long* acc, int64_t key, unsigned long long val) {
+    const int64_t k0 = __shfl(key, 0);
+    const bool same = key == k0;
+    unsigned long long x = same ? val : 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o);
+        x = y > x ? y : x;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (x) atomicMax(&acc[k0], x);
+    }
+    if (!same && val) atomicMax(&acc[key], val);
+}
+
 // level[e] = number of sorted thresholds delta_i with NOT (sim(e) < delta_i)
 __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ src,
                                                     const int32_t* __restrict__ adj,
@@ -95,8 +110,8 @@ __global__ __launch_bounds__(kThreads) void k_level_hist(const int32_t* __restri
                                                          const uint8_t* __restrict__ level, int64_t m,
                                                          const int32_t* __restrict__ gid, int K, int nbins,
                                                          unsigned long long* __restrict__ hist) {
-    __shared__ uint32_t h[2048];
-    const bool local = nbins <= 2048;
+    __shared__ uint32_t h[8192];
+    const bool local = nbins <= 8192;
     if (local)
         for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
     __syncthreads();
@@ -209,7 +224,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_
         const int32_t g = gid[v];
         const int32_t sz = size[r];
         agg_add(acc_a, g, (unsigned long long)(sz - 1));
-        if (r == (int32_t)v) atomicMax(&largest[g], (unsigned long long)sz);
+        agg_max(largest, g, r == (int32_t)v ? (unsigned long long)sz : 0ull);
         if (cls) {
             const uint64_t k = cell_key(r, cls[v]);
             const uint32_t mask = (1u << log2cap) - 1u;
