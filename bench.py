@@ -188,6 +188,8 @@ def main():
     t = torch.empty(P, dtype=torch.int32, device=dev)
     wf = torch.empty(P, dtype=torch.float32, device=dev)
     keep = torch.empty((P + 31) // 32 + 1, dtype=torch.int32, device=dev)
+    kept_pairs = torch.empty(M.KeptList.capacity(P), dtype=torch.int32, device=dev)
+    kept_counts = torch.empty(M.KEPT_SEGMENTS, dtype=torch.int32, device=dev)
     n_kept = torch.empty(1, dtype=torch.int64, device=dev)
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ncc = torch.empty(1, dtype=torch.int64, device=dev)
@@ -201,7 +203,7 @@ def main():
     log(f"HBM in use after allocation: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    stage_names = ["build", "triangles", "weights", "picker", "prune", "components", "sweep16"]
+    stage_names = ["build", "triangles", "picker", "weigh_prune", "components", "sweep16"]
 
     def step():
         e = [ev() for _ in range(len(stage_names) + 1)]
@@ -210,21 +212,21 @@ def main():
         e[1].record()
         M.mcd_triangles(g, t, ws=ws)
         e[2].record()
-        M.mcd_weights(g, M.MCD_SIM_TECTONIC, t, w_f32=wf)
-        e[3].record()
         if model is not None:
             M.mcd_features(g, t, vbase, x=x, ws=ws)
             M.mcd_mlp_forward(ctx, model.params, model.mean, model.std, x, y=yhat)
             M.mcd_grid_select(ctx, yhat, PK.GRID_K, PK.GRID_A, PK.GRID_B, PK.GRID_C, index=pidx, delta=pdelta)
         else:
             pdelta.copy_(torch.tensor([[3, 50]], dtype=torch.int64))
+        e[3].record()
+        kept = M.KeptList(g, kept_pairs, kept_counts)
+        M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, t, deltas=pdelta, vbase=vbase, w_f32=wf, keep_bits=keep,
+                          kept=kept, n_kept=n_kept)
         e[4].record()
-        M.mcd_prune_graphs(g, M.MCD_SIM_TECTONIC, t, pdelta, vbase, keep_bits=keep, n_kept=n_kept)
+        M.mcd_components_kept(g, kept, labels, ncc, ws=ws)
         e[5].record()
-        M.mcd_components(g, keep, labels, ncc, ws=ws)
-        e[6].record()
         M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, grid16, vbase=vbase, stats=sweep_stats, ws=ws)
-        e[7].record()
+        e[6].record()
         return g, e
 
     for i in range(args.warmup):
@@ -259,11 +261,12 @@ def main():
     tc_gbs = tc_bytes / (avg["triangles"] * 1e-3) / 1e9
     kept = int(n_kept.item())
     tri = int(t[:m].sum(dtype=torch.int64).item()) // 3
-    # weight + prune + components: t, src, adj and both degrees per edge read
-    # once per pass (weights, prune), w written, keep bits written then read,
-    # kept edges' endpoints read by the union step, parent/labels over n
-    wpc_bytes = 2 * (4.0 * m * 4) + 4.0 * m + (m / 8.0) * 2 + 8.0 * kept + 16.0 * n
-    wpc_ms = avg["weights"] + avg["prune"] + avg["components"]
+    # weight + prune + components, algorithmic bytes: t, head and the head's
+    # degree read per edge, w written, keep bits written, row offsets; then
+    # the kept edges read once by the union step and 12 bytes per vertex
+    # (parent, label, original id)
+    wpc_bytes = 16.0 * m + m / 8.0 + 8.0 * (n + 1) + 8.0 * kept + 12.0 * n
+    wpc_ms = avg["weigh_prune"] + avg["components"]
     wpc_gbs = wpc_bytes / (wpc_ms * 1e-3) / 1e9
     ncomp = int(ncc.item())
     sw = sweep_stats.cpu().numpy()[0]

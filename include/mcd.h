@@ -137,6 +137,11 @@ mcd_status mcd_graph_edges(const mcd_graph* g, int32_t* u, int32_t* v);
 /* deg(x) = |N(x)| for every original id x.  deg: device int32[n]. */
 mcd_status mcd_graph_degrees(const mcd_graph* g, int32_t* deg);
 
+/* The library's internal vertex numbering (rank by (degree, original id)):
+ * perm[r] is the original id of internal vertex r.  perm: device int32[n].
+ * Kept-edge lists (mcd_weigh_prune) hold internal numbers. */
+mcd_status mcd_graph_perm(const mcd_graph* g, int32_t* perm);
+
 mcd_status mcd_graph_destroy(mcd_graph* g);
 
 /* ----------------------------------------------------------------- steps */
@@ -166,7 +171,40 @@ mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t
 mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
                      uint32_t* keep_bits, int64_t* n_kept);
 
-/* Scratch for mcd_components / mcd_run on this graph. */
+/* Number of segments of a compacted kept-edge list (see mcd_weigh_prune). */
+#define MCD_KEPT_SEGMENTS 16384
+
+/* Weights and prune in ONE pass over the edges: the two read the same data
+ * (t, both endpoints, both degrees), so Algorithm 1's first step costs one
+ * stream of the edge arrays.  The decision is mcd_prune's (ties kept, exact
+ * integer cross-multiplication); the weights are mcd_weights'.
+ *   delta:      the threshold when deltas is NULL;
+ *   deltas:     NULL, or device int64[2 n_graphs]: graph k's threshold is
+ *               deltas[2k] / deltas[2k+1] (den > 0; the comparison is exact in
+ *               128-bit arithmetic); graph k owns the original ids
+ *               [vbase[k], vbase[k+1]) (vbase: device int64[n_graphs+1]).
+ *   w_f32, w_i32: as mcd_weights (each may be NULL; w_i32 for TW only).
+ *   keep_bits:  as mcd_prune (may be NULL).
+ *   kept_pairs, kept_counts: the kept edges as a segmented list, the input of
+ *               mcd_components_kept (both NULL, or both given).  The edges,
+ *               in library edge order, are cut into S = MCD_KEPT_SEGMENTS runs
+ *               of L = mcd_kept_segment_len edges; segment s writes the kept
+ *               edges of run s, in edge order, as pairs of INTERNAL vertex
+ *               numbers (mcd_graph_perm) to kept_pairs[2 s L ...] and their
+ *               number to kept_counts[s].  kept_pairs: device int32[2 S L];
+ *               kept_counts: device int32[MCD_KEPT_SEGMENTS].
+ *   n_kept:     device int64[1] (may be NULL), the number of kept edges.
+ * Asynchronous. */
+mcd_status mcd_weigh_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
+                           int32_t n_graphs, const int64_t* vbase, const int64_t* deltas, float* w_f32,
+                           int32_t* w_i32, uint32_t* keep_bits, int32_t* kept_pairs, int32_t* kept_counts,
+                           int64_t* n_kept);
+
+/* Edges per run (and pair capacity per segment) of a kept-edge list of this
+ * graph: L = 64 ceil(ceil(m / 64) / MCD_KEPT_SEGMENTS). */
+mcd_status mcd_kept_segment_len(const mcd_graph* g, int64_t* len);
+
+/* Scratch for mcd_components / mcd_components_kept / mcd_run on this graph. */
 mcd_status mcd_components_workspace_size(const mcd_graph* g, size_t* bytes);
 mcd_status mcd_run_workspace_size(const mcd_graph* g, size_t* bytes);
 
@@ -174,9 +212,17 @@ mcd_status mcd_run_workspace_size(const mcd_graph* g, size_t* bytes);
  * labels[x] (device int32[n], by original id) is the smallest original id in
  * x's component, so isolated vertices label themselves.  keep_bits may be
  * NULL (every edge kept).  n_components: device int64[1] (may be NULL).
- * Union-find with hooking toward the smaller original id and pointer jumping. */
+ * Lock-free union-find (roots hook under the higher-ranked root, finds halve
+ * paths), then every component takes the smallest original id among its
+ * vertices as its label. */
 mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
                           int64_t* n_components, void* ws, size_t ws_bytes);
+
+/* mcd_components over a kept-edge list written by mcd_weigh_prune on the
+ * same graph (kept_pairs, kept_counts as described there).  Same labels and
+ * count as mcd_components on the equivalent keep_bits.  Asynchronous. */
+mcd_status mcd_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
+                               int32_t* labels, int64_t* n_components, void* ws, size_t ws_bytes);
 
 /* Algorithm 1 in one call: triangles, weights, prune at delta, components.
  * labels / n_components as in mcd_components.  Asynchronous. */

@@ -50,6 +50,7 @@ struct StorageLayout {
     int64_t* off;
     int32_t* src;
     int32_t* adj;
+    int32_t* dsum;
     int32_t* deg;
     int32_t* perm;
     int64_t* in_off;
@@ -63,6 +64,7 @@ StorageLayout storage_layout(void* base, int64_t P, int64_t n) {
     L.off = c.take<int64_t>((size_t)n + 1);
     L.src = c.take<int32_t>((size_t)P);
     L.adj = c.take<int32_t>((size_t)P + 4);  // +4: 16-byte loads may read past the last edge
+    L.dsum = c.take<int32_t>((size_t)P);
     L.deg = c.take<int32_t>((size_t)n);
     L.perm = c.take<int32_t>((size_t)n);
     L.in_off = c.take<int64_t>((size_t)n + 1);
@@ -103,8 +105,9 @@ BuildLayout build_layout(void* base, int64_t P, int64_t n) {
 
 struct RunLayout {
     int32_t* t;
-    uint32_t* keep;
-    int32_t* parent;
+    int32_t* kept_pairs;
+    int32_t* kept_counts;
+    void* cc;
     void* tc;
     size_t bytes;
 };
@@ -113,8 +116,9 @@ RunLayout run_layout(void* base, const mcd_graph* g) {
     Carve c{(char*)base, 0, 0};
     RunLayout L;
     L.t = c.take<int32_t>((size_t)g->m);
-    L.keep = c.take<uint32_t>((size_t)(g->m + 31) / 32);
-    L.parent = c.take<int32_t>((size_t)g->n);
+    L.kept_pairs = c.take<int32_t>((size_t)2 * MCD_KEPT_SEGMENTS * mcd::kept_segment_len(g->m));
+    L.kept_counts = c.take<int32_t>((size_t)MCD_KEPT_SEGMENTS);
+    L.cc = c.take<char>(mcd::cc_scratch_bytes(g));
     L.tc = c.take<char>(mcd::tc_scratch_bytes(g, g->ctx->tc_chunk));
     L.bytes = c.used;
     return L;
@@ -277,6 +281,7 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     mcd::fill_i32(B.outdeg, n, 0, s);
     mcd::launch_csr_fill(oriented, m, bits, G.src, G.adj, B.outdeg, s);
     mcd::exclusive_scan_i32_i64(B.outdeg, n, G.off, B.scan, s);
+    mcd::launch_edge_dsum(G.src, G.adj, G.deg, m, G.dsum, s);
     mcd::launch_max_i32(B.outdeg, n, ctrl + 2, s);
     mcd::launch_max_i32(G.deg, n, ctrl + 3, s);
     // in-edge lists (edges grouped by head), in-degree = degree - out-degree
@@ -297,6 +302,7 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     g->off = G.off;
     g->src = G.src;
     g->adj = G.adj;
+    g->dsum = G.dsum;
     g->deg = G.deg;
     g->perm = G.perm;
     g->in_off = G.in_off;
@@ -328,6 +334,16 @@ mcd_status mcd_graph_degrees(const mcd_graph* g, int32_t* deg) {
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_scatter_by_perm(g->deg, g->perm, g->n, deg, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_perm(const mcd_graph* g, int32_t* perm) {
+    REQUIRE(g && (g->n == 0 || perm), MCD_ERR_INVALID_ARG, "NULL argument");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    if (g->n > 0)
+        MCD_HIP(hipMemcpyAsync(perm, g->perm, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToDevice,
+                               g->ctx->stream));
     return MCD_OK;
 }
 
@@ -379,7 +395,7 @@ mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, 
 
 mcd_status mcd_components_workspace_size(const mcd_graph* g, size_t* bytes) {
     REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
-    *bytes = mcd_align(sizeof(int32_t) * (size_t)g->n + 1);
+    *bytes = mcd::cc_scratch_bytes(g);
     return MCD_OK;
 }
 
@@ -391,7 +407,47 @@ mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t
     REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "components workspace too small");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
-    mcd::launch_components(g, keep_bits, labels, n_components, (int32_t*)ws, g->ctx->stream);
+    mcd::launch_components(g, keep_bits, labels, n_components, ws, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_kept_segment_len(const mcd_graph* g, int64_t* len) {
+    REQUIRE(g && len, MCD_ERR_INVALID_ARG, "NULL argument");
+    *len = mcd::kept_segment_len(g->m);
+    return MCD_OK;
+}
+
+mcd_status mcd_weigh_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
+                           int32_t n_graphs, const int64_t* vbase, const int64_t* deltas, float* w_f32,
+                           int32_t* w_i32, uint32_t* keep_bits, int32_t* kept_pairs, int32_t* kept_counts,
+                           int64_t* n_kept) {
+    REQUIRE(g, MCD_ERR_INVALID_ARG, "graph is NULL");
+    REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
+    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(!(measure == MCD_SIM_TECTONIC && w_i32), MCD_ERR_INVALID_ARG, "integer weights exist for TW only");
+    REQUIRE((kept_pairs == nullptr) == (kept_counts == nullptr), MCD_ERR_INVALID_ARG,
+            "kept_pairs and kept_counts go together");
+    mcd_status st;
+    if (deltas) {
+        REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "n_graphs must be at least 1");
+        REQUIRE(n_graphs == 1 || vbase, MCD_ERR_INVALID_ARG, "vbase is NULL");
+    } else if ((st = check_delta(delta)) != MCD_OK) {
+        return st;
+    }
+    if ((st = use_device(g->ctx)) != MCD_OK) return st;
+    mcd::launch_weigh_prune(g, measure, t, delta.num, delta.den, deltas ? n_graphs : 1, vbase, deltas, w_f32, w_i32,
+                            keep_bits, kept_pairs, kept_counts, n_kept, g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
+                               int32_t* labels, int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g->m == 0 || (kept_pairs && kept_counts), MCD_ERR_INVALID_ARG, "kept list is NULL");
+    REQUIRE(ws_bytes >= mcd::cc_scratch_bytes(g), MCD_ERR_WORKSPACE, "components workspace too small");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_components_kept(g, kept_pairs, kept_counts, labels, n_components, ws, g->ctx->stream);
     return MCD_OK;
 }
 
@@ -415,8 +471,9 @@ mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, 
     hipStream_t s = g->ctx->stream;
     mcd::launch_triangles(g, L.t, L.tc, g->ctx->tc_chunk, g->ctx->tc_lds_max, g->ctx->tc_packed_range,
                           g->ctx->tc_window_max, s);
-    mcd::launch_prune(g, measure, L.t, delta.num, delta.den, L.keep, nullptr, s);
-    mcd::launch_components(g, L.keep, labels, n_components, L.parent, s);
+    mcd::launch_weigh_prune(g, measure, L.t, delta.num, delta.den, 1, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            L.kept_pairs, L.kept_counts, nullptr, s);
+    mcd::launch_components_kept(g, L.kept_pairs, L.kept_counts, labels, n_components, L.cc, s);
     return MCD_OK;
 }
 

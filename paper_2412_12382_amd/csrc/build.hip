@@ -69,6 +69,16 @@ __global__ __launch_bounds__(kThreads) void k_rank_apply(const uint64_t* __restr
     }
 }
 
+// dsum[e] = deg u + deg v of every oriented edge (as uint32): the degree term
+// of both similarity measures, stored with the CSR so that every weight pass
+// streams it instead of gathering two degrees per edge.
+__global__ __launch_bounds__(kThreads) void k_edge_dsum(const int32_t* __restrict__ src,
+                                                        const int32_t* __restrict__ adj,
+                                                        const int32_t* __restrict__ deg, int64_t m,
+                                                        int32_t* __restrict__ dsum) {
+    GRID_STRIDE(e, m) dsum[e] = (int32_t)((uint32_t)deg[src[e]] + (uint32_t)deg[adj[e]]);
+}
+
 __global__ __launch_bounds__(kThreads) void k_orient_keys(const uint64_t* __restrict__ uniq, int64_t m,
                                                           int bits, const int32_t* __restrict__ inv,
                                                           uint64_t* __restrict__ keys) {
@@ -193,6 +203,12 @@ void launch_rank_apply(const uint64_t* sorted, int64_t n, int bits, const int32_
     if (n <= 0) return;
     hipLaunchKernelGGL(k_rank_apply, dim3(grid_for(n)), dim3(kThreads), 0, s, sorted, n, bits, deg_orig,
                        perm, inv, deg_new);
+}
+
+void launch_edge_dsum(const int32_t* src, const int32_t* adj, const int32_t* deg, int64_t m, int32_t* dsum,
+                      hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_edge_dsum, dim3(grid_for(m)), dim3(kThreads), 0, s, src, adj, deg, m, dsum);
 }
 
 void launch_orient_keys(const uint64_t* uniq, int64_t m, int bits, const int32_t* inv,

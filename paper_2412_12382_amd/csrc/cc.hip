@@ -1,13 +1,15 @@
 // Connected components of (V, kept edges), the second step of Algorithm 1.
 //
 // Lock-free union-find over the rank-numbered vertices: every kept edge
-// unites its endpoints by hooking the root with the larger ORIGINAL id under
-// the root with the smaller one (compare-and-swap on the root's parent),
-// and finds use path halving, i.e. pointer jumping to the grandparent.  The
-// original id strictly decreases along every parent chain, so the root of a
-// component is its smallest original id: the canonical label.  Parent reads
-// and halving writes use device-scope atomics so no wave spins on a stale
-// per-CU cache line.
+// unites its endpoints by hooking the root of lower rank under the root of
+// higher rank (compare-and-swap on the root's parent), and finds use path
+// halving, i.e. pointer jumping to the grandparent.  Parents only ever point
+// to higher ranks, so chains are acyclic; roots end at high-degree vertices,
+// which keeps trees shallow on skewed graphs.  The canonical label of a
+// component, its smallest original id, is then gathered per root with one
+// atomic minimum per vertex (aggregated over the wave) and read back by every
+// member.  Parent reads and halving writes use device-scope atomics so no wave
+// spins on a stale per-CU cache line.
 #include "common.hpp"
 
 namespace mcd {
@@ -40,44 +42,88 @@ __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x) {
     }
 }
 
-__device__ __forceinline__ void unite(int32_t* parent, const int32_t* __restrict__ perm, int32_t a,
-                                      int32_t b) {
+__device__ __forceinline__ void unite(int32_t* parent, int32_t a, int32_t b) {
     for (;;) {
         a = find_root(parent, a);
         b = find_root(parent, b);
         if (a == b) return;
-        if (perm[a] < perm[b]) {
+        if (a > b) {
             const int32_t x = a;
             a = b;
             b = x;
         }
-        int32_t expected = a;
+        int32_t expected = a;  // hook the lower-ranked root a under b
         if (__hip_atomic_compare_exchange_strong(&parent[a], &expected, b, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_cc_init(int32_t* __restrict__ parent, int64_t n) {
+__global__ __launch_bounds__(kThreads) void k_cc_init(int32_t* __restrict__ parent, int32_t* __restrict__ minid,
+                                                      const int32_t* __restrict__ perm, int64_t n) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x)
+         v += (int64_t)gridDim.x * blockDim.x) {
         parent[v] = (int32_t)v;
+        minid[v] = perm[v];
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_cc_union(const int32_t* __restrict__ src,
                                                        const int32_t* __restrict__ adj,
                                                        const uint32_t* __restrict__ keep, int64_t m,
-                                                       const int32_t* __restrict__ perm,
                                                        int32_t* parent) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         if (keep && !((keep[e >> 5] >> (e & 31)) & 1u)) continue;
-        unite(parent, perm, src[e], adj[e]);
+        unite(parent, src[e], adj[e]);
+    }
+}
+
+// One wave per segment of a kept-edge list, walked from its end: a segment
+// lists its edge groups in ascending rank of the lower endpoint, so all waves
+// together unite the edges among high-degree vertices first and the rest of
+// the graph then hooks straight under the roots that core has formed.
+__global__ __launch_bounds__(kThreads) void k_cc_union_kept(const int2* __restrict__ kept,
+                                                            const int32_t* __restrict__ counts, int64_t seg_len,
+                                                            int32_t* parent) {
+    const int lane = threadIdx.x & 63;
+    const int64_t seg = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int32_t cnt = counts[seg];
+    const int2* p = kept + seg * seg_len;
+    for (int32_t i = cnt - 1 - lane; i >= 0; i -= 64) {
+        const int2 e = p[i];
+        unite(parent, e.x, e.y);
+    }
+}
+
+// minid[root] = min over the component of the original ids
+__global__ __launch_bounds__(kThreads) void k_cc_min(int32_t* parent, const int32_t* __restrict__ perm, int64_t n,
+                                                     int32_t* __restrict__ minid) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nround = (n + stride - 1) / stride;
+    for (int64_t rd = 0; rd < nround; ++rd) {
+        const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + rd * stride;
+        int32_t r = -1, id = 0x7fffffff;
+        if (v < n) {
+            r = find_root(parent, (int32_t)v);
+            if (r != (int32_t)v) id = perm[v];
+            else r = -1;  // a root's own id is already in minid
+        }
+        // lanes sharing lane 0's root reduce first
+        const int32_t r0 = __shfl(r, 0);
+        int32_t x = r == r0 ? id : 0x7fffffff;
+        for (int o = 32; o > 0; o >>= 1) {
+            const int32_t y = __shfl_xor(x, o);
+            x = y < x ? y : x;
+        }
+        if ((threadIdx.x & 63) == 0 && r0 >= 0 && x != 0x7fffffff) atomicMin(&minid[r0], x);
+        if (r != r0 && r >= 0) atomicMin(&minid[r], id);
     }
 }
 
 __global__ __launch_bounds__(kThreads) void k_cc_label(int32_t* parent, const int32_t* __restrict__ perm,
-                                                       int64_t n, int32_t* __restrict__ labels,
+                                                       const int32_t* __restrict__ minid, int64_t n,
+                                                       int32_t* __restrict__ labels,
                                                        unsigned long long* __restrict__ ncc) {
     __shared__ unsigned long long wsum[kThreads / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -89,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_cc_label(int32_t* parent, const in
         bool is_root = false;
         if (v < n) {
             const int32_t r = find_root(parent, (int32_t)v);
-            labels[perm[v]] = perm[r];
+            labels[perm[v]] = minid[r];
             is_root = (r == (int32_t)v);
         }
         const uint64_t bal = __ballot(is_root);
@@ -105,18 +151,43 @@ __global__ __launch_bounds__(kThreads) void k_cc_label(int32_t* parent, const in
     }
 }
 
+void finish_components(const mcd_graph* g, int32_t* labels, int64_t* n_components, int32_t* parent,
+                       int32_t* minid, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_min, dim3(grid_for(g->n, 8192)), dim3(kThreads), 0, s, parent, g->perm, g->n, minid);
+    hipLaunchKernelGGL(k_cc_label, dim3(grid_for(g->n, 8192)), dim3(kThreads), 0, s, parent, g->perm, minid,
+                       g->n, labels, (unsigned long long*)n_components);
+}
+
 }  // namespace
 
-void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
-                       int64_t* n_components, int32_t* parent, hipStream_t s) {
+size_t cc_scratch_bytes(const mcd_graph* g) { return 2 * mcd_align(sizeof(int32_t) * (size_t)g->n + 1); }
+
+void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels, int64_t* n_components,
+                       void* ws, hipStream_t s) {
     if (n_components) fill_i64(n_components, 1, 0, s);
     if (g->n <= 0) return;
-    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, parent, g->n);
+    int32_t* parent = (int32_t*)ws;
+    int32_t* minid = (int32_t*)((char*)ws + mcd_align(sizeof(int32_t) * (size_t)g->n + 1));
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, parent, minid, g->perm,
+                       g->n);
     if (g->m > 0)
         hipLaunchKernelGGL(k_cc_union, dim3(grid_for(g->m, 1 << 16)), dim3(kThreads), 0, s, g->src, g->adj,
-                           keep_bits, g->m, g->perm, parent);
-    hipLaunchKernelGGL(k_cc_label, dim3(grid_for(g->n, 8192)), dim3(kThreads), 0, s, parent, g->perm, g->n,
-                       labels, (unsigned long long*)n_components);
+                           keep_bits, g->m, parent);
+    finish_components(g, labels, n_components, parent, minid, s);
+}
+
+void launch_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
+                            int32_t* labels, int64_t* n_components, void* ws, hipStream_t s) {
+    if (n_components) fill_i64(n_components, 1, 0, s);
+    if (g->n <= 0) return;
+    int32_t* parent = (int32_t*)ws;
+    int32_t* minid = (int32_t*)((char*)ws + mcd_align(sizeof(int32_t) * (size_t)g->n + 1));
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, parent, minid, g->perm,
+                       g->n);
+    if (g->m > 0)
+        hipLaunchKernelGGL(k_cc_union_kept, dim3(MCD_KEPT_SEGMENTS / (kThreads / 64)), dim3(kThreads), 0, s,
+                           (const int2*)kept_pairs, kept_counts, kept_segment_len(g->m), parent);
+    finish_components(g, labels, n_components, parent, minid, s);
 }
 
 }  // namespace mcd

@@ -41,6 +41,7 @@ struct mcd_graph {
     int64_t* off;      // [n+1] CSR row offsets of the oriented graph (rows = new ids)
     int32_t* src;      // [cap] row (new id) of every edge
     int32_t* adj;      // [cap] head (new id) of every edge; rows sorted ascending
+    int32_t* dsum;     // [cap] deg u + deg v of every edge (read as uint32)
     int32_t* deg;      // [n]   degree by new id (non-decreasing)
     int32_t* perm;     // [n]   original id of every new id
     int64_t* in_off;   // [n+1] offsets of the in-edge lists
@@ -102,6 +103,8 @@ void launch_degree(const uint64_t* uniq, int64_t m, int bits, int32_t* deg_orig,
 void launch_rank_keys(const int32_t* deg_orig, int64_t n, int bits, uint64_t* keys, hipStream_t s);
 void launch_rank_apply(const uint64_t* sorted, int64_t n, int bits, const int32_t* deg_orig,
                        int32_t* perm, int32_t* inv, int32_t* deg_new, hipStream_t s);
+void launch_edge_dsum(const int32_t* src, const int32_t* adj, const int32_t* deg, int64_t m, int32_t* dsum,
+                      hipStream_t s);
 void launch_orient_keys(const uint64_t* uniq, int64_t m, int bits, const int32_t* inv,
                         uint64_t* keys, hipStream_t s);
 void launch_csr_fill(const uint64_t* sorted, int64_t m, int bits, int32_t* src, int32_t* adj,
@@ -132,9 +135,20 @@ void launch_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num
 void launch_prune_graphs(const mcd_graph* g, int measure, const int32_t* t, int G, const int64_t* vbase,
                          const int64_t* deltas, uint32_t* keep_bits, int64_t* n_kept, hipStream_t s);
 
+// Edges per segment of a kept-edge list (multiple of 64).
+int64_t kept_segment_len(int64_t m);
+// Weights and prune in one pass; deltas (device, per graph) overrides num/den
+// when non-NULL.  Every output may be NULL.
+void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den, int G,
+                        const int64_t* vbase, const int64_t* deltas, float* wf, int32_t* wi, uint32_t* keep_bits,
+                        int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s);
+
 // ---- components (cc.hip) ----
+size_t cc_scratch_bytes(const mcd_graph* g);
 void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
-                       int64_t* n_components, int32_t* parent, hipStream_t s);
+                       int64_t* n_components, void* ws, hipStream_t s);
+void launch_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
+                            int32_t* labels, int64_t* n_components, void* ws, hipStream_t s);
 
 // ---- percentile (select.hip) ----
 size_t select_scratch_bytes(const mcd_graph* g);

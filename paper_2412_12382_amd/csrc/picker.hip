@@ -50,8 +50,7 @@ __device__ __forceinline__ int graph_of(const int64_t* __restrict__ vbase, int G
 // hist[g][b] over edges, bin = floor(128 t / D) (integer division, < 64 since
 // t <= min degree - 1); mdeg[g] = max degree
 __global__ __launch_bounds__(kThreads) void k_feat_hist(const int32_t* __restrict__ src,
-                                                        const int32_t* __restrict__ adj,
-                                                        const int32_t* __restrict__ deg,
+                                                        const int32_t* __restrict__ dsum,
                                                         const int32_t* __restrict__ perm,
                                                         const int32_t* __restrict__ t, int64_t m,
                                                         const int64_t* __restrict__ vbase, int G,
@@ -62,11 +61,10 @@ __global__ __launch_bounds__(kThreads) void k_feat_hist(const int32_t* __restric
         for (int i = threadIdx.x; i < G * 64; i += blockDim.x) h[i] = 0;
     __syncthreads();
     GRID_STRIDE(e, m) {
-        const int32_t u = src[e];
-        const int64_t D = (int64_t)deg[u] + deg[adj[e]];
+        const int64_t D = (uint32_t)dsum[e];
         int64_t b = (128 * (int64_t)t[e]) / D;
         if (b > 63) b = 63;
-        const int g = G == 1 ? 0 : graph_of(vbase, G, perm[u]);
+        const int g = G == 1 ? 0 : graph_of(vbase, G, perm[src[e]]);
         if (local) atomicAdd(&h[g * 64 + b], 1u);
         else atomicAdd(&hist[(int64_t)g * 64 + b], 1ull);
     }
@@ -284,7 +282,7 @@ void launch_features(const mcd_graph* g, const int32_t* t, int G, const int64_t*
     hipLaunchKernelGGL((k_fill_ull), dim3(grid_for((int64_t)G * 65, 1024)), dim3(kThreads), 0, s, hist,
                        (int64_t)G * 65);
     if (g->m > 0)
-        hipLaunchKernelGGL(k_feat_hist, dim3(grid_for(g->m, 4096)), dim3(kThreads), 0, s, g->src, g->adj, g->deg,
+        hipLaunchKernelGGL(k_feat_hist, dim3(grid_for(g->m, 4096)), dim3(kThreads), 0, s, g->src, g->dsum,
                            g->perm, t, g->m, vbase, G, hist);
     if (g->n > 0)
         hipLaunchKernelGGL(k_feat_maxdeg, dim3(grid_for(g->n, 4096)), dim3(kThreads), 0, s, g->deg, g->perm,

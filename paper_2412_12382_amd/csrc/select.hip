@@ -28,11 +28,10 @@ struct Sim {
     bool nonzero;
 };
 
-__device__ __forceinline__ Sim sim_of(const int32_t* __restrict__ src, const int32_t* __restrict__ adj,
-                                      const int32_t* __restrict__ deg, const int32_t* __restrict__ t,
+__device__ __forceinline__ Sim sim_of(const int32_t* __restrict__ dsum, const int32_t* __restrict__ t,
                                       int64_t e, int measure) {
     Sim s;
-    const int32_t D = deg[src[e]] + deg[adj[e]];
+    const int64_t D = (uint32_t)dsum[e];
     const int32_t tt = t[e];
     if (measure == MCD_SIM_TECTONIC) {
         s.num = tt;
@@ -40,7 +39,7 @@ __device__ __forceinline__ Sim sim_of(const int32_t* __restrict__ src, const int
         s.nonzero = tt != 0;
         s.key = __float_as_uint((float)tt / (float)D);
     } else {
-        const int32_t tw = 3 * tt - D + 2;
+        const int32_t tw = (int32_t)(3 * (int64_t)tt - D + 2);
         s.num = tw;
         s.den = 1;
         s.nonzero = tw != 0;
@@ -55,9 +54,7 @@ __device__ __forceinline__ int rat_cmp(int64_t a, int64_t b, int64_t c, int64_t 
     return (l > r) - (l < r);
 }
 
-__global__ __launch_bounds__(kThreads) void k_sel_hist(const int32_t* __restrict__ src,
-                                                       const int32_t* __restrict__ adj,
-                                                       const int32_t* __restrict__ deg,
+__global__ __launch_bounds__(kThreads) void k_sel_hist(const int32_t* __restrict__ dsum,
                                                        const int32_t* __restrict__ t, int64_t m,
                                                        int measure, uint32_t prefix, uint32_t pmask,
                                                        int shift, unsigned long long* __restrict__ hist) {
@@ -66,7 +63,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const int32_t* __restrict
     __syncthreads();
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const Sim s = sim_of(src, adj, deg, t, e, measure);
+        const Sim s = sim_of(dsum, t, e, measure);
         if (s.nonzero && (s.key & pmask) == prefix) atomicAdd(&h[(s.key >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -76,9 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_hist(const int32_t* __restrict
 // Per-block minimum rational strictly above lb (lb_valid = 0: no bound) among
 // nonzero similarities whose key equals `key`.  out[2*b] = num, out[2*b+1] =
 // den; den = 0 means none.
-__global__ __launch_bounds__(kThreads) void k_sel_min(const int32_t* __restrict__ src,
-                                                      const int32_t* __restrict__ adj,
-                                                      const int32_t* __restrict__ deg,
+__global__ __launch_bounds__(kThreads) void k_sel_min(const int32_t* __restrict__ dsum,
                                                       const int32_t* __restrict__ t, int64_t m,
                                                       int measure, uint32_t key, int64_t lb_num,
                                                       int64_t lb_den, int lb_valid,
@@ -87,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_min(const int32_t* __restrict_
     int64_t bn = 0, bd = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const Sim s = sim_of(src, adj, deg, t, e, measure);
+        const Sim s = sim_of(dsum, t, e, measure);
         if (!s.nonzero || s.key != key) continue;
         if (lb_valid && rat_cmp(s.num, s.den, lb_num, lb_den) <= 0) continue;
         if (bd == 0 || rat_cmp(s.num, s.den, bn, bd) < 0) {
@@ -129,16 +124,14 @@ __global__ __launch_bounds__(kThreads) void k_sel_min_final(int64_t* __restrict_
     out[1] = bd;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sel_count_eq(const int32_t* __restrict__ src,
-                                                           const int32_t* __restrict__ adj,
-                                                           const int32_t* __restrict__ deg,
+__global__ __launch_bounds__(kThreads) void k_sel_count_eq(const int32_t* __restrict__ dsum,
                                                            const int32_t* __restrict__ t, int64_t m,
                                                            int measure, uint32_t key, int64_t num,
                                                            int64_t den, unsigned long long* __restrict__ cnt) {
     unsigned long long c = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const Sim s = sim_of(src, adj, deg, t, e, measure);
+        const Sim s = sim_of(dsum, t, e, measure);
         if (s.nonzero && s.key == key && rat_cmp(s.num, s.den, num, den) == 0) ++c;
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
@@ -157,14 +150,14 @@ void sel_hist(const mcd_graph* g, int measure, const int32_t* t, uint32_t prefix
               int shift, int64_t* hist256, hipStream_t s) {
     fill_i64(hist256, 256, 0, s);
     if (g->m <= 0) return;
-    hipLaunchKernelGGL(k_sel_hist, dim3(grid_for(g->m, kSelBlocks)), dim3(kThreads), 0, s, g->src, g->adj,
-                       g->deg, t, g->m, measure, prefix, pmask, shift, (unsigned long long*)hist256);
+    hipLaunchKernelGGL(k_sel_hist, dim3(grid_for(g->m, kSelBlocks)), dim3(kThreads), 0, s, g->dsum, t, g->m, measure,
+                       prefix, pmask, shift, (unsigned long long*)hist256);
 }
 
 void sel_min_above(const mcd_graph* g, int measure, const int32_t* t, uint32_t key, int64_t lb_num,
                    int64_t lb_den, int lb_valid, int64_t* part, int64_t* out2, hipStream_t s) {
     const unsigned nb = grid_for(g->m, kSelBlocks);
-    hipLaunchKernelGGL(k_sel_min, dim3(nb), dim3(kThreads), 0, s, g->src, g->adj, g->deg, t, g->m, measure,
+    hipLaunchKernelGGL(k_sel_min, dim3(nb), dim3(kThreads), 0, s, g->dsum, t, g->m, measure,
                        key, lb_num, lb_den, lb_valid, part);
     hipLaunchKernelGGL(k_sel_min_final, dim3(1), dim3(64), 0, s, part, (int)nb, out2);
 }
@@ -172,8 +165,8 @@ void sel_min_above(const mcd_graph* g, int measure, const int32_t* t, uint32_t k
 void sel_count_eq(const mcd_graph* g, int measure, const int32_t* t, uint32_t key, int64_t num,
                   int64_t den, int64_t* cnt, hipStream_t s) {
     fill_i64(cnt, 1, 0, s);
-    hipLaunchKernelGGL(k_sel_count_eq, dim3(grid_for(g->m, kSelBlocks)), dim3(kThreads), 0, s, g->src,
-                       g->adj, g->deg, t, g->m, measure, key, num, den, (unsigned long long*)cnt);
+    hipLaunchKernelGGL(k_sel_count_eq, dim3(grid_for(g->m, kSelBlocks)), dim3(kThreads), 0, s, g->dsum, t, g->m,
+                       measure, key, num, den, (unsigned long long*)cnt);
 }
 
 }  // namespace mcd

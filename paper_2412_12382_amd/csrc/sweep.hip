@@ -6,8 +6,13 @@
 // survives) decides all K prune masks at once: kept at threshold i iff
 // level > i.  Walking i from K-1 down to 0 only ever adds edges, so one
 // union-find absorbs each level's edges in turn; after each level the
-// partition is exactly the components of the edges kept at threshold i (hooks
-// still go toward the smaller original id, so roots are canonical labels).
+// partition is exactly the components of the edges kept at threshold i.  Roots
+// hook under the higher-ranked root (as in the components step); a threshold
+// whose labels are asked for gets the smallest original id per root.
+//
+// Per-graph sums and the sizes of large components are accumulated per block
+// in LDS before one global atomic per block: with one graph (or one giant
+// component) a global atomic per wave would serialise on a single address.
 //
 // ARI (Hubert & Arabie) per graph and threshold from exact pair counts:
 //   S = sum over (cluster, class) cells of C(n_cc, 2)
@@ -66,14 +71,72 @@ __device__ __forceinline__ void agg_max(unsigned long long* acc, int64_t key, un
     if (!same && val) atomicMax(&acc[key], val);
 }
 
+constexpr int kLdsGraphs = 1024;  // per-graph accumulators held in LDS up to this many graphs
+constexpr int kRootSlots = 1024;  // LDS table of component roots per block (power of two)
+
+// Per-graph accumulator of a block: LDS when the graphs fit, else global.
+struct GraphAcc {
+    unsigned long long* lds;   // [G] in LDS, or nullptr
+    unsigned long long* glob;  // [G] in global memory
+    int G;
+    __device__ void init() {
+        if (lds)
+            for (int i = threadIdx.x; i < G; i += blockDim.x) lds[i] = 0ull;
+    }
+    __device__ void add(int64_t key, unsigned long long val) {
+        if (lds) agg_add(lds, key, val);
+        else agg_add(glob, key, val);
+    }
+    __device__ void max(int64_t key, unsigned long long val) {
+        if (lds) agg_max(lds, key, val);
+        else agg_max(glob, key, val);
+    }
+    // after a barrier
+    __device__ void flush_add() {
+        if (lds)
+            for (int i = threadIdx.x; i < G; i += blockDim.x)
+                if (lds[i]) atomicAdd(&glob[i], lds[i]);
+    }
+    __device__ void flush_max() {
+        if (lds)
+            for (int i = threadIdx.x; i < G; i += blockDim.x)
+                if (lds[i]) atomicMax(&glob[i], lds[i]);
+    }
+};
+
+// LDS table root -> count; false when the probe sequence is full.
+__device__ __forceinline__ bool root_table_add(int32_t* key, uint32_t* val, int32_t r, uint32_t c) {
+    uint32_t h = ((uint32_t)r * 2654435761u) >> 22;  // 10 bits: kRootSlots
+    for (int probe = 0; probe < 8; ++probe) {
+        const int32_t k = atomicCAS(&key[h], -1, r);
+        if (k == -1 || k == r) {
+            atomicAdd(&val[h], c);
+            return true;
+        }
+        h = (h + 1) & (kRootSlots - 1);
+    }
+    return false;
+}
+
 // level[e] = number of sorted thresholds delta_i with NOT (sim(e) < delta_i)
+// and hist[g][level] (edge counts): with one graph the lanes of a wave that
+// share a level are counted with one ballot, else an LDS histogram of
+// (graph, level) when it fits.
 __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ src,
-                                                    const int32_t* __restrict__ adj,
-                                                    const int32_t* __restrict__ deg,
+                                                    const int32_t* __restrict__ dsum,
                                                     const int32_t* __restrict__ t, int64_t m, int measure,
-                                                    SweepDeltas ds, uint8_t* __restrict__ level) {
+                                                    SweepDeltas ds, uint8_t* __restrict__ level,
+                                                    const int32_t* __restrict__ gid, int G,
+                                                    unsigned long long* __restrict__ hist) {
+    __shared__ uint32_t h[8192];
+    const int nbins = G * (ds.K + 1);
+    const bool local = nbins <= 8192;
+    const int lane = threadIdx.x & 63;
+    if (local)
+        for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
+    __syncthreads();
     GRID_STRIDE(e, m) {
-        const int64_t D = (int64_t)deg[src[e]] + deg[adj[e]];
+        const int64_t D = (uint32_t)dsum[e];
         const int64_t tt = t[e];
         const int64_t num = measure == MCD_SIM_TECTONIC ? tt : 3 * tt - D + 2;
         const int64_t den = measure == MCD_SIM_TECTONIC ? D : 1;
@@ -84,7 +147,25 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
             else hi = mid;
         }
         level[e] = (uint8_t)lo;
+        if (G == 1) {
+            uint64_t pending = __ballot(true);
+            while (pending) {  // once per distinct level in the wave
+                const int first = __ffsll((long long)pending) - 1;
+                const int l0 = __shfl(lo, first);
+                const uint64_t same = __ballot(lo == l0) & pending;
+                if (lane == first) atomicAdd(&h[l0], (uint32_t)__popcll(same));
+                pending &= ~same;
+            }
+        } else {
+            const int64_t key = (int64_t)gid[src[e]] * (ds.K + 1) + lo;
+            if (local) atomicAdd(&h[key], 1u);
+            else atomicAdd(&hist[key], 1ull);
+        }
     }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+            if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
 // graph id and class of every rank-numbered vertex
@@ -103,27 +184,6 @@ __global__ __launch_bounds__(kThreads) void k_vertex_info(const int32_t* __restr
         gid[v] = lo;
         if (truth) cls[v] = truth[x];
     }
-}
-
-// per-graph count of edges at each level; an LDS histogram when it fits
-__global__ __launch_bounds__(kThreads) void k_level_hist(const int32_t* __restrict__ src,
-                                                         const uint8_t* __restrict__ level, int64_t m,
-                                                         const int32_t* __restrict__ gid, int K, int nbins,
-                                                         unsigned long long* __restrict__ hist) {
-    __shared__ uint32_t h[8192];
-    const bool local = nbins <= 8192;
-    if (local)
-        for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    GRID_STRIDE(e, m) {
-        const int64_t key = (int64_t)gid[src[e]] * (K + 1) + level[e];
-        if (local) atomicAdd(&h[key], 1u);
-        else atomicAdd(&hist[key], 1ull);
-    }
-    __syncthreads();
-    if (local)
-        for (int i = threadIdx.x; i < nbins; i += blockDim.x)
-            if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
 __device__ __forceinline__ int32_t ld_parent(const int32_t* p) {
@@ -152,8 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_init_parent(int32_t* __restrict__ 
 __global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restrict__ src,
                                                           const int32_t* __restrict__ adj,
                                                           const uint8_t* __restrict__ level, int64_t m,
-                                                          int lv, const int32_t* __restrict__ perm,
-                                                          int32_t* parent) {
+                                                          int lv, int32_t* parent) {
     GRID_STRIDE(e, m) {
         if (level[e] != lv) continue;
         int32_t a = src[e], b = adj[e];
@@ -161,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restr
             a = find_root(parent, a);
             b = find_root(parent, b);
             if (a == b) break;
-            if (perm[a] < perm[b]) {
+            if (a > b) {  // hook the lower-ranked root a under b
                 const int32_t x = a;
                 a = b;
                 b = x;
@@ -175,27 +234,64 @@ __global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restr
 }
 
 // Pass 1 over vertices: compress to the root, count roots per graph, size of
-// every component, optional labels of this threshold.
+// every component.
 __global__ __launch_bounds__(kThreads) void k_pass_size(int32_t* parent, int64_t n,
-                                                        const int32_t* __restrict__ gid,
-                                                        const int32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ gid, int G,
                                                         int32_t* __restrict__ size,
-                                                        unsigned long long* __restrict__ ncc,
-                                                        int32_t* __restrict__ labels) {
+                                                        unsigned long long* __restrict__ ncc) {
+    __shared__ unsigned long long gl[kLdsGraphs];
+    __shared__ int32_t rk[kRootSlots];
+    __shared__ uint32_t rv[kRootSlots];
+    GraphAcc acc{G <= kLdsGraphs ? gl : nullptr, ncc, G};
+    acc.init();
+    for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x) {
+        rk[i] = -1;
+        rv[i] = 0u;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     GRID_STRIDE(v, n) {
         const int32_t r = find_root(parent, (int32_t)v);
         st_parent(&parent[v], r);
-        agg_add(ncc, gid[v], r == (int32_t)v ? 1ull : 0ull);
-        if (labels) labels[perm[v]] = perm[r];
+        const bool root = r == (int32_t)v;
+        acc.add(gid[v], root ? 1ull : 0ull);
+        // size[r] += 1, first summed over the lanes sharing lane 0's root;
+        // roots shared by several lanes go through the LDS table
         const int32_t r0 = __shfl(r, 0);
         const uint64_t same = __ballot(r == r0);
         if (r == r0) {
-            if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&size[r], (int32_t)__popcll(same));
-        } else {
+            if (lane == 0) {
+                const uint32_t c = (uint32_t)__popcll(same);
+                if ((c == 1 && root) || !root_table_add(rk, rv, r0, c)) atomicAdd(&size[r0], (int32_t)c);
+            }
+        } else if (root || !root_table_add(rk, rv, r, 1u)) {
             atomicAdd(&size[r], 1);
         }
     }
+    __syncthreads();
+    acc.flush_add();
+    for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x)
+        if (rk[i] >= 0) atomicAdd(&size[rk[i]], (int32_t)rv[i]);
+}
+
+// Labels of one threshold: the smallest original id of every component.
+__global__ __launch_bounds__(kThreads) void k_label_init(const int32_t* __restrict__ perm, int64_t n,
+                                                         int32_t* __restrict__ minid) {
+    GRID_STRIDE(v, n) minid[v] = perm[v];
+}
+
+__global__ __launch_bounds__(kThreads) void k_label_min(int32_t* parent, const int32_t* __restrict__ perm, int64_t n,
+                                                        int32_t* __restrict__ minid) {
+    GRID_STRIDE(v, n) {
+        const int32_t r = find_root(parent, (int32_t)v);
+        if (r != (int32_t)v) atomicMin(&minid[r], perm[v]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_label_write(int32_t* parent, const int32_t* __restrict__ perm,
+                                                          int64_t n, const int32_t* __restrict__ minid,
+                                                          int32_t* __restrict__ labels) {
+    GRID_STRIDE(v, n) labels[perm[v]] = minid[find_root(parent, (int32_t)v)];
 }
 
 __device__ __forceinline__ uint64_t cell_key(int32_t r, int32_t c) {
@@ -206,14 +302,33 @@ __device__ __forceinline__ uint32_t cell_slot(uint64_t k, int log2cap) {
     return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
 }
 
-// Pass 2: A (same cluster pairs) and the largest component per graph; with
-// labels, count every (cluster, class) cell in a hash table.
-__global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_t n,
-                                                         const int32_t* __restrict__ gid,
+// Pass 2: A (same cluster pairs) and the largest component per graph, read
+// off the component sizes: after pass 1 only roots hold a nonzero size, and
+// a root's graph is its own.  Streams size[] and gid[] once.
+__global__ __launch_bounds__(kThreads) void k_pass_roots(int64_t n, const int32_t* __restrict__ gid, int G,
                                                          const int32_t* __restrict__ size,
-                                                         const int32_t* __restrict__ cls,
                                                          unsigned long long* __restrict__ acc_a,
-                                                         unsigned long long* __restrict__ largest,
+                                                         unsigned long long* __restrict__ largest) {
+    __shared__ unsigned long long la[kLdsGraphs], ll[kLdsGraphs];
+    const bool lds = G <= kLdsGraphs;
+    GraphAcc A{lds ? la : nullptr, acc_a, G}, Lg{lds ? ll : nullptr, largest, G};
+    A.init();
+    Lg.init();
+    __syncthreads();
+    GRID_STRIDE(v, n) {
+        const int32_t sz = size[v];
+        const int32_t g = gid[v];
+        A.add(g, (unsigned long long)sz * (unsigned long long)(sz > 0 ? sz - 1 : 0));
+        Lg.max(g, (unsigned long long)sz);
+    }
+    __syncthreads();
+    A.flush_add();
+    Lg.flush_max();
+}
+
+// Pass 2b (with labels): count every (cluster, class) cell in a hash table.
+__global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_t n,
+                                                         const int32_t* __restrict__ cls,
                                                          unsigned long long* __restrict__ keys,
                                                          int32_t* __restrict__ counts, int log2cap) {
     const int lane = threadIdx.x & 63;
@@ -221,44 +336,44 @@ __global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_
         // pass 1 compressed the paths, but a concurrent halving may have left
         // parent[v] at an ancestor below the root: always follow to the root
         const int32_t r = find_root(parent, (int32_t)v);
-        const int32_t g = gid[v];
-        const int32_t sz = size[r];
-        agg_add(acc_a, g, (unsigned long long)(sz - 1));
-        agg_max(largest, g, r == (int32_t)v ? (unsigned long long)sz : 0ull);
-        if (cls) {
-            const uint64_t k = cell_key(r, cls[v]);
-            const uint32_t mask = (1u << log2cap) - 1u;
-            uint32_t h = cell_slot(k, log2cap);
-            for (;;) {
-                const unsigned long long prev = atomicCAS(&keys[h], ~0ull, (unsigned long long)k);
-                if (prev == ~0ull || prev == k) break;
-                h = (h + 1) & mask;
-            }
-            const uint64_t k0 = __shfl(k, 0);
-            const uint64_t same = __ballot(k == k0);
-            if (k == k0) {
-                if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&counts[h], (int32_t)__popcll(same));
-            } else {
-                atomicAdd(&counts[h], 1);
-            }
+        const uint64_t k = cell_key(r, cls[v]);
+        const uint32_t mask = (1u << log2cap) - 1u;
+        uint32_t h = cell_slot(k, log2cap);
+        for (;;) {
+            const unsigned long long prev = atomicCAS(&keys[h], ~0ull, (unsigned long long)k);
+            if (prev == ~0ull || prev == k) break;
+            h = (h + 1) & mask;
+        }
+        const uint64_t k0 = __shfl(k, 0);
+        const uint64_t same = __ballot(k == k0);
+        if (k == k0) {
+            if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&counts[h], (int32_t)__popcll(same));
+        } else {
+            atomicAdd(&counts[h], 1);
         }
     }
 }
 
 // Pass 3: S (pairs sharing cluster and class) per graph.
 __global__ __launch_bounds__(kThreads) void k_pass_s(int32_t* parent, int64_t n,
-                                                     const int32_t* __restrict__ gid,
+                                                     const int32_t* __restrict__ gid, int G,
                                                      const int32_t* __restrict__ cls,
                                                      const unsigned long long* __restrict__ keys,
                                                      const int32_t* __restrict__ counts, int log2cap,
                                                      unsigned long long* __restrict__ acc_s) {
+    __shared__ unsigned long long ls[kLdsGraphs];
+    GraphAcc S{G <= kLdsGraphs ? ls : nullptr, acc_s, G};
+    S.init();
+    __syncthreads();
     GRID_STRIDE(v, n) {
         const uint64_t k = cell_key(find_root(parent, (int32_t)v), cls[v]);
         const uint32_t mask = (1u << log2cap) - 1u;
         uint32_t h = cell_slot(k, log2cap);
         while (keys[h] != k) h = (h + 1) & mask;
-        agg_add(acc_s, gid[v], (unsigned long long)(counts[h] - 1));
+        S.add(gid[v], (unsigned long long)(counts[h] - 1));
     }
+    __syncthreads();
+    S.flush_add();
 }
 
 // class sizes (truth ids lie in [0, n)), then B per graph
@@ -278,10 +393,16 @@ __global__ __launch_bounds__(kThreads) void k_class_size(const int32_t* __restri
 }
 
 __global__ __launch_bounds__(kThreads) void k_class_b(const int32_t* __restrict__ cls, int64_t n,
-                                                      const int32_t* __restrict__ gid,
+                                                      const int32_t* __restrict__ gid, int G,
                                                       const int32_t* __restrict__ csize,
                                                       unsigned long long* __restrict__ acc_b) {
-    GRID_STRIDE(v, n) agg_add(acc_b, gid[v], (unsigned long long)(csize[cls[v]] - 1));
+    __shared__ unsigned long long lb[kLdsGraphs];
+    GraphAcc B{G <= kLdsGraphs ? lb : nullptr, acc_b, G};
+    B.init();
+    __syncthreads();
+    GRID_STRIDE(v, n) B.add(gid[v], (unsigned long long)(csize[cls[v]] - 1));
+    __syncthreads();
+    B.flush_add();
 }
 
 // Writes the statistics of threshold slot `out_i` for every graph.
@@ -345,6 +466,7 @@ struct SweepLayout {
     int32_t* gid;
     int32_t* cls;
     int32_t* size;
+    int32_t* minid;
     int32_t* csize;
     unsigned long long* keys;
     int32_t* counts;
@@ -365,6 +487,7 @@ SweepLayout sweep_layout(void* p, const mcd_graph* g, int G, int K, bool truth) 
     L.parent = c.take<int32_t>((size_t)n);
     L.gid = c.take<int32_t>((size_t)n);
     L.size = c.take<int32_t>((size_t)n);
+    L.minid = c.take<int32_t>((size_t)n);
     L.cls = truth ? c.take<int32_t>((size_t)n) : nullptr;
     L.csize = truth ? c.take<int32_t>((size_t)n) : nullptr;
     const int64_t cap = truth ? ((int64_t)1 << cells_log2(n)) : 0;
@@ -400,22 +523,20 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
         hipLaunchKernelGGL(k_vertex_info, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->perm, n, vbase, G,
                            truth, L.gid, L.cls);
     if (m > 0) {
-        hipLaunchKernelGGL(k_level, dim3(grid_for(m, 16384)), dim3(kThreads), 0, s, g->src, g->adj, g->deg, t, m,
-                           measure, ds, L.level);
-        hipLaunchKernelGGL(k_level_hist, dim3(grid_for(m, 4096)), dim3(kThreads), 0, s, g->src, L.level, m,
-                           L.gid, K, G * (K + 1), L.hist);
+        hipLaunchKernelGGL(k_level, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->dsum, t, m,
+                           measure, ds, L.level, L.gid, G, L.hist);
     }
     if (truth && n > 0) {
         fill_t<int32_t>(L.csize, n, 0, s);
         hipLaunchKernelGGL(k_class_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.csize);
-        hipLaunchKernelGGL(k_class_b, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.gid, L.csize,
-                           L.acc_b);
+        hipLaunchKernelGGL(k_class_b, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.gid, G,
+                           L.csize, L.acc_b);
     }
     if (n > 0) hipLaunchKernelGGL(k_init_parent, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n);
     for (int i = K - 1; i >= 0; --i) {
         if (m > 0)
             hipLaunchKernelGGL(k_union_level, dim3(grid_for(m, 16384)), dim3(kThreads), 0, s, g->src, g->adj,
-                               L.level, m, i + 1, g->perm, L.parent);
+                               L.level, m, i + 1, L.parent);
         fill_t<unsigned long long>(L.ncc, G, 0ull, s);
         fill_t<unsigned long long>(L.largest, G, 0ull, s);
         fill_t<unsigned long long>(L.acc_a, G, 0ull, s);
@@ -423,17 +544,28 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
         fill_t<int32_t>(L.size, n, 0, s);
         int32_t* lab = labels ? labels + (int64_t)out_index[i] * n : nullptr;
         if (n > 0) {
-            hipLaunchKernelGGL(k_pass_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid,
-                               g->perm, L.size, L.ncc, lab);
+            hipLaunchKernelGGL(k_pass_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid, G,
+                               L.size, L.ncc);
+            if (lab) {
+                hipLaunchKernelGGL(k_label_init, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->perm, n,
+                                   L.minid);
+                hipLaunchKernelGGL(k_label_min, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, g->perm,
+                                   n, L.minid);
+                hipLaunchKernelGGL(k_label_write, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent,
+                                   g->perm, n, L.minid, lab);
+            }
             if (truth) {
                 fill_t<unsigned long long>(L.keys, cap, ~0ull, s);
                 fill_t<int32_t>(L.counts, cap, 0, s);
             }
-            hipLaunchKernelGGL(k_pass_cells, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid,
-                               L.size, L.cls, L.acc_a, L.largest, L.keys, L.counts, l2);
-            if (truth)
-                hipLaunchKernelGGL(k_pass_s, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid,
+            hipLaunchKernelGGL(k_pass_roots, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, n, L.gid, G, L.size,
+                               L.acc_a, L.largest);
+            if (truth) {
+                hipLaunchKernelGGL(k_pass_cells, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n,
+                                   L.cls, L.keys, L.counts, l2);
+                hipLaunchKernelGGL(k_pass_s, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid, G,
                                    L.cls, L.keys, L.counts, l2, L.acc_s);
+            }
         }
         hipLaunchKernelGGL(k_write_stats, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), 0, s, G, K, i,
                            out_index[i], L.hist, L.ncc, L.largest, L.acc_a, L.acc_s, L.acc_b, vbase,

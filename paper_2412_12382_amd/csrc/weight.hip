@@ -4,81 +4,13 @@
 // form is t - wedge with |N(u) u N(v)| = deg u + deg v - t (Eq. eq:tw and the
 // notation paragraph of Sec. 1).  The keep decision never uses floating point:
 // with delta = num/den (den > 0), Tectonic keeps iff t*den >= num*D and TW
-// keeps iff TW*den >= num, evaluated in int64.
+// keeps iff TW*den >= num, evaluated in 128-bit integers.
 #include "common.hpp"
 
 namespace mcd {
 namespace {
 
 constexpr int kThreads = 256;
-
-inline unsigned grid_for(int64_t N, int64_t cap) {
-    int64_t b = (N + kThreads - 1) / kThreads;
-    if (b < 1) b = 1;
-    if (b > cap) b = cap;
-    return (unsigned)b;
-}
-
-__global__ __launch_bounds__(kThreads) void k_weights(const int32_t* __restrict__ src,
-                                                      const int32_t* __restrict__ adj,
-                                                      const int32_t* __restrict__ deg,
-                                                      const int32_t* __restrict__ t, int64_t m,
-                                                      int measure, float* __restrict__ wf,
-                                                      int32_t* __restrict__ wi) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t D = deg[src[e]] + deg[adj[e]];
-        const int32_t tt = t[e];
-        if (measure == MCD_SIM_TECTONIC) {
-            if (wf) wf[e] = (float)tt / (float)D;  // IEEE-correct fp32 division
-        } else {
-            const int32_t tw = 3 * tt - D + 2;
-            if (wi) wi[e] = tw;
-            if (wf) wf[e] = (float)tw;
-        }
-    }
-}
-
-// One wave handles 64 consecutive edges at a time; its keep decisions form a
-// 64-bit ballot = two keep words.  Kept counts are reduced per block.
-__global__ __launch_bounds__(kThreads) void k_prune(const int32_t* __restrict__ src,
-                                                    const int32_t* __restrict__ adj,
-                                                    const int32_t* __restrict__ deg,
-                                                    const int32_t* __restrict__ t, int64_t m,
-                                                    int measure, int64_t num, int64_t den,
-                                                    uint32_t* __restrict__ keep,
-                                                    unsigned long long* __restrict__ n_kept) {
-    __shared__ unsigned long long wsum[kThreads / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t nchunks = (m + 63) >> 6;
-    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
-    unsigned long long kept = 0;
-    for (int64_t c = (int64_t)blockIdx.x * (kThreads / 64) + w; c < nchunks; c += waves) {
-        const int64_t e = (c << 6) + lane;
-        bool k = false;
-        if (e < m) {
-            const int64_t D = (int64_t)deg[src[e]] + deg[adj[e]];
-            const int64_t tt = t[e];
-            if (measure == MCD_SIM_TECTONIC) k = tt * den >= num * D;
-            else k = (3 * tt - D + 2) * den >= num;
-        }
-        const uint64_t bal = __ballot(k);
-        if (lane == 0) {
-            keep[c * 2] = (uint32_t)bal;
-            kept += (unsigned long long)__popcll(bal);
-        } else if (lane == 1 && (c << 6) + 32 < m) {
-            keep[c * 2 + 1] = (uint32_t)(bal >> 32);
-        }
-    }
-    if (!n_kept) return;
-    if (lane == 0) wsum[w] = kept;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long s = 0;
-        for (int i = 0; i < kThreads / 64; ++i) s += wsum[i];
-        if (s) atomicAdd(n_kept, s);
-    }
-}
 
 __device__ __forceinline__ int graph_of(const int64_t* __restrict__ vbase, int G, int64_t x) {
     int lo = 0, hi = G;
@@ -90,45 +22,105 @@ __device__ __forceinline__ int graph_of(const int64_t* __restrict__ vbase, int G
     return lo;
 }
 
-// Algorithm 1's removal rule with a per-graph threshold read from device
-// memory (deltas[2g] / deltas[2g+1]); compared exactly in 128-bit integers.
-__global__ __launch_bounds__(kThreads) void k_prune_graphs(const int32_t* __restrict__ src,
-                                                           const int32_t* __restrict__ adj,
-                                                           const int32_t* __restrict__ deg,
-                                                           const int32_t* __restrict__ perm,
-                                                           const int32_t* __restrict__ t, int64_t m,
-                                                           int measure, int G, const int64_t* __restrict__ vbase,
-                                                           const int64_t* __restrict__ deltas,
-                                                           uint32_t* __restrict__ keep,
-                                                           unsigned long long* __restrict__ n_kept) {
+// Tectonic in fp32, correctly rounded: a single fp32 division is exact-input
+// and correctly rounded while both operands fit 24 bits; beyond that the
+// quotient is formed in fp64 and rounded once more, which is innocuous for a
+// single division (53 >= 2 * 24 + 2).
+__device__ __forceinline__ float tectonic_f32(int32_t t, int64_t D) {
+    if (t < (1 << 24) && D < (1 << 24)) return (float)t / (float)D;
+    return (float)((double)t / (double)D);
+}
+
+constexpr int kUnroll = 8;  // 64-edge groups in flight per wave
+
+// The exact keep test sn / sd >= num / den (sd, den > 0).  64-bit products
+// suffice when |sn| < 2^31, sd < 2^32 and |num|, den < 2^31 (NARROW, which
+// the host establishes from the maximum degree and a validated threshold);
+// otherwise 128-bit products are used.
+template <bool NARROW>
+__device__ __forceinline__ bool keep_test(int64_t sn, int64_t sd, int64_t num, int64_t den) {
+    if (NARROW) return sn * den >= num * sd;
+    return (__int128)sn * den >= (__int128)num * sd;
+}
+
+// One pass of weights + prune.  Wave `seg` owns edges [seg L, seg L + L),
+// L a multiple of 64, in groups of 64 (one edge per lane); a group's keep
+// decisions form one 64-bit ballot = two keep words, and its kept edges are
+// appended, in edge order, at the wave's running count inside the wave's own
+// run of the kept-pair array, so the compaction needs no atomics.  The
+// degree sum deg u + deg v of every edge comes from the graph (dsum), so the
+// pass streams its inputs.
+template <int MEASURE, bool MULTI, bool NARROW>
+__global__ __launch_bounds__(kThreads) void k_weigh_prune(
+    const int32_t* __restrict__ src, const int32_t* __restrict__ adj, const int32_t* __restrict__ dsum,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ t, int64_t m, int64_t seg_len, int G,
+    const int64_t* __restrict__ vbase, const int64_t* __restrict__ deltas, int64_t num0, int64_t den0,
+    float* __restrict__ wf, int32_t* __restrict__ wi, uint32_t* __restrict__ keep, int2* __restrict__ kept,
+    int32_t* __restrict__ kept_counts, unsigned long long* __restrict__ n_kept) {
     __shared__ unsigned long long wsum[kThreads / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t nchunks = (m + 63) >> 6;
-    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
-    unsigned long long kept = 0;
-    for (int64_t c = (int64_t)blockIdx.x * (kThreads / 64) + w; c < nchunks; c += waves) {
-        const int64_t e = (c << 6) + lane;
-        bool k = false;
-        if (e < m) {
-            const int32_t u = src[e];
-            const int64_t D = (int64_t)deg[u] + deg[adj[e]];
-            const int64_t tt = t[e];
-            const int g = G == 1 ? 0 : graph_of(vbase, G, perm[u]);
-            const int64_t num = deltas[2 * g], den = deltas[2 * g + 1];
-            const int64_t sn = measure == MCD_SIM_TECTONIC ? tt : 3 * tt - D + 2;
-            const int64_t sd = measure == MCD_SIM_TECTONIC ? D : 1;
-            k = (__int128)sn * den >= (__int128)num * sd;
+    const int64_t seg = (int64_t)blockIdx.x * (kThreads / 64) + w;
+    const int64_t e0 = seg * seg_len;
+    const int64_t e1 = e0 + seg_len < m ? e0 + seg_len : m;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const bool need_uv = kept != nullptr || MULTI;
+    int64_t cnt = 0;
+    for (int64_t c = e0; c < e1; c += 64 * kUnroll) {
+        int32_t u[kUnroll], v[kUnroll], tt[kUnroll], dd[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int64_t e = c + 64 * j + lane;
+            u[j] = v[j] = tt[j] = 0;
+            dd[j] = 1;
+            if (e < e1) {
+                tt[j] = t[e];
+                dd[j] = dsum[e];
+                if (need_uv) {
+                    u[j] = src[e];
+                    v[j] = adj[e];
+                }
+            }
         }
-        const uint64_t bal = __ballot(k);
-        if (lane == 0) {
-            keep[c * 2] = (uint32_t)bal;
-            kept += (unsigned long long)__popcll(bal);
-        } else if (lane == 1 && (c << 6) + 32 < m) {
-            keep[c * 2 + 1] = (uint32_t)(bal >> 32);
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const int64_t cj = c + 64 * j;
+            if (cj >= e1) break;  // wave-uniform
+            const int64_t e = cj + lane;
+            bool k = false;
+            if (e < e1) {
+                const int64_t D = (uint32_t)dd[j];  // deg u + deg v < 2^32
+                int64_t sn, sd;
+                if (MEASURE == MCD_SIM_TECTONIC) {
+                    if (wf) wf[e] = tectonic_f32(tt[j], D);
+                    sn = tt[j];
+                    sd = D;
+                } else {
+                    sn = 3 * (int64_t)tt[j] - D + 2;
+                    sd = 1;
+                    if (wi) wi[e] = (int32_t)sn;
+                    if (wf) wf[e] = (float)sn;
+                }
+                if (MULTI) {
+                    const int g = G == 1 ? 0 : graph_of(vbase, G, perm[u[j]]);
+                    const int64_t num = deltas[2 * g], den = deltas[2 * g + 1];
+                    const bool small = num > -(1ll << 31) && num < (1ll << 31) && den < (1ll << 31);
+                    k = small ? keep_test<NARROW>(sn, sd, num, den) : keep_test<false>(sn, sd, num, den);
+                } else {
+                    k = keep_test<NARROW>(sn, sd, num0, den0);
+                }
+            }
+            const uint64_t bal = __ballot(k);
+            if (keep) {
+                if (lane == 0) keep[cj >> 5] = (uint32_t)bal;
+                else if (lane == 1 && cj + 32 < m) keep[(cj >> 5) + 1] = (uint32_t)(bal >> 32);
+            }
+            if (kept && k) kept[e0 + cnt + __popcll(bal & below)] = make_int2(u[j], v[j]);
+            cnt += __popcll(bal);
         }
     }
+    if (kept_counts && lane == 0) kept_counts[seg] = (int32_t)cnt;
     if (!n_kept) return;
-    if (lane == 0) wsum[w] = kept;
+    if (lane == 0) wsum[w] = (unsigned long long)cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long s = 0;
@@ -139,27 +131,58 @@ __global__ __launch_bounds__(kThreads) void k_prune_graphs(const int32_t* __rest
 
 }  // namespace
 
+int64_t kept_segment_len(int64_t m) {
+    const int64_t groups = (m + 63) / 64;
+    return 64 * ((groups + MCD_KEPT_SEGMENTS - 1) / MCD_KEPT_SEGMENTS);
+}
+
+void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den, int G,
+                        const int64_t* vbase, const int64_t* deltas, float* wf, int32_t* wi, uint32_t* keep_bits,
+                        int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s) {
+    if (n_kept) fill_i64(n_kept, 1, 0, s);
+    if (g->m <= 0 && !kept_counts) return;
+    const int64_t L = kept_segment_len(g->m);
+    const dim3 grid(MCD_KEPT_SEGMENTS / (kThreads / 64)), block(kThreads);
+    const bool multi = deltas != nullptr;
+    // |TW| < 2^31 and deg u + deg v < 2^30 whenever every degree is below 2^29;
+    // host thresholds are validated to |num|, den < 2^31
+    const bool narrow = g->max_deg < (1 << 29);
+    int2* kp = (int2*)kept_pairs;
+    unsigned long long* nk = (unsigned long long*)n_kept;
+#define MCD_WP_ARGS                                                                                          \
+    g->src, g->adj, g->dsum, g->perm, t, g->m, L, G, vbase, deltas, num, den, wf, wi, keep_bits, kp, kept_counts, \
+        nk
+#define MCD_WP_LAUNCH(MEAS, MULTI)                                                                             \
+    do {                                                                                                   \
+        if (narrow) hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, true>), grid, block, 0, s, MCD_WP_ARGS);  \
+        else hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, false>), grid, block, 0, s, MCD_WP_ARGS);       \
+    } while (0)
+    if (measure == MCD_SIM_TECTONIC) {
+        if (multi) MCD_WP_LAUNCH(MCD_SIM_TECTONIC, true);
+        else MCD_WP_LAUNCH(MCD_SIM_TECTONIC, false);
+    } else {
+        if (multi) MCD_WP_LAUNCH(MCD_SIM_TW, true);
+        else MCD_WP_LAUNCH(MCD_SIM_TW, false);
+    }
+#undef MCD_WP_LAUNCH
+#undef MCD_WP_ARGS
+}
+
 void launch_prune_graphs(const mcd_graph* g, int measure, const int32_t* t, int G, const int64_t* vbase,
                          const int64_t* deltas, uint32_t* keep_bits, int64_t* n_kept, hipStream_t s) {
-    if (n_kept) fill_i64(n_kept, 1, 0, s);
-    if (g->m <= 0) return;
-    hipLaunchKernelGGL(k_prune_graphs, dim3(grid_for(g->m, 4096)), dim3(kThreads), 0, s, g->src, g->adj, g->deg,
-                       g->perm, t, g->m, measure, G, vbase, deltas, keep_bits, (unsigned long long*)n_kept);
+    launch_weigh_prune(g, measure, t, 0, 1, G, vbase, deltas, nullptr, nullptr, keep_bits, nullptr, nullptr,
+                       n_kept, s);
 }
 
 void launch_weights(const mcd_graph* g, int measure, const int32_t* t, float* wf, int32_t* wi,
                     hipStream_t s) {
-    if (g->m <= 0) return;
-    hipLaunchKernelGGL(k_weights, dim3(grid_for(g->m, 1 << 16)), dim3(kThreads), 0, s, g->src, g->adj,
-                       g->deg, t, g->m, measure, wf, wi);
+    launch_weigh_prune(g, measure, t, 0, 1, 1, nullptr, nullptr, wf, wi, nullptr, nullptr, nullptr, nullptr, s);
 }
 
 void launch_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den,
                   uint32_t* keep_bits, int64_t* n_kept, hipStream_t s) {
-    if (n_kept) fill_i64(n_kept, 1, 0, s);
-    if (g->m <= 0) return;
-    hipLaunchKernelGGL(k_prune, dim3(grid_for(g->m, 4096)), dim3(kThreads), 0, s, g->src, g->adj, g->deg,
-                       t, g->m, measure, num, den, keep_bits, (unsigned long long*)n_kept);
+    launch_weigh_prune(g, measure, t, num, den, 1, nullptr, nullptr, nullptr, nullptr, keep_bits, nullptr, nullptr,
+                       n_kept, s);
 }
 
 }  // namespace mcd

@@ -67,6 +67,7 @@ def lib():
                                ctypes.POINTER(I32)],
             "mcd_graph_edges": [P, P, P],
             "mcd_graph_degrees": [P, P],
+            "mcd_graph_perm": [P, P],
             "mcd_graph_destroy": [P],
             "mcd_triangles": [P, P, P, SZ],
             "mcd_weights": [P, ctypes.c_int, P, P, P],
@@ -88,6 +89,9 @@ def lib():
             "mcd_grid_select": [P, P, I32, I32, I64, I64, I64, P, P],
             "mcd_sweep_targets": [P, P, I32, I32, ctypes.c_double, P, P],
             "mcd_prune_graphs": [P, ctypes.c_int, P, I32, P, P, P, P],
+            "mcd_weigh_prune": [P, ctypes.c_int, P, mcd_rational, I32, P, P, P, P, P, P, P, P],
+            "mcd_kept_segment_len": [P, ctypes.POINTER(I64)],
+            "mcd_components_kept": [P, P, P, P, P, P, SZ],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
         for name, args in sig.items():
@@ -235,6 +239,12 @@ def mcd_graph_degrees(g: Graph, deg=None):
     deg = _empty(max(g.n, 1), torch.int32, g.ctx.device) if deg is None else deg
     _check(lib().mcd_graph_degrees(g.handle, _p(deg)))
     return deg[:g.n]
+
+
+def mcd_graph_perm(g: Graph, perm=None):
+    perm = _empty(max(g.n, 1), torch.int32, g.ctx.device) if perm is None else perm
+    _check(lib().mcd_graph_perm(g.handle, _p(perm)))
+    return perm[:g.n]
 
 
 # -------------------------------------------------------------------- steps
@@ -431,6 +441,87 @@ def mcd_prune_graphs(g: Graph, measure: int, t, deltas, vbase=None, keep_bits=No
     _check(lib().mcd_prune_graphs(g.handle, measure, _p(t), vb.numel() - 1, _p(vb), _p(deltas), _p(keep_bits),
                                   _p(n_kept)))
     return keep_bits, n_kept
+
+
+KEPT_SEGMENTS = 16384
+
+
+def mcd_kept_segment_len(g: Graph) -> int:
+    v = ctypes.c_int64()
+    _check(lib().mcd_kept_segment_len(g.handle, ctypes.byref(v)))
+    return v.value
+
+
+class KeptList:
+    """Segmented kept-edge list written by mcd_weigh_prune (pairs of internal
+    vertex numbers, int32[2 m], and per-segment counts)."""
+
+    def __init__(self, g: Graph, pairs=None, counts=None):
+        dev = g.ctx.device
+        self.seg_len = mcd_kept_segment_len(g)
+        need = 2 * KEPT_SEGMENTS * self.seg_len
+        if pairs is None:
+            pairs = _empty(max(need, 2), torch.int32, dev)
+        elif pairs.numel() < need:
+            raise ValueError(f"kept_pairs holds {pairs.numel()} int32, needs {need}")
+        self.pairs = pairs
+        self.counts = _empty(KEPT_SEGMENTS, torch.int32, dev) if counts is None else counts
+
+    @staticmethod
+    def capacity(m: int) -> int:
+        """int32 elements of kept_pairs for a graph of m edges."""
+        L = 64 * ((((m + 63) // 64) + KEPT_SEGMENTS - 1) // KEPT_SEGMENTS)
+        return 2 * KEPT_SEGMENTS * L
+
+    def edges(self):
+        """The kept pairs, segment by segment, as an int32 [k, 2] tensor."""
+        cnt = self.counts.cpu().tolist()
+        p = self.pairs.view(-1, 2)
+        parts = [p[s * self.seg_len: s * self.seg_len + c] for s, c in enumerate(cnt) if c]
+        return torch.cat(parts) if parts else p[:0]
+
+    def edge_ids(self, m: int):
+        """Library edge ids in the order the list visits them (runs of
+        seg_len edges, one per segment, in edge order): 0 .. m-1."""
+        import numpy as np
+        return np.arange(m, dtype=np.int64)
+
+
+def mcd_weigh_prune(g: Graph, measure: int, t, delta=None, deltas=None, vbase=None, w_f32=None, w_i32=None,
+                    keep_bits=None, kept=None, n_kept=None, want_f32=True, want_i32=False, want_keep=True,
+                    want_kept=True):
+    """One pass of weights and prune.  delta: a host (num, den), or deltas: a
+    device int64 [G, 2] tensor of per-graph thresholds with vbase."""
+    dev = g.ctx.device
+    if w_f32 is None and want_f32:
+        w_f32 = _empty(max(g.m, 1), torch.float32, dev)
+    if w_i32 is None and want_i32:
+        w_i32 = _empty(max(g.m, 1), torch.int32, dev)
+    if keep_bits is None and want_keep:
+        keep_bits = _empty(max((g.m + 31) // 32, 1), torch.int32, dev)
+    if kept is None and want_kept:
+        kept = KeptList(g)
+    n_kept = _empty(1, torch.int64, dev) if n_kept is None else n_kept
+    if deltas is not None:
+        vb = _vbase(g, vbase)
+        G, vbp, rat = vb.numel() - 1, _p(vb), mcd_rational(0, 1)
+    else:
+        G, vbp, rat = 1, None, _rat(delta)
+    _check(lib().mcd_weigh_prune(g.handle, measure, _p(t), rat, G, vbp, _p(deltas), _p(w_f32), _p(w_i32),
+                                 _p(keep_bits), None if kept is None else _p(kept.pairs),
+                                 None if kept is None else _p(kept.counts), _p(n_kept)))
+    return dict(w_f32=None if w_f32 is None else w_f32[:g.m], w_i32=None if w_i32 is None else w_i32[:g.m],
+                keep_bits=keep_bits, kept=kept, n_kept=n_kept)
+
+
+def mcd_components_kept(g: Graph, kept: KeptList, labels=None, n_components=None, ws=None):
+    labels = _empty(max(g.n, 1), torch.int32, g.ctx.device) if labels is None else labels
+    n_components = _empty(1, torch.int64, g.ctx.device) if n_components is None else n_components
+    if ws is None:
+        ws = _bytes(mcd_components_workspace_size(g), g.ctx.device)
+    _check(lib().mcd_components_kept(g.handle, _p(kept.pairs), _p(kept.counts), _p(labels), _p(n_components),
+                                     _p(ws), ws.numel() * ws.element_size()))
+    return labels[:g.n], n_components
 
 
 def mcd_status_string(status: int) -> str:

@@ -64,6 +64,6 @@ def pick(g, t, picker: Picker, vbase=None, measure: int = M.MCD_SIM_TECTONIC):
     x = M.mcd_features(g, t, vbase)
     y = M.mcd_mlp_forward(ctx, picker.params, picker.mean, picker.std, x)
     index, deltas = M.mcd_grid_select(ctx, y, GRID_K, GRID_A, GRID_B, GRID_C)
-    keep, _ = M.mcd_prune_graphs(g, measure, t, deltas, vbase)
-    labels, ncc = M.mcd_components(g, keep)
+    r = M.mcd_weigh_prune(g, measure, t, deltas=deltas, vbase=vbase, want_f32=False, want_keep=False)
+    labels, ncc = M.mcd_components_kept(g, r["kept"])
     return index, deltas, labels, ncc

@@ -2,8 +2,8 @@
 
 Runs, on R-MAT of the given scale: one calibration kernel of known traffic
 (an elementwise int32 add over `--copy-mib` MiB: that many bytes read and
-written), the graph build, the triangle count, weights, prune, components
-and the 16-point sweep, each once, and prints what it launched.  Used as
+written), the graph build, the triangle count, the one-pass weights + prune at
+num/den (default 9/900), components over the kept list and the 16-point sweep, each once, and prints what it launched.  Used as
     rocprofv3 --kernel-trace --stats -- python3 -m paper_2412_12382_amd.profile_run
     rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2412_12382_amd.profile_run
     rocprofv3 --pmc WRITE_SIZE -- python3 -m paper_2412_12382_amd.profile_run
@@ -22,6 +22,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--scale", type=int, default=26)
     ap.add_argument("--copy-mib", type=int, default=2048)
+    ap.add_argument("--num", type=int, default=9, help="prune threshold numerator")
+    ap.add_argument("--den", type=int, default=900, help="prune threshold denominator")
     args = ap.parse_args()
     import torch
 
@@ -42,9 +44,9 @@ def main():
     ctx = M.mcd_ctx_create(0)
     g = M.mcd_graph_build(ctx, src, dst, n)
     t = M.mcd_triangles(g)
-    M.mcd_weights(g, M.MCD_SIM_TECTONIC, t)
-    keep, nk = M.mcd_prune(g, M.MCD_SIM_TECTONIC, t, (1, 50))
-    lab, ncc = M.mcd_components(g, keep)
+    r = M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, t, delta=(args.num, args.den))
+    lab, ncc = M.mcd_components_kept(g, r["kept"])
+    nk = r["n_kept"]
     M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, [(k, 50) for k in range(16)])
     torch.cuda.synchronize()
     print(json.dumps(dict(scale=args.scale, n=n, m=g.m, kept=int(nk.item()), components=int(ncc.item()))),

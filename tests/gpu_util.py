@@ -50,6 +50,8 @@ def gpu_all(src, dst, n, measure, delta):
     keep, nk = M.mcd_prune(g, measure, t, delta)
     labels, ncc = M.mcd_components(g, keep)
     labels_run, ncc_run = M.mcd_run(g, measure, delta)
+    fused = M.mcd_weigh_prune(g, measure, t, delta=delta, want_i32=(measure == M.MCD_SIM_TW))
+    labels_k, ncc_k = M.mcd_components_kept(g, fused["kept"])
     torch.cuda.synchronize()
     out = dict(g=g, lo=lo, hi=hi, deg=deg[:n], t=t.cpu().numpy()[order],
                w=wf.cpu().numpy()[order] if g.m else np.zeros(0, np.float32),
@@ -58,4 +60,20 @@ def gpu_all(src, dst, n, measure, delta):
                labels_run=labels_run.cpu().numpy(), ncc_run=int(ncc_run.item()))
     if wi is not None:
         out["tw"] = wi.cpu().numpy()[order]
+    # fused pass: the kept list, mapped to original ids, must be the kept
+    # edges in the list's documented order (segment s: groups s, s + S, ...)
+    u, v = M.mcd_graph_edges(g)
+    u, v = u.cpu().numpy(), v.cpu().numpy()
+    keep_lib = unpack_bits(fused["keep_bits"], g.m).astype(bool)
+    perm = M.mcd_graph_perm(g).cpu().numpy()
+    kp = fused["kept"].edges().cpu().numpy().astype(np.int64)
+    out["fused"] = dict(
+        w=fused["w_f32"].cpu().numpy()[order] if g.m else np.zeros(0, np.float32),
+        tw=None if fused["w_i32"] is None else fused["w_i32"].cpu().numpy()[order],
+        keep=keep_lib.astype(np.uint8)[order], n_kept=int(fused["n_kept"].item()),
+        kept_u=perm[kp[:, 0]] if len(kp) else np.zeros(0, np.int32),
+        kept_v=perm[kp[:, 1]] if len(kp) else np.zeros(0, np.int32),
+        want_u=u[fused["kept"].edge_ids(g.m)][keep_lib[fused["kept"].edge_ids(g.m)]],
+        want_v=v[fused["kept"].edge_ids(g.m)][keep_lib[fused["kept"].edge_ids(g.m)]],
+        labels=labels_k.cpu().numpy(), ncc=int(ncc_k.item()))
     return out

@@ -45,3 +45,10 @@ def test_no_device_reported():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert M.lib().mcd_ctx_create(0, None, ctypes.byref(h)) == -5
+
+
+def test_kept_segments_constant_matches_header():
+    import re
+    text = open(M.HEADER).read()
+    v = int(re.search(r"#define MCD_KEPT_SEGMENTS (\d+)", text).group(1))
+    assert v == M.KEPT_SEGMENTS

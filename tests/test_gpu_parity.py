@@ -45,6 +45,13 @@ def check_all(src, dst, n, measure, delta):
     labels, ncc = oracle.components(n, lo, hi, keep)
     assert np.array_equal(r["labels"], labels) and r["ncc"] == ncc
     assert np.array_equal(r["labels_run"], labels) and r["ncc_run"] == ncc
+    f = r["fused"]  # one-pass weights + prune, kept list, components over it
+    assert np.array_equal(f["w"].view(np.int32), r["w"].view(np.int32))
+    if measure == oracle.TW:
+        assert np.array_equal(f["tw"], r["tw"])
+    assert np.array_equal(f["keep"], keep) and f["n_kept"] == int(keep.sum())
+    assert np.array_equal(f["kept_u"], f["want_u"]) and np.array_equal(f["kept_v"], f["want_v"])
+    assert np.array_equal(f["labels"], labels) and f["ncc"] == ncc
     return r
 
 

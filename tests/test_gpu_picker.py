@@ -121,6 +121,14 @@ def test_select_targets_and_per_graph_prune():
     assert np.array_equal(kg, want) and int(nk.item()) == int(want.sum())
     lab_o, ncc_o = oracle.components(n, lo, hi, want)
     assert np.array_equal(lab.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o
+    # the same per-graph thresholds through the one-pass weights + prune and
+    # components over its kept list
+    f = M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, t, deltas=cuda(deltas), vbase=cuda(vbase))
+    assert np.array_equal(unpack_bits(f["keep_bits"], g.m)[order], want)
+    assert int(f["n_kept"].item()) == int(want.sum())
+    assert int(f["kept"].counts.sum().item()) == int(want.sum())
+    lab2, ncc2 = M.mcd_components_kept(g, f["kept"])
+    assert np.array_equal(lab2.cpu().numpy(), lab_o) and int(ncc2.item()) == ncc_o
 
 
 def test_picker_end_to_end_small_batch():
