@@ -55,6 +55,31 @@ def parse():
     return ap.parse_args()
 
 
+def profiled_traffic(stages):
+    """HBM bytes per launch (read + written) of the given stages, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when any
+    kernel source of those stages has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "pipeline_rmat_s26_hbm_traffic.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    total = 0.0
+    for st in stages:
+        r = rec.get(st)
+        if r is None:
+            return None
+        for f, h in r["sources"].items():
+            src = os.path.join(ROOT, "paper_2412_12382_amd", "csrc", f)
+            if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != h:
+                return None
+        total += r["read_bytes"] + r["write_bytes"]
+    return total
+
+
 def cpu_baseline(scale: int, ef: int, seed: int, num: int, den: int):
     """The oracle (plain C, OpenMP) on a bounded sample of the same workload
     family: R-MAT at a smaller scale, same generator and a fixed threshold."""
@@ -301,10 +326,12 @@ def main():
         "stages_ms": {k: round(v_, 3) for k, v_ in avg.items()},
         "wpc_edges_per_s": m / (wpc_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": tc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": tc_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "triangles",
-                     "algorithmic_bytes": tc_bytes, "W": W},
+                     "frac": tc_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(["triangles"]),
+                     "kernel": "triangles", "algorithmic_bytes": tc_bytes, "W": W},
         "roofline_wpc": {"bound": "hbm", "achieved": wpc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": wpc_gbs / HBM_PEAK_GBS, "algorithmic_bytes": wpc_bytes},
+                         "frac": wpc_gbs / HBM_PEAK_GBS, "algorithmic_bytes": wpc_bytes,
+                         "traffic": profiled_traffic(["weigh_prune", "components"]),
+                         "kernel": "weigh_prune+components"},
         "results": {"triangles": tri, "picked_delta": pick_delta, "n_kept": kept, "n_components": ncomp,
                     "sweep16": {"delta": [f"{a}/{b}" for a, b in grid16],
                                 "m_kept": sw[:, 0].tolist(), "n_components": sw[:, 1].tolist(),
