@@ -40,12 +40,27 @@ __global__ __launch_bounds__(kThreads) void k_canon(const int32_t* __restrict__ 
     }
 }
 
+// deg[x] += 1 for both endpoints of every unique edge.  The keys are sorted by
+// their lower endpoint, so the lanes of a wave hold runs of equal lower
+// endpoints: each run adds its length with one atomic (a hub's run would
+// otherwise serialise 64 same-address atomics per wave).
 __global__ __launch_bounds__(kThreads) void k_degree(const uint64_t* __restrict__ uniq, int64_t m,
                                                      int bits, int32_t* __restrict__ deg) {
     const uint64_t mask = (1ull << bits) - 1;
+    const int lane = threadIdx.x & 63;
     GRID_STRIDE(e, m) {
         const uint64_t k = uniq[e];
-        atomicAdd(&deg[k >> bits], 1);
+        const int32_t lo = (int32_t)(k >> bits);
+        const int32_t prev = __shfl_up(lo, 1);
+        const bool head = lane == 0 || prev != lo;
+        const uint64_t heads = __ballot(head);
+        const uint64_t active = __ballot(true);
+        if (head) {
+            // run = lanes from this head up to the next head (or the last active lane)
+            const uint64_t above = heads & ~((2ull << lane) - 1ull);
+            const int end = above ? __ffsll((long long)above) - 1 : 64 - __clzll((long long)active);
+            atomicAdd(&deg[lo], end - lane);
+        }
         atomicAdd(&deg[k & mask], 1);
     }
 }

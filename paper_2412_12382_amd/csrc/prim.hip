@@ -73,19 +73,81 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_single(int64_t* __restric
     if (total && tid == kScanThreads - 1) *total = part[tid];
 }
 
+// Per digit d (one workgroup each): exclusive scan, in place, of the block
+// counts counts[d*NB .. d*NB+NB) and the digit total in tot[d].
+__global__ __launch_bounds__(kThreads) void k_rs_rowscan(int64_t* __restrict__ counts, int NB,
+                                                         int64_t* __restrict__ tot) {
+    __shared__ int64_t part[kThreads];
+    int64_t* row = counts + (int64_t)blockIdx.x * NB;
+    const int tid = threadIdx.x;
+    const int per = (NB + kThreads - 1) / kThreads;
+    const int b = tid * per, e = min(NB, b + per);
+    int64_t sum = 0;
+    for (int i = b; i < e; ++i) sum += row[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        const int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int i = b; i < e; ++i) {
+        const int64_t v = row[i];
+        row[i] = run;
+        run += v;
+    }
+    if (tid == kThreads - 1) tot[blockIdx.x] = part[tid];
+}
+
+// Exclusive prefix over the block's threads of x (one value per thread), and
+// the total in *total.  Uses sh[kWaves].
+template <class T>
+__device__ __forceinline__ T block_excl_scan(T x, T* sh, T* total) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) {
+        if (ww < w) before += sh[ww];
+        all += sh[ww];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
 // Stable scatter of block b's key range by the digit at `shift`.  Each wave
 // ranks its own contiguous 1024-key slice of the tile with 64-lane ballots
 // (lanes holding the same digit form a peer mask); slices are ordered wave by
-// wave, so the rank order equals the input order.
+// wave, so the rank order equals the input order.  The ranked tile is first
+// placed in LDS grouped by digit, then written out so that consecutive
+// threads store consecutive keys of a digit's run (coalesced writes).
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restrict__ in,
                                                          uint64_t* __restrict__ out, int64_t N,
                                                          int shift, int64_t tpb, int NB,
-                                                         const int64_t* __restrict__ offs) {
+                                                         const int64_t* __restrict__ rowpre,
+                                                         const int64_t* __restrict__ rowtot) {
     __shared__ int64_t run[256];
-    __shared__ int64_t wbase[kWaves][256];
     __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t loff[256];
+    __shared__ uint32_t tcnt[256];
+    __shared__ uint64_t stage[kTile];
+    __shared__ int64_t sh64[kWaves];
+    __shared__ uint32_t sh32[kWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    run[tid] = offs[(int64_t)tid * NB + blockIdx.x];
+    {
+        int64_t all;
+        const int64_t base = block_excl_scan<int64_t>(rowtot[tid], sh64, &all);
+        run[tid] = base + rowpre[(int64_t)tid * NB + blockIdx.x];
+    }
     const int64_t ntiles = div_up(N, kTile);
     const int64_t t0 = (int64_t)blockIdx.x * tpb;
     const int64_t t1 = min(ntiles, t0 + tpb);
@@ -114,14 +176,23 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restr
             key[it] = k;
         }
         __syncthreads();
-        {
-            int64_t acc = run[tid];
+        {  // digit tid: tile count, tile-local start, and each wave's start within it
+            uint32_t c[kWaves], sum = 0;
 #pragma unroll
             for (int ww = 0; ww < kWaves; ++ww) {
-                wbase[ww][tid] = acc;
-                acc += wcnt[ww][tid];
+                c[ww] = wcnt[ww][tid];
+                sum += c[ww];
             }
-            run[tid] = acc;
+            uint32_t total;
+            const uint32_t start = block_excl_scan<uint32_t>(sum, sh32, &total);
+            loff[tid] = start;
+            tcnt[tid] = sum;
+            uint32_t acc = start;
+#pragma unroll
+            for (int ww = 0; ww < kWaves; ++ww) {
+                wcnt[ww][tid] = acc;
+                acc += c[ww];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -129,9 +200,19 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restr
             const int64_t i = base + it * 64 + lane;
             if (i < N) {
                 const uint32_t d = (uint32_t)(key[it] >> shift) & 255u;
-                out[wbase[w][d] + rnk[it]] = key[it];
+                stage[wcnt[w][d] + rnk[it]] = key[it];
             }
         }
+        __syncthreads();
+        const int64_t tile_n = min((int64_t)kTile, N - tile * kTile);
+        for (int j = tid; j < tile_n; j += kThreads) {
+            const uint64_t k = stage[j];
+            const uint32_t d = (uint32_t)(k >> shift) & 255u;
+            out[run[d] + (j - (int64_t)loff[d])] = k;
+        }
+        __syncthreads();
+        run[tid] += tcnt[tid];
+        __syncthreads();
     }
 }
 
@@ -252,7 +333,7 @@ void fill_any(T* p, int64_t N, T v, hipStream_t s) {
 
 }  // namespace
 
-size_t radix_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * 256 * kMaxBlocks); }
+size_t radix_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * 256 * (kMaxBlocks + 1)); }
 
 uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch,
                          hipStream_t s) {
@@ -261,14 +342,14 @@ uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* s
     const int NB = grid_blocks(ntiles);
     const int64_t tpb = div_up(ntiles, NB);
     int64_t* counts = (int64_t*)scratch;
+    int64_t* tot = counts + (int64_t)256 * kMaxBlocks;
     const int passes = (nbits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(NB), dim3(kThreads), 0, s, a, N, shift, tpb, NB, counts);
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, counts,
-                           (int64_t)256 * NB, (int64_t*)nullptr);
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kThreads), 0, s, counts, NB, tot);
         hipLaunchKernelGGL(k_rs_scatter, dim3(NB), dim3(kThreads), 0, s, a, b, N, shift, tpb, NB,
-                           counts);
+                           counts, tot);
         uint64_t* t = a;
         a = b;
         b = t;

@@ -270,13 +270,15 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
     }
 }
 
-// Rank-window items, one item per workgroup, one in-edge per wave at a time.
-// All control state (in-edge descriptor, suffix bounds, chunk cursor) is
-// wave-uniform and kept in 32-bit scalars (edge ids are below 2^31); each lane
-// holds one suffix element per chunk.  The first chunk of the wave's next
-// in-edge is loaded while the current suffix is probed.
-template <int LOG2R>
-__global__ __launch_bounds__(kThreads) void k_tc_window(const Item* __restrict__ all_items,
+// Rank-window items, one item per workgroup of NT threads, one in-edge per wave
+// at a time.  All control state (in-edge descriptor, suffix bounds, chunk
+// cursor) is wave-uniform and kept in 32-bit scalars (edge ids are below
+// 2^31); each lane holds one suffix element per chunk.  The first chunk of the
+// wave's next in-edge is loaded while the current suffix is probed.  Wide
+// windows take large workgroups so that the LDS they need still leaves room
+// for enough waves per CU.
+template <int LOG2R, int NT>
+__global__ __launch_bounds__(NT) void k_tc_window(const Item* __restrict__ all_items,
                                                         const int64_t* __restrict__ heads, int cls,
                                                         const int64_t* __restrict__ off,
                                                         const int32_t* __restrict__ adj,
@@ -284,9 +286,10 @@ __global__ __launch_bounds__(kThreads) void k_tc_window(const Item* __restrict__
                                                         int32_t* __restrict__ t) {
     constexpr int NW = (1 << LOG2R) / 32;
     constexpr int MAXB = 4096;
+    constexpr int NWAVES = NT / 64;
     __shared__ uint32_t bm[NW];
     __shared__ uint16_t pre[NW];
-    __shared__ uint32_t part[4];
+    __shared__ uint32_t part[NWAVES];
     __shared__ uint32_t cnt[MAXB / 2];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const Item* __restrict__ items = all_items + heads[2 * cls];
@@ -297,10 +300,10 @@ __global__ __launch_bounds__(kThreads) void k_tc_window(const Item* __restrict__
         const int32_t v = I.v;
         const int32_t b0 = (int32_t)off[v];
         const int32_t B = (int32_t)(off[v + 1] - b0);
-        for (int i = tid; i < NW; i += kThreads) bm[i] = 0;
-        for (int i = tid; i < MAXB / 2; i += kThreads) cnt[i] = 0;
+        for (int i = tid; i < NW; i += NT) bm[i] = 0;
+        for (int i = tid; i < MAXB / 2; i += NT) cnt[i] = 0;
         __syncthreads();
-        for (int j = tid; j < B; j += kThreads) {
+        for (int j = tid; j < B; j += NT) {
             const uint32_t r = (uint32_t)(adj[b0 + j] - v - 1);
             atomicOr(&bm[r >> 5], 1u << (r & 31));
         }
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_tc_window(const Item* __restrict__
         __syncthreads();
         {  // exclusive prefix of popcounts over the words in use
             const int nw = (maxv - v + 31) >> 5;
-            const int per = (nw + kThreads - 1) / kThreads;
+            const int per = (nw + NT - 1) / NT;
             const int w0 = tid * per, w1 = min(nw, w0 + per);
             uint32_t sum = 0;
             for (int i = w0; i < w1; ++i) sum += __popc(bm[i]);
@@ -332,12 +335,12 @@ __global__ __launch_bounds__(kThreads) void k_tc_window(const Item* __restrict__
         int32_t k = kbeg + wave;
         int2 d = k < kend ? in_ea[k] : make_int2(0, 0);
         int32_t first = (k < kend && lane < d.y) ? adj[d.x + 1 + lane] : INT32_MAX;
-        for (; k < kend; k += 4) {
+        for (; k < kend; k += NWAVES) {
             const int32_t e = d.x;
             const int32_t a0 = e + 1, a1 = a0 + d.y;
             int32_t w = first;
             // next in-edge: descriptor and first chunk, in flight during this suffix
-            const int32_t kn = k + 4;
+            const int32_t kn = k + NWAVES;
             d = kn < kend ? in_ea[kn] : make_int2(0, 0);
             first = (kn < kend && lane < d.y) ? adj[d.x + 1 + lane] : INT32_MAX;
             uint32_t c = 0;
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(kThreads) void k_tc_window(const Item* __restrict__
             if (lane == 0 && c) add_relaxed(&t[e], (int32_t)c);
         }
         __syncthreads();
-        for (int j = tid; j < B; j += kThreads) {
+        for (int j = tid; j < B; j += NT) {
             const uint32_t x = (cnt[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
             if (x) add_relaxed(&t[b0 + j], (int32_t)x);
         }
@@ -546,11 +549,11 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
                        L.items, L.heads, c, g->off, g->adj, g->in_ea, t);
 }
 
-template <int LOG2R>
+template <int LOG2R, int NT>
 void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = cap_items < 16384 ? cap_items : 16384;
-    hipLaunchKernelGGL(k_tc_window<LOG2R>, dim3((unsigned)blocks), dim3(kThreads), 0, s, L.items, L.heads, c,
+    hipLaunchKernelGGL((k_tc_window<LOG2R, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads, c,
                        g->off, g->adj, g->in_ea, t);
 }
 
@@ -580,9 +583,9 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
-    launch_window<14>(g, L, 8, chunk, t, s);
-    launch_window<16>(g, L, 9, chunk, t, s);
-    launch_window<18>(g, L, 10, chunk, t, s);
+    launch_window<14, 256>(g, L, 8, chunk, t, s);
+    launch_window<16, 512>(g, L, 9, chunk, t, s);
+    launch_window<18, 1024>(g, L, 10, chunk, t, s);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
 }
