@@ -155,6 +155,19 @@ mcd_status mcd_triangles_workspace_size(const mcd_graph* g, size_t* bytes);
  * ws: device scratch of mcd_triangles_workspace_size bytes. */
 mcd_status mcd_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes);
 
+/* Autotuner of the triangle-count launch parameters (item chunk, rank-window
+ * cutoff, packed-hash range, LDS row cap) on this graph: a coordinate search
+ * over a fixed candidate grid, each setting timed with HIP events on the
+ * context's stream (smallest of `reps` runs, after a warm-up).  The fastest
+ * setting is stored in the context (mcd_ctx_get_param reads it back) and
+ * returned in host_best[4] = {tc_chunk, tc_lds_max, tc_packed_range,
+ * tc_window_max} (may be NULL) with its time in *host_ms (may be NULL).  The
+ * counts never depend on the parameters; t (device int32[m]) ends holding
+ * them.  ws: mcd_tune_triangles_workspace_size bytes.  Synchronous. */
+mcd_status mcd_tune_triangles_workspace_size(const mcd_graph* g, size_t* bytes);
+mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes, int32_t reps,
+                              int64_t* host_best, float* host_ms);
+
 /* Edge similarity of Table tab:simfunctions from t (as produced by
  * mcd_triangles).  w_f32 (device float[m], may be NULL): the measure in IEEE
  * fp32, Tectonic as the correctly rounded quotient t / (deg u + deg v).

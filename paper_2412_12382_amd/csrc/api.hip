@@ -6,6 +6,8 @@
 
 #include <string>
 
+#include <algorithm>
+
 #include "common.hpp"
 
 // The library is built with hidden visibility; the C ABI below is exported.
@@ -367,6 +369,92 @@ mcd_status mcd_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_byt
     if (st != MCD_OK) return st;
     mcd::launch_triangles(g, t, ws, g->ctx->tc_chunk, g->ctx->tc_lds_max, g->ctx->tc_packed_range,
                           g->ctx->tc_window_max, g->ctx->stream);
+    return MCD_OK;
+}
+
+// ---- autotuner for the triangle-count launch parameters ----
+namespace {
+constexpr int64_t kTuneChunks[] = {256, 512, 1024, 2048};
+constexpr int64_t kTuneWindows[] = {0, 1 << 14, 1 << 16, 1 << 18};
+constexpr int64_t kTunePacked[] = {0, MCD_TC_PACKED_LIMIT};
+constexpr int64_t kTuneLds[] = {1024, 2048, 4096};
+
+// Smallest time over reps of one triangle count with the given parameters.
+mcd_status time_triangles(const mcd_graph* g, int32_t* t, void* ws, const int64_t p[4], int reps, float* ms) {
+    hipStream_t s = g->ctx->stream;
+    hipEvent_t e0, e1;
+    MCD_HIP(hipEventCreate(&e0));
+    MCD_HIP(hipEventCreate(&e1));
+    float best = 3.4e38f;
+    for (int r = 0; r < reps; ++r) {
+        MCD_HIP(hipEventRecord(e0, s));
+        mcd::launch_triangles(g, t, ws, p[0], p[1], p[2], p[3], s);
+        MCD_HIP(hipEventRecord(e1, s));
+        MCD_HIP(hipEventSynchronize(e1));
+        float x = 0.f;
+        MCD_HIP(hipEventElapsedTime(&x, e0, e1));
+        if (x < best) best = x;
+    }
+    MCD_HIP(hipEventDestroy(e0));
+    MCD_HIP(hipEventDestroy(e1));
+    *ms = best;
+    return MCD_OK;
+}
+}  // namespace
+
+mcd_status mcd_tune_triangles_workspace_size(const mcd_graph* g, size_t* bytes) {
+    REQUIRE(g && bytes, MCD_ERR_INVALID_ARG, "NULL argument");
+    size_t need = 0;
+    for (int64_t c : kTuneChunks) need = std::max(need, mcd::tc_scratch_bytes(g, c));
+    need = std::max(need, mcd::tc_scratch_bytes(g, g->ctx->tc_chunk));
+    *bytes = need;
+    return MCD_OK;
+}
+
+mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes, int32_t reps,
+                              int64_t* host_best, float* host_ms) {
+    REQUIRE(g && (g->m == 0 || (t && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(reps >= 1 && reps <= 100, MCD_ERR_RANGE, "reps must lie in [1, 100]");
+    size_t need = 0;
+    mcd_tune_triangles_workspace_size(g, &need);
+    REQUIRE(g->m == 0 || ws_bytes >= need, MCD_ERR_WORKSPACE, "tuning workspace too small");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd_ctx* ctx = g->ctx;
+    int64_t best[4] = {ctx->tc_chunk, ctx->tc_lds_max, ctx->tc_packed_range, ctx->tc_window_max};
+    float best_ms = 0.f;
+    if (g->m > 0) {
+        if ((st = time_triangles(g, t, ws, best, 1, &best_ms)) != MCD_OK) return st;  // warm-up
+        if ((st = time_triangles(g, t, ws, best, reps, &best_ms)) != MCD_OK) return st;
+        // one coordinate at a time: item chunk, window cutoff, packed range, LDS cap
+        const int64_t* cand[4] = {kTuneChunks, kTuneLds, kTunePacked, kTuneWindows};
+        const int ncand[4] = {4, 3, 2, 4};
+        const int order[4] = {0, 3, 2, 1};
+        for (int oi = 0; oi < 4; ++oi) {
+            const int k = order[oi];
+            for (int j = 0; j < ncand[k]; ++j) {
+                if (cand[k][j] == best[k]) continue;
+                int64_t p[4] = {best[0], best[1], best[2], best[3]};
+                p[k] = cand[k][j];
+                float ms = 0.f;
+                if ((st = time_triangles(g, t, ws, p, reps, &ms)) != MCD_OK) return st;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best[k] = p[k];
+                }
+            }
+        }
+        ctx->tc_chunk = best[0];
+        ctx->tc_lds_max = best[1];
+        ctx->tc_packed_range = best[2];
+        ctx->tc_window_max = best[3];
+        // leave t holding the counts of the chosen setting
+        mcd::launch_triangles(g, t, ws, best[0], best[1], best[2], best[3], ctx->stream);
+        MCD_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    if (host_best)
+        for (int i = 0; i < 4; ++i) host_best[i] = best[i];
+    if (host_ms) *host_ms = best_ms;
     return MCD_OK;
 }
 

@@ -92,6 +92,8 @@ def lib():
             "mcd_weigh_prune": [P, ctypes.c_int, P, mcd_rational, I32, P, P, P, P, P, P, P, P],
             "mcd_kept_segment_len": [P, ctypes.POINTER(I64)],
             "mcd_components_kept": [P, P, P, P, P, P, SZ],
+            "mcd_tune_triangles_workspace_size": [P, ctypes.POINTER(SZ)],
+            "mcd_tune_triangles": [P, P, P, SZ, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float)],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
         for name, args in sig.items():
@@ -364,14 +366,18 @@ def _vbase(g: Graph, vbase):
     return vbase
 
 
+def mcd_features_workspace_size(n_graphs: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_features_workspace_size(n_graphs, ctypes.byref(b)))
+    return b.value
+
+
 def mcd_features(g: Graph, t, vbase=None, x=None, ws=None):
     vb = _vbase(g, vbase)
     G = vb.numel() - 1
     x = _empty((G, MLP_IN), torch.float32, g.ctx.device) if x is None else x
     if ws is None:
-        b = ctypes.c_size_t()
-        _check(lib().mcd_features_workspace_size(G, ctypes.byref(b)))
-        ws = _bytes(b.value, g.ctx.device)
+        ws = _bytes(mcd_features_workspace_size(G), g.ctx.device)
     _check(lib().mcd_features(g.handle, _p(t), G, _p(vb), _p(x), _p(ws), ws.numel() * ws.element_size()))
     return x
 
@@ -444,6 +450,21 @@ def mcd_prune_graphs(g: Graph, measure: int, t, deltas, vbase=None, keep_bits=No
 
 
 KEPT_SEGMENTS = 16384
+TUNE_PARAMS = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max")
+
+
+def mcd_tune_triangles(g: Graph, t=None, ws=None, reps: int = 2):
+    """Autotune the triangle-count parameters on g; returns ({name: value}, ms)."""
+    t = _empty(max(g.m, 1), torch.int32, g.ctx.device) if t is None else t
+    if ws is None:
+        b = ctypes.c_size_t()
+        _check(lib().mcd_tune_triangles_workspace_size(g.handle, ctypes.byref(b)))
+        ws = _bytes(b.value, g.ctx.device)
+    best = (ctypes.c_int64 * 4)()
+    ms = ctypes.c_float()
+    _check(lib().mcd_tune_triangles(g.handle, _p(t), _p(ws), ws.numel() * ws.element_size(), reps, best,
+                                    ctypes.byref(ms)))
+    return dict(zip(TUNE_PARAMS, list(best))), ms.value
 
 
 def mcd_kept_segment_len(g: Graph) -> int:

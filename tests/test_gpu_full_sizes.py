@@ -1,0 +1,157 @@
+"""GPU parity at the full sizes of the five workloads.
+
+R-MAT scale 20 and the degree-corrected SBM are compared with the oracle in
+full; the 256-graph planted batch at sampled thresholds of the 64-point grid;
+R-MAT scale 26 (the benchmark's workload, run with the same calls and
+buffers the benchmark uses) on sampled edges the oracle evaluates one by one
+from the raw pairs, plus properties of the labelling that hold at any size.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+M = pytest.importorskip("paper_2412_12382_amd.mcd")
+
+GRID64 = [(9 + 7 * i, 900) for i in range(64)]
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_c2_rmat_s20_percentile_both_measures():
+    from gpu_util import build, canonical_order, unpack_bits
+    src, dst, n = gg.rmat(20, seed=1)
+    print(f"C2: R-MAT scale 20 seed 1, {len(src)} pairs", flush=True)
+    g = build(src, dst, n)
+    lo, hi, order = canonical_order(g)
+    lo_o, hi_o = oracle.canon(n, src, dst)
+    assert np.array_equal(lo, lo_o) and np.array_equal(hi, hi_o)
+    deg = oracle.degrees(n, lo_o, hi_o)
+    t_o = oracle.triangles(n, lo_o, hi_o)
+    t = M.mcd_triangles(g)
+    assert np.array_equal(t.cpu().numpy()[order], t_o)
+    for measure in (oracle.TECTONIC, oracle.TW):
+        num, den = M.mcd_percentile_threshold(g, measure, t, 3, 10)
+        want = oracle.percentile(measure, lo_o, hi_o, t_o, deg, 3, 10)
+        assert Fraction(num, den) == Fraction(*want)
+        r = M.mcd_weigh_prune(g, measure, t, delta=(num, den), want_i32=(measure == oracle.TW))
+        keep_o = oracle.prune(measure, lo_o, hi_o, t_o, deg, num, den)
+        assert np.array_equal(unpack_bits(r["keep_bits"], g.m)[order], keep_o)
+        assert int(r["n_kept"].item()) == int(keep_o.sum())
+        if measure == oracle.TECTONIC:
+            w_o = oracle.tectonic(lo_o, hi_o, t_o, deg)
+            w = r["w_f32"].cpu().numpy()[order].astype(np.float64)
+            assert np.all(np.abs(w - w_o) <= 1e-6 * np.abs(w_o))
+        else:
+            assert np.array_equal(r["w_i32"].cpu().numpy()[order].astype(np.int64),
+                                  oracle.tw(lo_o, hi_o, t_o, deg))
+        lab, ncc = M.mcd_components_kept(g, r["kept"])
+        lab_o, ncc_o = oracle.components(n, lo_o, hi_o, keep_o)
+        assert np.array_equal(lab.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o
+
+
+def test_c3_dcsbm_sweep_64_with_ari():
+    from gpu_util import build
+    c = gg.dcsbm()
+    n = c["n"]
+    print(f"C3: DC-SBM n={n}, {len(c['src'])} pairs", flush=True)
+    g = build(c["src"], c["dst"], n)
+    t = M.mcd_triangles(g)
+    stats, ari, labels = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, GRID64, truth=cuda(c["truth"].astype(np.int32)),
+                                     want_labels=True)
+    stats, ari = stats.cpu().numpy()[0], ari.cpu().numpy()[0]
+    lo, hi = oracle.canon(n, c["src"], c["dst"])
+    deg = oracle.degrees(n, lo, hi)
+    t_o = oracle.triangles(n, lo, hi)
+    pick = list(range(0, 64, 4)) + [63]
+    st_o, ari_o, lab_o = oracle.sweep(n, lo, hi, t_o, deg, oracle.TECTONIC, [GRID64[i] for i in pick], c["truth"])
+    for j, i in enumerate(pick):
+        assert np.array_equal(stats[i], st_o[0, j]), (i, stats[i], st_o[0, j])
+        assert abs(ari[i] - ari_o[0, j]) <= 1e-12
+        assert np.array_equal(labels[i, :n].cpu().numpy(), lab_o[j])
+    # every threshold: fewer kept edges and a finer partition as delta grows
+    assert np.all(np.diff(stats[:, 0]) <= 0) and np.all(np.diff(stats[:, 1]) >= 0)
+
+
+def test_c4_batch_256_sweep_sampled_thresholds():
+    from gpu_util import build
+    b = gg.sbm_batch(256)
+    n, vbase = b["n"], b["vbase"]
+    print(f"C4: 256 planted graphs, n={n}, {len(b['src'])} pairs", flush=True)
+    g = build(b["src"], b["dst"], n)
+    t = M.mcd_triangles(g)
+    stats, ari, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, GRID64, vbase=cuda(vbase), truth=cuda(b["truth"]))
+    stats, ari = stats.cpu().numpy(), ari.cpu().numpy()
+    lo, hi = oracle.canon(n, b["src"], b["dst"])
+    deg = oracle.degrees(n, lo, hi)
+    t_o = oracle.triangles(n, lo, hi)
+    pick = [0, 9, 18, 27, 36, 45, 54, 63]
+    st_o, ari_o, _ = oracle.sweep(n, lo, hi, t_o, deg, oracle.TECTONIC, [GRID64[i] for i in pick], b["truth"],
+                                  vbase)
+    for j, i in enumerate(pick):
+        assert np.array_equal(stats[:, i], st_o[:, j]), i
+        assert np.all(np.abs(ari[:, i] - ari_o[:, j]) <= 1e-12), i
+
+
+def test_c5_rmat_s26_sampled_edges_and_label_properties():
+    """The benchmark's workload: R-MAT scale 26, one-pass weights + prune at
+    9/900 with the kept list, components over it, and the 16-point sweep."""
+    src, dst, n = gg.rmat(26, seed=3)
+    print(f"C5: R-MAT scale 26 seed 3, {len(src)} pairs", flush=True)
+    ctx = M.mcd_ctx_create(0)
+    g = M.mcd_graph_build(ctx, cuda(src), cuda(dst), n)
+    m = g.m
+    t = M.mcd_triangles(g)
+    delta = (9, 900)
+    r = M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, t, delta=delta)
+    lab, ncc = M.mcd_components_kept(g, r["kept"])
+    stats, _, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, [(k, 50) for k in range(16)])
+    u, v = M.mcd_graph_edges(g)
+    deg = M.mcd_graph_degrees(g)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(26)
+    idx = cuda(rng.choice(m, 512, replace=False).astype(np.int64))
+    qu, qv = u[idx].cpu().numpy(), v[idx].cpu().numpy()
+    tg = t[idx].cpu().numpy()
+    wg = r["w_f32"][idx].cpu().numpy()
+    kb = r["keep_bits"].view(torch.int32)
+    kg = ((kb[idx >> 5] >> (idx & 31)) & 1).cpu().numpy()
+    is_edge, du, dv, to = oracle.query_edges(n, src, dst, qu, qv)
+    assert np.all(is_edge == 1)
+    assert np.array_equal(tg, to)
+    dg = deg.cpu().numpy()
+    assert np.array_equal(dg[qu], du) and np.array_equal(dg[qv], dv)
+    w_o = to.astype(np.float64) / (du.astype(np.float64) + dv)
+    assert np.all(np.abs(wg.astype(np.float64) - w_o) <= 1e-6 * w_o)
+    keep_o = np.array([Fraction(int(a), int(b_ + c_)) >= Fraction(*delta) for a, b_, c_ in zip(to, du, dv)])
+    assert np.array_equal(kg.astype(bool), keep_o)
+    # counts agree between the mask, the kept list and the 16-point sweep
+    nk = int(r["n_kept"].item())
+    assert nk == int(r["kept"].counts.sum().item())
+    words = (m + 31) // 32
+    pop = torch.zeros(1, dtype=torch.int64, device="cuda")
+    kw = kb[:words].to(torch.int64) & 0xFFFFFFFF
+    for sh in range(32):
+        pop += ((kw >> sh) & 1).sum()
+    assert int(pop.item()) == nk
+    st = stats.cpu().numpy()[0]
+    assert st[0, 0] == m and np.all(np.diff(st[:, 0]) <= 0)
+    # labels: constant along sampled kept edges, never above the vertex,
+    # idempotent, and the roots count the components
+    ar = torch.arange(n, device="cuda", dtype=torch.int32)
+    assert bool((lab <= ar).all()) and bool((lab[lab.long()] == lab).all())
+    assert int((lab == ar).sum().item()) == int(ncc.item())
+    ks = np.flatnonzero(kg)
+    assert np.array_equal(lab[cuda(qu[ks]).long()].cpu().numpy(), lab[cuda(qv[ks]).long()].cpu().numpy())
+    # every kept pair of the list joins one component (the whole list)
+    pairs = r["kept"].edges().long()
+    perm = M.mcd_graph_perm(g).long()
+    a, b = perm[pairs[:, 0]], perm[pairs[:, 1]]
+    assert bool((lab[a] == lab[b]).all())

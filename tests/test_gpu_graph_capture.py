@@ -1,0 +1,117 @@
+"""The path after the graph build, captured once in a HIP graph and replayed.
+
+Triangles, one-pass weights + prune at per-graph device thresholds,
+components over the kept list, the 64-threshold sweep with ARI, picker
+features, MLP forward and grid snap are enqueued by the library on the
+context's stream while a HIP graph is being captured on it.  The graph is
+replayed several times, with eager work and synchronisations in between and
+every output overwritten before each replay, and each replay must equal the
+eager run bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+M = pytest.importorskip("paper_2412_12382_amd.mcd")
+
+GRID64 = [(9 + 7 * i, 900) for i in range(64)]
+
+
+def small_batch(G=5, n_cap=2500):
+    graphs = []
+    for g in range(G):
+        pr = gg.sbm_batch_params(g)
+        n = min(pr["n"], n_cap)
+        k = min(pr["k"], n // 4)
+        src, dst, lab = gg.sbm_skip(n, k, min(pr["d_in"] / (n / k - 1), 0.5),
+                                    pr["mu"] * pr["d_in"] / ((1 - pr["mu"]) * n), 1000 + g)
+        graphs.append((n, src, dst, lab))
+    vbase = np.zeros(G + 1, np.int64)
+    srcs, dsts, truths, cb = [], [], [], 0
+    for i, (n, src, dst, lab) in enumerate(graphs):
+        vbase[i + 1] = vbase[i] + n
+        srcs.append(src + vbase[i])
+        dsts.append(dst + vbase[i])
+        truths.append(lab + cb)
+        cb += int(lab.max()) + 1
+    return (np.concatenate(srcs).astype(np.int32), np.concatenate(dsts).astype(np.int32), int(vbase[-1]), vbase,
+            np.concatenate(truths).astype(np.int32))
+
+
+def test_capture_and_replay_matches_eager():
+    src, dst, n, vbase, truth = small_batch()
+    G = len(vbase) - 1
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream()
+    ctx = M.mcd_ctx_create(0, stream=s)
+    with torch.cuda.stream(s):
+        g = M.mcd_graph_build(ctx, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n)
+        m = g.m
+        cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        vb, tr = cu(vbase), cu(truth)
+        params = cu(np.random.default_rng(5).standard_normal(M.MLP_PARAMS).astype(np.float32) * 0.1)
+        mean = torch.zeros(M.MLP_IN, dtype=torch.float32, device=dev)
+        std = torch.ones(M.MLP_IN, dtype=torch.float32, device=dev)
+        out = dict(
+            t=torch.empty(m, dtype=torch.int32, device=dev),
+            wf=torch.empty(m, dtype=torch.float32, device=dev),
+            keep=torch.empty((m + 31) // 32 + 1, dtype=torch.int32, device=dev),
+            pairs=torch.empty(M.KeptList.capacity(m), dtype=torch.int32, device=dev),
+            counts=torch.empty(M.KEPT_SEGMENTS, dtype=torch.int32, device=dev),
+            nk=torch.empty(1, dtype=torch.int64, device=dev),
+            labels=torch.empty(n, dtype=torch.int32, device=dev),
+            ncc=torch.empty(1, dtype=torch.int64, device=dev),
+            stats=torch.empty((G, 64, 7), dtype=torch.int64, device=dev),
+            ari=torch.empty((G, 64), dtype=torch.float64, device=dev),
+            x=torch.empty((G, M.MLP_IN), dtype=torch.float32, device=dev),
+            y=torch.empty(G, dtype=torch.float32, device=dev),
+            idx=torch.empty(G, dtype=torch.int32, device=dev),
+            delta=torch.empty((G, 2), dtype=torch.int64, device=dev),
+        )
+        ws_t = torch.empty(M.mcd_triangles_workspace_size(g), dtype=torch.uint8, device=dev)
+        ws_c = torch.empty(M.mcd_components_workspace_size(g), dtype=torch.uint8, device=dev)
+        ws_s = torch.empty(M.mcd_sweep_workspace_size(g, G, 64, True), dtype=torch.uint8, device=dev)
+        ws_f = torch.empty(M.mcd_features_workspace_size(G), dtype=torch.uint8, device=dev)
+
+        def path():
+            M.mcd_triangles(g, out["t"], ws=ws_t)
+            M.mcd_features(g, out["t"], vb, x=out["x"], ws=ws_f)
+            M.mcd_mlp_forward(ctx, params, mean, std, out["x"], y=out["y"])
+            M.mcd_grid_select(ctx, out["y"], 64, 9, 7, 900, index=out["idx"], delta=out["delta"])
+            kept = M.KeptList(g, out["pairs"], out["counts"])
+            M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, out["t"], deltas=out["delta"], vbase=vb, w_f32=out["wf"],
+                              keep_bits=out["keep"], kept=kept, n_kept=out["nk"])
+            M.mcd_components_kept(g, kept, out["labels"], out["ncc"], ws=ws_c)
+            M.mcd_sweep(g, M.MCD_SIM_TECTONIC, out["t"], GRID64, vbase=vb, truth=tr, stats=out["stats"],
+                        ari=out["ari"], ws=ws_s)
+
+        path()
+    torch.cuda.synchronize()
+    words = (m + 31) // 32
+    snap = lambda: {k: (v[:words] if k == "keep" else v).clone() for k, v in out.items() if k != "pairs"}
+    eager = snap()
+
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cg, stream=s):
+        path()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            for k, v in out.items():  # overwrite every output before the replay
+                v.fill_(-7 if v.dtype != torch.float32 else float("nan"))
+            torch.cuda.synchronize()
+            _ = (torch.arange(1 << 20, device=dev) % 7).sum()  # unrelated eager work
+            cg.replay()
+        torch.cuda.synchronize()
+        got = snap()
+        for k in eager:
+            a, b = eager[k], got[k]
+            if a.dtype == torch.float32 or a.dtype == torch.float64:
+                assert torch.equal(a.view(torch.int32 if a.dtype == torch.float32 else torch.int64),
+                                   b.view(torch.int32 if b.dtype == torch.float32 else torch.int64)), (rep, k)
+            else:
+                assert torch.equal(a, b), (rep, k)
+    M.mcd_ctx_set_stream(ctx, None)

@@ -196,3 +196,25 @@ def test_complete_graph_closed_form(k):
     t = M.mcd_triangles(g).cpu().numpy()
     assert g.m == k * (k - 1) // 2 and np.all(t == k - 2)
     assert g.max_outdeg == k - 1
+
+
+def test_autotuner_sets_params_and_keeps_counts():
+    from gpu_util import build, canonical_order
+    s, d, n = gg.rmat(14, seed=41)
+    g = build(s, d, n)
+    t0 = M.mcd_triangles(g).clone()
+    best, ms = M.mcd_tune_triangles(g, reps=1)
+    assert ms > 0
+    assert best["tc_chunk"] in (256, 512, 1024, 2048)
+    assert best["tc_lds_max"] in (1024, 2048, 4096)
+    assert best["tc_window_max"] in (0, 1 << 14, 1 << 16, 1 << 18)
+    for k, v in best.items():
+        assert M.mcd_ctx_get_param(g.ctx, k) == v
+    t1 = M.mcd_triangles(g)
+    assert torch.equal(t0, t1)
+    lo, hi, order = canonical_order(g)
+    assert np.array_equal(t1.cpu().numpy()[order], oracle.triangles(n, lo, hi))
+    # restore the defaults for later tests sharing the context
+    for k, v in (("tc_chunk", 512), ("tc_lds_max", 4096), ("tc_packed_range", (1 << 20) - 2),
+                 ("tc_window_max", 1 << 18)):
+        M.mcd_ctx_set_param(g.ctx, k, v)
