@@ -169,16 +169,26 @@ __global__ __launch_bounds__(kThreads) void k_in_count(const int32_t* __restrict
     GRID_STRIDE(v, n) in_cnt[v] = deg[v] - outdeg[v];
 }
 
-__global__ __launch_bounds__(kThreads) void k_in_scatter(const int32_t* __restrict__ src,
-                                                         const int32_t* __restrict__ adj,
-                                                         const int64_t* __restrict__ off, int64_t m,
-                                                         const int64_t* __restrict__ in_off,
-                                                         int32_t* __restrict__ fill,
-                                                         int2* __restrict__ in_ea) {
+// keys[e] = (head << 32) | e, and suf[e] = length of the tail's row after e
+// (both in edge order, so the row offsets are read sequentially).
+__global__ __launch_bounds__(kThreads) void k_in_keys(const int32_t* __restrict__ src,
+                                                      const int32_t* __restrict__ adj,
+                                                      const int64_t* __restrict__ off, int64_t m,
+                                                      uint64_t* __restrict__ keys, int32_t* __restrict__ suf) {
     GRID_STRIDE(e, m) {
-        const int32_t v = adj[e];
-        const int32_t k = atomicAdd(&fill[v], 1);
-        in_ea[in_off[v] + k] = make_int2((int32_t)e, (int32_t)(off[src[e] + 1] - e - 1));
+        keys[e] = ((uint64_t)(uint32_t)adj[e] << 32) | (uint64_t)e;
+        suf[e] = (int32_t)(off[src[e] + 1] - e - 1);
+    }
+}
+
+// In-edge lists grouped by head, each in increasing edge id (= increasing
+// tail rank): the stable sort of (head, edge id) keys.
+__global__ __launch_bounds__(kThreads) void k_in_fill(const uint64_t* __restrict__ sorted,
+                                                      const int32_t* __restrict__ suf, int64_t m,
+                                                      int2* __restrict__ in_ea) {
+    GRID_STRIDE(i, m) {
+        const int32_t e = (int32_t)(uint32_t)sorted[i];
+        in_ea[i] = make_int2(e, suf[e]);
     }
 }
 
@@ -190,11 +200,15 @@ void launch_in_count(const int32_t* deg, const int32_t* outdeg, int64_t n, int32
     hipLaunchKernelGGL(k_in_count, dim3(grid_for(n)), dim3(kThreads), 0, s, deg, outdeg, n, in_cnt);
 }
 
-void launch_in_scatter(const int32_t* src, const int32_t* adj, const int64_t* off, int64_t m,
-                       const int64_t* in_off, int32_t* fill, int2* in_ea, hipStream_t s) {
+void launch_in_keys(const int32_t* src, const int32_t* adj, const int64_t* off, int64_t m, uint64_t* keys,
+                    int32_t* suf, hipStream_t s) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_in_scatter, dim3(grid_for(m)), dim3(kThreads), 0, s, src, adj, off, m, in_off, fill,
-                       in_ea);
+    hipLaunchKernelGGL(k_in_keys, dim3(grid_for(m)), dim3(kThreads), 0, s, src, adj, off, m, keys, suf);
+}
+
+void launch_in_fill(const uint64_t* sorted, const int32_t* suf, int64_t m, int2* in_ea, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_in_fill, dim3(grid_for(m)), dim3(kThreads), 0, s, sorted, suf, m, in_ea);
 }
 
 void launch_canon(const int32_t* src, const int32_t* dst, int64_t P, int64_t n, int bits,

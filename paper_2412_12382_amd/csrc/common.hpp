@@ -45,7 +45,7 @@ struct mcd_graph {
     int32_t* deg;      // [n]   degree by new id (non-decreasing)
     int32_t* perm;     // [n]   original id of every new id
     int64_t* in_off;   // [n+1] offsets of the in-edge lists
-    int2* in_ea;       // [cap] (edge id e of x->v, length of row x after v), grouped by head v
+    int2* in_ea;       // [cap] (edge id e of x->v, length of row x after v), grouped by head v, by e within
 };
 
 // Thread-local error reporting used by the ABI layer.
@@ -78,11 +78,12 @@ struct Carve {
 namespace mcd {
 
 // ---- device-wide primitives (prim.hip) ----
-// Radix sort of N keys on bits [0, nbits): ping-pongs between a and b and
-// returns the buffer holding the result.  scratch: radix_scratch_bytes(N).
+// Stable LSD radix sort of N keys on bits [first_bit, first_bit + nbits):
+// ping-pongs between a and b and returns the buffer holding the result.
+// scratch: radix_scratch_bytes(N).
 size_t radix_scratch_bytes(int64_t N);
 uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch,
-                         hipStream_t s);
+                         hipStream_t s, int first_bit = 0);
 // Distinct keys of a sorted array, MCD_SENTINEL excluded, into out; the count
 // goes to *d_count (device).  scratch: compact_scratch_bytes(N).
 size_t compact_scratch_bytes(int64_t N);
@@ -117,10 +118,12 @@ void launch_scatter_by_perm(const int32_t* val_new, const int32_t* perm, int64_t
 // in_cnt[v] = deg[v] - outdeg[v]
 void launch_in_count(const int32_t* deg, const int32_t* outdeg, int64_t n, int32_t* in_cnt,
                      hipStream_t s);
-// in_ea[in_off[v] + k] = (e, off[src[e]+1] - e - 1) for the edges e with head v
-// (fill: zeroed int32[n] counters)
-void launch_in_scatter(const int32_t* src, const int32_t* adj, const int64_t* off, int64_t m,
-                       const int64_t* in_off, int32_t* fill, int2* in_ea, hipStream_t s);
+// keys[e] = (head of e) << 32 | e, to be sorted on the head bits, and
+// suf[e] = off[src[e]+1] - e - 1
+void launch_in_keys(const int32_t* src, const int32_t* adj, const int64_t* off, int64_t m, uint64_t* keys,
+                    int32_t* suf, hipStream_t s);
+// in_ea[i] = (e, suf[e]) for the edges e of the head-sorted keys
+void launch_in_fill(const uint64_t* sorted, const int32_t* suf, int64_t m, int2* in_ea, hipStream_t s);
 
 // ---- triangles (tc.hip) ----
 size_t tc_scratch_bytes(const mcd_graph* g, int64_t chunk);

@@ -336,7 +336,7 @@ void fill_any(T* p, int64_t N, T v, hipStream_t s) {
 size_t radix_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * 256 * (kMaxBlocks + 1)); }
 
 uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch,
-                         hipStream_t s) {
+                         hipStream_t s, int first_bit) {
     if (N <= 1 || nbits <= 0) return a;
     const int64_t ntiles = div_up(N, kTile);
     const int NB = grid_blocks(ntiles);
@@ -345,7 +345,7 @@ uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* s
     int64_t* tot = counts + (int64_t)256 * kMaxBlocks;
     const int passes = (nbits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        const int shift = first_bit + 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(NB), dim3(kThreads), 0, s, a, N, shift, tpb, NB, counts);
         hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kThreads), 0, s, counts, NB, tot);
         hipLaunchKernelGGL(k_rs_scatter, dim3(NB), dim3(kThreads), 0, s, a, b, N, shift, tpb, NB,

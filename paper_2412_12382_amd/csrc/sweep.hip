@@ -122,6 +122,15 @@ __device__ __forceinline__ bool root_table_add(int32_t* key, uint32_t* val, int3
 // and hist[g][level] (edge counts): with one graph the lanes of a wave that
 // share a level are counted with one ballot, else an LDS histogram of
 // (graph, level) when it fits.
+// sign(a/b - c/d) for b, d > 0 in 64-bit products, exact when |a|, |c| < 2^31
+// and b, d < 2^32 (NARROW inputs: every degree below 2^29, thresholds below
+// 2^31 in magnitude)
+__device__ __forceinline__ int rat_cmp64(int64_t a, int64_t b, int64_t c, int64_t d) {
+    const int64_t l = a * d, r = c * b;
+    return (l > r) - (l < r);
+}
+
+template <bool NARROW>
 __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ src,
                                                     const int32_t* __restrict__ dsum,
                                                     const int32_t* __restrict__ t, int64_t m, int measure,
@@ -143,7 +152,9 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
         int lo = 0, hi = ds.K;  // first threshold that prunes e
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (rat_cmp(num, den, ds.num[mid], ds.den[mid]) >= 0) lo = mid + 1;
+            const int c = NARROW ? rat_cmp64(num, den, ds.num[mid], ds.den[mid])
+                                 : rat_cmp(num, den, ds.num[mid], ds.den[mid]);
+            if (c >= 0) lo = mid + 1;
             else hi = mid;
         }
         level[e] = (uint8_t)lo;
@@ -523,8 +534,13 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
         hipLaunchKernelGGL(k_vertex_info, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->perm, n, vbase, G,
                            truth, L.gid, L.cls);
     if (m > 0) {
-        hipLaunchKernelGGL(k_level, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->dsum, t, m,
-                           measure, ds, L.level, L.gid, G, L.hist);
+        // thresholds reach the kernel validated to |num|, den < 2^31
+        if (g->max_deg < (1 << 29))
+            hipLaunchKernelGGL(k_level<true>, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->dsum, t, m,
+                               measure, ds, L.level, L.gid, G, L.hist);
+        else
+            hipLaunchKernelGGL(k_level<false>, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->dsum, t,
+                               m, measure, ds, L.level, L.gid, G, L.hist);
     }
     if (truth && n > 0) {
         fill_t<int32_t>(L.csize, n, 0, s);
