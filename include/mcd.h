@@ -11,6 +11,8 @@
  *     wedge(u,v)  = |N(u) u N(v)| - |N(u) n N(v)| - 2
  *     Tectonic    = t(u,v) / (deg u + deg v)
  *     TW          = t(u,v) - wedge(u,v) = 3 t - deg u - deg v + 2   (Eq. eq:tw)
+ *     K3          = t(u,v)
+ *     Jaccard     = t(u,v) / (deg u + deg v - t(u,v))
  *
  * Conventions
  *   - Every call returns mcd_status: MCD_OK (0) or a negative error.  Nothing
@@ -65,7 +67,10 @@ typedef struct {
 /* Similarity measures of Table tab:simfunctions that the library evaluates. */
 typedef enum {
     MCD_SIM_TECTONIC = 0, /* t / (deg u + deg v)                      */
-    MCD_SIM_TW = 1        /* t - wedge = 3t - deg u - deg v + 2       */
+    MCD_SIM_TW = 1,       /* t - wedge = 3t - deg u - deg v + 2       */
+    MCD_SIM_K3 = 2,       /* t, the number of triangles on the edge   */
+    MCD_SIM_JACCARD = 3   /* t / (deg u + deg v - t) = |N(u) n N(v)| / |N(u) u N(v)|;
+                             Prop. 1: pruning it at p/q equals pruning Tectonic at p/(p+q) */
 } mcd_measure;
 
 /* ---------------------------------------------------------------- context */
@@ -170,15 +175,16 @@ mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t w
 
 /* Edge similarity of Table tab:simfunctions from t (as produced by
  * mcd_triangles).  w_f32 (device float[m], may be NULL): the measure in IEEE
- * fp32, Tectonic as the correctly rounded quotient t / (deg u + deg v).
- * w_i32 (device int32[m], may be NULL; TW only): the exact integer TW. */
+ * fp32; Tectonic and Jaccard as the correctly rounded quotient.
+ * w_i32 (device int32[m], may be NULL; TW and K3 only): the exact integer. */
 mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t, float* w_f32,
                        int32_t* w_i32);
 
 /* Algorithm 1, first step: edge e is removed iff sim(e) < delta, so it is
  * kept iff NOT (sim(e) < delta); ties are kept.  The decision is exact
- * integer arithmetic: Tectonic keeps iff t den >= num (deg u + deg v), TW
- * keeps iff TW den >= num.
+ * integer arithmetic on sim = sn / sd: Tectonic keeps iff t den >= num (deg u
+ * + deg v), TW iff TW den >= num, K3 iff t den >= num, Jaccard iff t den >=
+ * num (deg u + deg v - t).
  *   keep_bits: device uint32[ceil(m/32)], bit (e % 32) of word e / 32.
  *   n_kept:    device int64[1] (may be NULL), the number of kept edges. */
 mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
@@ -196,7 +202,7 @@ mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, 
  *               deltas[2k] / deltas[2k+1] (den > 0; the comparison is exact in
  *               128-bit arithmetic); graph k owns the original ids
  *               [vbase[k], vbase[k+1]) (vbase: device int64[n_graphs+1]).
- *   w_f32, w_i32: as mcd_weights (each may be NULL; w_i32 for TW only).
+ *   w_f32, w_i32: as mcd_weights (each may be NULL; w_i32 for TW and K3 only).
  *   keep_bits:  as mcd_prune (may be NULL).
  *   kept_pairs, kept_counts: the kept edges as a segmented list, the input of
  *               mcd_components_kept (both NULL, or both given).  The edges,

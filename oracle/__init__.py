@@ -22,7 +22,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 _lib = None
 
-TECTONIC, TW = 0, 1
+TECTONIC, TW, K3, JACCARD = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -46,6 +46,7 @@ def lib():
         L.or_adjacency.argtypes = [I64, I64, P, P, P, P, P]
         L.or_triangles.argtypes = [I64, P, P, P, P]
         L.or_tectonic.argtypes = [I64, P, P, P, P, P]
+        L.or_jaccard.argtypes = [I64, P, P, P, P, P]
         L.or_wedges.argtypes = [I64, P, P, P, P, P]
         L.or_tw.argtypes = [I64, P, P, P, P, P]
         L.or_prune.argtypes = [I64, ctypes.c_int, P, P, P, P, I64, I64, P, P]
@@ -118,6 +119,12 @@ def triangles(n: int, lo, hi):
 def tectonic(lo, hi, t, deg):
     w = np.empty(max(len(lo), 1), np.float64)
     lib().or_tectonic(len(lo), _p(lo), _p(hi), _p(t), _p(deg), _p(w))
+    return w[:len(lo)]
+
+
+def jaccard(lo, hi, t, deg):
+    w = np.empty(max(len(lo), 1), np.float64)
+    lib().or_jaccard(len(lo), _p(lo), _p(hi), _p(t), _p(deg), _p(w))
     return w[:len(lo)]
 
 
@@ -198,7 +205,8 @@ def run(n: int, src, dst, measure: int, num: int, den: int, timings: dict | None
     t = triangles(n, lo, hi)
     t2 = time.perf_counter()
     keep = prune(measure, lo, hi, t, deg, num, den)
-    w = tectonic(lo, hi, t, deg) if measure == TECTONIC else tw(lo, hi, t, deg)
+    w = {TECTONIC: lambda: tectonic(lo, hi, t, deg), TW: lambda: tw(lo, hi, t, deg),
+         K3: lambda: t.astype(np.int64), JACCARD: lambda: jaccard(lo, hi, t, deg)}[measure]()
     t3 = time.perf_counter()
     labels, ncc = components(n, lo, hi, keep)
     t4 = time.perf_counter()
@@ -225,13 +233,14 @@ def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None):
         keep = prune(measure, lo, hi, t, deg, num, den)
         labels, _ = components(n, lo, hi, keep)
         labels_all[i] = labels
+        kept_per_graph = np.bincount(egraph, weights=keep, minlength=G).astype(np.int64)
         for gk in range(G):
             a, b = vbase[gk], vbase[gk + 1]
             lab = labels[a:b]
             nv = b - a
             roots = np.count_nonzero(lab == np.arange(a, b))
             sizes = np.bincount(lab - a, minlength=max(nv, 1)) if nv else np.zeros(1, np.int64)
-            row = [int(keep[egraph == gk].sum()), roots, int(sizes.max()) if nv else 0]
+            row = [int(kept_per_graph[gk]), roots, int(sizes.max()) if nv else 0]
             if truth is not None and nv:
                 v, sums = ari(lab, truth[a:b])
                 row += [int(sums[1]), int(sums[2]), int(sums[0]), int(sums[3])]

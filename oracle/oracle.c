@@ -177,19 +177,39 @@ void or_tw(int64_t m, const int32_t* lo, const int32_t* hi, const int32_t* t,
     free(wedge);
 }
 
+/* Jaccard coefficient of the neighbourhoods, t / (deg u + deg v - t)
+ * (Table tab:simfunctions; |N(u) u N(v)| by inclusion-exclusion), in fp64. */
+void or_jaccard(int64_t m, const int32_t* lo, const int32_t* hi, const int32_t* t, const int32_t* deg,
+                double* w) {
+    for (int64_t e = 0; e < m; ++e)
+        w[e] = (double)t[e] / ((double)deg[lo[e]] + (double)deg[hi[e]] - (double)t[e]);
+}
+
 /* Exact sign of a/b - c/d for b,d > 0: sign(a d - c b). */
 static int rat_cmp(int64_t a, int64_t b, int64_t c, int64_t d) {
     __int128 l = (__int128)a * d, r = (__int128)c * b;
     return (l > r) - (l < r);
 }
 
+/* sim(e) of Table tab:simfunctions as an exact rational num : den, den > 0.
+ * measure 0 Tectonic: t : (deg u + deg v);  1 TW: tw : 1 (tw = t - wedge,
+ * precomputed);  2 K3 (triangles on the edge): t : 1;  3 Jaccard:
+ * t : (deg u + deg v - t). */
+static void sim_rat(int measure, int64_t t, int64_t du, int64_t dv, int64_t tw, int64_t* num, int64_t* den) {
+    switch (measure) {
+        case 0: *num = t; *den = du + dv; break;
+        case 1: *num = tw; *den = 1; break;
+        case 2: *num = t; *den = 1; break;
+        default: *num = t; *den = du + dv - t; break;
+    }
+}
+
 /* Algorithm 1, first step: edge e is removed iff sim(e) < delta, so it is kept
- * iff NOT (sim(e) < delta).  delta = num/den with den > 0 is compared exactly.
- * measure 0: sim = t/(deg u + deg v) as the exact rational t : (deg u + deg v).
- * measure 1: sim = TW(e), an integer. */
+ * iff NOT (sim(e) < delta).  delta = num/den with den > 0 is compared exactly
+ * with the rational form of sim (sim_rat). */
 int or_prune(int64_t m, int measure, const int32_t* lo, const int32_t* hi, const int32_t* t,
              const int32_t* deg, int64_t num, int64_t den, unsigned char* keep, int64_t* n_kept) {
-    if (den <= 0) return OR_ERR_ARG;
+    if (den <= 0 || measure < 0 || measure > 3) return OR_ERR_ARG;
     int64_t* tw = NULL;
     if (measure == 1) {
         tw = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
@@ -197,11 +217,9 @@ int or_prune(int64_t m, int measure, const int32_t* lo, const int32_t* hi, const
     }
     int64_t k = 0;
     for (int64_t e = 0; e < m; ++e) {
-        int below;
-        if (measure == 0)
-            below = rat_cmp(t[e], (int64_t)deg[lo[e]] + deg[hi[e]], num, den) < 0;
-        else
-            below = rat_cmp(tw[e], 1, num, den) < 0;
+        int64_t sn, sd;
+        sim_rat(measure, t[e], deg[lo[e]], deg[hi[e]], tw ? tw[e] : 0, &sn, &sd);
+        const int below = rat_cmp(sn, sd, num, den) < 0;
         keep[e] = below ? 0 : 1;
         k += keep[e];
     }
@@ -271,12 +289,13 @@ static int cmp_rat(const void* a, const void* b) {
 
 /* Nearest-rank percentile pn/pd of the nonzero similarity values: with K of
  * them sorted ascending (exact rational order), the value at 0-based index
- * ceil(pn K / pd) - 1 (clamped to 0).  Returned as num/den (den = 1 for TW).
+ * ceil(pn K / pd) - 1 (clamped to 0).  Returned as num/den (den = 1 for TW
+ * and K3).
  * Returns OR_ERR_EMPTY when every value is zero. */
 int or_percentile(int64_t m, int measure, const int32_t* lo, const int32_t* hi,
                   const int32_t* t, const int32_t* deg, int64_t pn, int64_t pd,
                   int64_t* out_num, int64_t* out_den) {
-    if (pd <= 0 || pn < 0 || pn > pd) return OR_ERR_ARG;
+    if (pd <= 0 || pn < 0 || pn > pd || measure < 0 || measure > 3) return OR_ERR_ARG;
     rat_t* v = (rat_t*)malloc(sizeof(rat_t) * (size_t)(m > 0 ? m : 1));
     int64_t* tw = NULL;
     if (measure == 1) {
@@ -286,13 +305,7 @@ int or_percentile(int64_t m, int measure, const int32_t* lo, const int32_t* hi,
     int64_t K = 0;
     for (int64_t e = 0; e < m; ++e) {
         rat_t r;
-        if (measure == 0) {
-            r.num = t[e];
-            r.den = (int64_t)deg[lo[e]] + deg[hi[e]];
-        } else {
-            r.num = tw[e];
-            r.den = 1;
-        }
+        sim_rat(measure, t[e], deg[lo[e]], deg[hi[e]], tw ? tw[e] : 0, &r.num, &r.den);
         if (r.num != 0) v[K++] = r;
     }
     free(tw);

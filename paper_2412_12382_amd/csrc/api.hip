@@ -40,6 +40,10 @@ mcd_status use_device(const mcd_ctx* ctx) {
     return MCD_OK;
 }
 
+bool valid_measure(int m) {
+    return m == MCD_SIM_TECTONIC || m == MCD_SIM_TW || m == MCD_SIM_K3 || m == MCD_SIM_JACCARD;
+}
+
 mcd_status check_delta(mcd_rational d) {
     REQUIRE(d.den > 0, MCD_ERR_INVALID_ARG, "threshold denominator must be positive");
     REQUIRE(d.den < ((int64_t)1 << 31) && d.num < ((int64_t)1 << 31) && d.num > -((int64_t)1 << 31),
@@ -463,9 +467,9 @@ mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t w
 mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t, float* w_f32,
                        int32_t* w_i32) {
     REQUIRE(g && (g->m == 0 || t), MCD_ERR_INVALID_ARG, "NULL argument");
-    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
-    REQUIRE(!(measure == MCD_SIM_TECTONIC && w_i32), MCD_ERR_INVALID_ARG,
-            "integer weights exist for TW only");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3, MCD_ERR_INVALID_ARG,
+            "integer weights exist for TW and K3 only");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_weights(g, measure, t, w_f32, w_i32, g->ctx->stream);
@@ -475,7 +479,7 @@ mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t
 mcd_status mcd_prune(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
                      uint32_t* keep_bits, int64_t* n_kept) {
     REQUIRE(g && (g->m == 0 || (t && keep_bits)), MCD_ERR_INVALID_ARG, "NULL argument");
-    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
     mcd_status st = check_delta(delta);
     if (st != MCD_OK) return st;
     if ((st = use_device(g->ctx)) != MCD_OK) return st;
@@ -513,8 +517,9 @@ mcd_status mcd_weigh_prune(const mcd_graph* g, mcd_measure measure, const int32_
                            int64_t* n_kept) {
     REQUIRE(g, MCD_ERR_INVALID_ARG, "graph is NULL");
     REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
-    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
-    REQUIRE(!(measure == MCD_SIM_TECTONIC && w_i32), MCD_ERR_INVALID_ARG, "integer weights exist for TW only");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3, MCD_ERR_INVALID_ARG,
+            "integer weights exist for TW and K3 only");
     REQUIRE((kept_pairs == nullptr) == (kept_counts == nullptr), MCD_ERR_INVALID_ARG,
             "kept_pairs and kept_counts go together");
     mcd_status st;
@@ -550,7 +555,7 @@ mcd_status mcd_run_workspace_size(const mcd_graph* g, size_t* bytes) {
 mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, int32_t* labels,
                    int64_t* n_components, void* ws, size_t ws_bytes) {
     REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
-    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
     mcd_status st = check_delta(delta);
     if (st != MCD_OK) return st;
     size_t need = 0;
@@ -582,7 +587,7 @@ mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                      int32_t* labels, void* ws, size_t ws_bytes) {
     REQUIRE(g && host_deltas && vbase && stats && ws, MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
-    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
     size_t need = 0;
     mcd_status st = mcd_sweep_workspace_size(g, n_graphs, n_thresholds, truth != nullptr, &need);
     if (st != MCD_OK) return st;
@@ -711,7 +716,7 @@ mcd_status mcd_prune_graphs(const mcd_graph* g, mcd_measure measure, const int32
                             int64_t* n_kept) {
     REQUIRE(g && vbase && deltas && (g->m == 0 || (t && keep_bits)), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "need n_graphs >= 1");
-    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_prune_graphs(g, measure, t, n_graphs, vbase, deltas, keep_bits, n_kept, g->ctx->stream);
@@ -728,7 +733,7 @@ mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, con
                                     int64_t pct_num, int64_t pct_den, void* ws, size_t ws_bytes,
                                     mcd_rational* host_out) {
     REQUIRE(g && t && ws && host_out, MCD_ERR_INVALID_ARG, "NULL argument");
-    REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW, MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
     REQUIRE(pct_den > 0 && pct_num >= 0 && pct_num <= pct_den && pct_den < ((int64_t)1 << 31),
             MCD_ERR_INVALID_ARG, "percentile must be a fraction in [0, 1] with den below 2^31");
     size_t need = 0;
@@ -763,7 +768,7 @@ mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, con
         prefix |= (uint32_t)d << shift;
         pmask |= 255u << shift;
     }
-    if (measure == MCD_SIM_TW) {
+    if (measure == MCD_SIM_TW || measure == MCD_SIM_K3) {  // integer similarities: the key is the value
         host_out->num = (int64_t)(int32_t)(prefix ^ 0x80000000u);
         host_out->den = 1;
         return MCD_OK;

@@ -33,17 +33,17 @@ __device__ __forceinline__ Sim sim_of(const int32_t* __restrict__ dsum, const in
     Sim s;
     const int64_t D = (uint32_t)dsum[e];
     const int32_t tt = t[e];
-    if (measure == MCD_SIM_TECTONIC) {
-        s.num = tt;
-        s.den = D;
-        s.nonzero = tt != 0;
-        s.key = __float_as_uint((float)tt / (float)D);
-    } else {
-        const int32_t tw = (int32_t)(3 * (int64_t)tt - D + 2);
-        s.num = tw;
+    if (measure == MCD_SIM_TW || measure == MCD_SIM_K3) {  // integers: key = the value, sign-flipped
+        const int32_t x = measure == MCD_SIM_K3 ? tt : (int32_t)(3 * (int64_t)tt - D + 2);
+        s.num = x;
         s.den = 1;
-        s.nonzero = tw != 0;
-        s.key = (uint32_t)tw ^ 0x80000000u;
+        s.nonzero = x != 0;
+        s.key = (uint32_t)x ^ 0x80000000u;
+    } else {  // non-negative rationals: key = fp32 value (monotone in the exact value)
+        s.num = tt;
+        s.den = measure == MCD_SIM_JACCARD ? D - tt : D;
+        s.nonzero = tt != 0;
+        s.key = __float_as_uint((float)tt / (float)s.den);
     }
     return s;
 }

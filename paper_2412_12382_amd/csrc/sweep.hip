@@ -147,8 +147,10 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
     GRID_STRIDE(e, m) {
         const int64_t D = (uint32_t)dsum[e];
         const int64_t tt = t[e];
-        const int64_t num = measure == MCD_SIM_TECTONIC ? tt : 3 * tt - D + 2;
-        const int64_t den = measure == MCD_SIM_TECTONIC ? D : 1;
+        int64_t num = tt, den = 1;  // K3
+        if (measure == MCD_SIM_TECTONIC) den = D;
+        else if (measure == MCD_SIM_JACCARD) den = D - tt;
+        else if (measure == MCD_SIM_TW) num = 3 * tt - D + 2;
         int lo = 0, hi = ds.K;  // first threshold that prunes e
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;

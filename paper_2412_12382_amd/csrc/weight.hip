@@ -1,10 +1,11 @@
 // Edge similarities (Table tab:simfunctions) and the prune step of Algorithm 1.
 //
-// Tectonic(e) = t / D and TW(e) = 3t - D + 2 with D = deg u + deg v; the TW
-// form is t - wedge with |N(u) u N(v)| = deg u + deg v - t (Eq. eq:tw and the
-// notation paragraph of Sec. 1).  The keep decision never uses floating point:
-// with delta = num/den (den > 0), Tectonic keeps iff t*den >= num*D and TW
-// keeps iff TW*den >= num, evaluated in 128-bit integers.
+// With D = deg u + deg v: Tectonic(e) = t / D, TW(e) = 3t - D + 2 (t - wedge
+// with |N(u) u N(v)| = D - t, Eq. eq:tw and the notation paragraph of Sec. 1),
+// K3(e) = t (triangles on the edge) and Jaccard(e) = t / (D - t).  Every
+// similarity is an exact rational sn / sd and the keep decision never uses
+// floating point: with delta = num/den (den > 0) an edge is kept iff
+// sn * den >= num * sd, in 64- or 128-bit integers.
 #include "common.hpp"
 
 namespace mcd {
@@ -22,13 +23,13 @@ __device__ __forceinline__ int graph_of(const int64_t* __restrict__ vbase, int G
     return lo;
 }
 
-// Tectonic in fp32, correctly rounded: a single fp32 division is exact-input
-// and correctly rounded while both operands fit 24 bits; beyond that the
-// quotient is formed in fp64 and rounded once more, which is innocuous for a
-// single division (53 >= 2 * 24 + 2).
-__device__ __forceinline__ float tectonic_f32(int32_t t, int64_t D) {
-    if (t < (1 << 24) && D < (1 << 24)) return (float)t / (float)D;
-    return (float)((double)t / (double)D);
+// t / d in fp32, correctly rounded (Tectonic, Jaccard): a single fp32
+// division is exact-input and correctly rounded while both operands fit 24
+// bits; beyond that the quotient is formed in fp64 and rounded once more,
+// which is innocuous for a single division (53 >= 2 * 24 + 2).
+__device__ __forceinline__ float ratio_f32(int32_t t, int64_t d) {
+    if (t < (1 << 24) && d < (1 << 24)) return (float)t / (float)d;
+    return (float)((double)t / (double)d);
 }
 
 constexpr int kUnroll = 8;  // 64-edge groups in flight per wave
@@ -90,12 +91,12 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
             if (e < e1) {
                 const int64_t D = (uint32_t)dd[j];  // deg u + deg v < 2^32
                 int64_t sn, sd;
-                if (MEASURE == MCD_SIM_TECTONIC) {
-                    if (wf) wf[e] = tectonic_f32(tt[j], D);
+                if (MEASURE == MCD_SIM_TECTONIC || MEASURE == MCD_SIM_JACCARD) {
                     sn = tt[j];
-                    sd = D;
+                    sd = MEASURE == MCD_SIM_TECTONIC ? D : D - tt[j];  // D - t >= t + 2 > 0
+                    if (wf) wf[e] = ratio_f32(tt[j], sd);
                 } else {
-                    sn = 3 * (int64_t)tt[j] - D + 2;
+                    sn = MEASURE == MCD_SIM_K3 ? (int64_t)tt[j] : 3 * (int64_t)tt[j] - D + 2;
                     sd = 1;
                     if (wi) wi[e] = (int32_t)sn;
                     if (wf) wf[e] = (float)sn;
@@ -157,12 +158,23 @@ void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64
         if (narrow) hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, true>), grid, block, 0, s, MCD_WP_ARGS);  \
         else hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, false>), grid, block, 0, s, MCD_WP_ARGS);       \
     } while (0)
-    if (measure == MCD_SIM_TECTONIC) {
-        if (multi) MCD_WP_LAUNCH(MCD_SIM_TECTONIC, true);
-        else MCD_WP_LAUNCH(MCD_SIM_TECTONIC, false);
-    } else {
-        if (multi) MCD_WP_LAUNCH(MCD_SIM_TW, true);
-        else MCD_WP_LAUNCH(MCD_SIM_TW, false);
+    switch (measure) {
+        case MCD_SIM_TECTONIC:
+            if (multi) MCD_WP_LAUNCH(MCD_SIM_TECTONIC, true);
+            else MCD_WP_LAUNCH(MCD_SIM_TECTONIC, false);
+            break;
+        case MCD_SIM_TW:
+            if (multi) MCD_WP_LAUNCH(MCD_SIM_TW, true);
+            else MCD_WP_LAUNCH(MCD_SIM_TW, false);
+            break;
+        case MCD_SIM_K3:
+            if (multi) MCD_WP_LAUNCH(MCD_SIM_K3, true);
+            else MCD_WP_LAUNCH(MCD_SIM_K3, false);
+            break;
+        default:
+            if (multi) MCD_WP_LAUNCH(MCD_SIM_JACCARD, true);
+            else MCD_WP_LAUNCH(MCD_SIM_JACCARD, false);
+            break;
     }
 #undef MCD_WP_LAUNCH
 #undef MCD_WP_ARGS

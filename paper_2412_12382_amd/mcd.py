@@ -21,6 +21,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "mcd.h")
 
 MCD_SIM_TECTONIC = 0
 MCD_SIM_TW = 1
+MCD_SIM_K3 = 2
+MCD_SIM_JACCARD = 3
 
 STATUS = {0: "MCD_OK", -1: "MCD_ERR_INVALID_ARG", -2: "MCD_ERR_INVALID_VERTEX", -3: "MCD_ERR_RANGE",
           -4: "MCD_ERR_WORKSPACE", -5: "MCD_ERR_NO_DEVICE", -6: "MCD_ERR_DEVICE",

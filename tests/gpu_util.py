@@ -46,11 +46,12 @@ def gpu_all(src, dst, n, measure, delta):
     lo, hi, order = canonical_order(g)
     deg = M.mcd_graph_degrees(g).cpu().numpy()
     t = M.mcd_triangles(g)
-    wf, wi = M.mcd_weights(g, measure, t, want_f32=True, want_i32=(measure == M.MCD_SIM_TW))
+    ints = measure in (M.MCD_SIM_TW, M.MCD_SIM_K3)
+    wf, wi = M.mcd_weights(g, measure, t, want_f32=True, want_i32=ints)
     keep, nk = M.mcd_prune(g, measure, t, delta)
     labels, ncc = M.mcd_components(g, keep)
     labels_run, ncc_run = M.mcd_run(g, measure, delta)
-    fused = M.mcd_weigh_prune(g, measure, t, delta=delta, want_i32=(measure == M.MCD_SIM_TW))
+    fused = M.mcd_weigh_prune(g, measure, t, delta=delta, want_i32=ints)
     labels_k, ncc_k = M.mcd_components_kept(g, fused["kept"])
     torch.cuda.synchronize()
     out = dict(g=g, lo=lo, hi=hi, deg=deg[:n], t=t.cpu().numpy()[order],

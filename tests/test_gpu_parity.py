@@ -31,12 +31,12 @@ def check_all(src, dst, n, measure, delta):
         assert r["g"].max_deg == deg.max()
     t = oracle.triangles(n, lo, hi)
     assert np.array_equal(r["t"], t)
-    if measure == oracle.TECTONIC:
-        w = oracle.tectonic(lo, hi, t, deg)
+    if measure in (oracle.TECTONIC, oracle.JACCARD):
+        w = (oracle.tectonic if measure == oracle.TECTONIC else oracle.jaccard)(lo, hi, t, deg)
         assert np.all(np.abs(r["w"].astype(np.float64) - w) <= 1e-6 * np.abs(w))
         assert np.all((r["w"] == 0) == (w == 0))
     else:
-        tw = oracle.tw(lo, hi, t, deg)
+        tw = oracle.tw(lo, hi, t, deg) if measure == oracle.TW else t.astype(np.int64)
         assert np.array_equal(r["tw"].astype(np.int64), tw)
         assert np.array_equal(r["w"].astype(np.float64), tw.astype(np.float64))
     keep = oracle.prune(measure, lo, hi, t, deg, *delta)
@@ -47,7 +47,7 @@ def check_all(src, dst, n, measure, delta):
     assert np.array_equal(r["labels_run"], labels) and r["ncc_run"] == ncc
     f = r["fused"]  # one-pass weights + prune, kept list, components over it
     assert np.array_equal(f["w"].view(np.int32), r["w"].view(np.int32))
-    if measure == oracle.TW:
+    if measure in (oracle.TW, oracle.K3):
         assert np.array_equal(f["tw"], r["tw"])
     assert np.array_equal(f["keep"], keep) and f["n_kept"] == int(keep.sum())
     assert np.array_equal(f["kept_u"], f["want_u"]) and np.array_equal(f["kept_v"], f["want_v"])
@@ -111,7 +111,7 @@ def test_rmat_percentile_thresholds():
     t = oracle.triangles(n, lo, hi)
     g = build(s, d, n)
     tg = M.mcd_triangles(g)
-    for measure in (oracle.TECTONIC, oracle.TW):
+    for measure in (oracle.TECTONIC, oracle.TW, oracle.K3, oracle.JACCARD):
         for pn, pd in ((3, 10), (1, 2), (1, 1), (1, 1000), (0, 1)):
             want = Fraction(*oracle.percentile(measure, lo, hi, t, deg, pn, pd))
             num, den = M.mcd_percentile_threshold(g, measure, tg, pn, pd)
@@ -218,3 +218,30 @@ def test_autotuner_sets_params_and_keeps_counts():
     for k, v in (("tc_chunk", 512), ("tc_lds_max", 4096), ("tc_packed_range", (1 << 20) - 2),
                  ("tc_window_max", 1 << 18)):
         M.mcd_ctx_set_param(g.ctx, k, v)
+
+
+@pytest.mark.parametrize("scale", [12, 15])
+def test_rmat_k3_and_jaccard(scale):
+    s, d, n = gg.rmat(scale, seed=100 + scale)
+    check_all(s, d, n, oracle.K3, (2, 1))
+    check_all(s, d, n, oracle.JACCARD, (1, 20))
+
+
+def test_c1_sbm_k3_and_jaccard():
+    c1 = gg.sbm_c1()
+    check_all(c1["src"], c1["dst"], c1["n"], oracle.K3, (4, 1))
+    check_all(c1["src"], c1["dst"], c1["n"], oracle.JACCARD, (3, 47))
+
+
+def test_prop1_on_the_gpu():
+    # Proposition 1: the GPU's Jaccard-prune at p/q and Tectonic-prune at
+    # p/(p+q) produce the same keep bits
+    from gpu_util import build
+    s, d, n = gg.rmat(14, seed=77)
+    g = build(s, d, n)
+    t = M.mcd_triangles(g)
+    words = (g.m + 31) // 32
+    for p, q in ((1, 20), (1, 9), (1, 3), (2, 5), (1, 1), (0, 1), (7, 93)):
+        kj, nj = M.mcd_prune(g, M.MCD_SIM_JACCARD, t, (p, q))
+        kt, nt = M.mcd_prune(g, M.MCD_SIM_TECTONIC, t, (p, p + q))
+        assert torch.equal(kj[:words], kt[:words]) and int(nj.item()) == int(nt.item())

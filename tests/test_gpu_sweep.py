@@ -101,3 +101,11 @@ def test_sweep_matches_single_threshold_pipeline():
         assert torch.equal(lab, labels[k, :n])
         assert int(ncc.item()) == int(stats[0, k, 1].item())
         assert int(nk.item()) == int(stats[0, k, 0].item())
+
+
+def test_sweep_k3_and_jaccard():
+    s, d, n = gg.rmat(13, seed=34)
+    k3 = [(k, 1) for k in (0, 1, 2, 3, 5, 8, 13, 40)]
+    compare(gpu_sweep(s, d, n, oracle.K3, k3), oracle_sweep(s, d, n, oracle.K3, k3))
+    jac = [(k, 100) for k in range(0, 60, 4)]
+    compare(gpu_sweep(s, d, n, oracle.JACCARD, jac), oracle_sweep(s, d, n, oracle.JACCARD, jac))

@@ -439,3 +439,31 @@ def test_expected_table_two_block_sbm():
     assert rel(D[across].mean() / nb, p1 + p2 + 2 * q) < 0.05
     tw = oracle.tw(lo, hi, t, deg)
     assert rel(tw[inside1].mean() / nb, 3 * p1 ** 2 - 2 * p1 + 3 * q ** 2 - 2 * q) < 0.05
+
+
+def test_prop1_jaccard_measure_equals_reparameterised_tectonic():
+    # Proposition 1 between two of the oracle's own measures: Jaccard-prune at
+    # p/q keeps exactly the edges Tectonic-prune keeps at p/(p+q); and the
+    # Jaccard weight w_J relates to Tectonic w_T by w_J = w_T / (1 - w_T).
+    s, d, n = gg.rmat(11, seed=12)
+    lo, hi = oracle.canon(n, s, d)
+    deg = oracle.degrees(n, lo, hi)
+    t = oracle.triangles(n, lo, hi)
+    for p, q in ((1, 20), (1, 9), (1, 3), (2, 5), (1, 1), (0, 1)):
+        assert np.array_equal(oracle.prune(oracle.JACCARD, lo, hi, t, deg, p, q),
+                              oracle.prune(oracle.TECTONIC, lo, hi, t, deg, p, p + q))
+    wt = oracle.tectonic(lo, hi, t, deg)
+    assert np.allclose(oracle.jaccard(lo, hi, t, deg), wt / (1 - wt), rtol=1e-12)
+
+
+def test_k3_measure_closed_forms():
+    # K_n: every edge lies in n - 2 triangles; K3-prune at n - 2 keeps all
+    # edges, at n - 1 none (ties kept).  A path has no triangles.
+    for k in (4, 6):
+        lo, hi, deg, t = full(k, complete(k))
+        assert oracle.prune(oracle.K3, lo, hi, t, deg, k - 2, 1).all()
+        assert not oracle.prune(oracle.K3, lo, hi, t, deg, k - 1, 1).any()
+        assert oracle.prune(oracle.K3, lo, hi, t, deg, 2 * k - 5, 2).all()  # (k-2.5) < k-2
+    lo, hi, deg, t = full(4, [(0, 1), (1, 2), (2, 3)])
+    assert oracle.prune(oracle.K3, lo, hi, t, deg, 0, 1).all()
+    assert not oracle.prune(oracle.K3, lo, hi, t, deg, 1, 3).any()
