@@ -228,7 +228,7 @@ def main():
     pidx = torch.empty(1, dtype=torch.int32, device=dev)
     pdelta = torch.empty((1, 2), dtype=torch.int64, device=dev)
     grid16 = [(k, 50) for k in range(16)]
-    sweep_stats = torch.empty((1, 16, 7), dtype=torch.int64, device=dev)
+    sweep_stats = torch.empty((1, 16, len(M.SWEEP_FIELDS)), dtype=torch.int64, device=dev)
     log(f"HBM in use after allocation: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)

@@ -257,6 +257,9 @@ typedef struct {
     int64_t pairs_class;       /* B: vertex pairs that share a planted class (or 0)  */
     int64_t pairs_both;        /* S: vertex pairs that share both (or 0)             */
     int64_t pairs_total;       /* N = n_g (n_g - 1) / 2                               */
+    int64_t intra_edges;       /* input edges inside one component (with modularity) */
+    int64_t volume_sq;         /* sum over components of (sum of input degrees)^2,
+                                  exact while 2m < 2^31.5 (with modularity)          */
 } mcd_sweep_stats;
 
 /* Most thresholds one mcd_sweep call evaluates. */
@@ -274,7 +277,11 @@ mcd_status mcd_sweep_workspace_size(const mcd_graph* g, int32_t n_graphs, int32_
  * (the selection statistics of Sec. 4.4: kept edges, number of components,
  * largest component).  With planted labels `truth`, the adjusted Rand index
  * ARI = (S - A B / N) / ((A + B) / 2 - A B / N) (1 when the denominator is 0)
- * is evaluated in fp64 from the exact pair counts.
+ * is evaluated in fp64 from the exact pair counts.  With `modularity`, each
+ * partition's modularity on the input graph (Sec. 2), Q = intra / m -
+ * volume_sq / (4 m^2) in fp64 from the exact integers of the stats, m the
+ * graph's edges (0 for a graph without edges); this adds a pass over the
+ * edges per threshold.
  *   host_deltas: K thresholds (any order, duplicates allowed), K <= 64.
  *   vbase:       device int64[n_graphs + 1], vbase[0] = 0, vbase[n_graphs] = n,
  *                non-decreasing (n_graphs = 1, vbase = {0, n}: a single graph).
@@ -283,13 +290,32 @@ mcd_status mcd_sweep_workspace_size(const mcd_graph* g, int32_t n_graphs, int32_
  *                pairs_both and ari are 0).
  *   stats:       device mcd_sweep_stats[n_graphs][K] (slot k = caller's k-th threshold).
  *   ari:         device double[n_graphs][K], may be NULL.
+ *   modularity:  device double[n_graphs][K], may be NULL (then intra_edges and
+ *                volume_sq are 0).
  *   labels:      device int32[K][n] min-original-id labels per threshold, may be NULL.
  * Asynchronous; no host synchronisation or memset inside, so the call can be
  * captured in a HIP graph. */
 mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                      const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
                      const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
-                     int32_t* labels, void* ws, size_t ws_bytes);
+                     double* modularity, int32_t* labels, void* ws, size_t ws_bytes);
+
+/* The paper's rule of thumb for the threshold (Sec. 4.4, Fig. tab:selection),
+ * per graph, from a sweep's statistics: walking the thresholds downwards, the
+ * largest single increase of the largest component (between consecutive
+ * thresholds, in vertices) marks where dense regions stop being split; if
+ * that jump is at least jump_num/jump_den of the graph's vertices the rule
+ * picks the threshold just above it.  Otherwise it picks the threshold of
+ * maximum modularity (ties: the highest threshold), or, when modularity is
+ * NULL, the highest threshold.
+ *   host_deltas, n_thresholds: the thresholds given to mcd_sweep (same order).
+ *   stats, modularity: mcd_sweep's outputs [n_graphs][K] (modularity may be NULL).
+ *   vbase: as for mcd_sweep.  index: device int32[n_graphs], the picked slot;
+ *   deltas: device int64[2 n_graphs] (may be NULL), the picked num, den.
+ * Asynchronous. */
+mcd_status mcd_sweep_rule(mcd_ctx* ctx, const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
+                          const int64_t* vbase, const mcd_sweep_stats* stats, const double* modularity,
+                          int64_t jump_num, int64_t jump_den, int32_t* index, int64_t* deltas);
 
 /* -------------------------------------------------- learned threshold picker */
 

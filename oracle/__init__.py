@@ -214,26 +214,38 @@ def run(n: int, src, dst, measure: int, num: int, den: int, timings: dict | None
     return dict(lo=lo, hi=hi, deg=deg, t=t, w=w, keep=keep, labels=labels, ncc=ncc)
 
 
-def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None):
+def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None, modularity=False):
     """Algorithm 1 at every threshold of `deltas`, one graph or a batch of
     disjoint graphs (graph k owns ids [vbase[k], vbase[k+1])).
 
-    Returns (stats[G][K][7], ari[G][K] or None, labels[K][n]) with the fields
+    Returns (stats[G][K][9], ari[G][K] or None, labels[K][n]) with the fields
     m_kept, n_components, largest_component, pairs_cluster (A), pairs_class
-    (B), pairs_both (S), pairs_total (N); ARI from or_ari on each graph."""
+    (B), pairs_both (S), pairs_total (N), intra_edges, volume_sq; ARI from
+    or_ari on each graph.  With modularity=True a fourth item, modularity
+    [G][K]: Q = intra / m - volume_sq / (4 m^2) of each partition on the input
+    graph (the modularity definition of Sec. 2 summed per community), where
+    intra counts input edges inside one component and volume_sq sums the
+    squared degree totals of the components."""
     if vbase is None:
         vbase = np.array([0, n], np.int64)
     vbase = np.asarray(vbase, np.int64)
     G, K = len(vbase) - 1, len(deltas)
-    stats = np.zeros((G, K, 7), np.int64)
+    stats = np.zeros((G, K, 9), np.int64)
     ari_out = np.zeros((G, K)) if truth is not None else None
+    q_out = np.zeros((G, K)) if modularity else None
     labels_all = np.zeros((K, n), np.int32)
     egraph = np.searchsorted(vbase, lo, side="right") - 1
+    m_graph = np.bincount(egraph, minlength=G).astype(np.int64)
     for i, (num, den) in enumerate(deltas):
         keep = prune(measure, lo, hi, t, deg, num, den)
         labels, _ = components(n, lo, hi, keep)
         labels_all[i] = labels
         kept_per_graph = np.bincount(egraph, weights=keep, minlength=G).astype(np.int64)
+        if modularity:
+            same = (labels[lo] == labels[hi]).astype(np.int64)
+            intra = np.bincount(egraph, weights=same, minlength=G).astype(np.int64)
+            vol = np.zeros(n, np.int64)
+            np.add.at(vol, labels, deg.astype(np.int64))
         for gk in range(G):
             a, b = vbase[gk], vbase[gk + 1]
             lab = labels[a:b]
@@ -250,5 +262,47 @@ def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None):
                 row += [A, 0, 0, nv * (nv - 1) // 2]
                 if truth is not None:
                     ari_out[gk, i] = 1.0
+            if modularity:
+                vsq = int(sum(int(x) * int(x) for x in vol[a:b] if x))
+                mg = int(m_graph[gk])
+                row += [int(intra[gk]), vsq]
+                q_out[gk, i] = 0.0 if mg == 0 else float(intra[gk]) / float(mg) - float(vsq) / (4.0 * mg * mg)
+            else:
+                row += [0, 0]
             stats[gk, i] = row
+    if modularity:
+        return stats, ari_out, labels_all, q_out
     return stats, ari_out, labels_all
+
+
+def rule_of_thumb(stats, deltas, vbase, modularity=None, jump=(1, 10)):
+    """The threshold rule of thumb of Sec. 4.4 per graph, in this reading:
+    with the thresholds in increasing exact order (ties in the given order),
+    take the largest increase of the largest component between consecutive
+    thresholds, the first maximum met walking downwards; if it is at least
+    jump[0]/jump[1] of the graph's vertices, pick the threshold just above it,
+    else the threshold of maximum modularity (the highest among equal maxima),
+    else (no modularity) the highest threshold.  Returns caller slot indices."""
+    from fractions import Fraction
+    K = len(deltas)
+    order = sorted(range(K), key=lambda k: (Fraction(int(deltas[k][0]), int(deltas[k][1])), k))
+    vbase = np.asarray(vbase, np.int64)
+    out = []
+    for g in range(stats.shape[0]):
+        nv = int(vbase[g + 1] - vbase[g])
+        largest = [int(stats[g, order[i], 2]) for i in range(K)]
+        best, at = 0, -1
+        for i in range(K - 2, -1, -1):
+            d = largest[i] - largest[i + 1]
+            if d > best:
+                best, at = d, i
+        pick = K - 1
+        if at >= 0 and best * jump[1] >= jump[0] * nv:
+            pick = at + 1
+        elif modularity is not None:
+            bq = modularity[g, order[K - 1]]
+            for i in range(K - 2, -1, -1):
+                if modularity[g, order[i]] > bq:
+                    bq, pick = modularity[g, order[i]], i
+        out.append(order[pick])
+    return np.array(out, np.int64)

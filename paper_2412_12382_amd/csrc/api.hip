@@ -581,25 +581,16 @@ mcd_status mcd_sweep_workspace_size(const mcd_graph* g, int32_t n_graphs, int32_
     return MCD_OK;
 }
 
-mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
-                     const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
-                     const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
-                     int32_t* labels, void* ws, size_t ws_bytes) {
-    REQUIRE(g && host_deltas && vbase && stats && ws, MCD_ERR_INVALID_ARG, "NULL argument");
-    REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
-    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
-    size_t need = 0;
-    mcd_status st = mcd_sweep_workspace_size(g, n_graphs, n_thresholds, truth != nullptr, &need);
-    if (st != MCD_OK) return st;
-    REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "sweep workspace too small");
-    const int K = n_thresholds;
-    int order[MCD_SWEEP_MAX_THRESHOLDS];
+// Thresholds of a sweep sorted by exact value (equal ones keep the caller's
+// order): order[i] = caller slot of the i-th smallest.
+mcd_status sort_thresholds(const mcd_rational* host_deltas, int K, int* order, mcd::SweepDeltas* ds) {
+    REQUIRE(K >= 1 && K <= MCD_SWEEP_MAX_THRESHOLDS, MCD_ERR_RANGE, "1 to 64 thresholds per sweep");
+    mcd_status st;
     for (int i = 0; i < K; ++i) {
         if ((st = check_delta(host_deltas[i])) != MCD_OK) return st;
         order[i] = i;
     }
-    // insertion sort by exact value; equal thresholds keep the caller's order
-    for (int i = 1; i < K; ++i) {
+    for (int i = 1; i < K; ++i) {  // insertion sort by exact value
         const int x = order[i];
         int j = i - 1;
         while (j >= 0) {
@@ -611,14 +602,48 @@ mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
         }
         order[j + 1] = x;
     }
-    mcd::SweepDeltas ds;
-    ds.K = K;
+    ds->K = K;
     for (int i = 0; i < K; ++i) {
-        ds.num[i] = host_deltas[order[i]].num;
-        ds.den[i] = host_deltas[order[i]].den;
+        ds->num[i] = host_deltas[order[i]].num;
+        ds->den[i] = host_deltas[order[i]].den;
     }
+    return MCD_OK;
+}
+
+mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                     const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
+                     const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
+                     double* modularity, int32_t* labels, void* ws, size_t ws_bytes) {
+    REQUIRE(g && host_deltas && vbase && stats && ws, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
+    size_t need = 0;
+    mcd_status st = mcd_sweep_workspace_size(g, n_graphs, n_thresholds, truth != nullptr, &need);
+    if (st != MCD_OK) return st;
+    REQUIRE(ws_bytes >= need, MCD_ERR_WORKSPACE, "sweep workspace too small");
+    int order[MCD_SWEEP_MAX_THRESHOLDS];
+    mcd::SweepDeltas ds;
+    if ((st = sort_thresholds(host_deltas, n_thresholds, order, &ds)) != MCD_OK) return st;
     if ((st = use_device(g->ctx)) != MCD_OK) return st;
-    mcd::launch_sweep(g, measure, t, ds, order, n_graphs, vbase, truth, stats, ari, labels, ws, g->ctx->stream);
+    mcd::launch_sweep(g, measure, t, ds, order, n_graphs, vbase, truth, stats, ari, modularity, labels, ws,
+                      g->ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_sweep_rule(mcd_ctx* ctx, const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
+                          const int64_t* vbase, const mcd_sweep_stats* stats, const double* modularity,
+                          int64_t jump_num, int64_t jump_den, int32_t* index, int64_t* deltas) {
+    REQUIRE(ctx && host_deltas && vbase && stats && index, MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "n_graphs must be at least 1");
+    REQUIRE(jump_den > 0 && jump_num >= 0 && jump_num < ((int64_t)1 << 31) && jump_den < ((int64_t)1 << 31),
+            MCD_ERR_RANGE, "jump fraction must be num/den with 0 <= num, 0 < den < 2^31");
+    int order[MCD_SWEEP_MAX_THRESHOLDS];
+    mcd::SweepDeltas ds;
+    mcd_status st = sort_thresholds(host_deltas, n_thresholds, order, &ds);
+    if (st != MCD_OK) return st;
+    if ((st = use_device(ctx)) != MCD_OK) return st;
+    mcd::launch_sweep_rule(ds, order, n_graphs, vbase, stats, modularity, jump_num, jump_den, index, deltas,
+                           ctx->stream);
     return MCD_OK;
 }
 

@@ -178,7 +178,13 @@ size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth);
 // out_index[i]: caller's slot of the i-th smallest threshold
 void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
                   const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
-                  mcd_sweep_stats* stats, double* ari, int32_t* labels, void* ws, hipStream_t s);
+                  mcd_sweep_stats* stats, double* ari, double* modularity, int32_t* labels, void* ws,
+                  hipStream_t s);
+
+// the threshold rule of thumb over a sweep's statistics (order as for launch_sweep)
+void launch_sweep_rule(const SweepDeltas& ds, const int* order, int G, const int64_t* vbase,
+                       const mcd_sweep_stats* stats, const double* modularity, int64_t jump_num, int64_t jump_den,
+                       int32_t* index, int64_t* deltas, hipStream_t s);
 
 // ---- picker (picker.hip) ----
 size_t features_scratch_bytes(int G);

@@ -418,6 +418,88 @@ __global__ __launch_bounds__(kThreads) void k_class_b(const int32_t* __restrict_
     B.flush_add();
 }
 
+// Modularity (the quality measure of the paper's threshold rule of thumb) of
+// the partition at this threshold, on the input graph:
+//   Q = sum over components c of e_c / m - (vol_c / 2m)^2,
+// with e_c the input edges inside c and vol_c the sum of input degrees over c.
+// vol[root] accumulates the degrees of each component (wave-aggregated, big
+// components through the block's LDS table like the sizes).
+__global__ __launch_bounds__(kThreads) void k_pass_volume(int32_t* parent, int64_t n,
+                                                          const int32_t* __restrict__ deg,
+                                                          unsigned long long* __restrict__ vol) {
+    __shared__ int32_t rk[kRootSlots];
+    __shared__ unsigned long long rv[kRootSlots];
+    for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x) {
+        rk[i] = -1;
+        rv[i] = 0ull;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    GRID_STRIDE(v, n) {
+        const int32_t r = find_root(parent, (int32_t)v);
+        const unsigned long long d = (unsigned long long)deg[v];
+        const int32_t r0 = __shfl(r, 0);
+        unsigned long long x = r == r0 ? d : 0ull;
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        bool done = r == r0;
+        if (lane == 0 && x) {
+            uint32_t h = ((uint32_t)r0 * 2654435761u) >> 22;
+            bool put = false;
+            for (int probe = 0; probe < 8 && !put; ++probe) {
+                const int32_t k = atomicCAS(&rk[h], -1, r0);
+                if (k == -1 || k == r0) {
+                    atomicAdd(&rv[h], x);
+                    put = true;
+                }
+                h = (h + 1) & (kRootSlots - 1);
+            }
+            if (!put) atomicAdd(&vol[r0], x);
+        }
+        if (!done && d) atomicAdd(&vol[r], d);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x)
+        if (rk[i] >= 0 && rv[i]) atomicAdd(&vol[rk[i]], rv[i]);
+}
+
+// Per graph: the input edges whose endpoints share a component at threshold
+// slot lv_thresh (kept edges always do; a pruned edge iff its endpoints have
+// one root), and the sum over components of vol_c^2.
+__global__ __launch_bounds__(kThreads) void k_pass_intra(const int32_t* __restrict__ src,
+                                                         const int32_t* __restrict__ adj,
+                                                         const uint8_t* __restrict__ level, int64_t m,
+                                                         int lv_thresh, int32_t* parent,
+                                                         const int32_t* __restrict__ gid, int G,
+                                                         unsigned long long* __restrict__ acc_intra) {
+    __shared__ unsigned long long li[kLdsGraphs];
+    GraphAcc I{G <= kLdsGraphs ? li : nullptr, acc_intra, G};
+    I.init();
+    __syncthreads();
+    GRID_STRIDE(e, m) {
+        const int32_t u = src[e];
+        bool in = level[e] > lv_thresh;
+        if (!in) in = find_root(parent, u) == find_root(parent, adj[e]);
+        I.add(G == 1 ? 0 : gid[u], in ? 1ull : 0ull);
+    }
+    __syncthreads();
+    I.flush_add();
+}
+
+__global__ __launch_bounds__(kThreads) void k_pass_vsq(int64_t n, const int32_t* __restrict__ gid, int G,
+                                                       const unsigned long long* __restrict__ vol,
+                                                       unsigned long long* __restrict__ acc_vsq) {
+    __shared__ unsigned long long lq[kLdsGraphs];
+    GraphAcc Q{G <= kLdsGraphs ? lq : nullptr, acc_vsq, G};
+    Q.init();
+    __syncthreads();
+    GRID_STRIDE(v, n) {
+        const unsigned long long x = vol[v];  // nonzero only at roots
+        Q.add(gid[v], x * x);
+    }
+    __syncthreads();
+    Q.flush_add();
+}
+
 // Writes the statistics of threshold slot `out_i` for every graph.
 __global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_thresh, int out_i,
                                                           const unsigned long long* __restrict__ hist,
@@ -426,12 +508,18 @@ __global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_t
                                                           const unsigned long long* __restrict__ acc_a,
                                                           const unsigned long long* __restrict__ acc_s,
                                                           const unsigned long long* __restrict__ acc_b,
+                                                          const unsigned long long* __restrict__ acc_intra,
+                                                          const unsigned long long* __restrict__ acc_vsq,
                                                           const int64_t* __restrict__ vbase, int has_truth,
                                                           mcd_sweep_stats* __restrict__ stats,
-                                                          double* __restrict__ ari) {
+                                                          double* __restrict__ ari, double* __restrict__ modularity) {
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
-        int64_t kept = 0;
-        for (int l = lv_thresh + 1; l <= K; ++l) kept += (int64_t)hist[(int64_t)g * (K + 1) + l];
+        int64_t kept = 0, mg = 0;
+        for (int l = 0; l <= K; ++l) {
+            const int64_t c = (int64_t)hist[(int64_t)g * (K + 1) + l];
+            mg += c;
+            if (l > lv_thresh) kept += c;
+        }
         mcd_sweep_stats st;
         const int64_t nv = vbase[g + 1] - vbase[g];
         st.m_kept = kept;
@@ -441,7 +529,14 @@ __global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_t
         st.pairs_class = has_truth ? (int64_t)(acc_b[g] / 2) : 0;
         st.pairs_both = has_truth ? (int64_t)(acc_s[g] / 2) : 0;
         st.pairs_total = nv * (nv - 1) / 2;
+        st.intra_edges = modularity ? (int64_t)acc_intra[g] : 0;
+        st.volume_sq = modularity ? (int64_t)acc_vsq[g] : 0;
         stats[(int64_t)g * K + out_i] = st;
+        if (modularity) {
+            const double mm = (double)mg;
+            modularity[(int64_t)g * K + out_i] =
+                mg == 0 ? 0.0 : (double)st.intra_edges / mm - (double)st.volume_sq / (4.0 * mm * mm);
+        }
         if (ari) {
             double r = 0.0;
             if (has_truth) {
@@ -452,6 +547,53 @@ __global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_t
                 r = (st.pairs_total == 0 || den == 0.0) ? 1.0 : (S - prod) / den;
             }
             ari[(int64_t)g * K + out_i] = r;
+        }
+    }
+}
+
+// One thread per graph: the rule of thumb over the thresholds in ascending
+// order (slot[i] = caller slot of the i-th smallest).
+struct SlotOrder {
+    int slot[MCD_SWEEP_MAX];
+};
+
+__global__ __launch_bounds__(kThreads) void k_sweep_rule(int G, SweepDeltas ds, SlotOrder so,
+                                                         const int64_t* __restrict__ vbase,
+                                                         const mcd_sweep_stats* __restrict__ stats,
+                                                         const double* __restrict__ modularity, int64_t jump_num,
+                                                         int64_t jump_den, int32_t* __restrict__ index,
+                                                         int64_t* __restrict__ deltas) {
+    const int K = ds.K;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+        const int64_t nv = vbase[g + 1] - vbase[g];
+        const mcd_sweep_stats* row = stats + (int64_t)g * K;
+        // largest increase of the largest component while the threshold falls;
+        // the first maximum met walking downwards
+        int64_t best_jump = 0;
+        int jump_at = -1;
+        for (int i = K - 2; i >= 0; --i) {
+            const int64_t d = row[so.slot[i]].largest_component - row[so.slot[i + 1]].largest_component;
+            if (d > best_jump) {
+                best_jump = d;
+                jump_at = i;
+            }
+        }
+        int pick = K - 1;
+        if (jump_at >= 0 && (__int128)best_jump * jump_den >= (__int128)jump_num * nv) {
+            pick = jump_at + 1;
+        } else if (modularity) {
+            const double* q = modularity + (int64_t)g * K;
+            double bq = q[so.slot[K - 1]];
+            for (int i = K - 2; i >= 0; --i)
+                if (q[so.slot[i]] > bq) {
+                    bq = q[so.slot[i]];
+                    pick = i;
+                }
+        }
+        index[g] = so.slot[pick];
+        if (deltas) {
+            deltas[2 * g] = ds.num[pick];
+            deltas[2 * g + 1] = ds.den[pick];
         }
     }
 }
@@ -489,6 +631,9 @@ struct SweepLayout {
     unsigned long long* acc_a;   // [G]
     unsigned long long* acc_s;   // [G]
     unsigned long long* acc_b;   // [G]
+    unsigned long long* acc_intra;  // [G]
+    unsigned long long* acc_vsq;    // [G]
+    unsigned long long* vol;        // [n]
     size_t bytes;
 };
 
@@ -512,6 +657,9 @@ SweepLayout sweep_layout(void* p, const mcd_graph* g, int G, int K, bool truth) 
     L.acc_a = c.take<unsigned long long>((size_t)G);
     L.acc_s = c.take<unsigned long long>((size_t)G);
     L.acc_b = c.take<unsigned long long>((size_t)G);
+    L.acc_intra = c.take<unsigned long long>((size_t)G);
+    L.acc_vsq = c.take<unsigned long long>((size_t)G);
+    L.vol = c.take<unsigned long long>((size_t)n);
     L.bytes = c.used;
     return L;
 }
@@ -524,7 +672,8 @@ size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth) {
 
 void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
                   const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
-                  mcd_sweep_stats* stats, double* ari, int32_t* labels, void* ws, hipStream_t s) {
+                  mcd_sweep_stats* stats, double* ari, double* modularity, int32_t* labels, void* ws,
+                  hipStream_t s) {
     const int K = ds.K;
     const int64_t n = g->n, m = g->m;
     SweepLayout L = sweep_layout(ws, g, G, K, truth != nullptr);
@@ -560,6 +709,11 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
         fill_t<unsigned long long>(L.acc_a, G, 0ull, s);
         fill_t<unsigned long long>(L.acc_s, G, 0ull, s);
         fill_t<int32_t>(L.size, n, 0, s);
+        if (modularity) {
+            fill_t<unsigned long long>(L.acc_intra, G, 0ull, s);
+            fill_t<unsigned long long>(L.acc_vsq, G, 0ull, s);
+            fill_t<unsigned long long>(L.vol, n, 0ull, s);
+        }
         int32_t* lab = labels ? labels + (int64_t)out_index[i] * n : nullptr;
         if (n > 0) {
             hipLaunchKernelGGL(k_pass_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid, G,
@@ -578,6 +732,15 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
             }
             hipLaunchKernelGGL(k_pass_roots, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, n, L.gid, G, L.size,
                                L.acc_a, L.largest);
+            if (modularity) {
+                hipLaunchKernelGGL(k_pass_volume, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, g->deg,
+                                   L.vol);
+                hipLaunchKernelGGL(k_pass_vsq, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, n, L.gid, G, L.vol,
+                                   L.acc_vsq);
+                if (m > 0)
+                    hipLaunchKernelGGL(k_pass_intra, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->adj,
+                                       L.level, m, i, L.parent, L.gid, G, L.acc_intra);
+            }
             if (truth) {
                 hipLaunchKernelGGL(k_pass_cells, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n,
                                    L.cls, L.keys, L.counts, l2);
@@ -586,9 +749,18 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
             }
         }
         hipLaunchKernelGGL(k_write_stats, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), 0, s, G, K, i,
-                           out_index[i], L.hist, L.ncc, L.largest, L.acc_a, L.acc_s, L.acc_b, vbase,
-                           truth ? 1 : 0, stats, ari);
+                           out_index[i], L.hist, L.ncc, L.largest, L.acc_a, L.acc_s, L.acc_b, L.acc_intra,
+                           L.acc_vsq, vbase, truth ? 1 : 0, stats, ari, modularity);
     }
+}
+
+void launch_sweep_rule(const SweepDeltas& ds, const int* order, int G, const int64_t* vbase,
+                       const mcd_sweep_stats* stats, const double* modularity, int64_t jump_num, int64_t jump_den,
+                       int32_t* index, int64_t* deltas, hipStream_t s) {
+    SlotOrder so;
+    for (int i = 0; i < ds.K; ++i) so.slot[i] = order[i];
+    hipLaunchKernelGGL(k_sweep_rule, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), 0, s, G, ds, so, vbase,
+                       stats, modularity, jump_num, jump_den, index, deltas);
 }
 
 }  // namespace mcd

@@ -40,7 +40,7 @@ class mcd_rational(ctypes.Structure):
 
 
 SWEEP_FIELDS = ("m_kept", "n_components", "largest_component", "pairs_cluster", "pairs_class",
-                "pairs_both", "pairs_total")
+                "pairs_both", "pairs_total", "intra_edges", "volume_sq")
 SWEEP_MAX = 64
 
 
@@ -80,7 +80,8 @@ def lib():
             "mcd_run": [P, ctypes.c_int, mcd_rational, P, P, P, SZ],
             "mcd_percentile_workspace_size": [P, ctypes.POINTER(SZ)],
             "mcd_sweep_workspace_size": [P, I32, I32, I32, ctypes.POINTER(SZ)],
-            "mcd_sweep": [P, ctypes.c_int, P, P, I32, I32, P, P, P, P, P, P, SZ],
+            "mcd_sweep": [P, ctypes.c_int, P, P, I32, I32, P, P, P, P, P, P, P, SZ],
+            "mcd_sweep_rule": [P, P, I32, I32, P, P, P, I64, I64, P, P],
             "mcd_features_workspace_size": [I32, ctypes.POINTER(SZ)],
             "mcd_features": [P, P, I32, P, P, P, SZ],
             "mcd_feature_stats": [P, P, I32, ctypes.c_float, P, P],
@@ -338,8 +339,9 @@ def mcd_sweep_workspace_size(g: Graph, n_graphs: int, K: int, has_truth: bool) -
 
 
 def mcd_sweep(g: Graph, measure: int, t, deltas, vbase=None, truth=None, stats=None, ari=None,
-              labels=None, want_labels=False, ws=None):
-    """Returns (stats int64[G][K][7], ari float64[G][K] or None, labels int32[K][n] or None)."""
+              labels=None, want_labels=False, ws=None, modularity=None, want_modularity=False):
+    """Returns (stats int64[G][K][9], ari float64[G][K] or None, labels int32[K][n] or None),
+    plus modularity float64[G][K] as a fourth item when want_modularity or modularity is given."""
     K = len(deltas)
     dev = g.ctx.device
     if vbase is None:
@@ -352,11 +354,31 @@ def mcd_sweep(g: Graph, measure: int, t, deltas, vbase=None, truth=None, stats=N
         ari = _empty((G, K), torch.float64, dev)
     if labels is None and want_labels:
         labels = _empty((K, max(g.n, 1)), torch.int32, dev)
+    with_q = want_modularity or modularity is not None
+    if modularity is None and want_modularity:
+        modularity = _empty((G, K), torch.float64, dev)
     if ws is None:
         ws = _bytes(mcd_sweep_workspace_size(g, G, K, truth is not None), dev)
     _check(lib().mcd_sweep(g.handle, measure, _p(t), ctypes.cast(arr, ctypes.c_void_p), K, G, _p(vbase),
-                           _p(truth), _p(stats), _p(ari), _p(labels), _p(ws), ws.numel() * ws.element_size()))
-    return stats, ari, labels
+                           _p(truth), _p(stats), _p(ari), _p(modularity), _p(labels), _p(ws),
+                           ws.numel() * ws.element_size()))
+    return (stats, ari, labels, modularity) if with_q else (stats, ari, labels)
+
+
+def mcd_sweep_rule(ctx: Context, deltas, stats, modularity=None, vbase=None, jump=(1, 10), index=None,
+                   delta=None):
+    """The rule-of-thumb threshold per graph from a sweep: (index int32[G], delta int64[G][2])."""
+    K = len(deltas)
+    G = stats.shape[0]
+    dev = ctx.device
+    if vbase is None:
+        raise ValueError("vbase is required (the graphs' vertex ranges)")
+    arr = (mcd_rational * K)(*[mcd_rational(int(a), int(b)) for a, b in deltas])
+    index = _empty(G, torch.int32, dev) if index is None else index
+    delta = _empty((G, 2), torch.int64, dev) if delta is None else delta
+    _check(lib().mcd_sweep_rule(ctx.handle, ctypes.cast(arr, ctypes.c_void_p), K, G, _p(vbase), _p(stats),
+                                _p(modularity), int(jump[0]), int(jump[1]), _p(index), _p(delta)))
+    return index, delta
 
 
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 66, 64, 8513

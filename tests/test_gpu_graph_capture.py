@@ -1,8 +1,9 @@
 """The path after the graph build, captured once in a HIP graph and replayed.
 
 Triangles, one-pass weights + prune at per-graph device thresholds,
-components over the kept list, the 64-threshold sweep with ARI, picker
-features, MLP forward and grid snap are enqueued by the library on the
+components over the kept list, the 64-threshold sweep with ARI and
+modularity, the threshold rule of thumb, picker features, MLP forward and
+grid snap are enqueued by the library on the
 context's stream while a HIP graph is being captured on it.  The graph is
 replayed several times, with eager work and synchronisations in between and
 every output overwritten before each replay, and each replay must equal the
@@ -64,8 +65,11 @@ def test_capture_and_replay_matches_eager():
             nk=torch.empty(1, dtype=torch.int64, device=dev),
             labels=torch.empty(n, dtype=torch.int32, device=dev),
             ncc=torch.empty(1, dtype=torch.int64, device=dev),
-            stats=torch.empty((G, 64, 7), dtype=torch.int64, device=dev),
+            stats=torch.empty((G, 64, len(M.SWEEP_FIELDS)), dtype=torch.int64, device=dev),
             ari=torch.empty((G, 64), dtype=torch.float64, device=dev),
+            q=torch.empty((G, 64), dtype=torch.float64, device=dev),
+            rule=torch.empty(G, dtype=torch.int32, device=dev),
+            rule_delta=torch.empty((G, 2), dtype=torch.int64, device=dev),
             x=torch.empty((G, M.MLP_IN), dtype=torch.float32, device=dev),
             y=torch.empty(G, dtype=torch.float32, device=dev),
             idx=torch.empty(G, dtype=torch.int32, device=dev),
@@ -86,7 +90,9 @@ def test_capture_and_replay_matches_eager():
                               keep_bits=out["keep"], kept=kept, n_kept=out["nk"])
             M.mcd_components_kept(g, kept, out["labels"], out["ncc"], ws=ws_c)
             M.mcd_sweep(g, M.MCD_SIM_TECTONIC, out["t"], GRID64, vbase=vb, truth=tr, stats=out["stats"],
-                        ari=out["ari"], ws=ws_s)
+                        ari=out["ari"], modularity=out["q"], ws=ws_s)
+            M.mcd_sweep_rule(ctx, GRID64, out["stats"], out["q"], vbase=vb, index=out["rule"],
+                             delta=out["rule_delta"])
 
         path()
     torch.cuda.synchronize()

@@ -109,3 +109,47 @@ def test_sweep_k3_and_jaccard():
     compare(gpu_sweep(s, d, n, oracle.K3, k3), oracle_sweep(s, d, n, oracle.K3, k3))
     jac = [(k, 100) for k in range(0, 60, 4)]
     compare(gpu_sweep(s, d, n, oracle.JACCARD, jac), oracle_sweep(s, d, n, oracle.JACCARD, jac))
+
+
+def test_sweep_modularity_and_rule_of_thumb():
+    # modularity per threshold bit-exact in its integers and within 1e-12 in Q,
+    # then the rule of thumb picks the same slots as the oracle's
+    from gpu_util import build
+    graphs = []
+    for g in range(5):
+        pr = gg.sbm_batch_params(g + 20)
+        n = min(pr["n"], 2500)
+        k = min(pr["k"], n // 4)
+        src, dst, lab = gg.sbm_skip(n, k, min(pr["d_in"] / (n / k - 1), 0.5),
+                                    pr["mu"] * pr["d_in"] / ((1 - pr["mu"]) * n), 2000 + g)
+        graphs.append((n, src, dst, lab))
+    vbase = np.zeros(len(graphs) + 1, np.int64)
+    srcs, dsts, truths, cb = [], [], [], 0
+    for i, (n, src, dst, lab) in enumerate(graphs):
+        vbase[i + 1] = vbase[i] + n
+        srcs.append(src + vbase[i])
+        dsts.append(dst + vbase[i])
+        truths.append(lab + cb)
+        cb += int(lab.max()) + 1
+    N = int(vbase[-1])
+    src = np.concatenate(srcs).astype(np.int32)
+    dst = np.concatenate(dsts).astype(np.int32)
+    truth = np.concatenate(truths).astype(np.int32)
+    deltas = GRID64[::3] + [(1, 2), (0, 1)]  # unsorted tail, a zero threshold
+    g = build(src, dst, N)
+    t = M.mcd_triangles(g)
+    vb = torch.from_numpy(vbase).cuda()
+    stats, ari, _, q = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, deltas, vbase=vb,
+                                   truth=torch.from_numpy(truth).cuda(), want_modularity=True)
+    lo, hi = oracle.canon(N, src, dst)
+    deg = oracle.degrees(N, lo, hi)
+    to = oracle.triangles(N, lo, hi)
+    st_o, ari_o, _, q_o = oracle.sweep(N, lo, hi, to, deg, oracle.TECTONIC, deltas, truth, vbase, modularity=True)
+    assert np.array_equal(stats.cpu().numpy(), st_o)
+    assert np.all(np.abs(q.cpu().numpy() - q_o) <= 1e-12)
+    for jump in ((1, 10), (1, 2), (1, 1000)):
+        for with_q in (True, False):
+            idx, dl = M.mcd_sweep_rule(g.ctx, deltas, stats, q if with_q else None, vbase=vb, jump=jump)
+            want = oracle.rule_of_thumb(st_o, deltas, vbase, q_o if with_q else None, jump)
+            assert np.array_equal(idx.cpu().numpy(), want), (jump, with_q)
+            assert np.array_equal(dl.cpu().numpy(), np.array([deltas[k] for k in want], np.int64))

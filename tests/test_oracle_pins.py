@@ -467,3 +467,51 @@ def test_k3_measure_closed_forms():
     lo, hi, deg, t = full(4, [(0, 1), (1, 2), (2, 3)])
     assert oracle.prune(oracle.K3, lo, hi, t, deg, 0, 1).all()
     assert not oracle.prune(oracle.K3, lo, hi, t, deg, 1, 3).any()
+
+
+def test_sweep_modularity_matches_networkx():
+    # Modularity of each threshold's partition on the input graph equals
+    # networkx's modularity of those communities (Sec. 2 definition).
+    import networkx as nx
+    from networkx.algorithms.community import modularity as nx_modularity
+    for seed in range(3):
+        rng = np.random.default_rng(40 + seed)
+        n = int(rng.integers(30, 120))
+        P = int(rng.integers(n, 5 * n))
+        s = rng.integers(0, n, P).astype(np.int32)
+        d = rng.integers(0, n, P).astype(np.int32)
+        lo, hi = oracle.canon(n, s, d)
+        if len(lo) == 0:
+            continue
+        deg = oracle.degrees(n, lo, hi)
+        t = oracle.triangles(n, lo, hi)
+        deltas = [(0, 1), (1, 10), (1, 5), (1, 3)]
+        st, _, labels, q = oracle.sweep(n, lo, hi, t, deg, oracle.TECTONIC, deltas, modularity=True)
+        Gx = nx.Graph()
+        Gx.add_nodes_from(range(n))
+        Gx.add_edges_from(zip(lo.tolist(), hi.tolist()))
+        for i in range(len(deltas)):
+            comms = {}
+            for v, c in enumerate(labels[i]):
+                comms.setdefault(int(c), set()).add(v)
+            assert abs(q[0, i] - nx_modularity(Gx, list(comms.values()))) <= 1e-12
+            # intra edges: every kept edge is inside a component
+            assert st[0, i, 7] >= st[0, i, 0]
+
+
+def test_rule_of_thumb_cases():
+    # thresholds given out of order; largest component (field 2) per slot
+    deltas = [(3, 10), (1, 10), (2, 10), (4, 10)]   # ascending order of slots: 1, 2, 0, 3
+    vbase = [0, 100]
+    st = np.zeros((1, 4, 9), np.int64)
+    # walking down 4/10 -> 3/10 -> 2/10 -> 1/10: largest 5, 8, 60, 70: jump 52 at 3/10 -> 2/10
+    for slot, L in ((3, 5), (0, 8), (2, 60), (1, 70)):
+        st[0, slot, 2] = L
+    assert oracle.rule_of_thumb(st, deltas, vbase).tolist() == [0]  # 3/10, just above the jump
+    # no jump of 10% of n: falls back to the maximum modularity
+    st2 = st.copy()
+    for slot, L in ((3, 5), (0, 8), (2, 12), (1, 14)):
+        st2[0, slot, 2] = L
+    q = np.array([[0.1, 0.3, 0.5, 0.2]])
+    assert oracle.rule_of_thumb(st2, deltas, vbase, q).tolist() == [2]
+    assert oracle.rule_of_thumb(st2, deltas, vbase).tolist() == [3]  # no modularity: highest threshold
