@@ -115,7 +115,9 @@ def picker_study(M, PK, dev):
     vb = cu(b["vbase"])
     g = M.mcd_graph_build(ctx, cu(b["src"]), cu(b["dst"]), b["n"])
     t = M.mcd_triangles(g)
-    _, ari, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vb, truth=cu(b["truth"]))
+    stats, ari, _, q = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vb, truth=cu(b["truth"]),
+                                   want_modularity=True)
+    rule_idx, _ = M.mcd_sweep_rule(ctx, PK.GRID, stats, q, vbase=vb)
     _, y = M.mcd_sweep_targets(ctx, ari)
     x = M.mcd_features(g, t, vb)
     gi = np.arange(256)
@@ -132,6 +134,8 @@ def picker_study(M, PK, dev):
                train_seconds=round(train_s, 3), final_loss=float(losses[-1]),
                ari_picker=float(A[va, pi[va]].mean()), ari_best_swept=float(A[va].max(1).mean()),
                ari_best_global=float(A[va][:, int(np.argmax(A[tr].mean(0)))].mean()))
+    ri = rule_idx.cpu().numpy()
+    res["ari_rule_of_thumb"] = float(A[va, ri[va]].mean())
     res["gap_to_best"] = res["ari_best_swept"] - res["ari_picker"]
     res["gain_over_global"] = res["ari_picker"] - res["ari_best_global"]
     # latency on the validation graphs packed as their own batch
@@ -229,6 +233,7 @@ def main():
     pdelta = torch.empty((1, 2), dtype=torch.int64, device=dev)
     grid16 = [(k, 50) for k in range(16)]
     sweep_stats = torch.empty((1, 16, len(M.SWEEP_FIELDS)), dtype=torch.int64, device=dev)
+    rule_idx = torch.empty(1, dtype=torch.int32, device=dev)
     log(f"HBM in use after allocation: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -255,6 +260,7 @@ def main():
         M.mcd_components_kept(g, kept, labels, ncc, ws=ws)
         e[5].record()
         M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, grid16, vbase=vbase, stats=sweep_stats, ws=ws)
+        M.mcd_sweep_rule(ctx, grid16, sweep_stats, None, vbase=vbase, index=rule_idx)
         e[6].record()
         return g, e
 
@@ -352,7 +358,8 @@ def main():
         "results": {"triangles": tri, "picked_delta": pick_delta, "n_kept": kept, "n_components": ncomp,
                     "sweep16": {"delta": [f"{a}/{b}" for a, b in grid16],
                                 "m_kept": sw[:, 0].tolist(), "n_components": sw[:, 1].tolist(),
-                                "largest_component": sw[:, 2].tolist()}},
+                                "largest_component": sw[:, 2].tolist(),
+                                "rule_of_thumb_delta": "%d/%d" % grid16[int(rule_idx.item())]}},
         "picker": pick_res,
         "cpu_baseline": cpu,
     }

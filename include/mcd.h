@@ -292,13 +292,19 @@ mcd_status mcd_sweep_workspace_size(const mcd_graph* g, int32_t n_graphs, int32_
  *   ari:         device double[n_graphs][K], may be NULL.
  *   modularity:  device double[n_graphs][K], may be NULL (then intra_edges and
  *                volume_sq are 0).
+ *   prf:         device double[n_graphs][K][3], may be NULL; with truth: the
+ *                evaluation of Sec. 4 (Setup, Evaluation): every component is
+ *                matched to the planted class of largest Jaccard overlap (ties:
+ *                smaller class id) and precision, recall and F1 are averaged
+ *                over components weighted by size (fp64 sums; the summation
+ *                order is not fixed, so the last bits may vary run to run).
  *   labels:      device int32[K][n] min-original-id labels per threshold, may be NULL.
  * Asynchronous; no host synchronisation or memset inside, so the call can be
  * captured in a HIP graph. */
 mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                      const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
                      const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
-                     double* modularity, int32_t* labels, void* ws, size_t ws_bytes);
+                     double* modularity, double* prf, int32_t* labels, void* ws, size_t ws_bytes);
 
 /* The paper's rule of thumb for the threshold (Sec. 4.4, Fig. tab:selection),
  * per graph, from a sweep's statistics: walking the thresholds downwards, the

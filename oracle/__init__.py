@@ -306,3 +306,37 @@ def rule_of_thumb(stats, deltas, vbase, modularity=None, jump=(1, 10)):
                     bq, pick = modularity[g, order[i]], i
         out.append(order[pick])
     return np.array(out, np.int64)
+
+
+def precision_recall_f1(labels, truth):
+    """Evaluation of Sec. 4 (Setup): each output community S (same label) is
+    matched to the planted class C of largest Jaccard overlap |C n S| / |C u S|
+    (compared exactly; ties to the smaller class id); p = |C n S| / |S|,
+    r = |C n S| / |C|; precision, recall and F1 = 2 p r / (p + r) are averaged
+    over the communities weighted by |S|.  Returns (precision, recall, F1)."""
+    labels = np.asarray(labels, np.int64)
+    truth = np.asarray(truth, np.int64)
+    n = len(labels)
+    if n == 0:
+        return 0.0, 0.0, 0.0
+    T = int(truth.max()) + 1
+    cells, x = np.unique(labels * T + truth, return_counts=True)
+    lab, cls = cells // T, cells % T
+    lsize = dict(zip(*np.unique(labels, return_counts=True)))
+    csize = dict(zip(*np.unique(truth, return_counts=True)))
+    best = {}
+    for L, C, X in zip(lab.tolist(), cls.tolist(), x.tolist()):
+        S, B = int(lsize[L]), int(csize[C])
+        if L in best:
+            X2, C2, B2 = best[L]
+            a, b = X * (S + B2 - X2), X2 * (S + B - X)
+            if a < b or (a == b and C > C2):
+                continue
+        best[L] = (X, C, B)
+    P = R = F = 0.0
+    for L, (X, C, B) in best.items():
+        S = float(lsize[L])
+        P += X
+        R += X * S / B
+        F += 2.0 * X * S / (S + B)
+    return P / n, R / n, F / n

@@ -613,7 +613,7 @@ mcd_status sort_thresholds(const mcd_rational* host_deltas, int K, int* order, m
 mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                      const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
                      const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
-                     double* modularity, int32_t* labels, void* ws, size_t ws_bytes) {
+                     double* modularity, double* prf, int32_t* labels, void* ws, size_t ws_bytes) {
     REQUIRE(g && host_deltas && vbase && stats && ws, MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
     REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
@@ -625,7 +625,7 @@ mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
     mcd::SweepDeltas ds;
     if ((st = sort_thresholds(host_deltas, n_thresholds, order, &ds)) != MCD_OK) return st;
     if ((st = use_device(g->ctx)) != MCD_OK) return st;
-    mcd::launch_sweep(g, measure, t, ds, order, n_graphs, vbase, truth, stats, ari, modularity, labels, ws,
+    mcd::launch_sweep(g, measure, t, ds, order, n_graphs, vbase, truth, stats, ari, modularity, prf, labels, ws,
                       g->ctx->stream);
     return MCD_OK;
 }

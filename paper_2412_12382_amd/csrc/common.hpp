@@ -178,8 +178,8 @@ size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth);
 // out_index[i]: caller's slot of the i-th smallest threshold
 void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
                   const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
-                  mcd_sweep_stats* stats, double* ari, double* modularity, int32_t* labels, void* ws,
-                  hipStream_t s);
+                  mcd_sweep_stats* stats, double* ari, double* modularity, double* prf, int32_t* labels,
+                  void* ws, hipStream_t s);
 
 // the threshold rule of thumb over a sweep's statistics (order as for launch_sweep)
 void launch_sweep_rule(const SweepDeltas& ds, const int* order, int G, const int64_t* vbase,

@@ -389,6 +389,69 @@ __global__ __launch_bounds__(kThreads) void k_pass_s(int32_t* parent, int64_t n,
     S.flush_add();
 }
 
+// Precision, recall and F1 of Sec. 4 (Evaluation): every output community S
+// (a component, root r, size s) is matched to the planted class C maximising
+// the Jaccard overlap |C n S| / |C u S| = x / (s + b - x) (x = the cell count,
+// b = |C|; ties go to the smaller class id); then p = x / s, r = x / b and,
+// weighted by s, precision = sum x / n, recall = sum x s / b / n and
+// F1 = sum 2 x s / (s + b) / n (2 p r / (p + r) = 2 x / (s + b)).
+//
+// best[r] holds (x << 32) | c of the best cell seen; cells compete by an exact
+// compare-and-swap maximum.
+__global__ __launch_bounds__(kThreads) void k_cells_best(const unsigned long long* __restrict__ keys,
+                                                         const int32_t* __restrict__ counts, int64_t cap,
+                                                         const int32_t* __restrict__ size,
+                                                         const int32_t* __restrict__ csize,
+                                                         unsigned long long* best) {
+    GRID_STRIDE(h, cap) {
+        const unsigned long long k = keys[h];
+        if (k == ~0ull) continue;
+        const int32_t r = (int32_t)(k >> 32), c = (int32_t)(uint32_t)k;
+        const int64_t x = counts[h], sz = size[r], b = csize[c];
+        const unsigned long long mine = ((unsigned long long)x << 32) | (uint32_t)c;
+        unsigned long long cur = __hip_atomic_load(&best[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (;;) {
+            if (cur != 0ull) {
+                const int64_t x2 = (int64_t)(cur >> 32);
+                const int32_t c2 = (int32_t)(uint32_t)cur;
+                const int64_t b2 = csize[c2];
+                // x / (sz + b - x) vs x2 / (sz + b2 - x2), both denominators >= 1
+                const int64_t l = x * (sz + b2 - x2), rr = x2 * (sz + b - x);
+                if (l < rr || (l == rr && c > c2)) break;  // the stored cell wins
+            }
+            const unsigned long long seen = atomicCAS(&best[r], cur, mine);
+            if (seen == cur) break;
+            cur = seen;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_prf_sums(int64_t n, const int32_t* __restrict__ gid, int G,
+                                                       const int32_t* __restrict__ size,
+                                                       const int32_t* __restrict__ csize,
+                                                       const unsigned long long* __restrict__ best,
+                                                       double* __restrict__ acc) {
+    __shared__ double lp[3 * 256];
+    const bool lds = G <= 256;
+    if (lds)
+        for (int i = threadIdx.x; i < 3 * G; i += blockDim.x) lp[i] = 0.0;
+    __syncthreads();
+    GRID_STRIDE(v, n) {
+        const int32_t sz = size[v];
+        if (sz == 0) continue;  // not a root
+        const unsigned long long rec = best[v];
+        const double x = (double)(rec >> 32), b = (double)csize[(int32_t)(uint32_t)rec], s = (double)sz;
+        double* dst = lds ? lp + 3 * gid[v] : acc + 3 * (int64_t)gid[v];
+        atomicAdd(dst + 0, x);
+        atomicAdd(dst + 1, x * s / b);
+        atomicAdd(dst + 2, 2.0 * x * s / (s + b));
+    }
+    __syncthreads();
+    if (lds)
+        for (int i = threadIdx.x; i < 3 * G; i += blockDim.x)
+            if (lp[i] != 0.0) atomicAdd(&acc[i], lp[i]);
+}
+
 // class sizes (truth ids lie in [0, n)), then B per graph
 __global__ __launch_bounds__(kThreads) void k_class_size(const int32_t* __restrict__ cls, int64_t n,
                                                          int32_t* __restrict__ csize) {
@@ -512,7 +575,9 @@ __global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_t
                                                           const unsigned long long* __restrict__ acc_vsq,
                                                           const int64_t* __restrict__ vbase, int has_truth,
                                                           mcd_sweep_stats* __restrict__ stats,
-                                                          double* __restrict__ ari, double* __restrict__ modularity) {
+                                                          double* __restrict__ ari, double* __restrict__ modularity,
+                                                          const double* __restrict__ acc_prf,
+                                                          double* __restrict__ prf) {
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
         int64_t kept = 0, mg = 0;
         for (int l = 0; l <= K; ++l) {
@@ -532,6 +597,13 @@ __global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_t
         st.intra_edges = modularity ? (int64_t)acc_intra[g] : 0;
         st.volume_sq = modularity ? (int64_t)acc_vsq[g] : 0;
         stats[(int64_t)g * K + out_i] = st;
+        if (prf) {
+            double* o = prf + ((int64_t)g * K + out_i) * 3;
+            const double nn = (double)nv;
+            o[0] = nv ? acc_prf[3 * g] / nn : 0.0;
+            o[1] = nv ? acc_prf[3 * g + 1] / nn : 0.0;
+            o[2] = nv ? acc_prf[3 * g + 2] / nn : 0.0;
+        }
         if (modularity) {
             const double mm = (double)mg;
             modularity[(int64_t)g * K + out_i] =
@@ -634,6 +706,8 @@ struct SweepLayout {
     unsigned long long* acc_intra;  // [G]
     unsigned long long* acc_vsq;    // [G]
     unsigned long long* vol;        // [n]
+    unsigned long long* best;       // [n] (planted labels)
+    double* acc_prf;                // [G][3]
     size_t bytes;
 };
 
@@ -660,6 +734,8 @@ SweepLayout sweep_layout(void* p, const mcd_graph* g, int G, int K, bool truth) 
     L.acc_intra = c.take<unsigned long long>((size_t)G);
     L.acc_vsq = c.take<unsigned long long>((size_t)G);
     L.vol = c.take<unsigned long long>((size_t)n);
+    L.best = truth ? c.take<unsigned long long>((size_t)n) : nullptr;
+    L.acc_prf = c.take<double>((size_t)3 * G);
     L.bytes = c.used;
     return L;
 }
@@ -672,9 +748,10 @@ size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth) {
 
 void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
                   const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
-                  mcd_sweep_stats* stats, double* ari, double* modularity, int32_t* labels, void* ws,
-                  hipStream_t s) {
+                  mcd_sweep_stats* stats, double* ari, double* modularity, double* prf, int32_t* labels,
+                  void* ws, hipStream_t s) {
     const int K = ds.K;
+    if (!truth) prf = nullptr;
     const int64_t n = g->n, m = g->m;
     SweepLayout L = sweep_layout(ws, g, G, K, truth != nullptr);
     const int l2 = truth ? cells_log2(n) : 0;
@@ -746,11 +823,19 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
                                    L.cls, L.keys, L.counts, l2);
                 hipLaunchKernelGGL(k_pass_s, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid, G,
                                    L.cls, L.keys, L.counts, l2, L.acc_s);
+                if (prf) {
+                    fill_t<unsigned long long>(L.best, n, 0ull, s);
+                    fill_t<double>(L.acc_prf, 3 * (int64_t)G, 0.0, s);
+                    hipLaunchKernelGGL(k_cells_best, dim3(grid_for(cap, 8192)), dim3(kThreads), 0, s, L.keys, L.counts,
+                                       cap, L.size, L.csize, L.best);
+                    hipLaunchKernelGGL(k_prf_sums, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, n, L.gid, G, L.size,
+                                       L.csize, L.best, L.acc_prf);
+                }
             }
         }
         hipLaunchKernelGGL(k_write_stats, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), 0, s, G, K, i,
                            out_index[i], L.hist, L.ncc, L.largest, L.acc_a, L.acc_s, L.acc_b, L.acc_intra,
-                           L.acc_vsq, vbase, truth ? 1 : 0, stats, ari, modularity);
+                           L.acc_vsq, vbase, truth ? 1 : 0, stats, ari, modularity, L.acc_prf, prf);
     }
 }
 

@@ -80,7 +80,7 @@ def lib():
             "mcd_run": [P, ctypes.c_int, mcd_rational, P, P, P, SZ],
             "mcd_percentile_workspace_size": [P, ctypes.POINTER(SZ)],
             "mcd_sweep_workspace_size": [P, I32, I32, I32, ctypes.POINTER(SZ)],
-            "mcd_sweep": [P, ctypes.c_int, P, P, I32, I32, P, P, P, P, P, P, P, SZ],
+            "mcd_sweep": [P, ctypes.c_int, P, P, I32, I32, P, P, P, P, P, P, P, P, SZ],
             "mcd_sweep_rule": [P, P, I32, I32, P, P, P, I64, I64, P, P],
             "mcd_features_workspace_size": [I32, ctypes.POINTER(SZ)],
             "mcd_features": [P, P, I32, P, P, P, SZ],
@@ -339,9 +339,11 @@ def mcd_sweep_workspace_size(g: Graph, n_graphs: int, K: int, has_truth: bool) -
 
 
 def mcd_sweep(g: Graph, measure: int, t, deltas, vbase=None, truth=None, stats=None, ari=None,
-              labels=None, want_labels=False, ws=None, modularity=None, want_modularity=False):
+              labels=None, want_labels=False, ws=None, modularity=None, want_modularity=False, prf=None,
+              want_prf=False):
     """Returns (stats int64[G][K][9], ari float64[G][K] or None, labels int32[K][n] or None),
-    plus modularity float64[G][K] as a fourth item when want_modularity or modularity is given."""
+    plus modularity float64[G][K] as a fourth item when want_modularity or modularity is given,
+    plus precision/recall/F1 float64[G][K][3] as a fifth when want_prf or prf is given."""
     K = len(deltas)
     dev = g.ctx.device
     if vbase is None:
@@ -354,14 +356,19 @@ def mcd_sweep(g: Graph, measure: int, t, deltas, vbase=None, truth=None, stats=N
         ari = _empty((G, K), torch.float64, dev)
     if labels is None and want_labels:
         labels = _empty((K, max(g.n, 1)), torch.int32, dev)
-    with_q = want_modularity or modularity is not None
+    with_prf = want_prf or prf is not None
+    with_q = want_modularity or modularity is not None or with_prf
     if modularity is None and want_modularity:
         modularity = _empty((G, K), torch.float64, dev)
+    if prf is None and want_prf:
+        prf = _empty((G, K, 3), torch.float64, dev)
     if ws is None:
         ws = _bytes(mcd_sweep_workspace_size(g, G, K, truth is not None), dev)
     _check(lib().mcd_sweep(g.handle, measure, _p(t), ctypes.cast(arr, ctypes.c_void_p), K, G, _p(vbase),
-                           _p(truth), _p(stats), _p(ari), _p(modularity), _p(labels), _p(ws),
+                           _p(truth), _p(stats), _p(ari), _p(modularity), _p(prf), _p(labels), _p(ws),
                            ws.numel() * ws.element_size()))
+    if with_prf:
+        return stats, ari, labels, modularity, prf
     return (stats, ari, labels, modularity) if with_q else (stats, ari, labels)
 
 

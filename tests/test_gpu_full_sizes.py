@@ -42,7 +42,7 @@ def test_c2_rmat_s20_percentile_both_measures():
         want = oracle.percentile(measure, lo_o, hi_o, t_o, deg, 3, 10)
         assert Fraction(num, den) == Fraction(*want)
         r = M.mcd_weigh_prune(g, measure, t, delta=(num, den), want_i32=(measure == oracle.TW))
-        keep_o = oracle.prune(measure, lo_o, hi_o, t_o, deg, num, den)
+        keep_o = oracle.prune(measure, lo_o, hi_o, t_o, deg, *want)
         assert np.array_equal(unpack_bits(r["keep_bits"], g.m)[order], keep_o)
         assert int(r["n_kept"].item()) == int(keep_o.sum())
         if measure == oracle.TECTONIC:
@@ -116,9 +116,19 @@ def test_c5_rmat_s26_sampled_edges_and_label_properties():
     u, v = M.mcd_graph_edges(g)
     deg = M.mcd_graph_degrees(g)
     torch.cuda.synchronize()
+    # query pairs drawn from the raw input (self-loops skipped), located in
+    # the library's edge order through a sorted key of its endpoints
     rng = np.random.default_rng(26)
-    idx = cuda(rng.choice(m, 512, replace=False).astype(np.int64))
-    qu, qv = u[idx].cpu().numpy(), v[idx].cpu().numpy()
+    pick = rng.choice(len(src), 2048, replace=False)
+    pick = pick[src[pick] != dst[pick]][:512]
+    qu = np.minimum(src[pick], dst[pick]).astype(np.int64)
+    qv = np.maximum(src[pick], dst[pick]).astype(np.int64)
+    lib_key = torch.minimum(u, v).long() * n + torch.maximum(u, v).long()
+    sorted_key, order = torch.sort(lib_key)
+    pos = torch.searchsorted(sorted_key, cuda(qu * n + qv))
+    assert bool((sorted_key[pos] == cuda(qu * n + qv)).all())
+    idx = order[pos]
+    del sorted_key, order, lib_key
     tg = t[idx].cpu().numpy()
     wg = r["w_f32"][idx].cpu().numpy()
     kb = r["keep_bits"].view(torch.int32)

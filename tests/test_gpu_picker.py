@@ -157,17 +157,20 @@ def test_picker_end_to_end_small_batch():
     best = A[va].max(1).mean()
     glob = A[va][:, np.argmax(A[tr].mean(0))].mean()
     print(f"small batch val ARI: picker {picked:.4f}  per-graph best {best:.4f}  best global {glob:.4f}")
-    # labels equal the oracle's components at the picked per-graph thresholds
+    # labels equal the oracle's components at the picked grid point of every
+    # graph: the oracle sweeps the whole grid by itself; the picked index only
+    # selects which of its results to compare with
     lo, hi = oracle.canon(n, b["src"], b["dst"])
     deg = oracle.degrees(n, lo, hi)
     to = oracle.triangles(n, lo, hi)
-    eg = np.searchsorted(b["vbase"], lo, side="right") - 1
-    keep = np.zeros(len(lo), np.uint8)
-    dd = deltas.cpu().numpy()
+    _, _, labels_o = oracle.sweep(n, lo, hi, to, deg, oracle.TECTONIC, PK.GRID, vbase=b["vbase"])
+    got = labels.cpu().numpy()
+    vb = b["vbase"]
     for k in range(G):
-        keep[eg == k] = oracle.prune(oracle.TECTONIC, lo, hi, to, deg, *dd[k])[eg == k]
-    lab_o, ncc_o = oracle.components(n, lo, hi, keep)
-    assert np.array_equal(labels.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o
+        assert np.array_equal(got[vb[k]:vb[k + 1]], labels_o[pi[k], vb[k]:vb[k + 1]]), k
+        assert tuple(deltas.cpu().numpy()[k]) == PK.GRID[pi[k]]
+    assert int(ncc.item()) == sum(int(np.count_nonzero(labels_o[pi[k], vb[k]:vb[k + 1]] ==
+                                                      np.arange(vb[k], vb[k + 1]))) for k in range(G))
 
 
 def test_picker_gain_on_planted_batch():

@@ -153,3 +153,43 @@ def test_sweep_modularity_and_rule_of_thumb():
             want = oracle.rule_of_thumb(st_o, deltas, vbase, q_o if with_q else None, jump)
             assert np.array_equal(idx.cpu().numpy(), want), (jump, with_q)
             assert np.array_equal(dl.cpu().numpy(), np.array([deltas[k] for k in want], np.int64))
+
+
+def test_sweep_precision_recall_f1():
+    from gpu_util import build
+    graphs = []
+    for g in range(4):
+        pr = gg.sbm_batch_params(g + 40)
+        n = min(pr["n"], 2000)
+        k = min(pr["k"], n // 4)
+        src, dst, lab = gg.sbm_skip(n, k, min(pr["d_in"] / (n / k - 1), 0.5),
+                                    pr["mu"] * pr["d_in"] / ((1 - pr["mu"]) * n), 3000 + g)
+        graphs.append((n, src, dst, lab))
+    vbase = np.zeros(len(graphs) + 1, np.int64)
+    srcs, dsts, truths, cb = [], [], [], 0
+    for i, (n, src, dst, lab) in enumerate(graphs):
+        vbase[i + 1] = vbase[i] + n
+        srcs.append(src + vbase[i])
+        dsts.append(dst + vbase[i])
+        truths.append(lab + cb)
+        cb += int(lab.max()) + 1
+    N = int(vbase[-1])
+    src = np.concatenate(srcs).astype(np.int32)
+    dst = np.concatenate(dsts).astype(np.int32)
+    truth = np.concatenate(truths).astype(np.int32)
+    deltas = GRID64[::5]
+    g = build(src, dst, N)
+    t = M.mcd_triangles(g)
+    stats, ari, labels, _, prf = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, deltas, vbase=torch.from_numpy(vbase).cuda(),
+                                             truth=torch.from_numpy(truth).cuda(), want_labels=True, want_prf=True)
+    labels, prf = labels.cpu().numpy()[:, :N], prf.cpu().numpy()
+    lo, hi = oracle.canon(N, src, dst)
+    deg = oracle.degrees(N, lo, hi)
+    to = oracle.triangles(N, lo, hi)
+    _, _, labels_o = oracle.sweep(N, lo, hi, to, deg, oracle.TECTONIC, deltas, truth, vbase)
+    assert np.array_equal(labels, labels_o)
+    for i in range(len(deltas)):
+        for gk in range(len(graphs)):
+            a, b = vbase[gk], vbase[gk + 1]
+            want = oracle.precision_recall_f1(labels_o[i, a:b], truth[a:b])
+            assert np.all(np.abs(prf[gk, i] - np.array(want)) <= 1e-12 * np.maximum(1.0, np.abs(want))), (i, gk)

@@ -515,3 +515,21 @@ def test_rule_of_thumb_cases():
     q = np.array([[0.1, 0.3, 0.5, 0.2]])
     assert oracle.rule_of_thumb(st2, deltas, vbase, q).tolist() == [2]
     assert oracle.rule_of_thumb(st2, deltas, vbase).tolist() == [3]  # no modularity: highest threshold
+
+
+def test_precision_recall_f1_hand_examples():
+    # S1 = {0,1,2}, S2 = {3,4}; C1 = {0,1}, C2 = {2,3,4}: S1 -> C1 (J 2/3 vs 1/5),
+    # S2 -> C2 (J 2/3): P = 4/5, R = 13/15, F1 = (12/5 + 8/5) / 5 = 4/5
+    p, r, f = oracle.precision_recall_f1([0, 0, 0, 3, 3], [1, 1, 2, 2, 2])
+    assert abs(p - 0.8) < 1e-15 and abs(r - 13 / 15) < 1e-15 and abs(f - 0.8) < 1e-15
+    # identical partitions
+    assert oracle.precision_recall_f1([5, 5, 7, 7, 7], [0, 0, 1, 1, 1]) == (1.0, 1.0, 1.0)
+    # all singletons against one class of size n: P = 1, R = 1/n, F1 = 2/(n+1)
+    n = 9
+    p, r, f = oracle.precision_recall_f1(list(range(n)), [0] * n)
+    assert p == 1.0 and abs(r - 1 / n) < 1e-15 and abs(f - 2 / (n + 1)) < 1e-15
+    # a Jaccard tie goes to the smaller class: S = {0,1}, C0 = {0,2}, C1 = {1,3}
+    p, r, f = oracle.precision_recall_f1([0, 0, 2, 3], [0, 1, 0, 1])
+    # S={0,1} -> C0 (x=1,b=2); S={2} -> C0 (x=1,b=2); S={3} -> C1 (x=1,b=2)
+    assert abs(p - (1 + 1 + 1) / 4) < 1e-15
+    assert abs(r - (1 * 2 / 2 + 1 * 1 / 2 + 1 * 1 / 2) / 4) < 1e-15
