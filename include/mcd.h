@@ -13,6 +13,7 @@
  *     TW          = t(u,v) - wedge(u,v) = 3 t - deg u - deg v + 2   (Eq. eq:tw)
  *     K3          = t(u,v)
  *     Jaccard     = t(u,v) / (deg u + deg v - t(u,v))
+ *     K4          = number of 4-cliques containing {u,v}
  *
  * Conventions
  *   - Every call returns mcd_status: MCD_OK (0) or a negative error.  Nothing
@@ -69,8 +70,10 @@ typedef enum {
     MCD_SIM_TECTONIC = 0, /* t / (deg u + deg v)                      */
     MCD_SIM_TW = 1,       /* t - wedge = 3t - deg u - deg v + 2       */
     MCD_SIM_K3 = 2,       /* t, the number of triangles on the edge   */
-    MCD_SIM_JACCARD = 3   /* t / (deg u + deg v - t) = |N(u) n N(v)| / |N(u) u N(v)|;
+    MCD_SIM_JACCARD = 3,  /* t / (deg u + deg v - t) = |N(u) n N(v)| / |N(u) u N(v)|;
                              Prop. 1: pruning it at p/q equals pruning Tectonic at p/(p+q) */
+    MCD_SIM_K4 = 4        /* kappa-clique participation, kappa = 4: the per-edge count of
+                             mcd_k4, passed where the other measures take t */
 } mcd_measure;
 
 /* ---------------------------------------------------------------- context */
@@ -173,10 +176,19 @@ mcd_status mcd_tune_triangles_workspace_size(const mcd_graph* g, size_t* bytes);
 mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes, int32_t reps,
                               int64_t* host_best, float* host_ms);
 
+/* kappa-clique participation for kappa = 4 (Table tab:simfunctions):
+ * k4[e] = the number of 4-cliques containing edge e (library edge order),
+ * device int32[m].  Each 4-clique is found once, from its lowest edge in the
+ * degree order, and credits its six edges with atomics.  The result feeds
+ * mcd_weights / mcd_prune / mcd_weigh_prune / mcd_sweep with MCD_SIM_K4 in
+ * place of t.  Errors: MCD_ERR_RANGE when a row of the oriented graph holds
+ * more than 4096 edges.  Asynchronous. */
+mcd_status mcd_k4(const mcd_graph* g, int32_t* k4);
+
 /* Edge similarity of Table tab:simfunctions from t (as produced by
  * mcd_triangles).  w_f32 (device float[m], may be NULL): the measure in IEEE
  * fp32; Tectonic and Jaccard as the correctly rounded quotient.
- * w_i32 (device int32[m], may be NULL; TW and K3 only): the exact integer. */
+ * w_i32 (device int32[m], may be NULL; TW, K3 and K4 only): the exact integer. */
 mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t, float* w_f32,
                        int32_t* w_i32);
 

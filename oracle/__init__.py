@@ -22,7 +22,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 _lib = None
 
-TECTONIC, TW, K3, JACCARD = 0, 1, 2, 3
+TECTONIC, TW, K3, JACCARD, K4 = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -45,6 +45,7 @@ def lib():
         L.or_degrees.argtypes = [I64, I64, P, P, P]
         L.or_adjacency.argtypes = [I64, I64, P, P, P, P, P]
         L.or_triangles.argtypes = [I64, P, P, P, P]
+        L.or_k4.argtypes = [I64, P, P, P, P]
         L.or_tectonic.argtypes = [I64, P, P, P, P, P]
         L.or_jaccard.argtypes = [I64, P, P, P, P, P]
         L.or_wedges.argtypes = [I64, P, P, P, P, P]
@@ -114,6 +115,14 @@ def triangles(n: int, lo, hi):
     t = np.zeros(max(len(lo), 1), np.int32)
     lib().or_triangles(n, _p(off), _p(adj), _p(eid), _p(t))
     return t[:len(lo)]
+
+
+def k4(n: int, lo, hi):
+    """Number of 4-cliques containing each canonical edge."""
+    off, adj, eid = adjacency(n, lo, hi)
+    c = np.zeros(max(len(lo), 1), np.int32)
+    lib().or_k4(n, _p(off), _p(adj), _p(eid), _p(c))
+    return c[:len(lo)]
 
 
 def tectonic(lo, hi, t, deg):
@@ -206,7 +215,8 @@ def run(n: int, src, dst, measure: int, num: int, den: int, timings: dict | None
     t2 = time.perf_counter()
     keep = prune(measure, lo, hi, t, deg, num, den)
     w = {TECTONIC: lambda: tectonic(lo, hi, t, deg), TW: lambda: tw(lo, hi, t, deg),
-         K3: lambda: t.astype(np.int64), JACCARD: lambda: jaccard(lo, hi, t, deg)}[measure]()
+         K3: lambda: t.astype(np.int64), JACCARD: lambda: jaccard(lo, hi, t, deg),
+         K4: lambda: t.astype(np.int64)}[measure]()
     t3 = time.perf_counter()
     labels, ncc = components(n, lo, hi, keep)
     t4 = time.perf_counter()

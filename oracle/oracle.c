@@ -151,6 +151,45 @@ void or_triangles(int64_t n, const int64_t* off, const int32_t* adj, const int32
     }
 }
 
+/* kappa-clique participation for kappa = 4 (Table tab:simfunctions): the
+ * number of 4-cliques containing edge {u,v} equals the number of adjacent
+ * pairs {x,y} inside N(u) n N(v).  Plain definition: mark N(u) n N(v), then
+ * for every marked x count the marked y > x in N(x).  off/adj/eid as built by
+ * or_adjacency (symmetric CSR); k4 indexed by edge id. */
+void or_k4(int64_t n, const int64_t* off, const int32_t* adj, const int32_t* eid, int32_t* k4) {
+#pragma omp parallel
+    {
+        unsigned char* inu = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+        unsigned char* com = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+        int32_t* list = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t u = 0; u < n; ++u) {
+            for (int64_t i = off[u]; i < off[u + 1]; ++i) inu[adj[i]] = 1;
+            for (int64_t i = off[u]; i < off[u + 1]; ++i) {
+                const int64_t v = adj[i];
+                if (v <= u) continue;  /* each edge once, from its smaller end */
+                int64_t L = 0;
+                for (int64_t j = off[v]; j < off[v + 1]; ++j)
+                    if (inu[adj[j]]) {
+                        com[adj[j]] = 1;
+                        list[L++] = adj[j];
+                    }
+                int64_t c = 0;
+                for (int64_t a = 0; a < L; ++a) {
+                    const int32_t x = list[a];
+                    for (int64_t j = off[x]; j < off[x + 1]; ++j) c += (adj[j] > x && com[adj[j]]);
+                }
+                for (int64_t a = 0; a < L; ++a) com[list[a]] = 0;
+                k4[eid[i]] = (int32_t)c;
+            }
+            for (int64_t i = off[u]; i < off[u + 1]; ++i) inu[adj[i]] = 0;
+        }
+        free(inu);
+        free(com);
+        free(list);
+    }
+}
+
 /* Tectonic similarity t(u,v) / (deg(u) + deg(v))  (Table tab:simfunctions),
  * in fp64. */
 void or_tectonic(int64_t m, const int32_t* lo, const int32_t* hi, const int32_t* t,
@@ -194,12 +233,14 @@ static int rat_cmp(int64_t a, int64_t b, int64_t c, int64_t d) {
 /* sim(e) of Table tab:simfunctions as an exact rational num : den, den > 0.
  * measure 0 Tectonic: t : (deg u + deg v);  1 TW: tw : 1 (tw = t - wedge,
  * precomputed);  2 K3 (triangles on the edge): t : 1;  3 Jaccard:
- * t : (deg u + deg v - t). */
+ * t : (deg u + deg v - t);  4 K4 (4-cliques on the edge): the count, passed
+ * in place of t, : 1. */
 static void sim_rat(int measure, int64_t t, int64_t du, int64_t dv, int64_t tw, int64_t* num, int64_t* den) {
     switch (measure) {
         case 0: *num = t; *den = du + dv; break;
         case 1: *num = tw; *den = 1; break;
-        case 2: *num = t; *den = 1; break;
+        case 2:
+        case 4: *num = t; *den = 1; break;
         default: *num = t; *den = du + dv - t; break;
     }
 }
@@ -209,7 +250,7 @@ static void sim_rat(int measure, int64_t t, int64_t du, int64_t dv, int64_t tw, 
  * with the rational form of sim (sim_rat). */
 int or_prune(int64_t m, int measure, const int32_t* lo, const int32_t* hi, const int32_t* t,
              const int32_t* deg, int64_t num, int64_t den, unsigned char* keep, int64_t* n_kept) {
-    if (den <= 0 || measure < 0 || measure > 3) return OR_ERR_ARG;
+    if (den <= 0 || measure < 0 || measure > 4) return OR_ERR_ARG;
     int64_t* tw = NULL;
     if (measure == 1) {
         tw = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
@@ -295,7 +336,7 @@ static int cmp_rat(const void* a, const void* b) {
 int or_percentile(int64_t m, int measure, const int32_t* lo, const int32_t* hi,
                   const int32_t* t, const int32_t* deg, int64_t pn, int64_t pd,
                   int64_t* out_num, int64_t* out_den) {
-    if (pd <= 0 || pn < 0 || pn > pd || measure < 0 || measure > 3) return OR_ERR_ARG;
+    if (pd <= 0 || pn < 0 || pn > pd || measure < 0 || measure > 4) return OR_ERR_ARG;
     rat_t* v = (rat_t*)malloc(sizeof(rat_t) * (size_t)(m > 0 ? m : 1));
     int64_t* tw = NULL;
     if (measure == 1) {

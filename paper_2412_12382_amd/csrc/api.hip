@@ -41,7 +41,7 @@ mcd_status use_device(const mcd_ctx* ctx) {
 }
 
 bool valid_measure(int m) {
-    return m == MCD_SIM_TECTONIC || m == MCD_SIM_TW || m == MCD_SIM_K3 || m == MCD_SIM_JACCARD;
+    return m == MCD_SIM_TECTONIC || m == MCD_SIM_TW || m == MCD_SIM_K3 || m == MCD_SIM_JACCARD || m == MCD_SIM_K4;
 }
 
 mcd_status check_delta(mcd_rational d) {
@@ -464,12 +464,22 @@ mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t w
     return MCD_OK;
 }
 
+mcd_status mcd_k4(const mcd_graph* g, int32_t* k4) {
+    REQUIRE(g && (g->m == 0 || k4), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g->max_outdeg <= MCD_K4_MAX_COMMON, MCD_ERR_RANGE,
+            "4-clique counts need every row of the oriented graph to hold at most 4096 edges");
+    mcd_status st = use_device(g->ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_k4(g, k4, g->ctx->stream);
+    return MCD_OK;
+}
+
 mcd_status mcd_weights(const mcd_graph* g, mcd_measure measure, const int32_t* t, float* w_f32,
                        int32_t* w_i32) {
     REQUIRE(g && (g->m == 0 || t), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
-    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3, MCD_ERR_INVALID_ARG,
-            "integer weights exist for TW and K3 only");
+    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3 || measure == MCD_SIM_K4,
+            MCD_ERR_INVALID_ARG, "integer weights exist for TW, K3 and K4 only");
     mcd_status st = use_device(g->ctx);
     if (st != MCD_OK) return st;
     mcd::launch_weights(g, measure, t, w_f32, w_i32, g->ctx->stream);
@@ -518,8 +528,8 @@ mcd_status mcd_weigh_prune(const mcd_graph* g, mcd_measure measure, const int32_
     REQUIRE(g, MCD_ERR_INVALID_ARG, "graph is NULL");
     REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
     REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
-    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3, MCD_ERR_INVALID_ARG,
-            "integer weights exist for TW and K3 only");
+    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3 || measure == MCD_SIM_K4,
+            MCD_ERR_INVALID_ARG, "integer weights exist for TW, K3 and K4 only");
     REQUIRE((kept_pairs == nullptr) == (kept_counts == nullptr), MCD_ERR_INVALID_ARG,
             "kept_pairs and kept_counts go together");
     mcd_status st;
@@ -793,7 +803,7 @@ mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, con
         prefix |= (uint32_t)d << shift;
         pmask |= 255u << shift;
     }
-    if (measure == MCD_SIM_TW || measure == MCD_SIM_K3) {  // integer similarities: the key is the value
+    if (measure == MCD_SIM_TW || measure == MCD_SIM_K3 || measure == MCD_SIM_K4) {  // integers: key = value
         host_out->num = (int64_t)(int32_t)(prefix ^ 0x80000000u);
         host_out->den = 1;
         return MCD_OK;

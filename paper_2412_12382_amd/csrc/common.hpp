@@ -27,6 +27,8 @@ struct mcd_ctx {
 #define MCD_TC_LDS_LIMIT 4096
 #define MCD_TC_PACKED_LIMIT ((1 << 20) - 2)
 #define MCD_CTRL_WORDS 64
+// longest common higher neighbourhood the 4-clique kernel holds in LDS
+#define MCD_K4_MAX_COMMON 4096
 
 struct mcd_graph {
     mcd_ctx* ctx;
@@ -145,6 +147,9 @@ int64_t kept_segment_len(int64_t m);
 void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den, int G,
                         const int64_t* vbase, const int64_t* deltas, float* wf, int32_t* wi, uint32_t* keep_bits,
                         int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s);
+
+// ---- 4-clique participation (k4.hip) ----
+void launch_k4(const mcd_graph* g, int32_t* k4, hipStream_t s);
 
 // ---- components (cc.hip) ----
 size_t cc_scratch_bytes(const mcd_graph* g);

@@ -33,8 +33,8 @@ __device__ __forceinline__ Sim sim_of(const int32_t* __restrict__ dsum, const in
     Sim s;
     const int64_t D = (uint32_t)dsum[e];
     const int32_t tt = t[e];
-    if (measure == MCD_SIM_TW || measure == MCD_SIM_K3) {  // integers: key = the value, sign-flipped
-        const int32_t x = measure == MCD_SIM_K3 ? tt : (int32_t)(3 * (int64_t)tt - D + 2);
+    if (measure == MCD_SIM_TW || measure == MCD_SIM_K3 || measure == MCD_SIM_K4) {  // integers: key = value
+        const int32_t x = measure == MCD_SIM_TW ? (int32_t)(3 * (int64_t)tt - D + 2) : tt;
         s.num = x;
         s.den = 1;
         s.nonzero = x != 0;

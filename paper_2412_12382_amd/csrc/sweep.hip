@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
     GRID_STRIDE(e, m) {
         const int64_t D = (uint32_t)dsum[e];
         const int64_t tt = t[e];
-        int64_t num = tt, den = 1;  // K3
+        int64_t num = tt, den = 1;  // K3, K4
         if (measure == MCD_SIM_TECTONIC) den = D;
         else if (measure == MCD_SIM_JACCARD) den = D - tt;
         else if (measure == MCD_SIM_TW) num = 3 * tt - D + 2;

@@ -2,7 +2,8 @@
 //
 // With D = deg u + deg v: Tectonic(e) = t / D, TW(e) = 3t - D + 2 (t - wedge
 // with |N(u) u N(v)| = D - t, Eq. eq:tw and the notation paragraph of Sec. 1),
-// K3(e) = t (triangles on the edge) and Jaccard(e) = t / (D - t).  Every
+// K3(e) = t (triangles on the edge), K4(e) = the 4-clique count (passed in
+// place of t) and Jaccard(e) = t / (D - t).  Every
 // similarity is an exact rational sn / sd and the keep decision never uses
 // floating point: with delta = num/den (den > 0) an edge is kept iff
 // sn * den >= num * sd, in 64- or 128-bit integers.
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
                     sd = MEASURE == MCD_SIM_TECTONIC ? D : D - tt[j];  // D - t >= t + 2 > 0
                     if (wf) wf[e] = ratio_f32(tt[j], sd);
                 } else {
-                    sn = MEASURE == MCD_SIM_K3 ? (int64_t)tt[j] : 3 * (int64_t)tt[j] - D + 2;
+                    sn = MEASURE == MCD_SIM_TW ? 3 * (int64_t)tt[j] - D + 2 : (int64_t)tt[j];
                     sd = 1;
                     if (wi) wi[e] = (int32_t)sn;
                     if (wf) wf[e] = (float)sn;
@@ -168,6 +169,7 @@ void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64
             else MCD_WP_LAUNCH(MCD_SIM_TW, false);
             break;
         case MCD_SIM_K3:
+        case MCD_SIM_K4:  // the count array passed as t
             if (multi) MCD_WP_LAUNCH(MCD_SIM_K3, true);
             else MCD_WP_LAUNCH(MCD_SIM_K3, false);
             break;

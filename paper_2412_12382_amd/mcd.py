@@ -23,6 +23,7 @@ MCD_SIM_TECTONIC = 0
 MCD_SIM_TW = 1
 MCD_SIM_K3 = 2
 MCD_SIM_JACCARD = 3
+MCD_SIM_K4 = 4
 
 STATUS = {0: "MCD_OK", -1: "MCD_ERR_INVALID_ARG", -2: "MCD_ERR_INVALID_VERTEX", -3: "MCD_ERR_RANGE",
           -4: "MCD_ERR_WORKSPACE", -5: "MCD_ERR_NO_DEVICE", -6: "MCD_ERR_DEVICE",
@@ -96,6 +97,7 @@ def lib():
             "mcd_kept_segment_len": [P, ctypes.POINTER(I64)],
             "mcd_components_kept": [P, P, P, P, P, P, SZ],
             "mcd_tune_triangles_workspace_size": [P, ctypes.POINTER(SZ)],
+            "mcd_k4": [P, P],
             "mcd_tune_triangles": [P, P, P, SZ, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float)],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
@@ -266,6 +268,13 @@ def mcd_triangles(g: Graph, t=None, ws=None):
         ws = _bytes(mcd_triangles_workspace_size(g), g.ctx.device)
     _check(lib().mcd_triangles(g.handle, _p(t), _p(ws), ws.numel() * ws.element_size()))
     return t[:g.m]
+
+
+def mcd_k4(g: Graph, k4=None):
+    """Number of 4-cliques containing every edge (library edge order)."""
+    k4 = _empty(max(g.m, 1), torch.int32, g.ctx.device) if k4 is None else k4
+    _check(lib().mcd_k4(g.handle, _p(k4)))
+    return k4[:g.m]
 
 
 def mcd_weights(g: Graph, measure: int, t, w_f32=None, w_i32=None, want_f32=True, want_i32=False):

@@ -245,3 +245,38 @@ def test_prop1_on_the_gpu():
         kj, nj = M.mcd_prune(g, M.MCD_SIM_JACCARD, t, (p, q))
         kt, nt = M.mcd_prune(g, M.MCD_SIM_TECTONIC, t, (p, p + q))
         assert torch.equal(kj[:words], kt[:words]) and int(nj.item()) == int(nt.item())
+
+
+@pytest.mark.parametrize("case", ["c1", "rmat12", "rmat14", "k9", "random"])
+def test_k4_participation_and_prune(case):
+    from gpu_util import build, canonical_order, unpack_bits
+    if case == "c1":
+        c1 = gg.sbm_c1()
+        s, d, n = c1["src"], c1["dst"], c1["n"]
+    elif case.startswith("rmat"):
+        s, d, n = gg.rmat(int(case[4:]), seed=70)
+    elif case == "k9":
+        pairs = [(i, j) for i in range(9) for j in range(i + 1, 9)]
+        s = np.array([p[0] for p in pairs], np.int32)
+        d = np.array([p[1] for p in pairs], np.int32)
+        n = 9
+    else:
+        rng = np.random.default_rng(71)
+        n = 400
+        s = rng.integers(0, n, 12000).astype(np.int32)
+        d = rng.integers(0, n, 12000).astype(np.int32)
+    g = build(s, d, n)
+    lo, hi, order = canonical_order(g)
+    k4 = M.mcd_k4(g)
+    want = oracle.k4(n, lo, hi)
+    assert np.array_equal(k4.cpu().numpy()[order], want)
+    if case == "k9":
+        assert np.all(want == 21)  # C(7, 2)
+    deg = oracle.degrees(n, lo, hi)
+    thr = (max(1, int(np.median(want))), 1)
+    keep, nk = M.mcd_prune(g, M.MCD_SIM_K4, k4, thr)
+    keep_o = oracle.prune(oracle.K4, lo, hi, want, deg, *thr)
+    assert np.array_equal(unpack_bits(keep, g.m)[order], keep_o)
+    lab, ncc = M.mcd_components(g, keep)
+    lab_o, ncc_o = oracle.components(n, lo, hi, keep_o)
+    assert np.array_equal(lab.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o

@@ -533,3 +533,31 @@ def test_precision_recall_f1_hand_examples():
     # S={0,1} -> C0 (x=1,b=2); S={2} -> C0 (x=1,b=2); S={3} -> C1 (x=1,b=2)
     assert abs(p - (1 + 1 + 1) / 4) < 1e-15
     assert abs(r - (1 * 2 / 2 + 1 * 1 / 2 + 1 * 1 / 2) / 4) < 1e-15
+
+
+def test_k4_participation_pins():
+    # brute force over all 4-subsets on tiny graphs; K_n closed form C(n-2, 2)
+    import itertools
+    for k in (4, 5, 7):
+        lo, hi, deg, t = full(k, complete(k))
+        assert np.all(oracle.k4(k, lo, hi) == (k - 2) * (k - 3) // 2)
+    for seed in range(5):
+        rng = np.random.default_rng(60 + seed)
+        n = int(rng.integers(5, 14))
+        A = np.triu(rng.random((n, n)) < 0.6, 1)
+        pairs = [(i, j) for i in range(n) for j in range(i + 1, n) if A[i, j]]
+        if not pairs:
+            continue
+        lo, hi = edges_of(n, pairs)
+        S = set(zip(lo.tolist(), hi.tolist()))
+        want = {e: 0 for e in S}
+        for q in itertools.combinations(range(n), 4):
+            es = list(itertools.combinations(q, 2))
+            if all(e in S for e in es):
+                for e in es:
+                    want[e] += 1
+        got = oracle.k4(n, lo, hi)
+        assert [want[e] for e in zip(lo.tolist(), hi.tolist())] == got.tolist()
+        # K4-prune at c keeps exactly the edges in at least c 4-cliques
+        keep = oracle.prune(oracle.K4, lo, hi, got, oracle.degrees(n, lo, hi), 2, 1)
+        assert np.array_equal(keep, (got >= 2).astype(np.uint8))
