@@ -602,8 +602,8 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
-    launch_window_g<14, 256, 64>(g, L, 8, chunk, t, s);
-    launch_window_g<16, 512, 64>(g, L, 9, chunk, t, s);
+    launch_window_g<14, 512, 64>(g, L, 8, chunk, t, s);
+    launch_window_g<16, 1024, 64>(g, L, 9, chunk, t, s);
     launch_window_g<18, 1024, 64>(g, L, 10, chunk, t, s);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
