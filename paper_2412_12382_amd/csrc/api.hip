@@ -279,6 +279,13 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     // Degrees, rank by (degree, id), orientation low -> high rank, CSR.
     mcd::fill_i32(B.deg_orig, n, 0, s);
     mcd::launch_degree(B.uniq, m, bits, B.deg_orig, s);
+    {  // upper endpoints: sorted as 32-bit keys, then counted by runs (no random atomics)
+        uint32_t* h1 = (uint32_t*)B.k1;
+        uint32_t* h2 = (uint32_t*)B.k2;
+        mcd::launch_upper_ends(B.uniq, m, bits, h1, s);
+        const uint32_t* sorted_hi = mcd::radix_sort_u32(h1, h2, m, bits, B.radix, s);
+        mcd::launch_count_runs(sorted_hi, m, B.deg_orig, s);
+    }
     mcd::launch_rank_keys(B.deg_orig, n, bits, B.k1, s);
     uint64_t* ranked = mcd::radix_sort_u64(B.k1, B.k2, n, 2 * bits, B.radix, s);
     mcd::launch_rank_apply(ranked, n, bits, B.deg_orig, G.perm, B.inv, G.deg, s);

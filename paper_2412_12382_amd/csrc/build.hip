@@ -40,29 +40,41 @@ __global__ __launch_bounds__(kThreads) void k_canon(const int32_t* __restrict__ 
     }
 }
 
-// deg[x] += 1 for both endpoints of every unique edge.  The keys are sorted by
-// their lower endpoint, so the lanes of a wave hold runs of equal lower
-// endpoints: each run adds its length with one atomic (a hub's run would
-// otherwise serialise 64 same-address atomics per wave).
+// deg[x] += the number of occurrences of x in a sequence whose equal values
+// are adjacent: the lanes of a wave hold runs of equal values and each run
+// adds its length with one atomic (a hub's run would otherwise serialise 64
+// same-address atomics per wave; a run crossing waves adds in parts).
+template <class T>
+__device__ __forceinline__ void add_runs(T x, int32_t* __restrict__ deg) {
+    const int lane = threadIdx.x & 63;
+    const T prev = __shfl_up(x, 1);
+    const bool head = lane == 0 || prev != x;
+    const uint64_t heads = __ballot(head);
+    const uint64_t active = __ballot(true);
+    if (head) {
+        // run = lanes from this head up to the next head (or the last active lane)
+        const uint64_t above = heads & ~((2ull << lane) - 1ull);
+        const int end = above ? __ffsll((long long)above) - 1 : 64 - __clzll((long long)active);
+        atomicAdd(&deg[x], end - lane);
+    }
+}
+
+// Lower endpoints of the unique keys (sorted by lower endpoint).
 __global__ __launch_bounds__(kThreads) void k_degree(const uint64_t* __restrict__ uniq, int64_t m,
                                                      int bits, int32_t* __restrict__ deg) {
+    GRID_STRIDE(e, m) add_runs<int32_t>((int32_t)(uniq[e] >> bits), deg);
+}
+
+__global__ __launch_bounds__(kThreads) void k_upper_ends(const uint64_t* __restrict__ uniq, int64_t m, int bits,
+                                                         uint32_t* __restrict__ hi) {
     const uint64_t mask = (1ull << bits) - 1;
-    const int lane = threadIdx.x & 63;
-    GRID_STRIDE(e, m) {
-        const uint64_t k = uniq[e];
-        const int32_t lo = (int32_t)(k >> bits);
-        const int32_t prev = __shfl_up(lo, 1);
-        const bool head = lane == 0 || prev != lo;
-        const uint64_t heads = __ballot(head);
-        const uint64_t active = __ballot(true);
-        if (head) {
-            // run = lanes from this head up to the next head (or the last active lane)
-            const uint64_t above = heads & ~((2ull << lane) - 1ull);
-            const int end = above ? __ffsll((long long)above) - 1 : 64 - __clzll((long long)active);
-            atomicAdd(&deg[lo], end - lane);
-        }
-        atomicAdd(&deg[k & mask], 1);
-    }
+    GRID_STRIDE(e, m) hi[e] = (uint32_t)(uniq[e] & mask);
+}
+
+// Upper endpoints after sorting: equal values are adjacent.
+__global__ __launch_bounds__(kThreads) void k_count_runs(const uint32_t* __restrict__ sorted, int64_t m,
+                                                         int32_t* __restrict__ deg) {
+    GRID_STRIDE(e, m) add_runs<int32_t>((int32_t)sorted[e], deg);
 }
 
 __global__ __launch_bounds__(kThreads) void k_rank_keys(const int32_t* __restrict__ deg, int64_t n,
@@ -220,6 +232,16 @@ void launch_canon(const int32_t* src, const int32_t* dst, int64_t P, int64_t n, 
 void launch_degree(const uint64_t* uniq, int64_t m, int bits, int32_t* deg, hipStream_t s) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_degree, dim3(grid_for(m)), dim3(kThreads), 0, s, uniq, m, bits, deg);
+}
+
+void launch_upper_ends(const uint64_t* uniq, int64_t m, int bits, uint32_t* hi, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_upper_ends, dim3(grid_for(m)), dim3(kThreads), 0, s, uniq, m, bits, hi);
+}
+
+void launch_count_runs(const uint32_t* sorted, int64_t m, int32_t* deg, hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_count_runs, dim3(grid_for(m)), dim3(kThreads), 0, s, sorted, m, deg);
 }
 
 void launch_rank_keys(const int32_t* deg, int64_t n, int bits, uint64_t* keys, hipStream_t s) {

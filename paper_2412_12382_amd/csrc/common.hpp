@@ -86,6 +86,8 @@ namespace mcd {
 size_t radix_scratch_bytes(int64_t N);
 uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch,
                          hipStream_t s, int first_bit = 0);
+// The same for 32-bit keys on bits [0, nbits).
+uint32_t* radix_sort_u32(uint32_t* a, uint32_t* b, int64_t N, int nbits, void* scratch, hipStream_t s);
 // Distinct keys of a sorted array, MCD_SENTINEL excluded, into out; the count
 // goes to *d_count (device).  scratch: compact_scratch_bytes(N).
 size_t compact_scratch_bytes(int64_t N);
@@ -102,7 +104,11 @@ void fill_u32(uint32_t* p, int64_t N, uint32_t v, hipStream_t s);
 // ---- graph construction (build.hip) ----
 void launch_canon(const int32_t* src, const int32_t* dst, int64_t P, int64_t n, int bits,
                   uint64_t* keys, int64_t* d_err, hipStream_t s);
+// deg[x] += occurrences of x as the lower endpoint of the sorted unique keys
 void launch_degree(const uint64_t* uniq, int64_t m, int bits, int32_t* deg_orig, hipStream_t s);
+// hi[e] = upper endpoint of key e (to be sorted), then deg[x] += its run length
+void launch_upper_ends(const uint64_t* uniq, int64_t m, int bits, uint32_t* hi, hipStream_t s);
+void launch_count_runs(const uint32_t* sorted, int64_t m, int32_t* deg, hipStream_t s);
 void launch_rank_keys(const int32_t* deg_orig, int64_t n, int bits, uint64_t* keys, hipStream_t s);
 void launch_rank_apply(const uint64_t* sorted, int64_t n, int bits, const int32_t* deg_orig,
                        int32_t* perm, int32_t* inv, int32_t* deg_new, hipStream_t s);

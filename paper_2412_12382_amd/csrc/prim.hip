@@ -26,7 +26,8 @@ inline int grid_blocks(int64_t tiles) {
 __device__ __forceinline__ uint64_t lane_lt_mask() { return __lanemask_lt(); }
 
 // Digit histogram of block b's key range, stored digit-major: counts[d*NB + b].
-__global__ __launch_bounds__(kThreads) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t N,
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_rs_hist(const K* __restrict__ keys, int64_t N,
                                                       int shift, int64_t tpb, int NB,
                                                       int64_t* __restrict__ counts) {
     __shared__ uint32_t h[kWaves][256];
@@ -130,8 +131,9 @@ __device__ __forceinline__ T block_excl_scan(T x, T* sh, T* total) {
 // wave, so the rank order equals the input order.  The ranked tile is first
 // placed in LDS grouped by digit, then written out so that consecutive
 // threads store consecutive keys of a digit's run (coalesced writes).
-__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restrict__ in,
-                                                         uint64_t* __restrict__ out, int64_t N,
+template <class K>
+__global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ in,
+                                                         K* __restrict__ out, int64_t N,
                                                          int shift, int64_t tpb, int NB,
                                                          const int64_t* __restrict__ rowpre,
                                                          const int64_t* __restrict__ rowtot) {
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restr
     __shared__ uint32_t wcnt[kWaves][256];
     __shared__ uint32_t loff[256];
     __shared__ uint32_t tcnt[256];
-    __shared__ uint64_t stage[kTile];
+    __shared__ K stage[kTile];
     __shared__ int64_t sh64[kWaves];
     __shared__ uint32_t sh32[kWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -155,14 +157,14 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restr
     __syncthreads();
     for (int64_t tile = t0; tile < t1; ++tile) {
         for (int j = lane; j < 256; j += 64) wcnt[w][j] = 0;
-        uint64_t key[kIters];
+        K key[kIters];
         uint32_t rnk[kIters];
         const int64_t base = tile * kTile + (int64_t)w * (kTile / kWaves);
 #pragma unroll
         for (int it = 0; it < kIters; ++it) {
             const int64_t i = base + it * 64 + lane;
             const bool valid = i < N;
-            const uint64_t k = valid ? in[i] : 0;
+            const K k = valid ? in[i] : (K)0;
             const uint32_t d = (uint32_t)(k >> shift) & 255u;
             uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* __restr
         __syncthreads();
         const int64_t tile_n = min((int64_t)kTile, N - tile * kTile);
         for (int j = tid; j < tile_n; j += kThreads) {
-            const uint64_t k = stage[j];
+            const K k = stage[j];
             const uint32_t d = (uint32_t)(k >> shift) & 255u;
             out[run[d] + (j - (int64_t)loff[d])] = k;
         }
@@ -335,8 +337,8 @@ void fill_any(T* p, int64_t N, T v, hipStream_t s) {
 
 size_t radix_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * 256 * (kMaxBlocks + 1)); }
 
-uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch,
-                         hipStream_t s, int first_bit) {
+template <class K>
+K* radix_sort(K* a, K* b, int64_t N, int nbits, void* scratch, hipStream_t s, int first_bit) {
     if (N <= 1 || nbits <= 0) return a;
     const int64_t ntiles = div_up(N, kTile);
     const int NB = grid_blocks(ntiles);
@@ -346,15 +348,23 @@ uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* s
     const int passes = (nbits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         const int shift = first_bit + 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(NB), dim3(kThreads), 0, s, a, N, shift, tpb, NB, counts);
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3(NB), dim3(kThreads), 0, s, a, N, shift, tpb, NB, counts);
         hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kThreads), 0, s, counts, NB, tot);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(NB), dim3(kThreads), 0, s, a, b, N, shift, tpb, NB,
-                           counts, tot);
-        uint64_t* t = a;
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(NB), dim3(kThreads), 0, s, a, b, N, shift, tpb, NB, counts, tot);
+        K* t = a;
         a = b;
         b = t;
     }
     return a;
+}
+
+uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch, hipStream_t s,
+                         int first_bit) {
+    return radix_sort<uint64_t>(a, b, N, nbits, scratch, s, first_bit);
+}
+
+uint32_t* radix_sort_u32(uint32_t* a, uint32_t* b, int64_t N, int nbits, void* scratch, hipStream_t s) {
+    return radix_sort<uint32_t>(a, b, N, nbits, scratch, s, 0);
 }
 
 size_t compact_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * (kMaxBlocks + 1)); }
