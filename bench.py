@@ -9,8 +9,9 @@ timed step is one full pass of the path on the GPU:
     graph build (canonicalise, dedup, degree rank, oriented CSR, in-edge lists)
     -> per-edge triangle counts
     -> learned threshold (features, FP32 MLP, snap to the grid (9 + 7 i)/900)
-    -> weights and prune at that threshold in one pass (Tectonic fp32 weights,
-       keep mask, kept-edge list) -> connected components (min-vertex labels)
+    -> weights, prune and connected components at that threshold in one pass
+       (Tectonic fp32 weights, keep mask, every kept edge united as it is
+       decided; then min-vertex labels)
     -> 16-point check sweep at k/50, k = 0..15 (kept edges, components,
        largest component per threshold).
 value = undirected edges m / step time.  HIP events around every stage give
@@ -221,8 +222,6 @@ def main():
     t = torch.empty(P, dtype=torch.int32, device=dev)
     wf = torch.empty(P, dtype=torch.float32, device=dev)
     keep = torch.empty((P + 31) // 32 + 1, dtype=torch.int32, device=dev)
-    kept_pairs = torch.empty(M.KeptList.capacity(P), dtype=torch.int32, device=dev)
-    kept_counts = torch.empty(M.KEPT_SEGMENTS, dtype=torch.int32, device=dev)
     n_kept = torch.empty(1, dtype=torch.int64, device=dev)
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ncc = torch.empty(1, dtype=torch.int64, device=dev)
@@ -237,7 +236,7 @@ def main():
     log(f"HBM in use after allocation: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    stage_names = ["build", "triangles", "picker", "weigh_prune", "components", "sweep16"]
+    stage_names = ["build", "triangles", "picker", "prune_components", "sweep16"]
 
     def step():
         e = [ev() for _ in range(len(stage_names) + 1)]
@@ -253,15 +252,13 @@ def main():
         else:
             pdelta.copy_(torch.tensor([[3, 50]], dtype=torch.int64))
         e[3].record()
-        kept = M.KeptList(g, kept_pairs, kept_counts)
-        M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, t, deltas=pdelta, vbase=vbase, w_f32=wf, keep_bits=keep,
-                          kept=kept, n_kept=n_kept)
+        # weights, prune and components in one pass over the edges
+        M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, deltas=pdelta, vbase=vbase, w_f32=wf, keep_bits=keep,
+                               n_kept=n_kept, labels=labels, n_components=ncc, ws=ws)
         e[4].record()
-        M.mcd_components_kept(g, kept, labels, ncc, ws=ws)
-        e[5].record()
         M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, grid16, vbase=vbase, stats=sweep_stats, ws=ws)
         M.mcd_sweep_rule(ctx, grid16, sweep_stats, None, vbase=vbase, index=rule_idx)
-        e[6].record()
+        e[5].record()
         return g, e
 
     tuned = None
@@ -312,7 +309,7 @@ def main():
     # the kept edges read once by the union step and 12 bytes per vertex
     # (parent, label, original id)
     wpc_bytes = 16.0 * m + m / 8.0 + 8.0 * (n + 1) + 8.0 * kept + 12.0 * n
-    wpc_ms = avg["weigh_prune"] + avg["components"]
+    wpc_ms = avg["prune_components"]
     wpc_gbs = wpc_bytes / (wpc_ms * 1e-3) / 1e9
     ncomp = int(ncc.item())
     sw = sweep_stats.cpu().numpy()[0]
@@ -343,7 +340,7 @@ def main():
                                f"(a,b,c,d)=(0.57,0.19,0.19,0.05), symmetrised, deduplicated; Tectonic weights, "
                                f"learned threshold, 16-point check sweep k/50, components",
                    "n": n, "m": m, "pairs": P,
-                   "step": "build+triangles+picker+weights/prune+components+sweep16",
+                   "step": "build+triangles+picker+weights/prune/components+sweep16",
                    "triangle_params": tuned},
         "stages_ms": {k: round(v_, 3) for k, v_ in avg.items()},
         "wpc_edges_per_s": m / (wpc_ms * 1e-3),
@@ -353,8 +350,9 @@ def main():
                      "merge_work_W": W},
         "roofline_wpc": {"bound": "hbm", "achieved": wpc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": wpc_gbs / HBM_PEAK_GBS, "algorithmic_bytes": wpc_bytes,
-                         "traffic": profiled_traffic(["weigh_prune", "components"]),
-                         "kernel": "weigh_prune+components"},
+                         "traffic": profiled_traffic(["prune_components"]),
+                         "kernel": "prune_components (k_cc_init, k_weigh_prune with unions, k_cc_min, "
+                                   "k_cc_label)"},
         "results": {"triangles": tri, "picked_delta": pick_delta, "n_kept": kept, "n_components": ncomp,
                     "sweep16": {"delta": [f"{a}/{b}" for a, b in grid16],
                                 "m_kept": sw[:, 0].tolist(), "n_components": sw[:, 1].tolist(),

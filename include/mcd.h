@@ -255,6 +255,18 @@ mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t
 mcd_status mcd_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
                                int32_t* labels, int64_t* n_components, void* ws, size_t ws_bytes);
 
+/* Algorithm 1's two steps fused into one pass over the edges, from given
+ * similarity inputs t: the weights and keep decisions of mcd_weigh_prune
+ * (delta, or per-graph deltas with vbase; w_f32, w_i32, keep_bits and n_kept
+ * may each be NULL), with every kept edge united in the components' union-find
+ * as soon as it is decided, then labels and n_components as mcd_components.
+ * No kept-edge list is written.  labels: device int32[n];
+ * ws: mcd_components_workspace_size bytes.  Asynchronous. */
+mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
+                                int32_t n_graphs, const int64_t* vbase, const int64_t* deltas, float* w_f32,
+                                int32_t* w_i32, uint32_t* keep_bits, int64_t* n_kept, int32_t* labels,
+                                int64_t* n_components, void* ws, size_t ws_bytes);
+
 /* Algorithm 1 in one call: triangles, weights, prune at delta, components.
  * labels / n_components as in mcd_components.  Asynchronous. */
 mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, int32_t* labels,

@@ -552,6 +552,33 @@ mcd_status mcd_weigh_prune(const mcd_graph* g, mcd_measure measure, const int32_
     return MCD_OK;
 }
 
+mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
+                                int32_t n_graphs, const int64_t* vbase, const int64_t* deltas, float* w_f32,
+                                int32_t* w_i32, uint32_t* keep_bits, int64_t* n_kept, int32_t* labels,
+                                int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3 || measure == MCD_SIM_K4,
+            MCD_ERR_INVALID_ARG, "integer weights exist for TW, K3 and K4 only");
+    REQUIRE(ws_bytes >= mcd::cc_scratch_bytes(g), MCD_ERR_WORKSPACE, "components workspace too small");
+    mcd_status st;
+    if (deltas) {
+        REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "n_graphs must be at least 1");
+        REQUIRE(n_graphs == 1 || vbase, MCD_ERR_INVALID_ARG, "vbase is NULL");
+    } else if ((st = check_delta(delta)) != MCD_OK) {
+        return st;
+    }
+    if ((st = use_device(g->ctx)) != MCD_OK) return st;
+    hipStream_t s = g->ctx->stream;
+    // with no vertex there is no edge either: the pass only zeroes n_kept
+    int32_t* parent = mcd::launch_components_init(g, labels, n_components, ws, s);
+    mcd::launch_weigh_prune(g, measure, t, delta.num, delta.den, deltas ? n_graphs : 1, vbase, deltas, w_f32, w_i32,
+                            keep_bits, nullptr, nullptr, n_kept, s, g->n > 0 ? parent : nullptr);
+    mcd::launch_components_finish(g, labels, n_components, ws, s);
+    return MCD_OK;
+}
+
 mcd_status mcd_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
                                int32_t* labels, int64_t* n_components, void* ws, size_t ws_bytes) {
     REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");

@@ -6,11 +6,14 @@
 // halving, i.e. pointer jumping to the grandparent.  Parents only ever point
 // to higher ranks, so chains are acyclic; roots end at high-degree vertices,
 // which keeps trees shallow on skewed graphs.  The canonical label of a
-// component, its smallest original id, is then gathered per root with one
-// atomic minimum per vertex (aggregated over the wave) and read back by every
-// member.  Parent reads and halving writes use device-scope atomics so no wave
-// spins on a stale per-CU cache line.
+// component is its smallest original id.  The label array itself holds the
+// running minimum: every label starts as its own original id, a root's label
+// cell takes the atomic minimum of its members' ids, and each member then
+// copies its root's cell.  Singletons, most vertices of a pruned graph, are
+// touched only by the first write.  Parent reads and halving writes use
+// device-scope atomics so no wave spins on a stale per-CU cache line.
 #include "common.hpp"
+#include "unionfind.hpp"
 
 namespace mcd {
 namespace {
@@ -24,47 +27,14 @@ inline unsigned grid_for(int64_t N, int64_t cap) {
     return (unsigned)b;
 }
 
-__device__ __forceinline__ int32_t ld_parent(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void st_parent(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x) {
-    for (;;) {
-        const int32_t p = ld_parent(&parent[x]);
-        if (p == x) return x;
-        const int32_t gp = ld_parent(&parent[p]);
-        if (gp != p) st_parent(&parent[x], gp);
-        x = gp;
-    }
-}
-
-__device__ __forceinline__ void unite(int32_t* parent, int32_t a, int32_t b) {
-    for (;;) {
-        a = find_root(parent, a);
-        b = find_root(parent, b);
-        if (a == b) return;
-        if (a > b) {
-            const int32_t x = a;
-            a = b;
-            b = x;
-        }
-        int32_t expected = a;  // hook the lower-ranked root a under b
-        if (__hip_atomic_compare_exchange_strong(&parent[a], &expected, b, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            return;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_cc_init(int32_t* __restrict__ parent, int32_t* __restrict__ minid,
-                                                      const int32_t* __restrict__ perm, int64_t n) {
+// Singletons: parent[v] = v, and every label (indexed by original id) its
+// own original id.
+__global__ __launch_bounds__(kThreads) void k_cc_init(int32_t* __restrict__ parent, int32_t* __restrict__ labels,
+                                                      int64_t n) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         parent[v] = (int32_t)v;
-        minid[v] = perm[v];
+        labels[v] = (int32_t)v;
     }
 }
 
@@ -75,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_cc_union(const int32_t* __restrict
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         if (keep && !((keep[e >> 5] >> (e & 31)) & 1u)) continue;
-        unite(parent, src[e], adj[e]);
+        uf_unite(parent, src[e], adj[e]);
     }
 }
 
@@ -92,37 +62,44 @@ __global__ __launch_bounds__(kThreads) void k_cc_union_kept(const int2* __restri
     const int2* p = kept + seg * seg_len;
     for (int32_t i = cnt - 1 - lane; i >= 0; i -= 64) {
         const int2 e = p[i];
-        unite(parent, e.x, e.y);
+        uf_unite(parent, e.x, e.y);
     }
 }
 
-// minid[root] = min over the component of the original ids
+// The label cell of every root, labels[perm[root]], takes the minimum of its
+// members' original ids.
 __global__ __launch_bounds__(kThreads) void k_cc_min(int32_t* parent, const int32_t* __restrict__ perm, int64_t n,
-                                                     int32_t* __restrict__ minid) {
+                                                     int32_t* __restrict__ labels) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t nround = (n + stride - 1) / stride;
     for (int64_t rd = 0; rd < nround; ++rd) {
         const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + rd * stride;
         int32_t r = -1, id = 0x7fffffff;
         if (v < n) {
-            r = find_root(parent, (int32_t)v);
-            if (r != (int32_t)v) id = perm[v];
-            else r = -1;  // a root's own id is already in minid
+            const int32_t p = uf_load(&parent[v]);
+            if (p != (int32_t)v) {
+                r = uf_find(parent, p);
+                id = perm[v];
+            }
         }
-        // lanes sharing lane 0's root reduce first
-        const int32_t r0 = __shfl(r, 0);
+        const uint64_t act = __ballot(r >= 0);
+        if (act == 0) continue;  // wave-uniform: only roots here
+        // lanes sharing the first active lane's root reduce first
+        const int lead = __ffsll((unsigned long long)act) - 1;
+        const int32_t r0 = __shfl(r, lead);
         int32_t x = r == r0 ? id : 0x7fffffff;
         for (int o = 32; o > 0; o >>= 1) {
             const int32_t y = __shfl_xor(x, o);
             x = y < x ? y : x;
         }
-        if ((threadIdx.x & 63) == 0 && r0 >= 0 && x != 0x7fffffff) atomicMin(&minid[r0], x);
-        if (r != r0 && r >= 0) atomicMin(&minid[r], id);
+        if ((threadIdx.x & 63) == lead) atomicMin(&labels[perm[r0]], x);
+        if (r != r0 && r >= 0) atomicMin(&labels[perm[r]], id);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_cc_label(int32_t* parent, const int32_t* __restrict__ perm,
-                                                       const int32_t* __restrict__ minid, int64_t n,
+// Every non-root copies its root's label cell (final after k_cc_min: root
+// cells are only read here, non-root cells only written); roots are counted.
+__global__ __launch_bounds__(kThreads) void k_cc_label(int32_t* parent, const int32_t* __restrict__ perm, int64_t n,
                                                        int32_t* __restrict__ labels,
                                                        unsigned long long* __restrict__ ncc) {
     __shared__ unsigned long long wsum[kThreads / 64];
@@ -134,9 +111,12 @@ __global__ __launch_bounds__(kThreads) void k_cc_label(int32_t* parent, const in
         const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + rd * stride;
         bool is_root = false;
         if (v < n) {
-            const int32_t r = find_root(parent, (int32_t)v);
-            labels[perm[v]] = minid[r];
-            is_root = (r == (int32_t)v);
+            const int32_t p = uf_load(&parent[v]);
+            is_root = p == (int32_t)v;
+            if (!is_root) {
+                const int32_t r = uf_find(parent, p);
+                labels[perm[v]] = labels[perm[r]];
+            }
         }
         const uint64_t bal = __ballot(is_root);
         if (lane == 0) roots += (unsigned long long)__popcll(bal);
@@ -151,43 +131,57 @@ __global__ __launch_bounds__(kThreads) void k_cc_label(int32_t* parent, const in
     }
 }
 
+void init_components(const mcd_graph* g, int32_t* parent, int32_t* labels, int64_t* n_components,
+                     hipStream_t s) {
+    if (n_components) fill_i64(n_components, 1, 0, s);
+    if (g->n <= 0) return;
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, parent, labels, g->n);
+}
+
 void finish_components(const mcd_graph* g, int32_t* labels, int64_t* n_components, int32_t* parent,
-                       int32_t* minid, hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_min, dim3(grid_for(g->n, 8192)), dim3(kThreads), 0, s, parent, g->perm, g->n, minid);
-    hipLaunchKernelGGL(k_cc_label, dim3(grid_for(g->n, 8192)), dim3(kThreads), 0, s, parent, g->perm, minid,
-                       g->n, labels, (unsigned long long*)n_components);
+                       hipStream_t s) {
+    if (g->n <= 0) return;
+    // (the label pass ends with one atomic per block on the component count,
+    // so its grid stays small)
+    hipLaunchKernelGGL(k_cc_min, dim3(grid_for(g->n, 8192)), dim3(kThreads), 0, s, parent, g->perm, g->n, labels);
+    hipLaunchKernelGGL(k_cc_label, dim3(grid_for(g->n, 8192)), dim3(kThreads), 0, s, parent, g->perm, g->n, labels,
+                       (unsigned long long*)n_components);
 }
 
 }  // namespace
 
-size_t cc_scratch_bytes(const mcd_graph* g) { return 2 * mcd_align(sizeof(int32_t) * (size_t)g->n + 1); }
+size_t cc_scratch_bytes(const mcd_graph* g) { return mcd_align(sizeof(int32_t) * (size_t)g->n + 1); }
 
 void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels, int64_t* n_components,
                        void* ws, hipStream_t s) {
-    if (n_components) fill_i64(n_components, 1, 0, s);
-    if (g->n <= 0) return;
     int32_t* parent = (int32_t*)ws;
-    int32_t* minid = (int32_t*)((char*)ws + mcd_align(sizeof(int32_t) * (size_t)g->n + 1));
-    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, parent, minid, g->perm,
-                       g->n);
-    if (g->m > 0)
+    init_components(g, parent, labels, n_components, s);
+    if (g->n > 0 && g->m > 0)
         hipLaunchKernelGGL(k_cc_union, dim3(grid_for(g->m, 1 << 16)), dim3(kThreads), 0, s, g->src, g->adj,
                            keep_bits, g->m, parent);
-    finish_components(g, labels, n_components, parent, minid, s);
+    finish_components(g, labels, n_components, parent, s);
 }
 
 void launch_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
                             int32_t* labels, int64_t* n_components, void* ws, hipStream_t s) {
-    if (n_components) fill_i64(n_components, 1, 0, s);
-    if (g->n <= 0) return;
     int32_t* parent = (int32_t*)ws;
-    int32_t* minid = (int32_t*)((char*)ws + mcd_align(sizeof(int32_t) * (size_t)g->n + 1));
-    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, parent, minid, g->perm,
-                       g->n);
-    if (g->m > 0)
+    init_components(g, parent, labels, n_components, s);
+    if (g->n > 0 && g->m > 0)
         hipLaunchKernelGGL(k_cc_union_kept, dim3(MCD_KEPT_SEGMENTS / (kThreads / 64)), dim3(kThreads), 0, s,
                            (const int2*)kept_pairs, kept_counts, kept_segment_len(g->m), parent);
-    finish_components(g, labels, n_components, parent, minid, s);
+    finish_components(g, labels, n_components, parent, s);
+}
+
+int32_t* launch_components_init(const mcd_graph* g, int32_t* labels, int64_t* n_components, void* ws,
+                                hipStream_t s) {
+    int32_t* parent = (int32_t*)ws;
+    init_components(g, parent, labels, n_components, s);
+    return parent;
+}
+
+void launch_components_finish(const mcd_graph* g, int32_t* labels, int64_t* n_components, void* ws,
+                              hipStream_t s) {
+    finish_components(g, labels, n_components, (int32_t*)ws, s);
 }
 
 }  // namespace mcd

@@ -152,7 +152,8 @@ int64_t kept_segment_len(int64_t m);
 // when non-NULL.  Every output may be NULL.
 void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den, int G,
                         const int64_t* vbase, const int64_t* deltas, float* wf, int32_t* wi, uint32_t* keep_bits,
-                        int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s);
+                        int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s,
+                        int32_t* parent = nullptr);  // non-NULL: unite every kept edge in that union-find
 
 // ---- 4-clique participation (k4.hip) ----
 void launch_k4(const mcd_graph* g, int32_t* k4, hipStream_t s);
@@ -163,6 +164,13 @@ void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* l
                        int64_t* n_components, void* ws, hipStream_t s);
 void launch_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
                             int32_t* labels, int64_t* n_components, void* ws, hipStream_t s);
+// The two halves of a components step around unions made elsewhere: the
+// union-find in ws set to singletons (its parent array returned), then the
+// labels and the count.
+int32_t* launch_components_init(const mcd_graph* g, int32_t* labels, int64_t* n_components, void* ws,
+                                hipStream_t s);
+void launch_components_finish(const mcd_graph* g, int32_t* labels, int64_t* n_components, void* ws,
+                              hipStream_t s);
 
 // ---- percentile (select.hip) ----
 size_t select_scratch_bytes(const mcd_graph* g);

@@ -19,6 +19,7 @@
 //   A = sum over clusters of C(a, 2), B = sum over classes of C(b, 2), N = C(n, 2)
 // each gathered as sum over vertices of (cell size - 1) / 2.
 #include "common.hpp"
+#include "unionfind.hpp"
 
 namespace mcd {
 namespace {
@@ -199,24 +200,6 @@ __global__ __launch_bounds__(kThreads) void k_vertex_info(const int32_t* __restr
     }
 }
 
-__device__ __forceinline__ int32_t ld_parent(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void st_parent(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x) {
-    for (;;) {
-        const int32_t p = ld_parent(&parent[x]);
-        if (p == x) return x;
-        const int32_t gp = ld_parent(&parent[p]);
-        if (gp != p) st_parent(&parent[x], gp);
-        x = gp;
-    }
-}
-
 __global__ __launch_bounds__(kThreads) void k_init_parent(int32_t* __restrict__ parent, int64_t n) {
     GRID_STRIDE(v, n) parent[v] = (int32_t)v;
 }
@@ -228,21 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restr
                                                           int lv, int32_t* parent) {
     GRID_STRIDE(e, m) {
         if (level[e] != lv) continue;
-        int32_t a = src[e], b = adj[e];
-        for (;;) {
-            a = find_root(parent, a);
-            b = find_root(parent, b);
-            if (a == b) break;
-            if (a > b) {  // hook the lower-ranked root a under b
-                const int32_t x = a;
-                a = b;
-                b = x;
-            }
-            int32_t expected = a;
-            if (__hip_atomic_compare_exchange_strong(&parent[a], &expected, b, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
-        }
+        uf_unite(parent, src[e], adj[e]);
     }
 }
 
@@ -264,8 +233,8 @@ __global__ __launch_bounds__(kThreads) void k_pass_size(int32_t* parent, int64_t
     __syncthreads();
     const int lane = threadIdx.x & 63;
     GRID_STRIDE(v, n) {
-        const int32_t r = find_root(parent, (int32_t)v);
-        st_parent(&parent[v], r);
+        const int32_t r = uf_find(parent, (int32_t)v);
+        uf_store(&parent[v], r);
         const bool root = r == (int32_t)v;
         acc.add(gid[v], root ? 1ull : 0ull);
         // size[r] += 1, first summed over the lanes sharing lane 0's root;
@@ -296,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void k_label_init(const int32_t* __restri
 __global__ __launch_bounds__(kThreads) void k_label_min(int32_t* parent, const int32_t* __restrict__ perm, int64_t n,
                                                         int32_t* __restrict__ minid) {
     GRID_STRIDE(v, n) {
-        const int32_t r = find_root(parent, (int32_t)v);
+        const int32_t r = uf_find(parent, (int32_t)v);
         if (r != (int32_t)v) atomicMin(&minid[r], perm[v]);
     }
 }
@@ -304,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_label_min(int32_t* parent, const i
 __global__ __launch_bounds__(kThreads) void k_label_write(int32_t* parent, const int32_t* __restrict__ perm,
                                                           int64_t n, const int32_t* __restrict__ minid,
                                                           int32_t* __restrict__ labels) {
-    GRID_STRIDE(v, n) labels[perm[v]] = minid[find_root(parent, (int32_t)v)];
+    GRID_STRIDE(v, n) labels[perm[v]] = minid[uf_find(parent, (int32_t)v)];
 }
 
 __device__ __forceinline__ uint64_t cell_key(int32_t r, int32_t c) {
@@ -348,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_
     GRID_STRIDE(v, n) {
         // pass 1 compressed the paths, but a concurrent halving may have left
         // parent[v] at an ancestor below the root: always follow to the root
-        const int32_t r = find_root(parent, (int32_t)v);
+        const int32_t r = uf_find(parent, (int32_t)v);
         const uint64_t k = cell_key(r, cls[v]);
         const uint32_t mask = (1u << log2cap) - 1u;
         uint32_t h = cell_slot(k, log2cap);
@@ -379,7 +348,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_s(int32_t* parent, int64_t n,
     S.init();
     __syncthreads();
     GRID_STRIDE(v, n) {
-        const uint64_t k = cell_key(find_root(parent, (int32_t)v), cls[v]);
+        const uint64_t k = cell_key(uf_find(parent, (int32_t)v), cls[v]);
         const uint32_t mask = (1u << log2cap) - 1u;
         uint32_t h = cell_slot(k, log2cap);
         while (keys[h] != k) h = (h + 1) & mask;
@@ -499,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_volume(int32_t* parent, int64
     __syncthreads();
     const int lane = threadIdx.x & 63;
     GRID_STRIDE(v, n) {
-        const int32_t r = find_root(parent, (int32_t)v);
+        const int32_t r = uf_find(parent, (int32_t)v);
         const unsigned long long d = (unsigned long long)deg[v];
         const int32_t r0 = __shfl(r, 0);
         unsigned long long x = r == r0 ? d : 0ull;
@@ -541,7 +510,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_intra(const int32_t* __restri
     GRID_STRIDE(e, m) {
         const int32_t u = src[e];
         bool in = level[e] > lv_thresh;
-        if (!in) in = find_root(parent, u) == find_root(parent, adj[e]);
+        if (!in) in = uf_find(parent, u) == uf_find(parent, adj[e]);
         I.add(G == 1 ? 0 : gid[u], in ? 1ull : 0ull);
     }
     __syncthreads();

@@ -8,6 +8,7 @@
 // floating point: with delta = num/den (den > 0) an edge is kept iff
 // sn * den >= num * sd, in 64- or 128-bit integers.
 #include "common.hpp"
+#include "unionfind.hpp"
 
 namespace mcd {
 namespace {
@@ -35,10 +36,16 @@ __device__ __forceinline__ float ratio_f32(int32_t t, int64_t d) {
 
 constexpr int kUnroll = 8;  // 64-edge groups in flight per wave
 
+// A device threshold whose terms fit the 64-bit products of keep_test<true>.
+__device__ __forceinline__ bool small_delta(int64_t num, int64_t den) {
+    return num > -(1ll << 31) && num < (1ll << 31) && den < (1ll << 31);
+}
+
 // The exact keep test sn / sd >= num / den (sd, den > 0).  64-bit products
 // suffice when |sn| < 2^31, sd < 2^32 and |num|, den < 2^31 (NARROW, which
 // the host establishes from the maximum degree and a validated threshold);
 // otherwise 128-bit products are used.
+
 template <bool NARROW>
 __device__ __forceinline__ bool keep_test(int64_t sn, int64_t sd, int64_t num, int64_t den) {
     if (NARROW) return sn * den >= num * sd;
@@ -52,31 +59,50 @@ __device__ __forceinline__ bool keep_test(int64_t sn, int64_t sd, int64_t num, i
 // run of the kept-pair array, so the compaction needs no atomics.  The
 // degree sum deg u + deg v of every edge comes from the graph (dsum), so the
 // pass streams its inputs.
-template <int MEASURE, bool MULTI, bool NARROW>
+//
+// UNION (the fused weights + prune + components pass): every kept edge is
+// united in the union-find `parent` right there instead of being listed, and
+// the wave walks its run from the end, so that the edges among high-degree
+// vertices (the high ranks) are united first and the rest hooks straight
+// under the roots that core forms.
+//
+// Endpoints are streamed with t and dsum only where every edge needs them (a
+// graph lookup); the kept list and the queue read them for kept edges alone.
+template <int MEASURE, bool MULTI, bool NARROW, bool UNION>
 __global__ __launch_bounds__(kThreads) void k_weigh_prune(
     const int32_t* __restrict__ src, const int32_t* __restrict__ adj, const int32_t* __restrict__ dsum,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ t, int64_t m, int64_t seg_len, int G,
     const int64_t* __restrict__ vbase, const int64_t* __restrict__ deltas, int64_t num0, int64_t den0,
     float* __restrict__ wf, int32_t* __restrict__ wi, uint32_t* __restrict__ keep, int2* __restrict__ kept,
-    int32_t* __restrict__ kept_counts, unsigned long long* __restrict__ n_kept) {
+    int32_t* __restrict__ kept_counts, unsigned long long* __restrict__ n_kept, int32_t* parent) {
     __shared__ unsigned long long wsum[kThreads / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t seg = (int64_t)blockIdx.x * (kThreads / 64) + w;
     const int64_t e0 = seg * seg_len;
     const int64_t e1 = e0 + seg_len < m ? e0 + seg_len : m;
     const uint64_t below = (1ull << lane) - 1ull;
-    const bool need_uv = kept != nullptr || MULTI;
+    const bool need_uv = MULTI && G > 1;
+    // one threshold for every edge: read once (a device threshold of one
+    // graph too), not per edge
+    int64_t num1 = num0, den1 = den0;
+    if (MULTI && G == 1) {
+        num1 = deltas[0];
+        den1 = deltas[1];
+    }
+    const bool narrow1 = !MULTI || small_delta(num1, den1);
+    const int64_t ng = e1 > e0 ? (e1 - e0 + 63) >> 6 : 0;  // 64-edge groups of the run
     int64_t cnt = 0;
-    for (int64_t c = e0; c < e1; c += 64 * kUnroll) {
+    for (int64_t gi = 0; gi < ng; gi += kUnroll) {
         int32_t u[kUnroll], v[kUnroll], tt[kUnroll], dd[kUnroll];
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
-            const int64_t e = c + 64 * j + lane;
+            const int64_t gj = UNION ? ng - 1 - (gi + j) : gi + j;
+            const int64_t e = gi + j < ng ? e0 + 64 * gj + lane : e1;
             u[j] = v[j] = tt[j] = 0;
             dd[j] = 1;
             if (e < e1) {
-                tt[j] = t[e];
-                dd[j] = dsum[e];
+                tt[j] = __builtin_nontemporal_load(&t[e]);  // streamed once: no reuse to cache
+                dd[j] = __builtin_nontemporal_load(&dsum[e]);
                 if (need_uv) {
                     u[j] = src[e];
                     v[j] = adj[e];
@@ -85,8 +111,8 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
         }
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
-            const int64_t cj = c + 64 * j;
-            if (cj >= e1) break;  // wave-uniform
+            if (gi + j >= ng) break;  // wave-uniform
+            const int64_t cj = e0 + 64 * (UNION ? ng - 1 - (gi + j) : gi + j);
             const int64_t e = cj + lane;
             bool k = false;
             if (e < e1) {
@@ -95,20 +121,20 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
                 if (MEASURE == MCD_SIM_TECTONIC || MEASURE == MCD_SIM_JACCARD) {
                     sn = tt[j];
                     sd = MEASURE == MCD_SIM_TECTONIC ? D : D - tt[j];  // D - t >= t + 2 > 0
-                    if (wf) wf[e] = ratio_f32(tt[j], sd);
+                    if (wf) __builtin_nontemporal_store(ratio_f32(tt[j], sd), &wf[e]);
                 } else {
                     sn = MEASURE == MCD_SIM_TW ? 3 * (int64_t)tt[j] - D + 2 : (int64_t)tt[j];
                     sd = 1;
-                    if (wi) wi[e] = (int32_t)sn;
-                    if (wf) wf[e] = (float)sn;
+                    if (wi) __builtin_nontemporal_store((int32_t)sn, &wi[e]);
+                    if (wf) __builtin_nontemporal_store((float)sn, &wf[e]);
                 }
-                if (MULTI) {
-                    const int g = G == 1 ? 0 : graph_of(vbase, G, perm[u[j]]);
+                if (MULTI && G > 1) {
+                    const int g = graph_of(vbase, G, perm[u[j]]);
                     const int64_t num = deltas[2 * g], den = deltas[2 * g + 1];
-                    const bool small = num > -(1ll << 31) && num < (1ll << 31) && den < (1ll << 31);
-                    k = small ? keep_test<NARROW>(sn, sd, num, den) : keep_test<false>(sn, sd, num, den);
+                    k = small_delta(num, den) ? keep_test<NARROW>(sn, sd, num, den)
+                                              : keep_test<false>(sn, sd, num, den);
                 } else {
-                    k = keep_test<NARROW>(sn, sd, num0, den0);
+                    k = narrow1 ? keep_test<NARROW>(sn, sd, num1, den1) : keep_test<false>(sn, sd, num1, den1);
                 }
             }
             const uint64_t bal = __ballot(k);
@@ -116,7 +142,12 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
                 if (lane == 0) keep[cj >> 5] = (uint32_t)bal;
                 else if (lane == 1 && cj + 32 < m) keep[(cj >> 5) + 1] = (uint32_t)(bal >> 32);
             }
+            if ((kept || UNION) && k && !need_uv) {
+                u[j] = src[e];
+                v[j] = adj[e];
+            }
             if (kept && k) kept[e0 + cnt + __popcll(bal & below)] = make_int2(u[j], v[j]);
+            if (UNION && k) uf_unite(parent, u[j], v[j]);
             cnt += __popcll(bal);
         }
     }
@@ -140,7 +171,7 @@ int64_t kept_segment_len(int64_t m) {
 
 void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64_t num, int64_t den, int G,
                         const int64_t* vbase, const int64_t* deltas, float* wf, int32_t* wi, uint32_t* keep_bits,
-                        int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s) {
+                        int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s, int32_t* parent) {
     if (n_kept) fill_i64(n_kept, 1, 0, s);
     if (g->m <= 0 && !kept_counts) return;
     const int64_t L = kept_segment_len(g->m);
@@ -153,11 +184,16 @@ void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64
     unsigned long long* nk = (unsigned long long*)n_kept;
 #define MCD_WP_ARGS                                                                                          \
     g->src, g->adj, g->dsum, g->perm, t, g->m, L, G, vbase, deltas, num, den, wf, wi, keep_bits, kp, kept_counts, \
-        nk
-#define MCD_WP_LAUNCH(MEAS, MULTI)                                                                             \
-    do {                                                                                                   \
-        if (narrow) hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, true>), grid, block, 0, s, MCD_WP_ARGS);  \
-        else hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, false>), grid, block, 0, s, MCD_WP_ARGS);       \
+        nk, parent
+#define MCD_WP_LAUNCH_U(MEAS, MULTI, UNION)                                                                      \
+    do {                                                                                                     \
+        if (narrow) hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, true, UNION>), grid, block, 0, s, MCD_WP_ARGS); \
+        else hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, false, UNION>), grid, block, 0, s, MCD_WP_ARGS);      \
+    } while (0)
+#define MCD_WP_LAUNCH(MEAS, MULTI)                            \
+    do {                                                  \
+        if (parent) MCD_WP_LAUNCH_U(MEAS, MULTI, true);   \
+        else MCD_WP_LAUNCH_U(MEAS, MULTI, false);         \
     } while (0)
     switch (measure) {
         case MCD_SIM_TECTONIC:
@@ -179,6 +215,7 @@ void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64
             break;
     }
 #undef MCD_WP_LAUNCH
+#undef MCD_WP_LAUNCH_U
 #undef MCD_WP_ARGS
 }
 

@@ -98,6 +98,7 @@ def lib():
             "mcd_components_kept": [P, P, P, P, P, P, SZ],
             "mcd_tune_triangles_workspace_size": [P, ctypes.POINTER(SZ)],
             "mcd_k4": [P, P],
+            "mcd_prune_components": [P, ctypes.c_int, P, mcd_rational, I32, P, P, P, P, P, P, P, P, P, SZ],
             "mcd_tune_triangles": [P, P, P, SZ, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float)],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
@@ -573,6 +574,35 @@ def mcd_weigh_prune(g: Graph, measure: int, t, delta=None, deltas=None, vbase=No
                                  None if kept is None else _p(kept.counts), _p(n_kept)))
     return dict(w_f32=None if w_f32 is None else w_f32[:g.m], w_i32=None if w_i32 is None else w_i32[:g.m],
                 keep_bits=keep_bits, kept=kept, n_kept=n_kept)
+
+
+def mcd_prune_components(g: Graph, measure: int, t, delta=None, deltas=None, vbase=None, w_f32=None, w_i32=None,
+                         keep_bits=None, n_kept=None, labels=None, n_components=None, ws=None, want_f32=True,
+                         want_i32=False, want_keep=True):
+    """Weights, prune and components in one pass (no kept list).  delta / deltas
+    as mcd_weigh_prune; returns a dict of the outputs."""
+    dev = g.ctx.device
+    if w_f32 is None and want_f32:
+        w_f32 = _empty(max(g.m, 1), torch.float32, dev)
+    if w_i32 is None and want_i32:
+        w_i32 = _empty(max(g.m, 1), torch.int32, dev)
+    if keep_bits is None and want_keep:
+        keep_bits = _empty(max((g.m + 31) // 32, 1), torch.int32, dev)
+    n_kept = _empty(1, torch.int64, dev) if n_kept is None else n_kept
+    labels = _empty(max(g.n, 1), torch.int32, dev) if labels is None else labels
+    n_components = _empty(1, torch.int64, dev) if n_components is None else n_components
+    if ws is None:
+        ws = _bytes(mcd_components_workspace_size(g), dev)
+    if deltas is not None:
+        vb = _vbase(g, vbase)
+        G, vbp, rat = vb.numel() - 1, _p(vb), mcd_rational(0, 1)
+    else:
+        G, vbp, rat = 1, None, _rat(delta)
+    _check(lib().mcd_prune_components(g.handle, measure, _p(t), rat, G, vbp, _p(deltas), _p(w_f32), _p(w_i32),
+                                      _p(keep_bits), _p(n_kept), _p(labels), _p(n_components), _p(ws),
+                                      ws.numel() * ws.element_size()))
+    return dict(w_f32=None if w_f32 is None else w_f32[:g.m], w_i32=None if w_i32 is None else w_i32[:g.m],
+                keep_bits=keep_bits, n_kept=n_kept, labels=labels[:g.n], n_components=n_components)
 
 
 def mcd_components_kept(g: Graph, kept: KeptList, labels=None, n_components=None, ws=None):

@@ -2,8 +2,9 @@
 
 Runs, on R-MAT of the given scale: one calibration kernel of known traffic
 (an elementwise int32 add over `--copy-mib` MiB: that many bytes read and
-written), the graph build, the triangle count, the one-pass weights + prune at
-num/den (default 9/900), components over the kept list and the 16-point sweep, each once, and prints what it launched.  Used as
+written), the graph build, the triangle count, the one-pass weights + prune +
+components at num/den (default 9/900) and the 16-point sweep, each once, and
+prints what it launched.  Used as
     rocprofv3 --kernel-trace --stats -- python3 -m paper_2412_12382_amd.profile_run
     rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2412_12382_amd.profile_run
     rocprofv3 --pmc WRITE_SIZE -- python3 -m paper_2412_12382_amd.profile_run
@@ -44,9 +45,8 @@ def main():
     ctx = M.mcd_ctx_create(0)
     g = M.mcd_graph_build(ctx, src, dst, n)
     t = M.mcd_triangles(g)
-    r = M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, t, delta=(args.num, args.den))
-    lab, ncc = M.mcd_components_kept(g, r["kept"])
-    nk = r["n_kept"]
+    r = M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, delta=(args.num, args.den))
+    ncc, nk = r["n_components"], r["n_kept"]
     M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, [(k, 50) for k in range(16)])
     torch.cuda.synchronize()
     print(json.dumps(dict(scale=args.scale, n=n, m=g.m, kept=int(nk.item()), components=int(ncc.item()))),

@@ -53,6 +53,7 @@ def gpu_all(src, dst, n, measure, delta):
     labels_run, ncc_run = M.mcd_run(g, measure, delta)
     fused = M.mcd_weigh_prune(g, measure, t, delta=delta, want_i32=ints)
     labels_k, ncc_k = M.mcd_components_kept(g, fused["kept"])
+    pc = M.mcd_prune_components(g, measure, t, delta=delta, want_i32=ints)
     torch.cuda.synchronize()
     out = dict(g=g, lo=lo, hi=hi, deg=deg[:n], t=t.cpu().numpy()[order],
                w=wf.cpu().numpy()[order] if g.m else np.zeros(0, np.float32),
@@ -77,4 +78,10 @@ def gpu_all(src, dst, n, measure, delta):
         want_u=u[fused["kept"].edge_ids(g.m)][keep_lib[fused["kept"].edge_ids(g.m)]],
         want_v=v[fused["kept"].edge_ids(g.m)][keep_lib[fused["kept"].edge_ids(g.m)]],
         labels=labels_k.cpu().numpy(), ncc=int(ncc_k.item()))
+    # weights + prune + components in one pass
+    out["pc"] = dict(
+        w=pc["w_f32"].cpu().numpy()[order] if g.m else np.zeros(0, np.float32),
+        tw=None if pc["w_i32"] is None else pc["w_i32"].cpu().numpy()[order],
+        keep=unpack_bits(pc["keep_bits"], g.m)[order], n_kept=int(pc["n_kept"].item()),
+        labels=pc["labels"].cpu().numpy(), ncc=int(pc["n_components"].item()))
     return out

@@ -55,6 +55,9 @@ def test_c2_rmat_s20_percentile_both_measures():
         lab, ncc = M.mcd_components_kept(g, r["kept"])
         lab_o, ncc_o = oracle.components(n, lo_o, hi_o, keep_o)
         assert np.array_equal(lab.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o
+        pc = M.mcd_prune_components(g, measure, t, delta=(num, den), want_f32=False)
+        assert np.array_equal(unpack_bits(pc["keep_bits"], g.m)[order], keep_o)
+        assert np.array_equal(pc["labels"].cpu().numpy(), lab_o) and int(pc["n_components"].item()) == ncc_o
 
 
 def test_c3_dcsbm_sweep_64_with_ari():
@@ -112,6 +115,11 @@ def test_c5_rmat_s26_sampled_edges_and_label_properties():
     delta = (9, 900)
     r = M.mcd_weigh_prune(g, M.MCD_SIM_TECTONIC, t, delta=delta)
     lab, ncc = M.mcd_components_kept(g, r["kept"])
+    # the one-pass weights + prune + components gives the same labelling
+    pc = M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, delta=delta, want_f32=False)
+    assert bool(torch.equal(pc["labels"], lab)) and int(pc["n_components"].item()) == int(ncc.item())
+    assert bool(torch.equal(pc["keep_bits"][:(m + 31) // 32], r["keep_bits"][:(m + 31) // 32]))
+    del pc
     stats, _, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, [(k, 50) for k in range(16)])
     u, v = M.mcd_graph_edges(g)
     deg = M.mcd_graph_degrees(g)

@@ -52,6 +52,12 @@ def check_all(src, dst, n, measure, delta):
     assert np.array_equal(f["keep"], keep) and f["n_kept"] == int(keep.sum())
     assert np.array_equal(f["kept_u"], f["want_u"]) and np.array_equal(f["kept_v"], f["want_v"])
     assert np.array_equal(f["labels"], labels) and f["ncc"] == ncc
+    p = r["pc"]  # weights + prune + components in one pass
+    assert np.array_equal(p["w"].view(np.int32), r["w"].view(np.int32))
+    if measure in (oracle.TW, oracle.K3):
+        assert np.array_equal(p["tw"], r["tw"])
+    assert np.array_equal(p["keep"], keep) and p["n_kept"] == int(keep.sum())
+    assert np.array_equal(p["labels"], labels) and p["ncc"] == ncc
     return r
 
 
@@ -280,3 +286,27 @@ def test_k4_participation_and_prune(case):
     lab, ncc = M.mcd_components(g, keep)
     lab_o, ncc_o = oracle.components(n, lo, hi, keep_o)
     assert np.array_equal(lab.cpu().numpy(), lab_o) and int(ncc.item()) == ncc_o
+    pc = M.mcd_prune_components(g, M.MCD_SIM_K4, k4, delta=thr, want_i32=True)
+    assert np.array_equal(pc["w_i32"].cpu().numpy()[order], want)
+    assert np.array_equal(unpack_bits(pc["keep_bits"], g.m)[order], keep_o)
+    assert np.array_equal(pc["labels"].cpu().numpy(), lab_o) and int(pc["n_components"].item()) == ncc_o
+
+
+def test_device_threshold_one_graph_any_width():
+    # a device threshold for a single graph, with terms that need the 128-bit
+    # comparison and with small ones, decides exactly as the host threshold
+    from gpu_util import build
+    s, d, n = gg.rmat(14, seed=78)
+    g = build(s, d, n)
+    t = M.mcd_triangles(g)
+    words = (g.m + 31) // 32
+    for measure, (p, q) in ((M.MCD_SIM_TECTONIC, (3, 50)), (M.MCD_SIM_TW, (-7, 1)), (M.MCD_SIM_JACCARD, (1, 9))):
+        want = M.mcd_weigh_prune(g, measure, t, delta=(p, q), want_kept=False)
+        wk = want["keep_bits"][:words]
+        for scale in (1, 1 << 40):
+            dev = torch.tensor([[p * scale, q * scale]], dtype=torch.int64, device="cuda")
+            got = M.mcd_weigh_prune(g, measure, t, deltas=dev, want_kept=False)
+            assert torch.equal(got["keep_bits"][:words], wk), (measure, scale)
+            assert int(got["n_kept"].item()) == int(want["n_kept"].item())
+            pc = M.mcd_prune_components(g, measure, t, deltas=dev)
+            assert torch.equal(pc["keep_bits"][:words], wk), (measure, scale)

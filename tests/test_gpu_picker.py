@@ -129,6 +129,11 @@ def test_select_targets_and_per_graph_prune():
     assert int(f["kept"].counts.sum().item()) == int(want.sum())
     lab2, ncc2 = M.mcd_components_kept(g, f["kept"])
     assert np.array_equal(lab2.cpu().numpy(), lab_o) and int(ncc2.item()) == ncc_o
+    # and weights + prune + components in one pass
+    pc = M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, deltas=cuda(deltas), vbase=cuda(vbase))
+    assert np.array_equal(unpack_bits(pc["keep_bits"], g.m)[order], want)
+    assert int(pc["n_kept"].item()) == int(want.sum())
+    assert np.array_equal(pc["labels"].cpu().numpy(), lab_o) and int(pc["n_components"].item()) == ncc_o
 
 
 def test_picker_end_to_end_small_batch():
