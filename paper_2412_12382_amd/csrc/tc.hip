@@ -270,16 +270,62 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
     }
 }
 
-// Rank-window items, one item per workgroup of NT threads.  The wave is split
-// into 64/G lane groups, each walking its own in-edges G suffix elements per
-// step, and every group keeps the descriptor and first chunk of its next
-// in-edge loaded ahead.  Group state lives in vector registers; the loop runs
-// while any group has work.  Wide windows take large workgroups so that the
-// LDS they need still leaves room for enough waves per CU.  (Measured on
-// R-MAT: G = 64 is fastest; smaller groups put more rows in flight but cost
-// more per element.)
-template <int LOG2R, int NT, int G>
-__global__ __launch_bounds__(NT) void k_tc_window_g(const Item* __restrict__ all_items,
+// The chunks a wave streams for the rank-window kernel: `left` more in-edge
+// descriptors at dp, dp + stride, ... of its item, and for the current one
+// the suffix [pos, a1) of row u after v in 64-element chunks.  Descriptors
+// are fetched 64 at a time, one per lane (bx, by), and read out lane by lane
+// into scalar registers; every other field is wave-uniform.
+struct ChunkGen {
+    const int2* __restrict__ dp;
+    int32_t left, stride, e, pos, a1, bi;
+    int32_t bx, by;  // per lane: a batch of descriptors
+    bool done;
+    // move to the next non-empty chunk
+    __device__ __forceinline__ void next(int lane) {
+        pos += 64;
+        while (pos >= a1) {
+            if (left == 0) {
+                done = true;
+                return;
+            }
+            if (bi == 64) {
+                const int2 d = lane < left ? dp[lane * stride] : make_int2(0, 0);
+                bx = d.x;
+                by = d.y;
+                dp += 64 * stride;
+                bi = 0;
+            }
+            e = __builtin_amdgcn_readlane(bx, bi);
+            const int32_t len = __builtin_amdgcn_readlane(by, bi);
+            ++bi;
+            --left;
+            pos = e + 1;
+            a1 = e + 1 + len;
+        }
+    }
+};
+
+// The generator's current chunk as one element per lane (lanes past its end
+// repeat its last element).  Issued unconditionally, from a valid address
+// when the generator is done too (the kernel runs only on graphs with edges),
+// so that every slot of the ring below issues exactly one load and the wait
+// for a slot's data counts the loads issued after it.
+__device__ __forceinline__ int32_t load_chunk(const int32_t* __restrict__ adj, const ChunkGen& g, int lane) {
+    const int32_t nv = g.done ? 1 : g.a1 - g.pos;
+    const int32_t* row = adj + (g.done ? 0 : g.pos);
+    return row[(uint32_t)(lane < nv ? lane : nv - 1)];
+}
+
+// Rank-window items, one item per workgroup of NT threads.  Each wave walks
+// its own in-edges of the item, one at a time, all 64 lanes on 64-element
+// chunks of the in-edge's suffix.  The walk (in-edge, chunk, loop control)
+// is wave-uniform, so it runs on the scalar unit and the vector work per
+// element is the probe alone; loads run D chunks ahead of their use in a
+// ring of registers.  t(v,w) partial counts are 32-bit LDS counters, one per
+// element of N+(v).  Wide windows take large workgroups so that the LDS they
+// need still leaves room for enough waves per CU.
+template <int LOG2R, int NT, int D>
+__global__ __launch_bounds__(NT) void k_tc_window_s(const Item* __restrict__ all_items,
                                                     const int64_t* __restrict__ heads, int cls,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ adj,
@@ -288,14 +334,12 @@ __global__ __launch_bounds__(NT) void k_tc_window_g(const Item* __restrict__ all
     constexpr int NW = (1 << LOG2R) / 32;
     constexpr int MAXB = 4096;
     constexpr int NWAVES = NT / 64;
-    constexpr int NG = 64 / G;
     __shared__ uint32_t bm[NW];
     __shared__ uint16_t pre[NW];
     __shared__ uint32_t part[NWAVES];
-    __shared__ uint32_t cnt[MAXB / 2];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int gl = lane % G, gi = lane / G;
-    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (gi * G));
+    __shared__ uint32_t cnt[MAXB];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const Item* __restrict__ items = all_items + heads[2 * cls];
     const int64_t n_items = heads[2 * cls + 1];
 
@@ -305,7 +349,7 @@ __global__ __launch_bounds__(NT) void k_tc_window_g(const Item* __restrict__ all
         const int32_t b0 = (int32_t)off[v];
         const int32_t B = (int32_t)(off[v + 1] - b0);
         for (int i = tid; i < NW; i += NT) bm[i] = 0;
-        for (int i = tid; i < MAXB / 2; i += NT) cnt[i] = 0;
+        for (int i = tid; i < B; i += NT) cnt[i] = 0;
         __syncthreads();
         for (int j = tid; j < B; j += NT) {
             const uint32_t r = (uint32_t)(adj[b0 + j] - v - 1);
@@ -335,60 +379,59 @@ __global__ __launch_bounds__(NT) void k_tc_window_g(const Item* __restrict__ all
         }
         __syncthreads();
 
-        const int32_t kend = (int32_t)I.s + I.len;
-        constexpr int32_t kstride = NWAVES * NG;
-        int32_t k = (int32_t)I.s + wave * NG + gi;
-        // current in-edge of the group
-        bool live = k < kend;
-        int2 d = live ? in_ea[k] : make_int2(0, 0);
-        int32_t e = d.x, cb = d.x + 1, a1 = d.x + 1 + d.y;
-        int32_t w = (live && gl < d.y) ? adj[cb + gl] : INT32_MAX;
-        // next in-edge, loaded ahead
-        int32_t kn = k + kstride;
-        int2 dn = kn < kend ? in_ea[kn] : make_int2(0, 0);
-        int32_t wfirst = (kn < kend && gl < dn.y) ? adj[dn.x + 1 + gl] : INT32_MAX;
-        uint32_t c = 0;
-        while (__ballot(live) != 0) {
-            const int32_t i = cb + gl;
-            const int32_t nxt = i + G;
-            const int32_t wn = (live && nxt < a1) ? adj[nxt] : INT32_MAX;
-            const bool cand = live && i < a1 && w <= maxv;
-            bool hit = false;
-            if (cand) {
-                const uint32_t r = (uint32_t)(w - v - 1);
-                const uint32_t word = bm[r >> 5];
-                const uint32_t bit = 1u << (r & 31);
-                if (word & bit) {
-                    const uint32_t p = (uint32_t)pre[r >> 5] + __popc(word & (bit - 1u));
-                    hit = true;
-                    atomicAdd(&cnt[p >> 1], 1u << ((p & 1u) * 16u));
-                    add_relaxed(&t[i], 1);
+        const uint32_t rmax = (uint32_t)(maxv - v - 1);  // ranks v+1 .. maxv are in the window
+        ChunkGen gen{in_ea + I.s + wave, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES, 0, -64, 0,
+                     64, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
+        gen.next(lane);
+        int32_t w[D], spos[D], sa1[D], se[D];
+        bool sv[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            sv[q] = !gen.done;
+            spos[q] = gen.pos;
+            sa1[q] = gen.a1;
+            se[q] = gen.e;
+            w[q] = load_chunk(adj, gen, lane);
+            if (sv[q]) gen.next(lane);
+        }
+        uint32_t c = 0;  // hits of the current in-edge (wave-uniform)
+        bool more = sv[0];
+        while (more) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                if (!sv[q]) {  // this and every later slot are empty
+                    more = false;
+                    break;
                 }
-            }
-            c += (uint32_t)__popcll(__ballot(hit) & gmask);
-            const bool any = (__ballot(cand) & gmask) != 0;
-            if (live) {
-                if (any && cb + G < a1) {  // more of this suffix
-                    cb += G;
-                    w = wn;
-                } else {  // in-edge done: credit t(u,v), move to the prefetched next one
-                    if (gl == 0 && c) add_relaxed(&t[e], (int32_t)c);
+                const int32_t pos = spos[q], nv = sa1[q] - pos;
+                const uint32_t r = (uint32_t)(w[q] - v - 1);
+                bool hit = false;
+                if (lane < nv && r <= rmax) {
+                    const uint32_t word = bm[r >> 5];
+                    const uint32_t bit = 1u << (r & 31);
+                    if (word & bit) {
+                        hit = true;
+                        atomicAdd(&cnt[(uint32_t)pre[r >> 5] + __popc(word & (bit - 1u))], 1u);
+                        add_relaxed(&(t + pos)[(uint32_t)lane], 1);  // t(u,w)
+                    }
+                }
+                c += (uint32_t)__popcll(__ballot(hit));
+                if (pos + 64 >= sa1[q]) {  // last chunk of the in-edge: t(u,v)
+                    if (lane == 0 && c) add_relaxed(&t[se[q]], (int32_t)c);
                     c = 0;
-                    k = kn;
-                    live = k < kend;
-                    e = dn.x;
-                    cb = dn.x + 1;
-                    a1 = dn.x + 1 + dn.y;
-                    w = wfirst;
-                    kn = k + kstride;
-                    dn = kn < kend ? in_ea[kn] : make_int2(0, 0);
-                    wfirst = (kn < kend && gl < dn.y) ? adj[dn.x + 1 + gl] : INT32_MAX;
                 }
+                // refill the slot with the chunk D ahead
+                sv[q] = !gen.done;
+                spos[q] = gen.pos;
+                sa1[q] = gen.a1;
+                se[q] = gen.e;
+                w[q] = load_chunk(adj, gen, lane);
+                if (sv[q]) gen.next(lane);
             }
         }
         __syncthreads();
         for (int j = tid; j < B; j += NT) {
-            const uint32_t x = (cnt[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+            const uint32_t x = cnt[j];
             if (x) add_relaxed(&t[b0 + j], (int32_t)x);
         }
         __syncthreads();
@@ -568,11 +611,11 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
                        L.items, L.heads, c, g->off, g->adj, g->in_ea, t);
 }
 
-template <int LOG2R, int NT, int G>
-void launch_window_g(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
+template <int LOG2R, int NT, int D>
+void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = cap_items < 16384 ? cap_items : 16384;
-    hipLaunchKernelGGL((k_tc_window_g<LOG2R, NT, G>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads, c,
+    hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads, c,
                        g->off, g->adj, g->in_ea, t);
 }
 
@@ -602,9 +645,9 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
-    launch_window_g<14, 512, 64>(g, L, 8, chunk, t, s);
-    launch_window_g<16, 1024, 64>(g, L, 9, chunk, t, s);
-    launch_window_g<18, 1024, 64>(g, L, 10, chunk, t, s);
+    launch_window<14, 512, 8>(g, L, 8, chunk, t, s);
+    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s);
+    launch_window<18, 1024, 8>(g, L, 10, chunk, t, s);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
 }

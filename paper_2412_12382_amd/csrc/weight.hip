@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
                 v[j] = adj[e];
             }
             if (kept && k) kept[e0 + cnt + __popcll(bal & below)] = make_int2(u[j], v[j]);
-            if (UNION && k) uf_unite(parent, u[j], v[j]);
+            if (UNION && k) uf_unite_meet(parent, u[j], v[j]);
             cnt += __popcll(bal);
         }
     }
