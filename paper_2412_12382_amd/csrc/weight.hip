@@ -60,11 +60,13 @@ __device__ __forceinline__ bool keep_test(int64_t sn, int64_t sd, int64_t num, i
 // degree sum deg u + deg v of every edge comes from the graph (dsum), so the
 // pass streams its inputs.
 //
-// UNION (the fused weights + prune + components pass): every kept edge is
-// united in the union-find `parent` right there instead of being listed, and
-// the wave walks its run from the end, so that the edges among high-degree
-// vertices (the high ranks) are united first and the rest hooks straight
-// under the roots that core forms.
+// UNION (the fused weights + prune + components pass): instead of being
+// listed, kept edges are united in the union-find `parent`: the kept edge ids
+// of the wave's 8 groups in flight are compacted in LDS, then all lanes fetch
+// their endpoints and unite them, 64 edges per round, so a round never runs
+// with a few lanes.  The wave walks its run from the end, so that the edges
+// among high-degree vertices (the high ranks) are united first and the rest
+// hooks straight under the roots that core forms.
 //
 // Endpoints are streamed with t and dsum only where every edge needs them (a
 // graph lookup); the kept list and the queue read them for kept edges alone.
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
     float* __restrict__ wf, int32_t* __restrict__ wi, uint32_t* __restrict__ keep, int2* __restrict__ kept,
     int32_t* __restrict__ kept_counts, unsigned long long* __restrict__ n_kept, int32_t* parent) {
     __shared__ unsigned long long wsum[kThreads / 64];
+    __shared__ int32_t queue[UNION ? kThreads / 64 : 1][UNION ? 64 * kUnroll : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t seg = (int64_t)blockIdx.x * (kThreads / 64) + w;
     const int64_t e0 = seg * seg_len;
@@ -94,6 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
     int64_t cnt = 0;
     for (int64_t gi = 0; gi < ng; gi += kUnroll) {
         int32_t u[kUnroll], v[kUnroll], tt[kUnroll], dd[kUnroll];
+        int nq = 0;  // kept edges of this iteration queued for union (wave-uniform)
 #pragma unroll
         for (int j = 0; j < kUnroll; ++j) {
             const int64_t gj = UNION ? ng - 1 - (gi + j) : gi + j;
@@ -142,13 +146,31 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
                 if (lane == 0) keep[cj >> 5] = (uint32_t)bal;
                 else if (lane == 1 && cj + 32 < m) keep[(cj >> 5) + 1] = (uint32_t)(bal >> 32);
             }
-            if ((kept || UNION) && k && !need_uv) {
-                u[j] = src[e];
-                v[j] = adj[e];
+            if (kept && k) {
+                if (!need_uv) {
+                    u[j] = src[e];
+                    v[j] = adj[e];
+                }
+                kept[e0 + cnt + __popcll(bal & below)] = make_int2(u[j], v[j]);
             }
-            if (kept && k) kept[e0 + cnt + __popcll(bal & below)] = make_int2(u[j], v[j]);
-            if (UNION && k) uf_unite_meet(parent, u[j], v[j]);
+            if (UNION && k) queue[w][nq + __popcll(bal & below)] = (int32_t)e;  // e < m < 2^31
+            nq += __popcll(bal);
             cnt += __popcll(bal);
+        }
+        if (UNION && nq > 0) {  // wave-uniform
+            // the queue was written by other lanes of this wave: order the
+            // LDS writes before the reads (one wave: no barrier needed)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int r = lane; r < nq; r += 64) {
+                const int32_t e = queue[w][r];
+                uf_unite_meet(parent, src[e], adj[e]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // reads done before the next writes
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            nq = 0;
         }
     }
     if (kept_counts && lane == 0) kept_counts[seg] = (int32_t)cnt;
