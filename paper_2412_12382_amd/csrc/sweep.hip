@@ -119,6 +119,8 @@ __device__ __forceinline__ bool root_table_add(int32_t* key, uint32_t* val, int3
     return false;
 }
 
+constexpr int kLevelBins = 8192;  // largest (graph, level) histogram kept in LDS
+
 // level[e] = number of sorted thresholds delta_i with NOT (sim(e) < delta_i)
 // and hist[g][level] (edge counts): with one graph the lanes of a wave that
 // share a level are counted with one ballot, else an LDS histogram of
@@ -138,9 +140,9 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
                                                     SweepDeltas ds, uint8_t* __restrict__ level,
                                                     const int32_t* __restrict__ gid, int G,
                                                     unsigned long long* __restrict__ hist) {
-    __shared__ uint32_t h[8192];
+    extern __shared__ uint32_t h[];  // nbins counters when local (sized at launch)
     const int nbins = G * (ds.K + 1);
-    const bool local = nbins <= 8192;
+    const bool local = nbins <= kLevelBins;
     const int lane = threadIdx.x & 63;
     if (local)
         for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
@@ -204,14 +206,39 @@ __global__ __launch_bounds__(kThreads) void k_init_parent(int32_t* __restrict__ 
     GRID_STRIDE(v, n) parent[v] = (int32_t)v;
 }
 
-// unite the endpoints of every edge at level lv
+// unite the endpoints of every edge at level lv.  Every level scans all m
+// level bytes, most of them for a handful of edges, so the bytes are read 16
+// at a time and a group without a match is passed over with one test.
+__device__ __forceinline__ bool has_byte(uint32_t x, uint32_t pat) {
+    const uint32_t v = x ^ pat;  // a zero byte where x matches
+    return ((v - 0x01010101u) & ~v & 0x80808080u) != 0u;
+}
+
 __global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restrict__ src,
                                                           const int32_t* __restrict__ adj,
                                                           const uint8_t* __restrict__ level, int64_t m,
                                                           int lv, int32_t* parent) {
-    GRID_STRIDE(e, m) {
-        if (level[e] != lv) continue;
-        uf_unite(parent, src[e], adj[e]);
+    const int64_t head = min(m, (int64_t)((16u - ((uint32_t)(uintptr_t)level & 15u)) & 15u));
+    const int64_t nq = (m - head) >> 4;
+    const int64_t tail0 = head + 16 * nq;
+    const uint32_t pat = 0x01010101u * (uint32_t)lv;
+    GRID_STRIDE(q, nq) {
+        const int64_t e0 = head + 16 * q;
+        const uint4 x = *(const uint4*)(level + e0);
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (!has_byte(w[i], pat)) continue;
+            for (int b = 0; b < 4; ++b)
+                if (((w[i] >> (8 * b)) & 0xffu) == (uint32_t)lv) {
+                    const int64_t e = e0 + 4 * i + b;
+                    uf_unite(parent, src[e], adj[e]);
+                }
+        }
+    }
+    GRID_STRIDE(i, head + (m - tail0)) {  // unaligned head and tail bytes
+        const int64_t e = i < head ? i : tail0 + (i - head);
+        if (level[e] == lv) uf_unite(parent, src[e], adj[e]);
     }
 }
 
@@ -732,11 +759,15 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
                            truth, L.gid, L.cls);
     if (m > 0) {
         // thresholds reach the kernel validated to |num|, den < 2^31
+        // LDS for the histogram only as large as it is (a few bins for one
+        // graph), so that it does not limit the waves per CU
+        const int nbins = G * (K + 1);
+        const unsigned lds = nbins <= kLevelBins ? (unsigned)nbins * 4u : 0u;
         if (g->max_deg < (1 << 29))
-            hipLaunchKernelGGL(k_level<true>, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->dsum, t, m,
+            hipLaunchKernelGGL(k_level<true>, dim3(grid_for(m, 8192)), dim3(kThreads), lds, s, g->src, g->dsum, t, m,
                                measure, ds, L.level, L.gid, G, L.hist);
         else
-            hipLaunchKernelGGL(k_level<false>, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->dsum, t,
+            hipLaunchKernelGGL(k_level<false>, dim3(grid_for(m, 8192)), dim3(kThreads), lds, s, g->src, g->dsum, t,
                                m, measure, ds, L.level, L.gid, G, L.hist);
     }
     if (truth && n > 0) {
