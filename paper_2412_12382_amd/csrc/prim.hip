@@ -26,24 +26,40 @@ inline int grid_blocks(int64_t tiles) {
 __device__ __forceinline__ uint64_t lane_lt_mask() { return __lanemask_lt(); }
 
 // Digit histogram of block b's key range, stored digit-major: counts[d*NB + b].
+// Keys are read 16 bytes per lane when the key array is 16-byte aligned (the
+// block range starts on a tile); each wave keeps 4 sub-histograms, picked
+// by lane, so that lanes with the same digit (skewed keys: hub vertices)
+// collide 4 times less on one LDS address.
 template <class K>
 __global__ __launch_bounds__(kThreads) void k_rs_hist(const K* __restrict__ keys, int64_t N,
                                                       int shift, int64_t tpb, int NB,
                                                       int64_t* __restrict__ counts) {
-    __shared__ uint32_t h[kWaves][256];
-    const int tid = threadIdx.x, w = tid >> 6;
-    for (int i = tid; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
+    constexpr int kSub = 4;
+    constexpr int kPer = 16 / (int)sizeof(K);  // keys per 16-byte load
+    __shared__ uint32_t h[kWaves * kSub][256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    uint32_t* hh = h[w * kSub + (lane & (kSub - 1))];
+    for (int i = tid; i < kWaves * kSub * 256; i += kThreads) (&h[0][0])[i] = 0;
     __syncthreads();
     const int64_t beg = (int64_t)blockIdx.x * tpb * kTile;
     const int64_t end = min(N, beg + tpb * (int64_t)kTile);
-    for (int64_t i = beg + tid; i < end; i += kThreads) {
-        uint32_t d = (uint32_t)(keys[i] >> shift) & 255u;
-        atomicAdd(&h[w][d], 1u);
+    const int64_t nvec = ((uintptr_t)keys & 15u) == 0u ? (end - beg) / kPer : 0;
+    const uint4* __restrict__ v4 = (const uint4*)(keys + beg);
+    for (int64_t i = tid; i < nvec; i += kThreads) {
+        union {
+            uint4 v;
+            K k[kPer];
+        } u;
+        u.v = v4[i];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) atomicAdd(&hh[(uint32_t)(u.k[j] >> shift) & 255u], 1u);
     }
+    for (int64_t i = beg + nvec * kPer + tid; i < end; i += kThreads)
+        atomicAdd(&hh[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     __syncthreads();
     uint32_t s = 0;
 #pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) s += h[ww][tid];
+    for (int ww = 0; ww < kWaves * kSub; ++ww) s += h[ww][tid];
     counts[(int64_t)tid * NB + blockIdx.x] = s;
 }
 
@@ -154,17 +170,27 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ i
     const int64_t t0 = (int64_t)blockIdx.x * tpb;
     const int64_t t1 = min(ntiles, t0 + tpb);
     const uint64_t lt = lane_lt_mask();
+    // keys of the next tile are loaded while the current one is written out
+    K key[kIters];
+    auto load_tile = [&](int64_t tile) {
+        const int64_t base = tile * kTile + (int64_t)w * (kTile / kWaves);
+#pragma unroll
+        for (int it = 0; it < kIters; ++it) {
+            const int64_t i = base + it * 64 + lane;
+            key[it] = (tile < t1 && i < N) ? in[i] : (K)0;
+        }
+    };
+    load_tile(t0);
     __syncthreads();
     for (int64_t tile = t0; tile < t1; ++tile) {
         for (int j = lane; j < 256; j += 64) wcnt[w][j] = 0;
-        K key[kIters];
         uint32_t rnk[kIters];
         const int64_t base = tile * kTile + (int64_t)w * (kTile / kWaves);
 #pragma unroll
         for (int it = 0; it < kIters; ++it) {
             const int64_t i = base + it * 64 + lane;
             const bool valid = i < N;
-            const K k = valid ? in[i] : (K)0;
+            const K k = key[it];
             const uint32_t d = (uint32_t)(k >> shift) & 255u;
             uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -175,7 +201,6 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ i
             const uint32_t before = valid ? wcnt[w][d] : 0u;
             rnk[it] = before + (uint32_t)__popcll(peers & lt);
             if (valid && (peers & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
-            key[it] = k;
         }
         __syncthreads();
         {  // digit tid: tile count, tile-local start, and each wave's start within it
@@ -205,6 +230,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ i
                 stage[wcnt[w][d] + rnk[it]] = key[it];
             }
         }
+        load_tile(tile + 1);
         __syncthreads();
         const int64_t tile_n = min((int64_t)kTile, N - tile * kTile);
         for (int j = tid; j < tile_n; j += kThreads) {
