@@ -9,11 +9,13 @@ timed step is one full pass of the path on the GPU:
     graph build (canonicalise, dedup, degree rank, oriented CSR, in-edge lists)
     -> per-edge triangle counts
     -> learned threshold (features, FP32 MLP, snap to the grid (9 + 7 i)/900)
+    -> 16-point check sweep at k/50, k = 0..15 (kept edges, components,
+       largest component per threshold) and its rule of thumb, which is the
+       picker's fallback: when the graph's features leave the picker's
+       training range, the rule's threshold is used instead
     -> weights, prune and connected components at that threshold in one pass
        (Tectonic fp32 weights, keep mask, every kept edge united as it is
-       decided; then min-vertex labels)
-    -> 16-point check sweep at k/50, k = 0..15 (kept edges, components,
-       largest component per threshold).
+       decided; then min-vertex labels).
 value = undirected edges m / step time.  HIP events around every stage give
 the roofline of the dominant kernel (triangle counting) and of the
 weight+prune+components part.
@@ -128,14 +130,16 @@ def picker_study(M, PK, dev):
     model, losses = PK.train(ctx, x[cu(tr)].contiguous(), y[cu(tr)].contiguous())
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    index, _, _, _ = PK.pick(g, t, model, vb)
+    index, _, _, _, flags = PK.pick(g, t, model, vb)
     A = ari.cpu().numpy()
-    pi = index.cpu().numpy()
+    ri = rule_idx.cpu().numpy()
+    fl = flags.cpu().numpy().astype(bool)
+    pi = np.where(fl, ri, index.cpu().numpy())  # the grid point each graph used (fallback where out of range)
     res = dict(train_graphs=int(len(tr)), val_graphs=int(len(va)), train_steps=len(losses),
                train_seconds=round(train_s, 3), final_loss=float(losses[-1]),
                ari_picker=float(A[va, pi[va]].mean()), ari_best_swept=float(A[va].max(1).mean()),
-               ari_best_global=float(A[va][:, int(np.argmax(A[tr].mean(0)))].mean()))
-    ri = rule_idx.cpu().numpy()
+               ari_best_global=float(A[va][:, int(np.argmax(A[tr].mean(0)))].mean()),
+               val_out_of_range=int(fl[va].sum()))
     res["ari_rule_of_thumb"] = float(A[va, ri[va]].mean())
     res["gap_to_best"] = res["ari_best_swept"] - res["ari_picker"]
     res["gain_over_global"] = res["ari_picker"] - res["ari_best_global"]
@@ -233,10 +237,13 @@ def main():
     grid16 = [(k, 50) for k in range(16)]
     sweep_stats = torch.empty((1, 16, len(M.SWEEP_FIELDS)), dtype=torch.int64, device=dev)
     rule_idx = torch.empty(1, dtype=torch.int32, device=dev)
+    rule_delta = torch.empty((1, 2), dtype=torch.int64, device=dev)
+    net_delta = torch.empty((1, 2), dtype=torch.int64, device=dev)
+    out_of_range = torch.zeros(1, dtype=torch.int32, device=dev)
     log(f"HBM in use after allocation: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    stage_names = ["build", "triangles", "picker", "prune_components", "sweep16"]
+    stage_names = ["build", "triangles", "picker", "sweep16", "prune_components"]
 
     def step():
         e = [ev() for _ in range(len(stage_names) + 1)]
@@ -248,16 +255,22 @@ def main():
         if model is not None:
             M.mcd_features(g, t, vbase, x=x, ws=ws)
             M.mcd_mlp_forward(ctx, model.params, model.mean, model.std, x, y=yhat)
-            M.mcd_grid_select(ctx, yhat, PK.GRID_K, PK.GRID_A, PK.GRID_B, PK.GRID_C, index=pidx, delta=pdelta)
+            M.mcd_grid_select(ctx, yhat, PK.GRID_K, PK.GRID_A, PK.GRID_B, PK.GRID_C, index=pidx, delta=net_delta)
         else:
             pdelta.copy_(torch.tensor([[3, 50]], dtype=torch.int64))
         e[3].record()
+        # the 16-point check sweep and its rule of thumb, which is also the
+        # picker's fallback: a graph outside the picker's training range takes
+        # the rule's threshold instead of the network's
+        M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, grid16, vbase=vbase, stats=sweep_stats, ws=ws)
+        M.mcd_sweep_rule(ctx, grid16, sweep_stats, None, vbase=vbase, index=rule_idx, delta=rule_delta)
+        if model is not None:
+            M.mcd_picker_fallback(ctx, x, model.lo, model.hi, model.margin, picked=net_delta, fallback=rule_delta,
+                                  delta=pdelta, flags=out_of_range)
+        e[4].record()
         # weights, prune and components in one pass over the edges
         M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, deltas=pdelta, vbase=vbase, w_f32=wf, keep_bits=keep,
                                n_kept=n_kept, labels=labels, n_components=ncc, ws=ws)
-        e[4].record()
-        M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, grid16, vbase=vbase, stats=sweep_stats, ws=ws)
-        M.mcd_sweep_rule(ctx, grid16, sweep_stats, None, vbase=vbase, index=rule_idx)
         e[5].record()
         return g, e
 
@@ -314,6 +327,8 @@ def main():
     ncomp = int(ncc.item())
     sw = sweep_stats.cpu().numpy()[0]
     pick_delta = [int(v_) for v_ in pdelta.cpu().numpy()[0]]
+    net_pick = [int(v_) for v_ in net_delta.cpu().numpy()[0]] if model is not None else None
+    ood = bool(out_of_range.item())
     log(f"m={m} triangles={tri} picked delta={pick_delta[0]}/{pick_delta[1]} kept={kept} components={ncomp} "
         f"S={S:.3e} W={W:.3e} tc {tc_gbs:.0f} GB/s, wpc {wpc_gbs:.0f} GB/s")
 
@@ -357,7 +372,11 @@ def main():
                     "sweep16": {"delta": [f"{a}/{b}" for a, b in grid16],
                                 "m_kept": sw[:, 0].tolist(), "n_components": sw[:, 1].tolist(),
                                 "largest_component": sw[:, 2].tolist(),
-                                "rule_of_thumb_delta": "%d/%d" % grid16[int(rule_idx.item())]}},
+                                "rule_of_thumb_delta": "%d/%d" % grid16[int(rule_idx.item())]},
+                    "network_delta": net_pick, "picker_out_of_range": ood,
+                    "delta_source": ("none (fixed 3/50)" if model is None else
+                                     "sweep rule of thumb (fallback: features outside the training range)"
+                                     if ood else "learned picker")},
         "picker": pick_res,
         "cpu_baseline": cpu,
     }

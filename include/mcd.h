@@ -368,6 +368,22 @@ mcd_status mcd_features(const mcd_graph* g, const int32_t* t, int32_t n_graphs, 
 mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float min_std, float* mean,
                              float* std);
 
+/* Column minimum and maximum of a feature matrix x (device float[batch][66],
+ * batch >= 1) into lo, hi (device float[66]): the training range that
+ * mcd_picker_fallback checks against. */
+mcd_status mcd_feature_range(mcd_ctx* ctx, const float* x, int32_t batch, float* lo, float* hi);
+
+/* The learned threshold's guard (the full sweep is the picker's fallback):
+ * graph g is out of the training range when some feature x[g][k] lies
+ * outside [lo[k] - margin w_k, hi[k] + margin w_k], w_k = hi[k] - lo[k] (each
+ * bound formed in fp32, one rounding per operation); flags[g] = 1 then, else
+ * 0 (flags: device int32[batch], may be NULL).  delta[g] (device
+ * int64[batch][2], may be NULL) = fallback[g] for flagged graphs, else
+ * picked[g] (delta may alias picked or fallback).  margin >= 0. */
+mcd_status mcd_picker_fallback(mcd_ctx* ctx, const float* x, int32_t batch, const float* lo, const float* hi,
+                               float margin, const int64_t* picked, const int64_t* fallback, int64_t* delta,
+                               int32_t* flags);
+
 /* FP32 MLP 66 -> 64 -> 64 -> 1 with ReLU on the hidden layers, applied to
  * (x - mean) / std.  params: device float[MCD_MLP_PARAMS]; y: device float[batch]. */
 mcd_status mcd_mlp_forward(mcd_ctx* ctx, const float* params, const float* mean, const float* std,

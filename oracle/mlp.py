@@ -110,3 +110,30 @@ def select(y, K, a, b, c):
     q = np.float32(K - 1) * np.asarray(y, np.float32)
     i = np.clip(np.rint(q), 0, K - 1).astype(np.int64)
     return i, np.stack([a + b * i, np.full_like(i, c)], 1)
+
+
+def feature_range(x):
+    """Column minimum and maximum of the training features."""
+    x = np.asarray(x, np.float32)
+    return x.min(0), x.max(0)
+
+
+def out_of_range(x, lo, hi, margin):
+    """Guard of the learned threshold (the sweep is its fallback): a graph is
+    flagged when some feature lies outside [lo - margin w, hi + margin w],
+    w = hi - lo.  Each bound is formed in fp32 with one rounding per
+    operation, the precision of the features, so both sides take the same
+    decision."""
+    x = np.asarray(x, np.float32)
+    lo = np.asarray(lo, np.float32)
+    hi = np.asarray(hi, np.float32)
+    w = np.float32(margin) * (hi - lo)
+    below = x < (lo - w)
+    above = x > (hi + w)
+    return (below | above).any(1).astype(np.int32)
+
+
+def choose_thresholds(flags, picked, fallback):
+    """Per graph: the fallback's threshold where flagged, else the picked one."""
+    flags = np.asarray(flags).astype(bool)
+    return np.where(flags[:, None], np.asarray(fallback), np.asarray(picked))

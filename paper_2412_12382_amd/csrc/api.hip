@@ -718,6 +718,26 @@ mcd_status mcd_feature_stats(mcd_ctx* ctx, const float* x, int32_t batch, float 
     return MCD_OK;
 }
 
+mcd_status mcd_feature_range(mcd_ctx* ctx, const float* x, int32_t batch, float* lo, float* hi) {
+    REQUIRE(ctx && x && lo && hi && batch >= 1, MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_feature_range(x, batch, lo, hi, ctx->stream);
+    return MCD_OK;
+}
+
+mcd_status mcd_picker_fallback(mcd_ctx* ctx, const float* x, int32_t batch, const float* lo, const float* hi,
+                               float margin, const int64_t* picked, const int64_t* fallback, int64_t* delta,
+                               int32_t* flags) {
+    REQUIRE(ctx && lo && hi && batch >= 0 && (batch == 0 || x), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(!delta || (picked && fallback), MCD_ERR_INVALID_ARG, "delta needs picked and fallback");
+    REQUIRE(margin >= 0.f, MCD_ERR_INVALID_ARG, "margin must be non-negative");
+    mcd_status st = use_device(ctx);
+    if (st != MCD_OK) return st;
+    mcd::launch_fallback(x, batch, lo, hi, margin, picked, fallback, delta, flags, ctx->stream);
+    return MCD_OK;
+}
+
 mcd_status mcd_mlp_forward(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
                            const float* x, int32_t batch, float* y) {
     REQUIRE(ctx && params && mean && std && batch >= 0 && (batch == 0 || (x && y)), MCD_ERR_INVALID_ARG,

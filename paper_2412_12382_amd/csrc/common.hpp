@@ -221,5 +221,8 @@ void launch_select(const float* y, int B, int K, int64_t a, int64_t b, int64_t c
                    int64_t* delta, hipStream_t s);
 void launch_targets(const double* ari, int G, int K, double frac, int32_t* index, float* y, hipStream_t s);
 void launch_feature_stats(const float* x, int B, float min_std, float* mean, float* stdv, hipStream_t s);
+void launch_feature_range(const float* x, int B, float* lo, float* hi, hipStream_t s);
+void launch_fallback(const float* x, int B, const float* lo, const float* hi, float margin, const int64_t* picked,
+                     const int64_t* fallback, int64_t* delta, int32_t* flags, hipStream_t s);
 
 }  // namespace mcd

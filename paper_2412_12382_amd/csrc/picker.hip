@@ -271,7 +271,59 @@ __global__ __launch_bounds__(64) void k_feat_stats(const float* __restrict__ x, 
     }
 }
 
+// column minimum and maximum
+__global__ __launch_bounds__(64) void k_feat_range(const float* __restrict__ x, int B, float* __restrict__ lo,
+                                                   float* __restrict__ hi) {
+    for (int k = threadIdx.x; k < NI; k += 64) {
+        float a = x[k], b = x[k];
+        for (int r = 1; r < B; ++r) {
+            const float v = x[(int64_t)r * NI + k];
+            a = fminf(a, v);
+            b = fmaxf(b, v);
+        }
+        lo[k] = a;
+        hi[k] = b;
+    }
+}
+
+// Graph g is outside the training range when some feature leaves
+// [lo - margin (hi - lo), hi + margin (hi - lo)]; its threshold is then the
+// fallback's.  The bounds are formed in fp32 with one rounding per operation
+// (no fused multiply-add), as the oracle does.
+__global__ __launch_bounds__(kThreads) void k_fallback(const float* __restrict__ x, int B,
+                                                       const float* __restrict__ lo, const float* __restrict__ hi,
+                                                       float margin, const int64_t* __restrict__ picked,
+                                                       const int64_t* __restrict__ fallback,
+                                                       int64_t* __restrict__ delta, int32_t* __restrict__ flags) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < B; g += gridDim.x * blockDim.x) {
+        bool out = false;
+        for (int k = 0; k < NI; ++k) {
+            const float w = __fmul_rn(margin, __fsub_rn(hi[k], lo[k]));
+            const float v = x[(int64_t)g * NI + k];
+            out |= v < __fsub_rn(lo[k], w) || v > __fadd_rn(hi[k], w);
+        }
+        if (flags) flags[g] = out ? 1 : 0;
+        if (delta) {
+            const int64_t* src = out ? fallback : picked;
+            const int64_t num = src[2 * g], den = src[2 * g + 1];
+            delta[2 * g] = num;
+            delta[2 * g + 1] = den;
+        }
+    }
+}
+
 }  // namespace
+
+void launch_feature_range(const float* x, int B, float* lo, float* hi, hipStream_t s) {
+    hipLaunchKernelGGL(k_feat_range, dim3(1), dim3(64), 0, s, x, B, lo, hi);
+}
+
+void launch_fallback(const float* x, int B, const float* lo, const float* hi, float margin, const int64_t* picked,
+                     const int64_t* fallback, int64_t* delta, int32_t* flags, hipStream_t s) {
+    if (B <= 0) return;
+    hipLaunchKernelGGL(k_fallback, dim3(grid_for(B, 1024)), dim3(kThreads), 0, s, x, B, lo, hi, margin, picked,
+                       fallback, delta, flags);
+}
 
 size_t features_scratch_bytes(int G) { return mcd_align(sizeof(unsigned long long) * (size_t)G * 65); }
 

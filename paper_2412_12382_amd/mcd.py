@@ -86,6 +86,8 @@ def lib():
             "mcd_features_workspace_size": [I32, ctypes.POINTER(SZ)],
             "mcd_features": [P, P, I32, P, P, P, SZ],
             "mcd_feature_stats": [P, P, I32, ctypes.c_float, P, P],
+            "mcd_feature_range": [P, P, I32, P, P],
+            "mcd_picker_fallback": [P, P, I32, P, P, ctypes.c_float, P, P, P, P],
             "mcd_mlp_forward": [P, P, P, P, P, I32, P],
             "mcd_mlp_workspace_size": [I32, ctypes.POINTER(SZ)],
             "mcd_mlp_gradient": [P, P, P, P, P, P, I32, P, P, P, SZ],
@@ -428,6 +430,27 @@ def mcd_feature_stats(ctx: Context, x, min_std: float = 1e-2, mean=None, std=Non
     std = _empty(MLP_IN, torch.float32, ctx.device) if std is None else std
     _check(lib().mcd_feature_stats(ctx.handle, _p(x), x.shape[0], min_std, _p(mean), _p(std)))
     return mean, std
+
+
+def mcd_feature_range(ctx: Context, x, lo=None, hi=None):
+    lo = _empty(MLP_IN, torch.float32, ctx.device) if lo is None else lo
+    hi = _empty(MLP_IN, torch.float32, ctx.device) if hi is None else hi
+    _check(lib().mcd_feature_range(ctx.handle, _p(x), x.shape[0], _p(lo), _p(hi)))
+    return lo, hi
+
+
+def mcd_picker_fallback(ctx: Context, x, lo, hi, margin: float, picked=None, fallback=None, delta=None,
+                        flags=None, want_flags=True):
+    """Out-of-range flags per graph and, given both threshold tables, the
+    threshold each graph uses (fallback where flagged)."""
+    B = x.shape[0]
+    if flags is None and want_flags:
+        flags = _empty(max(B, 1), torch.int32, ctx.device)
+    if delta is None and picked is not None:
+        delta = _empty((max(B, 1), 2), torch.int64, ctx.device)
+    _check(lib().mcd_picker_fallback(ctx.handle, _p(x), B, _p(lo), _p(hi), margin, _p(picked), _p(fallback),
+                                     _p(delta), _p(flags)))
+    return (None if flags is None else flags[:B]), (None if delta is None else delta[:B])
 
 
 def mcd_mlp_forward(ctx: Context, params, mean, std, x, y=None):

@@ -2,8 +2,8 @@
 
 Triangles, one-pass weights + prune at per-graph device thresholds,
 components over the kept list, the 64-threshold sweep with ARI and
-modularity, the threshold rule of thumb, picker features, MLP forward and
-grid snap are enqueued by the library on the
+modularity, the threshold rule of thumb, picker features, MLP forward,
+grid snap and the picker's range guard are enqueued by the library on the
 context's stream while a HIP graph is being captured on it.  The graph is
 replayed several times, with eager work and synchronisations in between and
 every output overwritten before each replay, and each replay must equal the
@@ -74,6 +74,10 @@ def test_capture_and_replay_matches_eager():
             y=torch.empty(G, dtype=torch.float32, device=dev),
             idx=torch.empty(G, dtype=torch.int32, device=dev),
             delta=torch.empty((G, 2), dtype=torch.int64, device=dev),
+            lo=torch.empty(M.MLP_IN, dtype=torch.float32, device=dev),
+            hi=torch.empty(M.MLP_IN, dtype=torch.float32, device=dev),
+            ood=torch.empty(G, dtype=torch.int32, device=dev),
+            used=torch.empty((G, 2), dtype=torch.int64, device=dev),
         )
         ws_t = torch.empty(M.mcd_triangles_workspace_size(g), dtype=torch.uint8, device=dev)
         ws_c = torch.empty(M.mcd_components_workspace_size(g), dtype=torch.uint8, device=dev)
@@ -93,6 +97,11 @@ def test_capture_and_replay_matches_eager():
                         ari=out["ari"], modularity=out["q"], ws=ws_s)
             M.mcd_sweep_rule(ctx, GRID64, out["stats"], out["q"], vbase=vb, index=out["rule"],
                              delta=out["rule_delta"])
+            # the picker's range guard (range of the first three graphs) and
+            # the threshold each graph then uses
+            M.mcd_feature_range(ctx, out["x"][:3], lo=out["lo"], hi=out["hi"])
+            M.mcd_picker_fallback(ctx, out["x"], out["lo"], out["hi"], 0.25, picked=out["delta"],
+                                  fallback=out["rule_delta"], delta=out["used"], flags=out["ood"])
 
         path()
     torch.cuda.synchronize()

@@ -136,6 +136,43 @@ def test_select_targets_and_per_graph_prune():
     assert np.array_equal(pc["labels"].cpu().numpy(), lab_o) and int(pc["n_components"].item()) == ncc_o
 
 
+def test_feature_range_and_fallback_guard():
+    # the training range and the out-of-range guard on feature rows built
+    # around the bounds, against the oracle's fp32 decisions; the threshold
+    # each row then uses
+    from gpu_util import ctx
+    rng = np.random.default_rng(11)
+    xt = rng.random((20, M.MLP_IN)).astype(np.float32) * rng.random(M.MLP_IN).astype(np.float32) * 8
+    lo_g, hi_g = M.mcd_feature_range(ctx(), cuda(xt))
+    lo_o, hi_o = mlp.feature_range(xt)
+    assert np.array_equal(lo_g.cpu().numpy(), lo_o) and np.array_equal(hi_g.cpu().numpy(), hi_o)
+    margin = np.float32(0.25)
+    w = margin * (hi_o - lo_o)
+    up, down = hi_o + w, lo_o - w
+    rows = [xt[0], xt[7], (lo_o + hi_o) / 2, up, down]
+    for j in (0, 17, 65):
+        for edge, away in ((up, np.float32(np.inf)), (down, np.float32(-np.inf))):
+            r = (lo_o + hi_o) / 2
+            r[j] = np.nextafter(edge[j], away)
+            rows.append(r.copy())
+    rows += list(rng.random((12, M.MLP_IN)).astype(np.float32) * 10)
+    x = np.stack(rows).astype(np.float32)
+    B = len(x)
+    picked = np.stack([9 + 7 * np.arange(B), np.full(B, 900)], 1).astype(np.int64)
+    fb = np.stack([np.arange(B), np.full(B, 50)], 1).astype(np.int64)
+    flags, delta = M.mcd_picker_fallback(ctx(), cuda(x), lo_g, hi_g, float(margin), picked=cuda(picked),
+                                         fallback=cuda(fb))
+    fo = mlp.out_of_range(x, lo_o, hi_o, margin)
+    assert fo[:5].tolist() == [0, 0, 0, 0, 0] and fo[5:11].tolist() == [1] * 6
+    assert np.array_equal(flags.cpu().numpy(), fo)
+    assert np.array_equal(delta.cpu().numpy(), mlp.choose_thresholds(fo, picked, fb))
+    # the chosen thresholds written over the picked table itself
+    pk = cuda(picked)
+    M.mcd_picker_fallback(ctx(), cuda(x), lo_g, hi_g, float(margin), picked=pk, fallback=cuda(fb), delta=pk,
+                          want_flags=False)
+    assert np.array_equal(pk.cpu().numpy(), mlp.choose_thresholds(fo, picked, fb))
+
+
 def test_picker_end_to_end_small_batch():
     # a reduced planted-partition batch: sweep -> targets -> train -> pick;
     # the picked labels are the oracle's at the picked thresholds, and the
@@ -155,27 +192,49 @@ def test_picker_end_to_end_small_batch():
     model, losses = PK.train(ctx(), x[torch.from_numpy(tr).cuda()].contiguous(),
                              y[torch.from_numpy(tr).cuda()].contiguous())
     assert losses[-1] < losses[0]
-    index, deltas, labels, ncc = PK.pick(g, t, model, vbase)
+    index, deltas, labels, ncc, flags = PK.pick(g, t, model, vbase)
     A = ari.cpu().numpy()
     pi = index.cpu().numpy()
     picked = A[va, pi[va]].mean()
     best = A[va].max(1).mean()
     glob = A[va][:, np.argmax(A[tr].mean(0))].mean()
     print(f"small batch val ARI: picker {picked:.4f}  per-graph best {best:.4f}  best global {glob:.4f}")
-    # labels equal the oracle's components at the picked grid point of every
-    # graph: the oracle sweeps the whole grid by itself; the picked index only
-    # selects which of its results to compare with
+    # the range guard: the oracle's own features of every graph, the range of
+    # the training graphs' features, and its fp32 decision per graph
     lo, hi = oracle.canon(n, b["src"], b["dst"])
     deg = oracle.degrees(n, lo, hi)
     to = oracle.triangles(n, lo, hi)
-    _, _, labels_o = oracle.sweep(n, lo, hi, to, deg, oracle.TECTONIC, PK.GRID, vbase=b["vbase"])
-    got = labels.cpu().numpy()
     vb = b["vbase"]
+    xo = []
     for k in range(G):
-        assert np.array_equal(got[vb[k]:vb[k + 1]], labels_o[pi[k], vb[k]:vb[k + 1]]), k
-        assert tuple(deltas.cpu().numpy()[k]) == PK.GRID[pi[k]]
-    assert int(ncc.item()) == sum(int(np.count_nonzero(labels_o[pi[k], vb[k]:vb[k + 1]] ==
+        sel = (lo >= vb[k]) & (lo < vb[k + 1])
+        l2, h2 = (lo[sel] - vb[k]).astype(np.int32), (hi[sel] - vb[k]).astype(np.int32)
+        nk = int(vb[k + 1] - vb[k])
+        xo.append(mlp.features(nk, l2, h2, oracle.triangles(nk, l2, h2), oracle.degrees(nk, l2, h2)))
+    xo = np.stack(xo).astype(np.float32)
+    lo_f, hi_f = mlp.feature_range(xo[tr])
+    flags_o = mlp.out_of_range(xo, lo_f, hi_f, PK.MARGIN)
+    assert np.array_equal(flags.cpu().numpy(), flags_o)
+    print(f"graphs out of the training range (fallback to the sweep's rule): {int(flags_o.sum())} of {G}")
+    # labels equal the oracle's components at the threshold each graph used:
+    # the network's grid point, or the oracle's own rule of thumb on its own
+    # sweep with modularity where the guard fired; the GPU's index only
+    # selects which of the oracle's results to compare with
+    st_o, _, labels_o, q_o = oracle.sweep(n, lo, hi, to, deg, oracle.TECTONIC, PK.GRID, vbase=vb,
+                                          modularity=True)
+    rule_o = np.asarray(oracle.rule_of_thumb(st_o, PK.GRID, vb, q_o))
+    chosen = np.where(flags_o == 1, rule_o, pi)
+    got = labels.cpu().numpy()
+    for k in range(G):
+        assert np.array_equal(got[vb[k]:vb[k + 1]], labels_o[chosen[k], vb[k]:vb[k + 1]]), k
+        assert tuple(deltas.cpu().numpy()[k]) == PK.GRID[chosen[k]]
+    assert int(ncc.item()) == sum(int(np.count_nonzero(labels_o[chosen[k], vb[k]:vb[k + 1]] ==
                                                       np.arange(vb[k], vb[k + 1]))) for k in range(G))
+    # forced fallback: every graph takes the rule of thumb
+    _, dforce, lforce, _, _ = PK.pick(g, t, model, vbase, fallback="force")
+    for k in range(G):
+        assert tuple(dforce.cpu().numpy()[k]) == PK.GRID[rule_o[k]], k
+        assert np.array_equal(lforce.cpu().numpy()[vb[k]:vb[k + 1]], labels_o[rule_o[k], vb[k]:vb[k + 1]]), k
 
 
 def test_picker_gain_on_planted_batch():
@@ -194,7 +253,7 @@ def test_picker_gain_on_planted_batch():
     gi = np.arange(256)
     tr, va = gi[gi % 4 != 3], gi[gi % 4 == 3]
     model, losses = PK.train(ctx(), x[cuda(tr)].contiguous(), y[cuda(tr)].contiguous())
-    index, _, _, _ = PK.pick(g, t, model, vb)
+    index, _, _, _, _ = PK.pick(g, t, model, vb)
     A = ari.cpu().numpy()
     pi = index.cpu().numpy()
     picked = A[va, pi[va]].mean()

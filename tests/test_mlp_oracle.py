@@ -57,3 +57,21 @@ def test_targets_and_select():
     i, d = mlp.select([-0.2, 0.0, 0.49, 0.5, 1.7], 64, 9, 7, 900)
     assert i.tolist() == [0, 0, 31, 32, 63]
     assert d[1].tolist() == [9, 900] and d[4].tolist() == [9 + 7 * 63, 900]
+
+
+def test_range_guard_hand_cases():
+    # training range [0, 1] and [0, 2], margin 1/4: bounds [-1/4, 5/4] and
+    # [-1/2, 5/2] (exact in fp32); the bounds themselves are inside
+    train = np.array([[0.0, 2.0], [1.0, 0.0], [0.5, 1.0]], np.float32)
+    lo, hi = mlp.feature_range(train)
+    assert lo.tolist() == [0.0, 0.0] and hi.tolist() == [1.0, 2.0]
+    x = np.array([[1.25, 2.5], [np.nextafter(np.float32(1.25), np.float32(2)), 0.0], [-0.5, -0.5],
+                  [0.0, np.nextafter(np.float32(-0.5), np.float32(-1))], [0.5, 1.0], [-0.25, 0.0]], np.float32)
+    assert mlp.out_of_range(x, lo, hi, 0.25).tolist() == [0, 1, 1, 1, 0, 0]
+    # margin 0: exactly the training range; training rows are never out of it
+    assert mlp.out_of_range(x, lo, hi, 0.0).tolist() == [1, 1, 1, 1, 0, 1]
+    assert mlp.out_of_range(train, lo, hi, 0.0).tolist() == [0, 0, 0]
+    picked = np.array([[9, 900]] * 6)
+    fb = np.array([[k, 50] for k in range(6)])
+    got = mlp.choose_thresholds(mlp.out_of_range(x, lo, hi, 0.25), picked, fb)
+    assert got.tolist() == [[9, 900], [1, 50], [2, 50], [3, 50], [9, 900], [9, 900]]
