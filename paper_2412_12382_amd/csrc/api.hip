@@ -300,10 +300,14 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     // in-edge lists (edges grouped by head), in-degree = degree - out-degree
     mcd::launch_in_count(G.deg, B.outdeg, n, B.inv, s);
     mcd::exclusive_scan_i32_i64(B.inv, n, G.in_off, B.scan, s);
-    int32_t* suf = (int32_t*)B.uniq;  // the unique keys are consumed by now
+    // the suffix lengths ride along with the sort (two int32[m] buffers in
+    // the unique keys' uint64[P] space, consumed by now)
+    int32_t* suf = (int32_t*)B.uniq;
+    int32_t* suf2 = suf + m;
+    int32_t* suf_sorted = suf;
     mcd::launch_in_keys(G.src, G.adj, G.off, m, B.k1, suf, s);
-    uint64_t* by_head = mcd::radix_sort_u64(B.k1, B.k2, m, bits, B.radix, s, 32);
-    mcd::launch_in_fill(by_head, suf, m, G.in_ea, s);
+    uint64_t* by_head = mcd::radix_sort_u64_kv(B.k1, B.k2, suf, suf2, &suf_sorted, m, bits, B.radix, s, 32);
+    mcd::launch_in_fill(by_head, suf_sorted, m, G.in_ea, s);
     if ((st = sync_read(ctx, ctrl, ctx->h_ctrl, 4)) != MCD_OK) return st;
 
     mcd_graph* g = new mcd_graph();

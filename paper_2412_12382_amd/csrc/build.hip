@@ -194,14 +194,12 @@ __global__ __launch_bounds__(kThreads) void k_in_keys(const int32_t* __restrict_
 }
 
 // In-edge lists grouped by head, each in increasing edge id (= increasing
-// tail rank): the stable sort of (head, edge id) keys.
+// tail rank): the stable sort of (head, edge id) keys, which carried each
+// edge's suffix length along (suf is in sorted order: no gather).
 __global__ __launch_bounds__(kThreads) void k_in_fill(const uint64_t* __restrict__ sorted,
                                                       const int32_t* __restrict__ suf, int64_t m,
                                                       int2* __restrict__ in_ea) {
-    GRID_STRIDE(i, m) {
-        const int32_t e = (int32_t)(uint32_t)sorted[i];
-        in_ea[i] = make_int2(e, suf[e]);
-    }
+    GRID_STRIDE(i, m) in_ea[i] = make_int2((int32_t)(uint32_t)sorted[i], suf[i]);
 }
 
 }  // namespace

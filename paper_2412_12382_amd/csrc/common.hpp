@@ -88,6 +88,10 @@ uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* s
                          hipStream_t s, int first_bit = 0);
 // The same for 32-bit keys on bits [0, nbits).
 uint32_t* radix_sort_u32(uint32_t* a, uint32_t* b, int64_t N, int nbits, void* scratch, hipStream_t s);
+// radix_sort_u64 carrying an int32 value with every key (va, vb: the value
+// buffers, like a, b); *vres receives the buffer holding the sorted values.
+uint64_t* radix_sort_u64_kv(uint64_t* a, uint64_t* b, int32_t* va, int32_t* vb, int32_t** vres, int64_t N,
+                            int nbits, void* scratch, hipStream_t s, int first_bit = 0);
 // Distinct keys of a sorted array, MCD_SENTINEL excluded, into out; the count
 // goes to *d_count (device).  scratch: compact_scratch_bytes(N).
 size_t compact_scratch_bytes(int64_t N);
@@ -131,6 +135,7 @@ void launch_in_count(const int32_t* deg, const int32_t* outdeg, int64_t n, int32
 void launch_in_keys(const int32_t* src, const int32_t* adj, const int64_t* off, int64_t m, uint64_t* keys,
                     int32_t* suf, hipStream_t s);
 // in_ea[i] = (e, suf[e]) for the edges e of the head-sorted keys
+// sorted: (head, edge id) keys; suf: the suffix lengths in the same order
 void launch_in_fill(const uint64_t* sorted, const int32_t* suf, int64_t m, int2* in_ea, hipStream_t s);
 
 // ---- triangles (tc.hip) ----

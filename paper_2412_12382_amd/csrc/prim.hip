@@ -141,15 +141,17 @@ __device__ __forceinline__ T block_excl_scan(T x, T* sh, T* total) {
     return before + inc - x;
 }
 
-// Stable scatter of block b's key range by the digit at `shift`.  Each wave
+// Stable scatter of block b's key range by the digit at `shift` (KV: an
+// int32 value travels with every key, vin -> vout).  Each wave
 // ranks its own contiguous 1024-key slice of the tile with 64-lane ballots
 // (lanes holding the same digit form a peer mask); slices are ordered wave by
 // wave, so the rank order equals the input order.  The ranked tile is first
 // placed in LDS grouped by digit, then written out so that consecutive
 // threads store consecutive keys of a digit's run (coalesced writes).
-template <class K>
+template <class K, bool KV>
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ in,
-                                                         K* __restrict__ out, int64_t N,
+                                                         K* __restrict__ out, const int32_t* __restrict__ vin,
+                                                         int32_t* __restrict__ vout, int64_t N,
                                                          int shift, int64_t tpb, int NB,
                                                          const int64_t* __restrict__ rowpre,
                                                          const int64_t* __restrict__ rowtot) {
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ i
     __shared__ uint32_t loff[256];
     __shared__ uint32_t tcnt[256];
     __shared__ K stage[kTile];
+    __shared__ int32_t vstage[KV ? kTile : 1];
     __shared__ int64_t sh64[kWaves];
     __shared__ uint32_t sh32[kWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -172,12 +175,15 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ i
     const uint64_t lt = lane_lt_mask();
     // keys of the next tile are loaded while the current one is written out
     K key[kIters];
+    int32_t val[KV ? kIters : 1];
     auto load_tile = [&](int64_t tile) {
         const int64_t base = tile * kTile + (int64_t)w * (kTile / kWaves);
 #pragma unroll
         for (int it = 0; it < kIters; ++it) {
             const int64_t i = base + it * 64 + lane;
-            key[it] = (tile < t1 && i < N) ? in[i] : (K)0;
+            const bool ok = tile < t1 && i < N;
+            key[it] = ok ? in[i] : (K)0;
+            if (KV) val[KV ? it : 0] = ok ? vin[i] : 0;
         }
     };
     load_tile(t0);
@@ -228,6 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ i
             if (i < N) {
                 const uint32_t d = (uint32_t)(key[it] >> shift) & 255u;
                 stage[wcnt[w][d] + rnk[it]] = key[it];
+                if (KV) vstage[wcnt[w][d] + rnk[it]] = val[KV ? it : 0];
             }
         }
         load_tile(tile + 1);
@@ -237,6 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const K* __restrict__ i
             const K k = stage[j];
             const uint32_t d = (uint32_t)(k >> shift) & 255u;
             out[run[d] + (j - (int64_t)loff[d])] = k;
+            if (KV) vout[run[d] + (j - (int64_t)loff[d])] = vstage[j];
         }
         __syncthreads();
         run[tid] += tcnt[tid];
@@ -363,8 +371,10 @@ void fill_any(T* p, int64_t N, T v, hipStream_t s) {
 
 size_t radix_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * 256 * (kMaxBlocks + 1)); }
 
-template <class K>
-K* radix_sort(K* a, K* b, int64_t N, int nbits, void* scratch, hipStream_t s, int first_bit) {
+template <class K, bool KV>
+K* radix_sort(K* a, K* b, int32_t* va, int32_t* vb, int32_t** vres, int64_t N, int nbits, void* scratch,
+              hipStream_t s, int first_bit) {
+    if (KV) *vres = va;
     if (N <= 1 || nbits <= 0) return a;
     const int64_t ntiles = div_up(N, kTile);
     const int NB = grid_blocks(ntiles);
@@ -376,21 +386,31 @@ K* radix_sort(K* a, K* b, int64_t N, int nbits, void* scratch, hipStream_t s, in
         const int shift = first_bit + 8 * p;
         hipLaunchKernelGGL(k_rs_hist<K>, dim3(NB), dim3(kThreads), 0, s, a, N, shift, tpb, NB, counts);
         hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kThreads), 0, s, counts, NB, tot);
-        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(NB), dim3(kThreads), 0, s, a, b, N, shift, tpb, NB, counts, tot);
+        hipLaunchKernelGGL((k_rs_scatter<K, KV>), dim3(NB), dim3(kThreads), 0, s, a, b, va, vb, N, shift, tpb, NB,
+                           counts, tot);
         K* t = a;
         a = b;
         b = t;
+        int32_t* tv = va;
+        va = vb;
+        vb = tv;
     }
+    if (KV) *vres = va;
     return a;
 }
 
 uint64_t* radix_sort_u64(uint64_t* a, uint64_t* b, int64_t N, int nbits, void* scratch, hipStream_t s,
                          int first_bit) {
-    return radix_sort<uint64_t>(a, b, N, nbits, scratch, s, first_bit);
+    return radix_sort<uint64_t, false>(a, b, nullptr, nullptr, nullptr, N, nbits, scratch, s, first_bit);
+}
+
+uint64_t* radix_sort_u64_kv(uint64_t* a, uint64_t* b, int32_t* va, int32_t* vb, int32_t** vres, int64_t N,
+                            int nbits, void* scratch, hipStream_t s, int first_bit) {
+    return radix_sort<uint64_t, true>(a, b, va, vb, vres, N, nbits, scratch, s, first_bit);
 }
 
 uint32_t* radix_sort_u32(uint32_t* a, uint32_t* b, int64_t N, int nbits, void* scratch, hipStream_t s) {
-    return radix_sort<uint32_t>(a, b, N, nbits, scratch, s, 0);
+    return radix_sort<uint32_t, false>(a, b, nullptr, nullptr, nullptr, N, nbits, scratch, s, 0);
 }
 
 size_t compact_scratch_bytes(int64_t) { return mcd_align(sizeof(int64_t) * (kMaxBlocks + 1)); }
