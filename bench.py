@@ -87,6 +87,33 @@ def profiled_traffic(stages):
     return total
 
 
+def tw_vs_tectonic(M, dev, G: int = 64):
+    """The paper's imbalanced two-block SBM (blocks of 50, p1 0.1, p2 0.8, q
+    0.05), G seeds as one batch: best ARI over a threshold sweep per measure
+    (TW: integers -50..13; Tectonic: (9 + 7 i)/900), on the GPU."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+
+    b = gg.sbm_two_blocks_batch(G)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = M.mcd_ctx_create(0)
+    g = M.mcd_graph_build(ctx, cu(b["src"]), cu(b["dst"]), b["n"])
+    t = M.mcd_triangles(g)
+    out = {}
+    for name, meas, grid in (("tw", M.MCD_SIM_TW, [(k, 1) for k in range(-50, 14)]),
+                             ("tectonic", M.MCD_SIM_TECTONIC, [(9 + 7 * i, 900) for i in range(64)])):
+        _, ari, _ = M.mcd_sweep(g, meas, t, grid, vbase=cu(b["vbase"]), truth=cu(b["truth"]))
+        best = ari.cpu().numpy().max(1)
+        out[name] = best
+    return dict(graphs=G, setting="two blocks of 50, p1=0.1, p2=0.8, q=0.05",
+                best_ari_tw=float(out["tw"].mean()), best_ari_tectonic=float(out["tectonic"].mean()),
+                exact_recovery_tw=int((out["tw"] == 1.0).sum()),
+                exact_recovery_tectonic=int((out["tectonic"] == 1.0).sum()),
+                tw_at_least_tectonic=int((out["tw"] >= out["tectonic"]).sum()))
+
+
 def cpu_baseline(scale: int, ef: int, seed: int, num: int, den: int):
     """The oracle (plain C, OpenMP) on a bounded sample of the same workload
     family: R-MAT at a smaller scale, same generator and a fixed threshold."""
@@ -208,6 +235,10 @@ def main():
             f"best global {pick_res['ari_best_global']:.4f}); latency {pick_res['latency_picker_ms']:.3f} ms vs "
             f"sweep {pick_res['latency_sweep_ms']:.3f} ms")
         torch.cuda.empty_cache()
+    study = tw_vs_tectonic(M, dev)
+    log(f"imbalanced two-block SBM, {study['graphs']} graphs: best ARI TW {study['best_ari_tw']:.3f} "
+        f"({study['exact_recovery_tw']} exact), Tectonic {study['best_ari_tectonic']:.3f} "
+        f"({study['exact_recovery_tectonic']} exact)")
 
     log(f"generating R-MAT scale {args.scale} edge factor {args.edge_factor} on the host")
     t0 = time.perf_counter()
@@ -378,6 +409,7 @@ def main():
                                      "sweep rule of thumb (fallback: features outside the training range)"
                                      if ood else "learned picker")},
         "picker": pick_res,
+        "tw_vs_tectonic": study,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -271,3 +271,31 @@ def sbm_batch(G: int = 256, n_max: int | None = None, first: int = 0):
     return dict(src=np.concatenate(srcs).astype(np.int32), dst=np.concatenate(dsts).astype(np.int32),
                 n=vbase[-1], vbase=np.array(vbase, np.int64),
                 truth=np.concatenate(truths).astype(np.int32), params=params)
+
+
+def sbm_two_blocks(n: int, p1: float, p2: float, q: float, seed: int):
+    """The imbalanced two-block SBM of the paper's Sec. 3 analysis: blocks B1
+    = [0, n) and B2 = [n, 2n), pairs inside B_i joined with probability p_i,
+    pairs across with probability q, every pair an independent draw (three
+    per-pair Bernoulli streams of distinct seeds).  (src, dst, labels)."""
+    s1, d1, _ = sbm_pairs(n, 1, p1, 0.0, 3 * seed)
+    s2, d2, _ = sbm_pairs(n, 1, p2, 0.0, 3 * seed + 1)
+    sx, dx, labels = sbm_pairs(2 * n, 2, 0.0, q, 3 * seed + 2)  # across pairs only
+    src = np.concatenate([s1, s2 + n, sx]).astype(np.int32)
+    dst = np.concatenate([d1, d2 + n, dx]).astype(np.int32)
+    return src, dst, labels
+
+
+def sbm_two_blocks_batch(G: int, n: int = 50, p1: float = 0.1, p2: float = 0.8, q: float = 0.05, seed0: int = 0):
+    """G independent imbalanced two-block SBMs (seeds seed0 .. seed0+G-1; the
+    defaults are the paper's visualised setting) as one disjoint union:
+    dict(src, dst, n, vbase[G+1], truth (block ids unique across graphs))."""
+    srcs, dsts, truths = [], [], []
+    for g in range(G):
+        src, dst, lab = sbm_two_blocks(n, p1, p2, q, seed0 + g)
+        srcs.append(src + 2 * n * g)
+        dsts.append(dst + 2 * n * g)
+        truths.append(lab + 2 * g)
+    return dict(src=np.concatenate(srcs).astype(np.int32), dst=np.concatenate(dsts).astype(np.int32),
+                n=2 * n * G, vbase=np.arange(G + 1, dtype=np.int64) * 2 * n,
+                truth=np.concatenate(truths).astype(np.int32))

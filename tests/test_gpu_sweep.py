@@ -193,3 +193,16 @@ def test_sweep_precision_recall_f1():
             a, b = vbase[gk], vbase[gk + 1]
             want = oracle.precision_recall_f1(labels_o[i, a:b], truth[a:b])
             assert np.all(np.abs(prf[gk, i] - np.array(want)) <= 1e-12 * np.maximum(1.0, np.abs(want))), (i, gk)
+
+
+def test_imbalanced_sbm_tw_vs_tectonic():
+    # the two-block study on the GPU: both sweeps equal the oracle's, and the
+    # GPU's ARIs show the paper's outcome (TW recovers the blocks, Tectonic not)
+    b = gg.sbm_two_blocks_batch(20)
+    tw_grid = [(k, 1) for k in range(-50, 14)]
+    got_tw = gpu_sweep(b["src"], b["dst"], b["n"], M.MCD_SIM_TW, tw_grid, b["truth"], b["vbase"])
+    compare(got_tw, oracle_sweep(b["src"], b["dst"], b["n"], oracle.TW, tw_grid, b["truth"], b["vbase"]))
+    got_te = gpu_sweep(b["src"], b["dst"], b["n"], M.MCD_SIM_TECTONIC, GRID64, b["truth"], b["vbase"])
+    compare(got_te, oracle_sweep(b["src"], b["dst"], b["n"], oracle.TECTONIC, GRID64, b["truth"], b["vbase"]))
+    best_tw, best_te = got_tw[1].max(1), got_te[1].max(1)
+    assert np.all(best_tw >= best_te) and best_tw.mean() > 0.95 and best_te.mean() < 0.8

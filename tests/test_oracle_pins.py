@@ -561,3 +561,30 @@ def test_k4_participation_pins():
         # K4-prune at c keeps exactly the edges in at least c 4-cliques
         keep = oracle.prune(oracle.K4, lo, hi, got, oracle.degrees(n, lo, hi), 2, 1)
         assert np.array_equal(keep, (got >= 2).astype(np.uint8))
+
+
+def test_imbalanced_sbm_tw_recovers_tectonic_does_not():
+    # Sec. 3's two-block analysis in the paper's visualised setting (blocks of
+    # 50, p1 = 0.1, p2 = 0.8, q = 0.05), 20 seeds: across-block edges score
+    # above the sparse block's own edges under Tectonic but far below them
+    # under TW, so TW's best threshold recovers the blocks (nearly always
+    # exactly) and Tectonic's does not; per graph TW's best ARI is never lower
+    b = gg.sbm_two_blocks_batch(20)
+    n, vb = b["n"], b["vbase"]
+    lo, hi = oracle.canon(n, b["src"], b["dst"])
+    deg = oracle.degrees(n, lo, hi)
+    t = oracle.triangles(n, lo, hi)
+    blk = np.asarray(b["truth"])
+    in_b1 = (blk[lo] == blk[hi]) & (blk[lo] % 2 == 0)
+    across = blk[lo] != blk[hi]
+    w = oracle.tectonic(lo, hi, t, deg)
+    tw = oracle.tw(lo, hi, t, deg)
+    assert w[across].mean() > w[in_b1].mean()
+    assert tw[in_b1].mean() > tw[across].mean() + 20
+    _, a_tw, _ = oracle.sweep(n, lo, hi, t, deg, oracle.TW, [(k, 1) for k in range(-50, 14)], b["truth"], vb)
+    _, a_te, _ = oracle.sweep(n, lo, hi, t, deg, oracle.TECTONIC, [(9 + 7 * i, 900) for i in range(64)],
+                              b["truth"], vb)
+    best_tw, best_te = a_tw.max(1), a_te.max(1)
+    assert np.all(best_tw >= best_te)
+    assert best_tw.mean() > 0.95 and (best_tw == 1.0).sum() >= 12
+    assert best_te.mean() < 0.8 and not np.any(best_te == 1.0)
