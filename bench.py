@@ -305,12 +305,20 @@ def main():
         e[5].record()
         return g, e
 
+    # the scratch buffer serves every stage: at least the build's, the
+    # triangle count's (with the tuner's) and the later stages' needs
+    g0 = M.mcd_graph_build(ctx, src, dst, n, storage=storage, ws=ws)
+    need = max(ws_b, M.mcd_triangles_workspace_size(g0), M.mcd_tune_triangles_workspace_size(g0))
+    if need > ws.numel():
+        del ws
+        torch.cuda.empty_cache()
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        log(f"scratch grown to {need / 2**30:.1f} GiB for the triangle count")
     tuned = None
     if not args.no_tune:
-        g0 = M.mcd_graph_build(ctx, src, dst, n, storage=storage, ws=ws)
         tuned, tuned_ms = M.mcd_tune_triangles(g0, t, ws=ws, reps=1)
         log(f"triangle-count parameters tuned on this graph: {tuned} ({tuned_ms:.1f} ms)")
-        del g0
+    del g0
 
     for i in range(args.warmup):
         g, _ = step()

@@ -517,6 +517,12 @@ KEPT_SEGMENTS = 16384
 TUNE_PARAMS = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max")
 
 
+def mcd_tune_triangles_workspace_size(g: Graph) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_tune_triangles_workspace_size(g.handle, ctypes.byref(b)))
+    return b.value
+
+
 def mcd_tune_triangles(g: Graph, t=None, ws=None, reps: int = 2):
     """Autotune the triangle-count parameters on g; returns ({name: value}, ms)."""
     t = _empty(max(g.m, 1), torch.int32, g.ctx.device) if t is None else t
