@@ -55,23 +55,47 @@ __global__ __launch_bounds__(kThreads) void k_feat_hist(const int32_t* __restric
                                                         const int32_t* __restrict__ t, int64_t m,
                                                         const int64_t* __restrict__ vbase, int G,
                                                         unsigned long long* __restrict__ hist) {
+    // one graph: 8 copies of the 64 bins per wave, picked by lane (stride 65
+    // words: the copies sit in different banks), so lanes with equal bins
+    // (t = 0 above all) collide at most 8 ways; batches: one (graph, bin)
+    // table per block when it fits
+    constexpr int kCopies = 8, kStride = 65;
     __shared__ uint32_t h[4096];
     const bool local = G * 64 <= 4096;
+    const int nloc = G == 1 ? (kThreads / 64) * kCopies * kStride : G * 64;
     if (local)
-        for (int i = threadIdx.x; i < G * 64; i += blockDim.x) h[i] = 0;
+        for (int i = threadIdx.x; i < nloc; i += blockDim.x) h[i] = 0;
     __syncthreads();
+    const int lane = threadIdx.x & 63;
     GRID_STRIDE(e, m) {
-        const int64_t D = (uint32_t)dsum[e];
-        int64_t b = (128 * (int64_t)t[e]) / D;
+        const uint32_t D = (uint32_t)dsum[e];
+        const uint32_t tt = (uint32_t)t[e];
+        // floor(128 t / D) without a 64-bit division: an fp32 estimate (off by
+        // at most one near a bin edge), then one exact integer correction
+        int b = (int)(128.0f * (float)tt * __frcp_rn((float)D));
+        const uint64_t num = (uint64_t)tt << 7;
+        if (b > 0 && num < (uint64_t)b * D) --b;
+        else if (num >= (uint64_t)(b + 1) * D) ++b;
         if (b > 63) b = 63;
-        const int g = G == 1 ? 0 : graph_of(vbase, G, perm[src[e]]);
-        if (local) atomicAdd(&h[g * 64 + b], 1u);
-        else atomicAdd(&hist[(int64_t)g * 64 + b], 1ull);
+        if (G == 1) {
+            atomicAdd(&h[((threadIdx.x >> 6) * kCopies + (lane & (kCopies - 1))) * kStride + b], 1u);
+        } else {
+            const int g = graph_of(vbase, G, perm[src[e]]);
+            if (local) atomicAdd(&h[g * 64 + b], 1u);
+            else atomicAdd(&hist[(int64_t)g * 64 + b], 1ull);
+        }
     }
     __syncthreads();
-    if (local)
+    if (G == 1) {
+        for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+            uint32_t c = 0;
+            for (int k = 0; k < (kThreads / 64) * kCopies; ++k) c += h[k * kStride + i];
+            if (c) atomicAdd(&hist[i], (unsigned long long)c);
+        }
+    } else if (local) {
         for (int i = threadIdx.x; i < G * 64; i += blockDim.x)
             if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+    }
 }
 
 // max degree per graph; lanes sharing lane 0's graph reduce before one atomic
