@@ -23,7 +23,9 @@
  *     says host_.  The library never allocates device memory except a small
  *     control block in mcd_ctx_create.  Calls that need scratch memory take a
  *     workspace (ws, ws_bytes) sized by the matching *_workspace_size query;
- *     a smaller workspace gives MCD_ERR_WORKSPACE.
+ *     a smaller workspace gives MCD_ERR_WORKSPACE.  Workspaces and the graph
+ *     storage buffer must start on a 256-byte boundary (the library carves
+ *     them into typed arrays); another start gives MCD_ERR_INVALID_ARG.
  *   - Work is enqueued on the context's stream.  Calls documented as
  *     "synchronous" wait for that stream before returning (they return host
  *     scalars); all others are asynchronous and their outputs are valid once

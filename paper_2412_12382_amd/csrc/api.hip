@@ -27,6 +27,11 @@ mcd_status mcd_fail(mcd_status s, const std::string& msg) {
         if (!(cond)) return mcd_fail(code, msg); \
     } while (0)
 
+// Caller buffers that the library carves into typed arrays (graph storage,
+// workspaces) must start on a 256-byte boundary; NULL passes.
+#define REQUIRE_ALIGNED(p)                                                                          \
+    REQUIRE(((uintptr_t)(p) & 255u) == 0u, MCD_ERR_INVALID_ARG, #p " must be 256-byte aligned")
+
 namespace {
 
 int id_bits(int64_t n) {
@@ -249,6 +254,8 @@ mcd_status mcd_graph_build_sizes(int64_t n_pairs, int64_t n_vertices, size_t* st
 mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst, int64_t n_pairs,
                            int64_t n_vertices, void* storage, size_t storage_bytes, void* ws,
                            size_t ws_bytes, mcd_graph** out) {
+    REQUIRE_ALIGNED(storage);
+    REQUIRE_ALIGNED(ws);
     REQUIRE(ctx && out, MCD_ERR_INVALID_ARG, "ctx or out is NULL");
     *out = nullptr;
     size_t need_st = 0, need_ws = 0;
@@ -378,6 +385,7 @@ mcd_status mcd_triangles_workspace_size(const mcd_graph* g, size_t* bytes) {
 }
 
 mcd_status mcd_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && (g->m == 0 || (t && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     size_t need = 0;
     mcd_triangles_workspace_size(g, &need);
@@ -430,6 +438,7 @@ mcd_status mcd_tune_triangles_workspace_size(const mcd_graph* g, size_t* bytes) 
 
 mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes, int32_t reps,
                               int64_t* host_best, float* host_ms) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && (g->m == 0 || (t && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(reps >= 1 && reps <= 100, MCD_ERR_RANGE, "reps must lie in [1, 100]");
     size_t need = 0;
@@ -516,6 +525,7 @@ mcd_status mcd_components_workspace_size(const mcd_graph* g, size_t* bytes) {
 
 mcd_status mcd_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels,
                           int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     size_t need = 0;
     mcd_components_workspace_size(g, &need);
@@ -560,6 +570,7 @@ mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const i
                                 int32_t n_graphs, const int64_t* vbase, const int64_t* deltas, float* w_f32,
                                 int32_t* w_i32, uint32_t* keep_bits, int64_t* n_kept, int32_t* labels,
                                 int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
     REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
@@ -585,6 +596,7 @@ mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const i
 
 mcd_status mcd_components_kept(const mcd_graph* g, const int32_t* kept_pairs, const int32_t* kept_counts,
                                int32_t* labels, int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(g->m == 0 || (kept_pairs && kept_counts), MCD_ERR_INVALID_ARG, "kept list is NULL");
     REQUIRE(ws_bytes >= mcd::cc_scratch_bytes(g), MCD_ERR_WORKSPACE, "components workspace too small");
@@ -602,6 +614,7 @@ mcd_status mcd_run_workspace_size(const mcd_graph* g, size_t* bytes) {
 
 mcd_status mcd_run(const mcd_graph* g, mcd_measure measure, mcd_rational delta, int32_t* labels,
                    int64_t* n_components, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && (g->n == 0 || (labels && ws)), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
     mcd_status st = check_delta(delta);
@@ -662,6 +675,7 @@ mcd_status mcd_sweep(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                      const mcd_rational* host_deltas, int32_t n_thresholds, int32_t n_graphs,
                      const int64_t* vbase, const int32_t* truth, mcd_sweep_stats* stats, double* ari,
                      double* modularity, double* prf, int32_t* labels, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && host_deltas && vbase && stats && ws, MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
     REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
@@ -703,6 +717,7 @@ mcd_status mcd_features_workspace_size(int32_t n_graphs, size_t* bytes) {
 
 mcd_status mcd_features(const mcd_graph* g, const int32_t* t, int32_t n_graphs, const int64_t* vbase,
                         float* x, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && vbase && x && ws && (g->m == 0 || t), MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "need n_graphs >= 1");
     REQUIRE(ws_bytes >= mcd::features_scratch_bytes(n_graphs), MCD_ERR_WORKSPACE, "features workspace too small");
@@ -761,6 +776,7 @@ mcd_status mcd_mlp_workspace_size(int32_t batch, size_t* bytes) {
 mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
                             const float* x, const float* target, int32_t batch, float* grad, float* loss,
                             void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(ctx && params && mean && std && x && target && grad && ws && batch >= 1, MCD_ERR_INVALID_ARG,
             "NULL argument or empty batch");
     REQUIRE(ws_bytes >= mcd::mlp_scratch_bytes(batch), MCD_ERR_WORKSPACE, "MLP workspace too small");
@@ -773,6 +789,7 @@ mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean
 mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
                               float lr, float weight_decay, const float* mean, const float* std, const float* x,
                               const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(ctx && params && adam_m && adam_v && mean && std && x && target && ws && batch >= 1,
             MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
     REQUIRE(step >= 1, MCD_ERR_INVALID_ARG, "Adam steps count from 1");
@@ -825,6 +842,7 @@ mcd_status mcd_percentile_workspace_size(const mcd_graph* g, size_t* bytes) {
 mcd_status mcd_percentile_threshold(const mcd_graph* g, mcd_measure measure, const int32_t* t,
                                     int64_t pct_num, int64_t pct_den, void* ws, size_t ws_bytes,
                                     mcd_rational* host_out) {
+    REQUIRE_ALIGNED(ws);
     REQUIRE(g && t && ws && host_out, MCD_ERR_INVALID_ARG, "NULL argument");
     REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
     REQUIRE(pct_den > 0 && pct_num >= 0 && pct_num <= pct_den && pct_den < ((int64_t)1 << 31),

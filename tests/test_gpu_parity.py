@@ -193,6 +193,28 @@ def test_param_validation():
     assert ei.value.status == -1
 
 
+def test_workspace_alignment_checked():
+    # a workspace or storage buffer off a 256-byte boundary is refused before
+    # any work is enqueued; the aligned buffer still works
+    from gpu_util import build
+    s, d, n = gg.rmat(10, seed=5)
+    g = build(s, d, n)
+    ws = torch.empty(M.mcd_triangles_workspace_size(g) + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(M.MCDError) as ei:
+        M.mcd_triangles(g, ws=ws[8:])
+    assert ei.value.status == -1 and "aligned" in M.mcd_last_error()
+    t = M.mcd_triangles(g, ws=ws)
+    wc = torch.empty(M.mcd_components_workspace_size(g) + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(M.MCDError):
+        M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, delta=(1, 10), ws=wc[64:])
+    st_b, ws_b = M.mcd_graph_build_sizes(len(s), n)
+    storage = torch.empty(st_b + 256, dtype=torch.uint8, device="cuda")
+    wsb = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
+    with pytest.raises(M.MCDError):
+        M.mcd_graph_build(g.ctx, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), n, storage=storage[4:],
+                          ws=wsb)
+
+
 @pytest.mark.parametrize("k", [5, 130, 700])
 def test_complete_graph_closed_form(k):
     # K_k: every edge lies in k-2 triangles (rows longer than the small LDS classes)
