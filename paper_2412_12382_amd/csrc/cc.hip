@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_cc_union(const int32_t* __restrict
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         if (keep && !((keep[e >> 5] >> (e & 31)) & 1u)) continue;
-        uf_unite_meet(parent, src[e], adj[e]);
+        uf_unite(parent, src[e], adj[e]);
     }
 }
 
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kThreads) void k_cc_union_kept(const int2* __restri
     const int2* p = kept + seg * seg_len;
     for (int32_t i = cnt - 1 - lane; i >= 0; i -= 64) {
         const int2 e = p[i];
-        uf_unite_meet(parent, e.x, e.y);
+        uf_unite(parent, e.x, e.y);
     }
 }
 

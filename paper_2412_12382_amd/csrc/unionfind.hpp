@@ -32,37 +32,17 @@ __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
     }
 }
 
-// Unite the sets of a and b: both roots found in turn, then the lower-ranked
-// hooked under the higher-ranked by compare-and-swap (a lost race finds again).
-__device__ __forceinline__ void uf_unite(int32_t* parent, int32_t a, int32_t b) {
-    for (;;) {
-        a = uf_find(parent, a);
-        b = uf_find(parent, b);
-        if (a == b) return;
-        if (a > b) {
-            const int32_t x = a;
-            a = b;
-            b = x;
-        }
-        int32_t expected = a;
-        if (__hip_atomic_compare_exchange_strong(&parent[a], &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
-            return;
-    }
-}
-
-// uf_unite for edge streams that are mostly redundant (a pruned graph's dense
-// core, walked from its high ranks): the two walks to the roots advance in
-// lockstep (their loads are issued together) with path halving, and stop as soon as
+// Unite the sets of a and b.  The two walks to the roots advance in lockstep
+// (their loads are issued together) with path halving, and stop as soon as
 // the two sides meet: equal parents, or one side's parent is the other
 // vertex.  Every parent read is an ancestor of the vertex read, so a meeting
 // proves one set; an edge whose endpoints already share a parent (most edges
 // of a dense core once it has formed) costs one round trip.  Two distinct
 // roots are joined by hooking the lower-ranked under the higher-ranked by
-// compare-and-swap; a lost race re-reads both sides.  (Measured: 1.3x faster
-// than uf_unite on the kept edges of a pruned R-MAT, 4.5x on all edges under
-// a keep mask; 6 % slower on the threshold sweep's level-by-level unions.)
-__device__ __forceinline__ void uf_unite_meet(int32_t* parent, int32_t a, int32_t b) {
+// compare-and-swap; a lost race re-reads both sides.  (Measured against two
+// finds in turn: 1.3x faster on the kept edges of a pruned R-MAT, 4.5x on all
+// edges under a keep mask, on par for the threshold sweep's level unions.)
+__device__ __forceinline__ void uf_unite(int32_t* parent, int32_t a, int32_t b) {
     int32_t pa = uf_load(&parent[a]), pb = uf_load(&parent[b]);
     for (;;) {
         if (a == b || pa == pb || pa == b || pb == a) return;

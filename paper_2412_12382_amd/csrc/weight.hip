@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             for (int r = lane; r < nq; r += 64) {
                 const int32_t e = queue[w][r];
-                uf_unite_meet(parent, src[e], adj[e]);
+                uf_unite(parent, src[e], adj[e]);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();  // reads done before the next writes
