@@ -214,8 +214,8 @@ def picker_study(M, PK, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
-              f"described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded over "
+              f"several GPUs.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

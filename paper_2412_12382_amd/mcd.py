@@ -53,7 +53,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2412_12382_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
         PP = ctypes.POINTER(ctypes.c_void_p)

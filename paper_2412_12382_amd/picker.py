@@ -70,7 +70,7 @@ def pick(g, t, picker: Picker, vbase=None, measure: int = M.MCD_SIM_TECTONIC, fa
     the training range; the sweep runs only if one is), "force" (for every
     graph) or "off".  Returns (index int32[G]: the network's grid index,
     deltas int64[G][2]: the thresholds used, labels int32[n], n_components,
-    flags int32[G]: the range guard's verdict, 1 = out of range; with "auto"
+    flags int32[G]: the range guard's decision, 1 = out of range; with "auto"
     exactly the graphs whose threshold the fallback decided)."""
     if fallback not in ("auto", "force", "off"):
         raise ValueError(f"fallback must be 'auto', 'force' or 'off', not {fallback!r}")
