@@ -188,6 +188,18 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
         delete c;
         return mcd_fail(MCD_ERR_DEVICE, "hipHostMalloc of the read-back block failed");
     }
+    bool ok = true;
+    for (int i = 0; i < 2; ++i) {
+        ok = ok && hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming) == hipSuccess;
+    }
+    ok = ok && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipFree(c->d_ctrl);
+        (void)hipHostFree(c->h_ctrl);
+        delete c;
+        return mcd_fail(MCD_ERR_DEVICE, "creating the side streams failed");
+    }
     *out = c;
     return MCD_OK;
 }
@@ -235,6 +247,12 @@ mcd_status mcd_ctx_destroy(mcd_ctx* ctx) {
     if (!ctx) return MCD_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (int i = 0; i < 2; ++i) {
+        (void)hipStreamSynchronize(ctx->side[i]);
+        (void)hipStreamDestroy(ctx->side[i]);
+        (void)hipEventDestroy(ctx->join[i]);
+    }
+    (void)hipEventDestroy(ctx->fork);
     (void)hipFree(ctx->d_ctrl);
     (void)hipHostFree(ctx->h_ctrl);
     delete ctx;

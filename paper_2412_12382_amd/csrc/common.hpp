@@ -22,6 +22,11 @@ struct mcd_ctx {
     int64_t tc_lds_max;  // longest row hashed in LDS; longer rows use binary search
     int64_t tc_packed_range;  // widest rank range (w - v - 1) of a packed LDS table
     int64_t tc_window_max;    // widest rank range of a row held as an LDS rank window
+    // side streams (default priority) and events on which the triangle
+    // count runs its work-item classes concurrently, forked from and joined
+    // back into `stream`
+    hipStream_t side[2];
+    hipEvent_t fork, join[2];
 };
 #define MCD_TC_WINDOW_LIMIT (1 << 18)
 #define MCD_TC_LDS_LIMIT 4096

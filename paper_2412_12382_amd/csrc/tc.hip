@@ -637,19 +637,32 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
                        chunk, L.cnt, L.base, L.items);
     hipLaunchKernelGGL(k_item_heads, dim3(1), dim3(64), 0, s, L.base, n, L.heads);
-    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s);
-    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s);
-    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s);
+    // The classes run on three streams at once (the context's and its two
+    // side streams, forked here and joined at the end): each kernel's tail of
+    // long items then overlaps the others' work.  The counts are integer
+    // atomics, so the result does not depend on the interleaving.
+    mcd_ctx* c = g->ctx;
+    hipStream_t s1 = c->side[0], s2 = c->side[1];
+    (void)hipEventRecord(c->fork, s);
+    (void)hipStreamWaitEvent(s1, c->fork, 0);
+    (void)hipStreamWaitEvent(s2, c->fork, 0);
+    launch_window<14, 512, 8>(g, L, 8, chunk, t, s);
+    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s1);
+    launch_window<18, 1024, 8>(g, L, 10, chunk, t, s2);
+    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s1);
+    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s2);
+    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s2);
+    launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s1);
+    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s2);
     launch_class<RowHash<13, true>, 4096, 4, 64>(g, L, 3, chunk, t, s);
-    launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
-    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
-    launch_window<14, 512, 8>(g, L, 8, chunk, t, s);
-    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s);
-    launch_window<18, 1024, 8>(g, L, 10, chunk, t, s);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
+    (void)hipEventRecord(c->join[0], s1);
+    (void)hipEventRecord(c->join[1], s2);
+    (void)hipStreamWaitEvent(s, c->join[0], 0);
+    (void)hipStreamWaitEvent(s, c->join[1], 0);
 }
 
 }  // namespace mcd
