@@ -330,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_tc_window_s(const Item* __restrict__ all
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ adj,
                                                     const int2* __restrict__ in_ea,
-                                                    int32_t* __restrict__ t) {
+                                                    int32_t* __restrict__ t, int ipart, int nparts) {
     constexpr int NW = (1 << LOG2R) / 32;
     constexpr int MAXB = 4096;
     constexpr int NWAVES = NT / 64;
@@ -343,7 +343,8 @@ __global__ __launch_bounds__(NT) void k_tc_window_s(const Item* __restrict__ all
     const Item* __restrict__ items = all_items + heads[2 * cls];
     const int64_t n_items = heads[2 * cls + 1];
 
-    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    // this launch takes the items it = ipart (mod nparts) of the class
+    for (int64_t it = (int64_t)blockIdx.x * nparts + ipart; it < n_items; it += (int64_t)gridDim.x * nparts) {
         const Item I = items[it];
         const int32_t v = I.v;
         const int32_t b0 = (int32_t)off[v];
@@ -611,12 +612,14 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
                        L.items, L.heads, c, g->off, g->adj, g->in_ea, t);
 }
 
+// ipart / nparts: this launch takes every nparts-th item of the class
 template <int LOG2R, int NT, int D>
-void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
+void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
+                   int ipart = 0, int nparts = 1) {
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = cap_items < 16384 ? cap_items : 16384;
     hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads, c,
-                       g->off, g->adj, g->in_ea, t);
+                       g->off, g->adj, g->in_ea, t, ipart, nparts);
 }
 
 }  // namespace
@@ -646,8 +649,11 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     (void)hipEventRecord(c->fork, s);
     (void)hipStreamWaitEvent(s1, c->fork, 0);
     (void)hipStreamWaitEvent(s2, c->fork, 0);
-    launch_window<14, 512, 8>(g, L, 8, chunk, t, s);
-    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s1);
+    // the two largest classes in two halves each
+    launch_window<14, 512, 8>(g, L, 8, chunk, t, s, 0, 2);
+    launch_window<14, 512, 8>(g, L, 8, chunk, t, s2, 1, 2);
+    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s1, 0, 2);
+    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s, 1, 2);
     launch_window<18, 1024, 8>(g, L, 10, chunk, t, s2);
     launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s1);
     launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s2);
