@@ -4,7 +4,8 @@ Runs, on R-MAT of the given scale: one calibration kernel of known traffic
 (an elementwise int32 add over `--copy-mib` MiB: that many bytes read and
 written), the graph build, the triangle count, the one-pass weights + prune +
 components at num/den (default 9/900) and the 16-point sweep, each once, and
-prints what it launched.  Used as
+prints what it launched; with `--k4` also the 4-clique participation count.
+Used as
     rocprofv3 --kernel-trace --stats -- python3 -m paper_2412_12382_amd.profile_run
     rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2412_12382_amd.profile_run
     rocprofv3 --pmc WRITE_SIZE -- python3 -m paper_2412_12382_amd.profile_run
@@ -22,6 +23,8 @@ if ROOT not in sys.path:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--scale", type=int, default=26)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--k4", action="store_true", help="also count 4-cliques per edge")
     ap.add_argument("--copy-mib", type=int, default=2048)
     ap.add_argument("--num", type=int, default=9, help="prune threshold numerator")
     ap.add_argument("--den", type=int, default=900, help="prune threshold denominator")
@@ -39,7 +42,7 @@ def main():
     torch.cuda.synchronize()
     print(f"calibration add: {args.copy_mib} MiB read, {args.copy_mib} MiB written", flush=True)
     del a, b
-    s, d, n = gg.rmat(args.scale, seed=3)
+    s, d, n = gg.rmat(args.scale, seed=args.seed)
     src, dst = torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev)
     del s, d
     ctx = M.mcd_ctx_create(0)
@@ -48,6 +51,8 @@ def main():
     r = M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, delta=(args.num, args.den))
     ncc, nk = r["n_components"], r["n_kept"]
     M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, [(k, 50) for k in range(16)])
+    if args.k4:
+        M.mcd_k4(g)
     torch.cuda.synchronize()
     print(json.dumps(dict(scale=args.scale, n=n, m=g.m, kept=int(nk.item()), components=int(ncc.item()))),
           flush=True)

@@ -275,7 +275,7 @@ def test_prop1_on_the_gpu():
         assert torch.equal(kj[:words], kt[:words]) and int(nj.item()) == int(nt.item())
 
 
-@pytest.mark.parametrize("case", ["c1", "rmat12", "rmat14", "k9", "random"])
+@pytest.mark.parametrize("case", ["c1", "rmat12", "rmat14", "rmat16", "k9", "random", "k300_rmat12"])
 def test_k4_participation_and_prune(case):
     from gpu_util import build, canonical_order, unpack_bits
     if case == "c1":
@@ -283,6 +283,18 @@ def test_k4_participation_and_prune(case):
         s, d, n = c1["src"], c1["dst"], c1["n"]
     elif case.startswith("rmat"):
         s, d, n = gg.rmat(int(case[4:]), seed=70)
+    elif case == "k300_rmat12":
+        # a 300-clique (rows of up to 299 edges: the LDS path) beside an
+        # R-MAT graph, joined by random cross pairs
+        k = 300
+        pairs = [(i, j) for i in range(k) for j in range(i + 1, k)]
+        s2, d2, n2 = gg.rmat(12, seed=5)
+        rng = np.random.default_rng(3)
+        s = np.concatenate([np.array([p[0] for p in pairs], np.int32), s2 + k,
+                            rng.integers(0, k, 3000).astype(np.int32)])
+        d = np.concatenate([np.array([p[1] for p in pairs], np.int32), d2 + k,
+                            (k + rng.integers(0, n2, 3000)).astype(np.int32)])
+        n = k + n2
     elif case == "k9":
         pairs = [(i, j) for i in range(9) for j in range(i + 1, 9)]
         s = np.array([p[0] for p in pairs], np.int32)
