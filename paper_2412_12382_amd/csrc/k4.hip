@@ -4,30 +4,47 @@
 // On the degree-ordered orientation a 4-clique {a < b < c < d} is found once,
 // from its lowest edge a->b: c and d lie in L = N+(a) n N+(b) (both rows
 // sorted, so L is the part of N+(a) after b that also lies in N+(b)), and the
-// clique closes when d lies in N+(c).  One wave takes one edge at a time and
-// tests every element of the suffix of row a against row b by binary search;
-// then for every c in L it tests the later elements d of L against row c.  A
-// clique credits its six edges: a->b once per wave (a single add), a->c and
-// b->c once per c (summed over its hits), a->d, b->d and c->d per hit.
+// clique closes when d lies in N+(c).  Per edge a->b: every element of the
+// suffix of row a after b is tested against row b by binary search and the
+// hits are gathered into LDS (value, position in row a, position in row b,
+// the row offsets of c); then the nL(nL-1)/2 pairs c < d of L are spread
+// over the lanes, one pair per lane, and d is searched in row c.
+//
+// Credits: a clique credits its six edges.  c->d is a global atomic at the
+// position the search found.  The others are summed on chip first: a->x and
+// b->x, for x in L, both gain the degree of x in the subgraph that L induces
+// (counted in LDS, written once per element), and a->b gains that subgraph's
+// number of edges (one add per wave).
 //
 // |L| is at most min(suffix length, outd(b)), known from the offsets alone:
-// an edge whose bound is below 2 closes no clique and is skipped.  The suffix
-// length sorts the rest into two kernels.  Up to 64 * kRegChunks elements the
-// suffix stays in registers, lane i holding element i of each 64-element
-// chunk with a ballot mask of the hits, so that kernel needs no LDS and runs
-// at full occupancy.  Longer suffixes (hub rows) gather L into LDS sized by
-// the graph's longest row.
+// an edge whose bound is below 2 closes no clique and is skipped.  Edges are
+// scanned 64 (or 256) at a time and only the candidates are worked on.  A
+// suffix of at most kWaveSuffix elements is one wave's work; longer ones (hub
+// rows) take a workgroup of four waves that share L in LDS sized by the
+// graph's longest row.
 #include "common.hpp"
 
 namespace mcd {
 namespace {
 
-constexpr int kRegChunks = 4;     // register path: suffixes of at most 256 elements
-constexpr int kRegThreads = 256;  // 4 waves per workgroup
-constexpr int kRegSuffix = 64 * kRegChunks;
+constexpr int kWaveSuffix = 256;   // longest suffix one wave takes
+constexpr int kWaveBlock = 4;      // waves per workgroup of the wave kernel
+constexpr int kBlockThreads = 256; // workgroup of the long-suffix kernel
 
 __device__ __forceinline__ void add_relaxed(int32_t* p, int32_t x) {
     __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_lds(int32_t* p) {
+    __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// LDS written by other lanes of this wave: order the writes before the reads
+// (one wave: no barrier needed)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // position of x in the sorted slice adj[lo, hi), or -1
@@ -42,148 +59,225 @@ __device__ __forceinline__ int64_t find_sorted(const int32_t* __restrict__ adj, 
     return -1;
 }
 
-// upper bound of |L| for edge e = a->b
-__device__ __forceinline__ int64_t common_bound(int64_t e, int64_t a1, int64_t b0, int64_t b1) {
-    const int64_t suf = a1 - e - 1;
-    const int64_t ob = b1 - b0;
-    return suf < ob ? suf : ob;
+// pairs (x, y), x < y < nL, numbered row by row: row x starts at
+// x (2 nL - x - 1) / 2
+__device__ __forceinline__ int pair_row_start(int x, int nL) { return (x * (2 * nL - x - 1)) >> 1; }
+
+__device__ __forceinline__ void pair_of(int p, int nL, int& x, int& y) {
+    // the row from the quadratic's smaller root, then exact integer correction
+    const float bb = (float)(2 * nL - 1);
+    int r = (int)((bb - sqrtf(fmaxf(bb * bb - 8.0f * (float)p, 0.0f))) * 0.5f);
+    r = r < 0 ? 0 : (r > nL - 2 ? nL - 2 : r);
+    while (r > 0 && pair_row_start(r, nL) > p) --r;
+    while (r < nL - 2 && pair_row_start(r + 1, nL) <= p) ++r;
+    x = r;
+    y = p - pair_row_start(r, nL) + r + 1;
 }
 
-__global__ __launch_bounds__(kRegThreads) void k_k4_reg(const int32_t* __restrict__ src,
-                                                        const int32_t* __restrict__ adj,
-                                                        const int64_t* __restrict__ off, int64_t m,
-                                                        int32_t* __restrict__ k4) {
+// whether edge e (row a ending at a1, head b with row [b0, b1)) goes to the
+// wave kernel (LONG = false) or the workgroup kernel (LONG = true)
+template <bool LONG>
+__device__ __forceinline__ bool k4_candidate(int64_t e, int64_t a1, int64_t b0, int64_t b1) {
+    const int64_t suf = a1 - e - 1;
+    const int64_t bound = suf < b1 - b0 ? suf : b1 - b0;
+    return bound >= 2 && (LONG ? suf > kWaveSuffix : suf <= kWaveSuffix);
+}
+
+__global__ __launch_bounds__(64 * kWaveBlock) void k_k4_wave(const int32_t* __restrict__ src,
+                                                            const int32_t* __restrict__ adj,
+                                                            const int64_t* __restrict__ off, int64_t m,
+                                                            int32_t* __restrict__ k4) {
+    __shared__ int32_t sv[kWaveBlock][kWaveSuffix], spa[kWaveBlock][kWaveSuffix], spb[kWaveBlock][kWaveSuffix];
+    __shared__ int32_t scnt[kWaveBlock][kWaveSuffix], sc0[kWaveBlock][kWaveSuffix], sc1[kWaveBlock][kWaveSuffix];
     const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (kRegThreads / 64);
-    const int64_t w0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kRegThreads / 64) + (threadIdx.x >> 6)));
-    for (int64_t e = w0; e < m; e += nw) {
-        const int32_t a = src[e], b = adj[e];
-        const int64_t a1 = off[a + 1];
-        const int64_t b0 = off[b], b1 = off[b + 1];
-        if (a1 - e - 1 > kRegSuffix || common_bound(e, a1, b0, b1) < 2) continue;
-        // L: hits of the suffix of row a (after b) in row b, kept in place
-        int32_t cv[kRegChunks], pb[kRegChunks];
-        uint64_t hm[kRegChunks];
-        int nL = 0;
-#pragma unroll
-        for (int r = 0; r < kRegChunks; ++r) {
-            cv[r] = 0;
-            pb[r] = -1;
-            hm[r] = 0;
-            const int64_t i0 = e + 1 + 64 * r;
-            if (i0 < a1) {
+    const int w = threadIdx.x >> 6;
+    int32_t *lv = sv[w], *lpa = spa[w], *lpb = spb[w], *lcnt = scnt[w], *lc0 = sc0[w], *lc1 = sc1[w];
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t nchunks = (m + 63) >> 6;
+    const int64_t stride = (int64_t)gridDim.x * kWaveBlock;
+    for (int64_t ch = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWaveBlock + w)); ch < nchunks;
+         ch += stride) {
+        // the chunk's candidates, one edge per lane
+        const int64_t el = (ch << 6) + lane;
+        bool cand = false;
+        if (el < m) {
+            const int64_t a1 = off[src[el] + 1];
+            const int32_t b = adj[el];
+            cand = k4_candidate<false>(el, a1, off[b], off[b + 1]);
+        }
+        uint64_t todo = __ballot(cand);
+        while (todo) {
+            const int64_t e = (ch << 6) + __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int32_t a = src[e], b = adj[e];
+            const int64_t a1 = off[a + 1];
+            const int64_t b0 = off[b], b1 = off[b + 1];
+            // L: the suffix's hits in row b, at most kWaveSuffix of them
+            int nL = 0;
+            for (int64_t i0 = e + 1; i0 < a1; i0 += 64) {
                 const int64_t i = i0 + lane;
+                int64_t pb = -1;
+                int32_t c = 0;
                 if (i < a1) {
-                    cv[r] = adj[i];
-                    pb[r] = (int32_t)find_sorted(adj, b0, b1, cv[r]);
+                    c = adj[i];
+                    pb = find_sorted(adj, b0, b1, c);
                 }
-                hm[r] = __ballot(pb[r] >= 0);
-                nL += __popcll(hm[r]);
+                const bool hit = pb >= 0;
+                const uint64_t bal = __ballot(hit);
+                if (hit) {
+                    const int slot = nL + __popcll(bal & below);
+                    lv[slot] = c;
+                    lpa[slot] = (int32_t)i;  // positions < m < 2^31
+                    lpb[slot] = (int32_t)pb;
+                    lcnt[slot] = 0;
+                    lc0[slot] = (int32_t)off[c];
+                    lc1[slot] = (int32_t)off[c + 1];
+                }
+                nL += __popcll(bal);
             }
-        }
-        if (nL < 2) continue;
-        int32_t cliques = 0;
-#pragma unroll
-        for (int xr = 0; xr < kRegChunks; ++xr) {
-            uint64_t bits = hm[xr];
-            while (bits) {
-                const int xl = __builtin_ctzll(bits);
-                bits &= bits - 1;
-                const int32_t c = __builtin_amdgcn_readlane(cv[xr], xl);
-                const int32_t pbc = __builtin_amdgcn_readlane(pb[xr], xl);
-                const int64_t c0 = off[c], c1 = off[c + 1];
-                uint32_t hits = 0;
-#pragma unroll
-                for (int yr = xr; yr < kRegChunks; ++yr) {
-                    // the hits after c: later lanes of c's chunk, all of later chunks
-                    const uint64_t cand = yr == xr ? (hm[yr] & ~((2ull << xl) - 1ull)) : hm[yr];
-                    if (cand == 0) continue;
-                    bool hit = false;
-                    if ((cand >> lane) & 1ull) {
-                        const int64_t pcd = find_sorted(adj, c0, c1, cv[yr]);
-                        if (pcd >= 0) {
-                            hit = true;
-                            add_relaxed(&k4[e + 1 + 64 * yr + lane], 1);  // a->d
-                            add_relaxed(&k4[pb[yr]], 1);                 // b->d
-                            add_relaxed(&k4[pcd], 1);                    // c->d
-                        }
+            if (nL < 2) continue;
+            wave_lds_sync();
+            const int P = nL * (nL - 1) / 2;
+            int32_t total = 0;
+            for (int p0 = 0; p0 < P; p0 += 64) {
+                const int p = p0 + lane;
+                bool hit = false;
+                if (p < P) {
+                    int x, y;
+                    pair_of(p, nL, x, y);
+                    const int64_t pcd = find_sorted(adj, lc0[x], lc1[x], lv[y]);
+                    if (pcd >= 0) {
+                        hit = true;
+                        add_relaxed(&k4[pcd], 1);  // c->d
+                        add_lds(&lcnt[x]);
+                        add_lds(&lcnt[y]);
                     }
-                    hits += (uint32_t)__popcll(__ballot(hit));
                 }
-                if (lane == 0 && hits) {
-                    add_relaxed(&k4[e + 1 + 64 * xr + xl], (int32_t)hits);  // a->c
-                    add_relaxed(&k4[pbc], (int32_t)hits);                  // b->c
-                }
-                cliques += (int32_t)hits;
+                total += __popcll(__ballot(hit));
             }
+            wave_lds_sync();
+            for (int i = lane; i < nL; i += 64) {
+                const int32_t k = lcnt[i];
+                if (k) {
+                    add_relaxed(&k4[lpa[i]], k);  // a->x
+                    add_relaxed(&k4[lpb[i]], k);  // b->x
+                }
+            }
+            if (lane == 0 && total) add_relaxed(&k4[e], total);  // a->b
+            wave_lds_sync();  // reads done before the next edge's writes
         }
-        if (lane == 0 && cliques) add_relaxed(&k4[e], cliques);  // a->b
     }
 }
 
-// edges whose suffix is longer than the register path holds: L gathered into LDS (value,
-// position in row a, position in row b), cap entries each
-__global__ __launch_bounds__(64) void k_k4_lds(const int32_t* __restrict__ src, const int32_t* __restrict__ adj,
-                                               const int64_t* __restrict__ off, int64_t m, int cap,
-                                               int32_t* __restrict__ k4) {
+// suffixes longer than one wave takes: four waves share L (cap entries per
+// array; with ROWS the row offsets of every c are kept beside it)
+template <bool ROWS>
+__global__ __launch_bounds__(kBlockThreads) void k_k4_block(const int32_t* __restrict__ src,
+                                                           const int32_t* __restrict__ adj,
+                                                           const int64_t* __restrict__ off, int64_t m, int cap,
+                                                           int32_t* __restrict__ k4) {
     extern __shared__ int32_t lds[];
-    int32_t* lv = lds;             // elements c of L
-    int32_t* lpa = lds + cap;      // edge a->c
-    int32_t* lpb = lds + 2 * cap;  // edge b->c
-    const int lane = threadIdx.x;
+    __shared__ uint64_t wmask[kBlockThreads / 64];
+    __shared__ int32_t wcount[kBlockThreads / 64];
+    int32_t *lv = lds, *lpa = lds + cap, *lpb = lds + 2 * cap, *lcnt = lds + 3 * cap;
+    int32_t *lc0 = lds + 4 * cap, *lc1 = lds + 5 * cap;  // ROWS only
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    constexpr int NW = kBlockThreads / 64;
     const uint64_t below = (1ull << lane) - 1ull;
-    for (int64_t e = blockIdx.x; e < m; e += gridDim.x) {
-        const int32_t a = src[e], b = adj[e];
-        const int64_t a1 = off[a + 1];
-        const int64_t b0 = off[b], b1 = off[b + 1];
-        if (a1 - e - 1 <= kRegSuffix || common_bound(e, a1, b0, b1) < 2) continue;
-        int nL = 0;
-        for (int64_t i0 = e + 1; i0 < a1; i0 += 64) {
-            const int64_t i = i0 + lane;
-            int64_t pbi = -1;
-            int32_t c = 0;
-            if (i < a1) {
-                c = adj[i];
-                pbi = find_sorted(adj, b0, b1, c);
-            }
-            const bool hit = pbi >= 0;
-            const uint64_t bal = __ballot(hit);
-            if (hit) {
-                const int slot = nL + __popcll(bal & below);
-                lv[slot] = c;
-                lpa[slot] = (int32_t)i;
-                lpb[slot] = (int32_t)pbi;
-            }
-            nL += __popcll(bal);
+    const int64_t nchunks = (m + kBlockThreads - 1) / kBlockThreads;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t el = ch * kBlockThreads + tid;
+        bool cand = false;
+        if (el < m) {
+            const int64_t a1 = off[src[el] + 1];
+            const int32_t b = adj[el];
+            cand = k4_candidate<true>(el, a1, off[b], off[b + 1]);
         }
+        const uint64_t bal0 = __ballot(cand);
+        if (lane == 0) wmask[w] = bal0;
         __syncthreads();
-        int32_t cliques = 0;
-        for (int x = 0; x + 1 < nL; ++x) {
-            const int32_t c = lv[x];
-            const int64_t c0 = off[c], c1 = off[c + 1];
-            uint32_t hits = 0;
-            for (int y0 = x + 1; y0 < nL; y0 += 64) {
-                const int y = y0 + lane;
-                bool hit = false;
-                if (y < nL) {
-                    const int64_t pcd = find_sorted(adj, c0, c1, lv[y]);
-                    if (pcd >= 0) {
-                        hit = true;
-                        add_relaxed(&k4[lpa[y]], 1);  // a->d
-                        add_relaxed(&k4[lpb[y]], 1);  // b->d
-                        add_relaxed(&k4[pcd], 1);     // c->d
+        for (int ww = 0; ww < NW; ++ww) {
+            uint64_t todo = wmask[ww];
+            while (todo) {
+                const int64_t e = ch * kBlockThreads + 64 * ww + __builtin_ctzll(todo);
+                todo &= todo - 1;
+                const int32_t a = src[e], b = adj[e];
+                const int64_t a1 = off[a + 1];
+                const int64_t b0 = off[b], b1 = off[b + 1];
+                int nL = 0;
+                for (int64_t i0 = e + 1; i0 < a1; i0 += kBlockThreads) {
+                    const int64_t i = i0 + tid;
+                    int64_t pb = -1;
+                    int32_t c = 0;
+                    if (i < a1) {
+                        c = adj[i];
+                        pb = find_sorted(adj, b0, b1, c);
+                    }
+                    const bool hit = pb >= 0;
+                    const uint64_t bal = __ballot(hit);
+                    if (lane == 0) wcount[w] = __popcll(bal);
+                    __syncthreads();
+                    int base = nL, add = 0;
+                    for (int k = 0; k < NW; ++k) {
+                        const int ck = wcount[k];
+                        base += k < w ? ck : 0;
+                        add += ck;
+                    }
+                    if (hit) {
+                        const int slot = base + __popcll(bal & below);
+                        lv[slot] = c;
+                        lpa[slot] = (int32_t)i;
+                        lpb[slot] = (int32_t)pb;
+                        lcnt[slot] = 0;
+                        if (ROWS) {
+                            lc0[slot] = (int32_t)off[c];
+                            lc1[slot] = (int32_t)off[c + 1];
+                        }
+                    }
+                    nL += add;
+                    __syncthreads();  // entries written, wcount free again
+                }
+                if (nL < 2) continue;  // workgroup-uniform
+                const int P = nL * (nL - 1) / 2;
+                int32_t total = 0;
+                for (int p0 = 0; p0 < P; p0 += kBlockThreads) {
+                    const int p = p0 + tid;
+                    bool hit = false;
+                    if (p < P) {
+                        int x, y;
+                        pair_of(p, nL, x, y);
+                        int64_t c0, c1;
+                        if (ROWS) {
+                            c0 = lc0[x];
+                            c1 = lc1[x];
+                        } else {
+                            const int32_t c = lv[x];
+                            c0 = off[c];
+                            c1 = off[c + 1];
+                        }
+                        const int64_t pcd = find_sorted(adj, c0, c1, lv[y]);
+                        if (pcd >= 0) {
+                            hit = true;
+                            add_relaxed(&k4[pcd], 1);  // c->d
+                            add_lds(&lcnt[x]);
+                            add_lds(&lcnt[y]);
+                        }
+                    }
+                    total += __popcll(__ballot(hit));
+                }
+                if (lane == 0 && total) add_relaxed(&k4[e], total);  // a->b, one add per wave
+                __syncthreads();
+                for (int i = tid; i < nL; i += kBlockThreads) {
+                    const int32_t k = lcnt[i];
+                    if (k) {
+                        add_relaxed(&k4[lpa[i]], k);  // a->x
+                        add_relaxed(&k4[lpb[i]], k);  // b->x
                     }
                 }
-                hits += (uint32_t)__popcll(__ballot(hit));
+                __syncthreads();  // reads done before the next edge's writes
             }
-            if (lane == 0 && hits) {
-                add_relaxed(&k4[lpa[x]], (int32_t)hits);  // a->c
-                add_relaxed(&k4[lpb[x]], (int32_t)hits);  // b->c
-            }
-            cliques += (int32_t)hits;
         }
-        if (lane == 0 && cliques) add_relaxed(&k4[e], cliques);
-        __syncthreads();
+        __syncthreads();  // wmask read by every wave before the next chunk writes it
     }
 }
 
@@ -192,16 +286,24 @@ __global__ __launch_bounds__(64) void k_k4_lds(const int32_t* __restrict__ src, 
 void launch_k4(const mcd_graph* g, int32_t* k4, hipStream_t s) {
     fill_i32(k4, g->m, 0, s);
     if (g->m <= 0) return;
-    // the LDS path only has work when some row is longer than the register path's suffix
-    if (g->max_outdeg > kRegSuffix) {
-        const int cap = (g->max_outdeg + 63) & ~63;
-        const int64_t blocks = g->m < 16384 ? g->m : 16384;
-        hipLaunchKernelGGL(k_k4_lds, dim3((unsigned)blocks), dim3(64), (size_t)cap * 3 * sizeof(int32_t), s,
-                           g->src, g->adj, g->off, g->m, cap, k4);
+    // |L| <= outd(b) <= the longest row; the workgroup kernel only has work
+    // when some row is longer than one wave's suffix
+    if (g->max_outdeg > kWaveSuffix) {
+        const int cap = (g->max_outdeg + 63) & ~63;  // <= 4096
+        const int64_t nch = (g->m + kBlockThreads - 1) / kBlockThreads;
+        const unsigned blocks = (unsigned)(nch < 8192 ? nch : 8192);
+        const bool rows = (size_t)cap * 6 * sizeof(int32_t) <= 65536;
+        if (rows)
+            hipLaunchKernelGGL(k_k4_block<true>, dim3(blocks), dim3(kBlockThreads),
+                               (size_t)cap * 6 * sizeof(int32_t), s, g->src, g->adj, g->off, g->m, cap, k4);
+        else
+            hipLaunchKernelGGL(k_k4_block<false>, dim3(blocks), dim3(kBlockThreads),
+                               (size_t)cap * 4 * sizeof(int32_t), s, g->src, g->adj, g->off, g->m, cap, k4);
     }
-    const int64_t waves = g->m < (int64_t)1 << 16 ? g->m : (int64_t)1 << 16;
-    const int64_t blocks = (waves + kRegThreads / 64 - 1) / (kRegThreads / 64);
-    hipLaunchKernelGGL(k_k4_reg, dim3((unsigned)blocks), dim3(kRegThreads), 0, s, g->src, g->adj, g->off, g->m, k4);
+    const int64_t nch = (g->m + 63) >> 6;
+    const int64_t waves = nch < ((int64_t)1 << 16) ? nch : ((int64_t)1 << 16);
+    const unsigned blocks = (unsigned)((waves + kWaveBlock - 1) / kWaveBlock);
+    hipLaunchKernelGGL(k_k4_wave, dim3(blocks), dim3(64 * kWaveBlock), 0, s, g->src, g->adj, g->off, g->m, k4);
 }
 
 }  // namespace mcd
