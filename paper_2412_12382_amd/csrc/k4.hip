@@ -18,7 +18,8 @@
 //
 // |L| is at most min(suffix length, outd(b)), known from the offsets alone:
 // an edge whose bound is below 2 closes no clique and is skipped.  Edges are
-// scanned 64 (or 256) at a time and only the candidates are worked on.  A
+// dealt round-robin to the waves (or workgroups), which test 64 (or 256) of
+// theirs at a time and work only on the candidates.  A
 // suffix of at most kWaveSuffix elements is one wave's work; longer ones (hub
 // rows) take a workgroup of four waves that share L in LDS sized by the
 // graph's longest row.
@@ -93,12 +94,13 @@ __global__ __launch_bounds__(64 * kWaveBlock) void k_k4_wave(const int32_t* __re
     const int w = threadIdx.x >> 6;
     int32_t *lv = sv[w], *lpa = spa[w], *lpb = spb[w], *lcnt = scnt[w], *lc0 = sc0[w], *lc1 = sc1[w];
     const uint64_t below = (1ull << lane) - 1ull;
-    const int64_t nchunks = (m + 63) >> 6;
-    const int64_t stride = (int64_t)gridDim.x * kWaveBlock;
-    for (int64_t ch = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWaveBlock + w)); ch < nchunks;
-         ch += stride) {
-        // the chunk's candidates, one edge per lane
-        const int64_t el = (ch << 6) + lane;
+    // edges interleaved over the waves (edge e to wave e mod W): the heavy
+    // edges of a hub row spread over many waves
+    const int64_t W = (int64_t)gridDim.x * kWaveBlock;
+    const int64_t wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWaveBlock + w));
+    for (int64_t r0 = 0; wid + r0 * W < m; r0 += 64) {
+        // 64 of this wave's edges, one per lane
+        const int64_t el = wid + (r0 + lane) * W;
         bool cand = false;
         if (el < m) {
             const int64_t a1 = off[src[el] + 1];
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(64 * kWaveBlock) void k_k4_wave(const int32_t* __re
         }
         uint64_t todo = __ballot(cand);
         while (todo) {
-            const int64_t e = (ch << 6) + __builtin_ctzll(todo);
+            const int64_t e = wid + (r0 + __builtin_ctzll(todo)) * W;
             todo &= todo - 1;
             const int32_t a = src[e], b = adj[e];
             const int64_t a1 = off[a + 1];
@@ -184,9 +186,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_k4_block(const int32_t* __res
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     constexpr int NW = kBlockThreads / 64;
     const uint64_t below = (1ull << lane) - 1ull;
-    const int64_t nchunks = (m + kBlockThreads - 1) / kBlockThreads;
-    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int64_t el = ch * kBlockThreads + tid;
+    // edges interleaved over the workgroups (edge e to workgroup e mod G)
+    const int64_t G = gridDim.x;
+    for (int64_t r0 = 0; blockIdx.x + r0 * G < m; r0 += kBlockThreads) {
+        const int64_t el = blockIdx.x + (r0 + tid) * G;
         bool cand = false;
         if (el < m) {
             const int64_t a1 = off[src[el] + 1];
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_k4_block(const int32_t* __res
         for (int ww = 0; ww < NW; ++ww) {
             uint64_t todo = wmask[ww];
             while (todo) {
-                const int64_t e = ch * kBlockThreads + 64 * ww + __builtin_ctzll(todo);
+                const int64_t e = blockIdx.x + (r0 + 64 * ww + __builtin_ctzll(todo)) * G;
                 todo &= todo - 1;
                 const int32_t a = src[e], b = adj[e];
                 const int64_t a1 = off[a + 1];
@@ -290,8 +293,7 @@ void launch_k4(const mcd_graph* g, int32_t* k4, hipStream_t s) {
     // when some row is longer than one wave's suffix
     if (g->max_outdeg > kWaveSuffix) {
         const int cap = (g->max_outdeg + 63) & ~63;  // <= 4096
-        const int64_t nch = (g->m + kBlockThreads - 1) / kBlockThreads;
-        const unsigned blocks = (unsigned)(nch < 8192 ? nch : 8192);
+        const unsigned blocks = (unsigned)(g->m < 8192 ? g->m : 8192);
         const bool rows = (size_t)cap * 6 * sizeof(int32_t) <= 65536;
         if (rows)
             hipLaunchKernelGGL(k_k4_block<true>, dim3(blocks), dim3(kBlockThreads),
@@ -300,8 +302,7 @@ void launch_k4(const mcd_graph* g, int32_t* k4, hipStream_t s) {
             hipLaunchKernelGGL(k_k4_block<false>, dim3(blocks), dim3(kBlockThreads),
                                (size_t)cap * 4 * sizeof(int32_t), s, g->src, g->adj, g->off, g->m, cap, k4);
     }
-    const int64_t nch = (g->m + 63) >> 6;
-    const int64_t waves = nch < ((int64_t)1 << 16) ? nch : ((int64_t)1 << 16);
+    const int64_t waves = g->m < ((int64_t)1 << 16) ? g->m : ((int64_t)1 << 16);
     const unsigned blocks = (unsigned)((waves + kWaveBlock - 1) / kWaveBlock);
     hipLaunchKernelGGL(k_k4_wave, dim3(blocks), dim3(64 * kWaveBlock), 0, s, g->src, g->adj, g->off, g->m, k4);
 }
