@@ -290,21 +290,32 @@ void launch_k4(const mcd_graph* g, int32_t* k4, hipStream_t s) {
     fill_i32(k4, g->m, 0, s);
     if (g->m <= 0) return;
     // |L| <= outd(b) <= the longest row; the workgroup kernel only has work
-    // when some row is longer than one wave's suffix
-    if (g->max_outdeg > kWaveSuffix) {
+    // when some row is longer than one wave's suffix.  It runs beside the
+    // wave kernel on a side stream of the context (forked from and joined
+    // back into s), so that each fills the other's tail
+    mcd_ctx* c = g->ctx;
+    const bool two = g->max_outdeg > kWaveSuffix;
+    if (two) {
+        hipStream_t s1 = c->side[0];
+        (void)hipEventRecord(c->fork, s);
+        (void)hipStreamWaitEvent(s1, c->fork, 0);
         const int cap = (g->max_outdeg + 63) & ~63;  // <= 4096
         const unsigned blocks = (unsigned)(g->m < 8192 ? g->m : 8192);
         const bool rows = (size_t)cap * 6 * sizeof(int32_t) <= 65536;
         if (rows)
             hipLaunchKernelGGL(k_k4_block<true>, dim3(blocks), dim3(kBlockThreads),
-                               (size_t)cap * 6 * sizeof(int32_t), s, g->src, g->adj, g->off, g->m, cap, k4);
+                               (size_t)cap * 6 * sizeof(int32_t), s1, g->src, g->adj, g->off, g->m, cap, k4);
         else
             hipLaunchKernelGGL(k_k4_block<false>, dim3(blocks), dim3(kBlockThreads),
-                               (size_t)cap * 4 * sizeof(int32_t), s, g->src, g->adj, g->off, g->m, cap, k4);
+                               (size_t)cap * 4 * sizeof(int32_t), s1, g->src, g->adj, g->off, g->m, cap, k4);
     }
     const int64_t waves = g->m < ((int64_t)1 << 16) ? g->m : ((int64_t)1 << 16);
     const unsigned blocks = (unsigned)((waves + kWaveBlock - 1) / kWaveBlock);
     hipLaunchKernelGGL(k_k4_wave, dim3(blocks), dim3(64 * kWaveBlock), 0, s, g->src, g->adj, g->off, g->m, k4);
+    if (two) {
+        (void)hipEventRecord(c->join[0], c->side[0]);
+        (void)hipStreamWaitEvent(s, c->join[0], 0);
+    }
 }
 
 }  // namespace mcd
