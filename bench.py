@@ -211,6 +211,95 @@ def picker_study(M, PK, dev):
     return model, res
 
 
+def _time_ms(fn, reps=5):
+    """Median of reps runs after one warm-up, by events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return sorted(out)[len(out) // 2]
+
+
+def next_rows_study(M, PK, model, dev):
+    """The rows past the headline path, measured: the picker, the sweep with
+    modularity and Jaccard-matched F1, and 4-clique participation on the
+    degree-corrected SBM (n = 10^6, planted communities); 4-cliques also on
+    R-MAT scale 20."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = M.mcd_ctx_create(0)
+    res = {}
+    c = gg.dcsbm()
+    n = c["n"]
+    g = M.mcd_graph_build(ctx, cu(c["src"]), cu(c["dst"]), n)
+    vb = torch.tensor([0, n], dtype=torch.int64, device=dev)
+    truth = cu(c["truth"].astype(np.int32))
+    t = M.mcd_triangles(g)
+    ws = torch.empty(M.mcd_sweep_workspace_size(g, 1, PK.GRID_K, True), dtype=torch.uint8, device=dev)
+    stats, ari, _, q, prf = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vb, truth=truth, ws=ws,
+                                        want_modularity=True, want_prf=True)
+    rule_idx, _ = M.mcd_sweep_rule(ctx, PK.GRID, stats, q, vbase=vb)
+    A, Q, F = ari.cpu().numpy()[0], q.cpu().numpy()[0], prf.cpu().numpy()[0]
+    ri = int(rule_idx.item())
+    d3 = dict(workload=f"DC-SBM n={n}, m={g.m} (degree exponent 2.5, mean degree 20, planted communities)",
+              ari_best_swept=float(A.max()), best_index=int(A.argmax()), ari_rule_of_thumb=float(A[ri]),
+              rule_index=ri, f1_best=float(F[:, 2].max()), f1_at_rule=float(F[ri, 2]),
+              modularity_at_rule=float(Q[ri]))
+    if model is not None:
+        index, _, _, _, flags = PK.pick(g, t, model, vb)
+        out = bool(flags.item())
+        pi = ri if out else int(index.item())
+        ni = int(index.item())  # the network's own choice, before the range guard
+        d3.update(picker_index=pi, picker_out_of_range=out, ari_picker=float(A[pi]), f1_picker=float(F[pi, 2]),
+                  gap_to_best=float(A.max() - A[pi]), network_index=ni, ari_network_unguarded=float(A[ni]))
+        d3["latency_picker_ms"] = _time_ms(lambda: PK.pick(g, t, model, vb))
+    d3["latency_sweep_ms"] = _time_ms(lambda: M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vb,
+                                                          truth=truth, ws=ws))
+    d3["latency_sweep_q_f1_ms"] = _time_ms(lambda: M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vb,
+                                                               truth=truth, ws=ws, want_modularity=True,
+                                                               want_prf=True))
+    res["dcsbm"] = d3
+
+    def k4_case(name, g_, n_):
+        # algorithmic bytes: for every oriented edge a->b the suffix of N+(a)
+        # after b is streamed once (S elements of 4 bytes), the counts are
+        # written (4m) and the row offsets read; the probes of the common
+        # neighbours' rows are on top of this, so the fraction is a lower bound
+        k4 = torch.empty(max(g_.m, 1), dtype=torch.int32, device=dev)
+        ms = _time_ms(lambda: M.mcd_k4(g_, k4), reps=3)
+        u, _ = M.mcd_graph_edges(g_)
+        outd = torch.bincount(u.long(), minlength=n_).double()
+        S = float((outd * (outd - 1) / 2).sum())
+        byts = 4.0 * S + 4.0 * g_.m + 8.0 * (n_ + 1)
+        cl = int(k4[:g_.m].sum(dtype=torch.int64).item()) // 6
+        # every clique costs at least one global atomic (its c->d credit)
+        res[name] = dict(m=g_.m, k4_ms=ms, edges_per_s=g_.m / (ms * 1e-3), cliques=cl,
+                         clique_credits_per_s=cl / (ms * 1e-3),
+                         suffix_elements=S, algorithmic_bytes=byts, achieved_gbs=byts / (ms * 1e-3) / 1e9,
+                         frac_lower_bound=byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+    k4_case("k4_dcsbm", g, n)
+    del g, t, ws
+    src, dst, n2 = gg.rmat(20, seed=1)
+    g2 = M.mcd_graph_build(ctx, cu(src), cu(dst), n2)
+    k4_case("k4_rmat_s20", g2, n2)
+    del g2
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -240,6 +329,10 @@ def main():
         f"({study['exact_recovery_tw']} exact), Tectonic {study['best_ari_tectonic']:.3f} "
         f"({study['exact_recovery_tectonic']} exact)")
 
+    nxt = next_rows_study(M, PK, model, dev)
+    log(f"DC-SBM: best swept ARI {nxt['dcsbm']['ari_best_swept']:.4f}, picker "
+        f"{nxt['dcsbm'].get('ari_picker', float('nan')):.4f}; 4-cliques R-MAT s20 in "
+        f"{nxt['k4_rmat_s20']['k4_ms']:.1f} ms")
     log(f"generating R-MAT scale {args.scale} edge factor {args.edge_factor} on the host")
     t0 = time.perf_counter()
     src_h, dst_h, n = gg.rmat(args.scale, args.edge_factor, seed=args.seed)
@@ -417,6 +510,7 @@ def main():
                                      "sweep rule of thumb (fallback: features outside the training range)"
                                      if ood else "learned picker")},
         "picker": pick_res,
+        "next_rows": nxt,
         "tw_vs_tectonic": study,
         "cpu_baseline": cpu,
     }
