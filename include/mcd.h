@@ -183,8 +183,10 @@ mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t w
  * device int32[m].  Each 4-clique is found once, from its lowest edge in the
  * degree order, and credits its six edges with atomics.  The result feeds
  * mcd_weights / mcd_prune / mcd_weigh_prune / mcd_sweep with MCD_SIM_K4 in
- * place of t.  Errors: MCD_ERR_RANGE when a row of the oriented graph holds
- * more than 4096 edges.  Asynchronous. */
+ * place of t.  Work for rows longer than 256 edges runs on a side stream of
+ * the context, forked from and joined back into the context's stream (so the
+ * call can be captured into a graph like any other).  Errors: MCD_ERR_RANGE
+ * when a row of the oriented graph holds more than 4096 edges.  Asynchronous. */
 mcd_status mcd_k4(const mcd_graph* g, int32_t* k4);
 
 /* Edge similarity of Table tab:simfunctions from t (as produced by
