@@ -130,3 +130,41 @@ def test_capture_and_replay_matches_eager():
             else:
                 assert torch.equal(a, b), (rep, k)
     M.mcd_ctx_set_stream(ctx, None)
+
+
+def test_capture_k4_with_side_stream():
+    """The 4-clique count forks its long-row kernel onto a side stream of the
+    context: a 300-clique (rows of 299 edges) beside an R-MAT graph takes that
+    path, and the captured graph replays it bit-identically."""
+    k = 300
+    pairs = [(i, j) for i in range(k) for j in range(i + 1, k)]
+    s2, d2, n2 = gg.rmat(12, seed=5)
+    rng = np.random.default_rng(3)
+    src = np.concatenate([np.array([p[0] for p in pairs], np.int32), s2 + k,
+                          rng.integers(0, k, 3000).astype(np.int32)])
+    dst = np.concatenate([np.array([p[1] for p in pairs], np.int32), d2 + k,
+                          (k + rng.integers(0, n2, 3000)).astype(np.int32)])
+    n = k + n2
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream()
+    ctx = M.mcd_ctx_create(0, stream=s)
+    with torch.cuda.stream(s):
+        g = M.mcd_graph_build(ctx, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n)
+        assert M.mcd_graph_info(g)["max_outdeg"] > 256
+        k4 = torch.empty(g.m, dtype=torch.int32, device=dev)
+        M.mcd_k4(g, k4)
+    torch.cuda.synchronize()
+    eager = k4.clone()
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cg, stream=s):
+        M.mcd_k4(g, k4)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            k4.fill_(-7)
+            torch.cuda.synchronize()
+            _ = (torch.arange(1 << 20, device=dev) % 7).sum()  # unrelated eager work
+            cg.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(k4, eager), rep
+    M.mcd_ctx_set_stream(ctx, None)
