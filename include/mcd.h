@@ -96,7 +96,10 @@ mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream);
  *                table, [0, 2^20 - 2], default 2^20 - 2; wider rows use the
  *                two-array table;
  *   "tc_window_max" widest rank range of a row held as an LDS rank bitmap,
- *                [0, 2^18], default 2^18 (0 disables the bitmap path).
+ *                [0, 2^18], default 2^18 (0 disables the bitmap path);
+ *   "k4_row_cache" mcd_k4 keeps the row offsets of the common neighbours
+ *                of a long row in LDS when they fit, 0 or 1, default 1
+ *                (0: read them per pair).
  * Errors: MCD_ERR_INVALID_ARG (unknown name), MCD_ERR_RANGE (bad value). */
 mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value);
 mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* value);

@@ -178,6 +178,7 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
     c->tc_lds_max = MCD_TC_LDS_LIMIT;
     c->tc_packed_range = MCD_TC_PACKED_LIMIT;
     c->tc_window_max = MCD_TC_WINDOW_LIMIT;
+    c->k4_row_cache = 1;
     if (hipMalloc((void**)&c->d_ctrl, sizeof(int64_t) * MCD_CTRL_WORDS) != hipSuccess) {
         delete c;
         return mcd_fail(MCD_ERR_DEVICE, "hipMalloc of the control block failed");
@@ -226,6 +227,9 @@ mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value) {
         REQUIRE(value >= 0 && value <= MCD_TC_PACKED_LIMIT, MCD_ERR_RANGE,
                 "tc_packed_range must lie in [0, 2^20 - 2]");
         ctx->tc_packed_range = value;
+    } else if (k == "k4_row_cache") {
+        REQUIRE(value == 0 || value == 1, MCD_ERR_RANGE, "k4_row_cache must be 0 or 1");
+        ctx->k4_row_cache = value;
     } else {
         return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     }
@@ -239,6 +243,7 @@ mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* valu
     else if (k == "tc_lds_max") *value = ctx->tc_lds_max;
     else if (k == "tc_packed_range") *value = ctx->tc_packed_range;
     else if (k == "tc_window_max") *value = ctx->tc_window_max;
+    else if (k == "k4_row_cache") *value = ctx->k4_row_cache;
     else return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     return MCD_OK;
 }

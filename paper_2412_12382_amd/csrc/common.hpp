@@ -22,6 +22,7 @@ struct mcd_ctx {
     int64_t tc_lds_max;  // longest row hashed in LDS; longer rows use binary search
     int64_t tc_packed_range;  // widest rank range (w - v - 1) of a packed LDS table
     int64_t tc_window_max;    // widest rank range of a row held as an LDS rank window
+    int64_t k4_row_cache;     // 4-cliques: keep the row offsets of L in LDS when they fit
     // side streams (default priority) and events on which the triangle
     // count runs its work-item classes concurrently, forked from and joined
     // back into `stream`

@@ -6,8 +6,8 @@
 // sorted, so L is the part of N+(a) after b that also lies in N+(b)), and the
 // clique closes when d lies in N+(c).  Per edge a->b: every element of the
 // suffix of row a after b is tested against row b by binary search and the
-// hits are gathered into LDS (value, position in row a, position in row b,
-// the row offsets of c); then the nL(nL-1)/2 pairs c < d of L are spread
+// hits are gathered into LDS (value; its offsets in the suffix and in row b,
+// packed in one word; the row offsets of c); then the nL(nL-1)/2 pairs c < d of L are spread
 // over the lanes, one pair per lane, and d is searched in row c.
 //
 // Credits: a clique credits its six edges.  c->d is a global atomic at the
@@ -60,6 +60,12 @@ __device__ __forceinline__ int64_t find_sorted(const int32_t* __restrict__ adj, 
     return -1;
 }
 
+// an element of L by its offset in the suffix of row a and in row b, both
+// below 4096 (rows hold at most 4096 edges), in one word
+__device__ __forceinline__ int32_t pack_pos(int64_t in_suffix, int64_t in_b) {
+    return (int32_t)((uint32_t)in_suffix | ((uint32_t)in_b << 16));
+}
+
 // pairs (x, y), x < y < nL, numbered row by row: row x starts at
 // x (2 nL - x - 1) / 2
 __device__ __forceinline__ int pair_row_start(int x, int nL) { return (x * (2 * nL - x - 1)) >> 1; }
@@ -88,11 +94,11 @@ __global__ __launch_bounds__(64 * kWaveBlock) void k_k4_wave(const int32_t* __re
                                                             const int32_t* __restrict__ adj,
                                                             const int64_t* __restrict__ off, int64_t m,
                                                             int32_t* __restrict__ k4) {
-    __shared__ int32_t sv[kWaveBlock][kWaveSuffix], spa[kWaveBlock][kWaveSuffix], spb[kWaveBlock][kWaveSuffix];
+    __shared__ int32_t sv[kWaveBlock][kWaveSuffix], spk[kWaveBlock][kWaveSuffix];
     __shared__ int32_t scnt[kWaveBlock][kWaveSuffix], sc0[kWaveBlock][kWaveSuffix], sc1[kWaveBlock][kWaveSuffix];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    int32_t *lv = sv[w], *lpa = spa[w], *lpb = spb[w], *lcnt = scnt[w], *lc0 = sc0[w], *lc1 = sc1[w];
+    int32_t *lv = sv[w], *lpk = spk[w], *lcnt = scnt[w], *lc0 = sc0[w], *lc1 = sc1[w];
     const uint64_t below = (1ull << lane) - 1ull;
     // edges interleaved over the waves (edge e to wave e mod W): the heavy
     // edges of a hub row spread over many waves
@@ -129,10 +135,9 @@ __global__ __launch_bounds__(64 * kWaveBlock) void k_k4_wave(const int32_t* __re
                 if (hit) {
                     const int slot = nL + __popcll(bal & below);
                     lv[slot] = c;
-                    lpa[slot] = (int32_t)i;  // positions < m < 2^31
-                    lpb[slot] = (int32_t)pb;
+                    lpk[slot] = pack_pos(i - e - 1, pb - b0);
                     lcnt[slot] = 0;
-                    lc0[slot] = (int32_t)off[c];
+                    lc0[slot] = (int32_t)off[c];  // offsets < m < 2^31
                     lc1[slot] = (int32_t)off[c + 1];
                 }
                 nL += __popcll(bal);
@@ -161,8 +166,9 @@ __global__ __launch_bounds__(64 * kWaveBlock) void k_k4_wave(const int32_t* __re
             for (int i = lane; i < nL; i += 64) {
                 const int32_t k = lcnt[i];
                 if (k) {
-                    add_relaxed(&k4[lpa[i]], k);  // a->x
-                    add_relaxed(&k4[lpb[i]], k);  // b->x
+                    const uint32_t pk = (uint32_t)lpk[i];
+                    add_relaxed(&k4[e + 1 + (pk & 0xFFFFu)], k);  // a->x
+                    add_relaxed(&k4[b0 + (pk >> 16)], k);        // b->x
                 }
             }
             if (lane == 0 && total) add_relaxed(&k4[e], total);  // a->b
@@ -172,7 +178,8 @@ __global__ __launch_bounds__(64 * kWaveBlock) void k_k4_wave(const int32_t* __re
 }
 
 // suffixes longer than one wave takes: four waves share L (cap entries per
-// array; with ROWS the row offsets of every c are kept beside it)
+// array; with ROWS the row offsets of every c are kept beside it, else they
+// are read per pair)
 template <bool ROWS>
 __global__ __launch_bounds__(kBlockThreads) void k_k4_block(const int32_t* __restrict__ src,
                                                            const int32_t* __restrict__ adj,
@@ -181,8 +188,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_k4_block(const int32_t* __res
     extern __shared__ int32_t lds[];
     __shared__ uint64_t wmask[kBlockThreads / 64];
     __shared__ int32_t wcount[kBlockThreads / 64];
-    int32_t *lv = lds, *lpa = lds + cap, *lpb = lds + 2 * cap, *lcnt = lds + 3 * cap;
-    int32_t *lc0 = lds + 4 * cap, *lc1 = lds + 5 * cap;  // ROWS only
+    int32_t *lv = lds, *lpk = lds + cap, *lcnt = lds + 2 * cap;
+    int32_t *lc0 = lds + 3 * cap, *lc1 = lds + 4 * cap;  // ROWS only
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     constexpr int NW = kBlockThreads / 64;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -229,8 +236,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_k4_block(const int32_t* __res
                     if (hit) {
                         const int slot = base + __popcll(bal & below);
                         lv[slot] = c;
-                        lpa[slot] = (int32_t)i;
-                        lpb[slot] = (int32_t)pb;
+                        lpk[slot] = pack_pos(i - e - 1, pb - b0);
                         lcnt[slot] = 0;
                         if (ROWS) {
                             lc0[slot] = (int32_t)off[c];
@@ -273,8 +279,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_k4_block(const int32_t* __res
                 for (int i = tid; i < nL; i += kBlockThreads) {
                     const int32_t k = lcnt[i];
                     if (k) {
-                        add_relaxed(&k4[lpa[i]], k);  // a->x
-                        add_relaxed(&k4[lpb[i]], k);  // b->x
+                        const uint32_t pk = (uint32_t)lpk[i];
+                        add_relaxed(&k4[e + 1 + (pk & 0xFFFFu)], k);  // a->x
+                        add_relaxed(&k4[b0 + (pk >> 16)], k);        // b->x
                     }
                 }
                 __syncthreads();  // reads done before the next edge's writes
@@ -301,13 +308,15 @@ void launch_k4(const mcd_graph* g, int32_t* k4, hipStream_t s) {
         (void)hipStreamWaitEvent(s1, c->fork, 0);
         const int cap = (g->max_outdeg + 63) & ~63;  // <= 4096
         const unsigned blocks = (unsigned)(g->m < 8192 ? g->m : 8192);
-        const bool rows = (size_t)cap * 6 * sizeof(int32_t) <= 65536;
-        if (rows)
-            hipLaunchKernelGGL(k_k4_block<true>, dim3(blocks), dim3(kBlockThreads),
-                               (size_t)cap * 6 * sizeof(int32_t), s1, g->src, g->adj, g->off, g->m, cap, k4);
+        // the whole workgroup's LDS within 64 KB: 20 bytes per entry with
+        // the row offsets (cap <= 3264), 12 without (cap <= 4096)
+        const size_t with_rows = (size_t)cap * 5 * sizeof(int32_t), without = (size_t)cap * 3 * sizeof(int32_t);
+        if (c->k4_row_cache && with_rows + 64 <= 65536)
+            hipLaunchKernelGGL(k_k4_block<true>, dim3(blocks), dim3(kBlockThreads), with_rows, s1, g->src, g->adj,
+                               g->off, g->m, cap, k4);
         else
-            hipLaunchKernelGGL(k_k4_block<false>, dim3(blocks), dim3(kBlockThreads),
-                               (size_t)cap * 4 * sizeof(int32_t), s1, g->src, g->adj, g->off, g->m, cap, k4);
+            hipLaunchKernelGGL(k_k4_block<false>, dim3(blocks), dim3(kBlockThreads), without, s1, g->src, g->adj,
+                               g->off, g->m, cap, k4);
     }
     const int64_t waves = g->m < ((int64_t)1 << 16) ? g->m : ((int64_t)1 << 16);
     const unsigned blocks = (unsigned)((waves + kWaveBlock - 1) / kWaveBlock);

@@ -184,7 +184,7 @@ def test_param_validation():
     from gpu_util import ctx
     c = ctx()
     for name, bad in (("tc_chunk", 0), ("tc_lds_max", 5000), ("tc_lds_max", -1),
-                      ("tc_packed_range", 1 << 20), ("tc_window_max", (1 << 18) + 1)):
+                      ("tc_packed_range", 1 << 20), ("tc_window_max", (1 << 18) + 1), ("k4_row_cache", 2)):
         with pytest.raises(M.MCDError) as ei:
             M.mcd_ctx_set_param(c, name, bad)
         assert ei.value.status == -3
@@ -310,6 +310,15 @@ def test_k4_participation_and_prune(case):
     k4 = M.mcd_k4(g)
     want = oracle.k4(n, lo, hi)
     assert np.array_equal(k4.cpu().numpy()[order], want)
+    if M.mcd_graph_info(g)["max_outdeg"] > 256:
+        # the long-row kernel also without the row offsets kept in LDS
+        from gpu_util import ctx
+        c = ctx()
+        M.mcd_ctx_set_param(c, "k4_row_cache", 0)
+        try:
+            assert np.array_equal(M.mcd_k4(g).cpu().numpy()[order], want)
+        finally:
+            M.mcd_ctx_set_param(c, "k4_row_cache", 1)
     if case == "k9":
         assert np.all(want == 21)  # C(7, 2)
     deg = oracle.degrees(n, lo, hi)
