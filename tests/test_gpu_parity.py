@@ -145,8 +145,11 @@ def test_repeat_runs_bit_identical():
         t = M.mcd_triangles(g)
         keep, _ = M.mcd_prune(g, oracle.TECTONIC, t, (1, 25))
         lab, ncc = M.mcd_components(g, keep)
+        pc = M.mcd_prune_components(g, oracle.TECTONIC, t, delta=(1, 25), want_f32=False)
+        k4 = M.mcd_k4(g)
         torch.cuda.synchronize()
-        outs.append((t.cpu().numpy().copy(), unpack_bits(keep, g.m), lab.cpu().numpy().copy()))
+        outs.append((t.cpu().numpy().copy(), unpack_bits(keep, g.m), lab.cpu().numpy().copy(),
+                     pc["labels"].cpu().numpy().copy(), k4.cpu().numpy().copy()))
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
@@ -178,6 +181,23 @@ def test_triangle_paths_and_chunks(chunk, lds_max, packed, window):
     finally:
         for k, val in zip(names, old):
             M.mcd_ctx_set_param(c, k, val)
+
+
+def test_triangles_at_odd_word_offset():
+    # t need only be 4-byte aligned: an output array starting 4 bytes into
+    # an 8-byte word gives the same counts and nothing outside it is written
+    from gpu_util import build, canonical_order
+    s, d, n = gg.rmat(15, seed=22)
+    lo, hi = oracle.canon(n, s, d)
+    t_o = oracle.triangles(n, lo, hi)
+    g = build(s, d, n)
+    _, _, order = canonical_order(g)
+    for shift in (0, 1):
+        buf = torch.full((g.m + 2,), -5, dtype=torch.int32, device="cuda")
+        t = M.mcd_triangles(g, buf[shift:])
+        assert np.array_equal(t.cpu().numpy()[order], t_o), shift
+        rest = buf.cpu().numpy()
+        assert np.all(rest[:shift] == -5) and np.all(rest[shift + g.m:] == -5), shift  # nothing outside t
 
 
 def test_param_validation():
