@@ -11,8 +11,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kIters = 8;                    // 64-key rounds per wave and tile
-constexpr int kTile = kThreads * kIters;     // 2048 keys per block iteration
+constexpr int kIters = 16;                   // 64-key rounds per wave and tile
+constexpr int kTile = kThreads * kIters;     // 4096 keys per block iteration
 constexpr int kMaxBlocks = 2048;
 constexpr int kScanThreads = 1024;
 
