@@ -7,8 +7,9 @@
 // clique closes when d lies in N+(c).  Per edge a->b: every element of the
 // suffix of row a after b is tested against row b by binary search and the
 // hits are gathered into LDS (value; its offsets in the suffix and in row b,
-// packed in one word; the row offsets of c); then the nL(nL-1)/2 pairs c < d of L are spread
-// over the lanes, one pair per lane, and d is searched in row c.
+// packed in one word; the row offsets of c); then the nL(nL-1)/2 pairs
+// c < d of L are spread over the lanes, one pair per lane, and d is searched
+// in row c.
 //
 // Credits: a clique credits its six edges.  c->d is a global atomic at the
 // position the search found.  The others are summed on chip first: a->x and
@@ -19,10 +20,11 @@
 // |L| is at most min(suffix length, outd(b)), known from the offsets alone:
 // an edge whose bound is below 2 closes no clique and is skipped.  Edges are
 // dealt round-robin to the waves (or workgroups), which test 64 (or 256) of
-// theirs at a time and work only on the candidates.  A
-// suffix of at most kWaveSuffix elements is one wave's work; longer ones (hub
-// rows) take a workgroup of four waves that share L in LDS sized by the
-// graph's longest row.
+// theirs at a time and work only on the candidates.  A suffix of at most
+// kWaveSuffix elements is one wave's work; longer ones (hub rows) take a
+// workgroup of four waves that share L in LDS sized by the graph's longest
+// row.  The two kernels run at once, on the context's stream and one of its
+// side streams.
 #include "common.hpp"
 
 namespace mcd {
