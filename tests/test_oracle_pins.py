@@ -563,6 +563,33 @@ def test_k4_participation_pins():
         assert np.array_equal(keep, (got >= 2).astype(np.uint8))
 
 
+def test_complete_multipartite_closed_forms():
+    # complete multipartite graph with parts of sizes p_1..p_k: a 4-clique
+    # takes one vertex from each of four distinct parts, so an edge between
+    # parts i and j lies in the sum over pairs {k, l} of the other parts of
+    # p_k p_l 4-cliques (and K4 participation is 0 with fewer than four parts)
+    import itertools
+    for sizes in ((1, 1, 1, 1), (2, 2, 2), (3, 1, 4, 2), (2, 3, 1, 2, 4), (5, 5)):
+        part = np.repeat(np.arange(len(sizes)), sizes)
+        n = len(part)
+        pairs = [(u, v) for u in range(n) for v in range(u + 1, n) if part[u] != part[v]]
+        lo, hi = edges_of(n, pairs)
+        got = oracle.k4(n, lo, hi)
+        for e, (u, v) in enumerate(zip(lo.tolist(), hi.tolist())):
+            rest = [sizes[q] for q in range(len(sizes)) if q not in (part[u], part[v])]
+            want = sum(a * b for a, b in itertools.combinations(rest, 2))
+            assert got[e] == want, (sizes, u, v)
+        # the same graphs pin t, the degrees and the weights: an edge between
+        # parts i and j has t = n - p_i - p_j, deg u = n - p_i, deg v = n - p_j
+        deg = oracle.degrees(n, lo, hi)
+        t = oracle.triangles(n, lo, hi)
+        pu, pv = np.array(sizes)[part[lo]], np.array(sizes)[part[hi]]
+        assert np.array_equal(deg[lo], n - pu) and np.array_equal(deg[hi], n - pv)
+        assert np.array_equal(t, n - pu - pv)
+        assert np.array_equal(oracle.tw(lo, hi, t, deg), 3 * (n - pu - pv) - (n - pu) - (n - pv) + 2)
+        assert np.array_equal(oracle.tectonic(lo, hi, t, deg), (n - pu - pv) / ((n - pu) + (n - pv)))
+
+
 def test_imbalanced_sbm_tw_recovers_tectonic_does_not():
     # Sec. 3's two-block analysis in the paper's visualised setting (blocks of
     # 50, p1 = 0.1, p2 = 0.8, q = 0.05), 20 seeds: across-block edges score
