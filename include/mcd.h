@@ -21,7 +21,9 @@
  *     the calling thread's most recent failure.
  *   - Array arguments are DEVICE pointers owned by the caller unless the name
  *     says host_.  The library never allocates device memory except a small
- *     control block in mcd_ctx_create.  Calls that need scratch memory take a
+ *     control block in mcd_ctx_create (and the fixed scratch array of
+ *     mcd_prune_components_noalloc, held per device from load to process
+ *     end).  Calls that need scratch memory take a
  *     workspace (ws, ws_bytes) sized by the matching *_workspace_size query;
  *     a smaller workspace gives MCD_ERR_WORKSPACE.  Workspaces and the graph
  *     storage buffer must start on a 256-byte boundary (the library carves
@@ -273,6 +275,29 @@ mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const i
                                 int32_t n_graphs, const int64_t* vbase, const int64_t* deltas, float* w_f32,
                                 int32_t* w_i32, uint32_t* keep_bits, int64_t* n_kept, int32_t* labels,
                                 int64_t* n_components, void* ws, size_t ws_bytes);
+
+/* Most vertices of a graph given to mcd_prune_components_noalloc: the size of
+ * its device scratch array (int32 each, 64 MiB per device). */
+#define MCD_NOALLOC_MAX_VERTICES (1 << 24)
+
+/* mcd_prune_components without a workspace, for callers that cannot allocate
+ * device memory or pass a workspace (code under HIP graph capture, tight
+ * serving loops, hosts that forbid allocation).  Same arguments, kernels and
+ * results as mcd_prune_components, minus ws / ws_bytes: the components'
+ * union-find parent array lives in a device array of the library, sized for
+ * MCD_NOALLOC_MAX_VERTICES vertices, that each device holds from the
+ * library's load until the process ends.  The call allocates nothing and
+ * calls no allocating routine; the caller still passes every output buffer.
+ * Every call on one device shares that device's array and leaves its contents
+ * behind (each call first resets the part it uses), so calls that overlap on
+ * one device, on any streams or contexts, race and give wrong labels: order
+ * them.  Errors: MCD_ERR_RANGE when the graph has more than
+ * MCD_NOALLOC_MAX_VERTICES vertices; otherwise those of mcd_prune_components.
+ * Asynchronous. */
+mcd_status mcd_prune_components_noalloc(const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                                        mcd_rational delta, int32_t n_graphs, const int64_t* vbase,
+                                        const int64_t* deltas, float* w_f32, int32_t* w_i32, uint32_t* keep_bits,
+                                        int64_t* n_kept, int32_t* labels, int64_t* n_components);
 
 /* Algorithm 1 in one call: triangles, weights, prune at delta, components.
  * labels / n_components as in mcd_components.  Asynchronous. */

@@ -7,6 +7,8 @@
 #include <string>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -31,6 +33,14 @@ mcd_status mcd_fail(mcd_status s, const std::string& msg) {
 // workspaces) must start on a 256-byte boundary; NULL passes.
 #define REQUIRE_ALIGNED(p)                                                                          \
     REQUIRE(((uintptr_t)(p) & 255u) == 0u, MCD_ERR_INVALID_ARG, #p " must be 256-byte aligned")
+
+// Scratch of the allocation-free entry point (mcd_prune_components_noalloc):
+// the union-find parent array of a graph of at most MCD_NOALLOC_MAX_VERTICES
+// vertices.  Each device holds its own copy, at its own address, from module
+// load to process end.  Host code never passes `scratch` itself to a kernel
+// (on the host it names a stand-in, not device memory): the device address is
+// looked up once per device, with that device current, and kept.
+static __device__ __align__(256) int32_t scratch[MCD_NOALLOC_MAX_VERTICES];
 
 namespace {
 
@@ -135,6 +145,24 @@ RunLayout run_layout(void* base, const mcd_graph* g) {
     return L;
 }
 
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // by device id; null until looked up
+
+// Device address of `scratch` on the current device `device` (looked up on
+// the first call for that device).
+mcd_status scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        MCD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return mcd_fail(MCD_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return MCD_OK;
+}
+
 mcd_status sync_read(mcd_ctx* ctx, const int64_t* d, int64_t* h, int count) {
     MCD_HIP(hipMemcpyAsync(h, d, sizeof(int64_t) * count, hipMemcpyDeviceToHost, ctx->stream));
     MCD_HIP(hipStreamSynchronize(ctx->stream));
@@ -188,6 +216,13 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
         (void)hipFree(c->d_ctrl);
         delete c;
         return mcd_fail(MCD_ERR_DEVICE, "hipHostMalloc of the read-back block failed");
+    }
+    void* scr = nullptr;  // the allocation-free entry point's scratch, looked up once per device
+    if (scratch_address(device, &scr) != MCD_OK) {
+        (void)hipFree(c->d_ctrl);
+        (void)hipHostFree(c->h_ctrl);
+        delete c;
+        return MCD_ERR_DEVICE;  // message set by scratch_address
     }
     bool ok = true;
     for (int i = 0; i < 2; ++i) {
@@ -610,6 +645,37 @@ mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const i
     if ((st = use_device(g->ctx)) != MCD_OK) return st;
     hipStream_t s = g->ctx->stream;
     // with no vertex there is no edge either: the pass only zeroes n_kept
+    int32_t* parent = mcd::launch_components_init(g, labels, n_components, ws, s);
+    mcd::launch_weigh_prune(g, measure, t, delta.num, delta.den, deltas ? n_graphs : 1, vbase, deltas, w_f32, w_i32,
+                            keep_bits, nullptr, nullptr, n_kept, s, g->n > 0 ? parent : nullptr);
+    mcd::launch_components_finish(g, labels, n_components, ws, s);
+    return MCD_OK;
+}
+
+mcd_status mcd_prune_components_noalloc(const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                                        mcd_rational delta, int32_t n_graphs, const int64_t* vbase,
+                                        const int64_t* deltas, float* w_f32, int32_t* w_i32, uint32_t* keep_bits,
+                                        int64_t* n_kept, int32_t* labels, int64_t* n_components) {
+    REQUIRE(g && (g->n == 0 || labels), MCD_ERR_INVALID_ARG, "NULL argument");
+    REQUIRE(g->n <= MCD_NOALLOC_MAX_VERTICES, MCD_ERR_RANGE,
+            "mcd_prune_components_noalloc takes graphs of at most 2^24 vertices");
+    REQUIRE(g->m == 0 || t, MCD_ERR_INVALID_ARG, "t is NULL");
+    REQUIRE(valid_measure(measure), MCD_ERR_INVALID_ARG, "unknown measure");
+    REQUIRE(!w_i32 || measure == MCD_SIM_TW || measure == MCD_SIM_K3 || measure == MCD_SIM_K4,
+            MCD_ERR_INVALID_ARG, "integer weights exist for TW, K3 and K4 only");
+    mcd_status st;
+    if (deltas) {
+        REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "n_graphs must be at least 1");
+        REQUIRE(n_graphs == 1 || vbase, MCD_ERR_INVALID_ARG, "vbase is NULL");
+    } else if ((st = check_delta(delta)) != MCD_OK) {
+        return st;
+    }
+    if ((st = use_device(g->ctx)) != MCD_OK) return st;
+    void* ws = nullptr;  // looked up when the context was created: no allocation here
+    if ((st = scratch_address(g->ctx->device, &ws)) != MCD_OK) return st;
+    hipStream_t s = g->ctx->stream;
+    // the same kernels as mcd_prune_components; the init kernel sets every
+    // parent of this graph's vertices, so nothing left by an earlier call matters
     int32_t* parent = mcd::launch_components_init(g, labels, n_components, ws, s);
     mcd::launch_weigh_prune(g, measure, t, delta.num, delta.den, deltas ? n_graphs : 1, vbase, deltas, w_f32, w_i32,
                             keep_bits, nullptr, nullptr, n_kept, s, g->n > 0 ? parent : nullptr);

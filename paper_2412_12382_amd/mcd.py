@@ -101,6 +101,7 @@ def lib():
             "mcd_tune_triangles_workspace_size": [P, ctypes.POINTER(SZ)],
             "mcd_k4": [P, P],
             "mcd_prune_components": [P, ctypes.c_int, P, mcd_rational, I32, P, P, P, P, P, P, P, P, P, SZ],
+            "mcd_prune_components_noalloc": [P, ctypes.c_int, P, mcd_rational, I32, P, P, P, P, P, P, P, P],
             "mcd_tune_triangles": [P, P, P, SZ, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float)],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
         }
@@ -514,6 +515,7 @@ def mcd_prune_graphs(g: Graph, measure: int, t, deltas, vbase=None, keep_bits=No
 
 
 KEPT_SEGMENTS = 16384
+NOALLOC_MAX_VERTICES = 1 << 24
 TUNE_PARAMS = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max")
 
 
@@ -630,6 +632,33 @@ def mcd_prune_components(g: Graph, measure: int, t, delta=None, deltas=None, vba
     _check(lib().mcd_prune_components(g.handle, measure, _p(t), rat, G, vbp, _p(deltas), _p(w_f32), _p(w_i32),
                                       _p(keep_bits), _p(n_kept), _p(labels), _p(n_components), _p(ws),
                                       ws.numel() * ws.element_size()))
+    return dict(w_f32=None if w_f32 is None else w_f32[:g.m], w_i32=None if w_i32 is None else w_i32[:g.m],
+                keep_bits=keep_bits, n_kept=n_kept, labels=labels[:g.n], n_components=n_components)
+
+
+def mcd_prune_components_noalloc(g: Graph, measure: int, t, delta=None, deltas=None, vbase=None, w_f32=None,
+                                 w_i32=None, keep_bits=None, n_kept=None, labels=None, n_components=None,
+                                 want_f32=True, want_i32=False, want_keep=True):
+    """mcd_prune_components with the library's own device scratch instead of a
+    workspace (graphs of at most NOALLOC_MAX_VERTICES vertices).  Outputs the
+    caller does not pass are allocated here, by torch, before the call."""
+    dev = g.ctx.device
+    if w_f32 is None and want_f32:
+        w_f32 = _empty(max(g.m, 1), torch.float32, dev)
+    if w_i32 is None and want_i32:
+        w_i32 = _empty(max(g.m, 1), torch.int32, dev)
+    if keep_bits is None and want_keep:
+        keep_bits = _empty(max((g.m + 31) // 32, 1), torch.int32, dev)
+    n_kept = _empty(1, torch.int64, dev) if n_kept is None else n_kept
+    labels = _empty(max(g.n, 1), torch.int32, dev) if labels is None else labels
+    n_components = _empty(1, torch.int64, dev) if n_components is None else n_components
+    if deltas is not None:
+        vb = _vbase(g, vbase)
+        G, vbp, rat = vb.numel() - 1, _p(vb), mcd_rational(0, 1)
+    else:
+        G, vbp, rat = 1, None, _rat(delta)
+    _check(lib().mcd_prune_components_noalloc(g.handle, measure, _p(t), rat, G, vbp, _p(deltas), _p(w_f32),
+                                              _p(w_i32), _p(keep_bits), _p(n_kept), _p(labels), _p(n_components)))
     return dict(w_f32=None if w_f32 is None else w_f32[:g.m], w_i32=None if w_i32 is None else w_i32[:g.m],
                 keep_bits=keep_bits, n_kept=n_kept, labels=labels[:g.n], n_components=n_components)
 
