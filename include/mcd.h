@@ -59,6 +59,7 @@ typedef int32_t mcd_status;
 #define MCD_ERR_DEVICE (-6)         /* a HIP runtime call failed                     */
 #define MCD_ERR_NOT_CONVERGED (-7)  /* an iterative step hit its iteration cap       */
 #define MCD_ERR_EMPTY (-8)          /* the requested statistic has no data           */
+#define MCD_ERR_CHECKPOINT (-9)     /* a picker checkpoint is unreadable or corrupt  */
 
 typedef struct mcd_ctx mcd_ctx;
 typedef struct mcd_graph mcd_graph;
@@ -438,6 +439,99 @@ mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean
 mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
                               float lr, float weight_decay, const float* mean, const float* std, const float* x,
                               const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes);
+
+/* The picker as a library object.  mcd_picker_create allocates its device
+ * state (parameters, Adam moments, standardisation, training range: 103 KB)
+ * on the context's device; mcd_picker_destroy frees it.  The network maps a
+ * graph's features (mcd_features) to y in [0, 1], snapped to the grid
+ * delta_i = (MCD_PICKER_GRID_A + MCD_PICKER_GRID_B i) / MCD_PICKER_GRID_C,
+ * i < MCD_PICKER_GRID_K (64 evenly spaced values in [0.01, 0.5]).  The
+ * threshold sweep over the same grid is both its fallback and its judge:
+ * graphs whose features leave the training range (widened by the picker's
+ * margin) take the sweep's rule of thumb instead (mcd_sweep_rule). */
+typedef struct mcd_picker mcd_picker;
+#define MCD_PICKER_GRID_K 64
+#define MCD_PICKER_GRID_A 9
+#define MCD_PICKER_GRID_B 7
+#define MCD_PICKER_GRID_C 900
+#define MCD_PICKER_MARGIN 0.25f /* default margin of the range guard, of each feature's width */
+
+/* Creates a picker whose weights are He-uniform, drawn from `seed`: weight
+ * number i of the flat vector (a layer of fan-in f) is (2 u_i - 1) sqrt(6/f)
+ * rounded to fp32, u_i the uniform in (0,1) of Philox-4x32-10 (Salmon et al.,
+ * SC'11) at counter (i, 0x55, 0x4D4C5030) under key `seed`, built from the
+ * first two output words (53 bits, plus half a step); biases are zero.  The
+ * picker cannot pick until prepared, fitted or loaded.  Synchronous.
+ * Errors: MCD_ERR_INVALID_ARG, MCD_ERR_DEVICE. */
+mcd_status mcd_picker_create(mcd_ctx* ctx, uint64_t seed, mcd_picker** out);
+mcd_status mcd_picker_destroy(mcd_picker* p);
+
+/* Sets the standardisation (mcd_feature_stats with min_std) and the training
+ * range (mcd_feature_range) from training features x (device
+ * float[batch][66]), the guard's margin (>= 0), and restarts Adam. */
+mcd_status mcd_picker_prepare(mcd_picker* p, const float* x, int32_t batch, float min_std, float margin);
+
+/* One Adam step as mcd_mlp_train_step on the picker's own parameters and
+ * moments (its step counter advances); loss (device float[1]) may be NULL.
+ * ws: mcd_mlp_workspace_size(batch). */
+mcd_status mcd_picker_train_step(mcd_picker* p, const float* x, const float* y, int32_t batch, float lr,
+                                 float weight_decay, float* loss, void* ws, size_t ws_bytes);
+
+/* mcd_picker_prepare, then `steps` train steps on (x, y): full-batch
+ * training on the sweep's targets (mcd_sweep_targets).  losses: device
+ * float[steps], each step's pre-step loss, may be NULL.  Asynchronous. */
+mcd_status mcd_picker_fit(mcd_picker* p, const float* x, const float* y, int32_t batch, int32_t steps, float lr,
+                          float weight_decay, float min_std, float margin, float* losses, void* ws,
+                          size_t ws_bytes);
+
+/* The network's output y (device float[batch]) for features x. */
+mcd_status mcd_picker_forward(const mcd_picker* p, const float* x, int32_t batch, float* y);
+
+/* Scratch for mcd_picker_pick on this graph (or batch of n_graphs). */
+mcd_status mcd_picker_pick_workspace_size(const mcd_graph* g, int32_t n_graphs, size_t* bytes);
+
+#define MCD_PICK_AUTO 0        /* the network, the sweep's rule where the guard fires */
+#define MCD_PICK_FORCE_SWEEP 1 /* the sweep's rule of thumb for every graph          */
+#define MCD_PICK_NETWORK 2     /* the network for every graph, no guard               */
+
+/* Algorithm 1 with a learned threshold, per graph of a batch (vbase as in
+ * mcd_sweep): features -> network -> grid snap -> range guard -> (where the
+ * guard fires, or in MCD_PICK_FORCE_SWEEP mode, or when the environment sets
+ * MCD_FORCE_SWEEP to anything but "0": the grid sweep with modularity and its
+ * rule of thumb, jump 1/10) -> prune at each graph's threshold and components.
+ *   index:         device int32[n_graphs], the network's grid index (may be NULL);
+ *   deltas:        device int64[n_graphs][2], the threshold each graph used (may be NULL);
+ *   used_fallback: device int32[n_graphs], 1 where the sweep's threshold was used (may be NULL);
+ *   labels, n_components: as for mcd_components over the whole batch.
+ * MCD_PICK_AUTO reads the guard's flags back once (synchronous) and runs the
+ * sweep only if some graph needs it; the other modes are asynchronous.
+ * Errors: MCD_ERR_INVALID_ARG (unprepared picker, other context),
+ * MCD_ERR_WORKSPACE. */
+mcd_status mcd_picker_pick(const mcd_picker* p, const mcd_graph* g, mcd_measure measure, const int32_t* t,
+                           int32_t n_graphs, const int64_t* vbase, int32_t mode, int32_t* index, int64_t* deltas,
+                           int32_t* used_fallback, int32_t* labels, int64_t* n_components, void* ws,
+                           size_t ws_bytes);
+
+/* Copies the picker's state out to (export) or in from (import) caller
+ * device buffers: params float[MCD_MLP_PARAMS], mean, std, lo, hi float[66];
+ * export skips NULL outputs and returns the margin in *host_margin (may be
+ * NULL); import restarts Adam and marks the picker prepared. */
+mcd_status mcd_picker_export(const mcd_picker* p, float* params, float* mean, float* std, float* lo, float* hi,
+                             float* host_margin);
+mcd_status mcd_picker_import(mcd_picker* p, const float* params, const float* mean, const float* std,
+                             const float* lo, const float* hi, float margin);
+
+/* Checkpoint of a prepared picker (network, standardisation, training range,
+ * margin) as a little-endian file: "MCDPICK\0", version 1, the network shape,
+ * the grid, the margin, the arrays, and a CRC-32 (IEEE) of everything before
+ * it.  save writes `path`.tmp and renames it; load checks length, magic,
+ * version, CRC, shape, grid, finiteness and positive std before touching the
+ * picker.  Both synchronous.  Errors: MCD_ERR_CHECKPOINT (I/O or any check). */
+mcd_status mcd_picker_save(const mcd_picker* p, const char* path);
+mcd_status mcd_picker_load(mcd_picker* p, const char* path);
+/* The checks of mcd_picker_load alone, on the host (no device needed):
+ * MCD_OK for a sound checkpoint, MCD_ERR_CHECKPOINT otherwise. */
+mcd_status mcd_picker_check_file(const char* path);
 
 /* Snaps picker outputs to the grid delta_i = (a + b i) / c, i = 0..K-1:
  * i = clamp(round((K - 1) y), 0, K - 1).  index: device int32[batch] (may be

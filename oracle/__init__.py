@@ -91,7 +91,8 @@ def canon(n: int, src, dst):
         raise OracleError("vertex id out of range")
     if rc != 0:
         raise OracleError(f"or_canon failed ({rc})")
-    return lo[:m.value].copy(), hi[:m.value].copy()
+    # views of the full-length buffers: no second copy of a billion-edge list
+    return lo[:m.value], hi[:m.value]
 
 
 def degrees(n: int, lo, hi):

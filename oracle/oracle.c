@@ -39,6 +39,47 @@ static int cmp_u64(const void* a, const void* b) {
     return (x > y) - (x < y);
 }
 
+/* Ascending sort of k 64-bit keys.  Large arrays are cut into one run per
+ * thread, each run sorted by qsort, and neighbouring runs merged pairwise
+ * until one remains: the output is the same sorted array that a single qsort
+ * gives, in less wall time on many cores. */
+static void merge_u64(const uint64_t* a, int64_t na, const uint64_t* b, int64_t nb, uint64_t* out) {
+    int64_t i = 0, j = 0, o = 0;
+    while (i < na && j < nb) out[o++] = (b[j] < a[i]) ? b[j++] : a[i++];
+    while (i < na) out[o++] = a[i++];
+    while (j < nb) out[o++] = b[j++];
+}
+
+static void sort_u64(uint64_t* a, int64_t k) {
+    int T = 1;
+#ifdef _OPENMP
+    T = omp_get_max_threads();
+#endif
+    if (T < 2 || k < (1 << 20)) {
+        qsort(a, (size_t)k, sizeof(uint64_t), cmp_u64);
+        return;
+    }
+    int64_t* bnd = (int64_t*)malloc(sizeof(int64_t) * (size_t)(T + 1));
+    for (int i = 0; i <= T; ++i) bnd[i] = k * i / T;
+#pragma omp parallel for schedule(static, 1)
+    for (int i = 0; i < T; ++i) qsort(a + bnd[i], (size_t)(bnd[i + 1] - bnd[i]), sizeof(uint64_t), cmp_u64);
+    uint64_t* buf = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)k);
+    uint64_t *from = a, *to = buf;
+    for (int w = 1; w < T; w *= 2) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int i = 0; i < T; i += 2 * w) {
+            const int i1 = (i + w < T) ? i + w : T, i2 = (i + 2 * w < T) ? i + 2 * w : T;
+            merge_u64(from + bnd[i], bnd[i1] - bnd[i], from + bnd[i1], bnd[i2] - bnd[i1], to + bnd[i]);
+        }
+        uint64_t* x = from;
+        from = to;
+        to = x;
+    }
+    if (from != a) memcpy(a, from, sizeof(uint64_t) * (size_t)k);
+    free(buf);
+    free(bnd);
+}
+
 /* Simple undirected graph from raw pairs (Sec. 1 notation: undirected,
  * unweighted, no self-loops, no multi-edges).  Each pair (u,v), u != v, is the
  * edge {min,max}; self-loops are dropped; duplicates collapse.  Output: the m
@@ -59,7 +100,7 @@ int or_canon(int64_t n, int64_t n_pairs, const int32_t* src, const int32_t* dst,
         uint64_t a = (uint64_t)(u < v ? u : v), b = (uint64_t)(u < v ? v : u);
         keys[k++] = (a << 32) | b;
     }
-    qsort(keys, (size_t)k, sizeof(uint64_t), cmp_u64);
+    sort_u64(keys, k);
     int64_t m = 0;
     for (int64_t i = 0; i < k; ++i) {
         if (i > 0 && keys[i] == keys[i - 1]) continue;
@@ -112,6 +153,7 @@ void or_adjacency(int64_t n, int64_t m, const int32_t* lo, const int32_t* hi,
         tmp[off[b] + fill[b]].eid = (int32_t)e;
         fill[b]++;
     }
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t u = 0; u < n; ++u)
         qsort(tmp + off[u], (size_t)(off[u + 1] - off[u]), sizeof(nbr_t), cmp_nbr);
     for (int64_t i = 0; i < 2 * m; ++i) {

@@ -185,6 +185,7 @@ const char* mcd_status_string(mcd_status s) {
         case MCD_ERR_DEVICE: return "MCD_ERR_DEVICE";
         case MCD_ERR_NOT_CONVERGED: return "MCD_ERR_NOT_CONVERGED";
         case MCD_ERR_EMPTY: return "MCD_ERR_EMPTY";
+        case MCD_ERR_CHECKPOINT: return "MCD_ERR_CHECKPOINT";
         default: return "MCD_ERR_UNKNOWN";
     }
 }

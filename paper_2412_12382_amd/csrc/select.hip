@@ -1,9 +1,12 @@
 // Exact nearest-rank selection among the nonzero edge similarities.
 //
 // Every nonzero similarity gets a 32-bit key whose unsigned order agrees with
-// the order of the exact values: for Tectonic the bit pattern of the positive
-// fp32 quotient t/D (rounding is monotone, so exact order implies key order),
-// for TW the int32 value with its sign bit flipped (exact).  A four-pass
+// the order of the exact values: for Tectonic and Jaccard the bit pattern of
+// the positive quotient num/den rounded to fp32 through fp64 (the integers
+// are exact in fp64, and each rounding is monotone, so exact order implies
+// key order for any operands below 2^53, whereas converting a denominator of
+// 2^24 or more to fp32 first would not be); for TW the int32 value with its
+// sign bit flipped (exact).  A four-pass
 // 8-bit radix select finds the key of the k-th smallest value.  For TW that is
 // the answer; for Tectonic several distinct rationals may share one fp32 key,
 // so the rationals inside that key are ordered exactly by cross-multiplying
@@ -43,7 +46,7 @@ __device__ __forceinline__ Sim sim_of(const int32_t* __restrict__ dsum, const in
         s.num = tt;
         s.den = measure == MCD_SIM_JACCARD ? D - tt : D;
         s.nonzero = tt != 0;
-        s.key = __float_as_uint((float)tt / (float)s.den);
+        s.key = __float_as_uint((float)((double)tt / (double)s.den));
     }
     return s;
 }

@@ -25,10 +25,13 @@ __device__ __forceinline__ int graph_of(const int64_t* __restrict__ vbase, int G
     return lo;
 }
 
-// t / d in fp32, correctly rounded (Tectonic, Jaccard): a single fp32
-// division is exact-input and correctly rounded while both operands fit 24
-// bits; beyond that the quotient is formed in fp64 and rounded once more,
-// which is innocuous for a single division (53 >= 2 * 24 + 2).
+// t / d in fp32 (Tectonic, Jaccard), defined as the fp64 quotient rounded to
+// fp32.  While both integers fit 24 bits they are exact fp32 values and the
+// single fp32 division gives the same result (double rounding of one
+// division of 24-bit operands through 53 bits is innocuous, 53 >= 2 * 24 + 2),
+// so it is the correctly rounded quotient.  Wider operands (degree sums of
+// 2^24 or more) take the fp64 route itself; there the value can differ from
+// the correctly rounded quotient by one ulp, but it is still the defined one.
 __device__ __forceinline__ float ratio_f32(int32_t t, int64_t d) {
     if (t < (1 << 24) && d < (1 << 24)) return (float)t / (float)d;
     return (float)((double)t / (double)d);

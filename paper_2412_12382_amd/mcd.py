@@ -27,7 +27,7 @@ MCD_SIM_K4 = 4
 
 STATUS = {0: "MCD_OK", -1: "MCD_ERR_INVALID_ARG", -2: "MCD_ERR_INVALID_VERTEX", -3: "MCD_ERR_RANGE",
           -4: "MCD_ERR_WORKSPACE", -5: "MCD_ERR_NO_DEVICE", -6: "MCD_ERR_DEVICE",
-          -7: "MCD_ERR_NOT_CONVERGED", -8: "MCD_ERR_EMPTY"}
+          -7: "MCD_ERR_NOT_CONVERGED", -8: "MCD_ERR_EMPTY", -9: "MCD_ERR_CHECKPOINT"}
 
 
 class MCDError(RuntimeError):
@@ -104,6 +104,20 @@ def lib():
             "mcd_prune_components_noalloc": [P, ctypes.c_int, P, mcd_rational, I32, P, P, P, P, P, P, P, P],
             "mcd_tune_triangles": [P, P, P, SZ, I32, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float)],
             "mcd_percentile_threshold": [P, ctypes.c_int, P, I64, I64, P, SZ, ctypes.POINTER(mcd_rational)],
+            "mcd_picker_create": [P, ctypes.c_uint64, PP],
+            "mcd_picker_destroy": [P],
+            "mcd_picker_prepare": [P, P, I32, ctypes.c_float, ctypes.c_float],
+            "mcd_picker_train_step": [P, P, P, I32, ctypes.c_float, ctypes.c_float, P, P, SZ],
+            "mcd_picker_fit": [P, P, P, I32, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P,
+                               P, SZ],
+            "mcd_picker_forward": [P, P, I32, P],
+            "mcd_picker_pick_workspace_size": [P, I32, ctypes.POINTER(SZ)],
+            "mcd_picker_pick": [P, P, ctypes.c_int, P, I32, P, I32, P, P, P, P, P, P, SZ],
+            "mcd_picker_export": [P, P, P, P, P, P, ctypes.POINTER(ctypes.c_float)],
+            "mcd_picker_import": [P, P, P, P, P, P, ctypes.c_float],
+            "mcd_picker_save": [P, ctypes.c_char_p],
+            "mcd_picker_load": [P, ctypes.c_char_p],
+            "mcd_picker_check_file": [ctypes.c_char_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -512,6 +526,115 @@ def mcd_prune_graphs(g: Graph, measure: int, t, deltas, vbase=None, keep_bits=No
     _check(lib().mcd_prune_graphs(g.handle, measure, _p(t), vb.numel() - 1, _p(vb), _p(deltas), _p(keep_bits),
                                   _p(n_kept)))
     return keep_bits, n_kept
+
+
+# ------------------------------------------------------ picker as an object
+
+PICKER_GRID_K, PICKER_GRID_A, PICKER_GRID_B, PICKER_GRID_C = 64, 9, 7, 900
+PICKER_MARGIN = 0.25
+MCD_PICK_AUTO, MCD_PICK_FORCE_SWEEP, MCD_PICK_NETWORK = 0, 1, 2
+
+
+class PickerHandle:
+    """An mcd_picker and the context it lives in."""
+
+    def __init__(self, handle, ctx: Context):
+        self.handle = handle
+        self.ctx = ctx
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mcd_picker_destroy(self.handle)
+            self.handle = None
+
+
+def mcd_picker_create(ctx: Context, seed: int = 0) -> PickerHandle:
+    h = ctypes.c_void_p()
+    _check(lib().mcd_picker_create(ctx.handle, int(seed), ctypes.byref(h)))
+    return PickerHandle(h, ctx)
+
+
+def mcd_picker_prepare(p: PickerHandle, x, min_std: float = 1.0, margin: float = PICKER_MARGIN) -> None:
+    _check(lib().mcd_picker_prepare(p.handle, _p(x), x.shape[0], min_std, margin))
+
+
+def mcd_picker_train_step(p: PickerHandle, x, y, lr: float, weight_decay: float = 0.0, loss=None, ws=None):
+    B = x.shape[0]
+    loss = _empty(1, torch.float32, p.ctx.device) if loss is None else loss
+    ws = _bytes(mcd_mlp_workspace_size(B), p.ctx.device) if ws is None else ws
+    _check(lib().mcd_picker_train_step(p.handle, _p(x), _p(y), B, lr, weight_decay, _p(loss), _p(ws),
+                                       ws.numel() * ws.element_size()))
+    return loss
+
+
+def mcd_picker_fit(p: PickerHandle, x, y, steps: int, lr: float, weight_decay: float = 0.0, min_std: float = 1.0,
+                   margin: float = PICKER_MARGIN, losses=None, ws=None):
+    B = x.shape[0]
+    losses = _empty(max(steps, 1), torch.float32, p.ctx.device) if losses is None else losses
+    ws = _bytes(mcd_mlp_workspace_size(B), p.ctx.device) if ws is None else ws
+    _check(lib().mcd_picker_fit(p.handle, _p(x), _p(y), B, steps, lr, weight_decay, min_std, margin, _p(losses),
+                                _p(ws), ws.numel() * ws.element_size()))
+    return losses[:steps]
+
+
+def mcd_picker_forward(p: PickerHandle, x, y=None):
+    B = x.shape[0]
+    y = _empty(max(B, 1), torch.float32, p.ctx.device) if y is None else y
+    _check(lib().mcd_picker_forward(p.handle, _p(x), B, _p(y)))
+    return y[:B]
+
+
+def mcd_picker_pick_workspace_size(g: Graph, n_graphs: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().mcd_picker_pick_workspace_size(g.handle, n_graphs, ctypes.byref(b)))
+    return b.value
+
+
+def mcd_picker_pick(p: PickerHandle, g: Graph, measure: int, t, vbase=None, mode: int = MCD_PICK_AUTO, index=None,
+                    deltas=None, used_fallback=None, labels=None, n_components=None, ws=None):
+    """Returns (index int32[G], deltas int64[G][2], used_fallback int32[G],
+    labels int32[n], n_components int64[1])."""
+    vb = _vbase(g, vbase)
+    G = vb.numel() - 1
+    dev = g.ctx.device
+    index = _empty(G, torch.int32, dev) if index is None else index
+    deltas = _empty((G, 2), torch.int64, dev) if deltas is None else deltas
+    used_fallback = _empty(G, torch.int32, dev) if used_fallback is None else used_fallback
+    labels = _empty(max(g.n, 1), torch.int32, dev) if labels is None else labels
+    n_components = _empty(1, torch.int64, dev) if n_components is None else n_components
+    ws = _bytes(mcd_picker_pick_workspace_size(g, G), dev) if ws is None else ws
+    _check(lib().mcd_picker_pick(p.handle, g.handle, measure, _p(t), G, _p(vb), mode, _p(index), _p(deltas),
+                                 _p(used_fallback), _p(labels), _p(n_components), _p(ws),
+                                 ws.numel() * ws.element_size()))
+    return index, deltas, used_fallback, labels[:g.n], n_components
+
+
+def mcd_picker_export(p: PickerHandle) -> dict:
+    dev = p.ctx.device
+    out = dict(params=_empty(MLP_PARAMS, torch.float32, dev), mean=_empty(MLP_IN, torch.float32, dev),
+               std=_empty(MLP_IN, torch.float32, dev), lo=_empty(MLP_IN, torch.float32, dev),
+               hi=_empty(MLP_IN, torch.float32, dev))
+    margin = ctypes.c_float()
+    _check(lib().mcd_picker_export(p.handle, _p(out["params"]), _p(out["mean"]), _p(out["std"]), _p(out["lo"]),
+                                   _p(out["hi"]), ctypes.byref(margin)))
+    out["margin"] = margin.value
+    return out
+
+
+def mcd_picker_import(p: PickerHandle, params, mean, std, lo, hi, margin: float = PICKER_MARGIN) -> None:
+    _check(lib().mcd_picker_import(p.handle, _p(params), _p(mean), _p(std), _p(lo), _p(hi), margin))
+
+
+def mcd_picker_save(p: PickerHandle, path: str) -> None:
+    _check(lib().mcd_picker_save(p.handle, os.fsencode(path)))
+
+
+def mcd_picker_load(p: PickerHandle, path: str) -> None:
+    _check(lib().mcd_picker_load(p.handle, os.fsencode(path)))
+
+
+def mcd_picker_check_file(path: str) -> None:
+    _check(lib().mcd_picker_check_file(os.fsencode(path)))
 
 
 KEPT_SEGMENTS = 16384

@@ -52,3 +52,75 @@ def test_kept_segments_constant_matches_header():
     text = open(M.HEADER).read()
     v = int(re.search(r"#define MCD_KEPT_SEGMENTS (\d+)", text).group(1))
     assert v == M.KEPT_SEGMENTS
+
+
+def _checkpoint_bytes(params, mean, std, lo, hi, margin=0.25, version=1, grid=(64, 9, 7, 900), shape=(66, 64, 8513)):
+    """A picker checkpoint laid out as include/mcd.h documents it, with the
+    IEEE CRC-32 of zlib."""
+    import struct
+    import zlib
+
+    import numpy as np
+    head = b"MCDPICK\0" + struct.pack("<IIII", version, *shape) + struct.pack("<ii", grid[0], 0)
+    head += struct.pack("<qqq", *grid[1:]) + struct.pack("<fI", margin, 0)
+    assert len(head) == 64
+    body = np.concatenate([np.asarray(a, "<f4") for a in (params, mean, std, lo, hi)]).tobytes()
+    data = head + body
+    return data + struct.pack("<I", zlib.crc32(data))
+
+
+def test_picker_checkpoint_checks_on_host(tmp_path):
+    import numpy as np
+    rng = np.random.default_rng(0)
+    p = rng.normal(0, 0.1, 8513).astype(np.float32)
+    mean, std = rng.normal(0, 1, 66), rng.uniform(0.5, 2, 66)
+    lo, hi = -np.ones(66), np.ones(66)
+    good = _checkpoint_bytes(p, mean, std, lo, hi)
+    assert len(good) == 64 + 4 * (8513 + 4 * 66) + 4
+    path = tmp_path / "picker.ckpt"
+
+    def status(data):
+        path.write_bytes(data)
+        try:
+            M.mcd_picker_check_file(str(path))
+            return 0
+        except M.MCDError as e:
+            return e.status
+
+    assert status(good) == 0
+    flipped = bytearray(good)
+    flipped[64 + 4 * 100] ^= 0x10  # one bit of a weight: the CRC no longer matches
+    bad_std = std.copy()
+    bad_std[3] = 0.0
+    nan_p = p.copy()
+    nan_p[7] = np.nan
+    cases = {
+        "bit flip": bytes(flipped),
+        "truncated": good[:-1],
+        "trailing byte": good + b"\0",
+        "bad magic": b"MCDPICX\0" + good[8:],
+        "version 2": _checkpoint_bytes(p, mean, std, lo, hi, version=2),
+        "other grid": _checkpoint_bytes(p, mean, std, lo, hi, grid=(64, 9, 7, 1000)),
+        "other shape": _checkpoint_bytes(p, mean, std, lo, hi, shape=(66, 32, 8513)),
+        "zero std": _checkpoint_bytes(p, mean, bad_std, lo, hi),
+        "nan weight": _checkpoint_bytes(nan_p, mean, std, lo, hi),
+        "negative margin": _checkpoint_bytes(p, mean, std, lo, hi, margin=-0.5),
+        "empty": b"",
+    }
+    for name, data in cases.items():
+        assert status(data) == -9, name
+    missing = tmp_path / "absent.ckpt"
+    with pytest.raises(M.MCDError) as ei:
+        M.mcd_picker_check_file(str(missing))
+    assert ei.value.status == -9
+    assert M.lib().mcd_picker_check_file(None) == -1
+    assert M.mcd_status_string(-9) == "MCD_ERR_CHECKPOINT"
+
+
+def test_picker_calls_reject_null_without_device():
+    L = M.lib()
+    assert L.mcd_picker_create(None, 0, None) == -1
+    assert L.mcd_picker_pick(None, None, 0, None, 1, None, 0, None, None, None, None, None, None, 0) == -1
+    assert L.mcd_picker_load(None, b"x") == -1
+    assert L.mcd_picker_save(None, b"x") == -1
+    assert L.mcd_picker_destroy(None) == 0

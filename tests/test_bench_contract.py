@@ -20,18 +20,26 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
-    # the committed summary matches the committed sources
-    tri = bench.profiled_traffic(["triangles"])
-    wpc = bench.profiled_traffic(["prune_components"])
-    assert tri is not None and tri > 0 and wpc is not None and wpc > 0
-    assert bench.profiled_traffic(["no_such_stage"]) is None
-    # a copy of the tree whose triangle kernel differs by one byte: that
-    # stage's traffic is withdrawn, the other stage's stays
+    # a counter record taken with the current sources is reported; once a
+    # kernel source differs by one byte, that stage's traffic is withdrawn
+    # and the other stage's stays
+    import hashlib
+    import json
     root = tmp_path / "tree"
-    shutil.copytree(os.path.join(ROOT, "profiles"), root / "profiles")
-    shutil.copytree(os.path.join(ROOT, "paper_2412_12382_amd", "csrc"), root / "paper_2412_12382_amd" / "csrc")
-    with open(root / "paper_2412_12382_amd" / "csrc" / "tc.hip", "a") as f:
-        f.write("\n")
+    csrc = root / "paper_2412_12382_amd" / "csrc"
+    shutil.copytree(os.path.join(ROOT, "paper_2412_12382_amd", "csrc"), csrc)
+    h = lambda f: hashlib.sha256(open(csrc / f, "rb").read()).hexdigest()[:16]
+    rec = {"triangles": {"sources": {"tc.hip": h("tc.hip")}, "read_bytes": 3.0e12, "write_bytes": 1.0e12},
+           "prune_components": {"sources": {"weight.hip": h("weight.hip"), "cc.hip": h("cc.hip")},
+                                "read_bytes": 1.0e10, "write_bytes": 5.0e9}}
+    (root / "profiles").mkdir()
+    (root / "profiles" / "pipeline_rmat_s26_hbm_traffic.md").write_text(
+        "# record\n\n```json\n" + json.dumps(rec, indent=1) + "\n```\n")
     monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.profiled_traffic(["triangles"]) == 4.0e12
+    assert bench.profiled_traffic(["prune_components"]) == 1.5e10
+    assert bench.profiled_traffic(["no_such_stage"]) is None
+    with open(csrc / "tc.hip", "a") as f:
+        f.write("\n")
     assert bench.profiled_traffic(["triangles"]) is None
-    assert bench.profiled_traffic(["prune_components"]) == wpc
+    assert bench.profiled_traffic(["prune_components"]) == 1.5e10

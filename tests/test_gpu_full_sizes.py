@@ -47,8 +47,9 @@ def test_c2_rmat_s20_percentile_both_measures():
         assert int(r["n_kept"].item()) == int(keep_o.sum())
         if measure == oracle.TECTONIC:
             w_o = oracle.tectonic(lo_o, hi_o, t_o, deg)
-            w = r["w_f32"].cpu().numpy()[order].astype(np.float64)
-            assert np.all(np.abs(w - w_o) <= 1e-6 * np.abs(w_o))
+            w = r["w_f32"].cpu().numpy()[order]
+            assert np.all(np.abs(w.astype(np.float64) - w_o) <= 1e-6 * np.abs(w_o))
+            assert np.array_equal(w.view(np.int32), w_o.astype(np.float32).view(np.int32))
         else:
             assert np.array_equal(r["w_i32"].cpu().numpy()[order].astype(np.int64),
                                   oracle.tw(lo_o, hi_o, t_o, deg))
@@ -148,6 +149,7 @@ def test_c5_rmat_s26_sampled_edges_and_label_properties():
     assert np.array_equal(dg[qu], du) and np.array_equal(dg[qv], dv)
     w_o = to.astype(np.float64) / (du.astype(np.float64) + dv)
     assert np.all(np.abs(wg.astype(np.float64) - w_o) <= 1e-6 * w_o)
+    assert np.array_equal(wg.view(np.int32), w_o.astype(np.float32).view(np.int32))
     keep_o = np.array([Fraction(int(a), int(b_ + c_)) >= Fraction(*delta) for a, b_, c_ in zip(to, du, dv)])
     assert np.array_equal(kg.astype(bool), keep_o)
     # counts agree between the mask, the kept list and the 16-point sweep

@@ -262,3 +262,96 @@ def test_picker_gain_on_planted_batch():
     print(f"planted batch val ARI: picker {picked:.4f}  per-graph best {best:.4f}  best global {glob:.4f}")
     assert picked > glob + 0.05
     assert losses[-1] < 0.1 * losses[0]
+
+
+def _he_uniform_expected(seed):
+    """The documented initial weights: weight i of a layer with fan-in f is
+    (2 u_i - 1) sqrt(6/f) in fp64, rounded to fp32, u_i the input module's
+    Philox uniform of counter i under (seed, "MLP0"); biases zero."""
+    import math
+    u = gg.uniforms(seed, 0x4D4C5030, mlp.NPAR)
+    p = np.zeros(mlp.NPAR, np.float32)
+    o = 0
+    for fan_out, fan_in in ((64, 66), (64, 64), (1, 64)):
+        k = fan_out * fan_in
+        p[o:o + k] = ((2.0 * u[o:o + k] - 1.0) * math.sqrt(6.0 / fan_in)).astype(np.float32)
+        o += k + fan_out
+    return p
+
+
+def test_picker_object_initial_weights():
+    from gpu_util import ctx
+    for seed in (0, 7, 2**40 + 3):
+        h = M.mcd_picker_create(ctx(), seed)
+        st = M.mcd_picker_export(h)
+        want = _he_uniform_expected(seed)
+        assert np.array_equal(st["params"].cpu().numpy().view(np.int32), want.view(np.int32)), seed
+        assert st["margin"] == np.float32(0.25)
+
+
+def test_picker_fit_equals_the_step_sequence():
+    # mcd_picker_fit = standardisation + range + Adam steps from the seeded
+    # weights: the same kernels called one by one give the same bits
+    from gpu_util import ctx
+    B, steps, lr, wd = 24, 5, 3e-3, 1.0
+    rng = np.random.default_rng(11)
+    x = cuda(rng.uniform(0, 1, (B, mlp.NI)).astype(np.float32))
+    y = cuda(rng.uniform(0, 1, B).astype(np.float32))
+    h = M.mcd_picker_create(ctx(), 5)
+    losses = M.mcd_picker_fit(h, x, y, steps, lr, wd, 1.0, 0.25)
+    got = M.mcd_picker_export(h)
+    params = cuda(_he_uniform_expected(5))
+    m1, m2 = torch.zeros_like(params), torch.zeros_like(params)
+    mean, std = M.mcd_feature_stats(ctx(), x, 1.0)
+    lo, hi = M.mcd_feature_range(ctx(), x)
+    ref_losses = []
+    for s in range(1, steps + 1):
+        ref_losses.append(M.mcd_mlp_train_step(ctx(), params, m1, m2, s, lr, mean, std, x, y, weight_decay=wd).item())
+    assert torch.equal(got["params"], params) and torch.equal(got["mean"], mean) and torch.equal(got["std"], std)
+    assert torch.equal(got["lo"], lo) and torch.equal(got["hi"], hi)
+    assert losses.cpu().numpy().tolist() == ref_losses
+
+
+def test_picker_checkpoint_save_load_pick_identical(tmp_path):
+    # save -> load -> pick equals the in-memory pick bit for bit; a corrupted
+    # file is refused and leaves the loading picker untouched
+    from gpu_util import ctx, build
+    from paper_2412_12382_amd import picker as PK
+    G = 32
+    b = gg.sbm_batch(G, n_max=5000)
+    vbase = cuda(b["vbase"])
+    g = build(b["src"], b["dst"], b["n"])
+    t = M.mcd_triangles(g)
+    _, ari, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, PK.GRID, vbase=vbase, truth=cuda(b["truth"]))
+    _, y = M.mcd_sweep_targets(ctx(), ari)
+    x = M.mcd_features(g, t, vbase)
+    model, _ = PK.train(ctx(), x[: G // 2].contiguous(), y[: G // 2].contiguous(), steps=300)
+    path = str(tmp_path / "picker.ckpt")
+    model.save(path)
+    M.mcd_picker_check_file(path)
+    loaded = PK.load(ctx(), path)
+    for mode in ("auto", "force", "off"):
+        a = PK.pick(g, t, model, vbase, fallback=mode)
+        c = PK.pick(g, t, loaded, vbase, fallback=mode)
+        for u, v in zip(a, c):
+            assert torch.equal(u, v), mode
+    for k in ("params", "mean", "std", "lo", "hi"):
+        assert torch.equal(getattr(model, k), getattr(loaded, k)), k
+    # import of the exported state picks the same
+    other = M.mcd_picker_create(ctx(), 99)
+    M.mcd_picker_import(other, model.params, model.mean, model.std, model.lo, model.hi, model.margin)
+    a = PK.pick(g, t, model, vbase)
+    c = M.mcd_picker_pick(other, g, M.MCD_SIM_TECTONIC, t, vbase=vbase)
+    assert torch.equal(a[0], c[0]) and torch.equal(a[1], c[1]) and torch.equal(a[2], c[3])
+    # a corrupted checkpoint: refused, the picker keeps its state
+    data = bytearray(open(path, "rb").read())
+    data[64 + 4 * 1000] ^= 1
+    bad = str(tmp_path / "bad.ckpt")
+    open(bad, "wb").write(bytes(data))
+    before = M.mcd_picker_export(loaded.handle)
+    with pytest.raises(M.MCDError) as ei:
+        M.mcd_picker_load(loaded.handle, bad)
+    assert ei.value.status == -9
+    after = M.mcd_picker_export(loaded.handle)
+    for k in ("params", "mean", "std", "lo", "hi"):
+        assert torch.equal(before[k], after[k]), k

@@ -75,3 +75,71 @@ def test_range_guard_hand_cases():
     fb = np.array([[k, 50] for k in range(6)])
     got = mlp.choose_thresholds(mlp.out_of_range(x, lo, hi, 0.25), picked, fb)
     assert got.tolist() == [[9, 900], [1, 50], [2, 50], [3, 50], [9, 900], [9, 900]]
+
+
+def _flat(kind, i, j=0):
+    """Index of one parameter in the flat vector, from the documented layout
+    W1[64][66], b1[64], W2[64][64], b2[64], W3[64], b3 (row-major, output
+    index first)."""
+    return {"W1": i * 66 + j, "b1": 4224 + i, "W2": 4288 + i * 64 + j, "b2": 8384 + i, "W3": 8448 + i,
+            "b3": 8512}[kind]
+
+
+def test_forward_hand_computed_sparse_network():
+    # a network with a handful of nonzero weights, evaluated by hand; every
+    # value is dyadic, so the fp64 forward must reproduce it exactly.  The
+    # standardisation (x - mean)/std, both ReLUs, the orientation of W2 and
+    # the flat layout all change the result if mistaken.
+    p = np.zeros(mlp.NPAR)
+    for (k, i, j), val in {("W1", 0, 3): 1.5, ("W1", 0, 65): 0.5, ("b1", 0, 0): -1.0, ("W1", 1, 3): -1.0,
+                           ("b1", 1, 0): 0.5, ("W1", 2, 65): 1.0, ("W2", 0, 0): 1.0, ("W2", 0, 2): 2.0,
+                           ("W2", 2, 0): -7.0, ("b2", 0, 0): -0.5, ("W2", 1, 1): 5.0, ("b2", 1, 0): 0.25,
+                           ("W3", 0, 0): 2.0, ("W3", 1, 0): -4.0, ("W3", 2, 0): 3.0, ("b3", 0, 0): 0.125}.items():
+        p[_flat(k, i, j)] = val
+    assert mlp.NPAR == 8513
+    mean, std = np.zeros(mlp.NI), np.ones(mlp.NI)
+    mean[3], std[3], mean[65], std[65] = 1.0, 2.0, -2.0, 4.0
+    x = np.zeros((2, mlp.NI))
+    x[0, 3], x[0, 65] = 5.0, 6.0   # standardised: 2, 2
+    x[1, 3], x[1, 65] = 1.0, -2.0  # standardised: 0, 0
+    # row 0: a1 = (1.5*2 + 0.5*2 - 1, -1*2 + 0.5, 1*2) = (3, -1.5, 2) -> h1 = (3, 0, 2)
+    #        a2 = (3 + 2*2 - 0.5, 5*0 + 0.25, -7*3) = (6.5, 0.25, -21) -> h2 = (6.5, 0.25, 0)
+    #        y = 2*6.5 - 4*0.25 + 3*0 + 0.125 = 12.125
+    # row 1: a1 = (-1, 0.5, 0) -> h1 = (0, 0.5, 0); a2 = (-0.5, 2.75, 0) -> h2 = (0, 2.75, 0)
+    #        y = -4*2.75 + 0.125 = -10.875
+    y, _ = mlp.forward(p, mean, std, x)
+    assert y.tolist() == [12.125, -10.875]
+
+
+def _features_of(n, edges):
+    import oracle
+    e = np.array(sorted((min(a, b), max(a, b)) for a, b in edges), np.int32).reshape(-1, 2)
+    lo, hi = e[:, 0].copy(), e[:, 1].copy()
+    deg = oracle.degrees(n, lo, hi)
+    t = oracle.triangles(n, lo, hi)
+    return mlp.features(n, lo, hi, t, deg)
+
+
+def test_features_on_complete_graph_and_star():
+    import math
+    # K5 (+ 3 isolated vertices): t = 3, deg u + deg v = 8 on every edge, so
+    # every edge falls in bin floor(128*3/8) = 48; 2m/n = 20/8, max degree 4
+    x = _features_of(8, [(a, b) for a in range(5) for b in range(a + 1, 5)])
+    want = np.zeros(mlp.NI)
+    want[48] = 1.0
+    want[64], want[65] = math.log(3.5), math.log(5.0)
+    assert np.allclose(x, want, rtol=1e-15, atol=0)
+    # star with 7 leaves: no triangles, every edge in bin 0; 2m/n = 14/8, max degree 7
+    x = _features_of(8, [(0, k) for k in range(1, 8)])
+    want = np.zeros(mlp.NI)
+    want[0] = 1.0
+    want[64], want[65] = math.log(2.75), math.log(8.0)
+    assert np.allclose(x, want, rtol=1e-15, atol=0)
+    # the wheel W5 (hub 0, rim 1..5): rim edges t = 1, D = 6 -> bin 21; spokes
+    # t = 2, D = 8 -> bin 32; 2m/n = 20/6, max degree 5
+    rim = [(k, k % 5 + 1) for k in range(1, 6)]
+    x = _features_of(6, [(0, k) for k in range(1, 6)] + rim)
+    want = np.zeros(mlp.NI)
+    want[21], want[32] = 0.5, 0.5
+    want[64], want[65] = math.log1p(20 / 6), math.log(6.0)
+    assert np.allclose(x, want, rtol=1e-15, atol=0)
