@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-picker", action="store_true", help="skip picker training (use delta 3/50)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default triangle-count parameters")
+    ap.add_argument("--no-cpu-single", action="store_true", help="skip the one-thread oracle runs")
+    ap.add_argument("--oracle-leg", default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -85,6 +87,36 @@ def profiled_traffic(stages):
                 return None
         total += r["read_bytes"] + r["write_bytes"]
     return total
+
+
+TW_DELTA = (-10, 1)
+# the build's per-edge degree sums (read by every weights pass instead of two
+# degree gathers), from the committed kernel trace of R-MAT scale 26
+EDGE_DSUM_PROFILED = {"kernel": "k_edge_dsum", "ms": 7.26, "bytes": "8m + 4m (src, adj read; dsum written) "
+                      "plus the gathered degrees", "source": "profiles/pipeline_rmat_s26_kernel_trace.md"}
+
+
+def wpc_roofline(m: int, n: int, kept: int, ms: float, traffic):
+    """HBM roofline of one weights + prune + components pass.  achieved/frac
+    count the bytes the fused pass must move: t and the degree sums read and
+    the weight written per edge (12m), the keep bits (m/8), both endpoints of
+    every kept edge (8 per kept edge) and four streams over the vertices
+    (parent and label written by the init, parent read by the minimum and the
+    label passes: 16n).  frac_survey_formula uses the scope table's B_wpc =
+    16m + m/8 + 8(n+1) + 8 kept + 12n, which also charges the head vertex and
+    its degree per edge (read by the build's degree-sum pass here) and the row
+    offsets (not read).  traffic: measured HBM bytes per call, when counters
+    of the current sources exist."""
+    moved = 12.0 * m + m / 8.0 + 8.0 * kept + 16.0 * n
+    formula = 16.0 * m + m / 8.0 + 8.0 * (n + 1) + 8.0 * kept + 12.0 * n
+    sec = ms * 1e-3
+    r = {"bound": "hbm", "achieved": moved / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": moved / sec / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": moved,
+         "survey_formula_bytes": formula, "frac_survey_formula": formula / sec / 1e9 / HBM_PEAK_GBS,
+         "traffic": traffic}
+    if traffic:
+        r["traffic_frac"] = traffic / sec / 1e9 / HBM_PEAK_GBS
+    return r
 
 
 def tw_vs_tectonic(M, dev, G: int = 64):
@@ -114,22 +146,83 @@ def tw_vs_tectonic(M, dev, G: int = 64):
                 tw_at_least_tectonic=int((out["tw"] >= out["tectonic"]).sum()))
 
 
-def cpu_baseline(scale: int, ef: int, seed: int, num: int, den: int):
-    """The oracle (plain C, OpenMP) on a bounded sample of the same workload
-    family: R-MAT at a smaller scale, same generator and a fixed threshold."""
+def _oracle_leg(spec: str) -> dict:
+    """One oracle run (called in a child process by cpu_baseline, so that the
+    child's peak RSS is the oracle's): canonicalise, triangles, Tectonic
+    weights, prune at the threshold, BFS components."""
     import graphgen as gg
     import oracle
 
-    src, dst, n = gg.rmat(scale, ef, seed=seed)
+    kind, a, b = spec.split(":")
+    if kind == "rmat":
+        src, dst, n = gg.rmat(int(a), 16, seed=int(b))
+        name = f"R-MAT scale {a} edge factor 16 seed {b}"
+    elif kind == "sbm":
+        c = gg.sbm_c1()
+        src, dst, n = c["src"], c["dst"], c["n"]
+        name = "planted partition, 1000 vertices in 4 blocks (p_in 0.10, p_out 0.005) seed 0"
+    else:
+        c = gg.dcsbm()
+        src, dst, n = c["src"], c["dst"], c["n"]
+        name = "degree-corrected SBM, 10^6 vertices (exponent 2.5, mean degree 20)"
     tm = {}
     t0 = time.perf_counter()
-    r = oracle.run(n, src, dst, oracle.TECTONIC, num, den, tm)
+    r = oracle.run(n, src, dst, oracle.TECTONIC, 3, 50, tm)
     dt = time.perf_counter() - t0
-    m = len(r["lo"])
-    return dict(value=m / dt, unit="edges/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"R-MAT scale {scale} edge factor {ef} (n={n}, m={m}): canonicalise, triangles, "
-                       f"Tectonic weights, prune at {num}/{den}, BFS components; {dt:.2f} s",
-                seconds=dt, stages_s={k: round(v, 3) for k, v in tm.items()})
+    # peak resident memory of this process since its exec (VmHWM; getrusage's
+    # maximum would carry the parent's high-water mark over the fork)
+    hwm_kib = 0
+    for line in open("/proc/self/status"):
+        if line.startswith("VmHWM:"):
+            hwm_kib = int(line.split()[1])
+    return dict(workload=name, n=int(n), m=int(len(r["lo"])), seconds=dt, threads=oracle.num_threads(),
+                stages_s={k: round(v, 3) for k, v in tm.items()}, peak_rss_gib=round(hwm_kib / 2**20, 3))
+
+
+def _host_facts() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), cpu_model=model)
+
+
+def cpu_baseline(scale: int, ef: int, seed: int, single: bool = True):
+    """The oracle (plain C, OpenMP) on a bounded sample of the workload family:
+    R-MAT at a smaller scale, same generator, Tectonic pruned at 3/50, on all
+    host threads; each leg in a child process whose peak RSS is reported.
+    With single=True also one-thread runs of the small configurations (the
+    planted partition, R-MAT scale 20, the degree-corrected SBM)."""
+    import subprocess
+
+    def leg(spec, threads=None):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = str(threads)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-leg", spec], env=env,
+                           capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"oracle leg {spec} failed: {r.stderr[-2000:]}")
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    main_leg = leg(f"rmat:{scale}:{seed}")
+    res = dict(value=main_leg["m"] / main_leg["seconds"], unit="edges/s", cores=main_leg["threads"], kind="oracle",
+               sample=f"{main_leg['workload']} (n={main_leg['n']}, m={main_leg['m']}): canonicalise, triangles, "
+                      f"Tectonic weights, prune at 3/50, BFS components; {main_leg['seconds']:.2f} s",
+               seconds=main_leg["seconds"], stages_s=main_leg["stages_s"], peak_rss_gib=main_leg["peak_rss_gib"],
+               host=_host_facts())
+    if single:
+        res["one_thread"] = {}
+        for name, spec in (("C1", "sbm:0:0"), ("C2", "rmat:20:1"), ("C3", "dcsbm:0:2")):
+            r = leg(spec, threads=1)
+            res["one_thread"][name] = dict(workload=r["workload"], m=r["m"], seconds=round(r["seconds"], 3),
+                                           edges_per_s=r["m"] / r["seconds"], stages_s=r["stages_s"],
+                                           peak_rss_gib=r["peak_rss_gib"])
+    return res
 
 
 def picker_study(M, PK, dev):
@@ -302,6 +395,9 @@ def next_rows_study(M, PK, model, dev):
 
 def main():
     args = parse()
+    if args.oracle_leg:  # child process of cpu_baseline: the oracle only, no GPU
+        print(json.dumps(_oracle_leg(args.oracle_leg)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded over "
               f"several GPUs.", file=sys.stderr)
@@ -353,6 +449,12 @@ def main():
     n_kept = torch.empty(1, dtype=torch.int64, device=dev)
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ncc = torch.empty(1, dtype=torch.int64, device=dev)
+    # the TW pass (Eq. eq:tw) writes its own integer weights, mask and labels
+    wi_tw = torch.empty(P, dtype=torch.int32, device=dev)
+    keep_tw = torch.empty((P + 31) // 32 + 1, dtype=torch.int32, device=dev)
+    n_kept_tw = torch.empty(1, dtype=torch.int64, device=dev)
+    labels_tw = torch.empty(n, dtype=torch.int32, device=dev)
+    ncc_tw = torch.empty(1, dtype=torch.int64, device=dev)
     vbase = torch.tensor([0, n], dtype=torch.int64, device=dev)
     x = torch.empty((1, M.MLP_IN), dtype=torch.float32, device=dev)
     yhat = torch.empty(1, dtype=torch.float32, device=dev)
@@ -367,7 +469,7 @@ def main():
     log(f"HBM in use after allocation: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    stage_names = ["build", "triangles", "picker", "sweep16", "prune_components"]
+    stage_names = ["build", "triangles", "picker", "sweep16", "prune_components", "prune_components_tw"]
 
     def step():
         e = [ev() for _ in range(len(stage_names) + 1)]
@@ -396,6 +498,11 @@ def main():
         M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, deltas=pdelta, vbase=vbase, w_f32=wf, keep_bits=keep,
                                n_kept=n_kept, labels=labels, n_components=ncc, ws=ws)
         e[5].record()
+        # the paper's own pipeline (Table tab:syn times TW + prune + components)
+        # at TW >= -10, a point of its TW grid (Table tab:params)
+        M.mcd_prune_components(g, M.MCD_SIM_TW, t, delta=TW_DELTA, w_i32=wi_tw, keep_bits=keep_tw,
+                               n_kept=n_kept_tw, labels=labels_tw, n_components=ncc_tw, ws=ws, want_f32=False)
+        e[6].record()
         return g, e
 
     # the scratch buffer serves every stage: at least the build's, the
@@ -448,15 +555,22 @@ def main():
     tc_bytes = 4.0 * S + 8.0 * m + 8.0 * (n + 1)
     tc_gbs = tc_bytes / (avg["triangles"] * 1e-3) / 1e9
     kept = int(n_kept.item())
-    tri = int(t[:m].sum(dtype=torch.int64).item()) // 3
-    # weight + prune + components, algorithmic bytes: t, head and the head's
-    # degree read per edge, w written, keep bits written, row offsets; then
-    # the kept edges read once by the union step and 12 bytes per vertex
-    # (parent, label, original id)
-    wpc_bytes = 16.0 * m + m / 8.0 + 8.0 * (n + 1) + 8.0 * kept + 12.0 * n
-    wpc_ms = avg["prune_components"]
-    wpc_gbs = wpc_bytes / (wpc_ms * 1e-3) / 1e9
     ncomp = int(ncc.item())
+    tri = int(t[:m].sum(dtype=torch.int64).item()) // 3
+    wpc_ms = avg["prune_components"]
+    wpc = wpc_roofline(m, n, kept, wpc_ms, profiled_traffic(["prune_components"]))
+    wpc_gbs = wpc["achieved"]
+    kept_tw = int(n_kept_tw.item())
+    wpc_tw = wpc_roofline(m, n, kept_tw, avg["prune_components_tw"], None)
+    # the same Tectonic pass with every edge kept (threshold 0): the union
+    # step at its heaviest
+    torch.cuda.synchronize()
+    ms_all = _time_ms(lambda: M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, delta=(0, 1), w_f32=wf, keep_bits=keep,
+                                                     n_kept=n_kept, labels=labels, n_components=ncc, ws=ws), reps=3)
+    kept_all = int(n_kept.item())
+    wpc_all = wpc_roofline(m, n, kept_all, ms_all, None)
+    wpc_all.update(delta="0/1", n_kept=kept_all, n_components=int(ncc.item()), ms=ms_all)
+    log(f"weights+prune+components with every edge kept: {ms_all:.2f} ms, {wpc_all['achieved']:.0f} GB/s")
     sw = sweep_stats.cpu().numpy()[0]
     pick_delta = [int(v_) for v_ in pdelta.cpu().numpy()[0]]
     net_pick = [int(v_) for v_ in net_delta.cpu().numpy()[0]] if model is not None else None
@@ -467,8 +581,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle on R-MAT scale {args.cpu_scale}")
-        cpu = cpu_baseline(args.cpu_scale, args.edge_factor, args.seed, 3, 50)
-        log(f"oracle: {cpu['value']:.3e} edges/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
+        cpu = cpu_baseline(args.cpu_scale, args.edge_factor, args.seed, single=not args.no_cpu_single)
+        log(f"oracle: {cpu['value']:.3e} edges/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s, "
+            f"peak RSS {cpu['peak_rss_gib']:.1f} GiB)")
 
     out = {
         "metric": "edges/s (weight+prune+CC) R-MAT s26; ARI & latency learned vs swept threshold",
@@ -487,19 +602,23 @@ def main():
                                f"(a,b,c,d)=(0.57,0.19,0.19,0.05), symmetrised, deduplicated; Tectonic weights, "
                                f"learned threshold, 16-point check sweep k/50, components",
                    "n": n, "m": m, "pairs": P,
-                   "step": "build+triangles+picker+weights/prune/components+sweep16",
+                   "step": "build+triangles+picker+sweep16+weights/prune/components (Tectonic, TW)",
                    "triangle_params": tuned},
+        "value_scope": "whole step: m / (build + triangles + picker + sweep16 + weights/prune/components "
+                       "(Tectonic, then TW)); the metric's weight+prune+CC pass alone is wpc_edges_per_s",
         "stages_ms": {k: round(v_, 3) for k, v_ in avg.items()},
         "wpc_edges_per_s": m / (wpc_ms * 1e-3),
+        "wpc_tw_edges_per_s": m / (avg["prune_components_tw"] * 1e-3),
         "roofline": {"bound": "hbm", "achieved": tc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": tc_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(["triangles"]),
                      "kernel": "triangles", "algorithmic_bytes": tc_bytes, "suffix_elements": S,
                      "merge_work_W": W},
-        "roofline_wpc": {"bound": "hbm", "achieved": wpc_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": wpc_gbs / HBM_PEAK_GBS, "algorithmic_bytes": wpc_bytes,
-                         "traffic": profiled_traffic(["prune_components"]),
-                         "kernel": "prune_components (k_cc_init, k_weigh_prune with unions, k_cc_min, "
-                                   "k_cc_label)"},
+        "roofline_wpc": dict(wpc, delta="%d/%d" % tuple(pick_delta), n_kept=kept, ms=wpc_ms,
+                             kernel="prune_components (k_cc_init, k_weigh_prune with unions, k_cc_min, k_cc_label)"),
+        "roofline_wpc_tw": dict(wpc_tw, delta="%d/%d" % TW_DELTA, n_kept=kept_tw, n_components=int(ncc_tw.item()),
+                                ms=avg["prune_components_tw"]),
+        "roofline_wpc_all_kept": wpc_all,
+        "k_edge_dsum_profiled": EDGE_DSUM_PROFILED,
         "results": {"triangles": tri, "picked_delta": pick_delta, "n_kept": kept, "n_components": ncomp,
                     "sweep16": {"delta": [f"{a}/{b}" for a, b in grid16],
                                 "m_kept": sw[:, 0].tolist(), "n_components": sw[:, 1].tolist(),

@@ -102,7 +102,10 @@ mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream);
  *                [0, 2^18], default 2^18 (0 disables the bitmap path);
  *   "k4_row_cache" mcd_k4 keeps the row offsets of the common neighbours
  *                of a long row in LDS when they fit, 0 or 1, default 1
- *                (0: read them per pair).
+ *                (0: read them per pair);
+ *   "sweep_shape" launch shape of mcd_sweep's level loop (one persistent
+ *                launch): 0 = 1024 threads per block, 1 = 512, 2 = 256
+ *                threads per block, default 0.
  * Errors: MCD_ERR_INVALID_ARG (unknown name), MCD_ERR_RANGE (bad value). */
 mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value);
 mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* value);
@@ -503,10 +506,12 @@ mcd_status mcd_picker_pick_workspace_size(const mcd_graph* g, int32_t n_graphs, 
  *   deltas:        device int64[n_graphs][2], the threshold each graph used (may be NULL);
  *   used_fallback: device int32[n_graphs], 1 where the sweep's threshold was used (may be NULL);
  *   labels, n_components: as for mcd_components over the whole batch.
- * MCD_PICK_AUTO reads the guard's flags back once (synchronous) and runs the
- * sweep only if some graph needs it; the other modes are asynchronous.
- * Errors: MCD_ERR_INVALID_ARG (unprepared picker, other context),
- * MCD_ERR_WORKSPACE. */
+ * Asynchronous in every mode (the call can be captured in a HIP graph):
+ * MCD_PICK_AUTO decides on the device whether any graph needs the sweep, whose
+ * kernels otherwise return at once.
+ * The work goes to the graph's context stream; picker and graph must be on
+ * one device.  Errors: MCD_ERR_INVALID_ARG (unprepared picker, another
+ * device), MCD_ERR_WORKSPACE. */
 mcd_status mcd_picker_pick(const mcd_picker* p, const mcd_graph* g, mcd_measure measure, const int32_t* t,
                            int32_t n_graphs, const int64_t* vbase, int32_t mode, int32_t* index, int64_t* deltas,
                            int32_t* used_fallback, int32_t* labels, int64_t* n_components, void* ws,

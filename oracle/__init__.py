@@ -225,7 +225,7 @@ def run(n: int, src, dst, measure: int, num: int, den: int, timings: dict | None
     return dict(lo=lo, hi=hi, deg=deg, t=t, w=w, keep=keep, labels=labels, ncc=ncc)
 
 
-def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None, modularity=False):
+def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None, modularity=False, workers=1):
     """Algorithm 1 at every threshold of `deltas`, one graph or a batch of
     disjoint graphs (graph k owns ids [vbase[k], vbase[k+1])).
 
@@ -236,7 +236,9 @@ def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None, 
     [G][K]: Q = intra / m - volume_sq / (4 m^2) of each partition on the input
     graph (the modularity definition of Sec. 2 summed per community), where
     intra counts input edges inside one component and volume_sq sums the
-    squared degree totals of the components."""
+    squared degree totals of the components.  workers > 1 evaluates the
+    thresholds' prune and components in that many threads at once (each
+    threshold on its own, as with one worker)."""
     if vbase is None:
         vbase = np.array([0, n], np.int64)
     vbase = np.asarray(vbase, np.int64)
@@ -247,10 +249,21 @@ def sweep(n: int, lo, hi, t, deg, measure: int, deltas, truth=None, vbase=None, 
     labels_all = np.zeros((K, n), np.int32)
     egraph = np.searchsorted(vbase, lo, side="right") - 1
     m_graph = np.bincount(egraph, minlength=G).astype(np.int64)
-    for i, (num, den) in enumerate(deltas):
+    def one(i):
+        num, den = deltas[i]
         keep = prune(measure, lo, hi, t, deg, num, den)
-        labels, _ = components(n, lo, hi, keep)
-        labels_all[i] = labels
+        labels_all[i], _ = components(n, lo, hi, keep)
+        return keep
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            keeps = list(ex.map(one, range(K)))
+    else:
+        keeps = None
+    for i in range(K):
+        keep = keeps[i] if keeps is not None else one(i)
+        labels = labels_all[i]
         kept_per_graph = np.bincount(egraph, weights=keep, minlength=G).astype(np.int64)
         if modularity:
             same = (labels[lo] == labels[hi]).astype(np.int64)

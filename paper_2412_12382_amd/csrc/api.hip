@@ -208,6 +208,7 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
     c->tc_packed_range = MCD_TC_PACKED_LIMIT;
     c->tc_window_max = MCD_TC_WINDOW_LIMIT;
     c->k4_row_cache = 1;
+    c->sweep_shape = 0;
     if (hipMalloc((void**)&c->d_ctrl, sizeof(int64_t) * MCD_CTRL_WORDS) != hipSuccess) {
         delete c;
         return mcd_fail(MCD_ERR_DEVICE, "hipMalloc of the control block failed");
@@ -266,6 +267,9 @@ mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value) {
     } else if (k == "k4_row_cache") {
         REQUIRE(value == 0 || value == 1, MCD_ERR_RANGE, "k4_row_cache must be 0 or 1");
         ctx->k4_row_cache = value;
+    } else if (k == "sweep_shape") {
+        REQUIRE(value >= 0 && value <= 2, MCD_ERR_RANGE, "sweep_shape must be 0, 1 or 2");
+        ctx->sweep_shape = value;
     } else {
         return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     }
@@ -280,6 +284,7 @@ mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* valu
     else if (k == "tc_packed_range") *value = ctx->tc_packed_range;
     else if (k == "tc_window_max") *value = ctx->tc_window_max;
     else if (k == "k4_row_cache") *value = ctx->k4_row_cache;
+    else if (k == "sweep_shape") *value = ctx->sweep_shape;
     else return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     return MCD_OK;
 }
@@ -331,8 +336,8 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     const int bits = id_bits(n);
     StorageLayout G = storage_layout(storage, P, n);
     BuildLayout B = build_layout(ws, P, n);
-    int64_t* ctrl = ctx->d_ctrl;  // [0] bad id flag, [1] m, [2] max out-degree
-    mcd::fill_i64(ctrl, 4, 0, s);
+    int64_t* ctrl = ctx->d_ctrl;  // [0] bad id flag, [1] m, [2] max out-degree, [3] max degree, [4] bitmask words
+    mcd::fill_i64(ctrl, 5, 0, s);
 
     // Canonical simple graph: sort + dedup of packed (min, max) pairs.
     mcd::launch_canon(src, dst, P, n, bits, B.k1, ctrl + 0, s);
@@ -363,6 +368,7 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     mcd::launch_edge_dsum(G.src, G.adj, G.deg, m, G.dsum, s);
     mcd::launch_max_i32(B.outdeg, n, ctrl + 2, s);
     mcd::launch_max_i32(G.deg, n, ctrl + 3, s);
+    mcd::launch_bitmask_words(B.outdeg, n, ctrl + 4, s);
     // in-edge lists (edges grouped by head), in-degree = degree - out-degree
     mcd::launch_in_count(G.deg, B.outdeg, n, B.inv, s);
     mcd::exclusive_scan_i32_i64(B.inv, n, G.in_off, B.scan, s);
@@ -374,7 +380,7 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     mcd::launch_in_keys(G.src, G.adj, G.off, m, B.k1, suf, s);
     uint64_t* by_head = mcd::radix_sort_u64_kv(B.k1, B.k2, suf, suf2, &suf_sorted, m, bits, B.radix, s, 32);
     mcd::launch_in_fill(by_head, suf_sorted, m, G.in_ea, s);
-    if ((st = sync_read(ctx, ctrl, ctx->h_ctrl, 4)) != MCD_OK) return st;
+    if ((st = sync_read(ctx, ctrl, ctx->h_ctrl, 5)) != MCD_OK) return st;
 
     mcd_graph* g = new mcd_graph();
     g->ctx = ctx;
@@ -384,6 +390,7 @@ mcd_status mcd_graph_build(mcd_ctx* ctx, const int32_t* src, const int32_t* dst,
     g->bits = bits;
     g->max_outdeg = (int32_t)ctx->h_ctrl[2];
     g->max_deg = (int32_t)ctx->h_ctrl[3];
+    g->bitmask_words = ctx->h_ctrl[4];
     g->off = G.off;
     g->src = G.src;
     g->adj = G.adj;

@@ -159,6 +159,24 @@ __global__ __launch_bounds__(kThreads) void k_max_i32(const int32_t* __restrict_
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)mx);
 }
 
+// Words of the triangle count's hit bitmasks for a row of d out-neighbours:
+// one bit per suffix element, the suffix after the row's j-th edge having
+// d - 1 - j elements, each suffix in whole 64-bit words:
+//   sum over L = 0 .. d-1 of ceil(L / 64) = 64 q (q + 1) / 2 + r (q + 1)
+// with d - 1 = 64 q + r.
+__global__ __launch_bounds__(kThreads) void k_bitmask_words(const int32_t* __restrict__ outdeg, int64_t n,
+                                                            unsigned long long* __restrict__ out) {
+    unsigned long long sum = 0;
+    GRID_STRIDE(v, n) {
+        const int64_t d = outdeg[v];
+        if (d < 2) continue;
+        const int64_t q = (d - 1) >> 6, r = (d - 1) & 63;
+        sum += (unsigned long long)(32 * q * (q + 1) + r * (q + 1));
+    }
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if ((threadIdx.x & 63) == 0 && sum) atomicAdd(out, sum);
+}
+
 __global__ __launch_bounds__(kThreads) void k_edges_orig(const int32_t* __restrict__ src,
                                                          const int32_t* __restrict__ adj,
                                                          const int32_t* __restrict__ perm, int64_t m,
@@ -277,6 +295,13 @@ void launch_max_i32(const int32_t* a, int64_t N, int64_t* d_out, hipStream_t s) 
     fill_i64(d_out, 1, 0, s);
     if (N <= 0) return;
     hipLaunchKernelGGL(k_max_i32, dim3(grid_for(N, 4096)), dim3(kThreads), 0, s, a, N,
+                       (unsigned long long*)d_out);
+}
+
+void launch_bitmask_words(const int32_t* outdeg, int64_t n, int64_t* d_out, hipStream_t s) {
+    fill_i64(d_out, 1, 0, s);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_bitmask_words, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, outdeg, n,
                        (unsigned long long*)d_out);
 }
 

@@ -23,6 +23,7 @@ struct mcd_ctx {
     int64_t tc_packed_range;  // widest rank range (w - v - 1) of a packed LDS table
     int64_t tc_window_max;    // widest rank range of a row held as an LDS rank window
     int64_t k4_row_cache;     // 4-cliques: keep the row offsets of L in LDS when they fit
+    int64_t sweep_shape;      // launch shape of the sweep's level loop (0, 1, 2)
     // side streams (default priority) and events on which the triangle
     // count runs its work-item classes concurrently, forked from and joined
     // back into `stream`
@@ -44,6 +45,7 @@ struct mcd_graph {
     int bits;          // bits of a vertex id in packed keys (>= 1)
     int32_t max_deg;
     int32_t max_outdeg;
+    int64_t bitmask_words;  // sum over edges of ceil(suffix length / 64)
     // Borrowed from the caller's storage buffer.  Vertices are renumbered by
     // rank (degree, original id); "new id" below means that rank.
     int64_t* off;      // [n+1] CSR row offsets of the oriented graph (rows = new ids)
@@ -129,6 +131,8 @@ void launch_orient_keys(const uint64_t* uniq, int64_t m, int bits, const int32_t
 void launch_csr_fill(const uint64_t* sorted, int64_t m, int bits, int32_t* src, int32_t* adj,
                      int32_t* outdeg, hipStream_t s);
 void launch_max_i32(const int32_t* a, int64_t N, int64_t* d_out, hipStream_t s);
+// *d_out = the words of the triangle count's hit bitmasks over all rows
+void launch_bitmask_words(const int32_t* outdeg, int64_t n, int64_t* d_out, hipStream_t s);
 void launch_edges_orig(const int32_t* src, const int32_t* adj, const int32_t* perm, int64_t m,
                        int32_t* u, int32_t* v, hipStream_t s);
 void launch_scatter_by_perm(const int32_t* val_new, const int32_t* perm, int64_t n,
@@ -209,7 +213,7 @@ size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth);
 void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
                   const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
                   mcd_sweep_stats* stats, double* ari, double* modularity, double* prf, int32_t* labels,
-                  void* ws, hipStream_t s);
+                  void* ws, hipStream_t s, const int32_t* gate = nullptr);
 
 // the threshold rule of thumb over a sweep's statistics (order as for launch_sweep)
 void launch_sweep_rule(const SweepDeltas& ds, const int* order, int G, const int64_t* vbase,
@@ -235,5 +239,7 @@ void launch_feature_stats(const float* x, int B, float min_std, float* mean, flo
 void launch_feature_range(const float* x, int B, float* lo, float* hi, hipStream_t s);
 void launch_fallback(const float* x, int B, const float* lo, const float* hi, float margin, const int64_t* picked,
                      const int64_t* fallback, int64_t* delta, int32_t* flags, hipStream_t s);
+// *any = 1 if some flags[0..B) is nonzero, else 0
+void launch_any_flag(const int32_t* flags, int B, int32_t* any, hipStream_t s);
 
 }  // namespace mcd

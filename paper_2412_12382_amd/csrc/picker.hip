@@ -349,6 +349,23 @@ void launch_fallback(const float* x, int B, const float* lo, const float* hi, fl
                        fallback, delta, flags);
 }
 
+// One block: *any = whether some flag is set (the picker's decision to run
+// the sweep, taken on the device).
+__global__ __launch_bounds__(kThreads) void k_any_flag(const int32_t* __restrict__ flags, int B,
+                                                       int32_t* __restrict__ any) {
+    __shared__ int hit;
+    if (threadIdx.x == 0) hit = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < B; i += blockDim.x)
+        if (flags[i]) hit = 1;  // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) *any = hit;
+}
+
+void launch_any_flag(const int32_t* flags, int B, int32_t* any, hipStream_t s) {
+    hipLaunchKernelGGL(k_any_flag, dim3(1), dim3(kThreads), 0, s, flags, B, any);
+}
+
 size_t features_scratch_bytes(int G) { return mcd_align(sizeof(unsigned long long) * (size_t)G * 65); }
 
 void launch_features(const mcd_graph* g, const int32_t* t, int G, const int64_t* vbase, float* x, void* ws,

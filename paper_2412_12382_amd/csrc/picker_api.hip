@@ -152,6 +152,7 @@ struct PickLayout {
     double* q;
     int32_t* rule_index;
     int64_t* rule_deltas;
+    int32_t* any;
     void* cc;
     size_t bytes;
 };
@@ -170,6 +171,7 @@ PickLayout pick_layout(void* ws, const mcd_graph* g, int G) {
     L.q = c.take<double>((size_t)G * kGridK);
     L.rule_index = c.take<int32_t>(G);
     L.rule_deltas = c.take<int64_t>(2 * (size_t)G);
+    L.any = c.take<int32_t>(1);
     L.cc = c.take<char>(mcd::cc_scratch_bytes(g));
     L.bytes = c.used;
     return L;
@@ -333,7 +335,7 @@ mcd_status mcd_picker_pick(const mcd_picker* p, const mcd_graph* g, mcd_measure 
             "NULL argument");
     REQUIRE(((uintptr_t)ws & 255u) == 0u, MCD_ERR_INVALID_ARG, "ws must be 256-byte aligned");
     REQUIRE(n_graphs >= 1, MCD_ERR_INVALID_ARG, "need n_graphs >= 1");
-    REQUIRE(p->ctx == g->ctx, MCD_ERR_INVALID_ARG, "picker and graph belong to different contexts");
+    REQUIRE(p->ctx->device == g->ctx->device, MCD_ERR_INVALID_ARG, "picker and graph live on different devices");
     REQUIRE(p->prepared, MCD_ERR_INVALID_ARG, "the picker has no standardisation: prepare, fit or load it first");
     REQUIRE(measure == MCD_SIM_TECTONIC || measure == MCD_SIM_TW || measure == MCD_SIM_K3 ||
                 measure == MCD_SIM_JACCARD || measure == MCD_SIM_K4,
@@ -356,19 +358,19 @@ mcd_status mcd_picker_pick(const mcd_picker* p, const mcd_graph* g, mcd_measure 
     mcd::launch_mlp_forward(p->params, p->mean, p->stdv, L.x, G, L.y, s);
     mcd::launch_select(L.y, G, kGridK, kGridA, kGridB, kGridC, idx, dl, s);
     mcd::launch_fallback(L.x, G, p->lo, p->hi, p->margin, nullptr, nullptr, nullptr, flags, s);
-    bool sweep = mode == MCD_PICK_FORCE_SWEEP;
-    if (mode == MCD_PICK_AUTO) {  // the one host read-back: does any graph need the sweep?
-        std::vector<int32_t> h(G);
-        MCD_HIP(hipMemcpyAsync(h.data(), flags, sizeof(int32_t) * (size_t)G, hipMemcpyDeviceToHost, s));
-        MCD_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < G && !sweep; ++k) sweep = h[k] != 0;
-    }
-    if (sweep) {  // the full sweep with modularity, and its rule of thumb (jump 1/10)
+    if (mode != MCD_PICK_NETWORK) {  // the full sweep with modularity, and its rule of thumb (jump 1/10)
+        // automatic mode decides on the device whether any graph needs the
+        // sweep: its kernels return at once otherwise
+        const int32_t* gate = nullptr;
+        if (mode == MCD_PICK_AUTO) {
+            mcd::launch_any_flag(flags, G, L.any, s);
+            gate = L.any;
+        }
         mcd::SweepDeltas ds;
         int order[MCD_SWEEP_MAX];
         grid_deltas(&ds, order);
         mcd::launch_sweep(g, measure, t, ds, order, G, vbase, nullptr, L.stats, nullptr, L.q, nullptr, nullptr,
-                          L.sweep, s);
+                          L.sweep, s, gate);
         mcd::launch_sweep_rule(ds, order, G, vbase, L.stats, L.q, 1, 10, L.rule_index, L.rule_deltas, s);
         if (mode == MCD_PICK_FORCE_SWEEP) {  // every graph takes the rule's threshold
             MCD_HIP(hipMemcpyAsync(dl, L.rule_deltas, sizeof(int64_t) * 2 * (size_t)G, hipMemcpyDeviceToDevice, s));
@@ -376,7 +378,7 @@ mcd_status mcd_picker_pick(const mcd_picker* p, const mcd_graph* g, mcd_measure 
         } else {
             mcd::launch_fallback(L.x, G, p->lo, p->hi, p->margin, dl, L.rule_deltas, dl, flags, s);
         }
-    } else if (mode == MCD_PICK_NETWORK) {
+    } else {
         mcd::fill_i32(flags, G, 0, s);
     }
     int32_t* parent = mcd::launch_components_init(g, labels, n_components, L.cc, s);

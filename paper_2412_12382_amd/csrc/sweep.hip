@@ -18,6 +18,8 @@
 //   S = sum over (cluster, class) cells of C(n_cc, 2)
 //   A = sum over clusters of C(a, 2), B = sum over classes of C(b, 2), N = C(n, 2)
 // each gathered as sum over vertices of (cell size - 1) / 2.
+#include <algorithm>
+
 #include "common.hpp"
 #include "unionfind.hpp"
 
@@ -133,13 +135,20 @@ __device__ __forceinline__ int rat_cmp64(int64_t a, int64_t b, int64_t c, int64_
     return (l > r) - (l < r);
 }
 
+// gate (nullable): a device flag; when it reads 0 the sweep's kernels return
+// at once (a caller that needs the sweep only for some inputs decides on the
+// device, without a host round trip).
+__device__ __forceinline__ bool gated_off(const int32_t* gate) { return gate && *gate == 0; }
+
 template <bool NARROW>
 __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ src,
                                                     const int32_t* __restrict__ dsum,
                                                     const int32_t* __restrict__ t, int64_t m, int measure,
                                                     SweepDeltas ds, uint8_t* __restrict__ level,
                                                     const int32_t* __restrict__ gid, int G,
-                                                    unsigned long long* __restrict__ hist) {
+                                                    unsigned long long* __restrict__ hist,
+                                                    const int32_t* __restrict__ gate) {
+    if (gated_off(gate)) return;
     extern __shared__ uint32_t h[];  // nbins counters when local (sized at launch)
     const int nbins = G * (ds.K + 1);
     const bool local = nbins <= kLevelBins;
@@ -188,7 +197,9 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
 __global__ __launch_bounds__(kThreads) void k_vertex_info(const int32_t* __restrict__ perm, int64_t n,
                                                           const int64_t* __restrict__ vbase, int G,
                                                           const int32_t* __restrict__ truth,
-                                                          int32_t* __restrict__ gid, int32_t* __restrict__ cls) {
+                                                          int32_t* __restrict__ gid, int32_t* __restrict__ cls,
+                                                          const int32_t* __restrict__ gate) {
+    if (gated_off(gate)) return;
     GRID_STRIDE(v, n) {
         const int64_t x = perm[v];
         int lo = 0, hi = G;  // last g with vbase[g] <= x
@@ -202,9 +213,21 @@ __global__ __launch_bounds__(kThreads) void k_vertex_info(const int32_t* __restr
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_init_parent(int32_t* __restrict__ parent, int64_t n) {
+__global__ __launch_bounds__(kThreads) void k_init_parent(int32_t* __restrict__ parent, int64_t n,
+                                                          const int32_t* __restrict__ gate) {
+    if (gated_off(gate)) return;
     GRID_STRIDE(v, n) parent[v] = (int32_t)v;
 }
+
+// ---- the level loop -------------------------------------------------------
+//
+// The passes below are device functions over grid-stride loops, run by one
+// persistent kernel (k_sweep_levels) whose blocks are all resident and meet
+// at grid barriers between phases.  `sh` is the block's LDS scratch
+// (kShWords 64-bit words); a pass that uses it initialises it, and ends with
+// a block barrier so the next pass may reuse it.
+
+constexpr int kShWords = 2 * kLdsGraphs;  // 16 KB
 
 // unite the endpoints of every edge at level lv.  Every level scans all m
 // level bytes, most of them for a handful of edges, so the bytes are read 16
@@ -214,10 +237,8 @@ __device__ __forceinline__ bool has_byte(uint32_t x, uint32_t pat) {
     return ((v - 0x01010101u) & ~v & 0x80808080u) != 0u;
 }
 
-__global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restrict__ src,
-                                                          const int32_t* __restrict__ adj,
-                                                          const uint8_t* __restrict__ level, int64_t m,
-                                                          int lv, int32_t* parent) {
+__device__ void d_union_level(const int32_t* __restrict__ src, const int32_t* __restrict__ adj,
+                              const uint8_t* __restrict__ level, int64_t m, int lv, int32_t* parent) {
     const int64_t head = min(m, (int64_t)((16u - ((uint32_t)(uintptr_t)level & 15u)) & 15u));
     const int64_t nq = (m - head) >> 4;
     const int64_t tail0 = head + 16 * nq;
@@ -242,16 +263,13 @@ __global__ __launch_bounds__(kThreads) void k_union_level(const int32_t* __restr
     }
 }
 
-// Pass 1 over vertices: compress to the root, count roots per graph, size of
-// every component.
-__global__ __launch_bounds__(kThreads) void k_pass_size(int32_t* parent, int64_t n,
-                                                        const int32_t* __restrict__ gid, int G,
-                                                        int32_t* __restrict__ size,
-                                                        unsigned long long* __restrict__ ncc) {
-    __shared__ unsigned long long gl[kLdsGraphs];
-    __shared__ int32_t rk[kRootSlots];
-    __shared__ uint32_t rv[kRootSlots];
-    GraphAcc acc{G <= kLdsGraphs ? gl : nullptr, ncc, G};
+// Compress every vertex to its root, count roots per graph, size of every
+// component.
+__device__ void d_pass_size(int32_t* parent, int64_t n, const int32_t* __restrict__ gid, int G,
+                            int32_t* size, unsigned long long* ncc, unsigned long long* sh) {
+    int32_t* rk = (int32_t*)(sh + kLdsGraphs);
+    uint32_t* rv = (uint32_t*)(rk + kRootSlots);
+    GraphAcc acc{G <= kLdsGraphs ? sh : nullptr, ncc, G};
     acc.init();
     for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x) {
         rk[i] = -1;
@@ -281,26 +299,22 @@ __global__ __launch_bounds__(kThreads) void k_pass_size(int32_t* parent, int64_t
     acc.flush_add();
     for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x)
         if (rk[i] >= 0) atomicAdd(&size[rk[i]], (int32_t)rv[i]);
+    __syncthreads();
 }
 
-// Labels of one threshold: the smallest original id of every component.
-__global__ __launch_bounds__(kThreads) void k_label_init(const int32_t* __restrict__ perm, int64_t n,
-                                                         int32_t* __restrict__ minid) {
-    GRID_STRIDE(v, n) minid[v] = perm[v];
-}
-
-__global__ __launch_bounds__(kThreads) void k_label_min(int32_t* parent, const int32_t* __restrict__ perm, int64_t n,
-                                                        int32_t* __restrict__ minid) {
+// Labels of one threshold: the smallest original id of every component
+// (minid starts as perm, set with the other per-level resets).
+__device__ void d_label_min(int32_t* parent, const int32_t* __restrict__ perm, int64_t n, int32_t* minid) {
     GRID_STRIDE(v, n) {
         const int32_t r = uf_find(parent, (int32_t)v);
         if (r != (int32_t)v) atomicMin(&minid[r], perm[v]);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_label_write(int32_t* parent, const int32_t* __restrict__ perm,
-                                                          int64_t n, const int32_t* __restrict__ minid,
-                                                          int32_t* __restrict__ labels) {
-    GRID_STRIDE(v, n) labels[perm[v]] = minid[uf_find(parent, (int32_t)v)];
+__device__ void d_label_write(int32_t* parent, const int32_t* __restrict__ perm, int64_t n, const int32_t* minid,
+                              int32_t* __restrict__ labels) {
+    GRID_STRIDE(v, n) labels[perm[v]] = __hip_atomic_load(&minid[uf_find(parent, (int32_t)v)], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t cell_key(int32_t r, int32_t c) {
@@ -311,21 +325,18 @@ __device__ __forceinline__ uint32_t cell_slot(uint64_t k, int log2cap) {
     return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
 }
 
-// Pass 2: A (same cluster pairs) and the largest component per graph, read
-// off the component sizes: after pass 1 only roots hold a nonzero size, and
-// a root's graph is its own.  Streams size[] and gid[] once.
-__global__ __launch_bounds__(kThreads) void k_pass_roots(int64_t n, const int32_t* __restrict__ gid, int G,
-                                                         const int32_t* __restrict__ size,
-                                                         unsigned long long* __restrict__ acc_a,
-                                                         unsigned long long* __restrict__ largest) {
-    __shared__ unsigned long long la[kLdsGraphs], ll[kLdsGraphs];
+// A (same cluster pairs) and the largest component per graph, read off the
+// component sizes: after the size pass only roots hold a nonzero size, and a
+// root's graph is its own.
+__device__ void d_pass_roots(int64_t n, const int32_t* __restrict__ gid, int G, const int32_t* size,
+                             unsigned long long* acc_a, unsigned long long* largest, unsigned long long* sh) {
     const bool lds = G <= kLdsGraphs;
-    GraphAcc A{lds ? la : nullptr, acc_a, G}, Lg{lds ? ll : nullptr, largest, G};
+    GraphAcc A{lds ? sh : nullptr, acc_a, G}, Lg{lds ? sh + kLdsGraphs : nullptr, largest, G};
     A.init();
     Lg.init();
     __syncthreads();
     GRID_STRIDE(v, n) {
-        const int32_t sz = size[v];
+        const int32_t sz = __hip_atomic_load(&size[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int32_t g = gid[v];
         A.add(g, (unsigned long long)sz * (unsigned long long)(sz > 0 ? sz - 1 : 0));
         Lg.max(g, (unsigned long long)sz);
@@ -333,17 +344,16 @@ __global__ __launch_bounds__(kThreads) void k_pass_roots(int64_t n, const int32_
     __syncthreads();
     A.flush_add();
     Lg.flush_max();
+    __syncthreads();
 }
 
-// Pass 2b (with labels): count every (cluster, class) cell in a hash table.
-__global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_t n,
-                                                         const int32_t* __restrict__ cls,
-                                                         unsigned long long* __restrict__ keys,
-                                                         int32_t* __restrict__ counts, int log2cap) {
+// With planted labels: count every (cluster, class) cell in a hash table.
+__device__ void d_pass_cells(int32_t* parent, int64_t n, const int32_t* __restrict__ cls, unsigned long long* keys,
+                             int32_t* counts, int log2cap) {
     const int lane = threadIdx.x & 63;
     GRID_STRIDE(v, n) {
-        // pass 1 compressed the paths, but a concurrent halving may have left
-        // parent[v] at an ancestor below the root: always follow to the root
+        // the size pass compressed the paths, but a concurrent halving may
+        // have left parent[v] at an ancestor below the root: follow to the root
         const int32_t r = uf_find(parent, (int32_t)v);
         const uint64_t k = cell_key(r, cls[v]);
         const uint32_t mask = (1u << log2cap) - 1u;
@@ -363,26 +373,24 @@ __global__ __launch_bounds__(kThreads) void k_pass_cells(int32_t* parent, int64_
     }
 }
 
-// Pass 3: S (pairs sharing cluster and class) per graph.
-__global__ __launch_bounds__(kThreads) void k_pass_s(int32_t* parent, int64_t n,
-                                                     const int32_t* __restrict__ gid, int G,
-                                                     const int32_t* __restrict__ cls,
-                                                     const unsigned long long* __restrict__ keys,
-                                                     const int32_t* __restrict__ counts, int log2cap,
-                                                     unsigned long long* __restrict__ acc_s) {
-    __shared__ unsigned long long ls[kLdsGraphs];
-    GraphAcc S{G <= kLdsGraphs ? ls : nullptr, acc_s, G};
+// S (pairs sharing cluster and class) per graph.
+__device__ void d_pass_s(int32_t* parent, int64_t n, const int32_t* __restrict__ gid, int G,
+                         const int32_t* __restrict__ cls, const unsigned long long* keys, const int32_t* counts,
+                         int log2cap, unsigned long long* acc_s, unsigned long long* sh) {
+    GraphAcc S{G <= kLdsGraphs ? sh : nullptr, acc_s, G};
     S.init();
     __syncthreads();
     GRID_STRIDE(v, n) {
         const uint64_t k = cell_key(uf_find(parent, (int32_t)v), cls[v]);
         const uint32_t mask = (1u << log2cap) - 1u;
         uint32_t h = cell_slot(k, log2cap);
-        while (keys[h] != k) h = (h + 1) & mask;
-        S.add(gid[v], (unsigned long long)(counts[h] - 1));
+        while (__hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != k) h = (h + 1) & mask;
+        const int32_t c = __hip_atomic_load(&counts[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        S.add(gid[v], (unsigned long long)(c - 1));
     }
     __syncthreads();
     S.flush_add();
+    __syncthreads();
 }
 
 // Precision, recall and F1 of Sec. 4 (Evaluation): every output community S
@@ -394,16 +402,15 @@ __global__ __launch_bounds__(kThreads) void k_pass_s(int32_t* parent, int64_t n,
 //
 // best[r] holds (x << 32) | c of the best cell seen; cells compete by an exact
 // compare-and-swap maximum.
-__global__ __launch_bounds__(kThreads) void k_cells_best(const unsigned long long* __restrict__ keys,
-                                                         const int32_t* __restrict__ counts, int64_t cap,
-                                                         const int32_t* __restrict__ size,
-                                                         const int32_t* __restrict__ csize,
-                                                         unsigned long long* best) {
+__device__ void d_cells_best(const unsigned long long* keys, const int32_t* counts, int64_t cap, const int32_t* size,
+                             const int32_t* __restrict__ csize, unsigned long long* best) {
     GRID_STRIDE(h, cap) {
-        const unsigned long long k = keys[h];
+        const unsigned long long k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (k == ~0ull) continue;
         const int32_t r = (int32_t)(k >> 32), c = (int32_t)(uint32_t)k;
-        const int64_t x = counts[h], sz = size[r], b = csize[c];
+        const int64_t x = __hip_atomic_load(&counts[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t sz = __hip_atomic_load(&size[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t b = csize[c];
         const unsigned long long mine = ((unsigned long long)x << 32) | (uint32_t)c;
         unsigned long long cur = __hip_atomic_load(&best[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (;;) {
@@ -422,20 +429,18 @@ __global__ __launch_bounds__(kThreads) void k_cells_best(const unsigned long lon
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_prf_sums(int64_t n, const int32_t* __restrict__ gid, int G,
-                                                       const int32_t* __restrict__ size,
-                                                       const int32_t* __restrict__ csize,
-                                                       const unsigned long long* __restrict__ best,
-                                                       double* __restrict__ acc) {
-    __shared__ double lp[3 * 256];
-    const bool lds = G <= 256;
+__device__ void d_prf_sums(int64_t n, const int32_t* __restrict__ gid, int G, const int32_t* size,
+                           const int32_t* __restrict__ csize, const unsigned long long* best, double* acc,
+                           unsigned long long* sh) {
+    double* lp = (double*)sh;  // 3 doubles per graph
+    const bool lds = 3 * G <= kShWords;
     if (lds)
         for (int i = threadIdx.x; i < 3 * G; i += blockDim.x) lp[i] = 0.0;
     __syncthreads();
     GRID_STRIDE(v, n) {
-        const int32_t sz = size[v];
+        const int32_t sz = __hip_atomic_load(&size[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (sz == 0) continue;  // not a root
-        const unsigned long long rec = best[v];
+        const unsigned long long rec = __hip_atomic_load(&best[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double x = (double)(rec >> 32), b = (double)csize[(int32_t)(uint32_t)rec], s = (double)sz;
         double* dst = lds ? lp + 3 * gid[v] : acc + 3 * (int64_t)gid[v];
         atomicAdd(dst + 0, x);
@@ -446,35 +451,7 @@ __global__ __launch_bounds__(kThreads) void k_prf_sums(int64_t n, const int32_t*
     if (lds)
         for (int i = threadIdx.x; i < 3 * G; i += blockDim.x)
             if (lp[i] != 0.0) atomicAdd(&acc[i], lp[i]);
-}
-
-// class sizes (truth ids lie in [0, n)), then B per graph
-__global__ __launch_bounds__(kThreads) void k_class_size(const int32_t* __restrict__ cls, int64_t n,
-                                                         int32_t* __restrict__ csize) {
-    const int lane = threadIdx.x & 63;
-    GRID_STRIDE(v, n) {
-        const int32_t c = cls[v];
-        const int32_t c0 = __shfl(c, 0);
-        const uint64_t same = __ballot(c == c0);
-        if (c == c0) {
-            if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&csize[c], (int32_t)__popcll(same));
-        } else {
-            atomicAdd(&csize[c], 1);
-        }
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_class_b(const int32_t* __restrict__ cls, int64_t n,
-                                                      const int32_t* __restrict__ gid, int G,
-                                                      const int32_t* __restrict__ csize,
-                                                      unsigned long long* __restrict__ acc_b) {
-    __shared__ unsigned long long lb[kLdsGraphs];
-    GraphAcc B{G <= kLdsGraphs ? lb : nullptr, acc_b, G};
-    B.init();
     __syncthreads();
-    GRID_STRIDE(v, n) B.add(gid[v], (unsigned long long)(csize[cls[v]] - 1));
-    __syncthreads();
-    B.flush_add();
 }
 
 // Modularity (the quality measure of the paper's threshold rule of thumb) of
@@ -483,11 +460,10 @@ __global__ __launch_bounds__(kThreads) void k_class_b(const int32_t* __restrict_
 // with e_c the input edges inside c and vol_c the sum of input degrees over c.
 // vol[root] accumulates the degrees of each component (wave-aggregated, big
 // components through the block's LDS table like the sizes).
-__global__ __launch_bounds__(kThreads) void k_pass_volume(int32_t* parent, int64_t n,
-                                                          const int32_t* __restrict__ deg,
-                                                          unsigned long long* __restrict__ vol) {
-    __shared__ int32_t rk[kRootSlots];
-    __shared__ unsigned long long rv[kRootSlots];
+__device__ void d_pass_volume(int32_t* parent, int64_t n, const int32_t* __restrict__ deg, unsigned long long* vol,
+                              unsigned long long* sh) {
+    unsigned long long* rv = sh;
+    int32_t* rk = (int32_t*)(sh + kRootSlots);
     for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x) {
         rk[i] = -1;
         rv[i] = 0ull;
@@ -500,7 +476,7 @@ __global__ __launch_bounds__(kThreads) void k_pass_volume(int32_t* parent, int64
         const int32_t r0 = __shfl(r, 0);
         unsigned long long x = r == r0 ? d : 0ull;
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        bool done = r == r0;
+        const bool done = r == r0;
         if (lane == 0 && x) {
             uint32_t h = ((uint32_t)r0 * 2654435761u) >> 22;
             bool put = false;
@@ -519,19 +495,17 @@ __global__ __launch_bounds__(kThreads) void k_pass_volume(int32_t* parent, int64
     __syncthreads();
     for (int i = threadIdx.x; i < kRootSlots; i += blockDim.x)
         if (rk[i] >= 0 && rv[i]) atomicAdd(&vol[rk[i]], rv[i]);
+    __syncthreads();
 }
 
 // Per graph: the input edges whose endpoints share a component at threshold
 // slot lv_thresh (kept edges always do; a pruned edge iff its endpoints have
-// one root), and the sum over components of vol_c^2.
-__global__ __launch_bounds__(kThreads) void k_pass_intra(const int32_t* __restrict__ src,
-                                                         const int32_t* __restrict__ adj,
-                                                         const uint8_t* __restrict__ level, int64_t m,
-                                                         int lv_thresh, int32_t* parent,
-                                                         const int32_t* __restrict__ gid, int G,
-                                                         unsigned long long* __restrict__ acc_intra) {
-    __shared__ unsigned long long li[kLdsGraphs];
-    GraphAcc I{G <= kLdsGraphs ? li : nullptr, acc_intra, G};
+// one root).
+__device__ void d_pass_intra(const int32_t* __restrict__ src, const int32_t* __restrict__ adj,
+                             const uint8_t* __restrict__ level, int64_t m, int lv_thresh, int32_t* parent,
+                             const int32_t* __restrict__ gid, int G, unsigned long long* acc_intra,
+                             unsigned long long* sh) {
+    GraphAcc I{G <= kLdsGraphs ? sh : nullptr, acc_intra, G};
     I.init();
     __syncthreads();
     GRID_STRIDE(e, m) {
@@ -542,88 +516,284 @@ __global__ __launch_bounds__(kThreads) void k_pass_intra(const int32_t* __restri
     }
     __syncthreads();
     I.flush_add();
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(kThreads) void k_pass_vsq(int64_t n, const int32_t* __restrict__ gid, int G,
-                                                       const unsigned long long* __restrict__ vol,
-                                                       unsigned long long* __restrict__ acc_vsq) {
-    __shared__ unsigned long long lq[kLdsGraphs];
-    GraphAcc Q{G <= kLdsGraphs ? lq : nullptr, acc_vsq, G};
+// and the sum over components of vol_c^2
+__device__ void d_pass_vsq(int64_t n, const int32_t* __restrict__ gid, int G, const unsigned long long* vol,
+                           unsigned long long* acc_vsq, unsigned long long* sh) {
+    GraphAcc Q{G <= kLdsGraphs ? sh : nullptr, acc_vsq, G};
     Q.init();
     __syncthreads();
     GRID_STRIDE(v, n) {
-        const unsigned long long x = vol[v];  // nonzero only at roots
-        Q.add(gid[v], x * x);
+        const unsigned long long x = __hip_atomic_load(&vol[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        Q.add(gid[v], x * x);  // nonzero only at roots
     }
     __syncthreads();
     Q.flush_add();
+    __syncthreads();
 }
 
-// Writes the statistics of threshold slot `out_i` for every graph.
-__global__ __launch_bounds__(kThreads) void k_write_stats(int G, int K, int lv_thresh, int out_i,
-                                                          const unsigned long long* __restrict__ hist,
-                                                          const unsigned long long* __restrict__ ncc,
-                                                          const unsigned long long* __restrict__ largest,
-                                                          const unsigned long long* __restrict__ acc_a,
-                                                          const unsigned long long* __restrict__ acc_s,
-                                                          const unsigned long long* __restrict__ acc_b,
-                                                          const unsigned long long* __restrict__ acc_intra,
-                                                          const unsigned long long* __restrict__ acc_vsq,
-                                                          const int64_t* __restrict__ vbase, int has_truth,
-                                                          mcd_sweep_stats* __restrict__ stats,
-                                                          double* __restrict__ ari, double* __restrict__ modularity,
-                                                          const double* __restrict__ acc_prf,
-                                                          double* __restrict__ prf) {
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+// class sizes (truth ids lie in [0, n)), then B per graph
+__global__ __launch_bounds__(kThreads) void k_class_size(const int32_t* __restrict__ cls, int64_t n,
+                                                         int32_t* __restrict__ csize,
+                                                         const int32_t* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const int lane = threadIdx.x & 63;
+    GRID_STRIDE(v, n) {
+        const int32_t c = cls[v];
+        const int32_t c0 = __shfl(c, 0);
+        const uint64_t same = __ballot(c == c0);
+        if (c == c0) {
+            if ((same & ((1ull << lane) - 1ull)) == 0) atomicAdd(&csize[c], (int32_t)__popcll(same));
+        } else {
+            atomicAdd(&csize[c], 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_class_b(const int32_t* __restrict__ cls, int64_t n,
+                                                      const int32_t* __restrict__ gid, int G,
+                                                      const int32_t* __restrict__ csize,
+                                                      unsigned long long* __restrict__ acc_b,
+                                                      const int32_t* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    __shared__ unsigned long long lb[kLdsGraphs];
+    GraphAcc B{G <= kLdsGraphs ? lb : nullptr, acc_b, G};
+    B.init();
+    __syncthreads();
+    GRID_STRIDE(v, n) B.add(gid[v], (unsigned long long)(csize[cls[v]] - 1));
+    __syncthreads();
+    B.flush_add();
+}
+
+// Slots of the caller's thresholds: slot[i] = caller slot of the i-th smallest.
+struct SlotOrder {
+    int slot[MCD_SWEEP_MAX];
+};
+
+// Per-graph accumulators of one level; the level loop keeps two sets and
+// alternates between them, so a level's statistics are written while the
+// next level's set is being cleared.
+enum { kAccNcc, kAccLargest, kAccA, kAccS, kAccIntra, kAccVsq, kAccFields };
+
+// State of the grid barrier (in the sweep workspace, zeroed before launch):
+// blocks arrive in groups (block index mod kSyncGroups), the last of a group
+// arrives at the top counter, and the last group moves every group's
+// generation on; each counter and generation sits on its own cache line, so
+// arrivals and the blocks' polling spread over several addresses.
+constexpr int kSyncGroups = 8;
+struct GridSync {
+    unsigned int top;  // groups arrived at the current barrier
+    unsigned int pad0[31];
+    struct Group {
+        unsigned int count;  // blocks of the group arrived
+        unsigned int gen;    // barriers completed
+        unsigned int pad[30];
+    } grp[kSyncGroups];
+    int timed_out;  // a block waited longer than the limit
+    int pad1[31];
+};
+
+struct SweepArgs {
+    const int32_t* src;
+    const int32_t* adj;
+    const uint8_t* level;
+    const int32_t* perm;
+    const int32_t* deg;
+    const int32_t* gid;
+    const int32_t* cls;    // planted class of every rank-numbered vertex, or null
+    const int32_t* csize;  // class sizes (with planted labels)
+    const int64_t* vbase;
+    const unsigned long long* hist;   // [G][K+1] edges per (graph, level)
+    const unsigned long long* acc_b;  // [G] B of every graph
+    int32_t* parent;
+    int32_t* size;
+    int32_t* minid;
+    unsigned long long* keys;
+    int32_t* counts;
+    unsigned long long* vol;
+    unsigned long long* best;
+    unsigned long long* acc[2];  // [kAccFields][G] per parity
+    double* acc_prf[2];          // [G][3] per parity
+    mcd_sweep_stats* stats;
+    double* ari;
+    double* modularity;
+    double* prf;
+    int32_t* labels;  // [K][n] or null
+    GridSync* sync;
+    int64_t n, m, cap;
+    int G, K, log2cap;
+    unsigned nblocks;
+    unsigned long long limit;  // barrier wait limit in wall-clock ticks
+    const int32_t* gate;       // nullable: run only when it reads nonzero
+    SlotOrder out;
+};
+
+// Grid barrier over the resident blocks of k_sweep_levels (a sense-reversing
+// central counter): each block's first thread releases the block's writes,
+// arrives, and waits for the generation to move on.  Every wait is bounded by
+// a wall-clock limit; a block that reaches it records the time-out and from
+// then on no block waits any more, so the kernel always ends (its statistics
+// are then marked invalid, n_components = -1).
+__device__ void grid_sync(const SweepArgs& a) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        GridSync* s = a.sync;
+        if (!__hip_atomic_load(&s->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __threadfence();
+            const unsigned ng = a.nblocks < kSyncGroups ? a.nblocks : kSyncGroups;
+            const unsigned gi = blockIdx.x % ng;
+            const unsigned members = a.nblocks / ng + (gi < a.nblocks % ng ? 1u : 0u);
+            GridSync::Group* gr = &s->grp[gi];
+            const unsigned g = __hip_atomic_load(&gr->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (atomicAdd(&gr->count, 1u) == members - 1) {  // last of its group
+                __hip_atomic_store(&gr->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (atomicAdd(&s->top, 1u) == ng - 1) {  // last group: release everyone
+                    __hip_atomic_store(&s->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    for (unsigned h = 0; h < ng; ++h)
+                        __hip_atomic_fetch_add(&s->grp[h].gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(&gr->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(4);
+                if (wall_clock64() - t0 > a.limit) {
+                    __hip_atomic_store(&s->timed_out, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+            __threadfence();
+        }
+    }
+    __syncthreads();
+}
+
+// Writes the statistics of threshold i (caller slot a.out.slot[i]) for every
+// graph from the accumulator set `p`.
+__device__ void d_write_stats(const SweepArgs& a, int i, int p) {
+    const int G = a.G, K = a.K;
+    const unsigned long long* acc = a.acc[p];
+    const bool bad = __hip_atomic_load(&a.sync->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const int out_i = a.out.slot[i];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
         int64_t kept = 0, mg = 0;
         for (int l = 0; l <= K; ++l) {
-            const int64_t c = (int64_t)hist[(int64_t)g * (K + 1) + l];
+            const int64_t c = (int64_t)a.hist[g * (K + 1) + l];
             mg += c;
-            if (l > lv_thresh) kept += c;
+            if (l > i) kept += c;
         }
+        auto ld = [&](int field) {
+            return (int64_t)__hip_atomic_load(&acc[field * G + g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
         mcd_sweep_stats st;
-        const int64_t nv = vbase[g + 1] - vbase[g];
+        const int64_t nv = a.vbase[g + 1] - a.vbase[g];
         st.m_kept = kept;
-        st.n_components = (int64_t)ncc[g];
-        st.largest_component = (int64_t)largest[g];
-        st.pairs_cluster = (int64_t)(acc_a[g] / 2);
-        st.pairs_class = has_truth ? (int64_t)(acc_b[g] / 2) : 0;
-        st.pairs_both = has_truth ? (int64_t)(acc_s[g] / 2) : 0;
+        st.n_components = bad ? -1 : ld(kAccNcc);
+        st.largest_component = ld(kAccLargest);
+        st.pairs_cluster = ld(kAccA) / 2;
+        st.pairs_class = a.cls ? (int64_t)(a.acc_b[g] / 2) : 0;
+        st.pairs_both = a.cls ? ld(kAccS) / 2 : 0;
         st.pairs_total = nv * (nv - 1) / 2;
-        st.intra_edges = modularity ? (int64_t)acc_intra[g] : 0;
-        st.volume_sq = modularity ? (int64_t)acc_vsq[g] : 0;
-        stats[(int64_t)g * K + out_i] = st;
-        if (prf) {
-            double* o = prf + ((int64_t)g * K + out_i) * 3;
+        st.intra_edges = a.modularity ? ld(kAccIntra) : 0;
+        st.volume_sq = a.modularity ? ld(kAccVsq) : 0;
+        a.stats[g * K + out_i] = st;
+        if (a.prf) {
+            const double* ap = a.acc_prf[p] + 3 * g;
+            double* o = a.prf + (g * K + out_i) * 3;
             const double nn = (double)nv;
-            o[0] = nv ? acc_prf[3 * g] / nn : 0.0;
-            o[1] = nv ? acc_prf[3 * g + 1] / nn : 0.0;
-            o[2] = nv ? acc_prf[3 * g + 2] / nn : 0.0;
+            for (int j = 0; j < 3; ++j)
+                o[j] = nv ? __hip_atomic_load(&ap[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / nn : 0.0;
         }
-        if (modularity) {
+        if (a.modularity) {
             const double mm = (double)mg;
-            modularity[(int64_t)g * K + out_i] =
+            a.modularity[g * K + out_i] =
                 mg == 0 ? 0.0 : (double)st.intra_edges / mm - (double)st.volume_sq / (4.0 * mm * mm);
         }
-        if (ari) {
+        if (a.ari) {
             double r = 0.0;
-            if (has_truth) {
+            if (a.cls) {
                 const double A = (double)st.pairs_cluster, B = (double)st.pairs_class;
                 const double S = (double)st.pairs_both, N = (double)st.pairs_total;
                 const double prod = (A * B) / N;
                 const double den = 0.5 * (A + B) - prod;
                 r = (st.pairs_total == 0 || den == 0.0) ? 1.0 : (S - prod) / den;
             }
-            ari[(int64_t)g * K + out_i] = r;
+            a.ari[g * K + out_i] = r;
         }
     }
 }
 
+// The whole level loop in one launch: from the highest threshold down, each
+// level's edges are united, then the per-graph statistics of the partition
+// are gathered, with grid barriers between the phases that depend on each
+// other:
+//   U : stats of the previous level | reset this level's accumulators and
+//       per-vertex arrays | unite this level's edges
+//   P1: roots and sizes (paths compressed) | label minima | (cluster, class)
+//       cells | component volumes | intra-component edges
+//   P2: A and largest | labels | S | best cells | sum of squared volumes
+//   P3: precision / recall / F1 sums (when asked for)
+// NT threads per block, at least WPE waves per SIMD (which bounds the
+// registers per thread)
+// The level loop's arguments live in device memory (written by one tiny
+// kernel, so a captured graph holds them by value): read through a pointer,
+// they do not occupy registers for the whole kernel.
+__global__ void k_store_args(SweepArgs a, SweepArgs* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
+}
+
+template <int NT, int WPE>
+__global__ __launch_bounds__(NT, WPE) void k_sweep_levels(const SweepArgs* __restrict__ ap) {
+    const SweepArgs& a = *ap;
+    if (gated_off(a.gate)) return;  // uniform over the grid: no block waits for another
+    __shared__ unsigned long long sh[kShWords];
+    const int64_t n = a.n, m = a.m;
+    const int G = a.G;
+    for (int i = a.K - 1; i >= 0; --i) {
+        const int p = i & 1;
+        unsigned long long* acc = a.acc[p];
+        if (i < a.K - 1) d_write_stats(a, i + 1, p ^ 1);
+        GRID_STRIDE(j, (int64_t)kAccFields * G) acc[j] = 0ull;
+        if (a.prf) GRID_STRIDE(j, 3 * (int64_t)G) a.acc_prf[p][j] = 0.0;
+        GRID_STRIDE(v, n) {
+            a.size[v] = 0;
+            if (a.modularity) a.vol[v] = 0ull;
+            if (a.prf) a.best[v] = 0ull;
+            if (a.labels) a.minid[v] = a.perm[v];
+        }
+        if (a.cls) GRID_STRIDE(h, a.cap) {
+            a.keys[h] = ~0ull;
+            a.counts[h] = 0;
+        }
+        if (m > 0) d_union_level(a.src, a.adj, a.level, m, i + 1, a.parent);
+        grid_sync(a);
+        d_pass_size(a.parent, n, a.gid, G, a.size, acc + kAccNcc * G, sh);
+        if (a.labels) d_label_min(a.parent, a.perm, n, a.minid);
+        if (a.cls) d_pass_cells(a.parent, n, a.cls, a.keys, a.counts, a.log2cap);
+        if (a.modularity) {
+            d_pass_volume(a.parent, n, a.deg, a.vol, sh);
+            if (m > 0) d_pass_intra(a.src, a.adj, a.level, m, i, a.parent, a.gid, G, acc + kAccIntra * G, sh);
+        }
+        grid_sync(a);
+        d_pass_roots(n, a.gid, G, a.size, acc + kAccA * G, acc + kAccLargest * G, sh);
+        if (a.labels) d_label_write(a.parent, a.perm, n, a.minid, a.labels + (int64_t)a.out.slot[i] * n);
+        if (a.cls) {
+            d_pass_s(a.parent, n, a.gid, G, a.cls, a.keys, a.counts, a.log2cap, acc + kAccS * G, sh);
+            if (a.prf) d_cells_best(a.keys, a.counts, a.cap, a.size, a.csize, a.best);
+        }
+        if (a.modularity) d_pass_vsq(n, a.gid, G, a.vol, acc + kAccVsq * G, sh);
+        grid_sync(a);
+        if (a.prf) {
+            d_prf_sums(n, a.gid, G, a.size, a.csize, a.best, a.acc_prf[p], sh);
+            grid_sync(a);
+        }
+    }
+    d_write_stats(a, 0, 0);
+}
+
 // One thread per graph: the rule of thumb over the thresholds in ascending
 // order (slot[i] = caller slot of the i-th smallest).
-struct SlotOrder {
-    int slot[MCD_SWEEP_MAX];
-};
 
 __global__ __launch_bounds__(kThreads) void k_sweep_rule(int G, SweepDeltas ds, SlotOrder so,
                                                          const int64_t* __restrict__ vbase,
@@ -694,16 +864,13 @@ struct SweepLayout {
     unsigned long long* keys;
     int32_t* counts;
     unsigned long long* hist;    // [G][K+1]
-    unsigned long long* ncc;     // [G]
-    unsigned long long* largest; // [G]
-    unsigned long long* acc_a;   // [G]
-    unsigned long long* acc_s;   // [G]
     unsigned long long* acc_b;   // [G]
-    unsigned long long* acc_intra;  // [G]
-    unsigned long long* acc_vsq;    // [G]
-    unsigned long long* vol;        // [n]
-    unsigned long long* best;       // [n] (planted labels)
-    double* acc_prf;                // [G][3]
+    unsigned long long* acc[2];  // [kAccFields][G] per parity
+    double* acc_prf[2];          // [G][3] per parity
+    unsigned long long* vol;     // [n]
+    unsigned long long* best;    // [n] (planted labels)
+    GridSync* sync;
+    SweepArgs* args;
     size_t bytes;
 };
 
@@ -722,18 +889,52 @@ SweepLayout sweep_layout(void* p, const mcd_graph* g, int G, int K, bool truth) 
     L.keys = truth ? c.take<unsigned long long>((size_t)cap) : nullptr;
     L.counts = truth ? c.take<int32_t>((size_t)cap) : nullptr;
     L.hist = c.take<unsigned long long>((size_t)G * (K + 1));
-    L.ncc = c.take<unsigned long long>((size_t)G);
-    L.largest = c.take<unsigned long long>((size_t)G);
-    L.acc_a = c.take<unsigned long long>((size_t)G);
-    L.acc_s = c.take<unsigned long long>((size_t)G);
     L.acc_b = c.take<unsigned long long>((size_t)G);
-    L.acc_intra = c.take<unsigned long long>((size_t)G);
-    L.acc_vsq = c.take<unsigned long long>((size_t)G);
+    for (int q = 0; q < 2; ++q) {
+        L.acc[q] = c.take<unsigned long long>((size_t)kAccFields * G);
+        L.acc_prf[q] = c.take<double>((size_t)3 * G);
+    }
     L.vol = c.take<unsigned long long>((size_t)n);
     L.best = truth ? c.take<unsigned long long>((size_t)n) : nullptr;
-    L.acc_prf = c.take<double>((size_t)3 * G);
+    L.sync = c.take<GridSync>(1);
+    L.args = c.take<SweepArgs>(1);
     L.bytes = c.used;
     return L;
+}
+
+// Launch shapes of the level loop (threads per block, waves per SIMD): the
+// context parameter sweep_shape picks (1024, 4), (512, 6) or (256, 8); all
+// give the same results.
+// Blocks of the level loop that are resident at once (by the occupancy
+// query, and no more than the work needs), so that every block reaches every
+// barrier.
+template <int NT, int WPE>
+unsigned sweep_blocks(int64_t work) {
+    int dev = 0, cus = 1, per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_levels<NT, WPE>, NT, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int64_t b = (int64_t)per_cu * cus;
+    const int64_t need = (work + NT - 1) / NT;
+    if (need < b) b = need;
+    return (unsigned)std::max<int64_t>(b, 1);
+}
+
+template <int NT, int WPE>
+void launch_levels(SweepArgs& a, SweepArgs* dev_args, int64_t work, hipStream_t s) {
+    a.nblocks = sweep_blocks<NT, WPE>(work);
+    hipLaunchKernelGGL(k_store_args, dim3(1), dim3(64), 0, s, a, dev_args);
+    hipLaunchKernelGGL((k_sweep_levels<NT, WPE>), dim3(a.nblocks), dim3(NT), 0, s, dev_args);
+}
+
+// Barrier wait limit: 30 s of the device's constant-rate wall clock.
+unsigned long long sweep_wait_limit() {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+    return (unsigned long long)khz * 1000ull * 30ull;
 }
 
 }  // namespace
@@ -745,7 +946,7 @@ size_t sweep_scratch_bytes(const mcd_graph* g, int G, int K, bool truth) {
 void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const SweepDeltas& ds,
                   const int* out_index, int G, const int64_t* vbase, const int32_t* truth,
                   mcd_sweep_stats* stats, double* ari, double* modularity, double* prf, int32_t* labels,
-                  void* ws, hipStream_t s) {
+                  void* ws, hipStream_t s, const int32_t* gate) {
     const int K = ds.K;
     if (!truth) prf = nullptr;
     const int64_t n = g->n, m = g->m;
@@ -754,9 +955,10 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
     const int64_t cap = truth ? ((int64_t)1 << l2) : 0;
     fill_t<unsigned long long>(L.hist, (int64_t)G * (K + 1), 0ull, s);
     fill_t<unsigned long long>(L.acc_b, G, 0ull, s);
+    fill_t<int32_t>((int32_t*)L.sync, (int64_t)(sizeof(GridSync) / sizeof(int32_t)), 0, s);
     if (n > 0)
         hipLaunchKernelGGL(k_vertex_info, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->perm, n, vbase, G,
-                           truth, L.gid, L.cls);
+                           truth, L.gid, L.cls, gate);
     if (m > 0) {
         // thresholds reach the kernel validated to |num|, den < 2^31
         // LDS for the histogram only as large as it is (a few bins for one
@@ -765,77 +967,62 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
         const unsigned lds = nbins <= kLevelBins ? (unsigned)nbins * 4u : 0u;
         if (g->max_deg < (1 << 29))
             hipLaunchKernelGGL(k_level<true>, dim3(grid_for(m, 8192)), dim3(kThreads), lds, s, g->src, g->dsum, t, m,
-                               measure, ds, L.level, L.gid, G, L.hist);
+                               measure, ds, L.level, L.gid, G, L.hist, gate);
         else
             hipLaunchKernelGGL(k_level<false>, dim3(grid_for(m, 8192)), dim3(kThreads), lds, s, g->src, g->dsum, t,
-                               m, measure, ds, L.level, L.gid, G, L.hist);
+                               m, measure, ds, L.level, L.gid, G, L.hist, gate);
     }
     if (truth && n > 0) {
         fill_t<int32_t>(L.csize, n, 0, s);
-        hipLaunchKernelGGL(k_class_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.csize);
+        hipLaunchKernelGGL(k_class_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.csize, gate);
         hipLaunchKernelGGL(k_class_b, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.cls, n, L.gid, G,
-                           L.csize, L.acc_b);
+                           L.csize, L.acc_b, gate);
     }
-    if (n > 0) hipLaunchKernelGGL(k_init_parent, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n);
-    for (int i = K - 1; i >= 0; --i) {
-        if (m > 0)
-            hipLaunchKernelGGL(k_union_level, dim3(grid_for(m, 16384)), dim3(kThreads), 0, s, g->src, g->adj,
-                               L.level, m, i + 1, L.parent);
-        fill_t<unsigned long long>(L.ncc, G, 0ull, s);
-        fill_t<unsigned long long>(L.largest, G, 0ull, s);
-        fill_t<unsigned long long>(L.acc_a, G, 0ull, s);
-        fill_t<unsigned long long>(L.acc_s, G, 0ull, s);
-        fill_t<int32_t>(L.size, n, 0, s);
-        if (modularity) {
-            fill_t<unsigned long long>(L.acc_intra, G, 0ull, s);
-            fill_t<unsigned long long>(L.acc_vsq, G, 0ull, s);
-            fill_t<unsigned long long>(L.vol, n, 0ull, s);
-        }
-        int32_t* lab = labels ? labels + (int64_t)out_index[i] * n : nullptr;
-        if (n > 0) {
-            hipLaunchKernelGGL(k_pass_size, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid, G,
-                               L.size, L.ncc);
-            if (lab) {
-                hipLaunchKernelGGL(k_label_init, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->perm, n,
-                                   L.minid);
-                hipLaunchKernelGGL(k_label_min, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, g->perm,
-                                   n, L.minid);
-                hipLaunchKernelGGL(k_label_write, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent,
-                                   g->perm, n, L.minid, lab);
-            }
-            if (truth) {
-                fill_t<unsigned long long>(L.keys, cap, ~0ull, s);
-                fill_t<int32_t>(L.counts, cap, 0, s);
-            }
-            hipLaunchKernelGGL(k_pass_roots, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, n, L.gid, G, L.size,
-                               L.acc_a, L.largest);
-            if (modularity) {
-                hipLaunchKernelGGL(k_pass_volume, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, g->deg,
-                                   L.vol);
-                hipLaunchKernelGGL(k_pass_vsq, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, n, L.gid, G, L.vol,
-                                   L.acc_vsq);
-                if (m > 0)
-                    hipLaunchKernelGGL(k_pass_intra, dim3(grid_for(m, 8192)), dim3(kThreads), 0, s, g->src, g->adj,
-                                       L.level, m, i, L.parent, L.gid, G, L.acc_intra);
-            }
-            if (truth) {
-                hipLaunchKernelGGL(k_pass_cells, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n,
-                                   L.cls, L.keys, L.counts, l2);
-                hipLaunchKernelGGL(k_pass_s, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, L.gid, G,
-                                   L.cls, L.keys, L.counts, l2, L.acc_s);
-                if (prf) {
-                    fill_t<unsigned long long>(L.best, n, 0ull, s);
-                    fill_t<double>(L.acc_prf, 3 * (int64_t)G, 0.0, s);
-                    hipLaunchKernelGGL(k_cells_best, dim3(grid_for(cap, 8192)), dim3(kThreads), 0, s, L.keys, L.counts,
-                                       cap, L.size, L.csize, L.best);
-                    hipLaunchKernelGGL(k_prf_sums, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, n, L.gid, G, L.size,
-                                       L.csize, L.best, L.acc_prf);
-                }
-            }
-        }
-        hipLaunchKernelGGL(k_write_stats, dim3((G + kThreads - 1) / kThreads), dim3(kThreads), 0, s, G, K, i,
-                           out_index[i], L.hist, L.ncc, L.largest, L.acc_a, L.acc_s, L.acc_b, L.acc_intra,
-                           L.acc_vsq, vbase, truth ? 1 : 0, stats, ari, modularity, L.acc_prf, prf);
+    if (n > 0)
+        hipLaunchKernelGGL(k_init_parent, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.parent, n, gate);
+    SweepArgs a;
+    a.src = g->src;
+    a.adj = g->adj;
+    a.level = L.level;
+    a.perm = g->perm;
+    a.deg = g->deg;
+    a.gid = L.gid;
+    a.cls = truth ? L.cls : nullptr;
+    a.csize = L.csize;
+    a.vbase = vbase;
+    a.hist = L.hist;
+    a.acc_b = L.acc_b;
+    a.parent = L.parent;
+    a.size = L.size;
+    a.minid = L.minid;
+    a.keys = L.keys;
+    a.counts = L.counts;
+    a.vol = L.vol;
+    a.best = L.best;
+    for (int q = 0; q < 2; ++q) {
+        a.acc[q] = L.acc[q];
+        a.acc_prf[q] = L.acc_prf[q];
+    }
+    a.stats = stats;
+    a.ari = ari;
+    a.modularity = modularity;
+    a.prf = prf;
+    a.labels = labels;
+    a.sync = L.sync;
+    a.n = n;
+    a.m = m;
+    a.cap = cap;
+    a.G = G;
+    a.K = K;
+    a.log2cap = l2;
+    for (int i = 0; i < K; ++i) a.out.slot[i] = out_index[i];
+    const int64_t work = std::max<int64_t>(std::max<int64_t>(n, (m + 15) / 16), std::max<int64_t>(cap, G));
+    a.limit = sweep_wait_limit();
+    a.gate = gate;
+    switch (g->ctx->sweep_shape) {
+        case 1: launch_levels<512, 6>(a, L.args, work, s); break;
+        case 2: launch_levels<256, 8>(a, L.args, work, s); break;
+        default: launch_levels<1024, 4>(a, L.args, work, s); break;
     }
 }
 

@@ -9,12 +9,20 @@
 // u->v.  The workgroup hashes N+(v) into LDS (key w -> position in N+(v)) and
 // every wave streams, for one in-edge at a time, the suffix of row u after v
 // in 64-element coalesced chunks, probing each element.  A hit w credits
-//     t(u,v) : one atomic per in-edge (wave ballot count),
-//     t(u,w) : a global atomic at the suffix position (same cache lines just read),
-//     t(v,w) : an LDS counter of v's row, flushed once per work item.
-// The probe count is the sum over edges of |suffix of N+(u) after v|, the
-// smallest list the intersection needs to scan.  All increments are integer
-// atomics, so the counts do not depend on scheduling.
+//     t(v,w) : an LDS counter of v's row, flushed once per work item;
+//     t(u,v) and t(u,w): in the rank-window classes (almost all the work),
+//              the wave's hit ballot of each chunk is stored as one 64-bit
+//              word of the in-edge's hit bitmask, and a second pass over the
+//              rows of u turns the bitmasks into counts (t(u,w) as column
+//              sums, t(u,v) as popcounts) with plain stores; in the smaller
+//              classes, global atomics (one per in-edge for t(u,v), one per
+//              hit for t(u,w)).
+// Device-scope atomics on a multi-XCD GPU are carried out at the memory side,
+// one request per cache line touched, so the bitmasks replace about 10^10
+// atomic requests by 8-byte stores.  The probe count is the sum over edges of
+// |suffix of N+(u) after v|, the smallest list the intersection needs to
+// scan.  Every count is an integer sum, so the result does not depend on
+// scheduling.
 //
 // Items are grouped by |N+(v)| into LDS size classes (a wave, two waves or
 // four waves per item); rows longer than the largest class (or than the
@@ -277,8 +285,11 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
 // into scalar registers; every other field is wave-uniform.
 struct ChunkGen {
     const int2* __restrict__ dp;
+    const int64_t* __restrict__ wbase;  // first word of every edge's hit bitmask
     int32_t left, stride, e, pos, a1, bi;
     int32_t bx, by;  // per lane: a batch of descriptors
+    int64_t bw;      // per lane: the bitmask base of the lane's descriptor
+    int64_t wb;      // bitmask base of the current in-edge
     bool done;
     // move to the next non-empty chunk
     __device__ __forceinline__ void next(int lane) {
@@ -292,17 +303,23 @@ struct ChunkGen {
                 const int2 d = lane < left ? dp[lane * stride] : make_int2(0, 0);
                 bx = d.x;
                 by = d.y;
+                bw = lane < left ? wbase[d.x] : 0;
                 dp += 64 * stride;
                 bi = 0;
             }
             e = __builtin_amdgcn_readlane(bx, bi);
             const int32_t len = __builtin_amdgcn_readlane(by, bi);
+            const uint32_t wlo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)bw, bi);
+            const uint32_t whi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(bw >> 32), bi);
+            wb = (int64_t)(((uint64_t)whi << 32) | wlo);
             ++bi;
             --left;
             pos = e + 1;
             a1 = e + 1 + len;
         }
     }
+    // bitmask word of the current chunk
+    __device__ __forceinline__ int64_t word() const { return wb + ((pos - e - 1) >> 6); }
 };
 
 // The generator's current chunk as one element per lane (lanes past its end
@@ -322,14 +339,18 @@ __device__ __forceinline__ int32_t load_chunk(const int32_t* __restrict__ adj, c
 // is wave-uniform, so it runs on the scalar unit and the vector work per
 // element is the probe alone; loads run D chunks ahead of their use in a
 // ring of registers.  t(v,w) partial counts are 32-bit LDS counters, one per
-// element of N+(v).  Wide windows take large workgroups so that the LDS they
-// need still leaves room for enough waves per CU.
+// element of N+(v).  The hit ballot of every chunk is stored as a word of the
+// in-edge's bitmask (bits, at wbase[e] + chunk index), for k_tc_credit.
+// Wide windows take large workgroups so that the LDS they need still leaves
+// room for enough waves per CU.
 template <int LOG2R, int NT, int D>
 __global__ __launch_bounds__(NT) void k_tc_window_s(const Item* __restrict__ all_items,
                                                     const int64_t* __restrict__ heads, int cls,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ adj,
                                                     const int2* __restrict__ in_ea,
+                                                    const int64_t* __restrict__ wbase,
+                                                    unsigned long long* __restrict__ bits,
                                                     int32_t* __restrict__ t, int ipart, int nparts) {
     constexpr int NW = (1 << LOG2R) / 32;
     constexpr int MAXB = 4096;
@@ -381,21 +402,21 @@ __global__ __launch_bounds__(NT) void k_tc_window_s(const Item* __restrict__ all
         __syncthreads();
 
         const uint32_t rmax = (uint32_t)(maxv - v - 1);  // ranks v+1 .. maxv are in the window
-        ChunkGen gen{in_ea + I.s + wave, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES, 0, -64, 0,
-                     64, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
+        ChunkGen gen{in_ea + I.s + wave, wbase, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES,
+                     0, -64, 0, 64, 0, 0, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
         gen.next(lane);
-        int32_t w[D], spos[D], sa1[D], se[D];
+        int32_t w[D], spos[D], sa1[D];
+        int64_t sw[D];
         bool sv[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) {
             sv[q] = !gen.done;
             spos[q] = gen.pos;
             sa1[q] = gen.a1;
-            se[q] = gen.e;
+            sw[q] = gen.word();
             w[q] = load_chunk(adj, gen, lane);
             if (sv[q]) gen.next(lane);
         }
-        uint32_t c = 0;  // hits of the current in-edge (wave-uniform)
         bool more = sv[0];
         while (more) {
 #pragma unroll
@@ -413,19 +434,17 @@ __global__ __launch_bounds__(NT) void k_tc_window_s(const Item* __restrict__ all
                     if (word & bit) {
                         hit = true;
                         atomicAdd(&cnt[(uint32_t)pre[r >> 5] + __popc(word & (bit - 1u))], 1u);
-                        add_relaxed(&(t + pos)[(uint32_t)lane], 1);  // t(u,w)
                     }
                 }
-                c += (uint32_t)__popcll(__ballot(hit));
-                if (pos + 64 >= sa1[q]) {  // last chunk of the in-edge: t(u,v)
-                    if (lane == 0 && c) add_relaxed(&t[se[q]], (int32_t)c);
-                    c = 0;
-                }
+                // this chunk's word of the in-edge's hit bitmask: every word
+                // of a window in-edge is written, once
+                const unsigned long long hb = __ballot(hit);
+                if (lane == 0) __builtin_nontemporal_store(hb, &bits[sw[q]]);
                 // refill the slot with the chunk D ahead
                 sv[q] = !gen.done;
                 spos[q] = gen.pos;
                 sa1[q] = gen.a1;
-                se[q] = gen.e;
+                sw[q] = gen.word();
                 w[q] = load_chunk(adj, gen, lane);
                 if (sv[q]) gen.next(lane);
             }
@@ -506,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
                                                          const int64_t* __restrict__ in_off, int64_t n,
                                                          int64_t chunk, int64_t lds_max,
                                                          int64_t packed_range, int64_t window_max,
-                                                         int32_t* __restrict__ cnt) {
+                                                         int32_t* __restrict__ cnt, uint8_t* __restrict__ wflag) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t B = off[v + 1] - off[v];
@@ -529,6 +548,82 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
         const int64_t cs = item_size(chunk, B);
         const int32_t k = cls >= 0 ? (int32_t)((I + cs - 1) / cs) : 0;
         for (int c = 0; c < kClasses; ++c) cnt[(int64_t)c * n + v] = (c == cls) ? k : 0;
+        wflag[v] = (cls >= 8 && cls <= 10) ? 1 : 0;  // in-edges credited through hit bitmasks
+    }
+}
+
+// Words of every edge's hit bitmask: ceil(suffix length / 64) when its head
+// is a rank-window item (the only kernels that write bitmasks), else 0.
+__global__ __launch_bounds__(kThreads) void k_tc_words(const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ src,
+                                                       const int32_t* __restrict__ adj,
+                                                       const uint8_t* __restrict__ wflag, int64_t m,
+                                                       int32_t* __restrict__ words) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t L = off[src[e] + 1] - e - 1;
+        words[e] = wflag[adj[e]] ? (int32_t)((L + 63) >> 6) : 0;
+    }
+}
+
+// The credits of the hit bitmasks, one wave per row u of the orientation.
+// With d the row's length and x_j the bitmask of its j-th edge u -> w_j (bit
+// s: the suffix element w_(j+1+s) is a common neighbour, i.e. {u, w_j,
+// w_(j+1+s)} is a triangle),
+//     t(u, w_k) += #{ j < k : bit k - j - 1 of x_j }   (column sums)
+//     t(u, w_j) += popcount(x_j)                       (the in-edge's count)
+// The row is cut into tiles of 64 positions; for a tile, 64 bitmasks at a
+// time are realigned to it (lane j holds the 64 bits of x_j that fall on the
+// tile) and summed column by column with wave ballots.  Each position of t
+// belongs to one row, so the additions are plain stores; the pass runs after
+// every other credit has landed.
+__device__ __forceinline__ unsigned long long tile_bits(const unsigned long long* __restrict__ bits, int64_t w0,
+                                                        int64_t nw, int64_t s0) {
+    if (nw <= 0 || s0 <= -64) return 0ull;
+    if (s0 < 0) return bits[w0] << (-s0);
+    const int64_t wi = s0 >> 6;
+    const int sh = (int)(s0 & 63);
+    const unsigned long long lo = wi < nw ? bits[w0 + wi] : 0ull;
+    if (sh == 0) return lo;
+    const unsigned long long hi = wi + 1 < nw ? bits[w0 + wi + 1] : 0ull;
+    return (lo >> sh) | (hi << (64 - sh));
+}
+
+__global__ __launch_bounds__(kThreads) void k_tc_credit(const int64_t* __restrict__ off,
+                                                        const int64_t* __restrict__ wbase,
+                                                        const unsigned long long* __restrict__ bits, int64_t n,
+                                                        int32_t* __restrict__ t) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t u = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); u < n; u += nwaves) {
+        const int64_t e0 = off[u], d = off[u + 1] - e0;
+        if (d < 2 || wbase[e0 + d] == wbase[e0]) continue;  // no bitmask in this row
+        const int64_t T = (d + 63) >> 6;
+        for (int64_t c = 0; c < T; ++c) {
+            const int64_t k0 = 64 * c;
+            const int ncol = (int)min((int64_t)64, d - k0);
+            int32_t col = 0;
+            for (int64_t gq = 0; gq <= c; ++gq) {
+                const int64_t j = 64 * gq + lane;
+                unsigned long long x = 0ull;
+                if (j < d - 1) {
+                    const int64_t w0 = wbase[e0 + j];
+                    x = tile_bits(bits, w0, wbase[e0 + j + 1] - w0, k0 - j - 1);
+                }
+                if (__ballot(x != 0ull) == 0ull) continue;
+                for (int i = 0; i < ncol; ++i) {
+                    const unsigned long long b = __ballot((x >> i) & 1ull);
+                    if (lane == i) col += __popcll(b);
+                }
+            }
+            // popcounts of this tile's own bitmasks
+            const int64_t j = k0 + lane;
+            int32_t pc = 0;
+            if (j < d - 1) {
+                const int64_t w1 = wbase[e0 + j + 1];
+                for (int64_t wq = wbase[e0 + j]; wq < w1; ++wq) pc += __popcll(bits[wq]);
+            }
+            if (j < d && (col | pc)) t[e0 + j] += col + pc;
+        }
     }
 }
 
@@ -583,6 +678,10 @@ struct TcLayout {
     int64_t* base;   // [kClasses][n+1]
     Item* items;     // [max items]
     int64_t* heads;  // [2*kClasses]: start, length per class
+    uint8_t* wflag;  // [n] head of rank-window items
+    int32_t* words;  // [m] bitmask words per edge
+    int64_t* wbase;  // [m+1] first bitmask word per edge
+    unsigned long long* bits;  // [bitmask words] hit bitmasks
     void* scan;
     size_t bytes;
 };
@@ -590,13 +689,17 @@ struct TcLayout {
 TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     Carve c{(char*)p, 0, 0};
     TcLayout L;
-    const int64_t n = g->n;
-    const int64_t max_items = n + g->m / item_size(chunk, 0) + 1;  // items hold >= item_size(chunk, 0) in-edges
+    const int64_t n = g->n, m = g->m;
+    const int64_t max_items = n + m / item_size(chunk, 0) + 1;  // items hold >= item_size(chunk, 0) in-edges
     L.cnt = c.take<int32_t>((size_t)kClasses * n);
     L.base = c.take<int64_t>((size_t)kClasses * (n + 1));
     L.items = c.take<Item>((size_t)max_items);
     L.heads = c.take<int64_t>(2 * kClasses);
-    L.scan = c.take<char>(scan_scratch_bytes(n));
+    L.wflag = c.take<uint8_t>((size_t)n);
+    L.words = c.take<int32_t>((size_t)m);
+    L.wbase = c.take<int64_t>((size_t)m + 1);
+    L.bits = c.take<unsigned long long>((size_t)g->bitmask_words);
+    L.scan = c.take<char>(scan_scratch_bytes(n > m ? n : m));
     L.bytes = c.used;
     return L;
 }
@@ -619,7 +722,7 @@ void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, 
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = cap_items < 16384 ? cap_items : 16384;
     hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads, c,
-                       g->off, g->adj, g->in_ea, t, ipart, nparts);
+                       g->off, g->adj, g->in_ea, L.wbase, L.bits, t, ipart, nparts);
 }
 
 }  // namespace
@@ -634,7 +737,12 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     TcLayout L = tc_layout(ws, g, chunk);
     const int64_t n = g->n;
     hipLaunchKernelGGL(k_item_count, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->adj, g->in_off,
-                       n, chunk, lds_max, packed_range, window_max, L.cnt);
+                       n, chunk, lds_max, packed_range, window_max, L.cnt, L.wflag);
+    // where the hit bitmask of every edge starts (edges whose head is not a
+    // rank-window item get none)
+    hipLaunchKernelGGL(k_tc_words, dim3(grid_for(g->m, 16384)), dim3(kThreads), 0, s, g->off, g->src, g->adj,
+                       L.wflag, g->m, L.words);
+    exclusive_scan_i32_i64(L.words, g->m, L.wbase, L.scan, s);
     for (int c = 0; c < kClasses; ++c)
         exclusive_scan_i32_i64(L.cnt + (int64_t)c * n, n, L.base + (int64_t)c * (n + 1), L.scan, s);
     hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
@@ -669,6 +777,8 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     (void)hipEventRecord(c->join[1], s2);
     (void)hipStreamWaitEvent(s, c->join[0], 0);
     (void)hipStreamWaitEvent(s, c->join[1], 0);
+    // every class has finished: the bitmasks' credits, row by row
+    hipLaunchKernelGGL(k_tc_credit, dim3(grid_for(n, 16384)), dim3(kThreads), 0, s, g->off, L.wbase, L.bits, n, t);
 }
 
 }  // namespace mcd

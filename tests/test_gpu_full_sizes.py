@@ -1,11 +1,13 @@
 """GPU parity at the full sizes of the five workloads.
 
-R-MAT scale 20 and the degree-corrected SBM are compared with the oracle in
-full; the 256-graph planted batch at sampled thresholds of the 64-point grid;
-R-MAT scale 26 (the benchmark's workload, run with the same calls and
-buffers the benchmark uses) on sampled edges the oracle evaluates one by one
-from the raw pairs, plus properties of the labelling that hold at any size.
+R-MAT scale 20, the degree-corrected SBM and the 256-graph planted batch are
+compared with the oracle in full (every threshold of the 64-point grid);
+R-MAT scale 26 (the benchmark's workload) in full against the oracle's
+digests of every edge and vertex, and on sampled edges the oracle evaluates
+one by one from the raw pairs, plus properties of the labelling that hold at
+any size.
 """
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -74,8 +76,9 @@ def test_c3_dcsbm_sweep_64_with_ari():
     lo, hi = oracle.canon(n, c["src"], c["dst"])
     deg = oracle.degrees(n, lo, hi)
     t_o = oracle.triangles(n, lo, hi)
-    pick = list(range(0, 64, 4)) + [63]
-    st_o, ari_o, lab_o = oracle.sweep(n, lo, hi, t_o, deg, oracle.TECTONIC, [GRID64[i] for i in pick], c["truth"])
+    pick = list(range(64))
+    st_o, ari_o, lab_o = oracle.sweep(n, lo, hi, t_o, deg, oracle.TECTONIC, [GRID64[i] for i in pick], c["truth"],
+                                      workers=min(16, os.cpu_count() or 1))
     for j, i in enumerate(pick):
         assert np.array_equal(stats[i], st_o[0, j]), (i, stats[i], st_o[0, j])
         assert abs(ari[i] - ari_o[0, j]) <= 1e-12
@@ -84,7 +87,7 @@ def test_c3_dcsbm_sweep_64_with_ari():
     assert np.all(np.diff(stats[:, 0]) <= 0) and np.all(np.diff(stats[:, 1]) >= 0)
 
 
-def test_c4_batch_256_sweep_sampled_thresholds():
+def test_c4_batch_256_sweep_every_threshold():
     from gpu_util import build
     b = gg.sbm_batch(256)
     n, vbase = b["n"], b["vbase"]
@@ -96,9 +99,9 @@ def test_c4_batch_256_sweep_sampled_thresholds():
     lo, hi = oracle.canon(n, b["src"], b["dst"])
     deg = oracle.degrees(n, lo, hi)
     t_o = oracle.triangles(n, lo, hi)
-    pick = [0, 9, 18, 27, 36, 45, 54, 63]
+    pick = list(range(64))
     st_o, ari_o, _ = oracle.sweep(n, lo, hi, t_o, deg, oracle.TECTONIC, [GRID64[i] for i in pick], b["truth"],
-                                  vbase)
+                                  vbase, workers=min(16, os.cpu_count() or 1))
     for j, i in enumerate(pick):
         assert np.array_equal(stats[:, i], st_o[:, j]), i
         assert np.all(np.abs(ari[:, i] - ari_o[:, j]) <= 1e-12), i
@@ -175,3 +178,77 @@ def test_c5_rmat_s26_sampled_edges_and_label_properties():
     perm = M.mcd_graph_perm(g).long()
     a, b = perm[pairs[:, 0]], perm[pairs[:, 1]]
     assert bool((lab[a] == lab[b]).all())
+
+
+GOLD_S26 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat_s26_seed3_digests.json")
+
+
+def _chunk_sha(a, chunk):
+    import hashlib
+    a = np.ascontiguousarray(a)
+    return [hashlib.sha256(memoryview(a[i:i + chunk]).cast("B")).hexdigest() for i in range(0, len(a), chunk)]
+
+
+def _bits_sha(bits_u8, chunk):
+    import hashlib
+    packed = np.packbits(bits_u8, bitorder="little")
+    return [hashlib.sha256(memoryview(packed[i:i + chunk // 8])).hexdigest() for i in range(0, len(packed), chunk // 8)]
+
+
+def _same(name, got, want, chunk):
+    bad = [i for i, (a, b) in enumerate(zip(got, want)) if a != b]
+    assert len(got) == len(want) and not bad, (
+        f"{name}: {len(bad)} of {len(want)} chunks differ; first differing elements "
+        f"[{bad[0] * chunk}, {(bad[0] + 1) * chunk})" if bad else f"{name}: {len(got)} chunks, want {len(want)}")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD_S26), reason="oracle digests of R-MAT scale 26 not generated")
+def test_c5_rmat_s26_every_edge_and_vertex_equals_oracle():
+    """The benchmark's workload in full: canonical edges, degrees, t of all
+    1.05 billion edges, keep masks at four thresholds and the labels of all
+    67 million vertices against the digests of the CPU oracle (written by
+    tests/golden/make_rmat_s26_digests.py from oracle/ alone)."""
+    import json
+    gold = json.load(open(GOLD_S26))
+    CH = gold["chunk"]
+    src, dst, n = gg.rmat(26, seed=3)
+    assert n == gold["n"] and len(src) == gold["pairs"]
+    print(f"C5 digests: R-MAT scale 26 seed 3, {len(src)} pairs", flush=True)
+    ctx = M.mcd_ctx_create(0)
+    g = M.mcd_graph_build(ctx, cuda(src), cuda(dst), n)
+    del src, dst
+    assert g.m == gold["m"] and g.max_deg == gold["max_degree"]
+    m = g.m
+    u, v = M.mcd_graph_edges(g)
+    lo, hi = torch.minimum(u, v), torch.maximum(u, v)
+    del u, v
+    order = torch.sort(lo.long() * n + hi.long()).indices
+    _same("lo", _chunk_sha(lo[order].cpu().numpy(), CH), gold["lo_sha256"], CH)
+    _same("hi", _chunk_sha(hi[order].cpu().numpy(), CH), gold["hi_sha256"], CH)
+    del lo, hi
+    _same("deg", _chunk_sha(M.mcd_graph_degrees(g).cpu().numpy(), CH), gold["deg_sha256"], CH)
+    t = M.mcd_triangles(g)
+    assert int(t[:m].sum(dtype=torch.int64).item()) == gold["t_sum"]
+    _same("t", _chunk_sha(t[order].cpu().numpy(), CH), gold["t_sha256"], CH)
+    print(f"C5 digests: edges, degrees and t of {m} edges equal the oracle's", flush=True)
+    measures = {"tectonic": M.MCD_SIM_TECTONIC, "tw": M.MCD_SIM_TW}
+    for d in gold["digested"]:
+        meas, delta = measures[d["measure"]], tuple(d["delta"])
+        r = M.mcd_prune_components(g, meas, t, delta=delta, want_f32=False)
+        assert int(r["n_kept"].item()) == d["n_kept"], d["delta"]
+        assert int(r["n_components"].item()) == d["n_components"], d["delta"]
+        kb = r["keep_bits"].view(torch.int32)
+        bits = ((kb[order >> 5] >> (order & 31).int()) & 1).to(torch.uint8).cpu().numpy()
+        _same(f"keep {d['measure']} {delta}", _bits_sha(bits, CH), d["keep_sha256"], CH)
+        lab = r["labels"]
+        _same(f"labels {d['measure']} {delta}", _chunk_sha(lab.cpu().numpy(), CH), d["labels_sha256"], CH)
+        assert int(torch.bincount(lab.long()).max().item()) == d["largest_component"]
+        del r, kb, bits, lab
+        print(f"C5 digests: {d['measure']} {delta[0]}/{delta[1]}: keep mask and labels equal the oracle's",
+              flush=True)
+    if "sweep16" in gold:
+        stats, _, _ = M.mcd_sweep(g, M.MCD_SIM_TECTONIC, t, [(k, 50) for k in range(16)])
+        st = stats.cpu().numpy()[0]
+        for k, row in enumerate(gold["sweep16"]):
+            assert (st[k, 0], st[k, 1], st[k, 2]) == (row["n_kept"], row["n_components"],
+                                                      row["largest_component"]), k
