@@ -35,7 +35,9 @@
  *   - Handles (mcd_ctx, mcd_graph) are host objects created and freed by the
  *     library.  A graph handle BORROWS the caller's storage buffer, which must
  *     outlive it.  One context per host thread.
- *   - Vertex ids are int32 in [0, n); n < 2^31; edge counts fit in int64.
+ *   - Vertex ids are int32 in [0, n); n < 2^31 - 1.  The build takes fewer
+ *     than 2^31 raw pairs (n_pairs < 2^31, so m < 2^31 undirected edges);
+ *     edge offsets and counts are int64 beyond that point.
  *   - Per-edge arrays are in LIBRARY EDGE ORDER: the order of mcd_graph_edges,
  *     fixed for a graph handle.  Vertex arrays are indexed by original id.
  */
@@ -121,7 +123,8 @@ const char* mcd_last_error(void);
 /* Sizes for mcd_graph_build on n_pairs raw pairs over n_vertices vertices:
  *   storage_bytes: the persistent graph storage the handle borrows;
  *   ws_bytes:      scratch needed only during the build.
- * Errors: MCD_ERR_INVALID_ARG, MCD_ERR_RANGE (n_vertices >= 2^31). */
+ * Errors: MCD_ERR_INVALID_ARG, MCD_ERR_RANGE (n_vertices >= 2^31 - 1 or
+ * n_pairs >= 2^31: the largest input is 2^31 - 1 raw pairs). */
 mcd_status mcd_graph_build_sizes(int64_t n_pairs, int64_t n_vertices, size_t* storage_bytes,
                                  size_t* ws_bytes);
 
@@ -428,20 +431,29 @@ mcd_status mcd_mlp_forward(mcd_ctx* ctx, const float* params, const float* mean,
 /* Scratch for mcd_mlp_gradient / mcd_mlp_train_step at this batch size. */
 mcd_status mcd_mlp_workspace_size(int32_t batch, size_t* bytes);
 
-/* Gradient of L = (1/batch) sum (y - target)^2 with respect to params (device
- * float[MCD_MLP_PARAMS]) and L itself (device float[1], may be NULL), summed
- * over the batch in a fixed order. */
+/* Gradient of the training loss L = (1/batch) sum over rows of
+ *     mse_weight (y - target)^2 - ARI_r((K - 1) y)
+ * with respect to params (device float[MCD_MLP_PARAMS]), and L itself (device
+ * float[1], may be NULL), summed over the batch in a fixed order.  ari (device
+ * double[batch][K], K >= 2, may be NULL: no ARI term) is each row's ARI at
+ * the K grid thresholds; ARI_r(z) interpolates it linearly at z clamped to
+ * [0, K - 1] (segment chosen in fp32), with slope 0 outside 0 < z < K - 1.
+ * mse_weight >= 0 (1 with no ARI table: the plain squared error).  The ARI
+ * term makes the network's snapped threshold score well under the sweep's own
+ * judge, the ARI against the planted partition. */
 mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
-                            const float* x, const float* target, int32_t batch, float* grad, float* loss,
-                            void* ws, size_t ws_bytes);
+                            const float* x, const float* target, const double* ari, int32_t K, float mse_weight,
+                            int32_t batch, float* grad, float* loss, void* ws, size_t ws_bytes);
 
 /* One full-batch Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
  * step counted from 1) on params with moment buffers adam_m, adam_v (device
  * float[MCD_MLP_PARAMS], zero before step 1), with decoupled weight decay
- * (p -= lr * weight_decay * p first; 0 = plain Adam).  loss: the pre-step loss. */
+ * (p -= lr * weight_decay * p first; 0 = plain Adam), on the loss of
+ * mcd_mlp_gradient.  loss: the pre-step loss. */
 mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
                               float lr, float weight_decay, const float* mean, const float* std, const float* x,
-                              const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes);
+                              const float* target, const double* ari, int32_t K, float mse_weight, int32_t batch,
+                              float* loss, void* ws, size_t ws_bytes);
 
 /* The picker as a library object.  mcd_picker_create allocates its device
  * state (parameters, Adam moments, standardisation, training range: 103 KB)
@@ -475,17 +487,20 @@ mcd_status mcd_picker_destroy(mcd_picker* p);
 mcd_status mcd_picker_prepare(mcd_picker* p, const float* x, int32_t batch, float min_std, float margin);
 
 /* One Adam step as mcd_mlp_train_step on the picker's own parameters and
- * moments (its step counter advances); loss (device float[1]) may be NULL.
+ * moments (its step counter advances), K = MCD_PICKER_GRID_K: ari (device
+ * double[batch][64], the rows' ARI over the picker's grid, may be NULL) and
+ * mse_weight as there.  loss (device float[1]) may be NULL.
  * ws: mcd_mlp_workspace_size(batch). */
-mcd_status mcd_picker_train_step(mcd_picker* p, const float* x, const float* y, int32_t batch, float lr,
-                                 float weight_decay, float* loss, void* ws, size_t ws_bytes);
+mcd_status mcd_picker_train_step(mcd_picker* p, const float* x, const float* y, const double* ari, float mse_weight,
+                                 int32_t batch, float lr, float weight_decay, float* loss, void* ws, size_t ws_bytes);
 
-/* mcd_picker_prepare, then `steps` train steps on (x, y): full-batch
- * training on the sweep's targets (mcd_sweep_targets).  losses: device
- * float[steps], each step's pre-step loss, may be NULL.  Asynchronous. */
-mcd_status mcd_picker_fit(mcd_picker* p, const float* x, const float* y, int32_t batch, int32_t steps, float lr,
-                          float weight_decay, float min_std, float margin, float* losses, void* ws,
-                          size_t ws_bytes);
+/* mcd_picker_prepare, then `steps` train steps on (x, y, ari): full-batch
+ * training on the sweep's targets (mcd_sweep_targets) and ARI table
+ * (mcd_sweep).  losses: device float[steps], each step's pre-step loss, may
+ * be NULL.  Asynchronous. */
+mcd_status mcd_picker_fit(mcd_picker* p, const float* x, const float* y, const double* ari, float mse_weight,
+                          int32_t batch, int32_t steps, float lr, float weight_decay, float min_std, float margin,
+                          float* losses, void* ws, size_t ws_bytes);
 
 /* The network's output y (device float[batch]) for features x. */
 mcd_status mcd_picker_forward(const mcd_picker* p, const float* x, int32_t batch, float* y);

@@ -2,7 +2,9 @@
 
 A plain numpy statement of the network and its training rule:
   y = W3 . relu(W2 relu(W1 xs + b1) + b2) + b3,   xs = (x - mean) / std,
-  L = (1/B) sum_r (y_r - target_r)^2,
+  L = (1/B) sum_r [mse_w (y_r - target_r)^2 - A_r((K-1) y_r)]
+  (A_r: the row's ARI curve over the threshold grid, linearly interpolated;
+  without it, mse_w = 1 gives the plain squared error),
   Adam (Kingma & Ba, ICLR 2015): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
   p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
 Parameters are one flat vector: W1[64][66], b1[64], W2[64][64], b2[64], W3[64], b3.
@@ -39,17 +41,44 @@ def forward(p, mean, std, x):
     return y, (xs, a1, h1, a2, h2)
 
 
-def loss(p, mean, std, x, target):
+def row_loss(y, target, ari=None, mse_w=1.0):
+    """Per-row training loss and its derivative in y:
+        mse_w (y - target)^2 - A_r((K-1) y),
+    A_r the row's ARI curve over the K grid thresholds, interpolated linearly
+    at z clamped to [0, K-1] (slope 0 outside 0 < z < K-1).  The segment
+    index is decided in fp32, the precision of the network output, as on the
+    GPU; the value and slope are formed in fp64."""
+    y = np.asarray(y, np.float64)
+    d = y - np.asarray(target, np.float64)
+    L = mse_w * d * d
+    g = 2.0 * mse_w * d
+    if ari is not None:
+        ari = np.asarray(ari, np.float64)
+        K = ari.shape[1]
+        zy32 = np.float32(K - 1) * y.astype(np.float32)
+        z32 = np.clip(zy32, np.float32(0), np.float32(K - 1))
+        i0 = np.minimum(np.floor(z32).astype(np.int64), K - 2)
+        rows = np.arange(len(y))
+        a0, a1 = ari[rows, i0], ari[rows, i0 + 1]
+        z = np.clip((K - 1) * y, 0.0, K - 1.0)
+        L = L - (a0 + (z - i0) * (a1 - a0))
+        inside = (zy32 > 0) & (zy32 < np.float32(K - 1))
+        g = g - np.where(inside, (K - 1) * (a1 - a0), 0.0)
+    return L, g
+
+
+def loss(p, mean, std, x, target, ari=None, mse_w=1.0):
     y, _ = forward(p, mean, std, x)
-    return float(np.mean((y - target) ** 2))
+    return float(np.mean(row_loss(y, target, ari, mse_w)[0]))
 
 
-def gradient(p, mean, std, x, target):
+def gradient(p, mean, std, x, target, ari=None, mse_w=1.0):
     """Analytic gradient of the loss (chain rule, ReLU derivative 1 iff > 0)."""
     P = unpack(p)
     y, (xs, a1, h1, a2, h2) = forward(p, mean, std, x)
     B = len(y)
-    dy = 2.0 * (y - target) / B
+    rl, dl = row_loss(y, target, ari, mse_w)
+    dy = dl / B
     g = {"W3": dy @ h2, "b3": np.array([dy.sum()])}
     dh2 = np.outer(dy, P["W3"]) * (a2 > 0)
     g["W2"] = dh2.T @ h1
@@ -57,7 +86,7 @@ def gradient(p, mean, std, x, target):
     dh1 = (dh2 @ P["W2"]) * (a1 > 0)
     g["W1"] = dh1.T @ xs
     g["b1"] = dh1.sum(0)
-    return pack(g), float(np.mean((y - target) ** 2))
+    return pack(g), float(np.mean(rl))
 
 
 def adam_step(p, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):

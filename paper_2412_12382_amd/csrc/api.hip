@@ -871,30 +871,37 @@ mcd_status mcd_mlp_workspace_size(int32_t batch, size_t* bytes) {
 }
 
 mcd_status mcd_mlp_gradient(mcd_ctx* ctx, const float* params, const float* mean, const float* std,
-                            const float* x, const float* target, int32_t batch, float* grad, float* loss,
-                            void* ws, size_t ws_bytes) {
+                            const float* x, const float* target, const double* ari, int32_t K, float mse_weight,
+                            int32_t batch, float* grad, float* loss, void* ws, size_t ws_bytes) {
     REQUIRE_ALIGNED(ws);
     REQUIRE(ctx && params && mean && std && x && target && grad && ws && batch >= 1, MCD_ERR_INVALID_ARG,
             "NULL argument or empty batch");
+    REQUIRE(!ari || K >= 2, MCD_ERR_INVALID_ARG, "an ARI table needs K >= 2");
+    REQUIRE(mse_weight >= 0.f && mse_weight < 1e30f, MCD_ERR_INVALID_ARG, "mse_weight must be finite and >= 0");
     REQUIRE(ws_bytes >= mcd::mlp_scratch_bytes(batch), MCD_ERR_WORKSPACE, "MLP workspace too small");
     mcd_status st = use_device(ctx);
     if (st != MCD_OK) return st;
-    mcd::launch_mlp_gradient(params, mean, std, x, target, batch, grad, loss, ws, ctx->stream);
+    const mcd::MlpLoss L{target, ari, K, mse_weight};
+    mcd::launch_mlp_gradient(params, mean, std, x, L, batch, grad, loss, ws, ctx->stream);
     return MCD_OK;
 }
 
 mcd_status mcd_mlp_train_step(mcd_ctx* ctx, float* params, float* adam_m, float* adam_v, int32_t step,
                               float lr, float weight_decay, const float* mean, const float* std, const float* x,
-                              const float* target, int32_t batch, float* loss, void* ws, size_t ws_bytes) {
+                              const float* target, const double* ari, int32_t K, float mse_weight, int32_t batch,
+                              float* loss, void* ws, size_t ws_bytes) {
     REQUIRE_ALIGNED(ws);
     REQUIRE(ctx && params && adam_m && adam_v && mean && std && x && target && ws && batch >= 1,
             MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
     REQUIRE(step >= 1, MCD_ERR_INVALID_ARG, "Adam steps count from 1");
+    REQUIRE(!ari || K >= 2, MCD_ERR_INVALID_ARG, "an ARI table needs K >= 2");
+    REQUIRE(mse_weight >= 0.f && mse_weight < 1e30f, MCD_ERR_INVALID_ARG, "mse_weight must be finite and >= 0");
     REQUIRE(ws_bytes >= mcd::mlp_scratch_bytes(batch), MCD_ERR_WORKSPACE, "MLP workspace too small");
     mcd_status st = use_device(ctx);
     if (st != MCD_OK) return st;
-    mcd::launch_mlp_train_step(params, adam_m, adam_v, step, lr, weight_decay, mean, std, x, target, batch,
-                               loss, ws, ctx->stream);
+    const mcd::MlpLoss L{target, ari, K, mse_weight};
+    mcd::launch_mlp_train_step(params, adam_m, adam_v, step, lr, weight_decay, mean, std, x, L, batch, loss, ws,
+                               ctx->stream);
     return MCD_OK;
 }
 

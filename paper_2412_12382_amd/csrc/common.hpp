@@ -227,10 +227,18 @@ void launch_features(const mcd_graph* g, const int32_t* t, int G, const int64_t*
 size_t mlp_scratch_bytes(int B);
 void launch_mlp_forward(const float* params, const float* mean, const float* stdv, const float* x, int B,
                         float* y, hipStream_t s);
+// Training loss per row: mse_w (y - target)^2, minus (when ari, the row's
+// ARI curve of K thresholds, is given) the ARI interpolated at (K-1) y.
+struct MlpLoss {
+    const float* target;
+    const double* ari;  // [B][K] or null
+    int K;
+    float mse_w;
+};
 void launch_mlp_gradient(const float* params, const float* mean, const float* stdv, const float* x,
-                         const float* target, int B, float* grad, float* loss, void* ws, hipStream_t s);
+                         const MlpLoss& L, int B, float* grad, float* loss, void* ws, hipStream_t s);
 void launch_mlp_train_step(float* params, float* m1, float* m2, int step, float lr, float wd, const float* mean,
-                           const float* stdv, const float* x, const float* target, int B, float* loss, void* ws,
+                           const float* stdv, const float* x, const MlpLoss& L, int B, float* loss, void* ws,
                            hipStream_t s);
 void launch_select(const float* y, int B, int K, int64_t a, int64_t b, int64_t c, int32_t* index,
                    int64_t* delta, hipStream_t s);

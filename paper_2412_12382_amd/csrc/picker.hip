@@ -170,11 +170,34 @@ __global__ __launch_bounds__(64) void k_mlp_fwd(const float* __restrict__ p, con
     }
 }
 
-// Per-row gradient of L = (1/B) sum_r (y_r - target_r)^2 into part[r][NPAR].
+// The training loss of one row with output y (MlpLoss): mse_w (y - target)^2,
+// minus, when the row's ARI curve a[0..K-1] is given, the ARI interpolated
+// linearly at z = (K-1) y clamped to [0, K-1].  The segment index is decided
+// in fp32.  Returns the loss; *dldy its derivative in y (the ARI term's slope
+// is 0 outside 0 < z < K-1).
+__device__ __forceinline__ float row_loss(const MlpLoss& L, int r, float y, float* dldy) {
+    const float d = y - L.target[r];
+    float loss = L.mse_w * d * d, g = 2.f * L.mse_w * d;
+    if (L.ari) {
+        const double* a = L.ari + (int64_t)r * L.K;
+        const float zmax = (float)(L.K - 1);
+        const float z = fminf(fmaxf(zmax * y, 0.f), zmax);
+        int i0 = (int)floorf(z);
+        if (i0 > L.K - 2) i0 = L.K - 2;
+        const float a0 = (float)a[i0], a1 = (float)a[i0 + 1];
+        loss -= a0 + (z - (float)i0) * (a1 - a0);
+        const float zy = zmax * y;
+        if (zy > 0.f && zy < zmax) g -= zmax * (a1 - a0);
+    }
+    *dldy = g;
+    return loss;
+}
+
+// Per-row gradient of the mean of row_loss over the batch into part[r][NPAR].
 __global__ __launch_bounds__(64) void k_mlp_bwd_row(const float* __restrict__ p, const float* __restrict__ xs_all,
                                                     const float* __restrict__ h1_all,
                                                     const float* __restrict__ h2_all,
-                                                    const float* __restrict__ y, const float* __restrict__ target,
+                                                    const float* __restrict__ y, MlpLoss L,
                                                     int B, float* __restrict__ part) {
     const int r = blockIdx.x, j = threadIdx.x;
     if (r >= B) return;
@@ -182,7 +205,9 @@ __global__ __launch_bounds__(64) void k_mlp_bwd_row(const float* __restrict__ p,
     for (int k = j; k < NI; k += 64) xs[k] = xs_all[(int64_t)r * NI + k];
     h1[j] = h1_all[(int64_t)r * NH + j];
     const float h2 = h2_all[(int64_t)r * NH + j];
-    const float dy = 2.f * (y[r] - target[r]) / (float)B;
+    float dldy;
+    row_loss(L, r, y[r], &dldy);
+    const float dy = dldy / (float)B;
     float* g = part + (int64_t)r * NPAR;
     g[OFF_W3 + j] = dy * h2;
     if (j == 0) g[OFF_B3] = dy;
@@ -200,8 +225,7 @@ __global__ __launch_bounds__(64) void k_mlp_bwd_row(const float* __restrict__ p,
 
 // grad[q] = sum over rows r = 0..B-1 (in order) of part[r][q]; loss likewise
 __global__ __launch_bounds__(kThreads) void k_mlp_reduce(const float* __restrict__ part, int B,
-                                                         const float* __restrict__ y,
-                                                         const float* __restrict__ target,
+                                                         const float* __restrict__ y, MlpLoss L,
                                                          float* __restrict__ grad, float* __restrict__ loss) {
     GRID_STRIDE(q, NPAR) {
         float s = 0.f;
@@ -209,11 +233,8 @@ __global__ __launch_bounds__(kThreads) void k_mlp_reduce(const float* __restrict
         grad[q] = s;
     }
     if (loss && blockIdx.x == 0 && threadIdx.x == 0) {
-        float l = 0.f;
-        for (int r = 0; r < B; ++r) {
-            const float d = y[r] - target[r];
-            l += d * d;
-        }
+        float l = 0.f, unused;
+        for (int r = 0; r < B; ++r) l += row_loss(L, r, y[r], &unused);
         *loss = l / (float)B;
     }
 }
@@ -411,19 +432,19 @@ void launch_mlp_forward(const float* params, const float* mean, const float* std
 }
 
 void launch_mlp_gradient(const float* params, const float* mean, const float* stdv, const float* x,
-                         const float* target, int B, float* grad, float* loss, void* ws, hipStream_t s) {
+                         const MlpLoss& L, int B, float* grad, float* loss, void* ws, hipStream_t s) {
     MlpWs w = mlp_ws(ws, B);
     hipLaunchKernelGGL(k_mlp_fwd, dim3(B), dim3(64), 0, s, params, mean, stdv, x, B, w.y, w.xs, w.h1, w.h2);
-    hipLaunchKernelGGL(k_mlp_bwd_row, dim3(B), dim3(64), 0, s, params, w.xs, w.h1, w.h2, w.y, target, B, w.part);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(NPAR, 64)), dim3(kThreads), 0, s, w.part, B, w.y, target,
+    hipLaunchKernelGGL(k_mlp_bwd_row, dim3(B), dim3(64), 0, s, params, w.xs, w.h1, w.h2, w.y, L, B, w.part);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(NPAR, 64)), dim3(kThreads), 0, s, w.part, B, w.y, L,
                        grad ? grad : w.grad, loss);
 }
 
 void launch_mlp_train_step(float* params, float* m1, float* m2, int step, float lr, float wd, const float* mean,
-                           const float* stdv, const float* x, const float* target, int B, float* loss, void* ws,
+                           const float* stdv, const float* x, const MlpLoss& L, int B, float* loss, void* ws,
                            hipStream_t s) {
     MlpWs w = mlp_ws(ws, B);
-    launch_mlp_gradient(params, mean, stdv, x, target, B, w.grad, loss, ws, s);
+    launch_mlp_gradient(params, mean, stdv, x, L, B, w.grad, loss, ws, s);
     hipLaunchKernelGGL(k_adam, dim3(grid_for(NPAR, 64)), dim3(kThreads), 0, s, params, w.grad, m1, m2, step, lr,
                        wd, 0.9f, 0.999f, 1e-8f);
 }

@@ -285,9 +285,10 @@ mcd_status mcd_picker_prepare(mcd_picker* p, const float* x, int32_t batch, floa
     return MCD_OK;
 }
 
-mcd_status mcd_picker_train_step(mcd_picker* p, const float* x, const float* y, int32_t batch, float lr,
-                                 float weight_decay, float* loss, void* ws, size_t ws_bytes) {
+mcd_status mcd_picker_train_step(mcd_picker* p, const float* x, const float* y, const double* ari, float mse_weight,
+                                 int32_t batch, float lr, float weight_decay, float* loss, void* ws, size_t ws_bytes) {
     REQUIRE(p && x && y && ws && batch >= 1, MCD_ERR_INVALID_ARG, "NULL argument or empty batch");
+    REQUIRE(mse_weight >= 0.f && mse_weight < 1e30f, MCD_ERR_INVALID_ARG, "mse_weight must be finite and >= 0");
     REQUIRE(((uintptr_t)ws & 255u) == 0u, MCD_ERR_INVALID_ARG, "ws must be 256-byte aligned");
     REQUIRE(p->prepared, MCD_ERR_INVALID_ARG, "mcd_picker_prepare must come before training");
     REQUIRE(ws_bytes >= mcd::mlp_scratch_bytes(batch), MCD_ERR_WORKSPACE, "MLP workspace too small");
@@ -295,20 +296,21 @@ mcd_status mcd_picker_train_step(mcd_picker* p, const float* x, const float* y, 
     mcd_status st = use_device(p->ctx);
     if (st != MCD_OK) return st;
     p->step += 1;
-    mcd::launch_mlp_train_step(p->params, p->adam_m, p->adam_v, p->step, lr, weight_decay, p->mean, p->stdv, x, y,
+    const mcd::MlpLoss L{y, ari, kGridK, mse_weight};
+    mcd::launch_mlp_train_step(p->params, p->adam_m, p->adam_v, p->step, lr, weight_decay, p->mean, p->stdv, x, L,
                                batch, loss, ws, p->ctx->stream);
     return MCD_OK;
 }
 
-mcd_status mcd_picker_fit(mcd_picker* p, const float* x, const float* y, int32_t batch, int32_t steps, float lr,
-                          float weight_decay, float min_std, float margin, float* losses, void* ws,
-                          size_t ws_bytes) {
+mcd_status mcd_picker_fit(mcd_picker* p, const float* x, const float* y, const double* ari, float mse_weight,
+                          int32_t batch, int32_t steps, float lr, float weight_decay, float min_std, float margin,
+                          float* losses, void* ws, size_t ws_bytes) {
     REQUIRE(p && steps >= 0, MCD_ERR_INVALID_ARG, "NULL picker or negative step count");
     mcd_status st = mcd_picker_prepare(p, x, batch, min_std, margin);
     if (st != MCD_OK) return st;
     for (int32_t k = 0; k < steps; ++k)
-        if ((st = mcd_picker_train_step(p, x, y, batch, lr, weight_decay, losses ? losses + k : nullptr, ws,
-                                        ws_bytes)) != MCD_OK)
+        if ((st = mcd_picker_train_step(p, x, y, ari, mse_weight, batch, lr, weight_decay,
+                                        losses ? losses + k : nullptr, ws, ws_bytes)) != MCD_OK)
             return st;
     return MCD_OK;
 }

@@ -90,8 +90,9 @@ def lib():
             "mcd_picker_fallback": [P, P, I32, P, P, ctypes.c_float, P, P, P, P],
             "mcd_mlp_forward": [P, P, P, P, P, I32, P],
             "mcd_mlp_workspace_size": [I32, ctypes.POINTER(SZ)],
-            "mcd_mlp_gradient": [P, P, P, P, P, P, I32, P, P, P, SZ],
-            "mcd_mlp_train_step": [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, P, P, P, P, I32, P, P, SZ],
+            "mcd_mlp_gradient": [P, P, P, P, P, P, P, I32, ctypes.c_float, I32, P, P, P, SZ],
+            "mcd_mlp_train_step": [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, P, P, P, P, P, I32,
+                                   ctypes.c_float, I32, P, P, SZ],
             "mcd_grid_select": [P, P, I32, I32, I64, I64, I64, P, P],
             "mcd_sweep_targets": [P, P, I32, I32, ctypes.c_double, P, P],
             "mcd_prune_graphs": [P, ctypes.c_int, P, I32, P, P, P, P],
@@ -107,9 +108,9 @@ def lib():
             "mcd_picker_create": [P, ctypes.c_uint64, PP],
             "mcd_picker_destroy": [P],
             "mcd_picker_prepare": [P, P, I32, ctypes.c_float, ctypes.c_float],
-            "mcd_picker_train_step": [P, P, P, I32, ctypes.c_float, ctypes.c_float, P, P, SZ],
-            "mcd_picker_fit": [P, P, P, I32, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P,
-                               P, SZ],
+            "mcd_picker_train_step": [P, P, P, P, ctypes.c_float, I32, ctypes.c_float, ctypes.c_float, P, P, SZ],
+            "mcd_picker_fit": [P, P, P, P, ctypes.c_float, I32, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, P, P, SZ],
             "mcd_picker_forward": [P, P, I32, P],
             "mcd_picker_pick_workspace_size": [P, I32, ctypes.POINTER(SZ)],
             "mcd_picker_pick": [P, P, ctypes.c_int, P, I32, P, I32, P, P, P, P, P, P, SZ],
@@ -481,24 +482,29 @@ def mcd_mlp_workspace_size(batch: int) -> int:
     return b.value
 
 
-def mcd_mlp_gradient(ctx: Context, params, mean, std, x, target, grad=None, loss=None, ws=None):
+def mcd_mlp_gradient(ctx: Context, params, mean, std, x, target, grad=None, loss=None, ws=None, ari=None,
+                     mse_weight: float = 1.0):
+    """ari: optional device float64 [B][K] ARI table (the loss then subtracts
+    the ARI interpolated at (K-1) y)."""
     B = x.shape[0]
+    K = 0 if ari is None else ari.shape[1]
     grad = _empty(MLP_PARAMS, torch.float32, ctx.device) if grad is None else grad
     loss = _empty(1, torch.float32, ctx.device) if loss is None else loss
     ws = _bytes(mcd_mlp_workspace_size(B), ctx.device) if ws is None else ws
-    _check(lib().mcd_mlp_gradient(ctx.handle, _p(params), _p(mean), _p(std), _p(x), _p(target), B, _p(grad),
-                                  _p(loss), _p(ws), ws.numel() * ws.element_size()))
+    _check(lib().mcd_mlp_gradient(ctx.handle, _p(params), _p(mean), _p(std), _p(x), _p(target), _p(ari), K,
+                                  mse_weight, B, _p(grad), _p(loss), _p(ws), ws.numel() * ws.element_size()))
     return grad, loss
 
 
 def mcd_mlp_train_step(ctx: Context, params, adam_m, adam_v, step: int, lr: float, mean, std, x, target,
-                       loss=None, ws=None, weight_decay: float = 0.0):
+                       loss=None, ws=None, weight_decay: float = 0.0, ari=None, mse_weight: float = 1.0):
     B = x.shape[0]
+    K = 0 if ari is None else ari.shape[1]
     loss = _empty(1, torch.float32, ctx.device) if loss is None else loss
     ws = _bytes(mcd_mlp_workspace_size(B), ctx.device) if ws is None else ws
     _check(lib().mcd_mlp_train_step(ctx.handle, _p(params), _p(adam_m), _p(adam_v), step, lr, weight_decay,
-                                    _p(mean), _p(std),
-                                    _p(x), _p(target), B, _p(loss), _p(ws), ws.numel() * ws.element_size()))
+                                    _p(mean), _p(std), _p(x), _p(target), _p(ari), K, mse_weight, B, _p(loss),
+                                    _p(ws), ws.numel() * ws.element_size()))
     return loss
 
 
@@ -558,22 +564,24 @@ def mcd_picker_prepare(p: PickerHandle, x, min_std: float = 1.0, margin: float =
     _check(lib().mcd_picker_prepare(p.handle, _p(x), x.shape[0], min_std, margin))
 
 
-def mcd_picker_train_step(p: PickerHandle, x, y, lr: float, weight_decay: float = 0.0, loss=None, ws=None):
+def mcd_picker_train_step(p: PickerHandle, x, y, lr: float, weight_decay: float = 0.0, loss=None, ws=None,
+                          ari=None, mse_weight: float = 1.0):
     B = x.shape[0]
     loss = _empty(1, torch.float32, p.ctx.device) if loss is None else loss
     ws = _bytes(mcd_mlp_workspace_size(B), p.ctx.device) if ws is None else ws
-    _check(lib().mcd_picker_train_step(p.handle, _p(x), _p(y), B, lr, weight_decay, _p(loss), _p(ws),
-                                       ws.numel() * ws.element_size()))
+    _check(lib().mcd_picker_train_step(p.handle, _p(x), _p(y), _p(ari), mse_weight, B, lr, weight_decay, _p(loss),
+                                       _p(ws), ws.numel() * ws.element_size()))
     return loss
 
 
 def mcd_picker_fit(p: PickerHandle, x, y, steps: int, lr: float, weight_decay: float = 0.0, min_std: float = 1.0,
-                   margin: float = PICKER_MARGIN, losses=None, ws=None):
+                   margin: float = PICKER_MARGIN, losses=None, ws=None, ari=None, mse_weight: float = 1.0):
+    """ari: optional device float64 [B][64] ARI table over the picker's grid."""
     B = x.shape[0]
     losses = _empty(max(steps, 1), torch.float32, p.ctx.device) if losses is None else losses
     ws = _bytes(mcd_mlp_workspace_size(B), p.ctx.device) if ws is None else ws
-    _check(lib().mcd_picker_fit(p.handle, _p(x), _p(y), B, steps, lr, weight_decay, min_std, margin, _p(losses),
-                                _p(ws), ws.numel() * ws.element_size()))
+    _check(lib().mcd_picker_fit(p.handle, _p(x), _p(y), _p(ari), mse_weight, B, steps, lr, weight_decay, min_std,
+                                margin, _p(losses), _p(ws), ws.numel() * ws.element_size()))
     return losses[:steps]
 
 

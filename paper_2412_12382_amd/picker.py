@@ -39,12 +39,20 @@ class Picker:
         M.mcd_picker_save(self.handle, path)
 
 
-def train(ctx, x, y, steps: int = 2000, lr: float = 3e-3, seed: int = 0, weight_decay: float = 1.0,
-          min_std: float = 1.0):
-    """Full-batch Adam (decoupled weight decay) on (x, y) (device tensors),
-    from the seeded initial weights; returns (Picker, losses as numpy)."""
+def train(ctx, x, y, ari=None, steps: int = 2000, lr: float = 3e-3, seed: int = 0, weight_decay: float | None = None,
+          min_std: float = 1.0, mse_weight: float | None = None):
+    """Full-batch Adam (decoupled weight decay) from the seeded initial
+    weights on features x and targets y (device tensors); with the training
+    graphs' ARI table over the grid (ari, float64 [B][64]) the loss also
+    rewards the ARI at the network's threshold (mse_weight 0.1, weight decay
+    0.1 by default), else it is the squared error to y (weight decay 1).
+    Returns (Picker, losses as numpy)."""
+    if weight_decay is None:
+        weight_decay = 1.0 if ari is None else 0.1
+    if mse_weight is None:
+        mse_weight = 1.0 if ari is None else 0.1
     h = M.mcd_picker_create(ctx, seed)
-    losses = M.mcd_picker_fit(h, x, y, steps, lr, weight_decay, min_std, MARGIN)
+    losses = M.mcd_picker_fit(h, x, y, steps, lr, weight_decay, min_std, MARGIN, ari=ari, mse_weight=mse_weight)
     return Picker(h), losses.cpu().numpy()
 
 

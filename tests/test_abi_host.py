@@ -29,6 +29,13 @@ def test_sizes_validation():
     with pytest.raises(M.MCDError) as ei:
         M.mcd_graph_build_sizes(10, 1 << 31)
     assert ei.value.status == -3
+    # the largest input: 2^31 - 1 raw pairs, n below 2^31 - 1
+    st, ws = M.mcd_graph_build_sizes((1 << 31) - 1, (1 << 31) - 2)
+    assert st > 8 * ((1 << 31) - 1) and ws > 8 * ((1 << 31) - 1)
+    for pairs, n in (((1 << 31), 10), (10, (1 << 31) - 1)):
+        with pytest.raises(M.MCDError) as ei:
+            M.mcd_graph_build_sizes(pairs, n)
+        assert ei.value.status == -3
 
 
 def test_null_arguments_rejected_without_device():

@@ -49,6 +49,36 @@ def test_mlp_forward_and_gradient():
         assert abs(float(loss.item()) - lo) <= 1e-5 * max(lo, 1.0)
 
 
+def test_mlp_gradient_with_ari_term():
+    # the training loss with the sweep's ARI table: mse_w (y - t)^2 minus the
+    # ARI interpolated at 63 y; rows whose 63 y lies near a grid point (where
+    # the fp32 segment choice could differ) are left out of the batch
+    from gpu_util import ctx
+    B = 40
+    p, mean, std, x, target = rand_problem(9, B)
+    p[8448:8512] *= 0.02
+    yo, _ = mlp.forward(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x)
+    p[8512] += np.float32(0.5 - np.median(yo))
+    yo, _ = mlp.forward(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x)
+    z = 63 * yo
+    keep = (z > 0.05) & (z < 62.95) & (np.abs(z - np.round(z)) > 0.01)
+    x, target = x[keep], target[keep]
+    assert len(x) >= 10
+    ari = np.random.default_rng(10).uniform(-0.1, 1.0, (len(x), 64))
+    g, loss = M.mcd_mlp_gradient(ctx(), cuda(p), cuda(mean), cuda(std), cuda(x), cuda(target), ari=cuda(ari),
+                                 mse_weight=0.1)
+    P64, m64, s64 = p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64)
+    go, lo = mlp.gradient(P64, m64, s64, x, target.astype(np.float64), ari, 0.1)
+    sabs = np.zeros(mlp.NPAR)
+    for r in range(len(x)):
+        gr, _ = mlp.gradient(P64, m64, s64, x[r:r + 1], target[r:r + 1].astype(np.float64), ari[r:r + 1], 0.1)
+        sabs += np.abs(gr) / len(x)
+    g = g.cpu().numpy()
+    tol = 1e-4 * (np.abs(go) + 1e-3) + 4 * (len(x) + 8) * 2.0 ** -24 * sabs
+    assert np.all(np.abs(g - go) <= tol), np.max(np.abs(g - go) / tol)
+    assert abs(float(loss.item()) - lo) <= 1e-5 * max(abs(lo), 1.0)
+
+
 def test_adam_step_matches_reference():
     from gpu_util import ctx
     B, lr = 32, 1e-3

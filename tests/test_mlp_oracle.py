@@ -143,3 +143,44 @@ def test_features_on_complete_graph_and_star():
     want[21], want[32] = 0.5, 0.5
     want[64], want[65] = math.log1p(20 / 6), math.log(6.0)
     assert np.allclose(x, want, rtol=1e-15, atol=0)
+
+
+def test_ari_loss_hand_cases():
+    # three grid thresholds with ARI 0.1, 0.5, 0.3; mse weight 0.25, target 0.5
+    ari = np.array([[0.1, 0.5, 0.3]] * 4)
+    y = np.array([0.25, 0.75, -0.5, 1.2])
+    L, g = mlp.row_loss(y, np.full(4, 0.5), ari, mse_w=0.25)
+    # z = 2y: 0.5 -> 0.1 + 0.5 * 0.4 = 0.3, slope 2 * 0.4; 1.5 -> 0.5 - 0.5 * 0.2 = 0.4,
+    # slope -2 * 0.2; -1 and 2.4 clamp to the ends (0.1 and 0.3) with slope 0
+    assert np.allclose(L, 0.25 * (y - 0.5) ** 2 - np.array([0.3, 0.4, 0.1, 0.3]), rtol=0, atol=1e-15)
+    assert np.allclose(g, 0.5 * (y - 0.5) - np.array([0.8, -0.4, 0.0, 0.0]), rtol=0, atol=1e-15)
+    # without a table: the squared error alone
+    L0, g0 = mlp.row_loss(y, np.full(4, 0.5))
+    assert np.array_equal(L0, (y - 0.5) ** 2) and np.array_equal(g0, 2 * (y - 0.5))
+
+
+def test_ari_loss_gradient_central_differences():
+    # away from the grid points the loss is smooth: central differences of the
+    # whole network's loss match the analytic gradient
+    p, mean, std, x, target = rand_problem(3, B=24)
+    rng = np.random.default_rng(4)
+    ari = rng.uniform(-0.1, 1.0, (24, 64))
+    # rescale the last layer so that (K-1) y spreads over (0, 63)
+    p = p.copy()
+    y, _ = mlp.forward(p, mean, std, x)
+    sd = np.std(y) if np.std(y) > 0 else 1.0
+    p[8448:8512] *= (10.0 / 63) / sd
+    y, _ = mlp.forward(p, mean, std, x)
+    p[8512] += 0.5 - np.median(y)
+    y, _ = mlp.forward(p, mean, std, x)
+    z = 63 * y
+    keep = (z > 0.01) & (z < 62.99) & (np.abs(z - np.round(z)) > 0.01)
+    x, target, ari = x[keep], target[keep], ari[keep]
+    assert len(x) >= 8
+    g, _ = mlp.gradient(p, mean, std, x, target, ari, mse_w=0.1)
+    h = 1e-7
+    for q in rng.choice(mlp.NPAR, 200, replace=False).tolist() + [mlp.NPAR - 1]:
+        e = np.zeros(mlp.NPAR)
+        e[q] = h
+        num = (mlp.loss(p + e, mean, std, x, target, ari, 0.1) - mlp.loss(p - e, mean, std, x, target, ari, 0.1)) / (2 * h)
+        assert abs(num - g[q]) <= 1e-5 * max(abs(num), 1.0), (q, num, g[q])
