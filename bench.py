@@ -247,6 +247,17 @@ def cpu_baseline(scale: int, ef: int, seed: int, single: bool = True):
                       f"Tectonic weights, prune at 3/50, BFS components; {main_leg['seconds']:.2f} s",
                seconds=main_leg["seconds"], stages_s=main_leg["stages_s"], peak_rss_gib=main_leg["peak_rss_gib"],
                host=_host_facts())
+    # the oracle's one full run at scale 26 (the run that wrote the committed
+    # digests the GPU path is checked against), as recorded by that run
+    gold = os.path.join(ROOT, "tests", "golden", "rmat_s26_seed3_digests.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            d = json.load(f)
+        secs = d.get("seconds", {})
+        res["full_size_oracle_run"] = dict(
+            workload=d["workload"], m=d["m"], host=d.get("host"), peak_rss_gib=d.get("peak_rss_gib"),
+            stages_s=secs, edges_per_s_canon_and_triangles=d["m"] / (secs["canon"] + secs["triangles"]),
+            note="recorded by tests/golden/make_rmat_s26_digests.py on its own host, not timed here")
     if single:
         res["one_thread"] = {}
         for name, spec in (("C1", "sbm:0:0"), ("C2", "rmat:20:1"), ("C3", "dcsbm:0:2")):
@@ -284,7 +295,7 @@ def picker_study(M, PK, dev):
     base, _ = PK.train(ctx, x[cu(tr)].contiguous(), y[cu(tr)].contiguous())
     bidx, _, _, _, _ = PK.pick(g, t, base, vb, fallback="off")
     ari_base = float(A[va, bidx.cpu().numpy()[va]].mean())
-    # the picker: the 192 graphs, 3072 more of their distribution and 512
+    # the picker: the 192 graphs, 11264 more of their distribution and 512
     # degree-corrected SBMs, trained on the ARI at its threshold
     x_tr, y_tr, ari_tr = PT.training_set(ctx, log=log)
     torch.cuda.synchronize()
@@ -297,7 +308,7 @@ def picker_study(M, PK, dev):
     fl = flags.cpu().numpy().astype(bool)
     pi = np.where(fl, ri, index.cpu().numpy())  # the grid point each graph used (fallback where out of range)
     res = dict(train_graphs=int(x_tr.shape[0]),
-               training_set="192 planted-batch training graphs + 3072 more of that distribution + 512 "
+               training_set="192 planted-batch training graphs + 11264 more of that distribution + 512 "
                             "degree-corrected SBMs (seeds disjoint from the validation graphs and the DC-SBM "
                             "workload); loss: 0.1 (y - target)^2 minus the interpolated ARI at 63 y",
                val_graphs=int(len(va)), train_steps=len(losses),

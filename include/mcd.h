@@ -107,7 +107,10 @@ mcd_status mcd_ctx_set_stream(mcd_ctx* ctx, void* stream);
  *                (0: read them per pair);
  *   "sweep_shape" launch shape of mcd_sweep's level loop (one persistent
  *                launch): 0 = 1024 threads per block, 1 = 512, 2 = 256
- *                threads per block, default 0.
+ *                threads per block, default 0;
+ *   "tc_window_occupancy" the rank-bitmap triangle kernels built for 8
+ *                waves per SIMD (1) or with the compiler's register budget
+ *                (0), default 1.  Counts are identical either way.
  * Errors: MCD_ERR_INVALID_ARG (unknown name), MCD_ERR_RANGE (bad value). */
 mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value);
 mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* value);

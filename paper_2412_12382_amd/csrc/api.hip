@@ -209,6 +209,7 @@ mcd_status mcd_ctx_create(int device, void* stream, mcd_ctx** out) {
     c->tc_window_max = MCD_TC_WINDOW_LIMIT;
     c->k4_row_cache = 1;
     c->sweep_shape = 0;
+    c->tc_window_occupancy = 1;
     if (hipMalloc((void**)&c->d_ctrl, sizeof(int64_t) * MCD_CTRL_WORDS) != hipSuccess) {
         delete c;
         return mcd_fail(MCD_ERR_DEVICE, "hipMalloc of the control block failed");
@@ -270,6 +271,9 @@ mcd_status mcd_ctx_set_param(mcd_ctx* ctx, const char* name, int64_t value) {
     } else if (k == "sweep_shape") {
         REQUIRE(value >= 0 && value <= 2, MCD_ERR_RANGE, "sweep_shape must be 0, 1 or 2");
         ctx->sweep_shape = value;
+    } else if (k == "tc_window_occupancy") {
+        REQUIRE(value == 0 || value == 1, MCD_ERR_RANGE, "tc_window_occupancy must be 0 or 1");
+        ctx->tc_window_occupancy = value;
     } else {
         return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     }
@@ -285,6 +289,7 @@ mcd_status mcd_ctx_get_param(const mcd_ctx* ctx, const char* name, int64_t* valu
     else if (k == "tc_window_max") *value = ctx->tc_window_max;
     else if (k == "k4_row_cache") *value = ctx->k4_row_cache;
     else if (k == "sweep_shape") *value = ctx->sweep_shape;
+    else if (k == "tc_window_occupancy") *value = ctx->tc_window_occupancy;
     else return mcd_fail(MCD_ERR_INVALID_ARG, "unknown parameter " + k);
     return MCD_OK;
 }

@@ -24,6 +24,7 @@ struct mcd_ctx {
     int64_t tc_window_max;    // widest rank range of a row held as an LDS rank window
     int64_t k4_row_cache;     // 4-cliques: keep the row offsets of L in LDS when they fit
     int64_t sweep_shape;      // launch shape of the sweep's level loop (0, 1, 2)
+    int64_t tc_window_occupancy;  // rank-window kernels built for 8 waves per SIMD (1) or not (0)
     // side streams (default priority) and events on which the triangle
     // count runs its work-item classes concurrently, forked from and joined
     // back into `stream`

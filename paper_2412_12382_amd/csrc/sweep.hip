@@ -637,33 +637,46 @@ struct SweepArgs {
 // then on no block waits any more, so the kernel always ends (its statistics
 // are then marked invalid, n_components = -1).
 __device__ void grid_sync(const SweepArgs& a) {
+    // Every wave waits until its own stores and atomics have completed at the
+    // L2: the block barrier alone orders them only within the CU, and the
+    // first thread's agent-scope release below writes back the L2 as it
+    // stands, so other waves' writes must have reached it by then.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         GridSync* s = a.sync;
         if (!__hip_atomic_load(&s->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            __threadfence();
+            // Arrival releases the block's writes (complete at the L2, see
+            // above); the last block of a group acquires
+            // its group's writes and releases them on at the top counter; the
+            // last group acquires everything and releases it with the new
+            // generation, which every waiting block then acquires.
             const unsigned ng = a.nblocks < kSyncGroups ? a.nblocks : kSyncGroups;
             const unsigned gi = blockIdx.x % ng;
             const unsigned members = a.nblocks / ng + (gi < a.nblocks % ng ? 1u : 0u);
             GridSync::Group* gr = &s->grp[gi];
             const unsigned g = __hip_atomic_load(&gr->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (atomicAdd(&gr->count, 1u) == members - 1) {  // last of its group
+            if (__hip_atomic_fetch_add(&gr->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __hip_atomic_store(&gr->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (atomicAdd(&s->top, 1u) == ng - 1) {  // last group: release everyone
+                if (__hip_atomic_fetch_add(&s->top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == ng - 1) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     __hip_atomic_store(&s->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     for (unsigned h = 0; h < ng; ++h)
                         __hip_atomic_fetch_add(&s->grp[h].gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(&gr->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(&gr->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(4);
                 if (wall_clock64() - t0 > a.limit) {
                     __hip_atomic_store(&s->timed_out, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
-            __threadfence();
+            // acquire every block's released writes (the block barrier below
+            // passes them on to the other threads of the block)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
     }
     __syncthreads();

@@ -343,8 +343,8 @@ __device__ __forceinline__ int32_t load_chunk(const int32_t* __restrict__ adj, c
 // in-edge's bitmask (bits, at wbase[e] + chunk index), for k_tc_credit.
 // Wide windows take large workgroups so that the LDS they need still leaves
 // room for enough waves per CU.
-template <int LOG2R, int NT, int D>
-__global__ __launch_bounds__(NT) void k_tc_window_s(const Item* __restrict__ all_items,
+template <int LOG2R, int NT, int D, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict__ all_items,
                                                     const int64_t* __restrict__ heads, int cls,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ adj,
@@ -565,65 +565,179 @@ __global__ __launch_bounds__(kThreads) void k_tc_words(const int64_t* __restrict
     }
 }
 
-// The credits of the hit bitmasks, one wave per row u of the orientation.
-// With d the row's length and x_j the bitmask of its j-th edge u -> w_j (bit
-// s: the suffix element w_(j+1+s) is a common neighbour, i.e. {u, w_j,
-// w_(j+1+s)} is a triangle),
+// The credits of the hit bitmasks.  With d the length of row u and x_j the
+// bitmask of its j-th edge u -> w_j (bit s: the suffix element w_(j+1+s) is a
+// common neighbour, i.e. {u, w_j, w_(j+1+s)} is a triangle),
 //     t(u, w_k) += #{ j < k : bit k - j - 1 of x_j }   (column sums)
 //     t(u, w_j) += popcount(x_j)                       (the in-edge's count)
-// The row is cut into tiles of 64 positions; for a tile, 64 bitmasks at a
-// time are realigned to it (lane j holds the 64 bits of x_j that fall on the
-// tile) and summed column by column with wave ballots.  Each position of t
-// belongs to one row, so the additions are plain stores; the pass runs after
-// every other credit has landed.
-__device__ __forceinline__ unsigned long long tile_bits(const unsigned long long* __restrict__ bits, int64_t w0,
-                                                        int64_t nw, int64_t s0) {
-    if (nw <= 0 || s0 <= -64) return 0ull;
-    if (s0 < 0) return bits[w0] << (-s0);
-    const int64_t wi = s0 >> 6;
-    const int sh = (int)(s0 & 63);
-    const unsigned long long lo = wi < nw ? bits[w0 + wi] : 0ull;
-    if (sh == 0) return lo;
-    const unsigned long long hi = wi + 1 < nw ? bits[w0 + wi + 1] : 0ull;
-    return (lo >> sh) | (hi << (64 - sh));
+// Each position of t belongs to one row, so the additions are plain stores;
+// the passes run after every other credit has landed.
+//
+// Rows of at most kShortRow edges (bitmasks of one word): edge-parallel, one
+// lane per edge over 64-edge windows; the earlier edges of a lane's row lie
+// within 63 positions, in its window or the previous one, so the column sum
+// is a walk over the distances k = 1 .. 63 with two lane shuffles each.
+constexpr int64_t kShortRow = 64;
+
+__global__ __launch_bounds__(kThreads) void k_tc_credit_short(const int64_t* __restrict__ off,
+                                                              const int32_t* __restrict__ src,
+                                                              const int64_t* __restrict__ wbase,
+                                                              const unsigned long long* __restrict__ bits,
+                                                              int64_t m, int64_t per_wave,
+                                                              int32_t* __restrict__ t) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int64_t nwin = (m + 63) >> 6;
+    const int64_t w_begin = wave * per_wave, w_end = min(nwin, w_begin + per_wave);
+    if (w_begin >= w_end) return;
+    // a lane's bitmask word (rows of at most kShortRow edges only) and its
+    // position in its row; -1 for lanes outside such rows
+    auto load = [&](int64_t win, unsigned long long& x, int32_t& j) {
+        const int64_t e = win * 64 + lane;
+        x = 0ull;
+        j = -1;
+        if (e < m) {
+            const int64_t rs = off[src[e]], d = off[src[e] + 1] - rs;
+            if (d <= kShortRow) {
+                j = (int32_t)(e - rs);
+                const int64_t w0 = wbase[e];
+                if (wbase[e + 1] > w0) x = bits[w0];
+            }
+        }
+    };
+    unsigned long long xprev = 0ull, x;
+    int32_t jprev, j;
+    if (w_begin > 0) load(w_begin - 1, xprev, jprev);
+    for (int64_t win = w_begin; win < w_end; ++win) {
+        load(win, x, j);
+        // distances that can reach an earlier edge of the same short row
+        int kmax = j > 0 ? j : 0;
+        for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+        int32_t col = 0;
+        if (__ballot(x != 0ull || xprev != 0ull) != 0ull) {
+            for (int k = 1; k <= kmax; ++k) {
+                const int srcl = (lane - k) & 63;
+                const unsigned long long a = __shfl(x, srcl), b = __shfl(xprev, srcl);
+                const unsigned long long xs = lane >= k ? a : b;
+                if (k <= j) col += (int32_t)((xs >> (k - 1)) & 1ull);
+            }
+        }
+        const int32_t add = col + __popcll(x);
+        if (j >= 0 && add) t[win * 64 + lane] += add;
+        xprev = x;
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_tc_credit(const int64_t* __restrict__ off,
-                                                        const int64_t* __restrict__ wbase,
-                                                        const unsigned long long* __restrict__ bits, int64_t n,
-                                                        int32_t* __restrict__ t) {
+// Rows longer than kShortRow: the row is cut into tiles of 64 positions and
+// the tiles into runs of kRun; one wave per run, the runs of all such rows
+// dealt out over the grid (a hub row's runs spread over many waves).  For a
+// run, the bitmasks of the row's edges are taken 64 at a time, lane j holding
+// edge j's: the lane loads the kRun + 1 consecutive words of its bitmask that
+// cover the run and realigns them to the tiles (one shift for all of them),
+// then, tile by tile, the 64 x 64 bit block is transposed across the lanes and
+// each lane's popcount is its column's sum, kept in registers until the run's
+// end.  Each bitmask word is thus read once per run instead of once per tile.
+constexpr int kRun = 16;
+
+// 64 x 64 bit transpose across the wave: lane j holds row j on entry, lane i
+// holds column i (bit j = bit i of row j) on exit.  Six stages swap the
+// off-diagonal blocks of 32, 16, ..., 1 bits between lanes j and j ^ s.
+__device__ __forceinline__ unsigned long long transpose64(unsigned long long x, int lane) {
+    const unsigned long long masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                         0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int sh = 32 >> k;
+        const unsigned long long m = masks[k];
+        const unsigned long long y = __shfl_xor(x, sh);
+        x = (lane & sh) ? ((x & ~m) | ((y & ~m) >> sh)) : ((x & m) | ((y & m) << sh));
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_tc_credit_long(const int64_t* __restrict__ off,
+                                                             const int64_t* __restrict__ wbase,
+                                                             const unsigned long long* __restrict__ bits,
+                                                             const int32_t* __restrict__ run_row,
+                                                             const int64_t* __restrict__ rbase, int64_t n,
+                                                             int32_t* __restrict__ t) {
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (kThreads / 64);
-    for (int64_t u = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); u < n; u += nwaves) {
+    const int64_t nr = rbase[n];
+    for (int64_t q = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); q < nr; q += nwaves) {
+        const int64_t u = run_row[q];
         const int64_t e0 = off[u], d = off[u + 1] - e0;
-        if (d < 2 || wbase[e0 + d] == wbase[e0]) continue;  // no bitmask in this row
-        const int64_t T = (d + 63) >> 6;
-        for (int64_t c = 0; c < T; ++c) {
-            const int64_t k0 = 64 * c;
-            const int ncol = (int)min((int64_t)64, d - k0);
-            int32_t col = 0;
-            for (int64_t gq = 0; gq <= c; ++gq) {
-                const int64_t j = 64 * gq + lane;
-                unsigned long long x = 0ull;
-                if (j < d - 1) {
-                    const int64_t w0 = wbase[e0 + j];
-                    x = tile_bits(bits, w0, wbase[e0 + j + 1] - w0, k0 - j - 1);
+        const int64_t c0 = (q - rbase[u]) * kRun;  // first tile of the run
+        const int64_t k0 = 64 * c0;                // its first position
+        const int nc = (int)min((int64_t)kRun, ((d + 63) >> 6) - c0);
+        // edges with a bit in the run: j < min(d - 1, k0 + 64 nc - 1)
+        const int64_t jend = min(d - 1, k0 + 64 * (int64_t)nc - 1);
+        int32_t col[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) col[k] = 0;
+        for (int64_t jb = 0; jb < jend; jb += 64) {
+            const int64_t j = jb + lane;
+            // bit s of edge j's bitmask is position j + 1 + s; the run starts at
+            // suffix offset s0 = k0 - j - 1, so tile k's bits are the bitmask's
+            // bits s0 + 64 k ... s0 + 64 k + 63
+            unsigned long long W[kRun + 1];
+            int sh = 0;
+            if (j < jend) {
+                const int64_t w0 = wbase[e0 + j], nw = wbase[e0 + j + 1] - w0;
+                const int64_t s0 = k0 - j - 1;
+                const int64_t wi = s0 >> 6;  // floor
+                sh = (int)(s0 & 63);
+#pragma unroll
+                for (int k = 0; k <= kRun; ++k) {
+                    const int64_t i = wi + k;
+                    W[k] = (i >= 0 && i < nw) ? bits[w0 + i] : 0ull;
                 }
-                if (__ballot(x != 0ull) == 0ull) continue;
-                for (int i = 0; i < ncol; ++i) {
-                    const unsigned long long b = __ballot((x >> i) & 1ull);
-                    if (lane == i) col += __popcll(b);
-                }
+            } else {
+#pragma unroll
+                for (int k = 0; k <= kRun; ++k) W[k] = 0ull;
             }
-            // popcounts of this tile's own bitmasks
-            const int64_t j = k0 + lane;
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const unsigned long long x = sh ? ((W[k] >> sh) | (W[k + 1] << (64 - sh))) : W[k];
+                if (__ballot(x != 0ull) == 0ull) continue;
+                col[k] += __popcll(transpose64(x, lane));
+            }
+        }
+        // popcounts of the run's own bitmasks (edge j credits t at its own
+        // position with its hit count), then the column sums
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            if (k >= nc) break;
+            const int64_t j = k0 + 64 * k + lane;
             int32_t pc = 0;
             if (j < d - 1) {
                 const int64_t w1 = wbase[e0 + j + 1];
                 for (int64_t wq = wbase[e0 + j]; wq < w1; ++wq) pc += __popcll(bits[wq]);
             }
-            if (j < d && (col | pc)) t[e0 + j] += col + pc;
+            if (j < d && (col[k] | pc)) t[e0 + j] += col[k] + pc;
         }
+    }
+}
+
+// Runs of every row longer than kShortRow that holds bitmask words:
+// ceil(ceil(length / 64) / kRun), else 0.
+__global__ __launch_bounds__(kThreads) void k_long_runs(const int64_t* __restrict__ off,
+                                                        const int64_t* __restrict__ wbase, int64_t n,
+                                                        int32_t* __restrict__ runs) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = off[u], b = off[u + 1];
+        const int64_t tiles = (b - a + 63) >> 6;
+        runs[u] = (b - a > kShortRow && wbase[b] > wbase[a]) ? (int32_t)((tiles + kRun - 1) / kRun) : 0;
+    }
+}
+
+// The row of every run: run_row[rbase[u] + r] = u for r < runs[u].
+__global__ __launch_bounds__(kThreads) void k_run_rows(const int32_t* __restrict__ runs,
+                                                       const int64_t* __restrict__ rbase, int64_t n,
+                                                       int32_t* __restrict__ run_row) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = runs[u];
+        for (int32_t r = 0; r < k; ++r) run_row[rbase[u] + r] = (int32_t)u;
     }
 }
 
@@ -682,6 +796,9 @@ struct TcLayout {
     int32_t* words;  // [m] bitmask words per edge
     int64_t* wbase;  // [m+1] first bitmask word per edge
     unsigned long long* bits;  // [bitmask words] hit bitmasks
+    int32_t* rruns;    // [n] runs of a row longer than kShortRow with bitmask words
+    int64_t* rbase;    // [n+1] its first run
+    int32_t* run_row;  // [m/32 + 1] row of every run
     void* scan;
     size_t bytes;
 };
@@ -699,6 +816,10 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     L.words = c.take<int32_t>((size_t)m);
     L.wbase = c.take<int64_t>((size_t)m + 1);
     L.bits = c.take<unsigned long long>((size_t)g->bitmask_words);
+    L.rruns = c.take<int32_t>((size_t)n);
+    L.rbase = c.take<int64_t>((size_t)n + 1);
+    // rows longer than 64 hold at most length / 32 tiles (so runs) each
+    L.run_row = c.take<int32_t>((size_t)(m / 32) + 1);
     L.scan = c.take<char>(scan_scratch_bytes(n > m ? n : m));
     L.bytes = c.used;
     return L;
@@ -715,14 +836,23 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
                        L.items, L.heads, c, g->off, g->adj, g->in_ea, t);
 }
 
-// ipart / nparts: this launch takes every nparts-th item of the class
+// ipart / nparts: this launch takes every nparts-th item of the class.
+// tc_window_occupancy = 1 (the default) takes the build of the kernel held to
+// 8 waves per SIMD (some scalar registers spilled to vector lanes) instead of
+// the compiler's own budget of 106 scalar registers, which allows 7: with
+// 16-wave workgroups that is the difference between one and two resident
+// workgroups per CU (R-MAT scale 26: 625 -> 513 ms for the whole count).
 template <int LOG2R, int NT, int D>
 void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
                    int ipart = 0, int nparts = 1) {
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = cap_items < 16384 ? cap_items : 16384;
-    hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads, c,
-                       g->off, g->adj, g->in_ea, L.wbase, L.bits, t, ipart, nparts);
+    if (g->ctx->tc_window_occupancy)
+        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 8>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads,
+                           c, g->off, g->adj, g->in_ea, L.wbase, L.bits, t, ipart, nparts);
+    else
+        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 1>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads,
+                           c, g->off, g->adj, g->in_ea, L.wbase, L.bits, t, ipart, nparts);
 }
 
 }  // namespace
@@ -763,14 +893,17 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     launch_window<16, 1024, 8>(g, L, 9, chunk, t, s1, 0, 2);
     launch_window<16, 1024, 8>(g, L, 9, chunk, t, s, 1, 2);
     launch_window<18, 1024, 8>(g, L, 10, chunk, t, s2);
+    // the hash classes after the windows, placed so that the three streams
+    // end together (at R-MAT scale 26 the side stream s1's window half ends
+    // first and takes the two largest hash classes)
     launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s1);
-    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s2);
-    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s2);
-    launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s1);
+    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s1);
     launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s2);
     launch_class<RowHash<13, true>, 4096, 4, 64>(g, L, 3, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
+    launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
+    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
     (void)hipEventRecord(c->join[0], s1);
@@ -778,7 +911,19 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     (void)hipStreamWaitEvent(s, c->join[0], 0);
     (void)hipStreamWaitEvent(s, c->join[1], 0);
     // every class has finished: the bitmasks' credits, row by row
-    hipLaunchKernelGGL(k_tc_credit, dim3(grid_for(n, 16384)), dim3(kThreads), 0, s, g->off, L.wbase, L.bits, n, t);
+    {
+        const int64_t m = g->m, nwin = (m + 63) >> 6;
+        const int64_t waves = 65536, per_wave = (nwin + waves - 1) / waves;
+        hipLaunchKernelGGL(k_tc_credit_short, dim3((unsigned)((waves + 3) / 4)), dim3(kThreads), 0, s, g->off, g->src,
+                           L.wbase, L.bits, m, per_wave, t);
+        hipLaunchKernelGGL(k_long_runs, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, L.wbase, n,
+                           L.rruns);
+        exclusive_scan_i32_i64(L.rruns, n, L.rbase, L.scan, s);
+        hipLaunchKernelGGL(k_run_rows, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, L.rruns, L.rbase, n,
+                           L.run_row);
+        hipLaunchKernelGGL(k_tc_credit_long, dim3(8192), dim3(kThreads), 0, s, g->off, L.wbase, L.bits, L.run_row,
+                           L.rbase, n, t);
+    }
 }
 
 }  // namespace mcd

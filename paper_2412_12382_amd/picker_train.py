@@ -8,7 +8,8 @@ against the planted labels, supplies both the target and the loss:
 
   * the 192 training graphs of the 256-graph planted batch (graphs g with
     g % 4 != 3; the others are the validation graphs and are never trained on);
-  * n_extra further graphs of the same distribution (graphs 256, 257, ...);
+  * n_extra further graphs of the same distribution (graphs 256, 257, ...;
+    11,264 by default, so graphs 256 .. 11,519);
   * n_dcsbm small degree-corrected SBMs (power-law degrees and community
     sizes, seeded from 5000), so that heavy-tailed graphs fall inside the
     range the picker was trained on.
@@ -71,7 +72,7 @@ def sweep_batch(ctx, b, dev):
     return x, ari
 
 
-def training_set(ctx, n_extra: int = 3072, n_dcsbm: int = 512, log=None):
+def training_set(ctx, n_extra: int = 11264, n_dcsbm: int = 512, log=None):
     """(x float32 [B][66], y float32 [B], ari float64 [B][64]) on the device:
     the C4 training graphs, n_extra more of their distribution and n_dcsbm
     degree-corrected ones."""
@@ -108,7 +109,7 @@ def training_set(ctx, n_extra: int = 3072, n_dcsbm: int = 512, log=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True, help="checkpoint file to write")
-    ap.add_argument("--extra", type=int, default=3072)
+    ap.add_argument("--extra", type=int, default=11264)
     ap.add_argument("--dcsbm", type=int, default=512)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--seed", type=int, default=0)

@@ -159,23 +159,26 @@ def test_repeat_runs_bit_identical():
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("chunk,lds_max,packed,window", [(512, 4096, 1048574, 262144), (1, 4096, 1048574, 0),
-                                                         (7, 100, 0, 0), (64, 0, 1048574, 262144),
-                                                         (3, 600, 5000, 5000), (100000, 2048, 0, 0),
-                                                         (512, 4096, 0, 0), (5, 4096, 1048574, 16384),
-                                                         (9, 4096, 1048574, 65536)])
-def test_triangle_paths_and_chunks(chunk, lds_max, packed, window):
-    # every launch configuration (work-item size, LDS classes vs binary search)
-    # must give the oracle's counts
+@pytest.mark.parametrize("chunk,lds_max,packed,window,occ", [(512, 4096, 1048574, 262144, 0), (1, 4096, 1048574, 0, 0),
+                                                             (7, 100, 0, 0, 0), (64, 0, 1048574, 262144, 0),
+                                                             (3, 600, 5000, 5000, 0), (100000, 2048, 0, 0, 0),
+                                                             (512, 4096, 0, 0, 0), (5, 4096, 1048574, 16384, 0),
+                                                             (9, 4096, 1048574, 65536, 0),
+                                                             (512, 4096, 1048574, 262144, 1),
+                                                             (5, 4096, 1048574, 16384, 1),
+                                                             (9, 4096, 1048574, 65536, 1)])
+def test_triangle_paths_and_chunks(chunk, lds_max, packed, window, occ):
+    # every launch configuration (work-item size, LDS classes vs binary search,
+    # the rank-window kernels' register budget) must give the oracle's counts
     from gpu_util import ctx, build
     s, d, n = gg.rmat(15, seed=21)
     lo, hi = oracle.canon(n, s, d)
     t_o = oracle.triangles(n, lo, hi)
     c = ctx()
-    names = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max")
+    names = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max", "tc_window_occupancy")
     old = [M.mcd_ctx_get_param(c, k) for k in names]
     try:
-        for k, val in zip(names, (chunk, lds_max, packed, window)):
+        for k, val in zip(names, (chunk, lds_max, packed, window, occ)):
             M.mcd_ctx_set_param(c, k, val)
         from gpu_util import canonical_order
         g = build(s, d, n)
@@ -208,7 +211,8 @@ def test_param_validation():
     from gpu_util import ctx
     c = ctx()
     for name, bad in (("tc_chunk", 0), ("tc_lds_max", 5000), ("tc_lds_max", -1),
-                      ("tc_packed_range", 1 << 20), ("tc_window_max", (1 << 18) + 1), ("k4_row_cache", 2)):
+                      ("tc_packed_range", 1 << 20), ("tc_window_max", (1 << 18) + 1), ("k4_row_cache", 2),
+                      ("tc_window_occupancy", 2), ("sweep_shape", 3)):
         with pytest.raises(M.MCDError) as ei:
             M.mcd_ctx_set_param(c, name, bad)
         assert ei.value.status == -3
