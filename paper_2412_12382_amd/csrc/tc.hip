@@ -8,7 +8,7 @@
 // the middle vertex v: a work item is v together with a slice of its in-edges
 // u->v.  The workgroup hashes N+(v) into LDS (key w -> position in N+(v)) and
 // every wave streams, for one in-edge at a time, the suffix of row u after v
-// in 64-element coalesced chunks, probing each element.  A hit w credits
+// in coalesced chunks, probing each element.  A hit w credits
 //     t(v,w) : an LDS counter of v's row, flushed once per work item;
 //     t(u,v) and t(u,w): in the rank-window classes (almost all the work),
 //              the wave's hit ballot of each chunk is stored as one 64-bit
@@ -280,9 +280,11 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
 
 // The chunks a wave streams for the rank-window kernel: `left` more in-edge
 // descriptors at dp, dp + stride, ... of its item, and for the current one
-// the suffix [pos, a1) of row u after v in 64-element chunks.  Descriptors
-// are fetched 64 at a time, one per lane (bx, by), and read out lane by lane
-// into scalar registers; every other field is wave-uniform.
+// the suffix [pos, a1) of row u after v in chunks of 64 E consecutive
+// elements (E per lane).  Descriptors are fetched 64 at a time, one per lane
+// (bx, by), and read out lane by lane into scalar registers; every other
+// field is wave-uniform.
+template <int E>
 struct ChunkGen {
     const int2* __restrict__ dp;
     const int64_t* __restrict__ wbase;  // first word of every edge's hit bitmask
@@ -293,7 +295,7 @@ struct ChunkGen {
     bool done;
     // move to the next non-empty chunk
     __device__ __forceinline__ void next(int lane) {
-        pos += 64;
+        pos += 64 * E;
         while (pos >= a1) {
             if (left == 0) {
                 done = true;
@@ -318,36 +320,46 @@ struct ChunkGen {
             a1 = e + 1 + len;
         }
     }
-    // bitmask word of the current chunk
+    // first bitmask word of the current chunk (one word per 64 elements)
     __device__ __forceinline__ int64_t word() const { return wb + ((pos - e - 1) >> 6); }
 };
 
-// The generator's current chunk as one element per lane (lanes past its end
+// Element 64 k + lane of the generator's current chunk (lanes past its end
 // repeat its last element).  Issued unconditionally, from a valid address
 // when the generator is done too (the kernel runs only on graphs with edges),
-// so that every slot of the ring below issues exactly one load and the wait
-// for a slot's data counts the loads issued after it.
-__device__ __forceinline__ int32_t load_chunk(const int32_t* __restrict__ adj, const ChunkGen& g, int lane) {
+// so that every slot of the ring below issues the same loads and the wait
+// for a slot's data counts the loads issued after it.  T16: from the 16-bit
+// copy of the adjacency (adj16[e] = adj[e] - top16 for the top 65,536 ranks),
+// for items whose suffixes lie entirely in that range.
+template <bool T16, int E>
+__device__ __forceinline__ int32_t load_elem(const int32_t* __restrict__ adj, const uint16_t* __restrict__ adj16,
+                                             int32_t top16, const ChunkGen<E>& g, int lane, int k) {
     const int32_t nv = g.done ? 1 : g.a1 - g.pos;
-    const int32_t* row = adj + (g.done ? 0 : g.pos);
-    return row[(uint32_t)(lane < nv ? lane : nv - 1)];
+    const int32_t i = 64 * k + lane;
+    const uint32_t j = (uint32_t)(i < nv ? i : nv - 1);
+    const int64_t p = g.done ? 0 : g.pos;
+    if (T16) return (int32_t)adj16[p + j] + top16;
+    return adj[p + j];
 }
 
 // Rank-window items, one item per workgroup of NT threads.  Each wave walks
-// its own in-edges of the item, one at a time, all 64 lanes on 64-element
-// chunks of the in-edge's suffix.  The walk (in-edge, chunk, loop control)
-// is wave-uniform, so it runs on the scalar unit and the vector work per
-// element is the probe alone; loads run D chunks ahead of their use in a
-// ring of registers.  t(v,w) partial counts are 32-bit LDS counters, one per
-// element of N+(v).  The hit ballot of every chunk is stored as a word of the
-// in-edge's bitmask (bits, at wbase[e] + chunk index), for k_tc_credit.
+// its own in-edges of the item, one at a time, all 64 lanes on chunks of
+// 64 E elements of the in-edge's suffix.  The walk (in-edge, chunk, loop
+// control) is wave-uniform, so it runs on the scalar unit and the vector work
+// per element is the probe alone; the scalar unit is shared by the CU's
+// waves, so a chunk of several elements per lane spreads its cost.  Loads
+// run D chunks ahead of their use in a ring of registers.  t(v,w) partial
+// counts are 32-bit LDS counters, one per element of N+(v).  The hit ballot
+// of every 64 elements is stored as a word of the in-edge's bitmask (bits, at
+// wbase[e] + suffix offset / 64), for the credit passes.
 // Wide windows take large workgroups so that the LDS they need still leaves
 // room for enough waves per CU.
-template <int LOG2R, int NT, int D, int MINW>
+template <int LOG2R, int NT, int D, int MINW, bool T16, int E>
 __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict__ all_items,
                                                     const int64_t* __restrict__ heads, int cls,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ adj,
+                                                    const uint16_t* __restrict__ adj16, int32_t top16,
                                                     const int2* __restrict__ in_ea,
                                                     const int64_t* __restrict__ wbase,
                                                     unsigned long long* __restrict__ bits,
@@ -402,10 +414,10 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
         __syncthreads();
 
         const uint32_t rmax = (uint32_t)(maxv - v - 1);  // ranks v+1 .. maxv are in the window
-        ChunkGen gen{in_ea + I.s + wave, wbase, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES,
-                     0, -64, 0, 64, 0, 0, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
+        ChunkGen<E> gen{in_ea + I.s + wave, wbase, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES,
+                        0, -64, 0, 64, 0, 0, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
         gen.next(lane);
-        int32_t w[D], spos[D], sa1[D];
+        int32_t w[D][E], spos[D], sa1[D];
         int64_t sw[D];
         bool sv[D];
 #pragma unroll
@@ -414,7 +426,8 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
             spos[q] = gen.pos;
             sa1[q] = gen.a1;
             sw[q] = gen.word();
-            w[q] = load_chunk(adj, gen, lane);
+#pragma unroll
+            for (int k = 0; k < E; ++k) w[q][k] = load_elem<T16>(adj, adj16, top16, gen, lane, k);
             if (sv[q]) gen.next(lane);
         }
         bool more = sv[0];
@@ -426,26 +439,39 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
                     break;
                 }
                 const int32_t pos = spos[q], nv = sa1[q] - pos;
-                const uint32_t r = (uint32_t)(w[q] - v - 1);
-                bool hit = false;
-                if (lane < nv && r <= rmax) {
-                    const uint32_t word = bm[r >> 5];
-                    const uint32_t bit = 1u << (r & 31);
-                    if (word & bit) {
-                        hit = true;
-                        atomicAdd(&cnt[(uint32_t)pre[r >> 5] + __popc(word & (bit - 1u))], 1u);
+                unsigned long long hb[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const uint32_t r = (uint32_t)(w[q][k] - v - 1);
+                    bool hit = false;
+                    if (64 * k + lane < nv && r <= rmax) {
+                        const uint32_t word = bm[r >> 5];
+                        const uint32_t bit = 1u << (r & 31);
+                        if (word & bit) {
+                            hit = true;
+                            atomicAdd(&cnt[(uint32_t)pre[r >> 5] + __popc(word & (bit - 1u))], 1u);
+                        }
                     }
+                    hb[k] = __ballot(hit);
                 }
-                // this chunk's word of the in-edge's hit bitmask: every word
-                // of a window in-edge is written, once
-                const unsigned long long hb = __ballot(hit);
-                if (lane == 0) __builtin_nontemporal_store(hb, &bits[sw[q]]);
+                // this chunk's words of the in-edge's hit bitmask, one per 64
+                // elements (lane k stores word k): every word of a window
+                // in-edge is written, once
+                const int nwords = (min(nv, 64 * E) + 63) >> 6;
+                if (lane < nwords) {
+                    unsigned long long x = hb[0];
+#pragma unroll
+                    for (int k = 1; k < E; ++k)
+                        if (lane == k) x = hb[k];
+                    __builtin_nontemporal_store(x, &bits[sw[q] + lane]);
+                }
                 // refill the slot with the chunk D ahead
                 sv[q] = !gen.done;
                 spos[q] = gen.pos;
                 sa1[q] = gen.a1;
                 sw[q] = gen.word();
-                w[q] = load_chunk(adj, gen, lane);
+#pragma unroll
+                for (int k = 0; k < E; ++k) w[q][k] = load_elem<T16>(adj, adj16, top16, gen, lane, k);
                 if (sv[q]) gen.next(lane);
             }
         }
@@ -503,12 +529,16 @@ __global__ __launch_bounds__(kThreads) void k_tc_search(const Item* __restrict__
 }
 
 // Work-item classes:
-//   0..3  hash, packed entries (row within 2^20 ranks above v), by row length
-//   4..7  hash, wide entries, by row length
-//   8..10 rank window of 2^14, 2^16, 2^18 ranks (rows longer than 128)
-//   11    binary search (rows longer than the LDS cap)
-constexpr int kClasses = 12;
+//   0..3   hash, packed entries (row within 2^20 ranks above v), by row length
+//   4..7   hash, wide entries, by row length
+//   8..10  rank window of 2^14, 2^16, 2^18 ranks (rows longer than 128)
+//   11     binary search (rows longer than the LDS cap)
+//   12, 13 rank window of 2^14, 2^16 ranks for v among the top 65,536 ranks:
+//          every suffix element then lies there too, and the suffixes are
+//          read from the 16-bit copy of the adjacency
+constexpr int kClasses = 14;
 constexpr int kSearch = 11;
+__host__ __device__ inline bool window_class(int c) { return (c >= 8 && c <= 10) || c == 12 || c == 13; }
 constexpr int kWindowLog2[3] = {14, 16, 18};
 
 // In-edges per work item: at least the row length (the hash build is then at
@@ -524,7 +554,7 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
                                                          const int32_t* __restrict__ adj,
                                                          const int64_t* __restrict__ in_off, int64_t n,
                                                          int64_t chunk, int64_t lds_max,
-                                                         int64_t packed_range, int64_t window_max,
+                                                         int64_t packed_range, int64_t window_max, int64_t top16,
                                                          int32_t* __restrict__ cnt, uint8_t* __restrict__ wflag) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -542,13 +572,14 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
                 if (B > kMaxB[0] && window_max > 0) {
                     for (int c = 2; c >= 0; --c)
                         if (R <= ((int64_t)1 << kWindowLog2[c]) && R <= window_max) cls = 8 + c;
+                    if (top16 >= 0 && v >= top16 && (cls == 8 || cls == 9)) cls += 4;
                 }
             }
         }
         const int64_t cs = item_size(chunk, B);
         const int32_t k = cls >= 0 ? (int32_t)((I + cs - 1) / cs) : 0;
         for (int c = 0; c < kClasses; ++c) cnt[(int64_t)c * n + v] = (c == cls) ? k : 0;
-        wflag[v] = (cls >= 8 && cls <= 10) ? 1 : 0;  // in-edges credited through hit bitmasks
+        wflag[v] = window_class(cls) ? 1 : 0;  // in-edges credited through hit bitmasks
     }
 }
 
@@ -741,6 +772,16 @@ __global__ __launch_bounds__(kThreads) void k_run_rows(const int32_t* __restrict
     }
 }
 
+// adj16[e] = adj[e] - top16 for ranks in the top 65,536 (others are never read
+// through it).
+__global__ __launch_bounds__(kThreads) void k_adj16(const int32_t* __restrict__ adj, int64_t m, int32_t top16,
+                                                    uint16_t* __restrict__ adj16) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = adj[e];
+        adj16[e] = a >= top16 ? (uint16_t)(a - top16) : (uint16_t)0xffff;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_item_fill(const int64_t* __restrict__ off,
                                                         const int64_t* __restrict__ in_off, int64_t n,
                                                         int64_t chunk, const int32_t* __restrict__ cnt,
@@ -780,6 +821,10 @@ __global__ void k_item_heads(const int64_t* __restrict__ base, int64_t n, int64_
     }
 }
 
+// First rank of the 16-bit range (the top 65,536 ranks; every rank when n is
+// smaller).
+inline int64_t top16_of(int64_t n) { return n > 65536 ? n - 65536 : 0; }
+
 inline unsigned grid_for(int64_t N, int64_t cap) {
     int64_t b = (N + kThreads - 1) / kThreads;
     if (b < 1) b = 1;
@@ -796,6 +841,7 @@ struct TcLayout {
     int32_t* words;  // [m] bitmask words per edge
     int64_t* wbase;  // [m+1] first bitmask word per edge
     unsigned long long* bits;  // [bitmask words] hit bitmasks
+    uint16_t* adj16;   // [m] 16-bit copy of the adjacency for the top 65,536 ranks
     int32_t* rruns;    // [n] runs of a row longer than kShortRow with bitmask words
     int64_t* rbase;    // [n+1] its first run
     int32_t* run_row;  // [m/32 + 1] row of every run
@@ -816,6 +862,7 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     L.words = c.take<int32_t>((size_t)m);
     L.wbase = c.take<int64_t>((size_t)m + 1);
     L.bits = c.take<unsigned long long>((size_t)g->bitmask_words);
+    L.adj16 = c.take<uint16_t>((size_t)m);
     L.rruns = c.take<int32_t>((size_t)n);
     L.rbase = c.take<int64_t>((size_t)n + 1);
     // rows longer than 64 hold at most length / 32 tiles (so runs) each
@@ -842,17 +889,27 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
 // the compiler's own budget of 106 scalar registers, which allows 7: with
 // 16-wave workgroups that is the difference between one and two resident
 // workgroups per CU (R-MAT scale 26: 625 -> 513 ms for the whole count).
-template <int LOG2R, int NT, int D>
+// Elements per lane of a rank-window chunk: 4, so that a wave's scalar walk
+// (in-edge, chunk, ring slot) is paid once per 256 suffix elements; with 4
+// ring slots a wave still has 16 loads in flight.  (R-MAT scale 26, whole
+// count: 1 element per lane 507 ms, 2 424 ms, 3 406 ms, 4 403 ms; ring depth
+// 2, 4 or 8 within 2 %.)
+constexpr int kWindowE = 4;
+
+template <int LOG2R, int NT, int D, bool T16 = false>
 void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
                    int ipart = 0, int nparts = 1) {
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = cap_items < 16384 ? cap_items : 16384;
+    const int32_t top16 = (int32_t)top16_of(g->n);
     if (g->ctx->tc_window_occupancy)
-        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 8>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads,
-                           c, g->off, g->adj, g->in_ea, L.wbase, L.bits, t, ipart, nparts);
+        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 8, T16, kWindowE>), dim3((unsigned)blocks), dim3(NT), 0, s,
+                           L.items, L.heads, c, g->off, g->adj, L.adj16, top16, g->in_ea, L.wbase, L.bits, t, ipart,
+                           nparts);
     else
-        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 1>), dim3((unsigned)blocks), dim3(NT), 0, s, L.items, L.heads,
-                           c, g->off, g->adj, g->in_ea, L.wbase, L.bits, t, ipart, nparts);
+        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 1, T16, kWindowE>), dim3((unsigned)blocks), dim3(NT), 0, s,
+                           L.items, L.heads, c, g->off, g->adj, L.adj16, top16, g->in_ea, L.wbase, L.bits, t, ipart,
+                           nparts);
 }
 
 }  // namespace
@@ -867,7 +924,9 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     TcLayout L = tc_layout(ws, g, chunk);
     const int64_t n = g->n;
     hipLaunchKernelGGL(k_item_count, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->adj, g->in_off,
-                       n, chunk, lds_max, packed_range, window_max, L.cnt, L.wflag);
+                       n, chunk, lds_max, packed_range, window_max, top16_of(n), L.cnt, L.wflag);
+    hipLaunchKernelGGL(k_adj16, dim3(grid_for(g->m, 16384)), dim3(kThreads), 0, s, g->adj, g->m,
+                       (int32_t)top16_of(n), L.adj16);
     // where the hit bitmask of every edge starts (edges whose head is not a
     // rank-window item get none)
     hipLaunchKernelGGL(k_tc_words, dim3(grid_for(g->m, 16384)), dim3(kThreads), 0, s, g->off, g->src, g->adj,
@@ -888,11 +947,13 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     (void)hipStreamWaitEvent(s1, c->fork, 0);
     (void)hipStreamWaitEvent(s2, c->fork, 0);
     // the two largest classes in two halves each
-    launch_window<14, 512, 8>(g, L, 8, chunk, t, s, 0, 2);
-    launch_window<14, 512, 8>(g, L, 8, chunk, t, s2, 1, 2);
-    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s1, 0, 2);
-    launch_window<16, 1024, 8>(g, L, 9, chunk, t, s, 1, 2);
-    launch_window<18, 1024, 8>(g, L, 10, chunk, t, s2);
+    launch_window<14, 512, 4, true>(g, L, 12, chunk, t, s, 0, 2);
+    launch_window<14, 512, 4, true>(g, L, 12, chunk, t, s2, 1, 2);
+    launch_window<16, 1024, 4, true>(g, L, 13, chunk, t, s1, 0, 2);
+    launch_window<16, 1024, 4, true>(g, L, 13, chunk, t, s, 1, 2);
+    launch_window<18, 1024, 4>(g, L, 10, chunk, t, s2);
+    launch_window<14, 512, 4>(g, L, 8, chunk, t, s1);
+    launch_window<16, 1024, 4>(g, L, 9, chunk, t, s);
     // the hash classes after the windows, placed so that the three streams
     // end together (at R-MAT scale 26 the side stream s1's window half ends
     // first and takes the two largest hash classes)

@@ -190,6 +190,48 @@ def test_triangle_paths_and_chunks(chunk, lds_max, packed, window, occ):
             M.mcd_ctx_set_param(c, k, val)
 
 
+@pytest.mark.parametrize("occ", [1, 0])
+def test_triangles_past_the_16_bit_rank_range(occ):
+    # with more than 65,536 vertices the rank-window items of the top 65,536
+    # ranks read their suffixes from the 16-bit copy of the adjacency and the
+    # others from the 32-bit one: both must give the oracle's counts
+    from gpu_util import ctx, build, canonical_order
+    s, d, n = gg.rmat(17, seed=5)
+    assert n > 65536
+    lo, hi = oracle.canon(n, s, d)
+    t_o = oracle.triangles(n, lo, hi)
+    c = ctx()
+    old = M.mcd_ctx_get_param(c, "tc_window_occupancy")
+    try:
+        M.mcd_ctx_set_param(c, "tc_window_occupancy", occ)
+        g = build(s, d, n)
+        _, _, order = canonical_order(g)
+        t = M.mcd_triangles(g).cpu().numpy()[order]
+        assert np.array_equal(t, t_o)
+    finally:
+        M.mcd_ctx_set_param(c, "tc_window_occupancy", old)
+
+
+def test_triangles_rank_windows_below_the_top_ranks():
+    # two dense random blocks, the lighter one ranked entirely below the top
+    # 65,536 ranks: its vertices are rank-window items read through the 32-bit
+    # adjacency (windows of 2^16 and 2^18 ranks), the heavier block's top part
+    # through the 16-bit copy
+    from gpu_util import build, canonical_order
+    rng = np.random.default_rng(1234)
+    na, nb = 40000, 70000
+    ea, eb = na * 300 // 2, nb * 400 // 2
+    s = np.concatenate([rng.integers(0, na, ea), na + rng.integers(0, nb, eb)]).astype(np.int32)
+    d = np.concatenate([rng.integers(0, na, ea), na + rng.integers(0, nb, eb)]).astype(np.int32)
+    n = na + nb
+    lo, hi = oracle.canon(n, s, d)
+    t_o = oracle.triangles(n, lo, hi)
+    g = build(s, d, n)
+    _, _, order = canonical_order(g)
+    t = M.mcd_triangles(g).cpu().numpy()[order]
+    assert np.array_equal(t, t_o)
+
+
 def test_triangles_at_odd_word_offset():
     # t need only be 4-byte aligned: an output array starting 4 bytes into
     # an 8-byte word gives the same counts and nothing outside it is written
