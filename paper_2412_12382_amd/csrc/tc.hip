@@ -442,16 +442,16 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
                 unsigned long long hb[E];
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
+                    // branch-free up to the count itself: lanes outside the
+                    // chunk or the window look up rank offset 0 and miss
                     const uint32_t r = (uint32_t)(w[q][k] - v - 1);
-                    bool hit = false;
-                    if (64 * k + lane < nv && r <= rmax) {
-                        const uint32_t word = bm[r >> 5];
-                        const uint32_t bit = 1u << (r & 31);
-                        if (word & bit) {
-                            hit = true;
-                            atomicAdd(&cnt[(uint32_t)pre[r >> 5] + __popc(word & (bit - 1u))], 1u);
-                        }
-                    }
+                    const bool inr = 64 * k + lane < nv && r <= rmax;
+                    const uint32_t rr = inr ? r : 0u;
+                    const uint32_t word = bm[rr >> 5];
+                    const uint32_t bit = 1u << (rr & 31);
+                    const bool hit = inr && (word & bit) != 0u;
+                    const uint32_t slot_j = (uint32_t)pre[rr >> 5] + __popc(word & (bit - 1u));
+                    if (hit) atomicAdd(&cnt[slot_j], 1u);
                     hb[k] = __ballot(hit);
                 }
                 // this chunk's words of the in-edge's hit bitmask, one per 64
@@ -947,24 +947,24 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     (void)hipStreamWaitEvent(s1, c->fork, 0);
     (void)hipStreamWaitEvent(s2, c->fork, 0);
     // the two largest classes in two halves each
+    // Classes in launch order per stream, placed so that the three streams
+    // end together (R-MAT scale 26: the 2^18 window class ends first, so its
+    // stream takes the largest hash class).
     launch_window<14, 512, 4, true>(g, L, 12, chunk, t, s, 0, 2);
     launch_window<14, 512, 4, true>(g, L, 12, chunk, t, s2, 1, 2);
     launch_window<16, 1024, 4, true>(g, L, 13, chunk, t, s1, 0, 2);
     launch_window<16, 1024, 4, true>(g, L, 13, chunk, t, s, 1, 2);
     launch_window<18, 1024, 4>(g, L, 10, chunk, t, s2);
     launch_window<14, 512, 4>(g, L, 8, chunk, t, s1);
-    launch_window<16, 1024, 4>(g, L, 9, chunk, t, s);
-    // the hash classes after the windows, placed so that the three streams
-    // end together (at R-MAT scale 26 the side stream s1's window half ends
-    // first and takes the two largest hash classes)
-    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s1);
-    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s1);
-    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s2);
+    launch_window<16, 1024, 4>(g, L, 9, chunk, t, s1);
+    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s2);
+    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s2);
+    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s);
+    launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
+    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s);
     launch_class<RowHash<13, true>, 4096, 4, 64>(g, L, 3, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
-    launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
-    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
     (void)hipEventRecord(c->join[0], s1);
