@@ -73,7 +73,11 @@ __device__ __forceinline__ bool keep_test(int64_t sn, int64_t sd, int64_t num, i
 //
 // Endpoints are streamed with t and dsum only where every edge needs them (a
 // graph lookup); the kept list and the queue read them for kept edges alone.
-template <int MEASURE, bool MULTI, bool NARROW, bool UNION>
+// THR: 0 one host threshold (num0 / den0, validated); 1 one device threshold
+// (deltas[0..1], read once per wave); 2 a device threshold per graph of a
+// batch (deltas[2 g .. 2 g + 1], the graph found from vbase).  Only THR 2
+// carries the endpoints and the graph lookup through the loop.
+template <int MEASURE, int THR, bool NARROW, bool UNION>
 __global__ __launch_bounds__(kThreads) void k_weigh_prune(
     const int32_t* __restrict__ src, const int32_t* __restrict__ adj, const int32_t* __restrict__ dsum,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ t, int64_t m, int64_t seg_len, int G,
@@ -87,15 +91,15 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
     const int64_t e0 = seg * seg_len;
     const int64_t e1 = e0 + seg_len < m ? e0 + seg_len : m;
     const uint64_t below = (1ull << lane) - 1ull;
-    const bool need_uv = MULTI && G > 1;
+    constexpr bool need_uv = THR == 2;
     // one threshold for every edge: read once (a device threshold of one
     // graph too), not per edge
     int64_t num1 = num0, den1 = den0;
-    if (MULTI && G == 1) {
+    if (THR == 1) {
         num1 = deltas[0];
         den1 = deltas[1];
     }
-    const bool narrow1 = !MULTI || small_delta(num1, den1);
+    const bool narrow1 = THR == 0 || small_delta(num1, den1);
     const int64_t ng = e1 > e0 ? (e1 - e0 + 63) >> 6 : 0;  // 64-edge groups of the run
     int64_t cnt = 0;
     for (int64_t gi = 0; gi < ng; gi += kUnroll) {
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_weigh_prune(
                     if (wi) __builtin_nontemporal_store((int32_t)sn, &wi[e]);
                     if (wf) __builtin_nontemporal_store((float)sn, &wf[e]);
                 }
-                if (MULTI && G > 1) {
+                if (THR == 2) {
                     const int g = graph_of(vbase, G, perm[u[j]]);
                     const int64_t num = deltas[2 * g], den = deltas[2 * g + 1];
                     k = small_delta(num, den) ? keep_test<NARROW>(sn, sd, num, den)
@@ -199,47 +203,51 @@ void launch_weigh_prune(const mcd_graph* g, int measure, const int32_t* t, int64
                         int32_t* kept_pairs, int32_t* kept_counts, int64_t* n_kept, hipStream_t s, int32_t* parent) {
     if (n_kept) fill_i64(n_kept, 1, 0, s);
     if (g->m <= 0 && !kept_counts) return;
-    const int64_t L = kept_segment_len(g->m);
-    const dim3 grid(MCD_KEPT_SEGMENTS / (kThreads / 64)), block(kThreads);
-    const bool multi = deltas != nullptr;
     // |TW| < 2^31 and deg u + deg v < 2^30 whenever every degree is below 2^29;
     // host thresholds are validated to |num|, den < 2^31
     const bool narrow = g->max_deg < (1 << 29);
+    const int64_t L = kept_segment_len(g->m);
+    const dim3 grid(MCD_KEPT_SEGMENTS / (kThreads / 64)), block(kThreads);
+    // 0: host threshold, 1: one device threshold, 2: per-graph device thresholds
+    const int thr = deltas == nullptr ? 0 : (G == 1 ? 1 : 2);
     int2* kp = (int2*)kept_pairs;
     unsigned long long* nk = (unsigned long long*)n_kept;
 #define MCD_WP_ARGS                                                                                          \
     g->src, g->adj, g->dsum, g->perm, t, g->m, L, G, vbase, deltas, num, den, wf, wi, keep_bits, kp, kept_counts, \
         nk, parent
-#define MCD_WP_LAUNCH_U(MEAS, MULTI, UNION)                                                                      \
+#define MCD_WP_LAUNCH_U(MEAS, THR, UNION)                                                                      \
     do {                                                                                                     \
-        if (narrow) hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, true, UNION>), grid, block, 0, s, MCD_WP_ARGS); \
-        else hipLaunchKernelGGL((k_weigh_prune<MEAS, MULTI, false, UNION>), grid, block, 0, s, MCD_WP_ARGS);      \
+        if (narrow) hipLaunchKernelGGL((k_weigh_prune<MEAS, THR, true, UNION>), grid, block, 0, s, MCD_WP_ARGS); \
+        else hipLaunchKernelGGL((k_weigh_prune<MEAS, THR, false, UNION>), grid, block, 0, s, MCD_WP_ARGS);      \
     } while (0)
-#define MCD_WP_LAUNCH(MEAS, MULTI)                            \
-    do {                                                  \
-        if (parent) MCD_WP_LAUNCH_U(MEAS, MULTI, true);   \
-        else MCD_WP_LAUNCH_U(MEAS, MULTI, false);         \
+#define MCD_WP_LAUNCH_T(MEAS, THR)                          \
+    do {                                                \
+        if (parent) MCD_WP_LAUNCH_U(MEAS, THR, true);   \
+        else MCD_WP_LAUNCH_U(MEAS, THR, false);         \
+    } while (0)
+#define MCD_WP_LAUNCH(MEAS)                                   \
+    do {                                                      \
+        if (thr == 0) MCD_WP_LAUNCH_T(MEAS, 0);               \
+        else if (thr == 1) MCD_WP_LAUNCH_T(MEAS, 1);          \
+        else MCD_WP_LAUNCH_T(MEAS, 2);                        \
     } while (0)
     switch (measure) {
         case MCD_SIM_TECTONIC:
-            if (multi) MCD_WP_LAUNCH(MCD_SIM_TECTONIC, true);
-            else MCD_WP_LAUNCH(MCD_SIM_TECTONIC, false);
+            MCD_WP_LAUNCH(MCD_SIM_TECTONIC);
             break;
         case MCD_SIM_TW:
-            if (multi) MCD_WP_LAUNCH(MCD_SIM_TW, true);
-            else MCD_WP_LAUNCH(MCD_SIM_TW, false);
+            MCD_WP_LAUNCH(MCD_SIM_TW);
             break;
         case MCD_SIM_K3:
         case MCD_SIM_K4:  // the count array passed as t
-            if (multi) MCD_WP_LAUNCH(MCD_SIM_K3, true);
-            else MCD_WP_LAUNCH(MCD_SIM_K3, false);
+            MCD_WP_LAUNCH(MCD_SIM_K3);
             break;
         default:
-            if (multi) MCD_WP_LAUNCH(MCD_SIM_JACCARD, true);
-            else MCD_WP_LAUNCH(MCD_SIM_JACCARD, false);
+            MCD_WP_LAUNCH(MCD_SIM_JACCARD);
             break;
     }
 #undef MCD_WP_LAUNCH
+#undef MCD_WP_LAUNCH_T
 #undef MCD_WP_LAUNCH_U
 #undef MCD_WP_ARGS
 }

@@ -232,6 +232,44 @@ def test_triangles_rank_windows_below_the_top_ranks():
     assert np.array_equal(t, t_o)
 
 
+@pytest.mark.parametrize("measure,delta", [(oracle.TECTONIC, (1, 20)), (oracle.TW, (-5, 1))])
+def test_prune_components_aligned_and_unaligned_inputs(measure, delta):
+    # the fused pass with a host and with a device threshold (separate
+    # kernel builds), on inputs and outputs at and off 16-byte boundaries,
+    # must give the oracle's results
+    from gpu_util import build, canonical_order, unpack_bits
+    s, d, n = gg.rmat(14, seed=31)
+    lo, hi = oracle.canon(n, s, d)
+    t_o = oracle.triangles(n, lo, hi)
+    deg = oracle.degrees(n, lo, hi)
+    keep_o = oracle.prune(measure, lo, hi, t_o, deg, *delta)
+    labels_o, ncc_o = oracle.components(n, lo, hi, keep_o)
+    g = build(s, d, n)
+    _, _, order = canonical_order(g)
+    t = M.mcd_triangles(g)
+    tw = measure == oracle.TW
+    dev_delta = torch.tensor([list(delta)], dtype=torch.int64, device="cuda")
+    for shift in (0, 1):
+        buf = torch.zeros(g.m + 4, dtype=torch.int32, device="cuda")
+        tt = buf[shift:shift + g.m]
+        tt.copy_(t)
+        wbuf = torch.zeros(g.m + 4, dtype=torch.int32 if tw else torch.float32, device="cuda")
+        wout = wbuf[shift:shift + g.m]
+        for kw in (dict(delta=delta), dict(deltas=dev_delta)):
+            r = M.mcd_prune_components(g, measure, tt, w_i32=wout if tw else None, w_f32=None if tw else wout,
+                                       want_f32=not tw, want_i32=tw, **kw)
+            keep = unpack_bits(r["keep_bits"], g.m)[order]
+            assert np.array_equal(keep, keep_o), (shift, kw)
+            assert int(r["n_kept"].item()) == int(keep_o.sum())
+            assert np.array_equal(r["labels"].cpu().numpy(), labels_o) and int(r["n_components"].item()) == ncc_o
+            w = wout.cpu().numpy()[order]
+            if tw:
+                assert np.array_equal(w.astype(np.int64), oracle.tw(lo, hi, t_o, deg))
+            else:
+                w_o = oracle.tectonic(lo, hi, t_o, deg)
+                assert np.array_equal(w.view(np.int32), w_o.astype(np.float32).view(np.int32))
+
+
 def test_triangles_at_odd_word_offset():
     # t need only be 4-byte aligned: an output array starting 4 bytes into
     # an 8-byte word gives the same counts and nothing outside it is written
