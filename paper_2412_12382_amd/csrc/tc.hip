@@ -442,6 +442,10 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
                 unsigned long long hb[E];
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
+                    // a part of the chunk past the suffix's end is skipped
+                    // (wave-uniform): short suffixes cost one probe, not E
+                    hb[k] = 0ull;
+                    if (64 * k >= nv) continue;
                     // branch-free up to the count itself: lanes outside the
                     // chunk or the window look up rank offset 0 and miss
                     const uint32_t r = (uint32_t)(w[q][k] - v - 1);
