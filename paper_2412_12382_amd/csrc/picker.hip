@@ -98,11 +98,33 @@ __global__ __launch_bounds__(kThreads) void k_feat_hist(const int32_t* __restric
     }
 }
 
-// max degree per graph; lanes sharing lane 0's graph reduce before one atomic
+// max degree per graph; lanes sharing lane 0's graph reduce before one atomic.
+// One graph: each thread keeps its maximum over the grid-stride loop and the
+// block reduces it, one atomic per block (one address would otherwise take an
+// atomic from every wave and iteration, serialised at the memory).
 __global__ __launch_bounds__(kThreads) void k_feat_maxdeg(const int32_t* __restrict__ deg,
                                                           const int32_t* __restrict__ perm, int64_t n,
                                                           const int64_t* __restrict__ vbase, int G,
                                                           unsigned long long* __restrict__ mdeg) {
+    if (G == 1) {
+        __shared__ unsigned long long wmax[kThreads / 64];
+        unsigned long long x = 0;
+        GRID_STRIDE(v, n) {
+            const unsigned long long d = (unsigned long long)deg[v];
+            x = d > x ? d : x;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long y = __shfl_xor(x, o);
+            x = y > x ? y : x;
+        }
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < kThreads / 64; ++i) x = wmax[i] > x ? wmax[i] : x;
+            if (x) atomicMax(&mdeg[0], x);
+        }
+        return;
+    }
     GRID_STRIDE(v, n) {
         const int g = G == 1 ? 0 : graph_of(vbase, G, perm[v]);
         const unsigned long long d = (unsigned long long)deg[v];

@@ -559,7 +559,8 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
                                                          const int64_t* __restrict__ in_off, int64_t n,
                                                          int64_t chunk, int64_t lds_max,
                                                          int64_t packed_range, int64_t window_max, int64_t top16,
-                                                         int32_t* __restrict__ cnt, uint8_t* __restrict__ wflag) {
+                                                         int8_t* __restrict__ vcls, int32_t* __restrict__ vcnt,
+                                                         uint8_t* __restrict__ wflag) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t B = off[v + 1] - off[v];
@@ -582,7 +583,8 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
         }
         const int64_t cs = item_size(chunk, B);
         const int32_t k = cls >= 0 ? (int32_t)((I + cs - 1) / cs) : 0;
-        for (int c = 0; c < kClasses; ++c) cnt[(int64_t)c * n + v] = (c == cls) ? k : 0;
+        vcls[v] = (int8_t)(k > 0 ? cls : -1);
+        vcnt[v] = k;
         wflag[v] = window_class(cls) ? 1 : 0;  // in-edges credited through hit bitmasks
     }
 }
@@ -786,42 +788,118 @@ __global__ __launch_bounds__(kThreads) void k_adj16(const int32_t* __restrict__ 
     }
 }
 
+// Work items grouped by class, each class's items in vertex order.  A block
+// of kVB vertices sums its items per class (k_class_blocks); a workgroup per
+// class scans those sums into every block's offset in that class's list
+// (k_class_offsets), one thread lays out the lists (k_class_heads); each block
+// then places its vertices' items (k_item_fill), one block-wide exclusive scan
+// per class.
+constexpr int kVB = 1024;               // vertices per block
+constexpr int kVPT = kVB / kThreads;    // per thread
+
+__global__ __launch_bounds__(kThreads) void k_class_blocks(const int8_t* __restrict__ vcls,
+                                                           const int32_t* __restrict__ vcnt, int64_t n,
+                                                           int64_t* __restrict__ bsum) {
+    __shared__ unsigned long long cs[kClasses];
+    const int tid = threadIdx.x;
+    if (tid < kClasses) cs[tid] = 0;
+    __syncthreads();
+    const int64_t v0 = (int64_t)blockIdx.x * kVB;
+    for (int i = 0; i < kVPT; ++i) {
+        const int64_t v = v0 + (int64_t)i * kThreads + tid;
+        if (v < n && vcls[v] >= 0) atomicAdd(&cs[vcls[v]], (unsigned long long)vcnt[v]);
+    }
+    __syncthreads();
+    if (tid < kClasses) bsum[(int64_t)blockIdx.x * kClasses + tid] = (int64_t)cs[tid];
+}
+
+// One workgroup per class c: bsum[b][c] becomes the offset of block b's
+// first item of class c within that class's list, ctot[c] the list's length.
+__global__ __launch_bounds__(1024) void k_class_offsets(int64_t* __restrict__ bsum, int64_t nb,
+                                                        int64_t* __restrict__ ctot) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x, c = blockIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = tid * per, b1 = min(nb, b0 + per);
+    int64_t sum = 0;
+    for (int64_t b = b0; b < b1; ++b) sum += bsum[b * kClasses + c];
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t x = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t x = bsum[b * kClasses + c];
+        bsum[b * kClasses + c] = run;
+        run += x;
+    }
+    if (tid == 1023) ctot[c] = part[1023];
+}
+
+// heads[2c], heads[2c+1]: start and length of class c's list (the lists are
+// laid out one after another).
+__global__ void k_class_heads(const int64_t* __restrict__ ctot, int64_t* __restrict__ heads) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t start = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        heads[2 * c] = start;
+        heads[2 * c + 1] = ctot[c];
+        start += ctot[c];
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_item_fill(const int64_t* __restrict__ off,
                                                         const int64_t* __restrict__ in_off, int64_t n,
-                                                        int64_t chunk, const int32_t* __restrict__ cnt,
-                                                        const int64_t* __restrict__ base,
+                                                        int64_t chunk, const int8_t* __restrict__ vcls,
+                                                        const int32_t* __restrict__ vcnt,
+                                                        const int64_t* __restrict__ bsum,
+                                                        const int64_t* __restrict__ heads,
                                                         Item* __restrict__ items) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        for (int c = 0; c < kClasses; ++c) {
-            const int32_t k = cnt[(int64_t)c * n + v];
-            if (!k) continue;
-            // class lists are laid out one after another: base of class c is
-            // the total of the earlier classes
-            int64_t b = base[(int64_t)c * (n + 1) + v];
-            for (int cc = 0; cc < c; ++cc) b += base[(int64_t)cc * (n + 1) + n];
+    __shared__ int64_t wpart[kThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t v0 = (int64_t)blockIdx.x * kVB;
+    // a thread's vertices are consecutive: v0 + tid * kVPT + i
+    int8_t cl[kVPT];
+    int32_t kk[kVPT];
+    for (int i = 0; i < kVPT; ++i) {
+        const int64_t v = v0 + (int64_t)tid * kVPT + i;
+        cl[i] = v < n ? vcls[v] : (int8_t)-1;
+        kk[i] = v < n ? vcnt[v] : 0;
+    }
+    for (int c = 0; c < kClasses; ++c) {
+        int64_t mine = 0;
+        for (int i = 0; i < kVPT; ++i) mine += cl[i] == c ? kk[i] : 0;
+        // block-wide exclusive prefix of mine
+        int64_t inc = mine;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wpart[w] = inc;
+        __syncthreads();
+        int64_t before = inc - mine;
+        for (int ww = 0; ww < w; ++ww) before += wpart[ww];
+        __syncthreads();
+        if (mine == 0) continue;
+        int64_t slot = heads[2 * c] + bsum[(int64_t)blockIdx.x * kClasses + c] + before;
+        for (int i = 0; i < kVPT; ++i) {
+            if (cl[i] != c) continue;
+            const int64_t v = v0 + (int64_t)tid * kVPT + i;
             const int64_t cs = item_size(chunk, off[v + 1] - off[v]);
             const int64_t i0 = in_off[v], i1 = in_off[v + 1];
-            for (int32_t j = 0; j < k; ++j) {
+            for (int32_t j = 0; j < kk[i]; ++j) {
                 Item I;
                 I.v = (int32_t)v;
                 I.s = i0 + (int64_t)j * cs;
                 I.len = (int32_t)min(cs, i1 - I.s);
-                items[b + j] = I;
+                items[slot + j] = I;
             }
+            slot += kk[i];
         }
-    }
-}
-
-// Offsets of the class lists and their lengths, on the device.
-__global__ void k_item_heads(const int64_t* __restrict__ base, int64_t n, int64_t* __restrict__ heads) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t acc = 0;
-    for (int c = 0; c < kClasses; ++c) {
-        const int64_t len = base[(int64_t)c * (n + 1) + n];
-        heads[2 * c] = acc;
-        heads[2 * c + 1] = len;
-        acc += len;
     }
 }
 
@@ -837,8 +915,10 @@ inline unsigned grid_for(int64_t N, int64_t cap) {
 }
 
 struct TcLayout {
-    int32_t* cnt;    // [kClasses][n]
-    int64_t* base;   // [kClasses][n+1]
+    int8_t* vcls;    // [n] class of each vertex's items (-1: none)
+    int32_t* vcnt;   // [n] items of each vertex
+    int64_t* bsum;   // [ceil(n / kVB)][kClasses] block sums, then block offsets within each class
+    int64_t* ctot;   // [kClasses] items per class
     Item* items;     // [max items]
     int64_t* heads;  // [2*kClasses]: start, length per class
     uint8_t* wflag;  // [n] head of rank-window items
@@ -858,8 +938,10 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
     TcLayout L;
     const int64_t n = g->n, m = g->m;
     const int64_t max_items = n + m / item_size(chunk, 0) + 1;  // items hold >= item_size(chunk, 0) in-edges
-    L.cnt = c.take<int32_t>((size_t)kClasses * n);
-    L.base = c.take<int64_t>((size_t)kClasses * (n + 1));
+    L.vcls = c.take<int8_t>((size_t)n);
+    L.vcnt = c.take<int32_t>((size_t)n);
+    L.bsum = c.take<int64_t>((size_t)kClasses * (size_t)((n + kVB - 1) / kVB));
+    L.ctot = c.take<int64_t>((size_t)kClasses);
     L.items = c.take<Item>((size_t)max_items);
     L.heads = c.take<int64_t>(2 * kClasses);
     L.wflag = c.take<uint8_t>((size_t)n);
@@ -928,7 +1010,7 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     TcLayout L = tc_layout(ws, g, chunk);
     const int64_t n = g->n;
     hipLaunchKernelGGL(k_item_count, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->adj, g->in_off,
-                       n, chunk, lds_max, packed_range, window_max, top16_of(n), L.cnt, L.wflag);
+                       n, chunk, lds_max, packed_range, window_max, top16_of(n), L.vcls, L.vcnt, L.wflag);
     hipLaunchKernelGGL(k_adj16, dim3(grid_for(g->m, 16384)), dim3(kThreads), 0, s, g->adj, g->m,
                        (int32_t)top16_of(n), L.adj16);
     // where the hit bitmask of every edge starts (edges whose head is not a
@@ -936,11 +1018,14 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     hipLaunchKernelGGL(k_tc_words, dim3(grid_for(g->m, 16384)), dim3(kThreads), 0, s, g->off, g->src, g->adj,
                        L.wflag, g->m, L.words);
     exclusive_scan_i32_i64(L.words, g->m, L.wbase, L.scan, s);
-    for (int c = 0; c < kClasses; ++c)
-        exclusive_scan_i32_i64(L.cnt + (int64_t)c * n, n, L.base + (int64_t)c * (n + 1), L.scan, s);
-    hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 8192)), dim3(kThreads), 0, s, g->off, g->in_off, n,
-                       chunk, L.cnt, L.base, L.items);
-    hipLaunchKernelGGL(k_item_heads, dim3(1), dim3(64), 0, s, L.base, n, L.heads);
+    {
+        const int64_t nb = (n + kVB - 1) / kVB;
+        hipLaunchKernelGGL(k_class_blocks, dim3((unsigned)nb), dim3(kThreads), 0, s, L.vcls, L.vcnt, n, L.bsum);
+        hipLaunchKernelGGL(k_class_offsets, dim3(kClasses), dim3(1024), 0, s, L.bsum, nb, L.ctot);
+        hipLaunchKernelGGL(k_class_heads, dim3(1), dim3(64), 0, s, L.ctot, L.heads);
+        hipLaunchKernelGGL(k_item_fill, dim3((unsigned)nb), dim3(kThreads), 0, s, g->off, g->in_off, n, chunk,
+                           L.vcls, L.vcnt, L.bsum, L.heads, L.items);
+    }
     // The classes run on three streams at once (the context's and its two
     // side streams, forked here and joined at the end): each kernel's tail of
     // long items then overlaps the others' work.  The counts are integer
