@@ -325,21 +325,25 @@ struct ChunkGen {
 };
 
 // Element 64 k + lane of the generator's current chunk (lanes past its end
-// repeat its last element).  Issued unconditionally, from a valid address
-// when the generator is done too (the kernel runs only on graphs with edges),
-// so that every slot of the ring below issues the same loads and the wait
-// for a slot's data counts the loads issued after it.  T16: from the 16-bit
-// copy of the adjacency (adj16[e] = adj[e] - top16 for the top 65,536 ranks),
-// for items whose suffixes lie entirely in that range.
-template <bool T16, int E>
-__device__ __forceinline__ int32_t load_elem(const int32_t* __restrict__ adj, const uint16_t* __restrict__ adj16,
-                                             int32_t top16, const ChunkGen<E>& g, int lane, int k) {
-    const int32_t nv = g.done ? 1 : g.a1 - g.pos;
-    const int32_t i = 64 * k + lane;
-    const uint32_t j = (uint32_t)(i < nv ? i : nv - 1);
-    const int64_t p = g.done ? 0 : g.pos;
-    if (T16) return (int32_t)adj16[p + j] + top16;
-    return adj[p + j];
+// repeat its last element), loaded from the chunk's first element `base` at
+// byte offset min(ob, last) where ob = (64 k + lane) * sizeof(element) and
+// last is the byte offset of the chunk's last element; a finished generator
+// reads element 0 of the adjacency (the kernel runs only on graphs with
+// edges), so that every slot of the ring below issues the same loads and the
+// wait for a slot's data counts the loads issued after it.  T16: from the
+// 16-bit copy of the adjacency (adj16[e] = adj[e] - top16 for the top 65,536
+// ranks), for items whose suffixes lie entirely in that range.
+// v_writelane_b32: `old` with lane `lane` replaced by the wave-uniform `val`
+// (the compiler's intrinsic; clang has no builtin name for it).
+__device__ int32_t writelane(int32_t val, int32_t lane, int32_t old) __asm("llvm.amdgcn.writelane.i32");
+
+template <bool T16>
+__device__ __forceinline__ int32_t load_elem(const void* __restrict__ base, uint32_t last, uint32_t ob,
+                                             int32_t top16) {
+    const uint32_t o = ob < last ? ob : last;
+    const char* __restrict__ p = (const char*)base + o;
+    if (T16) return (int32_t)*(const uint16_t*)p + top16;
+    return *(const int32_t*)p;
 }
 
 // Rank-window items, one item per workgroup of NT threads.  Each wave walks
@@ -367,8 +371,20 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
     constexpr int NW = (1 << LOG2R) / 32;
     constexpr int MAXB = 4096;
     constexpr int NWAVES = NT / 64;
-    __shared__ uint32_t bm[NW];
-    __shared__ uint16_t pre[NW];
+    // Bitmap words and their exclusive popcount prefixes.  Up to 2^16 ranks
+    // a word and its prefix sit side by side (one 8-byte LDS read per probe);
+    // the 2^18 window keeps 16-bit prefixes apart, so that two workgroups
+    // still fit a CU's LDS.  Word NW stays zero: lanes with nothing to probe
+    // look up rank offset 32 NW and miss.
+    constexpr bool PAIR = LOG2R <= 16;
+    constexpr uint32_t ZR = 32u * NW;
+    __shared__ uint2 bp[PAIR ? NW + 1 : 1];
+    __shared__ uint32_t bw[PAIR ? 1 : NW + 1];
+    __shared__ uint16_t bpre[PAIR ? 1 : NW];
+    auto word_at = [&](int i) -> uint32_t& {
+        if constexpr (PAIR) return bp[i].x;
+        else return bw[i];
+    };
     __shared__ uint32_t part[NWAVES];
     __shared__ uint32_t cnt[MAXB];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -382,12 +398,12 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
         const int32_t v = I.v;
         const int32_t b0 = (int32_t)off[v];
         const int32_t B = (int32_t)(off[v + 1] - b0);
-        for (int i = tid; i < NW; i += NT) bm[i] = 0;
+        for (int i = tid; i <= NW; i += NT) word_at(i) = 0;
         for (int i = tid; i < B; i += NT) cnt[i] = 0;
         __syncthreads();
         for (int j = tid; j < B; j += NT) {
             const uint32_t r = (uint32_t)(adj[b0 + j] - v - 1);
-            atomicOr(&bm[r >> 5], 1u << (r & 31));
+            atomicOr(&word_at(r >> 5), 1u << (r & 31));
         }
         const int32_t maxv = adj[b0 + B - 1];
         __syncthreads();
@@ -396,7 +412,7 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
             const int per = (nw + NT - 1) / NT;
             const int w0 = tid * per, w1 = min(nw, w0 + per);
             uint32_t sum = 0;
-            for (int i = w0; i < w1; ++i) sum += __popc(bm[i]);
+            for (int i = w0; i < w1; ++i) sum += __popc(word_at(i));
             uint32_t x = sum;
             for (int o = 1; o < 64; o <<= 1) {
                 const uint32_t y = __shfl_up(x, o);
@@ -407,8 +423,9 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
             uint32_t run = x - sum;
             for (int k = 0; k < wave; ++k) run += part[k];
             for (int i = w0; i < w1; ++i) {
-                pre[i] = (uint16_t)run;
-                run += __popc(bm[i]);
+                if constexpr (PAIR) bp[i].y = run;
+                else bpre[i] = (uint16_t)run;
+                run += __popc(word_at(i));
             }
         }
         __syncthreads();
@@ -417,19 +434,28 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
         ChunkGen<E> gen{in_ea + I.s + wave, wbase, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES,
                         0, -64, 0, 64, 0, 0, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
         gen.next(lane);
+        constexpr uint32_t SZ = T16 ? 2u : 4u;  // bytes per loaded element
+        uint32_t ob[E];                          // byte offset of this lane's element k in a chunk
+#pragma unroll
+        for (int k = 0; k < E; ++k) ob[k] = (uint32_t)(64 * k + lane) * SZ;
         int32_t w[D][E], spos[D], sa1[D];
         int64_t sw[D];
         bool sv[D];
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
+        // the ring's refill of slot q from the generator's current chunk
+        auto refill = [&](int q) {
             sv[q] = !gen.done;
             spos[q] = gen.pos;
             sa1[q] = gen.a1;
             sw[q] = gen.word();
+            const int64_t p = gen.done ? 0 : gen.pos;
+            const uint32_t last = gen.done ? 0u : (uint32_t)(gen.a1 - gen.pos - 1) * SZ;
+            const void* base = T16 ? (const void*)(adj16 + p) : (const void*)(adj + p);
 #pragma unroll
-            for (int k = 0; k < E; ++k) w[q][k] = load_elem<T16>(adj, adj16, top16, gen, lane, k);
+            for (int k = 0; k < E; ++k) w[q][k] = load_elem<T16>(base, last, ob[k], top16);
             if (sv[q]) gen.next(lane);
-        }
+        };
+#pragma unroll
+        for (int q = 0; q < D; ++q) refill(q);
         bool more = sv[0];
         while (more) {
 #pragma unroll
@@ -439,44 +465,47 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
                     break;
                 }
                 const int32_t pos = spos[q], nv = sa1[q] - pos;
-                unsigned long long hb[E];
+                const uint32_t lastb = (uint32_t)(nv - 1) * SZ;
+                // lane k of (xlo, xhi) collects the hit ballot of the chunk's
+                // k-th 64 elements
+                uint32_t xlo = 0u, xhi = 0u;
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     // a part of the chunk past the suffix's end is skipped
                     // (wave-uniform): short suffixes cost one probe, not E
-                    hb[k] = 0ull;
-                    if (64 * k >= nv) continue;
+                    if (64 * k >= nv) break;
                     // branch-free up to the count itself: lanes outside the
-                    // chunk or the window look up rank offset 0 and miss
+                    // chunk or the window look up the zero word and miss
                     const uint32_t r = (uint32_t)(w[q][k] - v - 1);
-                    const bool inr = 64 * k + lane < nv && r <= rmax;
-                    const uint32_t rr = inr ? r : 0u;
-                    const uint32_t word = bm[rr >> 5];
-                    const uint32_t bit = 1u << (rr & 31);
-                    const bool hit = inr && (word & bit) != 0u;
-                    const uint32_t slot_j = (uint32_t)pre[rr >> 5] + __popc(word & (bit - 1u));
-                    if (hit) atomicAdd(&cnt[slot_j], 1u);
-                    hb[k] = __ballot(hit);
+                    const uint32_t rr = ob[k] <= lastb && r <= rmax ? r : ZR;
+                    uint32_t word, pw;
+                    if constexpr (PAIR) {
+                        const uint2 e2 = bp[rr >> 5];
+                        word = e2.x;
+                        pw = e2.y;
+                    } else {
+                        word = bw[rr >> 5];
+                        pw = 0u;
+                    }
+                    // (the bit-field extract takes its offset and width mod 32)
+                    const bool hit = __builtin_amdgcn_ubfe(word, rr, 1u) != 0u;
+                    const unsigned long long hb = __ballot(hit);
+                    xlo = (uint32_t)writelane((int32_t)(uint32_t)hb, k, (int32_t)xlo);
+                    xhi = (uint32_t)writelane((int32_t)(uint32_t)(hb >> 32), k, (int32_t)xhi);
+                    if (hit) {
+                        if constexpr (!PAIR) pw = bpre[rr >> 5];
+                        // position of w in N+(v): the set bits below it
+                        atomicAdd(&cnt[pw + __popc(__builtin_amdgcn_ubfe(word, 0u, rr))], 1u);
+                    }
                 }
                 // this chunk's words of the in-edge's hit bitmask, one per 64
                 // elements (lane k stores word k): every word of a window
                 // in-edge is written, once
                 const int nwords = (min(nv, 64 * E) + 63) >> 6;
-                if (lane < nwords) {
-                    unsigned long long x = hb[0];
-#pragma unroll
-                    for (int k = 1; k < E; ++k)
-                        if (lane == k) x = hb[k];
-                    __builtin_nontemporal_store(x, &bits[sw[q] + lane]);
-                }
+                if (lane < nwords)
+                    __builtin_nontemporal_store(((unsigned long long)xhi << 32) | xlo, &bits[sw[q] + lane]);
                 // refill the slot with the chunk D ahead
-                sv[q] = !gen.done;
-                spos[q] = gen.pos;
-                sa1[q] = gen.a1;
-                sw[q] = gen.word();
-#pragma unroll
-                for (int k = 0; k < E; ++k) w[q][k] = load_elem<T16>(adj, adj16, top16, gen, lane, k);
-                if (sv[q]) gen.next(lane);
+                refill(q);
             }
         }
         __syncthreads();
@@ -1048,9 +1077,9 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     launch_window<16, 1024, 4>(g, L, 9, chunk, t, s1);
     launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s2);
     launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s2);
-    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s);
+    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s2);
+    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s1);
     launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
-    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s);
     launch_class<RowHash<13, true>, 4096, 4, 64>(g, L, 3, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
