@@ -308,6 +308,11 @@ struct ChunkGen {
                 bw = lane < left ? wbase[d.x] : 0;
                 dp += 64 * stride;
                 bi = 0;
+                // wait for the batch here (vmcnt(0)), once per 64 in-edges:
+                // the lane reads below then carry no wait, and the chunk
+                // loads in flight in the ring are not drained at every
+                // in-edge
+                __builtin_amdgcn_s_waitcnt(0x0F70);
             }
             e = __builtin_amdgcn_readlane(bx, bi);
             const int32_t len = __builtin_amdgcn_readlane(by, bi);
@@ -324,6 +329,10 @@ struct ChunkGen {
     __device__ __forceinline__ int64_t word() const { return wb + ((pos - e - 1) >> 6); }
 };
 
+// v_writelane_b32: `old` with lane `lane` replaced by the wave-uniform `val`
+// (the compiler's intrinsic; clang has no builtin name for it).
+__device__ int32_t writelane(int32_t val, int32_t lane, int32_t old) __asm("llvm.amdgcn.writelane.i32");
+
 // Element 64 k + lane of the generator's current chunk (lanes past its end
 // repeat its last element), loaded from the chunk's first element `base` at
 // byte offset min(ob, last) where ob = (64 k + lane) * sizeof(element) and
@@ -332,17 +341,14 @@ struct ChunkGen {
 // edges), so that every slot of the ring below issues the same loads and the
 // wait for a slot's data counts the loads issued after it.  T16: from the
 // 16-bit copy of the adjacency (adj16[e] = adj[e] - top16 for the top 65,536
-// ranks), for items whose suffixes lie entirely in that range.
-// v_writelane_b32: `old` with lane `lane` replaced by the wave-uniform `val`
-// (the compiler's intrinsic; clang has no builtin name for it).
-__device__ int32_t writelane(int32_t val, int32_t lane, int32_t old) __asm("llvm.amdgcn.writelane.i32");
-
+// ranks), for items whose suffixes lie entirely in that range; the element is
+// returned as stored (the caller adds top16), so that no instruction uses a
+// load before the probe that needs it.
 template <bool T16>
-__device__ __forceinline__ int32_t load_elem(const void* __restrict__ base, uint32_t last, uint32_t ob,
-                                             int32_t top16) {
+__device__ __forceinline__ int32_t load_elem(const void* __restrict__ base, uint32_t last, uint32_t ob) {
     const uint32_t o = ob < last ? ob : last;
     const char* __restrict__ p = (const char*)base + o;
-    if (T16) return (int32_t)*(const uint16_t*)p + top16;
+    if (T16) return (int32_t)*(const uint16_t*)p;
     return *(const int32_t*)p;
 }
 
@@ -431,6 +437,7 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
         __syncthreads();
 
         const uint32_t rmax = (uint32_t)(maxv - v - 1);  // ranks v+1 .. maxv are in the window
+        const int32_t roff = (T16 ? top16 : 0) - v - 1;    // loaded element + roff = rank offset
         ChunkGen<E> gen{in_ea + I.s + wave, wbase, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES,
                         0, -64, 0, 64, 0, 0, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
         gen.next(lane);
@@ -451,7 +458,7 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
             const uint32_t last = gen.done ? 0u : (uint32_t)(gen.a1 - gen.pos - 1) * SZ;
             const void* base = T16 ? (const void*)(adj16 + p) : (const void*)(adj + p);
 #pragma unroll
-            for (int k = 0; k < E; ++k) w[q][k] = load_elem<T16>(base, last, ob[k], top16);
+            for (int k = 0; k < E; ++k) w[q][k] = load_elem<T16>(base, last, ob[k]);
             if (sv[q]) gen.next(lane);
         };
 #pragma unroll
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
                     if (64 * k >= nv) break;
                     // branch-free up to the count itself: lanes outside the
                     // chunk or the window look up the zero word and miss
-                    const uint32_t r = (uint32_t)(w[q][k] - v - 1);
+                    const uint32_t r = (uint32_t)(w[q][k] + roff);
                     const uint32_t rr = ob[k] <= lastb && r <= rmax ? r : ZR;
                     uint32_t word, pw;
                     if constexpr (PAIR) {
