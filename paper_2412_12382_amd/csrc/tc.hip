@@ -342,8 +342,11 @@ __device__ int32_t writelane(int32_t val, int32_t lane, int32_t old) __asm("llvm
 // wait for a slot's data counts the loads issued after it.  T16: from the
 // 16-bit copy of the adjacency (adj16[e] = adj[e] - top16 for the top 65,536
 // ranks), for items whose suffixes lie entirely in that range; the element is
-// returned as stored (the caller adds top16), so that no instruction uses a
-// load before the probe that needs it.
+// returned as stored and the probe adds top16 with the rank offset.  (The
+// compiler zero-extends the 16-bit ring at the top of the ring's loop, which
+// waits there for the loads of all D slots: a wait per D chunks.  Variants
+// without that wait read 4 bytes from a 2-byte boundary, or 32-bit elements,
+// and were slower.)
 template <bool T16>
 __device__ __forceinline__ int32_t load_elem(const void* __restrict__ base, uint32_t last, uint32_t ob) {
     const uint32_t o = ob < last ? ob : last;
