@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
                                                        const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ adj,
                                                        const int2* __restrict__ in_ea,
-                                                       int32_t* __restrict__ t) {
+                                                       int32_t* __restrict__ t, int ipart, int nparts) {
     constexpr int NI = 4 / WPI;
     constexpr int GPW = 64 / G;
     constexpr int NGI = WPI * GPW;  // groups per item
@@ -195,7 +195,9 @@ __global__ __launch_bounds__(kThreads) void k_tc_items(const Item* __restrict__ 
     const int64_t n_items = heads[2 * cls + 1];
     Table& H = hash[slot];
 
-    for (int64_t base = (int64_t)blockIdx.x * NI; base < n_items; base += (int64_t)gridDim.x * NI) {
+    // this launch takes the groups of NI items g = ipart (mod nparts)
+    for (int64_t base = ((int64_t)blockIdx.x * nparts + ipart) * NI; base < n_items;
+         base += (int64_t)gridDim.x * nparts * NI) {
         const int64_t it = base + slot;
         const bool have = it < n_items;
         int64_t s = 0, b0 = 0;
@@ -998,14 +1000,15 @@ TcLayout tc_layout(void* p, const mcd_graph* g, int64_t chunk) {
 }
 
 template <class Table, int MAXB, int WPI, int G>
-void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s) {
+void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
+                  int ipart = 0, int nparts = 1) {
     constexpr int NI = 4 / WPI;
     // grid-stride over the class list; its length is read on the device
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = (cap_items + NI - 1) / NI;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL((k_tc_items<Table, MAXB, WPI, G>), dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                       L.items, L.heads, c, g->off, g->adj, g->in_ea, t);
+                       L.items, L.heads, c, g->off, g->adj, g->in_ea, t, ipart, nparts);
 }
 
 // ipart / nparts: this launch takes every nparts-th item of the class.
@@ -1014,12 +1017,14 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
 // the compiler's own budget of 106 scalar registers, which allows 7: with
 // 16-wave workgroups that is the difference between one and two resident
 // workgroups per CU (R-MAT scale 26: 625 -> 513 ms for the whole count).
-// Elements per lane of a rank-window chunk: 4, so that a wave's scalar walk
-// (in-edge, chunk, ring slot) is paid once per 256 suffix elements; with 4
-// ring slots a wave still has 16 loads in flight.  (R-MAT scale 26, whole
-// count: 1 element per lane 507 ms, 2 424 ms, 3 406 ms, 4 403 ms; ring depth
-// 2, 4 or 8 within 2 %.)
-constexpr int kWindowE = 4;
+// Elements per lane of a rank-window chunk: 8, so that a wave's walk
+// (in-edge, chunk, ring slot: scalar work, lane reads, the hit word store) is
+// paid once per 512 suffix elements, while a chunk's probes past its
+// suffix's end are skipped; 3 ring slots keep 24 loads of a wave in flight
+// within 64 registers (8 waves per SIMD).  (R-MAT scale 26, whole count: 4
+// elements per lane with 4 slots 363 ms, 5 354, 6 347, 8 with 3 slots 345,
+// 8 with 2 slots 352; 10 or 12 elements spill and take 1.2 s.)
+constexpr int kWindowE = 8;
 
 template <int LOG2R, int NT, int D, bool T16 = false>
 void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
@@ -1074,25 +1079,27 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     (void)hipEventRecord(c->fork, s);
     (void)hipStreamWaitEvent(s1, c->fork, 0);
     (void)hipStreamWaitEvent(s2, c->fork, 0);
-    // the two largest classes in two halves each
     // Classes in launch order per stream, placed so that the three streams
-    // end together (R-MAT scale 26: the 2^18 window class ends first, so its
-    // stream takes the largest hash class).
-    launch_window<14, 512, 4, true>(g, L, 12, chunk, t, s, 0, 2);
-    launch_window<14, 512, 4, true>(g, L, 12, chunk, t, s2, 1, 2);
-    launch_window<16, 1024, 4, true>(g, L, 13, chunk, t, s1, 0, 2);
-    launch_window<16, 1024, 4, true>(g, L, 13, chunk, t, s, 1, 2);
-    launch_window<18, 1024, 4>(g, L, 10, chunk, t, s2);
-    launch_window<14, 512, 4>(g, L, 8, chunk, t, s1);
-    launch_window<16, 1024, 4>(g, L, 9, chunk, t, s1);
-    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s2);
-    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s2);
-    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s2);
+    // end together (R-MAT scale 26, kernel times with three streams busy:
+    // stream 0 about 66 + 106 + 9 + 11 + 37 ms, stream 1 170 + 11 + 12 + 24 + 3,
+    // stream 2 68 + 134 + 37); the two largest window classes and the
+    // largest hash class run as two halves of their item lists.
+    launch_window<14, 512, 3, true>(g, L, 12, chunk, t, s, 0, 2);
+    launch_window<14, 512, 3, true>(g, L, 12, chunk, t, s2, 1, 2);
+    launch_window<16, 1024, 3, true>(g, L, 13, chunk, t, s1, 0, 2);
+    launch_window<16, 1024, 3, true>(g, L, 13, chunk, t, s, 1, 2);
+    launch_window<18, 1024, 3>(g, L, 10, chunk, t, s2);
+    launch_window<14, 512, 3>(g, L, 8, chunk, t, s1);
+    launch_window<16, 1024, 3>(g, L, 9, chunk, t, s1);
     launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s1);
+    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s1);
+    launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s1);
+    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s2, 1, 2);
     launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
     launch_class<RowHash<13, true>, 4096, 4, 64>(g, L, 3, chunk, t, s);
     launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
     launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
+    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s, 0, 2);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
     (void)hipEventRecord(c->join[0], s1);
