@@ -114,56 +114,6 @@ struct RowHash<LOG2S, false> {
     }
 };
 
-// Rank window of N+(v) in LDS, for rows whose ranks all lie in (v, v + 2^LOG2R]:
-// bit r of the bitmap marks rank v + 1 + r, and pre[k] counts the set bits
-// before word k, so a lookup is two independent LDS reads (word and prefix)
-// and a popcount, with no probe loop.  The prefix pass needs the whole
-// workgroup (one item per workgroup).
-template <int LOG2R>
-struct RowWindow {
-    static constexpr int NW = (1 << LOG2R) / 32;
-    uint32_t bm[NW];
-    uint16_t pre[NW];
-    uint32_t part[4];
-    __device__ __forceinline__ void clear(int tid, int nt) {
-        for (int i = tid; i < NW; i += nt) bm[i] = 0;
-    }
-    __device__ __forceinline__ void insert(int32_t w, int32_t v, int) {
-        const uint32_t r = (uint32_t)(w - v - 1);
-        atomicOr(&bm[r >> 5], 1u << (r & 31));
-    }
-    // exclusive prefix of popcounts over the words that can hold ranks <= v + R
-    __device__ __forceinline__ void prepare(int tid, int nt, int32_t R) {
-        const int nw = (R + 31) >> 5;
-        const int per = (nw + nt - 1) / nt;
-        const int w0 = tid * per, w1 = min(nw, w0 + per);
-        uint32_t s = 0;
-        for (int i = w0; i < w1; ++i) s += __popc(bm[i]);
-        uint32_t x = s;  // inclusive wave scan
-        const int lane = tid & 63;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) part[tid >> 6] = x;
-        __syncthreads();
-        uint32_t run = x - s;
-        for (int k = 0; k < (tid >> 6); ++k) run += part[k];
-        for (int i = w0; i < w1; ++i) {
-            pre[i] = (uint16_t)run;
-            run += __popc(bm[i]);
-        }
-    }
-    __device__ __forceinline__ int find(int32_t w, int32_t v) const {
-        const uint32_t r = (uint32_t)(w - v - 1);
-        const uint32_t word = bm[r >> 5];
-        const uint32_t p0 = pre[r >> 5];
-        const uint32_t bit = 1u << (r & 31);
-        if (!(word & bit)) return -1;
-        return (int)(p0 + __popc(word & (bit - 1u)));
-    }
-};
-
 // One item per WPI waves; 4/WPI items per workgroup.  LOG2S: log2 of hash
 // slots (rows up to 2^(LOG2S-1) out-neighbours).  Each wave is split into
 // 64/G groups of G lanes; a group walks its own in-edges (static stride inside
@@ -357,60 +307,43 @@ __device__ __forceinline__ int32_t load_elem(const void* __restrict__ base, uint
     return *(const int32_t*)p;
 }
 
-// Rank-window items, one item per workgroup of NT threads.  Each wave walks
-// its own in-edges of the item, one at a time, all 64 lanes on chunks of
-// 64 E elements of the in-edge's suffix.  The walk (in-edge, chunk, loop
-// control) is wave-uniform, so it runs on the scalar unit and the vector work
-// per element is the probe alone; the scalar unit is shared by the CU's
-// waves, so a chunk of several elements per lane spreads its cost.  Loads
-// run D chunks ahead of their use in a ring of registers.  t(v,w) partial
-// counts are 32-bit LDS counters, one per element of N+(v).  The hit ballot
-// of every 64 elements is stored as a word of the in-edge's bitmask (bits, at
-// wbase[e] + suffix offset / 64), for the credit passes.
-// Wide windows take large workgroups so that the LDS they need still leaves
-// room for enough waves per CU.
-template <int LOG2R, int NT, int D, int MINW, bool T16, int E>
-__global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict__ all_items,
-                                                    const int64_t* __restrict__ heads, int cls,
-                                                    const int64_t* __restrict__ off,
-                                                    const int32_t* __restrict__ adj,
-                                                    const uint16_t* __restrict__ adj16, int32_t top16,
-                                                    const int2* __restrict__ in_ea,
-                                                    const int64_t* __restrict__ wbase,
-                                                    unsigned long long* __restrict__ bits,
-                                                    int32_t* __restrict__ t, int ipart, int nparts) {
-    constexpr int NW = (1 << LOG2R) / 32;
-    constexpr int MAXB = 4096;
-    constexpr int NWAVES = NT / 64;
-    // Bitmap words and their exclusive popcount prefixes.  Up to 2^16 ranks
-    // a word and its prefix sit side by side (one 8-byte LDS read per probe);
-    // the 2^18 window keeps 16-bit prefixes apart, so that two workgroups
-    // still fit a CU's LDS.  Word NW stays zero: lanes with nothing to probe
-    // look up rank offset 32 NW and miss.
-    constexpr bool PAIR = LOG2R <= 16;
-    constexpr uint32_t ZR = 32u * NW;
-    __shared__ uint2 bp[PAIR ? NW + 1 : 1];
-    __shared__ uint32_t bw[PAIR ? 1 : NW + 1];
-    __shared__ uint16_t bpre[PAIR ? 1 : NW];
-    auto word_at = [&](int i) -> uint32_t& {
+// Rows of N+(v) for the walking kernel below, held in LDS by the workgroup.
+// build() enters them (the whole workgroup, ending with a barrier) and
+// returns the per-item constants the probes need; probe() tells whether a
+// suffix element is in the row, position() where (called for hits only).
+//
+// Rank window, for rows whose ranks all lie in (v, v + 2^LOG2R]: bit r of the
+// bitmap marks rank v + 1 + r, beside each 32-bit word the number of set bits
+// before it.  Up to 2^16 ranks a word and its prefix sit side by side (one
+// address for both); the 2^18 window keeps 16-bit prefixes apart, so that two
+// workgroups still fit a CU's LDS.  Word NW stays zero: lanes with nothing to
+// probe look up rank offset 32 NW and miss.  T16: suffix elements come from
+// the 16-bit copy of the adjacency (element + top16 is the rank).
+template <int LOG2R, bool T16_>
+struct WindowRow {
+    static constexpr bool T16 = T16_;
+    static constexpr int NW = (1 << LOG2R) / 32;
+    static constexpr bool PAIR = LOG2R <= 16;
+    static constexpr uint32_t ZR = 32u * NW;
+    uint2 bp[PAIR ? NW + 1 : 1];
+    uint32_t bw[PAIR ? 1 : NW + 1];
+    uint16_t bpre[PAIR ? 1 : NW];
+    uint32_t part[16];
+    struct Key {
+        int32_t roff;   // loaded element + roff = rank offset r
+        uint32_t rmax;  // ranks v+1 .. v+1+rmax are in the window
+    };
+    struct Hit {
+        uint32_t word, rr;
+    };
+    __device__ __forceinline__ uint32_t& word_at(int i) {
         if constexpr (PAIR) return bp[i].x;
         else return bw[i];
-    };
-    __shared__ uint32_t part[NWAVES];
-    __shared__ uint32_t cnt[MAXB];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const Item* __restrict__ items = all_items + heads[2 * cls];
-    const int64_t n_items = heads[2 * cls + 1];
-
-    // this launch takes the items it = ipart (mod nparts) of the class
-    for (int64_t it = (int64_t)blockIdx.x * nparts + ipart; it < n_items; it += (int64_t)gridDim.x * nparts) {
-        const Item I = items[it];
-        const int32_t v = I.v;
-        const int32_t b0 = (int32_t)off[v];
-        const int32_t B = (int32_t)(off[v + 1] - b0);
+    }
+    template <int NT>
+    __device__ __forceinline__ Key build(const int32_t* __restrict__ adj, int32_t b0, int32_t B, int32_t v,
+                                         int32_t top16, int tid, int lane, int wave) {
         for (int i = tid; i <= NW; i += NT) word_at(i) = 0;
-        for (int i = tid; i < B; i += NT) cnt[i] = 0;
         __syncthreads();
         for (int j = tid; j < B; j += NT) {
             const uint32_t r = (uint32_t)(adj[b0 + j] - v - 1);
@@ -440,9 +373,93 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
             }
         }
         __syncthreads();
+        return Key{(T16 ? top16 : 0) - v - 1, (uint32_t)(maxv - v - 1)};
+    }
+    // branch-free up to the count itself: lanes outside the chunk or the
+    // window look up the zero word and miss
+    __device__ __forceinline__ bool probe(const Key& k, int32_t x, bool valid, Hit& h) const {
+        const uint32_t r = (uint32_t)(x + k.roff);
+        h.rr = valid && r <= k.rmax ? r : ZR;
+        if constexpr (PAIR) h.word = bp[h.rr >> 5].x;
+        else h.word = bw[h.rr >> 5];
+        // (the bit-field extract takes its offset and width mod 32)
+        return __builtin_amdgcn_ubfe(h.word, h.rr, 1u) != 0u;
+    }
+    // position of the element in N+(v): the set bits below it
+    __device__ __forceinline__ uint32_t position(const Key&, const Hit& h) const {
+        const uint32_t pw = PAIR ? bp[h.rr >> 5].y : (uint32_t)bpre[h.rr >> 5];
+        return pw + __popc(__builtin_amdgcn_ubfe(h.word, 0u, h.rr));
+    }
+};
 
-        const uint32_t rmax = (uint32_t)(maxv - v - 1);  // ranks v+1 .. maxv are in the window
-        const int32_t roff = (T16 ? top16 : 0) - v - 1;    // loaded element + roff = rank offset
+// Hash of N+(v) (RowHash), for rows whose ranks span too much for a window.
+// Suffix elements above the row's largest rank are not looked up.
+template <int LOG2S, bool PACKED>
+struct HashRow {
+    static constexpr bool T16 = false;
+    RowHash<LOG2S, PACKED> H;
+    struct Key {
+        int32_t v, maxv;
+    };
+    struct Hit {
+        int32_t p;
+    };
+    template <int NT>
+    __device__ __forceinline__ Key build(const int32_t* __restrict__ adj, int32_t b0, int32_t B, int32_t v,
+                                         int32_t, int tid, int, int) {
+        H.clear(tid, NT);
+        __syncthreads();
+        for (int j = tid; j < B; j += NT) H.insert(adj[b0 + j], v, j);
+        __syncthreads();
+        return Key{v, adj[b0 + B - 1]};
+    }
+    __device__ __forceinline__ bool probe(const Key& k, int32_t x, bool valid, Hit& h) const {
+        h.p = valid && x <= k.maxv ? H.find(x, k.v) : -1;
+        return h.p >= 0;
+    }
+    __device__ __forceinline__ uint32_t position(const Key&, const Hit& h) const { return (uint32_t)h.p; }
+};
+
+// Items of the rank-window classes and of the larger hash classes, one item
+// per workgroup of NT threads.  Each wave walks its own in-edges of the item,
+// one at a time, all 64 lanes on chunks of 64 E elements of the in-edge's
+// suffix.  The walk (in-edge, chunk, loop control) is wave-uniform, so it
+// runs on the scalar unit and the vector work per element is the probe alone;
+// the scalar unit is shared by the CU's waves, so a chunk of several elements
+// per lane spreads its cost.  Loads run D chunks ahead of their use in a ring
+// of registers.  t(v,w) partial counts are 32-bit LDS counters, one per
+// element of N+(v).  The hit ballot of every 64 elements is stored as a word
+// of the in-edge's bitmask (bits, at wbase[e] + suffix offset / 64), for the
+// credit passes.  Wide windows take large workgroups so that the LDS they
+// need still leaves room for enough waves per CU.
+template <class Row, int MAXB, int NT, int D, int MINW, int E>
+__global__ __launch_bounds__(NT, MINW) void k_tc_walk(const Item* __restrict__ all_items,
+                                                     const int64_t* __restrict__ heads, int cls,
+                                                     const int64_t* __restrict__ off,
+                                                     const int32_t* __restrict__ adj,
+                                                     const uint16_t* __restrict__ adj16, int32_t top16,
+                                                     const int2* __restrict__ in_ea,
+                                                     const int64_t* __restrict__ wbase,
+                                                     unsigned long long* __restrict__ bits,
+                                                     int32_t* __restrict__ t, int ipart, int nparts) {
+    constexpr bool T16 = Row::T16;
+    constexpr int NWAVES = NT / 64;
+    __shared__ Row row;
+    __shared__ uint32_t cnt[MAXB];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const Item* __restrict__ items = all_items + heads[2 * cls];
+    const int64_t n_items = heads[2 * cls + 1];
+
+    // this launch takes the items it = ipart (mod nparts) of the class
+    for (int64_t it = (int64_t)blockIdx.x * nparts + ipart; it < n_items; it += (int64_t)gridDim.x * nparts) {
+        const Item I = items[it];
+        const int32_t v = I.v;
+        const int32_t b0 = (int32_t)off[v];
+        const int32_t B = (int32_t)(off[v + 1] - b0);
+        for (int i = tid; i < B; i += NT) cnt[i] = 0;
+        const typename Row::Key key = row.template build<NT>(adj, b0, B, v, top16, tid, lane, wave);
+
         ChunkGen<E> gen{in_ea + I.s + wave, wbase, I.len > wave ? (I.len - wave + NWAVES - 1) / NWAVES : 0, NWAVES,
                         0, -64, 0, 64, 0, 0, 0, 0, false};  // pos = -64, bi = 64: next() fetches the first batch
         gen.next(lane);
@@ -486,32 +503,15 @@ __global__ __launch_bounds__(NT, MINW) void k_tc_window_s(const Item* __restrict
                     // a part of the chunk past the suffix's end is skipped
                     // (wave-uniform): short suffixes cost one probe, not E
                     if (64 * k >= nv) break;
-                    // branch-free up to the count itself: lanes outside the
-                    // chunk or the window look up the zero word and miss
-                    const uint32_t r = (uint32_t)(w[q][k] + roff);
-                    const uint32_t rr = ob[k] <= lastb && r <= rmax ? r : ZR;
-                    uint32_t word, pw;
-                    if constexpr (PAIR) {
-                        const uint2 e2 = bp[rr >> 5];
-                        word = e2.x;
-                        pw = e2.y;
-                    } else {
-                        word = bw[rr >> 5];
-                        pw = 0u;
-                    }
-                    // (the bit-field extract takes its offset and width mod 32)
-                    const bool hit = __builtin_amdgcn_ubfe(word, rr, 1u) != 0u;
+                    typename Row::Hit h;
+                    const bool hit = row.probe(key, w[q][k], ob[k] <= lastb, h);
                     const unsigned long long hb = __ballot(hit);
                     xlo = (uint32_t)writelane((int32_t)(uint32_t)hb, k, (int32_t)xlo);
                     xhi = (uint32_t)writelane((int32_t)(uint32_t)(hb >> 32), k, (int32_t)xhi);
-                    if (hit) {
-                        if constexpr (!PAIR) pw = bpre[rr >> 5];
-                        // position of w in N+(v): the set bits below it
-                        atomicAdd(&cnt[pw + __popc(__builtin_amdgcn_ubfe(word, 0u, rr))], 1u);
-                    }
+                    if (hit) atomicAdd(&cnt[row.position(key, h)], 1u);
                 }
                 // this chunk's words of the in-edge's hit bitmask, one per 64
-                // elements (lane k stores word k): every word of a window
+                // elements (lane k stores word k): every word of such an
                 // in-edge is written, once
                 const int nwords = (min(nv, 64 * E) + 63) >> 6;
                 if (lane < nwords)
@@ -584,6 +584,9 @@ __global__ __launch_bounds__(kThreads) void k_tc_search(const Item* __restrict__
 constexpr int kClasses = 14;
 constexpr int kSearch = 11;
 __host__ __device__ inline bool window_class(int c) { return (c >= 8 && c <= 10) || c == 12 || c == 13; }
+// classes run by the walking kernel (hit bitmasks, no global atomics): the
+// rank windows and the hash classes of rows longer than 128
+__host__ __device__ inline bool walk_class(int c) { return window_class(c) || (c >= 1 && c <= 7 && c != 4); }
 constexpr int kWindowLog2[3] = {14, 16, 18};
 
 // In-edges per work item: at least the row length (the hash build is then at
@@ -626,12 +629,12 @@ __global__ __launch_bounds__(kThreads) void k_item_count(const int64_t* __restri
         const int32_t k = cls >= 0 ? (int32_t)((I + cs - 1) / cs) : 0;
         vcls[v] = (int8_t)(k > 0 ? cls : -1);
         vcnt[v] = k;
-        wflag[v] = window_class(cls) ? 1 : 0;  // in-edges credited through hit bitmasks
+        wflag[v] = walk_class(cls) ? 1 : 0;  // in-edges credited through hit bitmasks
     }
 }
 
 // Words of every edge's hit bitmask: ceil(suffix length / 64) when its head
-// is a rank-window item (the only kernels that write bitmasks), else 0.
+// is an item of the walking kernel (the only one that writes bitmasks), else 0.
 __global__ __launch_bounds__(kThreads) void k_tc_words(const int64_t* __restrict__ off,
                                                        const int32_t* __restrict__ src,
                                                        const int32_t* __restrict__ adj,
@@ -962,7 +965,7 @@ struct TcLayout {
     int64_t* ctot;   // [kClasses] items per class
     Item* items;     // [max items]
     int64_t* heads;  // [2*kClasses]: start, length per class
-    uint8_t* wflag;  // [n] head of rank-window items
+    uint8_t* wflag;  // [n] head of walking-kernel items
     int32_t* words;  // [m] bitmask words per edge
     int64_t* wbase;  // [m+1] first bitmask word per edge
     unsigned long long* bits;  // [bitmask words] hit bitmasks
@@ -1026,20 +1029,34 @@ void launch_class(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, i
 // 8 with 2 slots 352; 10 or 12 elements spill and take 1.2 s.)
 constexpr int kWindowE = 8;
 
-template <int LOG2R, int NT, int D, bool T16 = false>
-void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
-                   int ipart = 0, int nparts = 1) {
+template <class Row, int MAXB, int NT, int D>
+void launch_walk(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
+                 int ipart, int nparts) {
     const int64_t cap_items = g->n + g->m / item_size(chunk, 0) + 1;
     int64_t blocks = cap_items < 16384 ? cap_items : 16384;
     const int32_t top16 = (int32_t)top16_of(g->n);
     if (g->ctx->tc_window_occupancy)
-        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 8, T16, kWindowE>), dim3((unsigned)blocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((k_tc_walk<Row, MAXB, NT, D, 8, kWindowE>), dim3((unsigned)blocks), dim3(NT), 0, s,
                            L.items, L.heads, c, g->off, g->adj, L.adj16, top16, g->in_ea, L.wbase, L.bits, t, ipart,
                            nparts);
     else
-        hipLaunchKernelGGL((k_tc_window_s<LOG2R, NT, D, 1, T16, kWindowE>), dim3((unsigned)blocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((k_tc_walk<Row, MAXB, NT, D, 1, kWindowE>), dim3((unsigned)blocks), dim3(NT), 0, s,
                            L.items, L.heads, c, g->off, g->adj, L.adj16, top16, g->in_ea, L.wbase, L.bits, t, ipart,
                            nparts);
+}
+
+template <int LOG2R, int NT, int D, bool T16 = false>
+void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
+                   int ipart = 0, int nparts = 1) {
+    launch_walk<WindowRow<LOG2R, T16>, 4096, NT, D>(g, L, c, chunk, t, s, ipart, nparts);
+}
+
+// hash class c of the walking kernel: table of 2^LOG2S slots, rows of at
+// most kMaxB[c % 4] entries
+template <int LOG2S, bool PACKED, int NT, int D>
+void launch_hash_walk(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
+                      int ipart = 0, int nparts = 1) {
+    launch_walk<HashRow<LOG2S, PACKED>, (1 << (LOG2S - 1)), NT, D>(g, L, c, chunk, t, s, ipart, nparts);
 }
 
 }  // namespace
@@ -1058,7 +1075,7 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     hipLaunchKernelGGL(k_adj16, dim3(grid_for(g->m, 16384)), dim3(kThreads), 0, s, g->adj, g->m,
                        (int32_t)top16_of(n), L.adj16);
     // where the hit bitmask of every edge starts (edges whose head is not a
-    // rank-window item get none)
+    // walking-kernel item get none)
     hipLaunchKernelGGL(k_tc_words, dim3(grid_for(g->m, 16384)), dim3(kThreads), 0, s, g->off, g->src, g->adj,
                        L.wflag, g->m, L.words);
     exclusive_scan_i32_i64(L.words, g->m, L.wbase, L.scan, s);
@@ -1091,15 +1108,15 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     launch_window<18, 1024, 3>(g, L, 10, chunk, t, s2);
     launch_window<14, 512, 3>(g, L, 8, chunk, t, s1);
     launch_window<16, 1024, 3>(g, L, 9, chunk, t, s1);
-    launch_class<RowHash<10, false>, 512, 2, 64>(g, L, 5, chunk, t, s1);
-    launch_class<RowHash<12, true>, 2048, 4, 64>(g, L, 2, chunk, t, s1);
+    launch_hash_walk<10, false, 256, 3>(g, L, 5, chunk, t, s1);
+    launch_hash_walk<12, true, 512, 3>(g, L, 2, chunk, t, s1);
     launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s1);
-    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s2, 1, 2);
+    launch_hash_walk<10, true, 256, 3>(g, L, 1, chunk, t, s2, 1, 2);
     launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
-    launch_class<RowHash<13, true>, 4096, 4, 64>(g, L, 3, chunk, t, s);
-    launch_class<RowHash<12, false>, 2048, 4, 64>(g, L, 6, chunk, t, s);
-    launch_class<RowHash<13, false>, 4096, 4, 64>(g, L, 7, chunk, t, s);
-    launch_class<RowHash<10, true>, 512, 2, 64>(g, L, 1, chunk, t, s, 0, 2);
+    launch_hash_walk<13, true, 1024, 3>(g, L, 3, chunk, t, s);
+    launch_hash_walk<12, false, 512, 3>(g, L, 6, chunk, t, s);
+    launch_hash_walk<13, false, 1024, 3>(g, L, 7, chunk, t, s);
+    launch_hash_walk<10, true, 256, 3>(g, L, 1, chunk, t, s, 0, 2);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
     (void)hipEventRecord(c->join[0], s1);
