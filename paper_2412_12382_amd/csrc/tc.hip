@@ -1051,12 +1051,16 @@ void launch_window(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, 
     launch_walk<WindowRow<LOG2R, T16>, 4096, NT, D>(g, L, c, chunk, t, s, ipart, nparts);
 }
 
-// hash class c of the walking kernel: table of 2^LOG2S slots, rows of at
-// most kMaxB[c % 4] entries
-template <int LOG2S, bool PACKED, int NT, int D>
+// Hash class c of the walking kernel: rows of at most MAXB = kMaxB[c % 4]
+// entries in a table of 2^LOG2S slots.  A probe of the wave runs as long as
+// its longest linear-probe sequence, so the tables are kept sparse where the
+// LDS allows (R-MAT scale 26, whole count with rows of up to 512 entries in
+// 1024, 2048 and 4096 slots: 334, 307 and 300 ms).
+template <int LOG2S, bool PACKED, int MAXB, int NT, int D>
 void launch_hash_walk(const mcd_graph* g, const TcLayout& L, int c, int64_t chunk, int32_t* t, hipStream_t s,
                       int ipart = 0, int nparts = 1) {
-    launch_walk<HashRow<LOG2S, PACKED>, (1 << (LOG2S - 1)), NT, D>(g, L, c, chunk, t, s, ipart, nparts);
+    static_assert(2 * MAXB <= (1 << LOG2S), "hash tables at most half full");
+    launch_walk<HashRow<LOG2S, PACKED>, MAXB, NT, D>(g, L, c, chunk, t, s, ipart, nparts);
 }
 
 }  // namespace
@@ -1108,15 +1112,15 @@ void launch_triangles(const mcd_graph* g, int32_t* t, void* ws, int64_t chunk, i
     launch_window<18, 1024, 3>(g, L, 10, chunk, t, s2);
     launch_window<14, 512, 3>(g, L, 8, chunk, t, s1);
     launch_window<16, 1024, 3>(g, L, 9, chunk, t, s1);
-    launch_hash_walk<10, false, 256, 3>(g, L, 5, chunk, t, s1);
-    launch_hash_walk<12, true, 512, 3>(g, L, 2, chunk, t, s1);
+    launch_hash_walk<12, false, 512, 256, 3>(g, L, 5, chunk, t, s1);
+    launch_hash_walk<13, true, 2048, 512, 3>(g, L, 2, chunk, t, s1);
     launch_class<RowHash<8, true>, 128, 1, 16>(g, L, 0, chunk, t, s1);
-    launch_hash_walk<10, true, 256, 3>(g, L, 1, chunk, t, s2, 1, 2);
+    launch_hash_walk<12, true, 512, 256, 3>(g, L, 1, chunk, t, s2, 1, 2);
     launch_class<RowHash<8, false>, 128, 1, 16>(g, L, 4, chunk, t, s);
-    launch_hash_walk<13, true, 1024, 3>(g, L, 3, chunk, t, s);
-    launch_hash_walk<12, false, 512, 3>(g, L, 6, chunk, t, s);
-    launch_hash_walk<13, false, 1024, 3>(g, L, 7, chunk, t, s);
-    launch_hash_walk<10, true, 256, 3>(g, L, 1, chunk, t, s, 0, 2);
+    launch_hash_walk<13, true, 4096, 1024, 3>(g, L, 3, chunk, t, s);
+    launch_hash_walk<13, false, 2048, 512, 3>(g, L, 6, chunk, t, s);
+    launch_hash_walk<13, false, 4096, 1024, 3>(g, L, 7, chunk, t, s);
+    launch_hash_walk<12, true, 512, 256, 3>(g, L, 1, chunk, t, s, 0, 2);
     hipLaunchKernelGGL(k_tc_search, dim3(4096), dim3(kThreads), 0, s, L.items, L.heads, kSearch, g->off,
                        g->adj, g->in_ea, t);
     (void)hipEventRecord(c->join[0], s1);
