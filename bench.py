@@ -24,8 +24,11 @@ Before the timed steps (not timed): the picker is trained on the 256-graph
 planted-partition batch (192 train / 64 validation); its validation ARI is
 compared with the best swept threshold per graph and the best single global
 threshold, and its latency with the 64-threshold sweep on the same GPU.  The
-triangle-count launch parameters are then autotuned once on the workload
-graph (mcd_tune_triangles) and kept for the timed steps.
+triangle-count launch parameters and the sweep's launch shape are then
+autotuned once on the workload graph (mcd_tune_triangles, then each sweep
+shape timed), or read from an autotune cache file (--tune-cache or
+$MCD_AUTOTUNE_CACHE) that holds the graph's size bucket, and kept for the
+timed steps.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -58,7 +61,10 @@ def parse():
     ap.add_argument("--cpu-scale", type=int, default=22, help="R-MAT scale of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-picker", action="store_true", help="skip picker training (use delta 3/50)")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default triangle-count parameters")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file (default: $MCD_AUTOTUNE_CACHE); tuned values are read from it "
+                         "when it holds this graph's size bucket, else tuned and stored")
     ap.add_argument("--no-cpu-single", action="store_true", help="skip the one-thread oracle runs")
     ap.add_argument("--oracle-leg", default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
@@ -616,9 +622,24 @@ def main():
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
         log(f"scratch grown to {need / 2**30:.1f} GiB for the triangle count")
     tuned = None
+    tune_source = "defaults"
+    cache = args.tune_cache or os.environ.get("MCD_AUTOTUNE_CACHE")
     if not args.no_tune:
-        tuned, tuned_ms = M.mcd_tune_triangles(g0, t, ws=ws, reps=1)
-        log(f"triangle-count parameters tuned on this graph: {tuned} ({tuned_ms:.1f} ms)")
+        if cache and M.mcd_tune_cache_load(g0, cache):
+            tune_source = f"cache {cache}"
+        else:
+            tuned, tuned_ms = M.mcd_tune_triangles(g0, t, ws=ws, reps=1)
+            log(f"triangle-count parameters tuned on this graph: {tuned} ({tuned_ms:.1f} ms)")
+            # the sweep's launch shape, on this graph's 16-point sweep
+            shape_ms, shape = M.tune_sweep_shape(ctx, lambda: M.mcd_sweep(
+                g0, M.MCD_SIM_TECTONIC, t, grid16, vbase=vbase, stats=sweep_stats, ws=ws))
+            log(f"sweep launch shape tuned: {shape} ({', '.join(f'{k}: {v:.1f} ms' for k, v in shape_ms.items())})")
+            tune_source = "tuned on this graph"
+            if cache:
+                M.mcd_tune_cache_store(g0, cache, tuned_ms)
+                tune_source += f", stored in {cache}"
+    tuned = {k: M.mcd_ctx_get_param(ctx, k) for k in M.CACHED_PARAMS}
+    log(f"launch parameters ({tune_source}): {tuned}")
     del g0
 
     for i in range(args.warmup):
@@ -709,7 +730,7 @@ def main():
                                f"learned threshold, 16-point check sweep k/50, components",
                    "n": n, "m": m, "pairs": P,
                    "step": "build+triangles+picker+sweep16+weights/prune/components (Tectonic, TW)",
-                   "triangle_params": tuned},
+                   "launch_params": tuned, "launch_params_source": tune_source},
         "value_scope": "whole step: m / (build + triangles + picker + sweep16 + weights/prune/components "
                        "(Tectonic, then TW)); the metric's weight+prune+CC pass alone is wpc_edges_per_s",
         "stages_ms": {k: round(v_, 3) for k, v_ in avg.items()},

@@ -61,7 +61,8 @@ typedef int32_t mcd_status;
 #define MCD_ERR_DEVICE (-6)         /* a HIP runtime call failed                     */
 #define MCD_ERR_NOT_CONVERGED (-7)  /* an iterative step hit its iteration cap       */
 #define MCD_ERR_EMPTY (-8)          /* the requested statistic has no data           */
-#define MCD_ERR_CHECKPOINT (-9)     /* a picker checkpoint is unreadable or corrupt  */
+#define MCD_ERR_CHECKPOINT (-9)     /* a picker checkpoint or autotune cache file is
+                                       unreadable or corrupt                          */
 
 typedef struct mcd_ctx mcd_ctx;
 typedef struct mcd_graph mcd_graph;
@@ -192,6 +193,28 @@ mcd_status mcd_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_byt
 mcd_status mcd_tune_triangles_workspace_size(const mcd_graph* g, size_t* bytes);
 mcd_status mcd_tune_triangles(const mcd_graph* g, int32_t* t, void* ws, size_t ws_bytes, int32_t reps,
                               int64_t* host_best, float* host_ms);
+
+/* Autotune cache: the tuned launch parameters of a context kept in a JSON
+ * text file at `path`, one entry per (device architecture name, floor(log2 n),
+ * floor(log2 m), tuning version of this library).  The parameters kept are
+ * tc_chunk, tc_lds_max, tc_packed_range, tc_window_max, tc_window_occupancy
+ * and sweep_shape (see mcd_ctx_set_param).
+ *   mcd_tune_cache_load:  on an entry for g's key, every value passes the
+ *     checks of mcd_ctx_set_param and is set on ctx (all or none), *hit = 1;
+ *     otherwise ctx is unchanged and *hit = 0.  A missing file is a miss.
+ *   mcd_tune_cache_store: records ctx's current parameters (and ms, the tuned
+ *     time, for information) as g's entry, replacing an entry of the same
+ *     key and keeping the others; the file is written beside `path` and then
+ *     renamed over it.  Calls that write one file concurrently race.
+ *   mcd_tune_cache_check_file: the file checks alone, on the host (no device
+ *     needed): MCD_OK for a sound or missing file.
+ * g must belong to ctx.  Synchronous, host only (no device work).  Errors:
+ * MCD_ERR_CHECKPOINT (the file is unreadable, malformed, or holds a value
+ * the context refuses; the file is left as it was), MCD_ERR_INVALID_ARG,
+ * MCD_ERR_DEVICE (the device's properties could not be read). */
+mcd_status mcd_tune_cache_load(mcd_ctx* ctx, const mcd_graph* g, const char* path, int32_t* hit);
+mcd_status mcd_tune_cache_store(const mcd_ctx* ctx, const mcd_graph* g, const char* path, float ms);
+mcd_status mcd_tune_cache_check_file(const char* path);
 
 /* kappa-clique participation for kappa = 4 (Table tab:simfunctions):
  * k4[e] = the number of 4-cliques containing edge e (library edge order),

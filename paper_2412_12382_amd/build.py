@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmcd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["prim.hip", "build.hip", "tc.hip", "k4.hip", "weight.hip", "cc.hip", "select.hip", "sweep.hip", "picker.hip",
-           "picker_api.hip", "api.hip"]
+           "picker_api.hip", "tune_cache.hip", "api.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -119,6 +119,9 @@ def lib():
             "mcd_picker_save": [P, ctypes.c_char_p],
             "mcd_picker_load": [P, ctypes.c_char_p],
             "mcd_picker_check_file": [ctypes.c_char_p],
+            "mcd_tune_cache_load": [P, P, ctypes.c_char_p, ctypes.POINTER(I32)],
+            "mcd_tune_cache_store": [P, P, ctypes.c_char_p, ctypes.c_float],
+            "mcd_tune_cache_check_file": [ctypes.c_char_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -648,6 +651,8 @@ def mcd_picker_check_file(path: str) -> None:
 KEPT_SEGMENTS = 16384
 NOALLOC_MAX_VERTICES = 1 << 24
 TUNE_PARAMS = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max")
+# the launch parameters an autotune cache entry holds
+CACHED_PARAMS = TUNE_PARAMS + ("tc_window_occupancy", "sweep_shape")
 
 
 def mcd_tune_triangles_workspace_size(g: Graph) -> int:
@@ -668,6 +673,44 @@ def mcd_tune_triangles(g: Graph, t=None, ws=None, reps: int = 2):
     _check(lib().mcd_tune_triangles(g.handle, _p(t), _p(ws), ws.numel() * ws.element_size(), reps, best,
                                     ctypes.byref(ms)))
     return dict(zip(TUNE_PARAMS, list(best))), ms.value
+
+
+def mcd_tune_cache_load(g: Graph, path: str) -> bool:
+    """Sets g's context from the autotune cache at path; True on a hit."""
+    hit = ctypes.c_int32()
+    _check(lib().mcd_tune_cache_load(g.ctx.handle, g.handle, os.fsencode(path), ctypes.byref(hit)))
+    return bool(hit.value)
+
+
+def mcd_tune_cache_store(g: Graph, path: str, ms: float) -> None:
+    """Records g's context's current launch parameters in the cache at path."""
+    _check(lib().mcd_tune_cache_store(g.ctx.handle, g.handle, os.fsencode(path), float(ms)))
+
+
+def mcd_tune_cache_check_file(path: str) -> None:
+    _check(lib().mcd_tune_cache_check_file(os.fsencode(path)))
+
+
+def tune_sweep_shape(ctx: Context, run, reps: int = 1):
+    """Times `run` (a call of mcd_sweep on the context's stream) under each
+    launch shape of the sweep's level loop and keeps the fastest; returns
+    ({shape: ms}, best shape)."""
+    times = {}
+    for shape in (0, 1, 2):
+        mcd_ctx_set_param(ctx, "sweep_shape", shape)
+        run()  # warm-up
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        times[shape] = best
+    shape = min(times, key=times.get)
+    mcd_ctx_set_param(ctx, "sweep_shape", shape)
+    return times, shape
 
 
 def mcd_kept_segment_len(g: Graph) -> int:

@@ -131,3 +131,46 @@ def test_picker_calls_reject_null_without_device():
     assert L.mcd_picker_load(None, b"x") == -1
     assert L.mcd_picker_save(None, b"x") == -1
     assert L.mcd_picker_destroy(None) == 0
+
+
+def test_tune_cache_file_checks_on_host(tmp_path):
+    import json
+    entry = {"arch": "gfx950:sramecc+:xnack-", "tune_version": 2, "log2_n": 20, "log2_m": 23, "ms": 12.5,
+             "params": {"tc_chunk": 512, "tc_lds_max": 4096, "tc_packed_range": 1048574, "tc_window_max": 262144,
+                        "tc_window_occupancy": 1, "sweep_shape": 0}}
+    good = {"format": "mcd-tune-cache", "version": 1, "entries": [entry]}
+    path = tmp_path / "tune.json"
+
+    def status(text):
+        path.write_text(text)
+        try:
+            M.mcd_tune_cache_check_file(str(path))
+            return 0
+        except M.MCDError as e:
+            return e.status
+
+    assert status(json.dumps(good)) == 0
+    assert status(json.dumps({"format": "mcd-tune-cache", "version": 1, "entries": []})) == 0
+    bad_param = json.loads(json.dumps(good))
+    bad_param["entries"][0]["params"]["tc_chunk"] = "512"
+    no_arch = json.loads(json.dumps(good))
+    del no_arch["entries"][0]["arch"]
+    cases = {
+        "truncated": json.dumps(good)[:-3],
+        "trailing text": json.dumps(good) + " x",
+        "other format": json.dumps(dict(good, format="something-else")),
+        "version 2": json.dumps(dict(good, version=2)),
+        "entries not a list": json.dumps(dict(good, entries={})),
+        "string parameter": json.dumps(bad_param),
+        "entry without arch": json.dumps(no_arch),
+        "not an object": "[1, 2, 3]",
+        "empty": "",
+        "deep nesting": "[" * 64 + "]" * 64,
+    }
+    for name, text in cases.items():
+        assert status(text) == -9, name
+    M.mcd_tune_cache_check_file(str(tmp_path / "absent.json"))  # a missing file is an empty cache
+    L = M.lib()
+    assert L.mcd_tune_cache_check_file(None) == -1
+    assert L.mcd_tune_cache_load(None, None, b"x", None) == -1
+    assert L.mcd_tune_cache_store(None, None, b"x", ctypes.c_float(1.0)) == -1

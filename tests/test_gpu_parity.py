@@ -356,6 +356,51 @@ def test_autotuner_sets_params_and_keeps_counts():
         M.mcd_ctx_set_param(g.ctx, k, v)
 
 
+def test_tune_cache_round_trip(tmp_path):
+    """Parameters stored for a graph come back on a graph of the same size
+    bucket, not on another; a corrupt file is refused and changes nothing."""
+    from gpu_util import build
+    import json
+    path = str(tmp_path / "tune.json")
+    s, d, n = gg.rmat(12, seed=43)
+    g = build(s, d, n)
+    names = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max", "tc_window_occupancy", "sweep_shape")
+    saved = {k: M.mcd_ctx_get_param(g.ctx, k) for k in names}
+    chosen = {"tc_chunk": 300, "tc_lds_max": 2048, "tc_packed_range": 5000, "tc_window_max": 1 << 16,
+              "tc_window_occupancy": 0, "sweep_shape": 2}
+    try:
+        assert not M.mcd_tune_cache_load(g, path)  # no file yet: a miss
+        for k, v in chosen.items():
+            M.mcd_ctx_set_param(g.ctx, k, v)
+        M.mcd_tune_cache_store(g, path, 1.5)
+        s2, d2, n2 = gg.rmat(15, seed=44)
+        g2 = build(s2, d2, n2)
+        M.mcd_ctx_set_param(g.ctx, "tc_chunk", 700)
+        M.mcd_tune_cache_store(g2, path, 2.5)  # a second entry, other size bucket
+        M.mcd_tune_cache_check_file(path)
+        doc = json.load(open(path))
+        assert len(doc["entries"]) == 2
+        for k, v in saved.items():
+            M.mcd_ctx_set_param(g.ctx, k, v)
+        assert M.mcd_tune_cache_load(g, path)
+        assert {k: M.mcd_ctx_get_param(g.ctx, k) for k in names} == chosen
+        assert M.mcd_tune_cache_load(g2, path)
+        assert M.mcd_ctx_get_param(g.ctx, "tc_chunk") == 700
+        s3, d3, n3 = gg.rmat(10, seed=45)
+        assert not M.mcd_tune_cache_load(build(s3, d3, n3), path)
+        # a refused value: nothing is set
+        doc["entries"][0]["params"]["tc_window_max"] = 1 << 20
+        json.dump(doc, open(path, "w"))
+        before = {k: M.mcd_ctx_get_param(g.ctx, k) for k in names}
+        with pytest.raises(M.MCDError) as ei:
+            M.mcd_tune_cache_load(g, path)
+        assert ei.value.status == -9
+        assert {k: M.mcd_ctx_get_param(g.ctx, k) for k in names} == before
+    finally:
+        for k, v in saved.items():
+            M.mcd_ctx_set_param(g.ctx, k, v)
+
+
 @pytest.mark.parametrize("scale", [12, 15])
 def test_rmat_k3_and_jaccard(scale):
     s, d, n = gg.rmat(scale, seed=100 + scale)
