@@ -592,12 +592,16 @@ struct GridSync {
         unsigned int pad[30];
     } grp[kSyncGroups];
     int timed_out;  // a block waited longer than the limit
-    int pad1[31];
+    int giant;      // root of the sampled large component of a dense level
+    int pad1[30];
 };
 
 struct SweepArgs {
     const int32_t* src;
     const int32_t* adj;
+    const int64_t* off;     // CSR row offsets (out-edges of every vertex)
+    const int64_t* in_off;  // in-edge list offsets
+    const int2* in_ea;      // in-edge lists: (edge id, suffix length)
     const uint8_t* level;
     const int32_t* perm;
     const int32_t* deg;
@@ -680,6 +684,79 @@ __device__ void grid_sync(const SweepArgs& a) {
         }
     }
     __syncthreads();
+}
+
+// A level that holds most of a single graph's edges (the lowest thresholds)
+// is united vertex by vertex, skipping the vertices of one large component,
+// after the sampling idea of Sutton et al. (Afforest): (A) every vertex is
+// united with up to two of its first eight out-edges at the level, which
+// links most vertices of the graph's large component; (B) the root that most
+// of 1024 evenly spaced vertices reach is taken as that component's; (C) every
+// vertex outside it unites all its edges at the level, out-edges and
+// in-edges.  An edge with both endpoints inside the component at the time
+// they are looked at joins nothing new (components only grow), and every
+// other edge has an endpoint outside, whose lists hold it; so the partition
+// equals the edge-by-edge union's.  Each phase ends at a grid barrier.
+constexpr int kSampleVerts = 1024;
+
+__device__ void d_union_level_dense(const SweepArgs& a, int lv, unsigned long long* sh) {
+    const int64_t n = a.n;
+    int32_t* parent = a.parent;
+    GRID_STRIDE(x, n) {  // (A)
+        const int64_t e0 = a.off[x], e1 = min(a.off[x + 1], e0 + 8);
+        int linked = 0;
+        for (int64_t e = e0; e < e1 && linked < 2; ++e)
+            if (a.level[e] == lv) {
+                uf_unite(parent, (int32_t)x, a.adj[e]);
+                ++linked;
+            }
+    }
+    grid_sync(a);
+    if (blockIdx.x == 0) {  // (B): count the roots of the samples in an LDS table
+        int32_t* key = (int32_t*)sh;
+        uint32_t* cnt = (uint32_t*)(key + 2 * kSampleVerts);
+        for (int i = threadIdx.x; i < 2 * kSampleVerts; i += blockDim.x) {
+            key[i] = -1;
+            cnt[i] = 0u;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kSampleVerts; i += blockDim.x) {
+            const int32_t r = uf_find(parent, (int32_t)((int64_t)i * n / kSampleVerts));
+            uint32_t h = ((uint32_t)r * 2654435761u) >> 21;  // 11 bits: 2 kSampleVerts slots
+            for (;;) {
+                const int32_t k = atomicCAS(&key[h], -1, r);
+                if (k == -1 || k == r) break;
+                h = (h + 1) & (2 * kSampleVerts - 1);
+            }
+            atomicAdd(&cnt[h], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {  // the most sampled root (ties: the smaller root)
+            uint64_t best = 0;
+            for (int i = threadIdx.x; i < 2 * kSampleVerts; i += 64)
+                if (key[i] >= 0) {
+                    const uint64_t c = ((uint64_t)cnt[i] << 32) | (uint32_t)~(uint32_t)key[i];
+                    best = c > best ? c : best;
+                }
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint64_t y = __shfl_xor(best, o);
+                best = y > best ? y : best;
+            }
+            if (threadIdx.x == 0) a.sync->giant = best ? (int32_t)~(uint32_t)best : -1;
+        }
+        __syncthreads();
+    }
+    grid_sync(a);
+    const int32_t giant = __hip_atomic_load(&a.sync->giant, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    GRID_STRIDE(x, n) {  // (C)
+        if (uf_find(parent, (int32_t)x) == giant) continue;
+        for (int64_t e = a.off[x]; e < a.off[x + 1]; ++e)
+            if (a.level[e] == lv) uf_unite(parent, (int32_t)x, a.adj[e]);
+        for (int64_t k = a.in_off[x]; k < a.in_off[x + 1]; ++k) {
+            const int32_t e = a.in_ea[k].x;
+            if (a.level[e] == lv) uf_unite(parent, (int32_t)x, a.src[e]);
+        }
+    }
 }
 
 // Writes the statistics of threshold i (caller slot a.out.slot[i]) for every
@@ -779,7 +856,13 @@ __global__ __launch_bounds__(NT, WPE) void k_sweep_levels(const SweepArgs* __res
             a.keys[h] = ~0ull;
             a.counts[h] = 0;
         }
-        if (m > 0) d_union_level(a.src, a.adj, a.level, m, i + 1, a.parent);
+        // a single graph's level holding more than half its edges goes
+        // vertex by vertex (uniform over the grid: every block reads the
+        // same count)
+        if (m > 0 && G == 1 && 2 * a.hist[i + 1] > (unsigned long long)m)
+            d_union_level_dense(a, i + 1, sh);
+        else if (m > 0)
+            d_union_level(a.src, a.adj, a.level, m, i + 1, a.parent);
         grid_sync(a);
         d_pass_size(a.parent, n, a.gid, G, a.size, acc + kAccNcc * G, sh);
         if (a.labels) d_label_min(a.parent, a.perm, n, a.minid);
@@ -996,6 +1079,9 @@ void launch_sweep(const mcd_graph* g, int measure, const int32_t* t, const Sweep
     SweepArgs a;
     a.src = g->src;
     a.adj = g->adj;
+    a.off = g->off;
+    a.in_off = g->in_off;
+    a.in_ea = g->in_ea;
     a.level = L.level;
     a.perm = g->perm;
     a.deg = g->deg;

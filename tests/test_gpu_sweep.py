@@ -47,6 +47,20 @@ def test_sweep_rmat_grid16():
     compare(gpu_sweep(s, d, n, oracle.TECTONIC, GRID16), oracle_sweep(s, d, n, oracle.TECTONIC, GRID16))
 
 
+def test_sweep_dense_level_two_large_components():
+    """One graph made of two R-MAT graphs side by side: the lowest
+    thresholds hold most edges and two large components form, only one of
+    which the dense-level union may pass over; isolated vertices too."""
+    s1, d1, n1 = gg.rmat(13, seed=51)
+    s2, d2, n2 = gg.rmat(14, seed=52)
+    s = np.concatenate([s1, s2 + n1]).astype(np.int32)
+    d = np.concatenate([d1, d2 + n1]).astype(np.int32)
+    n = n1 + n2 + 100  # 100 isolated vertices at the end
+    compare(gpu_sweep(s, d, n, oracle.TECTONIC, GRID16), oracle_sweep(s, d, n, oracle.TECTONIC, GRID16))
+    deltas = [(-40, 3), (-10, 1), (-1, 1), (0, 1), (2, 1)]
+    compare(gpu_sweep(s, d, n, oracle.TW, deltas), oracle_sweep(s, d, n, oracle.TW, deltas))
+
+
 def test_sweep_tw_unsorted_duplicates():
     s, d, n = gg.rmat(12, seed=32)
     deltas = [(0, 1), (-10, 1), (3, 2), (-10, 1), (-40, 3), (7, 1), (-1, 1)]
