@@ -844,6 +844,21 @@ __global__ __launch_bounds__(NT, WPE) void k_sweep_levels(const SweepArgs* __res
         const int p = i & 1;
         unsigned long long* acc = a.acc[p];
         if (i < a.K - 1) d_write_stats(a, i + 1, p ^ 1);
+        // A level that adds no edge to any graph leaves every partition as it
+        // was: its statistics are the previous threshold's (m_kept, the only
+        // other input, is read from the level counts when written).  Without
+        // label output, the accumulators are copied instead of recomputed.
+        // The test reads the same counts in every block, so all skip together.
+        if (i < a.K - 1 && !a.labels && G <= kLdsGraphs) {
+            bool added = false;
+            for (int g = 0; g < G && !added; ++g) added = a.hist[(int64_t)g * (a.K + 1) + i + 1] != 0ull;
+            if (!added) {
+                GRID_STRIDE(j, (int64_t)kAccFields * G) acc[j] = a.acc[p ^ 1][j];
+                if (a.prf) GRID_STRIDE(j, 3 * (int64_t)G) a.acc_prf[p][j] = a.acc_prf[p ^ 1][j];
+                grid_sync(a);
+                continue;
+            }
+        }
         GRID_STRIDE(j, (int64_t)kAccFields * G) acc[j] = 0ull;
         if (a.prf) GRID_STRIDE(j, 3 * (int64_t)G) a.acc_prf[p][j] = 0.0;
         GRID_STRIDE(v, n) {

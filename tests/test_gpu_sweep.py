@@ -14,15 +14,16 @@ GRID64 = [(9 + 7 * i, 900) for i in range(64)]
 GRID16 = [(k, 50) for k in range(16)]
 
 
-def gpu_sweep(src, dst, n, measure, deltas, truth=None, vbase=None):
+def gpu_sweep(src, dst, n, measure, deltas, truth=None, vbase=None, want_labels=True):
     from gpu_util import build
     g = build(src, dst, n)
     t = M.mcd_triangles(g)
     vb = None if vbase is None else torch.from_numpy(np.asarray(vbase, np.int64)).cuda()
     tr = None if truth is None else torch.from_numpy(np.asarray(truth, np.int32)).cuda()
-    stats, ari, labels = M.mcd_sweep(g, measure, t, deltas, vbase=vb, truth=tr, want_labels=True)
+    stats, ari, labels = M.mcd_sweep(g, measure, t, deltas, vbase=vb, truth=tr, want_labels=want_labels)
     torch.cuda.synchronize()
-    return (stats.cpu().numpy(), None if ari is None else ari.cpu().numpy(), labels.cpu().numpy()[:, :n])
+    return (stats.cpu().numpy(), None if ari is None else ari.cpu().numpy(),
+            None if labels is None else labels.cpu().numpy()[:, :n])
 
 
 def oracle_sweep(src, dst, n, measure, deltas, truth=None, vbase=None):
@@ -35,7 +36,8 @@ def oracle_sweep(src, dst, n, measure, deltas, truth=None, vbase=None):
 def compare(got, want):
     gs, ga, gl = got
     ws, wa, wl = want
-    assert np.array_equal(gl, wl)
+    if gl is not None:
+        assert np.array_equal(gl, wl)
     bad = np.argwhere(gs != ws)
     assert len(bad) == 0, [(tuple(b), int(gs[tuple(b)]), int(ws[tuple(b)])) for b in bad[:10]]
     if wa is not None:
@@ -61,6 +63,24 @@ def test_sweep_dense_level_two_large_components():
     compare(gpu_sweep(s, d, n, oracle.TW, deltas), oracle_sweep(s, d, n, oracle.TW, deltas))
 
 
+def test_sweep_statistics_without_labels():
+    """Without label output, thresholds that add no edge copy the previous
+    threshold's statistics: duplicated thresholds, an empty top of the grid,
+    planted classes (ARI) and a batch."""
+    s, d, n = gg.rmat(14, seed=31)
+    compare(gpu_sweep(s, d, n, oracle.TECTONIC, GRID16, want_labels=False),
+            oracle_sweep(s, d, n, oracle.TECTONIC, GRID16))
+    s, d, n = gg.rmat(12, seed=32)
+    deltas = [(0, 1), (-10, 1), (3, 2), (-10, 1), (-40, 3), (7, 1), (-1, 1), (7, 1), (50, 1)]
+    compare(gpu_sweep(s, d, n, oracle.TW, deltas, want_labels=False), oracle_sweep(s, d, n, oracle.TW, deltas))
+    c1 = gg.sbm_c1()
+    args = (c1["src"], c1["dst"], c1["n"], oracle.TECTONIC, GRID64[:60] + [(1, 1), (1, 1), (2, 1)], c1["truth"])
+    compare(gpu_sweep(*args, want_labels=False), oracle_sweep(*args))
+    src, dst, N, truth, vbase = small_sbm_batch()
+    args = (src, dst, N, oracle.TECTONIC, GRID16 + [(15, 50)], truth, vbase)
+    compare(gpu_sweep(*args, want_labels=False), oracle_sweep(*args))
+
+
 def test_sweep_tw_unsorted_duplicates():
     s, d, n = gg.rmat(12, seed=32)
     deltas = [(0, 1), (-10, 1), (3, 2), (-10, 1), (-40, 3), (7, 1), (-1, 1)]
@@ -73,7 +93,9 @@ def test_sweep_sbm_planted_ari():
     compare(gpu_sweep(*args), oracle_sweep(*args))
 
 
-def test_sweep_batch_of_sbms():
+def small_sbm_batch():
+    """Six planted-partition graphs of the batch distribution (at most 3000
+    vertices each) as one disjoint union: src, dst, n, truth, vbase."""
     graphs = []
     for g in range(6):
         pr = gg.sbm_batch_params(g)
@@ -95,6 +117,11 @@ def test_sweep_batch_of_sbms():
     src = np.concatenate(srcs).astype(np.int32)
     dst = np.concatenate(dsts).astype(np.int32)
     truth = np.concatenate(truths).astype(np.int32)
+    return src, dst, N, truth, vbase
+
+
+def test_sweep_batch_of_sbms():
+    src, dst, N, truth, vbase = small_sbm_batch()
     args = (src, dst, N, oracle.TECTONIC, GRID64, truth, vbase)
     want = oracle_sweep(*args)
     for _ in range(3):  # repeated runs must agree exactly (surfaces races)
