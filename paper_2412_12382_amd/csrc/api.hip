@@ -659,8 +659,18 @@ mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const i
     hipStream_t s = g->ctx->stream;
     // with no vertex there is no edge either: the pass only zeroes n_kept
     int32_t* parent = mcd::launch_components_init(g, labels, n_components, ws, s);
-    mcd::launch_weigh_prune(g, measure, t, delta.num, delta.den, deltas ? n_graphs : 1, vbase, deltas, w_f32, w_i32,
-                            keep_bits, nullptr, nullptr, n_kept, s, g->n > 0 ? parent : nullptr);
+    // A threshold of at most 0 keeps every edge of a measure that is never
+    // negative: the pass then writes weights and keep bits only, and the
+    // components come from the vertex-by-vertex union of every edge.
+    const bool nonnegative = measure != MCD_SIM_TW;
+    if (!deltas && nonnegative && delta.num <= 0 && g->n > 0 && g->m > 0) {
+        mcd::launch_weigh_prune(g, measure, t, delta.num, delta.den, 1, nullptr, nullptr, w_f32, w_i32, keep_bits,
+                                nullptr, nullptr, n_kept, s, nullptr);
+        mcd::launch_components_all_edges(g, parent, parent + g->n, s);
+    } else {
+        mcd::launch_weigh_prune(g, measure, t, delta.num, delta.den, deltas ? n_graphs : 1, vbase, deltas, w_f32,
+                                w_i32, keep_bits, nullptr, nullptr, n_kept, s, g->n > 0 ? parent : nullptr);
+    }
     mcd::launch_components_finish(g, labels, n_components, ws, s);
     return MCD_OK;
 }

@@ -148,9 +148,92 @@ void finish_components(const mcd_graph* g, int32_t* labels, int64_t* n_component
                        (unsigned long long*)n_components);
 }
 
+// Every edge of the graph kept (a threshold no similarity falls below),
+// after the sampling idea of Sutton et al. (Afforest): each vertex first
+// unites its first two out-edges, which links most of the large component
+// of a skewed graph; the root most of 1024 evenly spaced vertices reach is
+// taken as that component's; then every vertex outside it unites all its
+// edges, out-edges from the CSR and in-edges from the in-edge lists.  An edge
+// with both endpoints inside that component when they are looked at joins
+// nothing new (components only grow), and every other edge is in the lists
+// of an endpoint outside it, so the partition is the edge-by-edge union's.
+constexpr int kSampleVerts = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_cc_sample(const int64_t* __restrict__ off,
+                                                        const int32_t* __restrict__ adj, int64_t n,
+                                                        int32_t* parent) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e0 = off[x], e1 = min(off[x + 1], e0 + 2);
+        for (int64_t e = e0; e < e1; ++e) uf_unite(parent, (int32_t)x, adj[e]);
+    }
+}
+
+// One workgroup of kSampleVerts threads: the most frequent root of the
+// samples (ties: the smaller root) into *giant.
+__global__ __launch_bounds__(kSampleVerts) void k_cc_giant(int32_t* parent, int64_t n, int32_t* __restrict__ giant) {
+    __shared__ int32_t key[2 * kSampleVerts];
+    __shared__ uint32_t cnt[2 * kSampleVerts];
+    __shared__ unsigned long long wbest[kSampleVerts / 64];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 2 * kSampleVerts; i += kSampleVerts) {
+        key[i] = -1;
+        cnt[i] = 0u;
+    }
+    __syncthreads();
+    const int32_t r = uf_find(parent, (int32_t)((int64_t)tid * n / kSampleVerts));
+    uint32_t h = ((uint32_t)r * 2654435761u) >> 21;  // 11 bits: 2 kSampleVerts slots
+    for (;;) {
+        const int32_t k = atomicCAS(&key[h], -1, r);
+        if (k == -1 || k == r) break;
+        h = (h + 1) & (2 * kSampleVerts - 1);
+    }
+    atomicAdd(&cnt[h], 1u);
+    __syncthreads();
+    unsigned long long best = 0;
+    for (int i = tid; i < 2 * kSampleVerts; i += kSampleVerts)
+        if (key[i] >= 0) {
+            const unsigned long long c = ((unsigned long long)cnt[i] << 32) | (uint32_t)~(uint32_t)key[i];
+            best = c > best ? c : best;
+        }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(best, o);
+        best = y > best ? y : best;
+    }
+    if ((tid & 63) == 0) wbest[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kSampleVerts / 64; ++w) best = wbest[w] > best ? wbest[w] : best;
+        *giant = (int32_t)~(uint32_t)best;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cc_rest(const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ adj,
+                                                      const int64_t* __restrict__ in_off,
+                                                      const int2* __restrict__ in_ea,
+                                                      const int32_t* __restrict__ src, int64_t n, int32_t* parent,
+                                                      const int32_t* __restrict__ giant) {
+    const int32_t c = *giant;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        if (uf_find(parent, (int32_t)x) == c) continue;
+        for (int64_t e = off[x]; e < off[x + 1]; ++e) uf_unite(parent, (int32_t)x, adj[e]);
+        for (int64_t k = in_off[x]; k < in_off[x + 1]; ++k) uf_unite(parent, (int32_t)x, src[in_ea[k].x]);
+    }
+}
+
 }  // namespace
 
-size_t cc_scratch_bytes(const mcd_graph* g) { return mcd_align(sizeof(int32_t) * (size_t)g->n + 1); }
+// parent (n int32) and one more int32 behind it (the vertex-by-vertex union
+// of every edge keeps its sampled root there)
+size_t cc_scratch_bytes(const mcd_graph* g) { return mcd_align(sizeof(int32_t) * ((size_t)g->n + 1)); }
+
+void launch_components_all_edges(const mcd_graph* g, int32_t* parent, int32_t* giant, hipStream_t s) {
+    if (g->n <= 0 || g->m <= 0) return;
+    hipLaunchKernelGGL(k_cc_sample, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, g->off, g->adj, g->n, parent);
+    hipLaunchKernelGGL(k_cc_giant, dim3(1), dim3(kSampleVerts), 0, s, parent, g->n, giant);
+    hipLaunchKernelGGL(k_cc_rest, dim3(grid_for(g->n, 1 << 16)), dim3(kThreads), 0, s, g->off, g->adj, g->in_off,
+                       g->in_ea, g->src, g->n, parent, giant);
+}
 
 void launch_components(const mcd_graph* g, const uint32_t* keep_bits, int32_t* labels, int64_t* n_components,
                        void* ws, hipStream_t s) {

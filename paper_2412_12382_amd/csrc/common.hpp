@@ -187,6 +187,10 @@ int32_t* launch_components_init(const mcd_graph* g, int32_t* labels, int64_t* n_
                                 hipStream_t s);
 void launch_components_finish(const mcd_graph* g, int32_t* labels, int64_t* n_components, void* ws,
                               hipStream_t s);
+// Unions of every edge of the graph into the union-find `parent` (after
+// launch_components_init), vertex by vertex around a sampled large
+// component; `giant`: one device int32 of scratch.
+void launch_components_all_edges(const mcd_graph* g, int32_t* parent, int32_t* giant, hipStream_t s);
 
 // ---- percentile (select.hip) ----
 size_t select_scratch_bytes(const mcd_graph* g);

@@ -96,6 +96,24 @@ def test_degenerate_inputs():
     check_all(s, d, 1 << 12, oracle.TECTONIC, (1, 4))  # mostly isolated vertices
 
 
+def test_every_edge_kept_components():
+    """A threshold of at most 0 keeps every edge of the nonnegative measures;
+    mcd_prune_components then unites vertex by vertex around a sampled large
+    component: two R-MAT graphs side by side (two large components, only one
+    passed over), isolated vertices, K3/Jaccard/Tectonic, thresholds 0 and
+    below; and a graph whose vertices all have degree 1 or 0."""
+    s1, d1, n1 = gg.rmat(12, seed=61)
+    s2, d2, n2 = gg.rmat(13, seed=62)
+    s = np.concatenate([s1, s2 + n1]).astype(np.int32)
+    d = np.concatenate([d1, d2 + n1]).astype(np.int32)
+    n = n1 + n2 + 50
+    check_all(s, d, n, oracle.TECTONIC, (0, 1))
+    check_all(s, d, n, oracle.K3, (-3, 2))
+    check_all(s, d, n, oracle.JACCARD, (0, 7))
+    m = np.arange(0, 2000, 2, dtype=np.int32)
+    check_all(m, m + 1, 2001, oracle.TECTONIC, (0, 1))
+
+
 def test_invalid_vertex_rejected():
     from gpu_util import build
     with pytest.raises(M.MCDError) as ei:
