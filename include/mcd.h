@@ -302,8 +302,11 @@ mcd_status mcd_components_kept(const mcd_graph* g, const int32_t* kept_pairs, co
  * (delta, or per-graph deltas with vbase; w_f32, w_i32, keep_bits and n_kept
  * may each be NULL), with every kept edge united in the components' union-find
  * as soon as it is decided, then labels and n_components as mcd_components.
- * No kept-edge list is written.  labels: device int32[n];
- * ws: mcd_components_workspace_size bytes.  Asynchronous. */
+ * A single delta <= 0 with a measure that is never negative (all but TW)
+ * keeps every edge: the pass then writes the weights and keep bits only, and
+ * every edge is united vertex by vertex around a sampled large component
+ * (same labels and count).  No kept-edge list is written.  labels: device
+ * int32[n]; ws: mcd_components_workspace_size bytes.  Asynchronous. */
 mcd_status mcd_prune_components(const mcd_graph* g, mcd_measure measure, const int32_t* t, mcd_rational delta,
                                 int32_t n_graphs, const int64_t* vbase, const int64_t* deltas, float* w_f32,
                                 int32_t* w_i32, uint32_t* keep_bits, int64_t* n_kept, int32_t* labels,
