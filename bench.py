@@ -703,14 +703,14 @@ def main():
     wpc = wpc_roofline(m, n, kept, wpc_ms, profiled_traffic(["prune_components"]))
     wpc_gbs = wpc["achieved"]
     kept_tw = int(n_kept_tw.item())
-    wpc_tw = wpc_roofline(m, n, kept_tw, avg["prune_components_tw"], None)
+    wpc_tw = wpc_roofline(m, n, kept_tw, avg["prune_components_tw"], profiled_traffic(["prune_components_tw"]))
     # the same Tectonic pass with every edge kept (threshold 0): the union
     # step at its heaviest
     torch.cuda.synchronize()
     ms_all = _time_ms(lambda: M.mcd_prune_components(g, M.MCD_SIM_TECTONIC, t, delta=(0, 1), w_f32=wf, keep_bits=keep,
                                                      n_kept=n_kept, labels=labels, n_components=ncc, ws=ws), reps=3)
     kept_all = int(n_kept.item())
-    wpc_all = wpc_roofline(m, n, kept_all, ms_all, None)
+    wpc_all = wpc_roofline(m, n, kept_all, ms_all, profiled_traffic(["prune_components_all_kept"]))
     wpc_all.update(delta="0/1", n_kept=kept_all, n_components=int(ncc.item()), ms=ms_all)
     log(f"weights+prune+components with every edge kept: {ms_all:.2f} ms, {wpc_all['achieved']:.0f} GB/s")
     sw = sweep_stats.cpu().numpy()[0]
