@@ -150,11 +150,19 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ gate) {
     if (gated_off(gate)) return;
     extern __shared__ uint32_t h[];  // nbins counters when local (sized at launch)
+    // the thresholds in LDS: the search's steps read them at lane-dependent
+    // indices, which from the kernel arguments would be a global load (and
+    // its latency) per step
+    __shared__ int64_t tnum[MCD_SWEEP_MAX], tden[MCD_SWEEP_MAX];
     const int nbins = G * (ds.K + 1);
     const bool local = nbins <= kLevelBins;
     const int lane = threadIdx.x & 63;
     if (local)
         for (int i = threadIdx.x; i < nbins; i += blockDim.x) h[i] = 0;
+    for (int i = threadIdx.x; i < ds.K; i += blockDim.x) {
+        tnum[i] = ds.num[i];
+        tden[i] = ds.den[i];
+    }
     __syncthreads();
     GRID_STRIDE(e, m) {
         const int64_t D = (uint32_t)dsum[e];
@@ -166,8 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_level(const int32_t* __restrict__ 
         int lo = 0, hi = ds.K;  // first threshold that prunes e
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            const int c = NARROW ? rat_cmp64(num, den, ds.num[mid], ds.den[mid])
-                                 : rat_cmp(num, den, ds.num[mid], ds.den[mid]);
+            const int c = NARROW ? rat_cmp64(num, den, tnum[mid], tden[mid]) : rat_cmp(num, den, tnum[mid], tden[mid]);
             if (c >= 0) lo = mid + 1;
             else hi = mid;
         }
