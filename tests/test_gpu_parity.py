@@ -352,6 +352,37 @@ def test_complete_graph_closed_form(k):
     assert g.max_outdeg == k - 1
 
 
+@pytest.mark.parametrize("packed,occ", [(1048574, 1), (0, 1), (1048574, 0), (0, 0)])
+def test_triangles_long_hash_rows(packed, occ):
+    """Rows of 129 to 4096 entries in LDS hash tables (the rank windows
+    switched off), packed and wide entries, both register budgets: a 1500-
+    clique (rows of up to 1499: k - 2 triangles on every edge) beside an
+    R-MAT graph (oracle counts), in one graph."""
+    from gpu_util import ctx, build, canonical_order
+    k = 1500
+    i, j = np.triu_indices(k, 1)
+    s2, d2, n2 = gg.rmat(12, seed=91)
+    s = np.concatenate([i, s2 + k]).astype(np.int32)
+    d = np.concatenate([j, d2 + k]).astype(np.int32)
+    n = k + n2
+    lo2, hi2 = oracle.canon(n2, s2, d2)
+    want = np.concatenate([np.full(k * (k - 1) // 2, k - 2, np.int32), oracle.triangles(n2, lo2, hi2)])
+    c = ctx()
+    names = ("tc_chunk", "tc_lds_max", "tc_packed_range", "tc_window_max", "tc_window_occupancy")
+    old = [M.mcd_ctx_get_param(c, x) for x in names]
+    try:
+        for x, val in zip(names, (300, 4096, packed, 0, occ)):
+            M.mcd_ctx_set_param(c, x, val)
+        g = build(s, d, n)
+        assert g.max_outdeg >= k - 1
+        _, _, order = canonical_order(g)
+        t = M.mcd_triangles(g).cpu().numpy()[order]
+        assert np.array_equal(t, want)
+    finally:
+        for x, val in zip(names, old):
+            M.mcd_ctx_set_param(c, x, val)
+
+
 def test_autotuner_sets_params_and_keeps_counts():
     from gpu_util import build, canonical_order
     s, d, n = gg.rmat(14, seed=41)
