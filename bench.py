@@ -761,6 +761,16 @@ def main():
                                 ms=avg["prune_components_tw"]),
         "roofline_wpc_all_kept": wpc_all,
         "k_edge_dsum_profiled": EDGE_DSUM_PROFILED,
+        # context only (other hardware, other R-MAT parameters): the paper's
+        # CPU times for its TW pipeline on graphs of 10^9 edges
+        "paper_context": {
+            "source": "Table tab:syn: TW weights + prune + components, R-MAT (0.45, 0.15, 0.15, 0.25), "
+                      "2x Xeon Gold 6242, 16 threads",
+            "rows": [{"n": 200_000_000, "m": 1_000_000_000, "seconds": 164.19, "edges_per_s": 6.09e6},
+                     {"n": 20_000_000, "m": 1_000_000_000, "seconds": 566.64, "edges_per_s": 1.76e6}],
+            "this_tw_pipeline_edges_per_s": m / ((avg["build"] + avg["triangles"] + avg["prune_components_tw"])
+                                                 * 1e-3),
+            "this_tw_pipeline_scope": "build + triangles + TW weights/prune/components at -10, one MI355X"},
         "results": {"triangles": tri, "picked_delta": pick_delta, "n_kept": kept, "n_components": ncomp,
                     "sweep16": {"delta": [f"{a}/{b}" for a, b in grid16],
                                 "m_kept": sw[:, 0].tolist(), "n_components": sw[:, 1].tolist(),
