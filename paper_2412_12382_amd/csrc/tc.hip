@@ -330,8 +330,7 @@ struct WindowRow {
     uint16_t bpre[PAIR ? 1 : NW];
     uint32_t part[16];
     struct Key {
-        int32_t roff;   // loaded element + roff = rank offset r
-        uint32_t rmax;  // ranks v+1 .. v+1+rmax are in the window
+        int32_t roff;  // loaded element + roff = rank offset r
     };
     struct Hit {
         uint32_t word, rr;
@@ -373,13 +372,15 @@ struct WindowRow {
             }
         }
         __syncthreads();
-        return Key{(T16 ? top16 : 0) - v - 1, (uint32_t)(maxv - v - 1)};
+        return Key{(T16 ? top16 : 0) - v - 1};
     }
-    // branch-free up to the count itself: lanes outside the chunk or the
-    // window look up the zero word and miss
+    // branch-free up to the count itself: lanes outside the chunk look up the
+    // zero word and miss, and so do elements outside the window (offsets of
+    // 32 NW or more, negative ones included, clamp to it); inside the window
+    // the words past the row's largest rank hold no bit
     __device__ __forceinline__ bool probe(const Key& k, int32_t x, bool valid, Hit& h) const {
         const uint32_t r = (uint32_t)(x + k.roff);
-        h.rr = valid && r <= k.rmax ? r : ZR;
+        h.rr = valid ? min(r, ZR) : ZR;
         if constexpr (PAIR) h.word = bp[h.rr >> 5].x;
         else h.word = bw[h.rr >> 5];
         // (the bit-field extract takes its offset and width mod 32)
