@@ -43,3 +43,22 @@ def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
         f.write("\n")
     assert bench.profiled_traffic(["triangles"]) is None
     assert bench.profiled_traffic(["prune_components"]) == 1.5e10
+
+
+def test_roofline_objects():
+    # the triangle roofline names its algorithmic unit; counted bytes give a
+    # second fraction when present, and none when the counters are stale
+    r = bench.tc_roofline(3200.0, 9.65e11, 300.0, 1.2e12)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == bench.HBM_PEAK_GBS
+    assert abs(r["frac"] - 3200.0 / bench.HBM_PEAK_GBS) < 1e-12
+    assert abs(r["traffic_frac"] - 1.2e12 / 0.3 / 1e9 / bench.HBM_PEAK_GBS) < 1e-12
+    assert "4S" in r["unit_basis"]
+    r = bench.tc_roofline(3200.0, 9.65e11, 300.0, None)
+    assert r["traffic"] is None and "traffic_frac" not in r
+    # the weight+prune+CC pass: moved bytes (16 per edge + 1/8 + 8 per kept
+    # edge + 20 per vertex + 8) over the time
+    m, n, kept, ms = 1000, 100, 10, 1e-3
+    w = bench.wpc_roofline(m, n, kept, ms, None)
+    assert w["bound"] == "hbm" and w["traffic"] is None
+    assert abs(w["achieved"] - w["algorithmic_bytes"] / (ms * 1e-3) / 1e9) < 1e-9
+    assert w["survey_formula_bytes"] > w["algorithmic_bytes"]
