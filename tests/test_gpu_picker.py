@@ -5,6 +5,7 @@ import pytest
 import torch
 
 import graphgen as gg
+import mlp_bound as mb
 import oracle
 from oracle import mlp
 
@@ -33,26 +34,28 @@ def test_mlp_forward_and_gradient():
         y = M.mcd_mlp_forward(ctx(), cuda(p), cuda(mean), cuda(std), cuda(x)).cpu().numpy()
         yo, _ = mlp.forward(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x)
         assert np.all(np.abs(y - yo) <= 1e-5 * np.maximum(np.abs(yo), 1.0))
+        assert np.all(np.abs(y - yo) <= mb.forward_bound(p, mean, std, x))
+        # the gradient on the rows whose ReLU masks are certain on both sides
+        # (all but two of the 192): within the a priori bound and within the
+        # much tighter empirical tolerance
+        keep = mb.rows_with_clear_masks(p, mean, std, x)
+        assert keep.sum() >= max(1, B - 2)
+        x, target = x[keep], target[keep]
         g, loss = M.mcd_mlp_gradient(ctx(), cuda(p), cuda(mean), cuda(std), cuda(x), cuda(target))
         go, lo = mlp.gradient(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x,
                               target.astype(np.float64))
         g = g.cpu().numpy()
-        # fp32 batch sum: besides 1e-4 relative per entry, allow the recursive
-        # summation bound (B - 1) u sum_r |dL_r/dp| (u = 2^-24) for cancellation
-        sabs = np.zeros(mlp.NPAR)
-        for r in range(B):
-            gr, _ = mlp.gradient(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64),
-                                 x[r:r + 1], target[r:r + 1].astype(np.float64))
-            sabs += np.abs(gr) / B
-        tol = 1e-4 * (np.abs(go) + 1e-3) + 4 * (B + 8) * 2.0 ** -24 * sabs
+        assert np.all(np.abs(g - go) <= mb.gradient_bound(p, mean, std, x, target))
+        tol = mb.empirical_tolerance(go, mb.row_abs_mean(p, mean, std, x, target), len(x))
         assert np.all(np.abs(g - go) <= tol), np.max(np.abs(g - go) / tol)
         assert abs(float(loss.item()) - lo) <= 1e-5 * max(lo, 1.0)
 
 
 def test_mlp_gradient_with_ari_term():
     # the training loss with the sweep's ARI table: mse_w (y - t)^2 minus the
-    # ARI interpolated at 63 y; rows whose 63 y lies near a grid point (where
-    # the fp32 segment choice could differ) are left out of the batch
+    # ARI interpolated at 63 y; rows whose 63 y lies within its error bound of
+    # a grid point or an end (where the fp32 segment choice could differ), or
+    # whose ReLU masks are uncertain, are left out of the batch
     from gpu_util import ctx
     B = 40
     p, mean, std, x, target = rand_problem(9, B)
@@ -60,8 +63,9 @@ def test_mlp_gradient_with_ari_term():
     yo, _ = mlp.forward(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x)
     p[8512] += np.float32(0.5 - np.median(yo))
     yo, _ = mlp.forward(p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64), x)
-    z = 63 * yo
-    keep = (z > 0.05) & (z < 62.95) & (np.abs(z - np.round(z)) > 0.01)
+    z, zb = 63 * yo, mb.grid_position_bound(p, mean, std, x, 64)
+    keep = (z > zb) & (z < 63 - zb) & (np.abs(z - np.round(z)) > zb)
+    keep &= mb.rows_with_clear_masks(p, mean, std, x)
     x, target = x[keep], target[keep]
     assert len(x) >= 10
     ari = np.random.default_rng(10).uniform(-0.1, 1.0, (len(x), 64))
@@ -69,12 +73,9 @@ def test_mlp_gradient_with_ari_term():
                                  mse_weight=0.1)
     P64, m64, s64 = p.astype(np.float64), mean.astype(np.float64), std.astype(np.float64)
     go, lo = mlp.gradient(P64, m64, s64, x, target.astype(np.float64), ari, 0.1)
-    sabs = np.zeros(mlp.NPAR)
-    for r in range(len(x)):
-        gr, _ = mlp.gradient(P64, m64, s64, x[r:r + 1], target[r:r + 1].astype(np.float64), ari[r:r + 1], 0.1)
-        sabs += np.abs(gr) / len(x)
     g = g.cpu().numpy()
-    tol = 1e-4 * (np.abs(go) + 1e-3) + 4 * (len(x) + 8) * 2.0 ** -24 * sabs
+    assert np.all(np.abs(g - go) <= mb.gradient_bound(p, mean, std, x, target, ari, 0.1))
+    tol = mb.empirical_tolerance(go, mb.row_abs_mean(p, mean, std, x, target, ari, 0.1), len(x))
     assert np.all(np.abs(g - go) <= tol), np.max(np.abs(g - go) / tol)
     assert abs(float(loss.item()) - lo) <= 1e-5 * max(abs(lo), 1.0)
 
