@@ -350,8 +350,6 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply_i32(const int32_t* __re
     }
 }
 
-__global__ void k_copy_total(const int64_t* __restrict__ a, int64_t* __restrict__ dst) { *dst = *a; }
-
 template <class T>
 __global__ void k_fill(T* __restrict__ p, int64_t N, T v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_sel_min(const int32_t* __restrict_
     sd[threadIdx.x] = bd;
     __syncthreads();
     for (int half = kThreads / 2; half > 0; half >>= 1) {
-        if (threadIdx.x < half) {
+        if ((int)threadIdx.x < half) {
             const int64_t on = sn[threadIdx.x + half], od = sd[threadIdx.x + half];
             if (od != 0 && (sd[threadIdx.x] == 0 || rat_cmp(on, od, sn[threadIdx.x], sd[threadIdx.x]) < 0)) {
                 sn[threadIdx.x] = on;
